@@ -1,0 +1,362 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test names the passage or identity it checks.  None of these compares
+the oracle with itself: sample counts are the paper's printed values, the
+tree is checked by brute force, the per-box algebra against explicitly formed
+dense E, F, L, U operators, and whole factorizations against dense LU solves,
+exactly H2 matrices, and the error trend in k.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from oracle import operators as oop
+from oracle import rsrs as orr
+from oracle import tree as ot
+from paper_2311_01451_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- tree / counts
+
+def test_paper_sample_counts():
+    """Experiment 1 prints n_samples 1520 (k=40) and 2280 (k=60) on the
+    284^2 / 401^2 grids with m = 4k (Sec. 5.1, figure legends)."""
+    with open(os.path.join(GOLDEN, "paper_sample_counts.json")) as fh:
+        cases = json.load(fh)["cases"]
+    for c in cases:
+        t = ot.build_tree(inputs.grid2d(c["grid_n"]), leaf_size=c["leaf"])
+        assert ot.samples_required(t, c["k"], c["p"]) == c["n_samples"]
+
+
+@pytest.mark.parametrize("n", [128, 256, 512])
+def test_sample_count_closed_form_independent_of_N(n):
+    """eq. s_uniform: s = (6^d + 1) k + p in 2D for uniform trees with m = 2^d k,
+    independent of N."""
+    k = 16
+    t = ot.build_tree(inputs.grid2d(n), leaf_size=4 * k)
+    assert ot.samples_required(t, k, k) == 37 * k + k
+
+
+def _brute_adjacent(t, a, b):
+    la, ha = t.box_lo_hi(a)
+    lb, hb = t.box_lo_hi(b)
+    return bool(np.all(la <= hb) and np.all(lb <= ha))
+
+
+def test_uniform_box_counts_and_interior_neighbours():
+    """eq. nboxes: n_leaf = N/m on a uniform grid; c_nei = 3^d (Sec. 4.5)."""
+    t = ot.build_tree(inputs.grid2d(64), leaf_size=16)     # 16x16 leaves of 4x4
+    assert len(t.level_boxes[t.nlevels]) == 64 * 64 // 16
+    nb = ot.neighbours(t, t.nlevels)
+    counts = [len(v) for v in nb.values()]
+    assert max(counts) == 8 and min(counts) == 3
+    t3 = ot.build_tree(inputs.grid3d_interior(16), leaf_size=8, lo=[0.0, 0.0, 0.0], side=1.0)
+    nb3 = ot.neighbours(t3, t3.nlevels)
+    assert max(len(v) for v in nb3.values()) == 26
+
+
+def test_adaptive_tree_balance_and_neighbours_brute_force():
+    """Sec. 3: leaves hold <= m points, adjacent leaves differ by <= 1 level
+    (2:1 balance); neighbour lists equal brute-force closed-box intersection."""
+    rng = np.random.default_rng(5)
+    pts = np.concatenate([rng.uniform(0, 1, (300, 2)),
+                          0.5 + 0.01 * rng.standard_normal((300, 2))])
+    pts = np.clip(pts, 0, 0.999999)
+    t = ot.build_tree(pts, leaf_size=12)
+    leaves = np.nonzero(t.is_leaf)[0]
+    for b in leaves:
+        assert t.pt_end[b] - t.pt_begin[b] <= 12 or t.level[b] == t.qbits
+    for i in leaves:
+        for j in leaves:
+            if i < j and _brute_adjacent(t, i, j):
+                assert abs(int(t.level[i]) - int(t.level[j])) <= 1
+    # permutation and contiguous ranges
+    assert np.array_equal(np.sort(t.perm), np.arange(len(pts)))
+    for b in range(t.nbox):
+        if not t.is_leaf[b]:
+            ch = t.children[b]
+            assert t.pt_begin[b] == t.pt_begin[ch].min() and t.pt_end[b] == t.pt_end[ch].max()
+    for lev in range(1, t.nlevels + 1):
+        reps = ot.representatives(t, lev)
+        nb = ot.neighbours(t, lev)
+        for b in t.level_boxes[lev]:
+            want = sorted(int(r) for r in reps if r != b and _brute_adjacent(t, int(b), int(r)))
+            assert nb[int(b)].tolist() == want
+
+
+def test_split_plane_goes_to_upper_child():
+    """Quantization reading: a point on a split plane belongs to the upper child."""
+    pts = np.array([[0.5, 0.25], [0.25, 0.5], [0.1, 0.1], [0.9, 0.9], [0.5, 0.5]])
+    t = ot.build_tree(pts, leaf_size=1)
+    for u in range(len(pts)):
+        pos = int(np.nonzero(t.perm == u)[0][0])
+        leaf = [b for b in np.nonzero(t.is_leaf)[0] if t.pt_begin[b] <= pos < t.pt_end[b]][0]
+        lo, hi = t.box_lo_hi(leaf)
+        q = ot.quantize(pts[u:u + 1], [0, 0], 1.0)[0]
+        assert np.all(lo <= q) and np.all(q < hi)
+        assert np.all(lo / float(2 ** t.qbits) <= pts[u])
+
+
+def test_colouring_has_disjoint_closed_neighbourhoods():
+    """Same-colour boxes touch disjoint rows, so their updates commute."""
+    t = ot.build_tree(inputs.grid2d(64), leaf_size=16)
+    sch = ot.schedule(t, 8)
+    for li, lev in enumerate(sch.levels):
+        nb = sch.nbrs[lev]
+        for cls in sch.order[li]:
+            for i, a in enumerate(cls):
+                for b in cls[i + 1:]:
+                    ca = set(nb[a].tolist()) | {a}
+                    cb = set(nb[b].tolist()) | {b}
+                    assert not (ca & cb)
+    # uniform interior: 9 colours on a wide level
+    assert len(sch.order[0]) == 9
+
+
+# ---------------------------------------------------------------- per-step identities
+
+def test_nullification_projector_and_formula():
+    """eq. Omegaprime_null: C Pi = 0 with Pi an orthogonal projector;
+    eq. nullformula: Y_B Pi = A_{B,F} (Omega Pi)_F for dense A."""
+    rng = np.random.default_rng(1)
+    N, s = 60, 40
+    A = rng.standard_normal((N, N))
+    Om = rng.standard_normal((N, s))
+    Y = A @ Om
+    B = np.arange(0, 8)
+    Nn = np.arange(8, 30)
+    Fr = np.arange(30, N)
+    C = Om[np.concatenate([B, Nn])]
+    I = np.eye(s)
+    Pi = orr.nullify(I, C)
+    assert np.abs(C @ Pi).max() < 1e-12
+    assert np.abs(Pi @ Pi - Pi).max() < 1e-12 and np.abs(Pi - Pi.T).max() < 1e-12
+    lhs = orr.nullify(Y[B], C)
+    rhs = A[np.ix_(B, Fr)] @ (Om[Fr] @ Pi)
+    assert np.abs(lhs - rhs).max() < 1e-11 * np.abs(rhs).max()
+
+
+def test_extraction_exact_for_block_sparse_rows():
+    """eq. pinvformula: (A_RB A_RN) = Y_R pinv([Omega_B; Omega_N]) when A_RF = 0."""
+    rng = np.random.default_rng(2)
+    N, s = 50, 36
+    A = rng.standard_normal((N, N))
+    R = np.arange(0, 5)
+    C = np.arange(0, 30)
+    A[np.ix_(R, np.arange(30, N))] = 0.0
+    Om = rng.standard_normal((N, s))
+    X = orr._right_pinv_apply((A @ Om)[R], Om[C])
+    assert np.abs(X - A[np.ix_(R, C)]).max() < 1e-11
+
+
+def test_row_id_matches_lapack_and_is_exact_at_rank_k():
+    """Sec. 2.3 / eq. id_factorization: greedy CPQR ID; exact when rank <= k."""
+    rng = np.random.default_rng(3)
+    M = rng.standard_normal((20, 5)) @ rng.standard_normal((5, 30))
+    S, R, T = orr.row_id(M, 5)
+    assert np.abs(M[R] - T @ M[S]).max() < 1e-11 * np.abs(M).max()
+    _, _, piv = sla.qr(M.T, pivoting=True)
+    assert sorted(piv[:5].tolist()) == S.tolist()
+
+
+def test_block_elimination_decouples():
+    """eq. LAU / LUdef: L A U is block diagonal in the eliminated block, and L, U
+    are inverted by flipping the sign of their off-diagonal block."""
+    rng = np.random.default_rng(4)
+    A = rng.standard_normal((9, 9)) + 9 * np.eye(9)
+    r, sn = np.arange(3), np.arange(3, 9)
+    KU = np.linalg.solve(A[np.ix_(r, r)], A[np.ix_(r, sn)])
+    KL = A[np.ix_(sn, r)] @ np.linalg.inv(A[np.ix_(r, r)])
+    L = np.eye(9); L[np.ix_(sn, r)] = -KL
+    U = np.eye(9); U[np.ix_(r, sn)] = -KU
+    X = L @ A @ U
+    assert np.abs(X[np.ix_(r, sn)]).max() < 1e-12 and np.abs(X[np.ix_(sn, r)]).max() < 1e-12
+    Li = np.eye(9); Li[np.ix_(sn, r)] = KL
+    assert np.abs(Li @ L - np.eye(9)).max() < 1e-14
+
+
+def _small_log_problem(n=16, m=16, k=8, skew=0.0):
+    pts = inputs.grid2d(n)
+    h = 1.0 / n
+    A = oop.log2d(pts, h) if skew == 0.0 else oop.log2d_skew(pts, h, skew)
+    t = ot.build_tree(pts, m)
+    s = ot.samples_required(t, k, k)
+    Om, Psi = inputs.test_matrices(n * n, s)
+    return A, t, Om, Psi
+
+
+def _dense_ops(bf, N):
+    E = np.eye(N); E[np.ix_(bf.R, bf.S)] = -bf.T
+    F = np.eye(N); F[np.ix_(bf.S, bf.R)] = -bf.T.T
+    L = np.eye(N); L[np.ix_(bf.SN, bf.R)] = -bf.KL
+    U = np.eye(N); U[np.ix_(bf.R, bf.SN)] = -bf.KU
+    return E, F, L, U
+
+
+@pytest.mark.parametrize("skew", [0.0, 2e-3])
+def test_sample_pair_invariant_every_box(skew):
+    """Sec. 1.1 and eq. updateVW_sketch/test/adj: after every box the updated
+    sketches are an exact sample pair of V^{-1} A W^{-1}, whatever the
+    approximation quality; the R rows/columns are decoupled to the level of the
+    far-field remainder."""
+    A, t, Om, Psi = _small_log_problem(skew=skew)
+    Y, Z = A @ Om, A.T @ Psi
+    N = A.shape[0]
+    P = t.perm
+    state = {"A": A[np.ix_(P, P)].copy()}
+    worst = [0.0, 0.0]
+
+    def check(bf, Yt, Zt, Omt, Psit):
+        E, F, L, U = _dense_ops(bf, N)
+        At = L @ E @ state["A"] @ F @ U
+        state["A"] = At
+        worst[0] = max(worst[0], np.abs(Yt - At @ Omt).max() / np.abs(Yt).max(),
+                       np.abs(Zt - At.T @ Psit).max() / np.abs(Zt).max())
+        rest = np.setdiff1d(np.arange(N), bf.R)
+        worst[1] = max(worst[1], np.abs(At[np.ix_(bf.R, rest)]).max(),
+                       np.abs(At[np.ix_(rest, bf.R)]).max())
+
+    orr.factor(t, Y, Z, Om, Psi, 8, on_box=check)
+    assert worst[0] < 1e-12
+    assert worst[1] < 2e-4 * np.abs(A).max()
+
+
+def test_solve_apply_inverse_and_adjoint():
+    """eq. Afact / Ainvfact: the forward and inverse factorizations are exact
+    inverses; transposed products are adjoints."""
+    A, t, Om, Psi = _small_log_problem(skew=2e-3)
+    F = orr.factor(t, A @ Om, A.T @ Psi, Om, Psi, 8)
+    rng = np.random.default_rng(9)
+    x = rng.standard_normal((A.shape[0], 3))
+    y = rng.standard_normal((A.shape[0], 3))
+    assert np.abs(orr.apply(F, orr.solve(F, x)) - x).max() < 1e-12
+    assert np.abs(orr.apply(F, orr.solve(F, x, True), True) - x).max() < 1e-12
+    assert abs(np.sum(orr.apply(F, x) * y) - np.sum(x * orr.apply(F, y, True))) < 1e-10
+    assert abs(np.sum(orr.solve(F, x) * y) - np.sum(x * orr.solve(F, y, True))) < 1e-10
+
+
+def test_nonsymmetric_operator_solves_and_transpose():
+    """A != A^T: the Y/Z sides and the transpose solve are exercised (every
+    configured workload is symmetric, so this is where a transposition slip shows)."""
+    A, t, Om, Psi = _small_log_problem(n=32, m=32, k=16, skew=5e-3)
+    assert np.abs(A - A.T).max() > 1e-6
+    F = orr.factor(t, A @ Om, A.T @ Psi, Om, Psi, 16)
+    f = inputs.rhs(A.shape[0], 2)
+    u = orr.solve(F, f)
+    ut = orr.solve(F, f, transpose=True)
+    r1 = np.linalg.norm(f - A @ u) / np.linalg.norm(f)
+    r2 = np.linalg.norm(f - A.T @ ut) / np.linalg.norm(f)
+    assert r1 < 1e-4 and r2 < 1e-4
+    # a transposition slip would leave the transpose solve at O(skew) error
+    assert r2 < 10 * r1 + 1e-12
+
+
+def test_single_leaf_equals_dense_solve():
+    """N <= m: no box is compressed, A_approx = Y pinv(Omega) = A (s >= N)."""
+    rng = np.random.default_rng(11)
+    pts = rng.uniform(0, 1, (40, 2))
+    A = oop.log2d(pts, 0.05) + 0.1 * rng.standard_normal((40, 40))
+    t = ot.build_tree(pts, leaf_size=64)
+    assert t.nlevels == 0
+    s = ot.samples_required(t, 8, 8)
+    assert s == 40
+    Om, Psi = rng.standard_normal((40, 50)), rng.standard_normal((40, 50))
+    F = orr.factor(t, A @ Om, A.T @ Psi, Om, Psi, 8)
+    f = rng.standard_normal(40)
+    assert np.abs(orr.solve(F, f) - np.linalg.solve(A, f)).max() < 1e-10 * np.linalg.cond(A)
+
+
+def test_rank_at_least_box_size_eliminates_nothing():
+    """k >= max |B_a|: every point stays active and the root extraction is the
+    whole (dense) matrix."""
+    A, t, Om, Psi = _small_log_problem(n=8, m=16, k=16)
+    F = orr.factor(t, A @ Om, A.T @ Psi, Om, Psi, 64, check_samples=False)
+    assert len(F.boxes) == 0 and len(F.Bt) == 64
+    f = inputs.rhs(64, 1)[:, 0]
+    assert np.abs(orr.solve(F, f) - np.linalg.solve(A, f)).max() < 1e-11
+
+
+def exact_h2(t, r, seed=3):
+    """A = blockdiag over leaves (Gaussian + m I) + U V^T with U, V of rank r
+    (far-field rank <= 2r; the R-block couplings vanish exactly after each ID)."""
+    rng = np.random.default_rng(seed)
+    N = t.n
+    A = np.zeros((N, N))
+    for b in np.nonzero(t.is_leaf)[0]:
+        idx = t.perm[t.pt_begin[b]:t.pt_end[b]]
+        m = len(idx)
+        A[np.ix_(idx, idx)] = rng.standard_normal((m, m)) + m * np.eye(m)
+    U = rng.standard_normal((N, r))
+    V = rng.standard_normal((N, r))
+    return A + U @ V.T
+
+
+def test_exact_h2_recovered_to_rounding():
+    """Far-field rank 2r <= k: every ID is exact, so A_approx = A up to rounding
+    (construction from Sec. 3.1 and the modified near field of Remark 2)."""
+    pts = inputs.grid2d(16)
+    t = ot.build_tree(pts, leaf_size=16)
+    A = exact_h2(t, r=3)
+    k = 6
+    s = ot.samples_required(t, k, k)
+    Om, Psi = inputs.test_matrices(256, s)
+    F = orr.factor(t, A @ Om, A.T @ Psi, Om, Psi, k)
+    assert len(F.boxes) == 20
+    assert orr.relerr(F, A) < 1e-11
+
+
+def test_error_decays_with_rank():
+    """Tables of Sec. 5: relerr falls as k grows (here k = 4, 6, 8, 12)."""
+    pts = inputs.grid2d(32)
+    A = oop.log2d(pts, 1.0 / 32)
+    t = ot.build_tree(pts, leaf_size=32)
+    errs = []
+    for k in (4, 6, 8, 12):
+        s = ot.samples_required(t, k, k)
+        Om, Psi = inputs.test_matrices(1024, s)
+        F = orr.factor(t, A @ Om, A.T @ Psi, Om, Psi, k)
+        errs.append(orr.relerr(F, A))
+    assert all(errs[i + 1] < errs[i] for i in range(len(errs) - 1)), errs
+    assert errs[-1] < 1e-6
+
+
+def test_refinement_and_solve_error_bound():
+    """eq. err_solve_cond: the one-shot error is bounded by 2 eps cond/(1-eps cond);
+    refinement through the black-box product drives the residual to rounding."""
+    A, t, Om, Psi = _small_log_problem(n=32, m=32, k=8)
+    F = orr.factor(t, A @ Om, A.T @ Psi, Om, Psi, 8)
+    eps = orr.relerr(F, A)
+    cond = np.linalg.cond(A)
+    f = inputs.rhs(1024, 1)[:, 0]
+    x = np.linalg.solve(A, f)
+    xt = orr.solve(F, f)
+    assert np.linalg.norm(x - xt) / np.linalg.norm(x) <= 2 * eps * cond / (1 - eps * cond)
+    _, hist = orr.refine(F, lambda v: A @ v, f, tol=1e-13, maxit=10)
+    assert hist[-1] < 1e-13 and len(hist) <= 6
+
+
+def test_insufficient_samples_raises():
+    A, t, Om, Psi = _small_log_problem()
+    with pytest.raises(orr.InsufficientSamples):
+        orr.factor(t, A @ Om[:, :50], A.T @ Psi[:, :50], Om[:, :50], Psi[:, :50], 8)
+
+
+def test_operators_definitions():
+    """The synthetic operators: log kernel entries, diagonal, symmetry; the
+    7-point operator is symmetric positive definite with 7 entries per interior row."""
+    pts = inputs.grid2d(4)
+    A = oop.log2d(pts, 0.25)
+    assert abs(A[0, 0] - (1 + 0.5 * 0.0625)) < 1e-15
+    r = np.linalg.norm(pts[0] - pts[5])
+    assert abs(A[0, 5] - 0.0625 * (-np.log(r) / (2 * np.pi))) < 1e-15
+    n = 6
+    a = inputs.smooth_log_coefficient(n + 2)
+    P = oop.poisson7(n, a).toarray()
+    assert np.abs(P - P.T).max() < 1e-9
+    assert np.linalg.eigvalsh(P).min() > 0
+    assert (np.count_nonzero(P, axis=1).max()) == 7
