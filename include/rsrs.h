@@ -1,0 +1,254 @@
+/*
+ * rsrs.h -- C ABI of the MI355X (gfx950) implementation of randomized strong
+ * recursive skeletonization (RSRS): compression and LU factorization of a
+ * strongly admissible H2 matrix from one set of sketches
+ *     Y = A Omega,   Z = A^T Psi,   Omega, Psi ~ N(0, 1)   (N x s each),
+ * where A (N x N, rows and columns tagged with points in R^2 or R^3) is known
+ * only through products with A and A^T (Yesypenko & Martinsson, Sec. 1 and
+ * Sec. 4, eq. rand_sample_setting).  The factorization produced is the one of
+ * Sec. 3 (eq. Afact, Ainvfact) reconstructed by Algorithm 1.
+ *
+ * Conventions (all entry points)
+ *  - Every function returns rsrs_status; RSRS_OK is 0.  On error nothing is
+ *    allocated for the caller and rsrs_last_error() (thread-local) describes
+ *    the failure.
+ *  - "device" pointers are HIP device allocations on the current device;
+ *    "host" pointers are ordinary process memory.
+ *  - Dense blocks of points are ROW-MAJOR: entry (point i, column j) of an
+ *    N x w block X with leading dimension ldx is X[i*ldx + j], ldx >= w.
+ *    Points are in the caller's ("user") order unless stated otherwise.
+ *  - stream: a hipStream_t passed as void*; NULL means the default stream.
+ *    Work is stream-ordered; functions that must read results on the host
+ *    (tree building, factor bookkeeping) synchronise the stream themselves.
+ *  - Handles are not thread-safe; distinct handles may be used from
+ *    distinct threads.  The library owns everything it returns through an
+ *    out-pointer until the matching *_destroy call.
+ */
+#ifndef RSRS_H
+#define RSRS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RSRS_OK = 0,
+  RSRS_E_INVALID = 1,      /* bad argument (null pointer, size, layout)          */
+  RSRS_E_SAMPLES = 2,      /* s below the requirement; see rsrs_last_required_s   */
+  RSRS_E_SINGULAR = 3,     /* a pivot block or the root block is singular        */
+  RSRS_E_CALLBACK = 4,     /* the user matvec returned nonzero                    */
+  RSRS_E_NUMERIC = 5,      /* NaN or Inf met in samples or residuals              */
+  RSRS_E_NOMEM = 6,        /* device allocation failed                            */
+  RSRS_E_HIP = 7,          /* HIP runtime error                                   */
+  RSRS_E_UNSUPPORTED = 8   /* option not implemented                              */
+} rsrs_status;
+
+typedef struct rsrs_tree_s rsrs_tree_t;
+typedef struct rsrs_samples_s rsrs_samples_t;
+typedef struct rsrs_factor_s rsrs_factor_t;
+typedef struct rsrs_operator_s rsrs_operator_t;
+
+const char* rsrs_status_string(rsrs_status st);
+const char* rsrs_last_error(void);
+/* After RSRS_E_SAMPLES: the number of samples that would have been enough. */
+int64_t rsrs_last_required_s(void);
+
+/* ------------------------------------------------------------------------
+ * Tree (Sec. 3, opening paragraphs; eq. active, BNactive).  Pure host code,
+ * deterministic and bit-identical for identical input bits.
+ *  - Root box: the cube [root_lo, root_lo + root_side)^dim.
+ *  - Coordinates are quantized to qbits (<= 20; 0 selects 20) bits per axis:
+ *    q = clamp(floor(((x - lo) / side) * 2^qbits), 0, 2^qbits - 1) in FP64;
+ *    a point on a split plane belongs to the upper child.
+ *  - A box holding more than leaf_size points is split into its non-empty
+ *    children; leaves are then split until the tree is 2:1 balanced
+ *    (no leaf's closed box meets a leaf two or more levels finer).
+ *  - Box ids: sorted by (level, Morton code), axis 0 in the lowest bit.
+ *  - Tree order of points: leaves in Morton order of their first finest cell,
+ *    ascending user index inside a leaf; each box owns a contiguous range.
+ * pts: host, n x dim row-major FP64.  *out is owned by the caller and freed
+ * with rsrs_tree_destroy.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  int dim;             /* 2 or 3 */
+  int leaf_size;       /* m >= 1 */
+  int qbits;           /* 0 -> 20 */
+  double root_lo[3];
+  double root_side;    /* > 0 */
+} rsrs_tree_opts;
+
+rsrs_status rsrs_build_tree(const double* pts, int64_t n, const rsrs_tree_opts* opts,
+                            rsrs_tree_t** out);
+void rsrs_tree_destroy(rsrs_tree_t* t);
+
+/* Read-only views of the tree arrays (host memory owned by the tree, valid
+ * until rsrs_tree_destroy).  coords is nbox x dim; perm maps tree position to
+ * user index. */
+typedef struct {
+  int dim, nlevels, qbits;
+  int64_t n, nbox;
+  const int32_t* level;
+  const int32_t* coords;
+  const int64_t* parent;     /* -1 for the root */
+  const uint8_t* is_leaf;
+  const int64_t* pt_begin;
+  const int64_t* pt_end;
+  const int64_t* perm;
+} rsrs_tree_info;
+rsrs_status rsrs_tree_get_info(const rsrs_tree_t* t, rsrs_tree_info* out);
+
+/* Neighbour lists while level `level` (1..nlevels) is processed: for each
+ * level-`level` box (ascending id, *nb of them, ids in *boxes), the
+ * representatives (level-`level` boxes and coarser leaves) whose closed box
+ * meets it, self excluded, ascending by id, in CSR form (offsets has *nb+1
+ * entries).  Pointers are owned by the tree. */
+rsrs_status rsrs_tree_neighbours(const rsrs_tree_t* t, int level, int64_t* nb,
+                                 const int64_t** boxes, const int64_t** offsets,
+                                 const int64_t** nbrs);
+
+/* Box order for fixed rank k (Algorithm 1 with the order the paper leaves
+ * open fixed as follows): levels nlevels..1; a level-l box is processed when
+ * its active count b exceeds k.  Processed boxes of a level are coloured
+ * greedily in order (sum_a (coord_a mod 3) 3^a, id): each takes the smallest
+ * colour not held by a box whose closed neighbourhood {B} u N(B) meets its
+ * own; colours run ascending, boxes inside a colour by id.  Host outputs of
+ * nbox entries (caller-allocated): colour (-1 = not processed), b_count
+ * (active count when its level runs), l_count (b + active neighbour count
+ * when processed, else 0).  *root_count = |B_t|. */
+rsrs_status rsrs_tree_schedule(const rsrs_tree_t* t, int k, int32_t* colour, int64_t* b_count,
+                               int64_t* l_count, int64_t* root_count);
+
+/* Smallest s with s >= |B_a| + |N_a| + k + p for every processed box
+ * (eq. s_L, s_B; count of Sec. 4.5 under the order above) and s >= |B_t|.
+ * Returns -1 on invalid arguments. */
+int64_t rsrs_samples_required(const rsrs_tree_t* t, int k, int p);
+
+/* ------------------------------------------------------------------------
+ * Black-box operator access (Sec. 4, eq. rand_sample_setting).
+ * The callback computes Y = A X (transpose = 0) or Y = A^T X (transpose = 1)
+ * for an N x ncols device block X (row-major, user order, leading dimension
+ * ldx) into the device block Y (leading dimension ldy), stream-ordered on
+ * `stream`.  It returns 0 on success; any other value aborts the caller with
+ * RSRS_E_CALLBACK.
+ * ---------------------------------------------------------------------- */
+typedef int (*rsrs_matvec_fn)(void* user, int transpose, int64_t ncols, const double* X,
+                              int64_t ldx, double* Y, int64_t ldy, void* stream);
+
+/* Built-in synthetic operators (HIP kernels; the handle is the `user` of
+ * rsrs_op_matvec, which has the rsrs_matvec_fn signature):
+ *  RSRS_OP_LOG2D  A_ij = delta_ij + h^2 (-log|x_i - x_j| / (2 pi)), i != j,
+ *                 A_ii = 1 + h^2 / 2      (param = h; dim 2)
+ *  RSRS_OP_INVR3D A_ij = delta_ij + (1/N) / (4 pi |x_i - x_j|), A_ii = 1
+ *                 (param unused; dim 3)
+ *  RSRS_OP_LOG2D_SKEW  LOG2D plus param2 * (x_i - x_j)_0 / |x_i - x_j|^2
+ *                 (non-symmetric)
+ * pts: host n x dim (user order); copied to the device. */
+enum { RSRS_OP_LOG2D = 1, RSRS_OP_INVR3D = 2, RSRS_OP_LOG2D_SKEW = 3 };
+rsrs_status rsrs_op_create_kernel(int kind, const double* pts, int64_t n, int dim,
+                                  double param, double param2, rsrs_operator_t** out);
+/* Explicit matrix: A is a device n x n row-major array (leading dimension
+ * lda), borrowed (must outlive the operator). */
+rsrs_status rsrs_op_create_dense(const double* A, int64_t n, int64_t lda, rsrs_operator_t** out);
+/* 7-point -div(a grad u) on the n^3 interior nodes of the grid h = 1/(n+1)
+ * (x fastest), face coefficient = mean of the two node values, Dirichlet
+ * nodes eliminated; coef: host (n+2)^3 node values indexed [z][y][x]. */
+rsrs_status rsrs_op_create_poisson7(int n, const double* coef, rsrs_operator_t** out);
+int rsrs_op_matvec(void* op, int transpose, int64_t ncols, const double* X, int64_t ldx,
+                   double* Y, int64_t ldy, void* stream);
+void rsrs_op_destroy(rsrs_operator_t* op);
+
+/* ------------------------------------------------------------------------
+ * Samples {Y, Z, Omega, Psi} (Algorithm 1, Require).  Stored by the library
+ * in tree order, row-major N x s FP64 on the device.
+ * ---------------------------------------------------------------------- */
+/* Copy caller-provided device sketches (user order, row-major, leading
+ * dimension ld >= s) into library-owned tree-ordered storage.  The caller's
+ * arrays are not modified. */
+rsrs_status rsrs_samples_wrap(const rsrs_tree_t* t, const double* Y, const double* Z,
+                              const double* Omega, const double* Psi, int64_t ld, int64_t s,
+                              void* stream, rsrs_samples_t** out);
+/* Draw Omega, Psi on the device with Philox-4x32-10 (Salmon et al., SC'11)
+ * and Box-Muller, then Y = A Omega and Z = A^T Psi through `mv`.  Element
+ * (user row i, column j) of Omega uses counter (i, j, 0, seed_hi) and key
+ * (seed_lo, 0x2311); Psi uses stream word 1 in place of 0. */
+rsrs_status rsrs_sample(const rsrs_tree_t* t, rsrs_matvec_fn mv, void* user, int64_t s,
+                        uint64_t seed, void* stream, rsrs_samples_t** out);
+void rsrs_samples_destroy(rsrs_samples_t* smp);
+
+/* Fill a device array with standard normals from the generator above:
+ * out[i*ld + j] for i < nrows, j < ncols uses counter (i, j, word, seed_hi). */
+rsrs_status rsrs_gaussian(double* out, int64_t nrows, int64_t ncols, int64_t ld, uint64_t seed,
+                          uint32_t word, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Factorization (Algorithm 1).  The samples are consumed: Algorithm 1
+ * updates them in place, so they cannot be reused afterwards.
+ *  s < rsrs_samples_required(t, k, p)  -> RSRS_E_SAMPLES
+ *  singular pivot block / root block   -> RSRS_E_SINGULAR
+ *  non-finite value in the samples     -> RSRS_E_NUMERIC
+ * The factor is device-resident and owned by the caller.
+ * ---------------------------------------------------------------------- */
+enum { RSRS_PREC_F64 = 0 };
+typedef struct {
+  int k;            /* fixed rank (k_B = min(k, b)) */
+  int p;            /* oversampling used in the sample check; < 0 -> p = k */
+  int precision;    /* RSRS_PREC_F64 */
+  int reproject;    /* extra projection passes in the nullification (0 or 1; default 1) */
+} rsrs_factor_opts;
+
+rsrs_status rsrs_factor(const rsrs_tree_t* t, rsrs_samples_t* smp, const rsrs_factor_opts* opts,
+                        void* stream, rsrs_factor_t** out);
+void rsrs_factor_destroy(rsrs_factor_t* f);
+
+typedef struct {
+  int64_t n, s, k;
+  int64_t nboxes;          /* processed boxes */
+  int64_t root_size;       /* |B_t| */
+  int64_t stored_doubles;  /* T, X_RR, X_RR^{-1}, K_U, K_L, root */
+  double flops;            /* algorithmic flop count of this factorization */
+  double factor_ms;        /* wall time of rsrs_factor (stream synchronised) */
+} rsrs_factor_info;
+rsrs_status rsrs_factor_get_info(const rsrs_factor_t* f, rsrs_factor_info* out);
+
+/* Per-box export for verification (box i in processing order).  Sizes first,
+ * then copies into caller host buffers (any pointer may be NULL to skip):
+ * Ba (b), Na (n), S (k), R (r) as tree positions; T r x k, XRR r x r,
+ * KU r x (k+n), KL (k+n) x r, row-major. */
+rsrs_status rsrs_factor_box_sizes(const rsrs_factor_t* f, int64_t i, int64_t* box, int32_t* level,
+                                  int32_t* colour, int64_t* b, int64_t* n, int64_t* r,
+                                  int64_t* k);
+rsrs_status rsrs_factor_box_copy(const rsrs_factor_t* f, int64_t i, int64_t* Ba, int64_t* Na,
+                                 int64_t* S, int64_t* R, double* T, double* XRR, double* KU,
+                                 double* KL);
+/* Root block: *nt = |B_t|; Bt (nt tree positions) and At (nt x nt row-major). */
+rsrs_status rsrs_factor_root_copy(const rsrs_factor_t* f, int64_t* nt, int64_t* Bt, double* At);
+
+/* ------------------------------------------------------------------------
+ * Using the factorization (eq. Afact and eq. Ainvfact).
+ *  rsrs_solve: U = A_approx^{-1} F (transpose = 0) or A_approx^{-T} F.
+ *  rsrs_apply: Y = A_approx X      (transpose = 0) or A_approx^T X.
+ * F, U, X, Y: device N x nrhs row-major blocks in user order; F == U (and
+ * X == Y) is allowed.  Stream-ordered, no host synchronisation.
+ * ---------------------------------------------------------------------- */
+rsrs_status rsrs_solve(const rsrs_factor_t* f, int transpose, int64_t nrhs, const double* F,
+                       int64_t ldf, double* U, int64_t ldu, void* stream);
+rsrs_status rsrs_apply(const rsrs_factor_t* f, int transpose, int64_t nrhs, const double* X,
+                       int64_t ldx, double* Y, int64_t ldy, void* stream);
+
+/* Iterative refinement u_{j+1} = u_j + A_approx^{-1} (f - A u_j) with the
+ * residual from the black-box product mv (FP64), until
+ * max_col ||f - A u||_2 / ||f||_2 <= tol or maxit corrections.  Returns
+ * RSRS_OK with *relres = the achieved value and *iters = corrections done
+ * (also when maxit is reached; compare *relres with tol).  Synchronises the
+ * stream once per step to read the residual norm. */
+rsrs_status rsrs_solve_refine(const rsrs_factor_t* f, rsrs_matvec_fn mv, void* user, int64_t nrhs,
+                              const double* F, int64_t ldf, double* U, int64_t ldu, double tol,
+                              int maxit, double* relres, int* iters, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RSRS_H */

@@ -1,0 +1,447 @@
+// extern "C" entry points of include/rsrs.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "impl.hpp"
+
+namespace rsrs {
+
+static thread_local std::string g_err;
+static thread_local int64_t g_req_s = -1;
+void set_error(const std::string& msg) { g_err = msg; }
+void set_required_s(int64_t s) { g_req_s = s; }
+
+rsrs_status factor_impl(const rsrs_tree_t* th, rsrs_samples_t* smp, const rsrs_factor_opts* o,
+                        hipStream_t st, rsrs_factor_t** out);
+rsrs_status apply_factor(const rsrs_factor_t* F, int op, int transpose, int64_t w, const double* Fin,
+                         int64_t ldf, double* Uout, int64_t ldu, hipStream_t st);
+
+static rsrs_status invalid(const char* msg) {
+  set_error(msg);
+  return RSRS_E_INVALID;
+}
+
+}  // namespace rsrs
+
+using namespace rsrs;
+
+extern "C" {
+
+const char* rsrs_status_string(rsrs_status st) {
+  switch (st) {
+    case RSRS_OK: return "ok";
+    case RSRS_E_INVALID: return "invalid argument";
+    case RSRS_E_SAMPLES: return "insufficient samples";
+    case RSRS_E_SINGULAR: return "singular block";
+    case RSRS_E_CALLBACK: return "matvec callback failed";
+    case RSRS_E_NUMERIC: return "non-finite value";
+    case RSRS_E_NOMEM: return "out of device memory";
+    case RSRS_E_HIP: return "HIP runtime error";
+    case RSRS_E_UNSUPPORTED: return "unsupported option";
+  }
+  return "unknown status";
+}
+
+const char* rsrs_last_error(void) { return g_err.c_str(); }
+int64_t rsrs_last_required_s(void) { return g_req_s; }
+
+// ------------------------------------------------------------------ tree
+rsrs_status rsrs_build_tree(const double* pts, int64_t n, const rsrs_tree_opts* o, rsrs_tree_t** out) {
+  if (!pts || !o || !out) return invalid("null argument");
+  *out = nullptr;
+  auto t = new rsrs_tree_t();
+  std::string err = build_tree(pts, n, o->dim, o->leaf_size, o->qbits, o->root_lo, o->root_side, t->t);
+  if (!err.empty()) {
+    delete t;
+    return invalid(err.c_str());
+  }
+  *out = t;
+  return RSRS_OK;
+}
+
+void rsrs_tree_destroy(rsrs_tree_t* t) { delete t; }
+
+rsrs_status rsrs_tree_get_info(const rsrs_tree_t* th, rsrs_tree_info* out) {
+  if (!th || !out) return invalid("null argument");
+  const Tree& t = th->t;
+  out->dim = t.dim;
+  out->nlevels = t.nlevels;
+  out->qbits = t.qbits;
+  out->n = t.n;
+  out->nbox = t.nbox();
+  out->level = t.level.data();
+  out->coords = t.coords.data();
+  out->parent = t.parent.data();
+  out->is_leaf = t.is_leaf.data();
+  out->pt_begin = t.pt_begin.data();
+  out->pt_end = t.pt_end.data();
+  out->perm = t.perm.data();
+  return RSRS_OK;
+}
+
+rsrs_status rsrs_tree_neighbours(const rsrs_tree_t* th, int level, int64_t* nb, const int64_t** boxes,
+                                 const int64_t** offsets, const int64_t** nbrs) {
+  if (!th || !nb || !boxes || !offsets || !nbrs) return invalid("null argument");
+  const Tree& t = th->t;
+  if (level < 1 || level > t.nlevels) return invalid("level out of range");
+  *nb = (int64_t)t.level_boxes[level].size();
+  *boxes = t.level_boxes[level].data();
+  *offsets = t.nb_off[level].data();
+  *nbrs = t.nb_ids[level].data();
+  return RSRS_OK;
+}
+
+rsrs_status rsrs_tree_schedule(const rsrs_tree_t* th, int k, int32_t* colour, int64_t* b_count,
+                               int64_t* l_count, int64_t* root_count) {
+  if (!th || k < 1) return invalid("bad tree or k");
+  Schedule s;
+  make_schedule(th->t, k, s);
+  const size_t nb = (size_t)th->t.nbox();
+  if (colour) std::memcpy(colour, s.colour.data(), nb * 4);
+  if (b_count) std::memcpy(b_count, s.b_count.data(), nb * 8);
+  if (l_count) std::memcpy(l_count, s.l_count.data(), nb * 8);
+  if (root_count) *root_count = s.root_count;
+  return RSRS_OK;
+}
+
+int64_t rsrs_samples_required(const rsrs_tree_t* th, int k, int p) {
+  if (!th || k < 1 || p < 0) return -1;
+  Schedule s;
+  make_schedule(th->t, k, s);
+  return samples_required(th->t, s, k, p);
+}
+
+// ------------------------------------------------------------------ operators
+rsrs_status rsrs_op_create_kernel(int kind, const double* pts, int64_t n, int dim, double param,
+                                  double param2, rsrs_operator_t** out) {
+  if (!pts || !out || n < 1) return invalid("bad operator arguments");
+  if (!((kind == RSRS_OP_LOG2D && dim == 2) || (kind == RSRS_OP_LOG2D_SKEW && dim == 2) ||
+        (kind == RSRS_OP_INVR3D && dim == 3)))
+    return invalid("unknown operator kind or wrong dimension");
+  *out = nullptr;
+  auto op = new rsrs_operator_t();
+  op->kind = kind;
+  op->n = n;
+  op->lda = n;
+  op->symmetric = kind != RSRS_OP_LOG2D_SKEW;
+  KernelOp ko;
+  ko.kind = kind;
+  ko.dim = dim;
+  ko.n = n;
+  ko.p1 = param;
+  ko.p2 = param2;
+  rsrs_status s = ko.pts.alloc((size_t)n * dim * 8);
+  if (s == RSRS_OK) s = op->owned.alloc((size_t)n * n * 8);
+  if (s != RSRS_OK) { delete op; return s; }
+  if (hipMemcpy(ko.pts.p, pts, (size_t)n * dim * 8, hipMemcpyHostToDevice) != hipSuccess) {
+    delete op;
+    set_error("hipMemcpy of points failed");
+    return RSRS_E_HIP;
+  }
+  s = kernel_materialise(nullptr, ko, op->owned.as<double>());
+  if (s == RSRS_OK && hipDeviceSynchronize() != hipSuccess) s = RSRS_E_HIP;
+  if (s != RSRS_OK) { delete op; return s; }
+  op->A = op->owned.as<double>();
+  *out = op;
+  return RSRS_OK;
+}
+
+rsrs_status rsrs_op_create_dense(const double* A, int64_t n, int64_t lda, rsrs_operator_t** out) {
+  if (!A || !out || n < 1 || lda < n) return invalid("bad dense operator arguments");
+  auto op = new rsrs_operator_t();
+  op->kind = 10;
+  op->n = n;
+  op->A = A;
+  op->lda = lda;
+  op->symmetric = false;
+  *out = op;
+  return RSRS_OK;
+}
+
+rsrs_status rsrs_op_create_poisson7(int n, const double* coef, rsrs_operator_t** out) {
+  if (!coef || !out || n < 1) return invalid("bad poisson arguments");
+  const int64_t N = (int64_t)n * n * n;
+  const int m = n + 2;
+  const double h = 1.0 / (n + 1), ih2 = 1.0 / (h * h);
+  std::vector<double> c((size_t)N * 7, 0.0);
+  auto a = [&](int z, int y, int x) { return coef[((int64_t)z * m + y) * m + x]; };
+  for (int z = 0; z < n; ++z)
+    for (int y = 0; y < n; ++y)
+      for (int x = 0; x < n; ++x) {
+        const int64_t i = ((int64_t)z * n + y) * n + x;
+        const double ai = a(z + 1, y + 1, x + 1);
+        const double nb[6] = {a(z + 1, y + 1, x), a(z + 1, y + 1, x + 2), a(z + 1, y, x + 1),
+                              a(z + 1, y + 2, x + 1), a(z, y + 1, x + 1), a(z + 2, y + 1, x + 1)};
+        double d = 0.0;
+        for (int f = 0; f < 6; ++f) {
+          const double face = 0.5 * (ai + nb[f]) * ih2;
+          d += face;
+          c[i * 7 + 1 + f] = -face;
+        }
+        c[i * 7] = d;
+      }
+  auto op = new rsrs_operator_t();
+  op->kind = 20;
+  op->n = N;
+  op->pois.n = n;
+  rsrs_status s = op->pois.coef.alloc(c.size() * 8);
+  if (s != RSRS_OK) { delete op; return s; }
+  if (hipMemcpy(op->pois.coef.p, c.data(), c.size() * 8, hipMemcpyHostToDevice) != hipSuccess) {
+    delete op;
+    set_error("hipMemcpy failed");
+    return RSRS_E_HIP;
+  }
+  *out = op;
+  return RSRS_OK;
+}
+
+int rsrs_op_matvec(void* opv, int transpose, int64_t ncols, const double* X, int64_t ldx, double* Y,
+                   int64_t ldy, void* stream) {
+  auto op = static_cast<rsrs_operator_t*>(opv);
+  if (!op || !X || !Y || ncols < 0) return 1;
+  if (ncols == 0) return 0;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (op->kind == 20) return poisson_matvec(st, op->pois, ncols, X, ldx, Y, ldy) == RSRS_OK ? 0 : 1;
+  if (!op->up_ready) {
+    if (op->up.init((size_t)1 << 20, st) != RSRS_OK) return 1;
+    op->up_ready = true;
+  }
+  if (op->up.st != st) {
+    if (op->up.reset() != RSRS_OK) return 1;
+    op->up.st = st;
+  }
+  const int n = (int)op->n;
+  std::vector<GemmDesc> d{gdesc(op->A, nullptr, op->lda, X, nullptr, ldx, Y, nullptr, ldy, n,
+                                (int)ncols, n)};
+  const int ta = (transpose && !op->symmetric) ? 1 : 0;
+  return gemm(op->up, st, d, ta, 0, GM_FULL, ncols <= 16 ? GS_64x16 : GS_64x64) == RSRS_OK ? 0 : 1;
+}
+
+void rsrs_op_destroy(rsrs_operator_t* op) { delete op; }
+
+// ------------------------------------------------------------------ samples
+static rsrs_status new_samples(const rsrs_tree_t* th, int64_t s, rsrs_samples_t** out) {
+  auto smp = new rsrs_samples_t();
+  smp->tree = th;
+  smp->n = th->t.n;
+  smp->s = s;
+  smp->ld = round_up(s, 16);
+  const size_t bytes = (size_t)smp->n * smp->ld * 8;
+  rsrs_status st = smp->Y.alloc(bytes);
+  if (st == RSRS_OK) st = smp->Z.alloc(bytes);
+  if (st == RSRS_OK) st = smp->Om.alloc(bytes);
+  if (st == RSRS_OK) st = smp->Psi.alloc(bytes);
+  if (st != RSRS_OK) { delete smp; return st; }
+  *out = smp;
+  return RSRS_OK;
+}
+
+rsrs_status rsrs_samples_wrap(const rsrs_tree_t* th, const double* Y, const double* Z, const double* Om,
+                              const double* Psi, int64_t ld, int64_t s, void* stream,
+                              rsrs_samples_t** out) {
+  if (!th || !Y || !Z || !Om || !Psi || !out || s < 1 || ld < s) return invalid("bad samples arguments");
+  *out = nullptr;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  rsrs_samples_t* smp = nullptr;
+  RSRS_TRY(new_samples(th, s, &smp));
+  DevBuf perm;
+  rsrs_status r = perm.alloc((size_t)smp->n * 8);
+  if (r != RSRS_OK) { delete smp; return r; }
+  if (hipMemcpyAsync(perm.p, th->t.perm.data(), (size_t)smp->n * 8, hipMemcpyHostToDevice, st) != hipSuccess) {
+    delete smp;
+    set_error("hipMemcpyAsync failed");
+    return RSRS_E_HIP;
+  }
+  const int64_t* pp = perm.as<int64_t>();
+  gather_rows(st, smp->Y.as<double>(), smp->ld, Y, ld, pp, smp->n, s);
+  gather_rows(st, smp->Z.as<double>(), smp->ld, Z, ld, pp, smp->n, s);
+  gather_rows(st, smp->Om.as<double>(), smp->ld, Om, ld, pp, smp->n, s);
+  gather_rows(st, smp->Psi.as<double>(), smp->ld, Psi, ld, pp, smp->n, s);
+  if (hipStreamSynchronize(st) != hipSuccess) {
+    delete smp;
+    set_error("stream synchronisation failed");
+    return RSRS_E_HIP;
+  }
+  *out = smp;
+  return RSRS_OK;
+}
+
+rsrs_status rsrs_sample(const rsrs_tree_t* th, rsrs_matvec_fn mv, void* user, int64_t s, uint64_t seed,
+                        void* stream, rsrs_samples_t** out) {
+  if (!th || !mv || !out || s < 1) return invalid("bad sample arguments");
+  *out = nullptr;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  rsrs_samples_t* smp = nullptr;
+  RSRS_TRY(new_samples(th, s, &smp));
+  DevBuf tu, ty, perm;
+  const size_t bytes = (size_t)smp->n * smp->ld * 8;
+  rsrs_status r = tu.alloc(bytes);
+  if (r == RSRS_OK) r = ty.alloc(bytes);
+  if (r == RSRS_OK) r = perm.alloc((size_t)smp->n * 8);
+  if (r != RSRS_OK) { delete smp; return r; }
+  (void)hipMemcpyAsync(perm.p, th->t.perm.data(), (size_t)smp->n * 8, hipMemcpyHostToDevice, st);
+  const int64_t* pp = perm.as<int64_t>();
+  for (int side = 0; side < 2; ++side) {
+    philox_normal(st, tu.as<double>(), smp->n, s, smp->ld, seed, (uint32_t)side);
+    if (mv(user, side, s, tu.as<double>(), smp->ld, ty.as<double>(), smp->ld, stream) != 0) {
+      (void)hipStreamSynchronize(st);
+      delete smp;
+      set_error("matvec callback returned nonzero");
+      return RSRS_E_CALLBACK;
+    }
+    gather_rows(st, (side ? smp->Psi : smp->Om).as<double>(), smp->ld, tu.as<double>(), smp->ld, pp, smp->n, s);
+    gather_rows(st, (side ? smp->Z : smp->Y).as<double>(), smp->ld, ty.as<double>(), smp->ld, pp, smp->n, s);
+  }
+  if (hipStreamSynchronize(st) != hipSuccess) {
+    delete smp;
+    set_error(std::string("sampling failed: ") + hipGetErrorString(hipGetLastError()));
+    return RSRS_E_HIP;
+  }
+  *out = smp;
+  return RSRS_OK;
+}
+
+void rsrs_samples_destroy(rsrs_samples_t* smp) { delete smp; }
+
+rsrs_status rsrs_gaussian(double* out, int64_t nrows, int64_t ncols, int64_t ld, uint64_t seed,
+                          uint32_t word, void* stream) {
+  if (!out || nrows < 0 || ncols < 0 || ld < ncols) return invalid("bad gaussian arguments");
+  philox_normal(static_cast<hipStream_t>(stream), out, nrows, ncols, ld, seed, word);
+  if (hipGetLastError() != hipSuccess) { set_error("philox launch failed"); return RSRS_E_HIP; }
+  return RSRS_OK;
+}
+
+// ------------------------------------------------------------------ factor
+rsrs_status rsrs_factor(const rsrs_tree_t* t, rsrs_samples_t* smp, const rsrs_factor_opts* opts,
+                        void* stream, rsrs_factor_t** out) {
+  if (!t || !smp || !opts || !out) return invalid("null argument");
+  *out = nullptr;
+  return factor_impl(t, smp, opts, static_cast<hipStream_t>(stream), out);
+}
+
+void rsrs_factor_destroy(rsrs_factor_t* f) { delete f; }
+
+rsrs_status rsrs_factor_get_info(const rsrs_factor_t* f, rsrs_factor_info* out) {
+  if (!f || !out) return invalid("null argument");
+  out->n = f->n;
+  out->s = f->s;
+  out->k = f->k;
+  out->nboxes = (int64_t)f->boxes.size();
+  out->root_size = f->nt;
+  out->stored_doubles = f->stored_doubles;
+  out->flops = f->flops;
+  out->factor_ms = f->factor_ms;
+  return RSRS_OK;
+}
+
+rsrs_status rsrs_factor_box_sizes(const rsrs_factor_t* f, int64_t i, int64_t* box, int32_t* level,
+                                  int32_t* colour, int64_t* b, int64_t* n, int64_t* r, int64_t* k) {
+  if (!f || i < 0 || i >= (int64_t)f->boxes.size()) return invalid("box index out of range");
+  const BoxRec& R = f->boxes[i];
+  if (box) *box = R.box;
+  if (level) *level = R.level;
+  if (colour) *colour = R.colour;
+  if (b) *b = R.b;
+  if (n) *n = R.n;
+  if (r) *r = R.r;
+  if (k) *k = R.k;
+  return RSRS_OK;
+}
+
+static rsrs_status d2h(void* dst, const void* src, size_t bytes) {
+  if (!dst || bytes == 0) return RSRS_OK;
+  RSRS_HIP(hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost));
+  return RSRS_OK;
+}
+
+rsrs_status rsrs_factor_box_copy(const rsrs_factor_t* f, int64_t i, int64_t* Ba, int64_t* Na, int64_t* S,
+                                 int64_t* R, double* T, double* XRR, double* KU, double* KL) {
+  if (!f || i < 0 || i >= (int64_t)f->boxes.size()) return invalid("box index out of range");
+  RSRS_HIP(hipDeviceSynchronize());
+  const BoxRec& B = f->boxes[i];
+  const int64_t kn = B.k + B.n;
+  RSRS_TRY(d2h(Ba, f->i() + B.oBa, (size_t)B.b * 8));
+  RSRS_TRY(d2h(Na, f->i() + B.oNa, (size_t)B.n * 8));
+  RSRS_TRY(d2h(S, f->i() + B.oS, (size_t)B.k * 8));
+  RSRS_TRY(d2h(R, f->i() + B.oR, (size_t)B.r * 8));
+  RSRS_TRY(d2h(T, f->d() + B.oT, (size_t)B.r * B.k * 8));
+  RSRS_TRY(d2h(XRR, f->d() + B.oXRR, (size_t)B.r * B.r * 8));
+  RSRS_TRY(d2h(KU, f->d() + B.oKU, (size_t)B.r * kn * 8));
+  RSRS_TRY(d2h(KL, f->d() + B.oKL, (size_t)kn * B.r * 8));
+  return RSRS_OK;
+}
+
+rsrs_status rsrs_factor_root_copy(const rsrs_factor_t* f, int64_t* nt, int64_t* Bt, double* At) {
+  if (!f) return invalid("null factor");
+  RSRS_HIP(hipDeviceSynchronize());
+  if (nt) *nt = f->nt;
+  RSRS_TRY(d2h(Bt, f->i() + f->oBt, (size_t)f->nt * 8));
+  RSRS_TRY(d2h(At, f->d() + f->oAt, (size_t)f->nt * f->nt * 8));
+  return RSRS_OK;
+}
+
+// ------------------------------------------------------------------ solve / apply / refine
+rsrs_status rsrs_solve(const rsrs_factor_t* f, int transpose, int64_t nrhs, const double* F, int64_t ldf,
+                       double* U, int64_t ldu, void* stream) {
+  if (!f || !F || !U || nrhs < 0 || ldf < nrhs || ldu < nrhs) return invalid("bad solve arguments");
+  return apply_factor(f, 0, transpose, nrhs, F, ldf, U, ldu, static_cast<hipStream_t>(stream));
+}
+
+rsrs_status rsrs_apply(const rsrs_factor_t* f, int transpose, int64_t nrhs, const double* X, int64_t ldx,
+                       double* Y, int64_t ldy, void* stream) {
+  if (!f || !X || !Y || nrhs < 0 || ldx < nrhs || ldy < nrhs) return invalid("bad apply arguments");
+  return apply_factor(f, 1, transpose, nrhs, X, ldx, Y, ldy, static_cast<hipStream_t>(stream));
+}
+
+rsrs_status rsrs_solve_refine(const rsrs_factor_t* f, rsrs_matvec_fn mv, void* user, int64_t nrhs,
+                              const double* F, int64_t ldf, double* U, int64_t ldu, double tol,
+                              int maxit, double* relres, int* iters, void* stream) {
+  if (!f || !mv || !F || !U || nrhs < 1 || ldf < nrhs || ldu < nrhs || maxit < 0)
+    return invalid("bad refine arguments");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t n = f->n, w = nrhs;
+  RSRS_TRY(f->wt.alloc((size_t)n * w * 8));
+  RSRS_TRY(f->wpart.alloc((size_t)256 * w * 8));
+  RSRS_TRY(f->wnorm.alloc((size_t)2 * w * 8));
+  double* r = f->wt.as<double>();
+  double* nrm = f->wnorm.as<double>();
+  std::vector<double> fn(w), rn(w);
+  RSRS_TRY(col_sumsq(st, F, n, w, ldf, f->wpart.as<double>(), nrm));
+  RSRS_HIP(hipMemcpyAsync(fn.data(), nrm, (size_t)w * 8, hipMemcpyDeviceToHost, st));
+  RSRS_TRY(apply_factor(f, 0, 0, w, F, ldf, U, ldu, st));
+  double rel = 0.0;
+  int it = 0;
+  for (;;) {
+    if (mv(user, 0, w, U, ldu, r, w, stream) != 0) {
+      set_error("matvec callback returned nonzero");
+      return RSRS_E_CALLBACK;
+    }
+    sub2d(st, F, ldf, r, w, r, w, n, w);
+    RSRS_TRY(col_sumsq(st, r, n, w, w, f->wpart.as<double>(), nrm));
+    RSRS_HIP(hipMemcpyAsync(rn.data(), nrm, (size_t)w * 8, hipMemcpyDeviceToHost, st));
+    RSRS_HIP(hipStreamSynchronize(st));
+    rel = 0.0;
+    for (int64_t c = 0; c < w; ++c) {
+      const double d = fn[c] > 0.0 ? std::sqrt(rn[c] / fn[c]) : std::sqrt(rn[c]);
+      if (!std::isfinite(d)) {
+        set_error("non-finite residual");
+        return RSRS_E_NUMERIC;
+      }
+      rel = std::max(rel, d);
+    }
+    if (rel <= tol || it >= maxit) break;
+    RSRS_TRY(apply_factor(f, 0, 0, w, r, w, r, w, st));
+    std::vector<Copy2D> c{Copy2D{r, U, w, ldu, (int)n, (int)w, 1.0, 1, 0}};
+    RSRS_TRY(copy2d(f->up, st, c));
+    ++it;
+  }
+  if (relres) *relres = rel;
+  if (iters) *iters = it;
+  return RSRS_OK;
+}
+
+}  // extern "C"

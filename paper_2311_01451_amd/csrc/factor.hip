@@ -1,0 +1,545 @@
+// Algorithm 1 (randomized strong recursive skeletonization), host orchestration.
+//
+// Levels run from the finest to the coarsest; inside a level, the colour
+// classes of the schedule (tree.cpp) run one after another and all boxes of a
+// class are processed together by batched kernels.  Boxes of one class touch
+// disjoint rows of Y, Z, Omega, Psi, so the batched result equals processing
+// them one at a time.  Per class:
+//
+//  phase A  Gram matrices G = C C^T of the test-matrix panels
+//           C_Omega = [Omega_Ba; Omega_Na], C_Psi likewise (l x s each);
+//           Cholesky G = L L^T and L^{-1} (recursive, GEMM-shaped);
+//           least-squares coefficients X = Y_B pinv(C) = (Y_B C^T) L^{-T} L^{-1}
+//           and the far-field sketch M_Y = Y_B - X C_Omega, i.e. Y_B times the
+//           projector onto null(C_Omega) (eq. nullYZ); one optional second
+//           pass re-projects M_Y and refines X.  Same for Z / Psi.
+//           ID of M = M_Y + M_Z by pivoted Gram-Schmidt (Sec. 2.3).
+//  phase B  Block extraction (eq. pinvYZ) from the same coefficients: since
+//           Y_hat_R = Y_R - T Y_S and Omega_hat_C = G_T Omega_C with
+//           G_T = I + e_S T^T e_R^T, Y_hat_R pinv(Omega_hat_C) =
+//           (X_R - T X_S) G_T^{-1}; G_T^{-1} subtracts columns S T^T from
+//           columns R.  X_RR^{-1} by Gauss-Jordan, K_U = X_RR^{-1} X_{R,SN},
+//           K_L = X_{SN,R} X_RR^{-1}; then the sketch updates of Algorithm 1:
+//           E, F (sparsify) followed by L, U (eliminate).
+//  root     A_t = Y_Bt pinv(Omega_Bt) by the same Gram route, then A_t^{-1}.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <numeric>
+#include <unordered_map>
+
+#include "impl.hpp"
+
+namespace rsrs {
+
+namespace {
+
+struct CholMat {
+  double* G;
+  double* L;
+  int64_t ld;
+  int n;
+};
+
+constexpr int kLeaf = 64;
+
+// Recursive Cholesky with inverse factor on the index range [a, b) shared by
+// all matrices of the batch (each clipped to its own size n).
+rsrs_status rchol(Uploader& up, hipStream_t st, const std::vector<CholMat>& mats, int a, int b,
+                  int* flag) {
+  if (b - a <= kLeaf) {
+    std::vector<CholLeaf> e;
+    for (const auto& m : mats) {
+      const int hi = std::min(b, m.n);
+      if (hi <= a) continue;
+      e.push_back(CholLeaf{m.G + (int64_t)a * m.ld + a, m.L + (int64_t)a * m.ld + a, m.ld, hi - a, 0});
+    }
+    return chol_leaf(up, st, e, flag);
+  }
+  const int nblk = (b - a + kLeaf - 1) / kLeaf;
+  const int h = a + kLeaf * ((nblk + 1) / 2);
+  RSRS_TRY(rchol(up, st, mats, a, h, flag));
+  std::vector<GemmDesc> g1, g2, g4, g5;
+  for (const auto& m : mats) {
+    const int hi = std::min(b, m.n);
+    if (hi <= h) continue;
+    const int rows = hi - h, w = h - a;
+    double* G21 = m.G + (int64_t)h * m.ld + a;
+    double* L11 = m.L + (int64_t)a * m.ld + a;
+    double* L21 = m.L + (int64_t)h * m.ld + a;
+    double* G22 = m.G + (int64_t)h * m.ld + h;
+    double* L22 = m.L + (int64_t)h * m.ld + h;
+    // (1) T1 = A21 L11^{-T} -> L21 slot
+    g1.push_back(gdesc(G21, nullptr, m.ld, L11, nullptr, m.ld, L21, nullptr, m.ld, rows, w, w));
+    // (2) A22 -= T1 T1^T (lower)
+    g2.push_back(gdesc(L21, nullptr, m.ld, L21, nullptr, m.ld, G22, nullptr, m.ld, rows, rows, w,
+                       -1.0, 1.0));
+    // (4) W = T1 L11^{-1} -> G21 slot (A21 is dead)
+    g4.push_back(gdesc(L21, nullptr, m.ld, L11, nullptr, m.ld, G21, nullptr, m.ld, rows, w, w));
+    // (5) L21^{-1} block = -L22^{-1} W
+    g5.push_back(gdesc(L22, nullptr, m.ld, G21, nullptr, m.ld, L21, nullptr, m.ld, rows, w, rows,
+                       -1.0, 0.0));
+  }
+  RSRS_TRY(gemm(up, st, g1, 0, 1, GM_B_NT_LOW));
+  RSRS_TRY(gemm(up, st, g2, 0, 1, GM_SYRK_L));
+  RSRS_TRY(gemm(up, st, g4, 0, 0, GM_B_NN_LOW));
+  RSRS_TRY(rchol(up, st, mats, h, b, flag));
+  RSRS_TRY(gemm(up, st, g5, 0, 0, GM_A_LOW));
+  return RSRS_OK;
+}
+
+struct Bump {
+  char* base = nullptr;
+  size_t off = 0, cap = 0;
+  template <class T> T* take(int64_t count) {
+    off = (size_t)round_up((int64_t)off, 256);
+    T* p = reinterpret_cast<T*>(base + off);
+    off += (size_t)count * sizeof(T);
+    return p;
+  }
+};
+
+// Workspace bytes of one box (b, l) in a class.
+size_t box_ws_bytes(int64_t b, int64_t l, int64_t k, int64_t sp) {
+  const int64_t lp = round_up(l, 16);
+  const int64_t r = b - k;
+  int64_t dbl = 4 * l * lp        // G, L for both sides
+                + 6 * b * lp      // P, W, X for both sides
+                + 2 * b * sp      // M_Y, M_Z
+                + 2 * b + b * k   // norms, R coefficients
+                + 4 * r * lp      // XR, Xp for both sides
+                + 2 * r * r;      // Gauss-Jordan work
+  int64_t ints = b + k;           // sel, piv (int32)
+  int64_t i64 = k + b;            // Spos, Rpos
+  return (size_t)(dbl * 8 + ints * 4 + i64 * 8 + 24 * 256);
+}
+
+struct BoxWs {
+  int64_t lp;
+  double *GO, *GP, *LO, *LP, *PY, *WY, *XY, *PZ, *WZ, *XZ, *MY, *MZ, *norms, *Rc;
+  double *XRy, *XRz, *Xpy, *Xpz, *gje;
+  int32_t *sel, *piv;
+  int64_t *Spos, *Rpos;
+};
+
+}  // namespace
+
+rsrs_status factor_impl(const rsrs_tree_t* th, rsrs_samples_t* smp, const rsrs_factor_opts* o,
+                        hipStream_t st, rsrs_factor_t** out) {
+  auto t0 = std::chrono::steady_clock::now();
+  const Tree& t = th->t;
+  const int k = o->k;
+  const int p = o->p < 0 ? k : o->p;
+  const int reproject = o->reproject;
+  if (k < 1) { set_error("k must be >= 1"); return RSRS_E_INVALID; }
+  if (o->precision != RSRS_PREC_F64) { set_error("only RSRS_PREC_F64 is implemented"); return RSRS_E_UNSUPPORTED; }
+  if (smp->consumed) { set_error("samples were already consumed by a factorization"); return RSRS_E_INVALID; }
+  if (smp->tree != th) { set_error("samples belong to another tree"); return RSRS_E_INVALID; }
+  if (k > 256) { set_error("k > 256 is not supported"); return RSRS_E_UNSUPPORTED; }
+  Schedule sch;
+  make_schedule(t, k, sch);
+  const int64_t need = samples_required(t, sch, k, p);
+  if (smp->s < need) {
+    set_required_s(need);
+    set_error("s = " + std::to_string(smp->s) + " is below the required " + std::to_string(need));
+    return RSRS_E_SAMPLES;
+  }
+  const int64_t s = smp->s, sld = smp->ld, n = t.n;
+  double* Y = smp->Y.as<double>();
+  double* Z = smp->Z.as<double>();
+  double* Om = smp->Om.as<double>();
+  double* Psi = smp->Psi.as<double>();
+
+  auto F = std::make_unique<rsrs_factor_t>();
+  F->n = n;
+  F->s = s;
+  F->k = k;
+
+  // ---- storage layout from the schedule (sizes are fixed by the count model)
+  int64_t dsz = 0, isz = 0;
+  size_t ws_max = 0;
+  for (size_t li = 0; li < sch.levels.size(); ++li) {
+    for (size_t c = 0; c < sch.classes[li].size(); ++c) {
+      Group g;
+      g.first = (int64_t)F->boxes.size();
+      size_t ws = 0;
+      for (int64_t b : sch.classes[li][c]) {
+        BoxRec r;
+        r.box = b;
+        r.level = sch.levels[li];
+        r.colour = (int)c;
+        r.b = sch.b_count[b];
+        r.n = sch.l_count[b] - r.b;
+        r.k = k;
+        r.r = r.b - k;
+        r.oT = dsz; dsz += r.r * k;
+        r.oXRR = dsz; dsz += r.r * r.r;
+        r.oXinv = dsz; dsz += r.r * r.r;
+        r.oKU = dsz; dsz += r.r * (k + r.n);
+        r.oKL = dsz; dsz += (k + r.n) * r.r;
+        r.oR = isz; isz += r.r;
+        r.oS = isz; isz += k;
+        r.oNa = isz; isz += r.n;
+        r.oBa = isz; isz += r.b + r.n;   // Ba followed by a second copy of Na
+        F->boxes.push_back(r);
+        ws += box_ws_bytes(r.b, r.b + r.n, k, sld);
+      }
+      g.count = (int64_t)F->boxes.size() - g.first;
+      F->groups.push_back(g);
+      ws_max = std::max(ws_max, ws);
+    }
+  }
+  F->nt = sch.root_count;
+  F->oBt = isz; isz += F->nt;
+  F->oAt = dsz; dsz += F->nt * F->nt;
+  F->oAtinv = dsz; dsz += F->nt * F->nt;
+  F->stored_doubles = dsz;
+  const int64_t ntp = round_up(F->nt, 16);
+  const size_t root_ws = (size_t)(4 * F->nt * ntp + F->nt * round_up(s, 16) + 2 * F->nt * F->nt) * 8 + 8 * 256;
+  ws_max = std::max(ws_max, root_ws);
+
+  RSRS_TRY(F->dstore.alloc((size_t)std::max<int64_t>(dsz, 1) * 8));
+  RSRS_TRY(F->istore.alloc((size_t)std::max<int64_t>(isz, 1) * 8));
+  RSRS_TRY(F->perm.alloc((size_t)n * 8));
+  DevBuf ws, flagbuf;
+  RSRS_TRY(ws.alloc(ws_max));
+  RSRS_TRY(flagbuf.alloc(256));
+  int* flag = flagbuf.as<int>();
+  RSRS_HIP(hipMemsetAsync(flag, 0, sizeof(int), st));
+  double* dS = F->dstore.as<double>();
+  int64_t* iS = F->istore.as<int64_t>();
+
+  Uploader up;
+  RSRS_TRY(up.init((size_t)64 << 20, st));
+  RSRS_HIP(hipMemcpyAsync(F->perm.p, t.perm.data(), (size_t)n * 8, hipMemcpyHostToDevice, st));
+  // non-finite samples are rejected up front
+  check_finite(st, Y, n, s, sld, flag);
+  check_finite(st, Z, n, s, sld, flag);
+  check_finite(st, Om, n, s, sld, flag);
+  check_finite(st, Psi, n, s, sld, flag);
+  RSRS_TRY(up.reset());
+  {
+    int hflag = 0;
+    RSRS_HIP(hipMemcpy(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost));
+    if (hflag & 4) { set_error("non-finite value in the samples"); return RSRS_E_NUMERIC; }
+  }
+
+  // staging for index uploads into the factor store
+  HostBuf hidx;
+  RSRS_TRY(hidx.alloc((size_t)std::max<int64_t>(isz, 1) * 8));
+  int64_t* hI = hidx.as<int64_t>();
+  HostBuf hpos;
+
+  double flops = 0.0;
+  const int64_t nbox = t.nbox();
+  std::vector<std::vector<int64_t>> cur(nbox), remaining(nbox);
+  auto leaf_range = [&](int64_t b) {
+    std::vector<int64_t> v((size_t)t.npts(b));
+    std::iota(v.begin(), v.end(), t.pt_begin[b]);
+    return v;
+  };
+
+  size_t gi = 0;
+  for (size_t li = 0; li < sch.levels.size(); ++li) {
+    const int lev = sch.levels[li];
+    const auto& lb = t.level_boxes[lev];
+    std::unordered_map<int64_t, size_t> pos;
+    for (size_t i = 0; i < lb.size(); ++i) {
+      const int64_t b = lb[i];
+      pos[b] = i;
+      if (t.is_leaf[b]) {
+        cur[b] = leaf_range(b);
+      } else {
+        std::vector<int64_t> v;
+        for (int64_t j = t.child_off[b]; j < t.child_off[b + 1]; ++j) {
+          const auto& rc = remaining[t.child_ids[j]];
+          v.insert(v.end(), rc.begin(), rc.end());
+        }
+        std::sort(v.begin(), v.end());
+        cur[b] = std::move(v);
+      }
+    }
+    auto active_of = [&](int64_t x) -> const std::vector<int64_t>& {
+      if (t.level[x] < lev && cur[x].empty()) cur[x] = leaf_range(x);
+      return cur[x];
+    };
+    for (size_t c = 0; c < sch.classes[li].size(); ++c, ++gi) {
+      const Group& g = F->groups[gi];
+      const int64_t nb = g.count;
+      // ---- host index lists and factor-store uploads (Ba, Na, Na copy)
+      std::vector<std::vector<int64_t>> Ba(nb), Na(nb);
+      for (int64_t q = 0; q < nb; ++q) {
+        BoxRec& R = F->boxes[g.first + q];
+        const size_t ip = pos.at(R.box);
+        Ba[q] = cur[R.box];
+        std::vector<int64_t> v;
+        for (int64_t j = t.nb_off[lev][ip]; j < t.nb_off[lev][ip + 1]; ++j) {
+          const auto& a = active_of(t.nb_ids[lev][j]);
+          v.insert(v.end(), a.begin(), a.end());
+        }
+        std::sort(v.begin(), v.end());
+        Na[q] = std::move(v);
+        if ((int64_t)Ba[q].size() != R.b || (int64_t)Na[q].size() != R.n) {
+          set_error("internal: active sets disagree with the count model");
+          return RSRS_E_INVALID;
+        }
+        std::memcpy(hI + R.oNa, Na[q].data(), R.n * 8);
+        std::memcpy(hI + R.oBa, Ba[q].data(), R.b * 8);
+        std::memcpy(hI + R.oBa + R.b, Na[q].data(), R.n * 8);
+        RSRS_HIP(hipMemcpyAsync(iS + R.oNa, hI + R.oNa, (size_t)(R.n + R.b + R.n) * 8,
+                                hipMemcpyHostToDevice, st));
+      }
+      // ---- workspace
+      Bump bump{ws.as<char>(), 0, ws.bytes};
+      std::vector<BoxWs> W(nb);
+      for (int64_t q = 0; q < nb; ++q) {
+        const BoxRec& R = F->boxes[g.first + q];
+        const int64_t l = R.b + R.n, lp = round_up(l, 16), b = R.b, r = R.r;
+        BoxWs& w = W[q];
+        w.lp = lp;
+        w.GO = bump.take<double>(l * lp); w.GP = bump.take<double>(l * lp);
+        w.LO = bump.take<double>(l * lp); w.LP = bump.take<double>(l * lp);
+        w.PY = bump.take<double>(b * lp); w.WY = bump.take<double>(b * lp); w.XY = bump.take<double>(b * lp);
+        w.PZ = bump.take<double>(b * lp); w.WZ = bump.take<double>(b * lp); w.XZ = bump.take<double>(b * lp);
+        w.MY = bump.take<double>(b * sld); w.MZ = bump.take<double>(b * sld);
+        w.norms = bump.take<double>(2 * b); w.Rc = bump.take<double>(b * k);
+        w.XRy = bump.take<double>(r * lp); w.XRz = bump.take<double>(r * lp);
+        w.Xpy = bump.take<double>(r * lp); w.Xpz = bump.take<double>(r * lp);
+        w.gje = bump.take<double>(2 * r * r);
+        w.sel = bump.take<int32_t>(b); w.piv = bump.take<int32_t>(k);
+        w.Spos = bump.take<int64_t>(k); w.Rpos = bump.take<int64_t>(b);
+      }
+      // ---- phase A: Gram matrices
+      std::vector<GemmDesc> gd;
+      std::vector<CholMat> cm;
+      int lmax = 0;
+      for (int64_t q = 0; q < nb; ++q) {
+        const BoxRec& R = F->boxes[g.first + q];
+        const BoxWs& w = W[q];
+        const int l = (int)(R.b + R.n);
+        const int64_t* idxC = iS + R.oBa;
+        gd.push_back(gdesc(Om, idxC, sld, Om, idxC, sld, w.GO, nullptr, w.lp, l, l, (int)s));
+        gd.push_back(gdesc(Psi, idxC, sld, Psi, idxC, sld, w.GP, nullptr, w.lp, l, l, (int)s));
+        cm.push_back(CholMat{w.GO, w.LO, w.lp, l});
+        cm.push_back(CholMat{w.GP, w.LP, w.lp, l});
+        lmax = std::max(lmax, l);
+        const double dl = l, db = (double)R.b, ds = (double)s;
+        flops += 2.0 * dl * dl * ds                               // two Gram matrices
+                 + 2.0 * (2.0 / 3.0) * dl * dl * dl               // Cholesky + inverse factor
+                 + (1.0 + reproject) * 2.0 * (4.0 * db * dl * ds + 2.0 * db * dl * dl);  // projections
+      }
+      RSRS_TRY(gemm(up, st, gd, 0, 1, GM_SYRK_L));
+      RSRS_TRY(rchol(up, st, cm, 0, lmax, flag));
+      // ---- projections (eq. nullYZ) and least-squares coefficients
+      for (int pass = 0; pass <= reproject; ++pass) {
+        std::vector<GemmDesc> gp, gw, gx, gm;
+        std::vector<Copy2D> acc;
+        for (int64_t q = 0; q < nb; ++q) {
+          const BoxRec& R = F->boxes[g.first + q];
+          const BoxWs& w = W[q];
+          const int l = (int)(R.b + R.n), b = (int)R.b;
+          const int64_t* idxB = iS + R.oBa;
+          const int64_t* idxC = iS + R.oBa;
+          for (int side = 0; side < 2; ++side) {
+            double* Ysd = side ? Z : Y;
+            double* Tst = side ? Psi : Om;
+            double* Pb = side ? w.PZ : w.PY;
+            double* Wb = side ? w.WZ : w.WY;
+            double* Xb = side ? w.XZ : w.XY;
+            double* Mb = side ? w.MZ : w.MY;
+            double* Lb = side ? w.LP : w.LO;
+            double* Xout = pass == 0 ? Xb : Pb;   // second pass: correction into P
+            if (pass == 0)
+              gp.push_back(gdesc(Ysd, idxB, sld, Tst, idxC, sld, Pb, nullptr, w.lp, b, l, (int)s));
+            else
+              gp.push_back(gdesc(Mb, nullptr, sld, Tst, idxC, sld, Pb, nullptr, w.lp, b, l, (int)s));
+            gw.push_back(gdesc(Pb, nullptr, w.lp, Lb, nullptr, w.lp, Wb, nullptr, w.lp, b, l, l));
+            gx.push_back(gdesc(Wb, nullptr, w.lp, Lb, nullptr, w.lp, Xout, nullptr, w.lp, b, l, l));
+            if (pass == 0)
+              gm.push_back(gdesc(Xout, nullptr, w.lp, Tst, idxC, sld, Mb, nullptr, sld, b, (int)s, l,
+                                 -1.0, 1.0, Ysd, idxB, sld));
+            else
+              gm.push_back(gdesc(Xout, nullptr, w.lp, Tst, idxC, sld, Mb, nullptr, sld, b, (int)s, l,
+                                 -1.0, 1.0));
+            if (pass == 1) acc.push_back(Copy2D{Pb, Xb, w.lp, w.lp, b, l, 1.0, 1, 0});
+          }
+        }
+        RSRS_TRY(gemm(up, st, gp, 0, 1, GM_FULL));
+        RSRS_TRY(gemm(up, st, gw, 0, 1, GM_B_NT_LOW));
+        RSRS_TRY(gemm(up, st, gx, 0, 0, GM_B_NN_LOW));
+        RSRS_TRY(gemm(up, st, gm, 0, 0, GM_FULL));
+        RSRS_TRY(copy2d(up, st, acc));
+      }
+      // ---- interpolative decomposition of M = M_Y + M_Z
+      std::vector<IdDesc> idd;
+      for (int64_t q = 0; q < nb; ++q) {
+        const BoxRec& R = F->boxes[g.first + q];
+        const BoxWs& w = W[q];
+        IdDesc e{};
+        e.M = w.MY; e.MZ = w.MZ; e.ldm = sld; e.ldz = sld;
+        e.norms = w.norms; e.sel = w.sel; e.Rc = w.Rc; e.piv = w.piv;
+        e.Spos = w.Spos; e.Rpos = w.Rpos; e.T = dS + R.oT;
+        e.b = (int)R.b; e.s = (int)s; e.k = k;
+        idd.push_back(e);
+        flops += 4.0 * R.b * s * k;
+      }
+      RSRS_TRY(id_run(up, st, idd));
+      // ---- skeleton sets back to the host
+      int64_t nposn = 0;
+      for (int64_t q = 0; q < nb; ++q) nposn += F->boxes[g.first + q].b;
+      RSRS_TRY(hpos.alloc((size_t)nposn * 8));
+      {
+        int64_t o2 = 0;
+        for (int64_t q = 0; q < nb; ++q) {
+          const BoxRec& R = F->boxes[g.first + q];
+          RSRS_HIP(hipMemcpyAsync(hpos.as<int64_t>() + o2, W[q].Spos, (size_t)k * 8, hipMemcpyDeviceToHost, st));
+          RSRS_HIP(hipMemcpyAsync(hpos.as<int64_t>() + o2 + k, W[q].Rpos, (size_t)R.r * 8, hipMemcpyDeviceToHost, st));
+          o2 += R.b;
+        }
+      }
+      RSRS_TRY(up.reset());
+      {
+        int hflag = 0;
+        RSRS_HIP(hipMemcpy(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost));
+        if (hflag & 1) {
+          set_error("Gram matrix of a test-matrix panel is not positive definite (rank-deficient panel)");
+          return RSRS_E_SINGULAR;
+        }
+      }
+      // ---- phase B: global R / S / SN lists
+      {
+        int64_t o2 = 0;
+        for (int64_t q = 0; q < nb; ++q) {
+          BoxRec& R = F->boxes[g.first + q];
+          const int64_t* sp = hpos.as<int64_t>() + o2;
+          const int64_t* rp = sp + k;
+          std::vector<int64_t> Sg(k), Rg(R.r);
+          for (int j = 0; j < k; ++j) Sg[j] = Ba[q][sp[j]];
+          for (int64_t j = 0; j < R.r; ++j) Rg[j] = Ba[q][rp[j]];
+          std::memcpy(hI + R.oR, Rg.data(), R.r * 8);
+          std::memcpy(hI + R.oS, Sg.data(), (size_t)k * 8);
+          RSRS_HIP(hipMemcpyAsync(iS + R.oR, hI + R.oR, (size_t)(R.r + k) * 8, hipMemcpyHostToDevice, st));
+          cur[R.box] = std::move(Sg);
+          o2 += R.b;
+        }
+      }
+      std::vector<GemmDesc> gxr;
+      std::vector<ColfixDesc> cf;
+      std::vector<Copy2D> cx;
+      std::vector<GjeDesc> gj;
+      for (int64_t q = 0; q < nb; ++q) {
+        const BoxRec& R = F->boxes[g.first + q];
+        const BoxWs& w = W[q];
+        const int l = (int)(R.b + R.n), r = (int)R.r;
+        for (int side = 0; side < 2; ++side) {
+          double* Xb = side ? w.XZ : w.XY;
+          double* XR = side ? w.XRz : w.XRy;
+          double* Xp = side ? w.Xpz : w.Xpy;
+          gxr.push_back(gdesc(dS + R.oT, nullptr, k, Xb, w.Spos, w.lp, XR, nullptr, w.lp, r, l, k,
+                              -1.0, 1.0, Xb, w.Rpos, w.lp));
+          cf.push_back(ColfixDesc{XR, w.Spos, w.Rpos, dS + R.oT, Xp, w.lp, w.lp, r, k, (int)R.b, l});
+        }
+        cx.push_back(Copy2D{w.Xpy, dS + R.oXRR, w.lp, r, r, r, 1.0, 0, 0});
+        gj.push_back(GjeDesc{w.Xpy, w.gje, dS + R.oXinv, w.lp, r, r, 0});
+        const double dr = r, dk = k, dn = (double)R.n, ds = (double)s;
+        flops += 2.0 * (2.0 * dr * dk * l + 2.0 * dr * dr * dk) + 2.0 * dr * dr * dr +
+                 2.0 * 2.0 * dr * dr * (dk + dn) + 4.0 * 2.0 * dr * dk * ds + 4.0 * 2.0 * dr * (dk + dn) * ds;
+      }
+      RSRS_TRY(gemm(up, st, gxr, 0, 0, GM_FULL));
+      RSRS_TRY(colfix(up, st, cf));
+      RSRS_TRY(copy2d(up, st, cx));
+      RSRS_TRY(gje_inverse(up, st, gj, flag));
+      std::vector<GemmDesc> gku, gkl;
+      for (int64_t q = 0; q < nb; ++q) {
+        const BoxRec& R = F->boxes[g.first + q];
+        const BoxWs& w = W[q];
+        const int r = (int)R.r, kn = (int)(k + R.n);
+        gku.push_back(gdesc(dS + R.oXinv, nullptr, r, w.Xpy + r, nullptr, w.lp, dS + R.oKU, nullptr, kn, r, kn, r));
+        gkl.push_back(gdesc(w.Xpz + r, nullptr, w.lp, dS + R.oXinv, nullptr, r, dS + R.oKL, nullptr, r, kn, r, r));
+      }
+      RSRS_TRY(gemm(up, st, gku, 0, 0, GM_FULL));
+      RSRS_TRY(gemm(up, st, gkl, 1, 0, GM_FULL));
+      // ---- sketch updates: sparsify (E, F) then eliminate (L, U)
+      std::vector<GemmDesc> s0, s1, e0, e1;
+      for (int64_t q = 0; q < nb; ++q) {
+        const BoxRec& R = F->boxes[g.first + q];
+        const int r = (int)R.r, kn = (int)(k + R.n);
+        const int64_t* gR = iS + R.oR;
+        const int64_t* gS = iS + R.oS;
+        const int64_t* gSN = iS + R.oS;
+        const double* T = dS + R.oT;
+        const double* KU = dS + R.oKU;
+        const double* KL = dS + R.oKL;
+        s0.push_back(gdesc(T, nullptr, k, Y, gS, sld, Y, gR, sld, r, (int)s, k, -1.0, 1.0));
+        s0.push_back(gdesc(T, nullptr, k, Z, gS, sld, Z, gR, sld, r, (int)s, k, -1.0, 1.0));
+        s1.push_back(gdesc(T, nullptr, k, Om, gR, sld, Om, gS, sld, k, (int)s, r, 1.0, 1.0));
+        s1.push_back(gdesc(T, nullptr, k, Psi, gR, sld, Psi, gS, sld, k, (int)s, r, 1.0, 1.0));
+        e0.push_back(gdesc(KL, nullptr, r, Y, gR, sld, Y, gSN, sld, kn, (int)s, r, -1.0, 1.0));
+        e0.push_back(gdesc(KU, nullptr, kn, Om, gSN, sld, Om, gR, sld, r, (int)s, kn, 1.0, 1.0));
+        e1.push_back(gdesc(KU, nullptr, kn, Z, gR, sld, Z, gSN, sld, kn, (int)s, r, -1.0, 1.0));
+        e1.push_back(gdesc(KL, nullptr, r, Psi, gSN, sld, Psi, gR, sld, r, (int)s, kn, 1.0, 1.0));
+      }
+      RSRS_TRY(gemm(up, st, s0, 0, 0, GM_FULL));
+      RSRS_TRY(gemm(up, st, s1, 1, 0, GM_FULL));
+      RSRS_TRY(gemm(up, st, e0, 0, 0, GM_FULL));
+      RSRS_TRY(gemm(up, st, e1, 1, 0, GM_FULL));
+    }
+    for (int64_t b : lb) remaining[b] = cur[b];
+  }
+
+  // ---- root: A_t = Y_Bt pinv(Omega_Bt)
+  {
+    std::vector<int64_t> Bt;
+    if (t.nlevels == 0) {
+      Bt.resize(n);
+      std::iota(Bt.begin(), Bt.end(), 0);
+    } else {
+      for (int64_t b : t.level_boxes[1]) Bt.insert(Bt.end(), remaining[b].begin(), remaining[b].end());
+      std::sort(Bt.begin(), Bt.end());
+    }
+    if ((int64_t)Bt.size() != F->nt) { set_error("internal: root size mismatch"); return RSRS_E_INVALID; }
+    const int nt = (int)F->nt;
+    std::memcpy(hI + F->oBt, Bt.data(), (size_t)nt * 8);
+    RSRS_HIP(hipMemcpyAsync(iS + F->oBt, hI + F->oBt, (size_t)nt * 8, hipMemcpyHostToDevice, st));
+    const int64_t* iBt = iS + F->oBt;
+    Bump bump{ws.as<char>(), 0, ws.bytes};
+    double* G = bump.take<double>(nt * ntp);
+    double* L = bump.take<double>(nt * ntp);
+    double* P = bump.take<double>(nt * ntp);
+    double* Wb = bump.take<double>(nt * ntp);
+    double* Rres = bump.take<double>(nt * round_up(s, 16));
+    double* gw = bump.take<double>(2 * (int64_t)nt * nt);
+    double* At = dS + F->oAt;
+    RSRS_TRY(gemm(up, st, {gdesc(Om, iBt, sld, Om, iBt, sld, G, nullptr, ntp, nt, nt, (int)s)}, 0, 1, GM_SYRK_L));
+    RSRS_TRY(rchol(up, st, {CholMat{G, L, ntp, nt}}, 0, nt, flag));
+    RSRS_TRY(gemm(up, st, {gdesc(Y, iBt, sld, Om, iBt, sld, P, nullptr, ntp, nt, nt, (int)s)}, 0, 1, GM_FULL));
+    RSRS_TRY(gemm(up, st, {gdesc(P, nullptr, ntp, L, nullptr, ntp, Wb, nullptr, ntp, nt, nt, nt)}, 0, 1, GM_B_NT_LOW));
+    RSRS_TRY(gemm(up, st, {gdesc(Wb, nullptr, ntp, L, nullptr, ntp, At, nullptr, nt, nt, nt, nt)}, 0, 0, GM_B_NN_LOW));
+    if (reproject) {
+      const int64_t rp = round_up(s, 16);
+      RSRS_TRY(gemm(up, st, {gdesc(At, nullptr, nt, Om, iBt, sld, Rres, nullptr, rp, nt, (int)s, nt, -1.0, 1.0, Y, iBt, sld)}, 0, 0, GM_FULL));
+      RSRS_TRY(gemm(up, st, {gdesc(Rres, nullptr, rp, Om, iBt, sld, P, nullptr, ntp, nt, nt, (int)s)}, 0, 1, GM_FULL));
+      RSRS_TRY(gemm(up, st, {gdesc(P, nullptr, ntp, L, nullptr, ntp, Wb, nullptr, ntp, nt, nt, nt)}, 0, 1, GM_B_NT_LOW));
+      RSRS_TRY(gemm(up, st, {gdesc(Wb, nullptr, ntp, L, nullptr, ntp, At, nullptr, nt, nt, nt, nt, 1.0, 1.0)}, 0, 0, GM_B_NN_LOW));
+    }
+    RSRS_TRY(gje_inverse(up, st, {GjeDesc{At, gw, dS + F->oAtinv, nt, nt, nt, 0}}, flag));
+    const double dt = nt;
+    flops += dt * dt * s + (2.0 / 3.0) * dt * dt * dt + (1 + reproject) * (2.0 * dt * dt * s + 2.0 * dt * dt * dt) + 2.0 * dt * dt * dt;
+  }
+  RSRS_TRY(up.reset());
+  {
+    int hflag = 0;
+    RSRS_HIP(hipMemcpy(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost));
+    if (hflag & 1) { set_error("Gram matrix of the root panel is not positive definite"); return RSRS_E_SINGULAR; }
+    if (hflag & 2) { set_error("singular pivot block X_RR or root block"); return RSRS_E_SINGULAR; }
+  }
+  smp->consumed = true;
+  F->flops = flops;
+  F->factor_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  *out = F.release();
+  return RSRS_OK;
+}
+
+}  // namespace rsrs

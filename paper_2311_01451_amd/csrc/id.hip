@@ -1,0 +1,212 @@
+// Row interpolative decomposition by greedy column-pivoted QR (Sec. 2.3,
+// eq. id_factorization), batched over the boxes of one colour class.
+//
+// The QR of M^T with column pivoting is run as pivoted modified Gram-Schmidt
+// on the rows of M: at step j the row of largest residual norm becomes pivot
+// p_j, every other unselected row i is orthogonalised against it,
+//   d_ij = <m_i, m_p> / |m_p|,   m_i <- m_i - (<m_i, m_p> / |m_p|^2) m_p,
+// and its residual norm is recomputed exactly from the updated row (no
+// downdating).  d_ij are the entries R[j, i] of the triangular factor, so with
+// S = {p_0..p_{k-1}} and R the other rows, T = (R11^{-1} R12)^T and
+// M_R ~ T M_S.  Ties in the pivot choice go to the lowest row index.
+//
+// One launch per step, one wave per row.  Norms are double-buffered by step
+// parity so that every wave of a step sees the same pivot; rows other than
+// the pivot are only written by their own wave, and the pivot row is only read.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+
+#include "kernels.hpp"
+
+namespace rsrs {
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(64) void id_init_kernel(const IdDesc* __restrict__ e) {
+  const IdDesc d = e[blockIdx.y];
+  const int i = blockIdx.x;
+  if (i >= d.b) return;
+  double* mi = d.M + (int64_t)i * d.ldm;
+  double s = 0.0;
+  for (int c = threadIdx.x; c < d.s; c += 64) {
+    double v = mi[c];
+    if (d.MZ) {
+      v += d.MZ[(int64_t)i * d.ldz + c];
+      mi[c] = v;
+    }
+    s += v * v;
+  }
+  s = wave_sum(s);
+  if (threadIdx.x == 0) {
+    d.norms[i] = s;
+    d.sel[i] = INT_MAX;
+  }
+}
+
+__global__ __launch_bounds__(64) void id_step_kernel(const IdDesc* __restrict__ e, int j) {
+  const IdDesc d = e[blockIdx.y];
+  const int i = blockIdx.x;
+  if (i >= d.b || j >= d.k) return;
+  const int lane = threadIdx.x;
+  const double* cur = d.norms + (j & 1) * d.b;
+  double* nxt = d.norms + ((j + 1) & 1) * d.b;
+  // pivot: argmax over rows not selected before step j (lowest index on ties)
+  double best = -1.0;
+  int bi = INT_MAX;
+  for (int x = lane; x < d.b; x += 64) {
+    if (d.sel[x] < j) continue;
+    const double v = cur[x];
+    // the first candidate is always taken, so a NaN norm cannot leave bi unset
+    if (bi == INT_MAX || v > best) { best = v; bi = x; }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ob = __shfl_xor(best, off, 64);
+    const int oi = __shfl_xor(bi, off, 64);
+    if (oi != INT_MAX && (bi == INT_MAX || ob > best || (ob == best && oi < bi))) { best = ob; bi = oi; }
+  }
+  const int p = bi;   // always a valid row: b - j > 0 candidates remain for j < k < b
+  const double pn2 = best > 0.0 ? best : 0.0;   // also maps NaN to 0
+  const double pn = sqrt(pn2);
+  if (i == p) {
+    if (lane == 0) {
+      d.sel[p] = j;
+      d.piv[j] = p;
+      d.Rc[(int64_t)p * d.k + j] = pn;
+      nxt[p] = 0.0;
+    }
+    return;
+  }
+  if (d.sel[i] < j) return;  // selected at an earlier step
+  double* mi = d.M + (int64_t)i * d.ldm;
+  const double* mp = d.M + (int64_t)p * d.ldm;
+  double dot = 0.0;
+  for (int c = lane; c < d.s; c += 64) dot += mi[c] * mp[c];
+  dot = wave_sum(dot);
+  const double coef = pn2 > 0.0 ? dot / pn2 : 0.0;
+  double s = 0.0;
+  for (int c = lane; c < d.s; c += 64) {
+    const double v = mi[c] - coef * mp[c];
+    mi[c] = v;
+    s += v * v;
+  }
+  s = wave_sum(s);
+  if (lane == 0) {
+    d.Rc[(int64_t)i * d.k + j] = pn > 0.0 ? dot / pn : 0.0;
+    nxt[i] = s;
+  }
+}
+
+// S, R sorted; T = (R11^{-1} R12)^T written with columns in sorted-S order.
+__global__ __launch_bounds__(256) void id_finalize_kernel(const IdDesc* __restrict__ e) {
+  const IdDesc d = e[blockIdx.x];
+  const int b = d.b, k = d.k, r = b - k;
+  __shared__ int rank_of_step[256];   // rank of pivot p_t inside sorted S
+  __shared__ int rrow[4096];          // sorted R rows
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    int ns = 0, nr = 0;
+    for (int x = 0; x < b; ++x) {
+      if (d.sel[x] < k) d.Spos[ns++] = x;
+      else { d.Rpos[nr] = x; rrow[nr] = x; ++nr; }
+    }
+    for (int t = 0; t < k; ++t) {
+      const int p = d.piv[t];
+      int rk = 0;
+      for (int x = 0; x < p; ++x) rk += d.sel[x] < k ? 1 : 0;
+      rank_of_step[t] = rk;
+    }
+  }
+  __syncthreads();
+  for (int q = tid; q < r; q += 256) {
+    const int i = rrow[q];
+    const double* c = d.Rc + (int64_t)i * k;
+    double* Tq = d.T + (int64_t)q * k;
+    // back substitution R11 x = c, R11[t][u] = Rc[p_u][t] (t <= u)
+    for (int t = k - 1; t >= 0; --t) {
+      double acc = c[t];
+      for (int u = t + 1; u < k; ++u)
+        acc -= d.Rc[(int64_t)d.piv[u] * k + t] * Tq[rank_of_step[u]];
+      const double diag = d.Rc[(int64_t)d.piv[t] * k + t];
+      Tq[rank_of_step[t]] = diag != 0.0 ? acc / diag : 0.0;
+    }
+  }
+}
+
+rsrs_status id_run(Uploader& up, hipStream_t st, const std::vector<IdDesc>& e) {
+  if (e.empty()) return RSRS_OK;
+  int bmax = 0, kmax = 0;
+  for (const auto& x : e) {
+    if (x.k > 256 || x.b - x.k > 4096 || x.k >= x.b) {
+      set_error("ID sizes out of range (need k < b, k <= 256, b - k <= 4096)");
+      return RSRS_E_UNSUPPORTED;
+    }
+    bmax = std::max(bmax, x.b);
+    kmax = std::max(kmax, x.k);
+  }
+  IdDesc* de = nullptr;
+  RSRS_TRY(up.put_vec(e, &de));
+  const unsigned nb = (unsigned)e.size();
+  hipLaunchKernelGGL(id_init_kernel, dim3((unsigned)bmax, nb), dim3(64), 0, st, de);
+  for (int j = 0; j < kmax; ++j)
+    hipLaunchKernelGGL(id_step_kernel, dim3((unsigned)bmax, nb), dim3(64), 0, st, de, j);
+  hipLaunchKernelGGL(id_finalize_kernel, dim3(nb), dim3(256), 0, st, de);
+  RSRS_HIP(hipGetLastError());
+  return RSRS_OK;
+}
+
+// ---------------------------------------------------------------- column fix-up
+// Xp[i][c] for output columns [R, S, N]:
+//   c <  r      : XR[i][Rpos[c]] - sum_t XR[i][Spos[t]] T[c][t]
+//   c <  r + k  : XR[i][Spos[c - r]]
+//   otherwise   : XR[i][b + c - r - k]
+__global__ __launch_bounds__(256) void colfix_kernel(const ColfixDesc* __restrict__ e) {
+  const ColfixDesc d = e[blockIdx.y];
+  const int i = blockIdx.x;
+  if (i >= d.r) return;
+  __shared__ double xs[256];
+  const double* xr = d.XR + (int64_t)i * d.ldx;
+  for (int t = threadIdx.x; t < d.k; t += 256) xs[t] = xr[d.Spos[t]];
+  __syncthreads();
+  double* out = d.Xp + (int64_t)i * d.ldp;
+  for (int c = threadIdx.x; c < d.l; c += 256) {
+    double v;
+    if (c < d.r) {
+      v = xr[d.Rpos[c]];
+      const double* tc = d.T + (int64_t)c * d.k;
+      for (int t = 0; t < d.k; ++t) v -= xs[t] * tc[t];
+    } else if (c < d.r + d.k) {
+      v = xs[c - d.r];
+    } else {
+      v = xr[d.b + (c - d.r - d.k)];
+    }
+    out[c] = v;
+  }
+}
+
+rsrs_status colfix(Uploader& up, hipStream_t st, const std::vector<ColfixDesc>& e) {
+  if (e.empty()) return RSRS_OK;
+  int rmax = 0;
+  for (const auto& x : e) {
+    if (x.k > 256) {
+      set_error("colfix: k > 256");
+      return RSRS_E_UNSUPPORTED;
+    }
+    rmax = std::max(rmax, x.r);
+  }
+  if (rmax == 0) return RSRS_OK;
+  ColfixDesc* de = nullptr;
+  RSRS_TRY(up.put_vec(e, &de));
+  hipLaunchKernelGGL(colfix_kernel, dim3((unsigned)rmax, (unsigned)e.size()), dim3(256), 0, st, de);
+  RSRS_HIP(hipGetLastError());
+  return RSRS_OK;
+}
+
+}  // namespace rsrs

@@ -1,0 +1,69 @@
+// Internal definitions of the opaque handles of include/rsrs.h.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "kernels.hpp"
+#include "tree.hpp"
+
+struct rsrs_tree_s {
+  rsrs::Tree t;
+};
+
+struct rsrs_samples_s {
+  const rsrs_tree_t* tree = nullptr;
+  int64_t n = 0, s = 0, ld = 0;
+  rsrs::DevBuf Y, Z, Om, Psi;   // tree order, row-major n x s (leading dimension ld)
+  bool consumed = false;
+};
+
+struct rsrs_operator_s {
+  int kind = 0;     // 1..3 kernel (explicit matrix), 10 dense borrowed, 20 poisson7
+  int64_t n = 0;
+  rsrs::DevBuf owned;        // explicit kernel matrix
+  const double* A = nullptr; // matrix used by the GEMM matvec
+  int64_t lda = 0;
+  bool symmetric = true;
+  rsrs::Poisson7Op pois;
+  rsrs::Uploader up;
+  bool up_ready = false;
+};
+
+namespace rsrs {
+
+// One processed box; offsets index the factor's double / int64 stores.
+struct BoxRec {
+  int64_t box = 0;
+  int level = 0, colour = 0;
+  int64_t b = 0, n = 0, r = 0, k = 0;
+  int64_t oT = 0, oXRR = 0, oXinv = 0, oKU = 0, oKL = 0;   // doubles
+  int64_t oR = 0, oS = 0, oSN = 0, oBa = 0, oNa = 0;       // int64 tree positions
+};
+
+struct Group {  // one colour class: boxes [first, first+count) in processing order
+  int64_t first = 0, count = 0;
+};
+
+rsrs_status kernel_materialise(hipStream_t st, const KernelOp& op, double* A);
+
+}  // namespace rsrs
+
+struct rsrs_factor_s {
+  int64_t n = 0, s = 0, k = 0;
+  rsrs::DevBuf dstore, istore, perm;   // perm: tree position -> user index
+  std::vector<rsrs::BoxRec> boxes;
+  std::vector<rsrs::Group> groups;
+  int64_t nt = 0, oBt = 0, oAt = 0, oAtinv = 0;
+  int64_t stored_doubles = 0;
+  double flops = 0.0, factor_ms = 0.0;
+  // solve workspace (grown on demand)
+  mutable rsrs::DevBuf wx, wu, wt, wpart, wnorm;
+  mutable rsrs::Uploader up;
+  mutable bool up_ready = false;
+  const double* d() const { return dstore.as<double>(); }
+  const int64_t* i() const { return istore.as<int64_t>(); }
+};

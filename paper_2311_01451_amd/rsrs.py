@@ -1,0 +1,420 @@
+"""Thin Python binding of ``include/rsrs.h`` (ctypes).
+
+Argument marshalling only: every step of the method runs in ``librsrs.so``.
+PyTorch supplies device memory (``torch.float64`` CUDA/HIP tensors, row-major
+N x w with ``stride(0)`` as leading dimension) and the current HIP stream.
+The functions carry the names of the C entry points; small handle classes own
+the C handles and free them on garbage collection.
+
+If ``librsrs.so`` is missing this module raises on first use: there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librsrs.so")
+_lib = None
+
+RSRS_OP_LOG2D = 1
+RSRS_OP_INVR3D = 2
+RSRS_OP_LOG2D_SKEW = 3
+RSRS_PREC_F64 = 0
+
+STATUS = {0: "RSRS_OK", 1: "RSRS_E_INVALID", 2: "RSRS_E_SAMPLES", 3: "RSRS_E_SINGULAR",
+          4: "RSRS_E_CALLBACK", 5: "RSRS_E_NUMERIC", 6: "RSRS_E_NOMEM", 7: "RSRS_E_HIP",
+          8: "RSRS_E_UNSUPPORTED"}
+
+
+class RSRSError(RuntimeError):
+    def __init__(self, status: int, message: str, required_s: int = -1):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+        self.required_s = required_s
+
+
+class TreeOpts(C.Structure):
+    _fields_ = [("dim", C.c_int), ("leaf_size", C.c_int), ("qbits", C.c_int),
+                ("root_lo", C.c_double * 3), ("root_side", C.c_double)]
+
+
+class TreeInfo(C.Structure):
+    _fields_ = [("dim", C.c_int), ("nlevels", C.c_int), ("qbits", C.c_int),
+                ("n", C.c_int64), ("nbox", C.c_int64),
+                ("level", C.POINTER(C.c_int32)), ("coords", C.POINTER(C.c_int32)),
+                ("parent", C.POINTER(C.c_int64)), ("is_leaf", C.POINTER(C.c_uint8)),
+                ("pt_begin", C.POINTER(C.c_int64)), ("pt_end", C.POINTER(C.c_int64)),
+                ("perm", C.POINTER(C.c_int64))]
+
+
+class FactorOpts(C.Structure):
+    _fields_ = [("k", C.c_int), ("p", C.c_int), ("precision", C.c_int), ("reproject", C.c_int)]
+
+
+class FactorInfo(C.Structure):
+    _fields_ = [("n", C.c_int64), ("s", C.c_int64), ("k", C.c_int64), ("nboxes", C.c_int64),
+                ("root_size", C.c_int64), ("stored_doubles", C.c_int64), ("flops", C.c_double),
+                ("factor_ms", C.c_double)]
+
+
+MATVEC_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int, C.c_int64, C.c_void_p, C.c_int64,
+                        C.c_void_p, C.c_int64, C.c_void_p)
+
+EXPORTS = [
+    "rsrs_status_string", "rsrs_last_error", "rsrs_last_required_s", "rsrs_build_tree",
+    "rsrs_tree_destroy", "rsrs_tree_get_info", "rsrs_tree_neighbours", "rsrs_tree_schedule",
+    "rsrs_samples_required", "rsrs_op_create_kernel", "rsrs_op_create_dense",
+    "rsrs_op_create_poisson7", "rsrs_op_matvec", "rsrs_op_destroy", "rsrs_samples_wrap",
+    "rsrs_sample", "rsrs_samples_destroy", "rsrs_gaussian", "rsrs_factor", "rsrs_factor_destroy",
+    "rsrs_factor_get_info", "rsrs_factor_box_sizes", "rsrs_factor_box_copy",
+    "rsrs_factor_root_copy", "rsrs_solve", "rsrs_apply", "rsrs_solve_refine",
+]
+
+
+def lib():
+    """Load librsrs.so (once); raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: run `python -m paper_2311_01451_amd.build` "
+                           "(there is no non-HIP fallback)")
+    L = C.CDLL(LIB_PATH)
+    vp, i64, i32, dbl = C.c_void_p, C.c_int64, C.c_int, C.c_double
+    P = C.POINTER
+    sig = {
+        "rsrs_status_string": (C.c_char_p, [C.c_int]),
+        "rsrs_last_error": (C.c_char_p, []),
+        "rsrs_last_required_s": (i64, []),
+        "rsrs_build_tree": (i32, [P(C.c_double), i64, P(TreeOpts), P(vp)]),
+        "rsrs_tree_destroy": (None, [vp]),
+        "rsrs_tree_get_info": (i32, [vp, P(TreeInfo)]),
+        "rsrs_tree_neighbours": (i32, [vp, i32, P(i64), P(P(i64)), P(P(i64)), P(P(i64))]),
+        "rsrs_tree_schedule": (i32, [vp, i32, P(C.c_int32), P(i64), P(i64), P(i64)]),
+        "rsrs_samples_required": (i64, [vp, i32, i32]),
+        "rsrs_op_create_kernel": (i32, [i32, P(C.c_double), i64, i32, dbl, dbl, P(vp)]),
+        "rsrs_op_create_dense": (i32, [vp, i64, i64, P(vp)]),
+        "rsrs_op_create_poisson7": (i32, [i32, P(C.c_double), P(vp)]),
+        "rsrs_op_matvec": (i32, [vp, i32, i64, vp, i64, vp, i64, vp]),
+        "rsrs_op_destroy": (None, [vp]),
+        "rsrs_samples_wrap": (i32, [vp, vp, vp, vp, vp, i64, i64, vp, P(vp)]),
+        "rsrs_sample": (i32, [vp, vp, vp, i64, C.c_uint64, vp, P(vp)]),
+        "rsrs_samples_destroy": (None, [vp]),
+        "rsrs_gaussian": (i32, [vp, i64, i64, i64, C.c_uint64, C.c_uint32, vp]),
+        "rsrs_factor": (i32, [vp, vp, P(FactorOpts), vp, P(vp)]),
+        "rsrs_factor_destroy": (None, [vp]),
+        "rsrs_factor_get_info": (i32, [vp, P(FactorInfo)]),
+        "rsrs_factor_box_sizes": (i32, [vp, i64, P(i64), P(C.c_int32), P(C.c_int32), P(i64),
+                                        P(i64), P(i64), P(i64)]),
+        "rsrs_factor_box_copy": (i32, [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp]),
+        "rsrs_factor_root_copy": (i32, [vp, P(i64), vp, vp]),
+        "rsrs_solve": (i32, [vp, i32, i64, vp, i64, vp, i64, vp]),
+        "rsrs_apply": (i32, [vp, i32, i64, vp, i64, vp, i64, vp]),
+        "rsrs_solve_refine": (i32, [vp, vp, vp, i64, vp, i64, vp, i64, dbl, i32, P(dbl),
+                                    P(i32), vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(st: int):
+    if st != 0:
+        L = lib()
+        msg = L.rsrs_last_error().decode()
+        raise RSRSError(st, msg, int(L.rsrs_last_required_s()) if st == 2 else -1)
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(int(s.cuda_stream))
+
+
+def _dev(t, name="tensor"):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64):
+        raise TypeError(f"{name} must be a float64 device tensor")
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise TypeError(f"{name} must be 2-D row-major (stride(1) == 1)")
+    return C.c_void_p(t.data_ptr()), t.stride(0)
+
+
+# --------------------------------------------------------------------------- tree
+class Tree:
+    def __init__(self, handle, n):
+        self._h = handle
+        self.n = n
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().rsrs_tree_destroy(self._h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        ti = TreeInfo()
+        _check(lib().rsrs_tree_get_info(self._h, C.byref(ti)))
+        nb, d, n = ti.nbox, ti.dim, ti.n
+        arr = lambda p, cnt, dt: np.ctypeslib.as_array(p, shape=(cnt,)).astype(dt, copy=True)
+        return dict(dim=d, nlevels=ti.nlevels, qbits=ti.qbits, n=n, nbox=nb,
+                    level=arr(ti.level, nb, np.int64), coords=arr(ti.coords, nb * d, np.int64).reshape(nb, d),
+                    parent=arr(ti.parent, nb, np.int64), is_leaf=arr(ti.is_leaf, nb, bool),
+                    pt_begin=arr(ti.pt_begin, nb, np.int64), pt_end=arr(ti.pt_end, nb, np.int64),
+                    perm=arr(ti.perm, n, np.int64))
+
+    def neighbours(self, level: int) -> dict:
+        nb = C.c_int64()
+        bx, off, ids = C.POINTER(C.c_int64)(), C.POINTER(C.c_int64)(), C.POINTER(C.c_int64)()
+        _check(lib().rsrs_tree_neighbours(self._h, level, C.byref(nb), C.byref(bx), C.byref(off),
+                                          C.byref(ids)))
+        n = nb.value
+        boxes = np.ctypeslib.as_array(bx, shape=(n,)).copy()
+        offs = np.ctypeslib.as_array(off, shape=(n + 1,)).copy()
+        allid = np.ctypeslib.as_array(ids, shape=(int(offs[-1]),)).copy() if offs[-1] else np.zeros(0, np.int64)
+        return {int(b): allid[offs[i]:offs[i + 1]] for i, b in enumerate(boxes)}
+
+    def schedule(self, k: int):
+        nb = self.info()["nbox"]
+        col = np.zeros(nb, np.int32)
+        bc = np.zeros(nb, np.int64)
+        lc = np.zeros(nb, np.int64)
+        rc = C.c_int64()
+        _check(lib().rsrs_tree_schedule(self._h, k, col.ctypes.data_as(C.POINTER(C.c_int32)),
+                                        bc.ctypes.data_as(C.POINTER(C.c_int64)),
+                                        lc.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(rc)))
+        return col, bc, lc, rc.value
+
+    def samples_required(self, k: int, p: int | None = None) -> int:
+        return rsrs_samples_required(self, k, k if p is None else p)
+
+
+def rsrs_build_tree(points, leaf_size: int, root_lo=None, root_side: float = 1.0,
+                    qbits: int = 0) -> Tree:
+    pts = np.ascontiguousarray(points, dtype=np.float64)
+    n, d = pts.shape
+    o = TreeOpts()
+    o.dim, o.leaf_size, o.qbits = d, leaf_size, qbits
+    lo = [0.0, 0.0, 0.0] if root_lo is None else list(root_lo) + [0.0] * (3 - len(root_lo))
+    for a in range(3):
+        o.root_lo[a] = lo[a]
+    o.root_side = root_side
+    h = C.c_void_p()
+    _check(lib().rsrs_build_tree(pts.ctypes.data_as(C.POINTER(C.c_double)), n, C.byref(o),
+                                 C.byref(h)))
+    return Tree(h, n)
+
+
+def rsrs_samples_required(tree: Tree, k: int, p: int) -> int:
+    v = lib().rsrs_samples_required(tree.handle, k, p)
+    if v < 0:
+        raise RSRSError(1, "invalid arguments to rsrs_samples_required")
+    return int(v)
+
+
+# --------------------------------------------------------------------------- operators
+class Operator:
+    """A built-in black-box operator; ``matvec_fn``/``handle`` satisfy rsrs_matvec_fn."""
+
+    def __init__(self, handle, n, keep=None):
+        self._h = handle
+        self.n = n
+        self._keep = keep
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().rsrs_op_destroy(self._h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    @staticmethod
+    def fn_ptr():
+        return C.cast(lib().rsrs_op_matvec, C.c_void_p)
+
+    def matvec(self, X, transpose: bool = False, out=None, stream=None):
+        import torch
+        px, ldx = _dev(X, "X")
+        if out is None:
+            out = torch.empty_like(X)
+        py, ldy = _dev(out, "out")
+        st = lib().rsrs_op_matvec(self._h, int(transpose), X.shape[1], px, ldx, py, ldy, _stream(stream))
+        if st != 0:
+            raise RSRSError(4, "rsrs_op_matvec failed: " + lib().rsrs_last_error().decode())
+        return out
+
+
+def rsrs_op_create_kernel(kind: int, points, param: float = 0.0, param2: float = 0.0) -> Operator:
+    pts = np.ascontiguousarray(points, dtype=np.float64)
+    h = C.c_void_p()
+    _check(lib().rsrs_op_create_kernel(kind, pts.ctypes.data_as(C.POINTER(C.c_double)), pts.shape[0],
+                                       pts.shape[1], param, param2, C.byref(h)))
+    return Operator(h, pts.shape[0])
+
+
+def rsrs_op_create_dense(A) -> Operator:
+    pa, lda = _dev(A, "A")
+    h = C.c_void_p()
+    _check(lib().rsrs_op_create_dense(pa, A.shape[0], lda, C.byref(h)))
+    return Operator(h, A.shape[0], keep=A)
+
+
+def rsrs_op_create_poisson7(n: int, coef_nodes) -> Operator:
+    c = np.ascontiguousarray(coef_nodes, dtype=np.float64)
+    h = C.c_void_p()
+    _check(lib().rsrs_op_create_poisson7(n, c.ctypes.data_as(C.POINTER(C.c_double)), C.byref(h)))
+    return Operator(h, n ** 3)
+
+
+# --------------------------------------------------------------------------- samples
+class Samples:
+    def __init__(self, handle, s):
+        self._h = handle
+        self.s = s
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().rsrs_samples_destroy(self._h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+
+def rsrs_samples_wrap(tree: Tree, Y, Z, Om, Psi, stream=None) -> Samples:
+    ptrs = []
+    ld = None
+    for name, t in (("Y", Y), ("Z", Z), ("Omega", Om), ("Psi", Psi)):
+        p, l = _dev(t, name)
+        if ld is None:
+            ld = l
+        if l != ld or t.shape != Y.shape:
+            raise TypeError("sketches must share shape and leading dimension")
+        ptrs.append(p)
+    h = C.c_void_p()
+    _check(lib().rsrs_samples_wrap(tree.handle, *ptrs, ld, Y.shape[1], _stream(stream), C.byref(h)))
+    return Samples(h, Y.shape[1])
+
+
+def rsrs_sample(tree: Tree, op: Operator, s: int, seed: int, stream=None) -> Samples:
+    h = C.c_void_p()
+    _check(lib().rsrs_sample(tree.handle, Operator.fn_ptr(), op.handle, s, seed, _stream(stream),
+                             C.byref(h)))
+    return Samples(h, s)
+
+
+def rsrs_gaussian(nrows: int, ncols: int, seed: int, word: int = 0, out=None, stream=None):
+    import torch
+    if out is None:
+        out = torch.empty((nrows, ncols), dtype=torch.float64, device="cuda")
+    p, ld = _dev(out, "out")
+    _check(lib().rsrs_gaussian(p, nrows, ncols, ld, seed, word, _stream(stream)))
+    return out
+
+
+# --------------------------------------------------------------------------- factor
+class Factor:
+    def __init__(self, handle, keep=None):
+        self._h = handle
+        self._keep = keep
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().rsrs_factor_destroy(self._h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        fi = FactorInfo()
+        _check(lib().rsrs_factor_get_info(self._h, C.byref(fi)))
+        return {f: getattr(fi, f) for f, _ in FactorInfo._fields_}
+
+    def box(self, i: int) -> dict:
+        L = lib()
+        box, lev, col = C.c_int64(), C.c_int32(), C.c_int32()
+        b, n, r, k = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
+        _check(L.rsrs_factor_box_sizes(self._h, i, C.byref(box), C.byref(lev), C.byref(col), C.byref(b),
+                                       C.byref(n), C.byref(r), C.byref(k)))
+        b, n, r, k = b.value, n.value, r.value, k.value
+        out = dict(box=box.value, level=lev.value, colour=col.value,
+                   Ba=np.zeros(b, np.int64), Na=np.zeros(n, np.int64), S=np.zeros(k, np.int64),
+                   R=np.zeros(r, np.int64), T=np.zeros((r, k)), XRR=np.zeros((r, r)),
+                   KU=np.zeros((r, k + n)), KL=np.zeros((k + n, r)))
+        ptr = lambda a: C.c_void_p(a.ctypes.data) if a.size else None
+        _check(L.rsrs_factor_box_copy(self._h, i, ptr(out["Ba"]), ptr(out["Na"]), ptr(out["S"]),
+                                      ptr(out["R"]), ptr(out["T"]), ptr(out["XRR"]), ptr(out["KU"]),
+                                      ptr(out["KL"])))
+        return out
+
+    def root(self):
+        nt = C.c_int64()
+        _check(lib().rsrs_factor_root_copy(self._h, C.byref(nt), None, None))
+        Bt = np.zeros(nt.value, np.int64)
+        At = np.zeros((nt.value, nt.value))
+        _check(lib().rsrs_factor_root_copy(self._h, C.byref(nt), C.c_void_p(Bt.ctypes.data),
+                                           C.c_void_p(At.ctypes.data)))
+        return Bt, At
+
+    def solve(self, F, transpose=False, out=None, stream=None):
+        return rsrs_solve(self, F, transpose, out, stream)
+
+    def apply(self, X, transpose=False, out=None, stream=None):
+        return rsrs_apply(self, X, transpose, out, stream)
+
+
+def rsrs_factor(tree: Tree, samples: Samples, k: int, p: int = -1, reproject: int = 1,
+                precision: int = RSRS_PREC_F64, stream=None) -> Factor:
+    o = FactorOpts(k, p, precision, reproject)
+    h = C.c_void_p()
+    _check(lib().rsrs_factor(tree.handle, samples.handle, C.byref(o), _stream(stream), C.byref(h)))
+    return Factor(h, keep=tree)
+
+
+def rsrs_solve(f: Factor, F, transpose=False, out=None, stream=None):
+    import torch
+    pf, ldf = _dev(F, "F")
+    if out is None:
+        out = torch.empty_like(F)
+    pu, ldu = _dev(out, "out")
+    _check(lib().rsrs_solve(f.handle, int(transpose), F.shape[1], pf, ldf, pu, ldu, _stream(stream)))
+    return out
+
+
+def rsrs_apply(f: Factor, X, transpose=False, out=None, stream=None):
+    import torch
+    px, ldx = _dev(X, "X")
+    if out is None:
+        out = torch.empty_like(X)
+    py, ldy = _dev(out, "out")
+    _check(lib().rsrs_apply(f.handle, int(transpose), X.shape[1], px, ldx, py, ldy, _stream(stream)))
+    return out
+
+
+def rsrs_solve_refine(f: Factor, op: Operator, F, tol: float = 1e-10, maxit: int = 10, out=None,
+                      stream=None):
+    import torch
+    pf, ldf = _dev(F, "F")
+    if out is None:
+        out = torch.empty_like(F)
+    pu, ldu = _dev(out, "out")
+    rel = C.c_double()
+    it = C.c_int()
+    _check(lib().rsrs_solve_refine(f.handle, Operator.fn_ptr(), op.handle, F.shape[1], pf, ldf, pu, ldu,
+                                   tol, maxit, C.byref(rel), C.byref(it), _stream(stream)))
+    return out, rel.value, it.value

@@ -17,6 +17,7 @@ from oracle import operators as oop
 from oracle import rsrs as orr
 from oracle import tree as ot
 from paper_2311_01451_amd import inputs
+from h2_helpers import exact_h2
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -279,21 +280,6 @@ def test_rank_at_least_box_size_eliminates_nothing():
     assert len(F.boxes) == 0 and len(F.Bt) == 64
     f = inputs.rhs(64, 1)[:, 0]
     assert np.abs(orr.solve(F, f) - np.linalg.solve(A, f)).max() < 1e-11
-
-
-def exact_h2(t, r, seed=3):
-    """A = blockdiag over leaves (Gaussian + m I) + U V^T with U, V of rank r
-    (far-field rank <= 2r; the R-block couplings vanish exactly after each ID)."""
-    rng = np.random.default_rng(seed)
-    N = t.n
-    A = np.zeros((N, N))
-    for b in np.nonzero(t.is_leaf)[0]:
-        idx = t.perm[t.pt_begin[b]:t.pt_end[b]]
-        m = len(idx)
-        A[np.ix_(idx, idx)] = rng.standard_normal((m, m)) + m * np.eye(m)
-    U = rng.standard_normal((N, r))
-    V = rng.standard_normal((N, r))
-    return A + U @ V.T
 
 
 def test_exact_h2_recovered_to_rounding():
