@@ -1,0 +1,267 @@
+#!/usr/bin/env python
+"""Benchmark of the RSRS hot path on one MI355X.
+
+Workload: 2D log-kernel operator A_ij = delta_ij + h^2 (-log|x_i - x_j| / 2 pi),
+A_ii = 1 + h^2/2, on the 256 x 256 cell-centred grid of [0,1]^2 (N = 65,536,
+h = 1/256), quadtree leaf 64, rank k = 64, p = k, FP64 end to end, 16
+right-hand sides N(0,1).  The configured s = 640 is below the sample count the
+method requires (s >= |B_a| + |N_a| + k + p for every box), so the step runs
+at s = max(640, s_required) and reports both.
+
+One step = the whole hot path on one batch: build the tree, draw Omega/Psi
+and sample Y = A Omega, Z = A^T Psi through the operator, factor (Algorithm
+1), solve the 16 right-hand sides and refine through the operator until the
+relative residual is <= 1e-6.  value = right-hand-side columns solved per
+second of step time.  The operator itself (the black box) is built once
+outside the timed region.
+
+Prints ONE JSON line (rank 0).  Extra fields: per-phase times, p50/p99 solve
+latency of the resident factor, the roofline of the dominant kernel measured
+with HIP events inside the timed region, and the CPU oracle timed on a bounded
+sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "factor s + solved RHS cols/s at rel. residual 1e-6, mixed vs FP64; p99 solve ms"
+PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+GRID_N = 256
+LEAF = 64
+K = 64
+S_CFG = 640
+NRHS = 16
+TOL = 1e-6
+
+
+def workload_config(s_req: int, s_eff: int) -> dict:
+    return {"workload": f"2D log-kernel operator on a {GRID_N}x{GRID_N} grid (N={GRID_N**2}), "
+                        f"quadtree leaf {LEAF}, k=p={K}, FP64, {NRHS} RHS, residual <= {TOL:g}",
+            "N": GRID_N ** 2, "leaf": LEAF, "k": K, "p": K, "s_configured": S_CFG,
+            "s_required": s_req, "s": s_eff, "nrhs": NRHS, "tol": TOL,
+            "precision": "fp64"}
+
+
+def gpu_bench(steps: int, warmup: int, do_profile: bool):
+    import torch
+    from paper_2311_01451_amd import inputs, rsrs
+
+    pts = inputs.grid2d(GRID_N)
+    h = 1.0 / GRID_N
+    op = rsrs.rsrs_op_create_kernel(rsrs.RSRS_OP_LOG2D, pts, h)
+    f = torch.tensor(inputs.rhs(GRID_N ** 2, NRHS), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+
+    def step(record):
+        t0 = time.perf_counter()
+        tree = rsrs.rsrs_build_tree(pts, LEAF)
+        s_req = tree.samples_required(K, K)
+        s_eff = max(S_CFG, s_req)
+        t1 = time.perf_counter()
+        smp = rsrs.rsrs_sample(tree, op, s_eff, inputs.BASE_SEED)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        F = rsrs.rsrs_factor(tree, smp, K)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        u, rel, it = rsrs.rsrs_solve_refine(F, op, f, tol=TOL, maxit=10)
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        record.append(dict(tree=t1 - t0, sample=t2 - t1, factor=t3 - t2, solve=t4 - t3,
+                           relres=rel, iters=it, s_req=s_req, s_eff=s_eff,
+                           flops=F.info()["flops"]))
+        return F
+
+    warm = []
+    for _ in range(warmup):
+        F = step(warm)
+        del F
+    if do_profile:
+        rsrs.rsrs_profile_reset()
+        rsrs.rsrs_profile_enable(True)
+    rec = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        F = step(rec)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = {}
+    if do_profile:
+        rsrs.rsrs_profile_enable(False)
+        prof = rsrs.rsrs_profile_read()
+        rsrs.rsrs_profile_reset()
+
+    # solve latency of the resident factor (16 RHS per request)
+    lat = []
+    for _ in range(40):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        F.solve(f)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - a) * 1e3)
+    lat = np.array(lat[5:])
+    return rec, elapsed, prof, lat
+
+
+def by_kernel(prof: dict) -> dict:
+    """Merge call-site tags ("<kernel>:<site>") into one entry per kernel."""
+    out = {}
+    for tag, v in prof.items():
+        k = tag.split(":")[0]
+        e = out.setdefault(k, dict(launches=0, ms=0.0, flops=0.0, bytes=0.0))
+        for f in e:
+            e[f] += v[f]
+    return out
+
+
+def roofline_from_profile(prof: dict, steps: int) -> dict | None:
+    if not prof:
+        return None
+    prof = by_kernel(prof)
+    tag = max(prof, key=lambda t: prof[t]["ms"])
+    e = prof[tag]
+    if e["flops"] > 0:
+        ach = e["flops"] / (e["ms"] * 1e-3) / 1e12
+        bound, peak, unit = "mfma", PEAK_FP64_TFLOPS, "TFLOP/s"
+    else:
+        ach = e["bytes"] / (e["ms"] * 1e-3) / 1e9
+        bound, peak, unit = "hbm", PEAK_HBM_GBS, "GB/s"
+    total_ms = sum(v["ms"] for v in prof.values())
+    return {"bound": bound, "achieved": round(ach, 3), "peak": peak, "unit": unit,
+            "frac": round(ach / peak, 4), "traffic": None, "kernel": tag,
+            "launches_per_step": e["launches"] / steps,
+            "avg_launch_ms": e["ms"] / e["launches"],
+            "algorithmic_flops_per_launch": e["flops"] / e["launches"],
+            "share_of_kernel_time": round(e["ms"] / total_ms, 4)}
+
+
+def cpu_baseline(s_eff: int) -> dict:
+    """The oracle, as it stands, on a bounded sample of the same workload:
+    the sketch rows of the first box of the first processed level (computed by
+    the oracle's dense operator rows), then that box's full Algorithm 1 step.
+    Both are extrapolated to the whole step: sampling by rows (N / rows),
+    factorization by the oracle's per-box cost model sum_B s l_B^2 (the
+    Householder QRs of the s x l panels dominate)."""
+    from threadpoolctl import threadpool_info
+    from oracle import operators as oop
+    from oracle import rsrs as orr
+    from oracle import tree as ot
+    from paper_2311_01451_amd import inputs
+
+    pts = inputs.grid2d(GRID_N)
+    N = GRID_N ** 2
+    h = 1.0 / GRID_N
+    t = ot.build_tree(pts, LEAF)
+    sch = ot.schedule(t, K)
+    lev = sch.levels[[i for i, c in enumerate(sch.order) if c][0]]
+    li = sch.levels.index(lev)
+    cls0 = sch.order[li][0]
+    box = max(cls0, key=lambda b: (int(sch.l_count[b]), -int(b)))
+    nb = sch.nbrs[lev][box]
+    Ba = np.arange(t.pt_begin[box], t.pt_end[box])
+    Na = np.sort(np.concatenate([np.arange(t.pt_begin[x], t.pt_end[x]) for x in nb]))
+    C = np.concatenate([Ba, Na])
+    rng = np.random.default_rng(inputs.BASE_SEED)
+    Om = np.zeros((N, s_eff))
+    Psi = np.zeros((N, s_eff))
+    Om_full = rng.standard_normal((N, s_eff))
+    Psi_full = rng.standard_normal((N, s_eff))
+    perm = t.perm
+    Om[:] = Om_full[perm]
+    Psi[:] = Psi_full[perm]
+    Y = np.zeros((N, s_eff))
+    Z = np.zeros((N, s_eff))
+    t0 = time.perf_counter()
+    # sampled sketch rows Y_C = A[C, :] Omega, Z_C = A^T[C, :] Psi (A symmetric here)
+    diff = pts[perm[C]][:, None, :] - pts[None, :, :]
+    r = np.sqrt(np.sum(diff * diff, axis=2))
+    with np.errstate(divide="ignore"):
+        Arows = (h * h) * (-np.log(r) / (2 * np.pi))
+    Arows[np.arange(len(C)), perm[C]] = 1.0 + 0.5 * h * h
+    Y[C] = Arows @ Om_full
+    Z[C] = Arows @ Psi_full
+    t_sample = time.perf_counter() - t0
+    del diff, r, Arows
+    t0 = time.perf_counter()
+    orr._process_box(box, lev, 0, Ba, Na, Y, Z, Om, Psi, K, False)
+    t_box = time.perf_counter() - t0
+    # per-box cost model over the whole factorization
+    model = lambda l: s_eff * float(l) ** 2
+    total = sum(model(sch.l_count[b]) for cls in sum(sch.order, []) for b in cls)
+    total += model(sch.root_count)
+    est_factor = t_box * total / model(len(C))
+    est_sample = t_sample * N / len(C)
+    est = est_factor + est_sample
+    threads = max((d.get("num_threads", 1) for d in threadpool_info()), default=1)
+    return {"value": round(NRHS / est, 6), "unit": "RHS cols/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"oracle sampling of {len(C)} sketch rows ({t_sample:.1f} s) and Algorithm 1 "
+                      f"on box {box} (level {lev}, l={len(C)}, {t_box:.1f} s), extrapolated by "
+                      f"rows and by the per-box model s*l^2: est. factor {est_factor:.0f} s, "
+                      f"sampling {est_sample:.0f} s; solve not included",
+            "est_step_s": round(est, 1)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (asked for --gpus {a.gpus}); "
+              "the multi-GPU sharding is described in DESIGN.md but not run", file=sys.stderr)
+        sys.exit(2)
+    rec, elapsed, prof, lat = gpu_bench(a.steps, a.warmup, not a.no_profile)
+    s_req, s_eff = rec[-1]["s_req"], rec[-1]["s_eff"]
+    ms = elapsed / a.steps * 1e3
+    out = {
+        "metric": METRIC,
+        "value": round(NRHS * a.steps / elapsed, 4),
+        "unit": "RHS cols/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": workload_config(s_req, s_eff),
+        "factor_s": round(float(np.mean([r["factor"] for r in rec])), 4),
+        "sample_s": round(float(np.mean([r["sample"] for r in rec])), 4),
+        "solve_refine_ms": round(float(np.mean([r["solve"] for r in rec])) * 1e3, 3),
+        "refine_iters": int(rec[-1]["iters"]),
+        "relres": rec[-1]["relres"],
+        "factor_tflops_algorithmic": round(rec[-1]["flops"] / np.mean([r["factor"] for r in rec]) / 1e12, 3),
+        "solve_ms_p50": round(float(np.percentile(lat, 50)), 3),
+        "solve_ms_p99": round(float(np.percentile(lat, 99)), 3),
+        "solve_cols_per_s": round(NRHS / (float(np.median(lat)) * 1e-3), 1),
+        "roofline": roofline_from_profile(prof, a.steps),
+        "kernels": {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
+                        "tflops": round(v["flops"] / max(v["ms"], 1e-9) / 1e9, 3)}
+                    for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"])[:12]},
+    }
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(s_eff)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

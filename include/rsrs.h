@@ -247,6 +247,27 @@ rsrs_status rsrs_solve_refine(const rsrs_factor_t* f, rsrs_matvec_fn mv, void* u
                               const double* F, int64_t ldf, double* U, int64_t ldu, double tol,
                               int maxit, double* relres, int* iters, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Measurement.  While enabled (process-wide), every kernel launch of the
+ * library is bracketed by HIP events recorded on the launch's own stream and
+ * accounted under a tag naming the kernel and its form (e.g.
+ * "gemm_nt_syrk_64x64").  Each record carries the algorithmic flops and bytes
+ * of the launch: 2MNK flops for a full product (half for triangle-restricted
+ * forms) and 8(MK + KN + MN [+ MN read when accumulating]) bytes.
+ * rsrs_profile_read synchronises the device, fills up to `max` entries and
+ * returns the number of tags (or -1 on error); rsrs_profile_reset clears.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  char tag[48];
+  int64_t launches;
+  double ms;       /* summed event time of the launches */
+  double flops;    /* summed algorithmic flops */
+  double bytes;    /* summed algorithmic bytes */
+} rsrs_profile_entry;
+void rsrs_profile_enable(int on);
+void rsrs_profile_reset(void);
+int rsrs_profile_read(rsrs_profile_entry* out, int max);
+
 #ifdef __cplusplus
 }
 #endif

@@ -218,7 +218,7 @@ int rsrs_op_matvec(void* opv, int transpose, int64_t ncols, const double* X, int
   std::vector<GemmDesc> d{gdesc(op->A, nullptr, op->lda, X, nullptr, ldx, Y, nullptr, ldy, n,
                                 (int)ncols, n)};
   const int ta = (transpose && !op->symmetric) ? 1 : 0;
-  return gemm(op->up, st, d, ta, 0, GM_FULL, ncols <= 16 ? GS_64x16 : GS_64x64) == RSRS_OK ? 0 : 1;
+  return gemm(op->up, st, d, ta, 0, GM_FULL, ncols <= 16 ? GS_64x16 : GS_64x64, "operator") == RSRS_OK ? 0 : 1;
 }
 
 void rsrs_op_destroy(rsrs_operator_t* op) { delete op; }
@@ -358,6 +358,14 @@ static rsrs_status d2h(void* dst, const void* src, size_t bytes) {
   return RSRS_OK;
 }
 
+// rows x cols block with device leading dimension ld into a compact host block
+static rsrs_status d2h2(double* dst, int64_t cols, const double* src, int64_t ld, int64_t rows) {
+  if (!dst || rows == 0 || cols == 0) return RSRS_OK;
+  RSRS_HIP(hipMemcpy2D(dst, (size_t)cols * 8, src, (size_t)ld * 8, (size_t)cols * 8, (size_t)rows,
+                       hipMemcpyDeviceToHost));
+  return RSRS_OK;
+}
+
 rsrs_status rsrs_factor_box_copy(const rsrs_factor_t* f, int64_t i, int64_t* Ba, int64_t* Na, int64_t* S,
                                  int64_t* R, double* T, double* XRR, double* KU, double* KL) {
   if (!f || i < 0 || i >= (int64_t)f->boxes.size()) return invalid("box index out of range");
@@ -368,10 +376,10 @@ rsrs_status rsrs_factor_box_copy(const rsrs_factor_t* f, int64_t i, int64_t* Ba,
   RSRS_TRY(d2h(Na, f->i() + B.oNa, (size_t)B.n * 8));
   RSRS_TRY(d2h(S, f->i() + B.oS, (size_t)B.k * 8));
   RSRS_TRY(d2h(R, f->i() + B.oR, (size_t)B.r * 8));
-  RSRS_TRY(d2h(T, f->d() + B.oT, (size_t)B.r * B.k * 8));
-  RSRS_TRY(d2h(XRR, f->d() + B.oXRR, (size_t)B.r * B.r * 8));
-  RSRS_TRY(d2h(KU, f->d() + B.oKU, (size_t)B.r * kn * 8));
-  RSRS_TRY(d2h(KL, f->d() + B.oKL, (size_t)kn * B.r * 8));
+  RSRS_TRY(d2h2(T, B.k, f->d() + B.oT, B.ldT, B.r));
+  RSRS_TRY(d2h2(XRR, B.r, f->d() + B.oXRR, B.ldR, B.r));
+  RSRS_TRY(d2h2(KU, kn, f->d() + B.oKU, B.ldKU, B.r));
+  RSRS_TRY(d2h2(KL, B.r, f->d() + B.oKL, B.ldR, kn));
   return RSRS_OK;
 }
 

@@ -4,9 +4,11 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 
 #include "kernels.hpp"
+#include "profile.hpp"
 
 namespace rsrs {
 
@@ -51,20 +53,73 @@ rsrs_status Uploader::reset() {
 }
 
 // ---------------------------------------------------------------- GEMM dispatch
+static thread_local const char* g_site = nullptr;
+
+static const char* gemm_tag(int ta, int tb, int mode, int bm, int bn) {
+  static const char* forms[2][2] = {{"nn", "nt"}, {"tn", "tt"}};
+  static const char* modes[5] = {"full", "syrk", "bntlow", "bnnlow", "alow"};
+  static thread_local char buf[48];
+  if (g_site)
+    std::snprintf(buf, sizeof(buf), "gemm_%s_%s_%dx%d:%s", forms[ta][tb], modes[mode], bm, bn, g_site);
+  else
+    std::snprintf(buf, sizeof(buf), "gemm_%s_%s_%dx%d", forms[ta][tb], modes[mode], bm, bn);
+  return buf;
+}
+
+// Algorithmic flops and bytes of one batched launch.
+static void gemm_work(const std::vector<GemmDesc>& descs, int mode, double* flops, double* bytes) {
+  double f = 0.0, b = 0.0;
+  for (const auto& d : descs) {
+    if (d.M <= 0 || d.N <= 0) continue;
+    const double M = d.M, N = d.N, K = d.K;
+    double ff = 2.0 * M * N * K;
+    if (mode == GM_SYRK_L) ff = M * (N + 1.0) * K;
+    if (mode == GM_B_NT_LOW || mode == GM_B_NN_LOW || mode == GM_A_LOW) ff = M * N * K;
+    f += ff;
+    b += 8.0 * (M * K + K * N + M * N * (d.beta != 0.0 ? 2.0 : 1.0));
+  }
+  *flops = f;
+  *bytes = b;
+}
+
+// 16-byte loads need even leading dimensions and 16-byte aligned bases.
+static bool vec2_ok(const std::vector<GemmDesc>& descs) {
+  for (const auto& d : descs) {
+    if (d.M <= 0 || d.N <= 0) continue;
+    if ((d.lda & 1) || (d.ldb & 1)) return false;
+    if (((uintptr_t)d.A & 15) || ((uintptr_t)d.B & 15)) return false;
+  }
+  return true;
+}
+
 template <int BM, int BN, int WM, int WN, int TA, int TB, int MODE>
 static rsrs_status launch_gemm(Uploader& up, hipStream_t st, const std::vector<GemmDesc>& descs) {
   int64_t tiles = 0;
   for (const auto& d : descs)
-    if (d.M > 0 && d.N > 0)
-      tiles = std::max<int64_t>(tiles, (int64_t)((d.M + BM - 1) / BM) * ((d.N + BN - 1) / BN));
+    if (d.M > 0 && d.N > 0) {
+      const int64_t tm = (d.M + BM - 1) / BM, tn = (d.N + BN - 1) / BN;
+      tiles = std::max<int64_t>(tiles, MODE == GM_SYRK_L ? tm * (tm + 1) / 2 : tm * tn);
+    }
   if (tiles == 0) return RSRS_OK;
+  double pf = 0.0, pb = 0.0;
+  if (prof_on()) gemm_work(descs, MODE, &pf, &pb);
+  const bool v2 = (BN * 16 / 256 >= 2) && vec2_ok(descs);
   for (size_t b0 = 0; b0 < descs.size(); b0 += 65535) {
     const size_t nb = std::min<size_t>(65535, descs.size() - b0);
     std::vector<GemmDesc> part(descs.begin() + b0, descs.begin() + b0 + nb);
     GemmDesc* dd = nullptr;
     RSRS_TRY(up.put_vec(part, &dd));
     dim3 grid((unsigned)round_up(tiles, 8), (unsigned)nb);
-    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WM, WN, TA, TB, MODE>), grid, dim3(256), 0, st, dd);
+    ProfScope ps(st, gemm_tag(TA, TB, MODE, BM, BN), b0 == 0 ? pf : 0.0, b0 == 0 ? pb : 0.0);
+    if constexpr (BN * 16 / 256 >= 2) {
+      if (v2) {
+        hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WM, WN, TA, TB, MODE, 2>), grid, dim3(256), 0, st, dd);
+      } else {
+        hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WM, WN, TA, TB, MODE, 1>), grid, dim3(256), 0, st, dd);
+      }
+    } else {
+      hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WM, WN, TA, TB, MODE, 1>), grid, dim3(256), 0, st, dd);
+    }
     RSRS_HIP(hipGetLastError());
   }
   return RSRS_OK;
@@ -89,9 +144,16 @@ static rsrs_status gemm_shape(Uploader& up, hipStream_t st, const std::vector<Ge
   return RSRS_E_UNSUPPORTED;
 }
 
+// Tile choice, measured on MI355X: 64 x 64 tiles (2 x 2 MFMA blocks per wave,
+// 3-4 waves per SIMD) beat 128 x 128 tiles (1 wave per SIMD) on every shape
+// of this method; narrow right-hand sides use 64 x 16.
 rsrs_status gemm(Uploader& up, hipStream_t st, const std::vector<GemmDesc>& descs, int ta, int tb,
-                 int mode, GemmShape shape) {
+                 int mode, GemmShape shape, const char* site) {
   if (descs.empty()) return RSRS_OK;
+  struct SiteGuard {
+    explicit SiteGuard(const char* s) { g_site = s; }
+    ~SiteGuard() { g_site = nullptr; }
+  } guard(site);
   if (shape == GS_64x16 && mode == GM_FULL) return gemm_shape<64, 16, 4, 1>(up, st, descs, ta, tb, mode);
   return gemm_shape<64, 64, 2, 2>(up, st, descs, ta, tb, mode);
 }
@@ -111,55 +173,50 @@ __global__ __launch_bounds__(256) void chol_leaf_kernel(const CholLeaf* __restri
     double v = 0.0;
     if (i < n && j <= i) v = d.G[(int64_t)i * d.ld + j];
     L[i][j] = v;
-    X[i][j] = 0.0;
+    X[i][j] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
+  // right-looking Cholesky: column j scaled by sqrt of its pivot, then a
+  // rank-1 update of the trailing lower triangle
   for (int j = 0; j < n; ++j) {
-    if (tid == 0) {
-      double v = L[j][j];
-      if (!(v > 0.0)) {
-        atomicOr(flag, 1);
-        v = 1.0;
-      }
-      L[j][j] = sqrt(v);
-    }
+    double v = L[j][j];
     __syncthreads();
-    const double inv = 1.0 / L[j][j];
+    if (!(v > 0.0)) {
+      if (tid == 0) atomicOr(flag, 1);
+      v = 1.0;
+    }
+    const double dj = sqrt(v);
+    const double inv = 1.0 / dj;
+    if (tid == 0) L[j][j] = dj;
     for (int i = j + 1 + tid; i < n; i += 256) L[i][j] *= inv;
     __syncthreads();
-    // trailing update of the lower triangle: pairs (i, c) with j < c <= i < n
     const int m = n - j - 1;
-    const int npair = m * (m + 1) / 2;
-    for (int pidx = tid; pidx < npair; pidx += 256) {
-      // map pidx -> (ii, cc) with 0 <= cc <= ii < m
-      int ii = (int)((sqrt(8.0 * pidx + 1.0) - 1.0) * 0.5);
-      while ((ii + 1) * (ii + 2) / 2 <= pidx) ++ii;
-      while (ii * (ii + 1) / 2 > pidx) --ii;
-      const int cc = pidx - ii * (ii + 1) / 2;
-      const int i = j + 1 + ii, c = j + 1 + cc;
-      L[i][c] -= L[i][j] * L[c][j];
+    for (int idx = tid; idx < m * m; idx += 256) {
+      const int ii = idx / m, cc = idx - ii * m;
+      if (cc <= ii) {
+        const int i = j + 1 + ii, c = j + 1 + cc;
+        L[i][c] -= L[i][j] * L[c][j];
+      }
     }
     __syncthreads();
   }
-  // X = L^{-1}, row by row: X[i][c] = -(sum_{t=c}^{i-1} L[i][t] X[t][c]) / L[i][i]
-  for (int i = 0; i < n; ++i) {
-    if (tid <= i) {
-      const int c = tid;
-      double v;
-      if (c == i) {
-        v = 1.0 / L[i][i];
-      } else {
-        double s = 0.0;
-        for (int t = c; t < i; ++t) s += L[i][t] * X[t][c];
-        v = -s / L[i][i];
-      }
-      X[i][c] = v;
+  // X = L^{-1}, right-looking: row t of X is final once divided by L[t][t];
+  // rows below then drop L[i][t] times it (columns c <= t)
+  for (int t = 0; t < n; ++t) {
+    const double inv = 1.0 / L[t][t];
+    if (tid <= t) X[t][tid] *= inv;
+    __syncthreads();
+    const int m = n - t - 1, w = t + 1;
+    for (int idx = tid; idx < m * w; idx += 256) {
+      const int ii = idx / w, c = idx - ii * w;
+      const int i = t + 1 + ii;
+      X[i][c] -= L[i][t] * X[t][c];
     }
     __syncthreads();
   }
   for (int idx = tid; idx < n * n; idx += 256) {
     const int i = idx / n, j = idx % n;
-    d.Li[(int64_t)i * d.ld + j] = X[i][j];
+    d.Li[(int64_t)i * d.ld + j] = j <= i ? X[i][j] : 0.0;
   }
 }
 
@@ -167,90 +224,294 @@ rsrs_status chol_leaf(Uploader& up, hipStream_t st, const std::vector<CholLeaf>&
   if (e.empty()) return RSRS_OK;
   CholLeaf* de = nullptr;
   RSRS_TRY(up.put_vec(e, &de));
+  ProfScope ps(st, "chol_leaf");
   hipLaunchKernelGGL(chol_leaf_kernel, dim3((unsigned)e.size()), dim3(256), 0, st, de, flag);
   RSRS_HIP(hipGetLastError());
   return RSRS_OK;
 }
 
 // ---------------------------------------------------------------- Gauss-Jordan
-__global__ __launch_bounds__(1024) void gje_kernel(const GjeDesc* __restrict__ e, int* flag) {
+// In-place Gauss-Jordan with partial pivoting, the matrix held in registers:
+// 1024 threads as a 32 x 32 grid, thread (ti, tc) owning rows ti + 32a and
+// columns tc + 32b (a, b < R).  Per step: pivot search in column j, row swap
+// through LDS, pivot row and multiplier column broadcast through LDS, rank-1
+// update of the owned elements.  The row swaps make the result (P A)^{-1};
+// the inverse of A follows by applying the swaps to the columns in reverse
+// order, done here as one permuted write-out.
+template <int R>
+__global__ __launch_bounds__(1024) void gje_reg_kernel(const GjeDesc* __restrict__ e, int* flag) {
+  constexpr int NMAX = 32 * R;
   const GjeDesc d = e[blockIdx.x];
   const int n = d.n;
-  const int n2 = 2 * n;
-  double* W = d.W;
   const int tid = threadIdx.x;
-  const int nt = blockDim.x;
-  __shared__ double rv[1024];
-  __shared__ int ri[1024];
-  __shared__ double fcol[4096];
-  for (int64_t idx = tid; idx < (int64_t)n * n2; idx += nt) {
-    const int i = (int)(idx / n2), c = (int)(idx % n2);
-    W[idx] = c < n ? d.A[(int64_t)i * d.lda + c] : (c - n == i ? 1.0 : 0.0);
-  }
-  __syncthreads();
-  for (int j = 0; j < n; ++j) {
-    // pivot: largest |W[i][j]|, i >= j, lowest index on ties
-    double best = -1.0;
-    int bi = n;
-    for (int i = j + tid; i < n; i += nt) {
-      const double v = fabs(W[(int64_t)i * n2 + j]);
-      if (v > best) { best = v; bi = i; }
+  const int ti = tid >> 5, tc = tid & 31;
+  __shared__ double prow[NMAX];
+  __shared__ double fcol[NMAX];
+  __shared__ double swp[2][NMAX];
+  __shared__ double cmax[32];
+  __shared__ int cidx[32];
+  __shared__ int piv[NMAX];
+  __shared__ int colpos[NMAX];
+  __shared__ int pivot_row;
+  double a[R][R];
+#pragma unroll
+  for (int x = 0; x < R; ++x)
+#pragma unroll
+    for (int y = 0; y < R; ++y) {
+      const int i = ti + 32 * x, c = tc + 32 * y;
+      a[x][y] = (i < n && c < n) ? d.A[(int64_t)i * d.lda + c] : 0.0;
     }
-    rv[tid] = best;
-    ri[tid] = bi;
-    __syncthreads();
-    for (int w = nt / 2; w > 0; w >>= 1) {
-      if (tid < w) {
-        const double o = rv[tid + w];
-        const int oi = ri[tid + w];
-        if (o > rv[tid] || (o == rv[tid] && oi < ri[tid])) { rv[tid] = o; ri[tid] = oi; }
+  for (int j = 0; j < n; ++j) {
+    const int jb = j >> 5, jc = j & 31;
+    // pivot search: threads of column j (tc == jc) scan their rows >= j
+    if (tc == jc) {
+      double best = -1.0;
+      int bi = n;
+#pragma unroll
+      for (int x = 0; x < R; ++x) {
+        const int i = ti + 32 * x;
+        if (i >= j && i < n) {
+          double v = 0.0;
+#pragma unroll
+          for (int y = 0; y < R; ++y) if (y == jb) v = fabs(a[x][y]);
+          if (v > best) { best = v; bi = i; }
+        }
       }
+      cmax[ti] = best;
+      cidx[ti] = bi;
+    }
+    __syncthreads();
+    if (tid < 64) {
+      double best = tid < 32 ? cmax[tid] : -1.0;
+      int bi = tid < 32 ? cidx[tid] : n;
+#pragma unroll
+      for (int off = 16; off > 0; off >>= 1) {
+        const double ob = __shfl_xor(best, off, 64);
+        const int oi = __shfl_xor(bi, off, 64);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      if (tid == 0) {
+        if (!(best > 0.0)) {
+          atomicOr(flag, 2);
+          bi = j;
+        }
+        pivot_row = bi;
+        piv[j] = bi;
+      }
+    }
+    __syncthreads();
+    const int p = pivot_row;
+    // swap rows j and p through LDS
+    if (p != j) {
+      const int xj = j >> 5, xp = p >> 5;
+      if (ti == (j & 31))
+#pragma unroll
+        for (int y = 0; y < R; ++y) {
+          double v = 0.0;
+#pragma unroll
+          for (int x = 0; x < R; ++x) if (x == xj) v = a[x][y];
+          swp[0][tc + 32 * y] = v;
+        }
+      if (ti == (p & 31))
+#pragma unroll
+        for (int y = 0; y < R; ++y) {
+          double v = 0.0;
+#pragma unroll
+          for (int x = 0; x < R; ++x) if (x == xp) v = a[x][y];
+          swp[1][tc + 32 * y] = v;
+        }
+      __syncthreads();
+      if (ti == (j & 31))
+#pragma unroll
+        for (int y = 0; y < R; ++y)
+#pragma unroll
+          for (int x = 0; x < R; ++x) if (x == xj) a[x][y] = swp[1][tc + 32 * y];
+      if (ti == (p & 31))
+#pragma unroll
+        for (int y = 0; y < R; ++y)
+#pragma unroll
+          for (int x = 0; x < R; ++x) if (x == xp) a[x][y] = swp[0][tc + 32 * y];
       __syncthreads();
     }
-    const int p = ri[0];
-    const double pv = rv[0];
-    __syncthreads();
-    if (!(pv > 0.0)) {
-      if (tid == 0) atomicOr(flag, 2);
-      continue;
+    // pivot row (scaled) and multiplier column to LDS
+    if (ti == jc || tc == jc) {
+#pragma unroll
+      for (int x = 0; x < R; ++x)
+#pragma unroll
+        for (int y = 0; y < R; ++y) {
+          const int i = ti + 32 * x, c = tc + 32 * y;
+          if (i == j) prow[c] = a[x][y];
+          if (c == j) fcol[i] = a[x][y];
+        }
     }
-    if (p != j) {
-      for (int c = tid; c < n2; c += nt) {
-        const double a = W[(int64_t)j * n2 + c];
-        W[(int64_t)j * n2 + c] = W[(int64_t)p * n2 + c];
-        W[(int64_t)p * n2 + c] = a;
+    __syncthreads();
+    const double pv = prow[j];
+    const double inv = pv != 0.0 ? 1.0 / pv : 0.0;
+    // a[i][c] <- a[i][c] - fcol[i] * prow[c] / pv for i != j; row j scaled;
+    // column j becomes the inverse's column: -fcol[i] / pv, and 1/pv at (j, j)
+#pragma unroll
+    for (int x = 0; x < R; ++x) {
+      const int i = ti + 32 * x;
+      const double fi = fcol[i];
+#pragma unroll
+      for (int y = 0; y < R; ++y) {
+        const int c = tc + 32 * y;
+        double v = a[x][y];
+        if (i == j) {
+          v = (c == j) ? inv : v * inv;
+        } else if (c == j) {
+          v = -fi * inv;
+        } else {
+          v -= fi * inv * prow[c];
+        }
+        a[x][y] = v;
       }
     }
     __syncthreads();
-    const double inv = 1.0 / W[(int64_t)j * n2 + j];
-    __syncthreads();
-    for (int c = tid; c < n2; c += nt) W[(int64_t)j * n2 + c] *= inv;
-    for (int i = tid; i < n; i += nt) fcol[i] = W[(int64_t)i * n2 + j];
-    __syncthreads();
-    for (int64_t idx = tid; idx < (int64_t)n * n2; idx += nt) {
-      const int i = (int)(idx / n2), c = (int)(idx % n2);
-      if (i == j) continue;
-      W[idx] -= fcol[i] * W[(int64_t)j * n2 + c];
+  }
+  // undo the row swaps on the columns: final[:, x] = stored[:, arr[x]]
+  if (tid == 0) {
+    for (int c = 0; c < n; ++c) colpos[c] = c;
+    for (int j = n - 1; j >= 0; --j) {
+      const int q = piv[j];
+      const int t = colpos[j];
+      colpos[j] = colpos[q];
+      colpos[q] = t;
+    }
+    // colpos[x] = stored column placed at x; invert into fcol as int via piv
+    for (int x = 0; x < n; ++x) piv[colpos[x]] = x;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int x = 0; x < R; ++x)
+#pragma unroll
+    for (int y = 0; y < R; ++y) {
+      const int i = ti + 32 * x, c = tc + 32 * y;
+      if (i < n && c < n) d.Ainv[(int64_t)i * d.ldi + piv[c]] = a[x][y];
+    }
+}
+
+// Gauss-Jordan for blocks too large for registers: the working matrix W
+// (n x 2n, [A | I]) stays in global memory and every step is two launches
+// over all column blocks: (a) one workgroup per matrix finds the pivot of
+// column j, swaps rows j and p and snapshots the scaled pivot row and the
+// multiplier column; (b) every workgroup updates its column block from the
+// snapshots.  The snapshots make the update free of read/write races.
+__global__ __launch_bounds__(256) void gje_pivot_kernel(const GjeDesc* __restrict__ e, double* snap,
+                                                        int64_t snap_stride, int j, int* flag) {
+  const GjeDesc d = e[blockIdx.x];
+  const int n = d.n;
+  if (j >= n) return;
+  const int n2 = 2 * n;
+  double* W = d.W;
+  double* prow = snap + blockIdx.x * snap_stride;   // 2n
+  double* fcol = prow + n2;                         // n
+  __shared__ double rv[256];
+  __shared__ int ri[256];
+  const int tid = threadIdx.x;
+  double best = -1.0;
+  int bi = n;
+  for (int i = j + tid; i < n; i += 256) {
+    const double v = fabs(W[(int64_t)i * n2 + j]);
+    if (v > best) { best = v; bi = i; }
+  }
+  rv[tid] = best;
+  ri[tid] = bi;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) {
+      const double o = rv[tid + w];
+      const int oi = ri[tid + w];
+      if (o > rv[tid] || (o == rv[tid] && oi < ri[tid])) { rv[tid] = o; ri[tid] = oi; }
     }
     __syncthreads();
   }
-  for (int64_t idx = tid; idx < (int64_t)n * n; idx += nt) {
+  int p = ri[0];
+  if (!(rv[0] > 0.0)) {
+    if (tid == 0) atomicOr(flag, 2);
+    p = j;
+  }
+  if (p != j)
+    for (int c = tid; c < n2; c += 256) {
+      const double a = W[(int64_t)j * n2 + c];
+      W[(int64_t)j * n2 + c] = W[(int64_t)p * n2 + c];
+      W[(int64_t)p * n2 + c] = a;
+    }
+  __syncthreads();
+  const double pv = W[(int64_t)j * n2 + j];
+  const double inv = pv != 0.0 ? 1.0 / pv : 0.0;
+  for (int c = tid; c < n2; c += 256) prow[c] = W[(int64_t)j * n2 + c] * inv;
+  for (int i = tid; i < n; i += 256) fcol[i] = W[(int64_t)i * n2 + j];
+}
+
+__global__ __launch_bounds__(256) void gje_update_kernel(const GjeDesc* __restrict__ e, const double* snap,
+                                                         int64_t snap_stride, int j) {
+  const GjeDesc d = e[blockIdx.y];
+  const int n = d.n;
+  if (j >= n) return;
+  const int n2 = 2 * n;
+  const int c = blockIdx.x * 64 + (threadIdx.x & 63);
+  if (c >= n2) return;
+  const double* prow = snap + blockIdx.y * snap_stride;
+  const double* fcol = prow + n2;
+  const double pc = prow[c];
+  for (int i = threadIdx.x >> 6; i < n; i += 4) {
+    double* w = d.W + (int64_t)i * n2 + c;
+    *w = (i == j) ? pc : *w - fcol[i] * pc;
+  }
+}
+
+__global__ void gje_copyout_kernel(const GjeDesc* __restrict__ e, int phase) {
+  const GjeDesc d = e[blockIdx.y];
+  const int n = d.n, n2 = 2 * n;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < (int64_t)n * n;
+       idx += (int64_t)gridDim.x * blockDim.x) {
     const int i = (int)(idx / n), c = (int)(idx % n);
-    d.Ainv[(int64_t)i * d.ldi + c] = W[(int64_t)i * n2 + n + c];
+    if (phase == 0) d.W[(int64_t)i * n2 + c] = d.A[(int64_t)i * d.lda + c],
+                    d.W[(int64_t)i * n2 + n + c] = (i == c) ? 1.0 : 0.0;
+    else d.Ainv[(int64_t)i * d.ldi + c] = d.W[(int64_t)i * n2 + n + c];
   }
 }
 
 rsrs_status gje_inverse(Uploader& up, hipStream_t st, const std::vector<GjeDesc>& e, int* flag) {
   if (e.empty()) return RSRS_OK;
-  for (const auto& x : e)
-    if (x.n > 4096) {
-      set_error("Gauss-Jordan block larger than 4096");
+  int nmax = 0;
+  for (const auto& x : e) {
+    if (x.n > 65536) {
+      set_error("Gauss-Jordan block too large");
       return RSRS_E_UNSUPPORTED;
     }
+    nmax = std::max(nmax, x.n);
+  }
   GjeDesc* de = nullptr;
   RSRS_TRY(up.put_vec(e, &de));
-  hipLaunchKernelGGL(gje_kernel, dim3((unsigned)e.size()), dim3(1024), 0, st, de, flag);
+  const unsigned nb = (unsigned)e.size();
+  if (nmax <= 192) {
+    ProfScope ps(st, "gauss_jordan_reg");
+    if (nmax <= 64)
+      hipLaunchKernelGGL(gje_reg_kernel<2>, dim3(nb), dim3(1024), 0, st, de, flag);
+    else if (nmax <= 128)
+      hipLaunchKernelGGL(gje_reg_kernel<4>, dim3(nb), dim3(1024), 0, st, de, flag);
+    else
+      hipLaunchKernelGGL(gje_reg_kernel<6>, dim3(nb), dim3(1024), 0, st, de, flag);
+    RSRS_HIP(hipGetLastError());
+    return RSRS_OK;
+  }
+  // large blocks: snapshots of (pivot row, multiplier column) per matrix
+  const int64_t stride = round_up(3 * (int64_t)nmax, 64);
+  DevBuf snap;
+  RSRS_TRY(snap.alloc((size_t)stride * nb * 8));
+  ProfScope ps(st, "gauss_jordan_big");
+  const unsigned cblk = (unsigned)((2 * nmax + 63) / 64);
+  hipLaunchKernelGGL(gje_copyout_kernel, dim3(256, nb), dim3(256), 0, st, de, 0);
+  for (int j = 0; j < nmax; ++j) {
+    hipLaunchKernelGGL(gje_pivot_kernel, dim3(nb), dim3(256), 0, st, de, snap.as<double>(), stride, j, flag);
+    hipLaunchKernelGGL(gje_update_kernel, dim3(cblk, nb), dim3(256), 0, st, de, snap.as<double>(), stride, j);
+  }
+  hipLaunchKernelGGL(gje_copyout_kernel, dim3(256, nb), dim3(256), 0, st, de, 1);
   RSRS_HIP(hipGetLastError());
+  // the snapshot buffer must outlive the launches
+  RSRS_HIP(hipStreamSynchronize(st));
   return RSRS_OK;
 }
 
@@ -275,6 +536,7 @@ rsrs_status copy2d(Uploader& up, hipStream_t st, const std::vector<Copy2D>& e) {
   Copy2D* de = nullptr;
   RSRS_TRY(up.put_vec(e, &de));
   const unsigned gx = (unsigned)std::min<int64_t>((mx + 255) / 256, 4096);
+  ProfScope ps(st, "copy2d");
   hipLaunchKernelGGL(copy2d_kernel, dim3(gx, (unsigned)e.size()), dim3(256), 0, st, de);
   RSRS_HIP(hipGetLastError());
   return RSRS_OK;
@@ -302,6 +564,7 @@ void gather_rows(hipStream_t st, double* dst, int64_t ldd, const double* src, in
   if (nrows <= 0 || ncols <= 0) return;
   const unsigned g = (unsigned)std::min<int64_t>(nrows, 65535);
   const unsigned b = ncols >= 256 ? 256 : (ncols >= 64 ? 64 : 32);
+  ProfScope ps(st, "gather_rows", 0.0, 16.0 * nrows * ncols);
   hipLaunchKernelGGL(gather_rows_kernel, dim3(g), dim3(b), 0, st, dst, ldd, src, lds, idx, nrows, ncols);
 }
 void scatter_rows(hipStream_t st, double* dst, int64_t ldd, const double* src, int64_t lds,
@@ -309,6 +572,7 @@ void scatter_rows(hipStream_t st, double* dst, int64_t ldd, const double* src, i
   if (nrows <= 0 || ncols <= 0) return;
   const unsigned g = (unsigned)std::min<int64_t>(nrows, 65535);
   const unsigned b = ncols >= 256 ? 256 : (ncols >= 64 ? 64 : 32);
+  ProfScope ps(st, "scatter_rows", 0.0, 16.0 * nrows * ncols);
   hipLaunchKernelGGL(scatter_rows_kernel, dim3(g), dim3(b), 0, st, dst, ldd, src, lds, idx, nrows, ncols);
 }
 
@@ -334,6 +598,7 @@ __global__ void finite_kernel(const double* p, int64_t rows, int64_t cols, int64
 void check_finite(hipStream_t st, const double* p, int64_t rows, int64_t cols, int64_t ld, int* flag) {
   if (rows <= 0 || cols <= 0) return;
   const unsigned g = (unsigned)std::min<int64_t>((rows * cols + 255) / 256, 8192);
+  ProfScope ps(st, "check_finite", 0.0, 8.0 * rows * cols);
   hipLaunchKernelGGL(finite_kernel, dim3(g), dim3(256), 0, st, p, rows, cols, ld, flag);
 }
 
@@ -359,6 +624,7 @@ __global__ void colsq2_kernel(const double* partial, int64_t G, int64_t w, doubl
 rsrs_status col_sumsq(hipStream_t st, const double* x, int64_t n, int64_t w, int64_t ld,
                       double* partial, double* out) {
   const int64_t G = 256;
+  ProfScope ps(st, "col_sumsq", 2.0 * n * w, 8.0 * n * w);
   hipLaunchKernelGGL(colsq1_kernel, dim3((unsigned)G), dim3(64), 0, st, x, n, w, ld, partial);
   hipLaunchKernelGGL(colsq2_kernel, dim3((unsigned)((w + 63) / 64)), dim3(64), 0, st, partial, G, w, out);
   RSRS_HIP(hipGetLastError());
@@ -377,6 +643,7 @@ void sub2d(hipStream_t st, const double* f, int64_t ldf, const double* y, int64_
            int64_t ldz, int64_t n, int64_t w) {
   if (n <= 0 || w <= 0) return;
   const unsigned g = (unsigned)std::min<int64_t>((n * w + 255) / 256, 8192);
+  ProfScope ps(st, "sub2d", n * w, 24.0 * n * w);
   hipLaunchKernelGGL(sub2d_kernel, dim3(g), dim3(256), 0, st, f, ldf, y, ldy, z, ldz, n, w);
 }
 

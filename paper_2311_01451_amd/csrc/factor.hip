@@ -82,11 +82,11 @@ rsrs_status rchol(Uploader& up, hipStream_t st, const std::vector<CholMat>& mats
     g5.push_back(gdesc(L22, nullptr, m.ld, G21, nullptr, m.ld, L21, nullptr, m.ld, rows, w, rows,
                        -1.0, 0.0));
   }
-  RSRS_TRY(gemm(up, st, g1, 0, 1, GM_B_NT_LOW));
-  RSRS_TRY(gemm(up, st, g2, 0, 1, GM_SYRK_L));
-  RSRS_TRY(gemm(up, st, g4, 0, 0, GM_B_NN_LOW));
+  RSRS_TRY(gemm(up, st, g1, 0, 1, GM_B_NT_LOW, GS_64x64, "chol"));
+  RSRS_TRY(gemm(up, st, g2, 0, 1, GM_SYRK_L, GS_64x64, "chol"));
+  RSRS_TRY(gemm(up, st, g4, 0, 0, GM_B_NN_LOW, GS_64x64, "chol"));
   RSRS_TRY(rchol(up, st, mats, h, b, flag));
-  RSRS_TRY(gemm(up, st, g5, 0, 0, GM_A_LOW));
+  RSRS_TRY(gemm(up, st, g5, 0, 0, GM_A_LOW, GS_64x64, "chol"));
   return RSRS_OK;
 }
 
@@ -174,11 +174,14 @@ rsrs_status factor_impl(const rsrs_tree_t* th, rsrs_samples_t* smp, const rsrs_f
         r.n = sch.l_count[b] - r.b;
         r.k = k;
         r.r = r.b - k;
-        r.oT = dsz; dsz += r.r * k;
-        r.oXRR = dsz; dsz += r.r * r.r;
-        r.oXinv = dsz; dsz += r.r * r.r;
-        r.oKU = dsz; dsz += r.r * (k + r.n);
-        r.oKL = dsz; dsz += (k + r.n) * r.r;
+        r.ldT = round_up(k, 2);
+        r.ldR = round_up(r.r, 2);
+        r.ldKU = round_up(k + r.n, 2);
+        r.oT = round_up(dsz, 2); dsz = r.oT + r.r * r.ldT;
+        r.oXRR = round_up(dsz, 2); dsz = r.oXRR + r.r * r.ldR;
+        r.oXinv = round_up(dsz, 2); dsz = r.oXinv + r.r * r.ldR;
+        r.oKU = round_up(dsz, 2); dsz = r.oKU + r.r * r.ldKU;
+        r.oKL = round_up(dsz, 2); dsz = r.oKL + (k + r.n) * r.ldR;
         r.oR = isz; isz += r.r;
         r.oS = isz; isz += k;
         r.oNa = isz; isz += r.n;
@@ -193,8 +196,8 @@ rsrs_status factor_impl(const rsrs_tree_t* th, rsrs_samples_t* smp, const rsrs_f
   }
   F->nt = sch.root_count;
   F->oBt = isz; isz += F->nt;
-  F->oAt = dsz; dsz += F->nt * F->nt;
-  F->oAtinv = dsz; dsz += F->nt * F->nt;
+  F->oAt = round_up(dsz, 2); dsz = F->oAt + F->nt * F->nt;
+  F->oAtinv = round_up(dsz, 2); dsz = F->oAtinv + F->nt * F->nt;
   F->stored_doubles = dsz;
   const int64_t ntp = round_up(F->nt, 16);
   const size_t root_ws = (size_t)(4 * F->nt * ntp + F->nt * round_up(s, 16) + 2 * F->nt * F->nt) * 8 + 8 * 256;
@@ -330,7 +333,7 @@ rsrs_status factor_impl(const rsrs_tree_t* th, rsrs_samples_t* smp, const rsrs_f
                  + 2.0 * (2.0 / 3.0) * dl * dl * dl               // Cholesky + inverse factor
                  + (1.0 + reproject) * 2.0 * (4.0 * db * dl * ds + 2.0 * db * dl * dl);  // projections
       }
-      RSRS_TRY(gemm(up, st, gd, 0, 1, GM_SYRK_L));
+      RSRS_TRY(gemm(up, st, gd, 0, 1, GM_SYRK_L, GS_64x64, "gram"));
       RSRS_TRY(rchol(up, st, cm, 0, lmax, flag));
       // ---- projections (eq. nullYZ) and least-squares coefficients
       for (int pass = 0; pass <= reproject; ++pass) {
@@ -366,10 +369,10 @@ rsrs_status factor_impl(const rsrs_tree_t* th, rsrs_samples_t* smp, const rsrs_f
             if (pass == 1) acc.push_back(Copy2D{Pb, Xb, w.lp, w.lp, b, l, 1.0, 1, 0});
           }
         }
-        RSRS_TRY(gemm(up, st, gp, 0, 1, GM_FULL));
-        RSRS_TRY(gemm(up, st, gw, 0, 1, GM_B_NT_LOW));
-        RSRS_TRY(gemm(up, st, gx, 0, 0, GM_B_NN_LOW));
-        RSRS_TRY(gemm(up, st, gm, 0, 0, GM_FULL));
+        RSRS_TRY(gemm(up, st, gp, 0, 1, GM_FULL, GS_64x64, "proj"));
+        RSRS_TRY(gemm(up, st, gw, 0, 1, GM_B_NT_LOW, GS_64x64, "proj"));
+        RSRS_TRY(gemm(up, st, gx, 0, 0, GM_B_NN_LOW, GS_64x64, "proj"));
+        RSRS_TRY(gemm(up, st, gm, 0, 0, GM_FULL, GS_64x64, "proj"));
         RSRS_TRY(copy2d(up, st, acc));
       }
       // ---- interpolative decomposition of M = M_Y + M_Z
@@ -381,7 +384,7 @@ rsrs_status factor_impl(const rsrs_tree_t* th, rsrs_samples_t* smp, const rsrs_f
         e.M = w.MY; e.MZ = w.MZ; e.ldm = sld; e.ldz = sld;
         e.norms = w.norms; e.sel = w.sel; e.Rc = w.Rc; e.piv = w.piv;
         e.Spos = w.Spos; e.Rpos = w.Rpos; e.T = dS + R.oT;
-        e.b = (int)R.b; e.s = (int)s; e.k = k;
+        e.b = (int)R.b; e.s = (int)s; e.k = k; e.ldt = (int)R.ldT;
         idd.push_back(e);
         flops += 4.0 * R.b * s * k;
       }
@@ -437,17 +440,17 @@ rsrs_status factor_impl(const rsrs_tree_t* th, rsrs_samples_t* smp, const rsrs_f
           double* Xb = side ? w.XZ : w.XY;
           double* XR = side ? w.XRz : w.XRy;
           double* Xp = side ? w.Xpz : w.Xpy;
-          gxr.push_back(gdesc(dS + R.oT, nullptr, k, Xb, w.Spos, w.lp, XR, nullptr, w.lp, r, l, k,
+          gxr.push_back(gdesc(dS + R.oT, nullptr, R.ldT, Xb, w.Spos, w.lp, XR, nullptr, w.lp, r, l, k,
                               -1.0, 1.0, Xb, w.Rpos, w.lp));
-          cf.push_back(ColfixDesc{XR, w.Spos, w.Rpos, dS + R.oT, Xp, w.lp, w.lp, r, k, (int)R.b, l});
+          cf.push_back(ColfixDesc{XR, w.Spos, w.Rpos, dS + R.oT, Xp, w.lp, w.lp, R.ldT, r, k, (int)R.b, l});
         }
-        cx.push_back(Copy2D{w.Xpy, dS + R.oXRR, w.lp, r, r, r, 1.0, 0, 0});
-        gj.push_back(GjeDesc{w.Xpy, w.gje, dS + R.oXinv, w.lp, r, r, 0});
+        cx.push_back(Copy2D{w.Xpy, dS + R.oXRR, w.lp, R.ldR, r, r, 1.0, 0, 0});
+        gj.push_back(GjeDesc{w.Xpy, w.gje, dS + R.oXinv, w.lp, R.ldR, r, 0});
         const double dr = r, dk = k, dn = (double)R.n, ds = (double)s;
         flops += 2.0 * (2.0 * dr * dk * l + 2.0 * dr * dr * dk) + 2.0 * dr * dr * dr +
                  2.0 * 2.0 * dr * dr * (dk + dn) + 4.0 * 2.0 * dr * dk * ds + 4.0 * 2.0 * dr * (dk + dn) * ds;
       }
-      RSRS_TRY(gemm(up, st, gxr, 0, 0, GM_FULL));
+      RSRS_TRY(gemm(up, st, gxr, 0, 0, GM_FULL, GS_64x64, "extract"));
       RSRS_TRY(colfix(up, st, cf));
       RSRS_TRY(copy2d(up, st, cx));
       RSRS_TRY(gje_inverse(up, st, gj, flag));
@@ -456,11 +459,11 @@ rsrs_status factor_impl(const rsrs_tree_t* th, rsrs_samples_t* smp, const rsrs_f
         const BoxRec& R = F->boxes[g.first + q];
         const BoxWs& w = W[q];
         const int r = (int)R.r, kn = (int)(k + R.n);
-        gku.push_back(gdesc(dS + R.oXinv, nullptr, r, w.Xpy + r, nullptr, w.lp, dS + R.oKU, nullptr, kn, r, kn, r));
-        gkl.push_back(gdesc(w.Xpz + r, nullptr, w.lp, dS + R.oXinv, nullptr, r, dS + R.oKL, nullptr, r, kn, r, r));
+        gku.push_back(gdesc(dS + R.oXinv, nullptr, R.ldR, w.Xpy + r, nullptr, w.lp, dS + R.oKU, nullptr, R.ldKU, r, kn, r));
+        gkl.push_back(gdesc(w.Xpz + r, nullptr, w.lp, dS + R.oXinv, nullptr, R.ldR, dS + R.oKL, nullptr, R.ldR, kn, r, r));
       }
-      RSRS_TRY(gemm(up, st, gku, 0, 0, GM_FULL));
-      RSRS_TRY(gemm(up, st, gkl, 1, 0, GM_FULL));
+      RSRS_TRY(gemm(up, st, gku, 0, 0, GM_FULL, GS_64x64, "mult"));
+      RSRS_TRY(gemm(up, st, gkl, 1, 0, GM_FULL, GS_64x64, "mult"));
       // ---- sketch updates: sparsify (E, F) then eliminate (L, U)
       std::vector<GemmDesc> s0, s1, e0, e1;
       for (int64_t q = 0; q < nb; ++q) {
@@ -472,19 +475,20 @@ rsrs_status factor_impl(const rsrs_tree_t* th, rsrs_samples_t* smp, const rsrs_f
         const double* T = dS + R.oT;
         const double* KU = dS + R.oKU;
         const double* KL = dS + R.oKL;
-        s0.push_back(gdesc(T, nullptr, k, Y, gS, sld, Y, gR, sld, r, (int)s, k, -1.0, 1.0));
-        s0.push_back(gdesc(T, nullptr, k, Z, gS, sld, Z, gR, sld, r, (int)s, k, -1.0, 1.0));
-        s1.push_back(gdesc(T, nullptr, k, Om, gR, sld, Om, gS, sld, k, (int)s, r, 1.0, 1.0));
-        s1.push_back(gdesc(T, nullptr, k, Psi, gR, sld, Psi, gS, sld, k, (int)s, r, 1.0, 1.0));
-        e0.push_back(gdesc(KL, nullptr, r, Y, gR, sld, Y, gSN, sld, kn, (int)s, r, -1.0, 1.0));
-        e0.push_back(gdesc(KU, nullptr, kn, Om, gSN, sld, Om, gR, sld, r, (int)s, kn, 1.0, 1.0));
-        e1.push_back(gdesc(KU, nullptr, kn, Z, gR, sld, Z, gSN, sld, kn, (int)s, r, -1.0, 1.0));
-        e1.push_back(gdesc(KL, nullptr, r, Psi, gSN, sld, Psi, gR, sld, r, (int)s, kn, 1.0, 1.0));
+        const int64_t lT = R.ldT, lR = R.ldR, lU = R.ldKU;
+        s0.push_back(gdesc(T, nullptr, lT, Y, gS, sld, Y, gR, sld, r, (int)s, k, -1.0, 1.0));
+        s0.push_back(gdesc(T, nullptr, lT, Z, gS, sld, Z, gR, sld, r, (int)s, k, -1.0, 1.0));
+        s1.push_back(gdesc(T, nullptr, lT, Om, gR, sld, Om, gS, sld, k, (int)s, r, 1.0, 1.0));
+        s1.push_back(gdesc(T, nullptr, lT, Psi, gR, sld, Psi, gS, sld, k, (int)s, r, 1.0, 1.0));
+        e0.push_back(gdesc(KL, nullptr, lR, Y, gR, sld, Y, gSN, sld, kn, (int)s, r, -1.0, 1.0));
+        e0.push_back(gdesc(KU, nullptr, lU, Om, gSN, sld, Om, gR, sld, r, (int)s, kn, 1.0, 1.0));
+        e1.push_back(gdesc(KU, nullptr, lU, Z, gR, sld, Z, gSN, sld, kn, (int)s, r, -1.0, 1.0));
+        e1.push_back(gdesc(KL, nullptr, lR, Psi, gSN, sld, Psi, gR, sld, r, (int)s, kn, 1.0, 1.0));
       }
-      RSRS_TRY(gemm(up, st, s0, 0, 0, GM_FULL));
-      RSRS_TRY(gemm(up, st, s1, 1, 0, GM_FULL));
-      RSRS_TRY(gemm(up, st, e0, 0, 0, GM_FULL));
-      RSRS_TRY(gemm(up, st, e1, 1, 0, GM_FULL));
+      RSRS_TRY(gemm(up, st, s0, 0, 0, GM_FULL, GS_64x64, "sparsify"));
+      RSRS_TRY(gemm(up, st, s1, 1, 0, GM_FULL, GS_64x64, "sparsify"));
+      RSRS_TRY(gemm(up, st, e0, 0, 0, GM_FULL, GS_64x64, "elim"));
+      RSRS_TRY(gemm(up, st, e1, 1, 0, GM_FULL, GS_64x64, "elim"));
     }
     for (int64_t b : lb) remaining[b] = cur[b];
   }

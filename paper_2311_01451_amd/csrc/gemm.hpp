@@ -9,6 +9,7 @@
 //   TB = 0 : B(kk, n) = B[ib(kk) * ldb + n]    ("NN": N contiguous)
 // where ix(j) = ix ? ix[j] : j.  MODE restricts the product to a triangle:
 //   SYRK_L   : only tiles meeting the lower triangle n <= m are computed
+//              (M == N, BM == BN; the grid enumerates just those tiles)
 //   B_NT_LOW : B(kk, n) is zero for kk > n (B = L^T, L lower triangular)
 //   B_NN_LOW : B(kk, n) is zero for kk < n (B = L lower triangular)
 //   A_LOW    : A(m, kk) is zero for kk > m (A lower triangular, TA = 0)
@@ -17,11 +18,16 @@
 //
 // One workgroup (4 waves) computes a BM x BN tile; waves are arranged WM x WN
 // and each holds (BM/WM/16) x (BN/WN/16) 16x16 FP64 accumulator blocks.  The
-// batch index is blockIdx.y; blockIdx.x enumerates tiles of the largest entry
-// and entries with fewer tiles return early.  Tiles are walked so that
-// consecutive workgroups (which land on different XCDs) take tiles far apart
-// while each XCD sweeps a contiguous range of tiles, keeping A-row panels
-// resident in that XCD's L2.
+// K loop is software pipelined: the next BK-slice of A and B is fetched into
+// registers while the current one is multiplied out of LDS, and LDS is double
+// buffered so one barrier per slice suffices.  With VEC = 2 every global
+// access is a 16-byte load along the operand's contiguous dimension (the host
+// selects it only when all leading dimensions are even and all base pointers
+// 16-byte aligned).  The batch index is blockIdx.y;
+// blockIdx.x enumerates tiles of the largest entry and entries with fewer
+// tiles return early.  Consecutive workgroups land on different XCDs, so the
+// tile index is remapped to give each XCD a contiguous range of tiles (rows of
+// tiles sharing an A panel stay in one XCD's L2).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -47,32 +53,41 @@ enum GemmMode { GM_FULL = 0, GM_SYRK_L = 1, GM_B_NT_LOW = 2, GM_B_NN_LOW = 3, GM
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-template <int BM, int BN, int WM, int WN, int TA, int TB, int MODE>
+template <int BM, int BN, int WM, int WN, int TA, int TB, int MODE, int VEC>
 __global__ __launch_bounds__(256) void gemm_f64_kernel(const GemmDesc* __restrict__ descs) {
   constexpr int BK = 16;
   constexpr int PA = BM + 2;
   constexpr int PB = BN + 2;
   constexpr int FM = BM / WM / 16;
   constexpr int FN = BN / WN / 16;
+  constexpr int NA = BM * BK / 256 / VEC;   // VEC-wide A fetches per thread per slice
+  constexpr int NB = BN * BK / 256 / VEC;
   static_assert(WM * WN == 4, "4 waves");
   static_assert(FM >= 1 && FN >= 1, "tile too small");
-  __shared__ double As[BK * PA];
-  __shared__ double Bs[BK * PB];
+  static_assert(NA >= 1 && NB >= 1 && NA * 256 * VEC == BM * BK && NB * 256 * VEC == BN * BK,
+                "tile split");
+  __shared__ double As[2][BK * PA];
+  __shared__ double Bs[2][BK * PB];
 
   const GemmDesc d = descs[blockIdx.y];
   const int tm = (d.M + BM - 1) / BM;
   const int tn = (d.N + BN - 1) / BN;
-  const int ntile = tm * tn;
-  // XCD-aware walk (gridDim.x is a multiple of 8): blockIdx.x % 8 picks the
-  // XCD, which then sweeps a contiguous chunk of tiles.
+  // SYRK_L (M == N, BM == BN) enumerates only the lower-triangle tiles
+  const int ntile = (MODE == GM_SYRK_L) ? tm * (tm + 1) / 2 : tm * tn;
   const int per = gridDim.x >> 3;
   const int t = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
   if (t >= ntile || d.M <= 0 || d.N <= 0) return;
-  const int tile_m = t / tn;
-  const int tile_n = t % tn;
-  const int m0 = tile_m * BM;
-  const int n0 = tile_n * BN;
-  if (MODE == GM_SYRK_L && n0 > m0 + BM - 1) return;
+  int m0, n0;
+  if (MODE == GM_SYRK_L) {
+    int ti = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+    while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+    while (ti * (ti + 1) / 2 > t) --ti;
+    m0 = ti * BM;
+    n0 = (t - ti * (ti + 1) / 2) * BN;
+  } else {
+    m0 = (t / tn) * BM;
+    n0 = (t % tn) * BN;
+  }
 
   int kbeg = 0, kend = d.K;
   if (MODE == GM_B_NT_LOW) kend = min(d.K, n0 + BN);
@@ -87,73 +102,171 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const GemmDesc* __restric
   const int rowq = lane >> 4;   // 0..3
   const int coll = lane & 15;   // 0..15
 
+  // Fetch coordinates (fixed across slices).  Each thread reads VEC
+  // consecutive elements along the contiguous dimension of its operand.
+  int am[NA], ak[NA], bn_[NB], bk[NB];
+  const double* arowp[NA];
+  const double* browp[NB];
+#pragma unroll
+  for (int q = 0; q < NA; ++q) {
+    const int e = (tid + q * 256) * VEC;
+    if (TA == 0) { am[q] = e / BK; ak[q] = e % BK; }
+    else         { ak[q] = e / BM; am[q] = e % BM; }
+    const int gm = min(m0 + am[q], d.M - 1);
+    arowp[q] = (TA == 0) ? d.A + (d.ia ? d.ia[gm] : (int64_t)gm) * d.lda : d.A;
+  }
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int e = (tid + q * 256) * VEC;
+    if (TB == 1) { bn_[q] = e / BK; bk[q] = e % BK; }
+    else         { bk[q] = e / BN; bn_[q] = e % BN; }
+    const int gn = min(n0 + bn_[q], d.N - 1);
+    browp[q] = (TB == 1) ? d.B + (d.ib ? d.ib[gn] : (int64_t)gn) * d.ldb : d.B;
+  }
+
+  // Row indices of the K-dimension gathers (TA = 1, TB = 0) are loaded one
+  // slice ahead, so the dependent index load never stalls a data load.
+  int64_t anext[NA], bnext[NB];
+#pragma unroll
+  for (int q = 0; q < NA; ++q) {
+    const int gk = kbeg + ak[q];
+    anext[q] = (TA == 1 && gk < kend) ? (d.ia ? d.ia[gk] : (int64_t)gk) : 0;
+  }
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int gk = kbeg + bk[q];
+    bnext[q] = (TB == 0 && gk < kend) ? (d.ib ? d.ib[gk] : (int64_t)gk) : 0;
+  }
+
+  double ra[NA][VEC], rb[NB][VEC];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int gm = m0 + am[q], gk = k0 + ak[q];
+      if (TA == 0) {
+        // VEC consecutive k of row gm
+        bool full = gm < d.M && gk + VEC - 1 < kend;
+        if (MODE == GM_A_LOW) full = full && gk + VEC - 1 <= gm;
+        if (VEC == 2 && full) {
+          const double2 v = *reinterpret_cast<const double2*>(arowp[q] + gk);
+          ra[q][0] = v.x;
+          ra[q][VEC - 1] = v.y;
+        } else {
+#pragma unroll
+          for (int u = 0; u < VEC; ++u) {
+            bool ok = gm < d.M && gk + u < kend;
+            if (MODE == GM_A_LOW) ok = ok && gk + u <= gm;
+            ra[q][u] = ok ? arowp[q][gk + u] : 0.0;
+          }
+        }
+      } else {
+        // VEC consecutive m of row gk (A stored K x M)
+        const bool rowok = gk < kend;
+        const double* rp = d.A + anext[q] * d.lda;
+        const int gk2 = gk + BK;
+        anext[q] = gk2 < kend ? (d.ia ? d.ia[gk2] : (int64_t)gk2) : 0;
+        if (VEC == 2 && rowok && gm + VEC - 1 < d.M) {
+          const double2 v = *reinterpret_cast<const double2*>(rp + gm);
+          ra[q][0] = v.x;
+          ra[q][VEC - 1] = v.y;
+        } else {
+#pragma unroll
+          for (int u = 0; u < VEC; ++u) ra[q][u] = (rowok && gm + u < d.M) ? rp[gm + u] : 0.0;
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int gn = n0 + bn_[q], gk = k0 + bk[q];
+      if (TB == 1) {
+        // VEC consecutive k of row gn
+        bool full = gn < d.N && gk + VEC - 1 < kend;
+        if (MODE == GM_B_NT_LOW) full = full && gk + VEC - 1 <= gn;
+        if (VEC == 2 && full) {
+          const double2 v = *reinterpret_cast<const double2*>(browp[q] + gk);
+          rb[q][0] = v.x;
+          rb[q][VEC - 1] = v.y;
+        } else {
+#pragma unroll
+          for (int u = 0; u < VEC; ++u) {
+            bool ok = gn < d.N && gk + u < kend;
+            if (MODE == GM_B_NT_LOW) ok = ok && gk + u <= gn;
+            rb[q][u] = ok ? browp[q][gk + u] : 0.0;
+          }
+        }
+      } else {
+        // VEC consecutive n of row gk
+        const bool rowok = gk < kend;
+        const double* rp = d.B + bnext[q] * d.ldb;
+        const int gk2 = gk + BK;
+        bnext[q] = gk2 < kend ? (d.ib ? d.ib[gk2] : (int64_t)gk2) : 0;
+        bool full = rowok && gn + VEC - 1 < d.N;
+        if (MODE == GM_B_NN_LOW) full = full && gk >= gn + VEC - 1;
+        if (VEC == 2 && full) {
+          const double2 v = *reinterpret_cast<const double2*>(rp + gn);
+          rb[q][0] = v.x;
+          rb[q][VEC - 1] = v.y;
+        } else {
+#pragma unroll
+          for (int u = 0; u < VEC; ++u) {
+            bool ok = rowok && gn + u < d.N;
+            if (MODE == GM_B_NN_LOW) ok = ok && gk >= gn + u;
+            rb[q][u] = ok ? rp[gn + u] : 0.0;
+          }
+        }
+      }
+    }
+  };
+  auto stash = [&](int b) {
+#pragma unroll
+    for (int q = 0; q < NA; ++q)
+#pragma unroll
+      for (int u = 0; u < VEC; ++u) {
+        if (TA == 0) As[b][(ak[q] + u) * PA + am[q]] = ra[q][u];
+        else         As[b][ak[q] * PA + am[q] + u] = ra[q][u];
+      }
+#pragma unroll
+    for (int q = 0; q < NB; ++q)
+#pragma unroll
+      for (int u = 0; u < VEC; ++u) {
+        if (TB == 1) Bs[b][(bk[q] + u) * PB + bn_[q]] = rb[q][u];
+        else         Bs[b][bk[q] * PB + bn_[q] + u] = rb[q][u];
+      }
+  };
+
   v4d acc[FM][FN];
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
 
-  for (int k0 = kbeg; k0 < kend; k0 += BK) {
-    // ---- global -> LDS, A tile (BM x BK) stored As[kk][m]
-#pragma unroll
-    for (int e = tid; e < BM * BK; e += 256) {
-      int m, kk;
-      if (TA == 0) { m = e / BK; kk = e % BK; }
-      else         { kk = e / BM; m = e % BM; }
-      const int gm = m0 + m, gk = k0 + kk;
-      double v = 0.0;
-      bool ok = gm < d.M && gk < kend;
-      if (MODE == GM_A_LOW) ok = ok && gk <= gm;
-      if (ok) {
-        if (TA == 0) {
-          const int64_t r = d.ia ? d.ia[gm] : gm;
-          v = d.A[r * d.lda + gk];
-        } else {
-          const int64_t r = d.ia ? d.ia[gk] : gk;
-          v = d.A[r * d.lda + gm];
-        }
-      }
-      As[kk * PA + m] = v;
-    }
-    // ---- B tile (BK x BN) stored Bs[kk][n]
-#pragma unroll
-    for (int e = tid; e < BN * BK; e += 256) {
-      int n, kk;
-      if (TB == 1) { n = e / BK; kk = e % BK; }
-      else         { kk = e / BN; n = e % BN; }
-      const int gn = n0 + n, gk = k0 + kk;
-      double v = 0.0;
-      bool ok = gn < d.N && gk < kend;
-      if (MODE == GM_B_NT_LOW) ok = ok && gk <= gn;
-      if (MODE == GM_B_NN_LOW) ok = ok && gk >= gn;
-      if (ok) {
-        if (TB == 1) {
-          const int64_t r = d.ib ? d.ib[gn] : gn;
-          v = d.B[r * d.ldb + gk];
-        } else {
-          const int64_t r = d.ib ? d.ib[gk] : gk;
-          v = d.B[r * d.ldb + gn];
-        }
-      }
-      Bs[kk * PB + n] = v;
-    }
+  if (kbeg < kend) {
+    fetch(kbeg);
+    stash(0);
     __syncthreads();
+  }
+  int buf = 0;
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    const bool more = k0 + BK < kend;
+    if (more) fetch(k0 + BK);
+    const double* as = As[buf];
+    const double* bs = Bs[buf];
 #pragma unroll
     for (int kq = 0; kq < BK; kq += 4) {
       double a[FM], b[FN];
 #pragma unroll
-      for (int i = 0; i < FM; ++i)
-        a[i] = As[(kq + rowq) * PA + wm * (BM / WM) + i * 16 + coll];
+      for (int i = 0; i < FM; ++i) a[i] = as[(kq + rowq) * PA + wm * (BM / WM) + i * 16 + coll];
 #pragma unroll
-      for (int j = 0; j < FN; ++j)
-        b[j] = Bs[(kq + rowq) * PB + wn * (BN / WN) + j * 16 + coll];
+      for (int j = 0; j < FN; ++j) b[j] = bs[(kq + rowq) * PB + wn * (BN / WN) + j * 16 + coll];
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
+    if (more) stash(buf ^ 1);
     __syncthreads();
+    buf ^= 1;
   }
 
   // ---- epilogue: register v of lane l holds D[4*v + l/16][l % 16] of each
@@ -161,21 +274,21 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const GemmDesc* __restric
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < FN; ++j)
+    for (int v = 0; v < 4; ++v) {
+      const int gm = m0 + wm * (BM / WM) + i * 16 + v * 4 + rowq;
+      if (gm >= d.M) continue;
+      const int64_t ro = d.ic ? d.ic[gm] : gm;
+      const int64_t rc = d.icin ? d.icin[gm] : gm;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int gm = m0 + wm * (BM / WM) + i * 16 + v * 4 + rowq;
+      for (int j = 0; j < FN; ++j) {
         const int gn = n0 + wn * (BN / WN) + j * 16 + coll;
-        if (gm < d.M && gn < d.N) {
+        if (gn < d.N) {
           double out = d.alpha * acc[i][j][v];
-          if (d.beta != 0.0) {
-            const int64_t rc = d.icin ? d.icin[gm] : gm;
-            out += d.beta * d.Cin[rc * d.ldcin + gn];
-          }
-          const int64_t ro = d.ic ? d.ic[gm] : gm;
+          if (d.beta != 0.0) out += d.beta * d.Cin[rc * d.ldcin + gn];
           d.C[ro * d.ldc + gn] = out;
         }
       }
+    }
 }
 
 }  // namespace rsrs

@@ -20,6 +20,7 @@
 #include <cmath>
 
 #include "kernels.hpp"
+#include "profile.hpp"
 
 namespace rsrs {
 
@@ -105,36 +106,62 @@ __global__ __launch_bounds__(64) void id_step_kernel(const IdDesc* __restrict__ 
 }
 
 // S, R sorted; T = (R11^{-1} R12)^T written with columns in sorted-S order.
+// Positions come from a block-wide prefix count of the selected rows; R11
+// (k <= 64) is staged in LDS for the back substitutions, one thread per row of R.
 __global__ __launch_bounds__(256) void id_finalize_kernel(const IdDesc* __restrict__ e) {
   const IdDesc d = e[blockIdx.x];
   const int b = d.b, k = d.k, r = b - k;
+  constexpr int KL = 64;
+  __shared__ int pre[4352 + 1];       // pre[x] = number of selected rows < x
+  __shared__ int cnt[256];
   __shared__ int rank_of_step[256];   // rank of pivot p_t inside sorted S
-  __shared__ int rrow[4096];          // sorted R rows
+  __shared__ double R11[KL * KL];
   const int tid = threadIdx.x;
+  const int seg = (b + 255) / 256;
+  const int lo = min(b, tid * seg), hi = min(b, lo + seg);
+  int c = 0;
+  for (int x = lo; x < hi; ++x) c += d.sel[x] < k ? 1 : 0;
+  cnt[tid] = c;
+  __syncthreads();
   if (tid == 0) {
-    int ns = 0, nr = 0;
-    for (int x = 0; x < b; ++x) {
-      if (d.sel[x] < k) d.Spos[ns++] = x;
-      else { d.Rpos[nr] = x; rrow[nr] = x; ++nr; }
-    }
-    for (int t = 0; t < k; ++t) {
-      const int p = d.piv[t];
-      int rk = 0;
-      for (int x = 0; x < p; ++x) rk += d.sel[x] < k ? 1 : 0;
-      rank_of_step[t] = rk;
+    int run = 0;
+    for (int q = 0; q < 256; ++q) {
+      const int v = cnt[q];
+      cnt[q] = run;
+      run += v;
     }
   }
   __syncthreads();
+  {
+    int run = cnt[tid];
+    for (int x = lo; x < hi; ++x) {
+      pre[x] = run;
+      if (d.sel[x] < k) d.Spos[run] = x;
+      else d.Rpos[x - run] = x;
+      run += d.sel[x] < k ? 1 : 0;
+    }
+  }
+  __syncthreads();
+  for (int t = tid; t < k; t += 256) rank_of_step[t] = pre[d.piv[t]];
+  const bool lds = k <= KL;
+  if (lds)
+    for (int idx = tid; idx < k * k; idx += 256) {
+      const int t = idx / k, u = idx % k;
+      R11[idx] = t <= u ? d.Rc[(int64_t)d.piv[u] * k + t] : 0.0;
+    }
+  __syncthreads();
   for (int q = tid; q < r; q += 256) {
-    const int i = rrow[q];
-    const double* c = d.Rc + (int64_t)i * k;
-    double* Tq = d.T + (int64_t)q * k;
+    const int i = (int)d.Rpos[q];
+    const double* cr = d.Rc + (int64_t)i * k;
+    double* Tq = d.T + (int64_t)q * d.ldt;
     // back substitution R11 x = c, R11[t][u] = Rc[p_u][t] (t <= u)
     for (int t = k - 1; t >= 0; --t) {
-      double acc = c[t];
-      for (int u = t + 1; u < k; ++u)
-        acc -= d.Rc[(int64_t)d.piv[u] * k + t] * Tq[rank_of_step[u]];
-      const double diag = d.Rc[(int64_t)d.piv[t] * k + t];
+      double acc = cr[t];
+      for (int u = t + 1; u < k; ++u) {
+        const double rtu = lds ? R11[t * k + u] : d.Rc[(int64_t)d.piv[u] * k + t];
+        acc -= rtu * Tq[rank_of_step[u]];
+      }
+      const double diag = lds ? R11[t * k + t] : d.Rc[(int64_t)d.piv[t] * k + t];
       Tq[rank_of_step[t]] = diag != 0.0 ? acc / diag : 0.0;
     }
   }
@@ -144,8 +171,8 @@ rsrs_status id_run(Uploader& up, hipStream_t st, const std::vector<IdDesc>& e) {
   if (e.empty()) return RSRS_OK;
   int bmax = 0, kmax = 0;
   for (const auto& x : e) {
-    if (x.k > 256 || x.b - x.k > 4096 || x.k >= x.b) {
-      set_error("ID sizes out of range (need k < b, k <= 256, b - k <= 4096)");
+    if (x.k > 256 || x.b > 4352 || x.k >= x.b) {
+      set_error("ID sizes out of range (need k < b <= 4352, k <= 256)");
       return RSRS_E_UNSUPPORTED;
     }
     bmax = std::max(bmax, x.b);
@@ -154,10 +181,23 @@ rsrs_status id_run(Uploader& up, hipStream_t st, const std::vector<IdDesc>& e) {
   IdDesc* de = nullptr;
   RSRS_TRY(up.put_vec(e, &de));
   const unsigned nb = (unsigned)e.size();
-  hipLaunchKernelGGL(id_init_kernel, dim3((unsigned)bmax, nb), dim3(64), 0, st, de);
-  for (int j = 0; j < kmax; ++j)
+  double fstep = 0.0, bstep = 0.0;
+  for (const auto& x : e) {
+    fstep += 4.0 * x.b * x.s;
+    bstep += 16.0 * x.b * x.s;
+  }
+  {
+    ProfScope ps(st, "id_init", 0.0, bstep);
+    hipLaunchKernelGGL(id_init_kernel, dim3((unsigned)bmax, nb), dim3(64), 0, st, de);
+  }
+  for (int j = 0; j < kmax; ++j) {
+    ProfScope ps(st, "id_step", fstep, bstep);
     hipLaunchKernelGGL(id_step_kernel, dim3((unsigned)bmax, nb), dim3(64), 0, st, de, j);
-  hipLaunchKernelGGL(id_finalize_kernel, dim3(nb), dim3(256), 0, st, de);
+  }
+  {
+    ProfScope ps(st, "id_finalize");
+    hipLaunchKernelGGL(id_finalize_kernel, dim3(nb), dim3(256), 0, st, de);
+  }
   RSRS_HIP(hipGetLastError());
   return RSRS_OK;
 }
@@ -180,7 +220,7 @@ __global__ __launch_bounds__(256) void colfix_kernel(const ColfixDesc* __restric
     double v;
     if (c < d.r) {
       v = xr[d.Rpos[c]];
-      const double* tc = d.T + (int64_t)c * d.k;
+      const double* tc = d.T + (int64_t)c * d.ldt;
       for (int t = 0; t < d.k; ++t) v -= xs[t] * tc[t];
     } else if (c < d.r + d.k) {
       v = xs[c - d.r];
@@ -204,6 +244,7 @@ rsrs_status colfix(Uploader& up, hipStream_t st, const std::vector<ColfixDesc>& 
   if (rmax == 0) return RSRS_OK;
   ColfixDesc* de = nullptr;
   RSRS_TRY(up.put_vec(e, &de));
+  ProfScope ps(st, "colfix");
   hipLaunchKernelGGL(colfix_kernel, dim3((unsigned)rmax, (unsigned)e.size()), dim3(256), 0, st, de);
   RSRS_HIP(hipGetLastError());
   return RSRS_OK;

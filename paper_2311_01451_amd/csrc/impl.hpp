@@ -40,7 +40,8 @@ struct BoxRec {
   int64_t box = 0;
   int level = 0, colour = 0;
   int64_t b = 0, n = 0, r = 0, k = 0;
-  int64_t oT = 0, oXRR = 0, oXinv = 0, oKU = 0, oKL = 0;   // doubles
+  int64_t oT = 0, oXRR = 0, oXinv = 0, oKU = 0, oKL = 0;   // doubles, 16-byte aligned
+  int64_t ldT = 0, ldR = 0, ldKU = 0;   // even leading dims: T, X_RR / X_RR^{-1} / K_L, K_U
   int64_t oR = 0, oS = 0, oSN = 0, oBa = 0, oNa = 0;       // int64 tree positions
 };
 

@@ -32,8 +32,9 @@ struct Uploader {
 
 // ---- GEMM (gemm.hpp) -------------------------------------------------------
 enum GemmShape { GS_64x64 = 0, GS_64x16 = 1 };
+// `site` (optional) is appended to the measurement tag ("gemm_<form>:<site>").
 rsrs_status gemm(Uploader& up, hipStream_t st, const std::vector<GemmDesc>& descs, int ta,
-                 int tb, int mode, GemmShape shape = GS_64x64);
+                 int tb, int mode, GemmShape shape = GS_64x64, const char* site = nullptr);
 inline GemmDesc gdesc(const double* A, const int64_t* ia, int64_t lda, const double* B,
                       const int64_t* ib, int64_t ldb, double* C, const int64_t* ic, int64_t ldc,
                       int M, int N, int K, double alpha = 1.0, double beta = 0.0,
@@ -91,8 +92,8 @@ struct IdDesc {
   int32_t* piv;       // k
   int64_t* Spos;      // k, sorted
   int64_t* Rpos;      // b-k, sorted
-  double* T;          // (b-k) x k, row-major, ld = k
-  int b, s, k, pad_;
+  double* T;          // (b-k) x k, row-major, leading dimension ldt
+  int b, s, k, ldt;
 };
 rsrs_status id_run(Uploader& up, hipStream_t st, const std::vector<IdDesc>& e);
 
@@ -102,7 +103,7 @@ struct ColfixDesc {
   const int64_t* Rpos;   // r
   const double* T;       // r x k
   double* Xp;            // r x l, columns ordered [R, S, N]
-  int64_t ldx, ldp;
+  int64_t ldx, ldp, ldt;
   int r, k, b, l;
 };
 // Columns of the extracted block: right-multiply by G^{-1} (columns R -= columns S T^T)

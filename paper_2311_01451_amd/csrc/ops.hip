@@ -16,6 +16,7 @@
 #include <cmath>
 
 #include "kernels.hpp"
+#include "profile.hpp"
 
 namespace rsrs {
 
@@ -59,6 +60,7 @@ void philox_normal(hipStream_t st, double* out, int64_t nrows, int64_t ncols, in
                    uint64_t seed, uint32_t word) {
   if (nrows <= 0 || ncols <= 0) return;
   const unsigned g = (unsigned)std::min<int64_t>((nrows * ncols + 255) / 256, 16384);
+  ProfScope ps(st, "philox_normal", 0.0, 8.0 * nrows * ncols);
   hipLaunchKernelGGL(philox_normal_kernel, dim3(g), dim3(256), 0, st, out, nrows, ncols, ld,
                      (uint32_t)seed, (uint32_t)(seed >> 32), word);
 }
@@ -128,6 +130,7 @@ rsrs_status poisson_matvec(hipStream_t st, const Poisson7Op& op, int64_t ncols, 
                            int64_t ldx, double* Y, int64_t ldy) {
   const int64_t N = (int64_t)op.n * op.n * op.n;
   const unsigned g = (unsigned)std::min<int64_t>((N * ncols + 255) / 256, 65536);
+  ProfScope ps(st, "poisson7", 13.0 * N * ncols, 8.0 * (9.0 * N * ncols));
   hipLaunchKernelGGL(poisson_kernel, dim3(g), dim3(256), 0, st, op.coef.as<double>(), op.n, ncols,
                      X, ldx, Y, ldy);
   RSRS_HIP(hipGetLastError());

@@ -63,24 +63,25 @@ rsrs_status apply_factor(const rsrs_factor_t* F, int op, int transpose, int64_t 
       const double* T = dS + R.oT;
       const double* KU = dS + R.oKU;
       const double* KL = dS + R.oKL;
+      const int64_t lT = R.ldT, lR = R.ldR, lU = R.ldKU;
       if (op == OP_SOLVE && !transpose) {        // E then L
-        a0.push_back(gdesc(T, nullptr, k, x, gS, w, x, gR, w, r, W, k, -1.0, 1.0));
-        b0.push_back(gdesc(KL, nullptr, r, x, gR, w, x, gSN, w, kn, W, r, -1.0, 1.0));
+        a0.push_back(gdesc(T, nullptr, lT, x, gS, w, x, gR, w, r, W, k, -1.0, 1.0));
+        b0.push_back(gdesc(KL, nullptr, lR, x, gR, w, x, gSN, w, kn, W, r, -1.0, 1.0));
       } else if (op == OP_SOLVE) {              // F^T then U^T
-        a0.push_back(gdesc(T, nullptr, k, x, gS, w, x, gR, w, r, W, k, -1.0, 1.0));
-        b1.push_back(gdesc(KU, nullptr, kn, x, gR, w, x, gSN, w, kn, W, r, -1.0, 1.0));
+        a0.push_back(gdesc(T, nullptr, lT, x, gS, w, x, gR, w, r, W, k, -1.0, 1.0));
+        b1.push_back(gdesc(KU, nullptr, lU, x, gR, w, x, gSN, w, kn, W, r, -1.0, 1.0));
       } else if (!transpose) {                   // F^{-1} then U^{-1}
-        a1.push_back(gdesc(T, nullptr, k, x, gR, w, x, gS, w, k, W, r, 1.0, 1.0));
-        b0.push_back(gdesc(KU, nullptr, kn, x, gSN, w, x, gR, w, r, W, kn, 1.0, 1.0));
+        a1.push_back(gdesc(T, nullptr, lT, x, gR, w, x, gS, w, k, W, r, 1.0, 1.0));
+        b0.push_back(gdesc(KU, nullptr, lU, x, gSN, w, x, gR, w, r, W, kn, 1.0, 1.0));
       } else {                                   // E^{-T} then L^{-T}
-        a1.push_back(gdesc(T, nullptr, k, x, gR, w, x, gS, w, k, W, r, 1.0, 1.0));
-        b1.push_back(gdesc(KL, nullptr, r, x, gSN, w, x, gR, w, r, W, kn, 1.0, 1.0));
+        a1.push_back(gdesc(T, nullptr, lT, x, gR, w, x, gS, w, k, W, r, 1.0, 1.0));
+        b1.push_back(gdesc(KL, nullptr, lR, x, gSN, w, x, gR, w, r, W, kn, 1.0, 1.0));
       }
     }
-    RSRS_TRY(gemm(up, st, a0, 0, 0, GM_FULL, shp));
-    RSRS_TRY(gemm(up, st, a1, 1, 0, GM_FULL, shp));
-    RSRS_TRY(gemm(up, st, b0, 0, 0, GM_FULL, shp));
-    RSRS_TRY(gemm(up, st, b1, 1, 0, GM_FULL, shp));
+    RSRS_TRY(gemm(up, st, a0, 0, 0, GM_FULL, shp, "solve"));
+    RSRS_TRY(gemm(up, st, a1, 1, 0, GM_FULL, shp, "solve"));
+    RSRS_TRY(gemm(up, st, b0, 0, 0, GM_FULL, shp, "solve"));
+    RSRS_TRY(gemm(up, st, b1, 1, 0, GM_FULL, shp, "solve"));
   }
   // block-diagonal middle factor D (or D^{-1}), every R block and the root
   {
@@ -90,13 +91,13 @@ rsrs_status apply_factor(const rsrs_factor_t* F, int op, int transpose, int64_t 
       const int r = (int)R.r;
       const double* D = dS + (op == OP_SOLVE ? R.oXinv : R.oXRR);
       const int64_t* gR = iS + R.oR;
-      dd.push_back(gdesc(D, nullptr, r, x, gR, w, u, gR, w, r, W, r));
+      dd.push_back(gdesc(D, nullptr, R.ldR, x, gR, w, u, gR, w, r, W, r));
     }
     const int nt = (int)F->nt;
     const int64_t* gB = iS + F->oBt;
     dd.push_back(gdesc(dS + (op == OP_SOLVE ? F->oAtinv : F->oAt), nullptr, nt, x, gB, w, u, gB, w,
                        nt, W, nt));
-    RSRS_TRY(gemm(up, st, dd, ta, 0, GM_FULL, shp));
+    RSRS_TRY(gemm(up, st, dd, ta, 0, GM_FULL, shp, "solve"));
   }
   // downward sweep, boxes in reverse factor order
   for (size_t gi = F->groups.size(); gi-- > 0;) {
@@ -111,24 +112,25 @@ rsrs_status apply_factor(const rsrs_factor_t* F, int op, int transpose, int64_t 
       const double* T = dS + R.oT;
       const double* KU = dS + R.oKU;
       const double* KL = dS + R.oKL;
+      const int64_t lT = R.ldT, lR = R.ldR, lU = R.ldKU;
       if (op == OP_SOLVE && !transpose) {        // U then F
-        a0.push_back(gdesc(KU, nullptr, kn, u, gSN, w, u, gR, w, r, W, kn, -1.0, 1.0));
-        b1.push_back(gdesc(T, nullptr, k, u, gR, w, u, gS, w, k, W, r, -1.0, 1.0));
+        a0.push_back(gdesc(KU, nullptr, lU, u, gSN, w, u, gR, w, r, W, kn, -1.0, 1.0));
+        b1.push_back(gdesc(T, nullptr, lT, u, gR, w, u, gS, w, k, W, r, -1.0, 1.0));
       } else if (op == OP_SOLVE) {              // L^T then E^T
-        a1.push_back(gdesc(KL, nullptr, r, u, gSN, w, u, gR, w, r, W, kn, -1.0, 1.0));
-        b1.push_back(gdesc(T, nullptr, k, u, gR, w, u, gS, w, k, W, r, -1.0, 1.0));
+        a1.push_back(gdesc(KL, nullptr, lR, u, gSN, w, u, gR, w, r, W, kn, -1.0, 1.0));
+        b1.push_back(gdesc(T, nullptr, lT, u, gR, w, u, gS, w, k, W, r, -1.0, 1.0));
       } else if (!transpose) {                   // L^{-1} then E^{-1}
-        a0.push_back(gdesc(KL, nullptr, r, u, gR, w, u, gSN, w, kn, W, r, 1.0, 1.0));
-        b0.push_back(gdesc(T, nullptr, k, u, gS, w, u, gR, w, r, W, k, 1.0, 1.0));
+        a0.push_back(gdesc(KL, nullptr, lR, u, gR, w, u, gSN, w, kn, W, r, 1.0, 1.0));
+        b0.push_back(gdesc(T, nullptr, lT, u, gS, w, u, gR, w, r, W, k, 1.0, 1.0));
       } else {                                   // U^{-T} then F^{-T}
-        a1.push_back(gdesc(KU, nullptr, kn, u, gR, w, u, gSN, w, kn, W, r, 1.0, 1.0));
-        b0.push_back(gdesc(T, nullptr, k, u, gS, w, u, gR, w, r, W, k, 1.0, 1.0));
+        a1.push_back(gdesc(KU, nullptr, lU, u, gR, w, u, gSN, w, kn, W, r, 1.0, 1.0));
+        b0.push_back(gdesc(T, nullptr, lT, u, gS, w, u, gR, w, r, W, k, 1.0, 1.0));
       }
     }
-    RSRS_TRY(gemm(up, st, a0, 0, 0, GM_FULL, shp));
-    RSRS_TRY(gemm(up, st, a1, 1, 0, GM_FULL, shp));
-    RSRS_TRY(gemm(up, st, b0, 0, 0, GM_FULL, shp));
-    RSRS_TRY(gemm(up, st, b1, 1, 0, GM_FULL, shp));
+    RSRS_TRY(gemm(up, st, a0, 0, 0, GM_FULL, shp, "solve"));
+    RSRS_TRY(gemm(up, st, a1, 1, 0, GM_FULL, shp, "solve"));
+    RSRS_TRY(gemm(up, st, b0, 0, 0, GM_FULL, shp, "solve"));
+    RSRS_TRY(gemm(up, st, b1, 1, 0, GM_FULL, shp, "solve"));
   }
   scatter_rows(st, Uout, ldu, u, w, perm, F->n, w);
   RSRS_HIP(hipGetLastError());

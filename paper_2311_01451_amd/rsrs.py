@@ -61,6 +61,11 @@ class FactorInfo(C.Structure):
                 ("factor_ms", C.c_double)]
 
 
+class ProfileEntry(C.Structure):
+    _fields_ = [("tag", C.c_char * 48), ("launches", C.c_int64), ("ms", C.c_double),
+                ("flops", C.c_double), ("bytes", C.c_double)]
+
+
 MATVEC_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int, C.c_int64, C.c_void_p, C.c_int64,
                         C.c_void_p, C.c_int64, C.c_void_p)
 
@@ -72,6 +77,7 @@ EXPORTS = [
     "rsrs_sample", "rsrs_samples_destroy", "rsrs_gaussian", "rsrs_factor", "rsrs_factor_destroy",
     "rsrs_factor_get_info", "rsrs_factor_box_sizes", "rsrs_factor_box_copy",
     "rsrs_factor_root_copy", "rsrs_solve", "rsrs_apply", "rsrs_solve_refine",
+    "rsrs_profile_enable", "rsrs_profile_reset", "rsrs_profile_read",
 ]
 
 
@@ -116,6 +122,9 @@ def lib():
         "rsrs_apply": (i32, [vp, i32, i64, vp, i64, vp, i64, vp]),
         "rsrs_solve_refine": (i32, [vp, vp, vp, i64, vp, i64, vp, i64, dbl, i32, P(dbl),
                                     P(i32), vp]),
+        "rsrs_profile_enable": (None, [i32]),
+        "rsrs_profile_reset": (None, []),
+        "rsrs_profile_read": (i32, [P(ProfileEntry), i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -154,8 +163,12 @@ class Tree:
         self.n = n
 
     def __del__(self):
-        if getattr(self, "_h", None):
-            lib().rsrs_tree_destroy(self._h)
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            try:
+                _lib.rsrs_tree_destroy(h)
+            except Exception:
+                pass
             self._h = None
 
     @property
@@ -232,8 +245,12 @@ class Operator:
         self._keep = keep
 
     def __del__(self):
-        if getattr(self, "_h", None):
-            lib().rsrs_op_destroy(self._h)
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            try:
+                _lib.rsrs_op_destroy(h)
+            except Exception:
+                pass
             self._h = None
 
     @property
@@ -285,8 +302,12 @@ class Samples:
         self.s = s
 
     def __del__(self):
-        if getattr(self, "_h", None):
-            lib().rsrs_samples_destroy(self._h)
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            try:
+                _lib.rsrs_samples_destroy(h)
+            except Exception:
+                pass
             self._h = None
 
     @property
@@ -332,8 +353,12 @@ class Factor:
         self._keep = keep
 
     def __del__(self):
-        if getattr(self, "_h", None):
-            lib().rsrs_factor_destroy(self._h)
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            try:
+                _lib.rsrs_factor_destroy(h)
+            except Exception:
+                pass
             self._h = None
 
     @property
@@ -418,3 +443,24 @@ def rsrs_solve_refine(f: Factor, op: Operator, F, tol: float = 1e-10, maxit: int
     _check(lib().rsrs_solve_refine(f.handle, Operator.fn_ptr(), op.handle, F.shape[1], pf, ldf, pu, ldu,
                                    tol, maxit, C.byref(rel), C.byref(it), _stream(stream)))
     return out, rel.value, it.value
+
+
+# --------------------------------------------------------------------------- measurement
+def rsrs_profile_enable(on: bool = True):
+    lib().rsrs_profile_enable(int(on))
+
+
+def rsrs_profile_reset():
+    lib().rsrs_profile_reset()
+
+
+def rsrs_profile_read() -> dict:
+    """{tag: dict(launches, ms, flops, bytes)} for launches since the last reset."""
+    L = lib()
+    n = L.rsrs_profile_read(None, 0)
+    if n < 0:
+        raise RSRSError(7, "rsrs_profile_read failed")
+    arr = (ProfileEntry * max(n, 1))()
+    n = L.rsrs_profile_read(arr, n)
+    return {arr[i].tag.decode(): dict(launches=arr[i].launches, ms=arr[i].ms, flops=arr[i].flops,
+                                      bytes=arr[i].bytes) for i in range(n)}
