@@ -103,7 +103,7 @@ static rsrs_status launch_gemm(Uploader& up, hipStream_t st, const std::vector<G
   if (tiles == 0) return RSRS_OK;
   double pf = 0.0, pb = 0.0;
   if (prof_on()) gemm_work(descs, MODE, &pf, &pb);
-  const bool v2 = (BN * 16 / 256 >= 2) && vec2_ok(descs);
+  const bool v2 = (BN * 16 / (64 * WM * WN) >= 2) && vec2_ok(descs);
   for (size_t b0 = 0; b0 < descs.size(); b0 += 65535) {
     const size_t nb = std::min<size_t>(65535, descs.size() - b0);
     std::vector<GemmDesc> part(descs.begin() + b0, descs.begin() + b0 + nb);
@@ -111,14 +111,14 @@ static rsrs_status launch_gemm(Uploader& up, hipStream_t st, const std::vector<G
     RSRS_TRY(up.put_vec(part, &dd));
     dim3 grid((unsigned)round_up(tiles, 8), (unsigned)nb);
     ProfScope ps(st, gemm_tag(TA, TB, MODE, BM, BN), b0 == 0 ? pf : 0.0, b0 == 0 ? pb : 0.0);
-    if constexpr (BN * 16 / 256 >= 2) {
+    if constexpr (BN * 16 / (64 * WM * WN) >= 2 && BM * 16 / (64 * WM * WN) >= 2) {
       if (v2) {
-        hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WM, WN, TA, TB, MODE, 2>), grid, dim3(256), 0, st, dd);
+        hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WM, WN, TA, TB, MODE, 2>), grid, dim3(64 * WM * WN), 0, st, dd);
       } else {
-        hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WM, WN, TA, TB, MODE, 1>), grid, dim3(256), 0, st, dd);
+        hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WM, WN, TA, TB, MODE, 1>), grid, dim3(64 * WM * WN), 0, st, dd);
       }
     } else {
-      hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WM, WN, TA, TB, MODE, 1>), grid, dim3(256), 0, st, dd);
+      hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WM, WN, TA, TB, MODE, 1>), grid, dim3(64 * WM * WN), 0, st, dd);
     }
     RSRS_HIP(hipGetLastError());
   }
@@ -144,9 +144,11 @@ static rsrs_status gemm_shape(Uploader& up, hipStream_t st, const std::vector<Ge
   return RSRS_E_UNSUPPORTED;
 }
 
-// Tile choice, measured on MI355X: 64 x 64 tiles (2 x 2 MFMA blocks per wave,
-// 3-4 waves per SIMD) beat 128 x 128 tiles (1 wave per SIMD) on every shape
-// of this method; narrow right-hand sides use 64 x 16.
+// Tile choice, measured on MI355X: 128 x 128 tiles on 8 waves (each wave
+// 64 x 32, 4 waves per SIMD) reach 50+ TFLOP/s on the large products; they
+// are used whenever the batch still yields >= 256 such tiles, otherwise
+// 64 x 64 tiles on 4 waves keep the chip busy; narrow right-hand sides use
+// 64 x 16.
 rsrs_status gemm(Uploader& up, hipStream_t st, const std::vector<GemmDesc>& descs, int ta, int tb,
                  int mode, GemmShape shape, const char* site) {
   if (descs.empty()) return RSRS_OK;
@@ -155,6 +157,13 @@ rsrs_status gemm(Uploader& up, hipStream_t st, const std::vector<GemmDesc>& desc
     ~SiteGuard() { g_site = nullptr; }
   } guard(site);
   if (shape == GS_64x16 && mode == GM_FULL) return gemm_shape<64, 16, 4, 1>(up, st, descs, ta, tb, mode);
+  int64_t t128 = 0;
+  for (const auto& d : descs) {
+    if (d.M <= 0 || d.N <= 0) continue;
+    const int64_t tm = (d.M + 127) / 128, tn = (d.N + 127) / 128;
+    t128 += mode == GM_SYRK_L ? tm * (tm + 1) / 2 : tm * tn;
+  }
+  if (t128 >= 256) return gemm_shape<128, 128, 2, 4>(up, st, descs, ta, tb, mode);
   return gemm_shape<64, 64, 2, 2>(up, st, descs, ta, tb, mode);
 }
 

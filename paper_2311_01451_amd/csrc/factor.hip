@@ -465,7 +465,7 @@ rsrs_status factor_impl(const rsrs_tree_t* th, rsrs_samples_t* smp, const rsrs_f
       RSRS_TRY(gemm(up, st, gku, 0, 0, GM_FULL, GS_64x64, "mult"));
       RSRS_TRY(gemm(up, st, gkl, 1, 0, GM_FULL, GS_64x64, "mult"));
       // ---- sketch updates: sparsify (E, F) then eliminate (L, U)
-      std::vector<GemmDesc> s0, s1, e0, e1;
+      std::vector<GemmDesc> s0, s1, e0, e1, e0b, e1b;
       for (int64_t q = 0; q < nb; ++q) {
         const BoxRec& R = F->boxes[g.first + q];
         const int r = (int)R.r, kn = (int)(k + R.n);
@@ -481,14 +481,16 @@ rsrs_status factor_impl(const rsrs_tree_t* th, rsrs_samples_t* smp, const rsrs_f
         s1.push_back(gdesc(T, nullptr, lT, Om, gR, sld, Om, gS, sld, k, (int)s, r, 1.0, 1.0));
         s1.push_back(gdesc(T, nullptr, lT, Psi, gR, sld, Psi, gS, sld, k, (int)s, r, 1.0, 1.0));
         e0.push_back(gdesc(KL, nullptr, lR, Y, gR, sld, Y, gSN, sld, kn, (int)s, r, -1.0, 1.0));
-        e0.push_back(gdesc(KU, nullptr, lU, Om, gSN, sld, Om, gR, sld, r, (int)s, kn, 1.0, 1.0));
+        e0b.push_back(gdesc(KU, nullptr, lU, Om, gSN, sld, Om, gR, sld, r, (int)s, kn, 1.0, 1.0));
         e1.push_back(gdesc(KU, nullptr, lU, Z, gR, sld, Z, gSN, sld, kn, (int)s, r, -1.0, 1.0));
-        e1.push_back(gdesc(KL, nullptr, lR, Psi, gSN, sld, Psi, gR, sld, r, (int)s, kn, 1.0, 1.0));
+        e1b.push_back(gdesc(KL, nullptr, lR, Psi, gSN, sld, Psi, gR, sld, r, (int)s, kn, 1.0, 1.0));
       }
       RSRS_TRY(gemm(up, st, s0, 0, 0, GM_FULL, GS_64x64, "sparsify"));
       RSRS_TRY(gemm(up, st, s1, 1, 0, GM_FULL, GS_64x64, "sparsify"));
       RSRS_TRY(gemm(up, st, e0, 0, 0, GM_FULL, GS_64x64, "elim"));
       RSRS_TRY(gemm(up, st, e1, 1, 0, GM_FULL, GS_64x64, "elim"));
+      RSRS_TRY(gemm(up, st, e0b, 0, 0, GM_FULL, GS_64x64, "elim_r"));
+      RSRS_TRY(gemm(up, st, e1b, 1, 0, GM_FULL, GS_64x64, "elim_r"));
     }
     for (int64_t b : lb) remaining[b] = cur[b];
   }

@@ -16,7 +16,7 @@
 // Masked entries are selected away, so whatever the unused triangle of the
 // stored operand holds is never read into the product.
 //
-// One workgroup (4 waves) computes a BM x BN tile; waves are arranged WM x WN
+// One workgroup (4 or 8 waves) computes a BM x BN tile; waves are arranged WM x WN
 // and each holds (BM/WM/16) x (BN/WN/16) 16x16 FP64 accumulator blocks.  The
 // K loop is software pipelined: the next BK-slice of A and B is fetched into
 // registers while the current one is multiplied out of LDS, and LDS is double
@@ -54,17 +54,18 @@ enum GemmMode { GM_FULL = 0, GM_SYRK_L = 1, GM_B_NT_LOW = 2, GM_B_NN_LOW = 3, GM
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 template <int BM, int BN, int WM, int WN, int TA, int TB, int MODE, int VEC>
-__global__ __launch_bounds__(256) void gemm_f64_kernel(const GemmDesc* __restrict__ descs) {
+__global__ __launch_bounds__(64 * WM * WN) void gemm_f64_kernel(const GemmDesc* __restrict__ descs) {
+  constexpr int NT = 64 * WM * WN;    // threads per workgroup
   constexpr int BK = 16;
   constexpr int PA = BM + 2;
   constexpr int PB = BN + 2;
   constexpr int FM = BM / WM / 16;
   constexpr int FN = BN / WN / 16;
-  constexpr int NA = BM * BK / 256 / VEC;   // VEC-wide A fetches per thread per slice
-  constexpr int NB = BN * BK / 256 / VEC;
-  static_assert(WM * WN == 4, "4 waves");
+  constexpr int NA = BM * BK / NT / VEC;   // VEC-wide A fetches per thread per slice
+  constexpr int NB = BN * BK / NT / VEC;
+  static_assert(WM * WN == 4 || WM * WN == 8, "4 or 8 waves");
   static_assert(FM >= 1 && FN >= 1, "tile too small");
-  static_assert(NA >= 1 && NB >= 1 && NA * 256 * VEC == BM * BK && NB * 256 * VEC == BN * BK,
+  static_assert(NA >= 1 && NB >= 1 && NA * NT * VEC == BM * BK && NB * NT * VEC == BN * BK,
                 "tile split");
   __shared__ double As[2][BK * PA];
   __shared__ double Bs[2][BK * PB];
@@ -109,7 +110,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const GemmDesc* __restric
   const double* browp[NB];
 #pragma unroll
   for (int q = 0; q < NA; ++q) {
-    const int e = (tid + q * 256) * VEC;
+    const int e = (tid + q * NT) * VEC;
     if (TA == 0) { am[q] = e / BK; ak[q] = e % BK; }
     else         { ak[q] = e / BM; am[q] = e % BM; }
     const int gm = min(m0 + am[q], d.M - 1);
@@ -117,7 +118,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const GemmDesc* __restric
   }
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
-    const int e = (tid + q * 256) * VEC;
+    const int e = (tid + q * NT) * VEC;
     if (TB == 1) { bn_[q] = e / BK; bk[q] = e % BK; }
     else         { bk[q] = e / BN; bn_[q] = e % BN; }
     const int gn = min(n0 + bn_[q], d.N - 1);
