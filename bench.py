@@ -54,9 +54,19 @@ def workload_config(s_req: int, s_eff: int) -> dict:
             "precision": "fp64"}
 
 
-def gpu_bench(steps: int, warmup: int, do_profile: bool):
+def gpu_bench(steps: int, warmup: int, do_profile: bool, latency_reps: int = 40,
+              calib_copy_mib: int = 0):
     import torch
     from paper_2311_01451_amd import inputs, rsrs
+
+    if calib_copy_mib > 0:
+        # a plain copy of known size: reference for the HBM byte counters
+        n = calib_copy_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     pts = inputs.grid2d(GRID_N)
     h = 1.0 / GRID_N
@@ -106,13 +116,13 @@ def gpu_bench(steps: int, warmup: int, do_profile: bool):
 
     # solve latency of the resident factor (16 RHS per request)
     lat = []
-    for _ in range(40):
+    for _ in range(latency_reps + 5):
         torch.cuda.synchronize()
         a = time.perf_counter()
         F.solve(f)
         torch.cuda.synchronize()
         lat.append((time.perf_counter() - a) * 1e3)
-    lat = np.array(lat[5:])
+    lat = np.array(lat[5:] if len(lat) > 5 else lat)
     return rec, elapsed, prof, lat
 
 
@@ -125,6 +135,28 @@ def by_kernel(prof: dict) -> dict:
         for f in e:
             e[f] += v[f]
     return out
+
+
+# rocprof kernel names of the measured forms (tag -> template instantiation)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_f64_128x128_nn_65k_log2d_traffic.json")
+TAG_TO_KERNEL = {"gemm_nn_full_128x128":
+                 "void rsrs::gemm_f64_kernel<128, 128, 2, 4, 0, 0, 0, 2>(rsrs::GemmDesc const*)"}
+
+
+def measured_traffic(tag: str):
+    """HBM bytes per launch from the committed counter summary, or None when
+    the kernel differs or its source changed since the counters were taken."""
+    import hashlib
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+        src = open(os.path.join(ROOT, t["source"]), "rb").read()
+    except (OSError, ValueError, KeyError):
+        return None
+    if TAG_TO_KERNEL.get(tag) != t.get("kernel"):
+        return None
+    if hashlib.sha256(src).hexdigest() != t.get("source_sha256"):
+        return None
+    return round(t["fetch_bytes_per_launch"] + t["write_bytes_per_launch"], 1)
 
 
 def roofline_from_profile(prof: dict, steps: int) -> dict | None:
@@ -141,7 +173,7 @@ def roofline_from_profile(prof: dict, steps: int) -> dict | None:
         bound, peak, unit = "hbm", PEAK_HBM_GBS, "GB/s"
     total_ms = sum(v["ms"] for v in prof.values())
     return {"bound": bound, "achieved": round(ach, 3), "peak": peak, "unit": unit,
-            "frac": round(ach / peak, 4), "traffic": None, "kernel": tag,
+            "frac": round(ach / peak, 4), "traffic": measured_traffic(tag), "kernel": tag,
             "launches_per_step": e["launches"] / steps,
             "avg_launch_ms": e["ms"] / e["launches"],
             "algorithmic_flops_per_launch": e["flops"] / e["launches"],
@@ -222,12 +254,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--latency-reps", type=int, default=40)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run a plain device copy of this size first (counter calibration)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {a.gpus}); "
               "the multi-GPU sharding is described in DESIGN.md but not run", file=sys.stderr)
         sys.exit(2)
-    rec, elapsed, prof, lat = gpu_bench(a.steps, a.warmup, not a.no_profile)
+    rec, elapsed, prof, lat = gpu_bench(a.steps, a.warmup, not a.no_profile, a.latency_reps,
+                                        a.calib_copy_mib)
     s_req, s_eff = rec[-1]["s_req"], rec[-1]["s_eff"]
     ms = elapsed / a.steps * 1e3
     out = {
