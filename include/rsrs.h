@@ -133,8 +133,14 @@ int64_t rsrs_samples_required(const rsrs_tree_t* t, int k, int p);
  * `stream`.  It returns 0 on success; any other value aborts the caller with
  * RSRS_E_CALLBACK.
  * ---------------------------------------------------------------------- */
-typedef int (*rsrs_matvec_fn)(void* user, int transpose, int64_t ncols, const double* X,
-                              int64_t ldx, double* Y, int64_t ldy, void* stream);
+/* Element type of a device block: RSRS_F64 (double) or RSRS_F32 (float). */
+enum { RSRS_F64 = 0, RSRS_F32 = 1 };
+/* X and Y have element type `dtype`.  The library asks for RSRS_F32 products
+ * only while sampling FP32 sketches (rsrs_sample with RSRS_F32); residuals of
+ * rsrs_solve_refine are always requested in RSRS_F64.  A callback that does
+ * not provide the requested type returns nonzero. */
+typedef int (*rsrs_matvec_fn)(void* user, int transpose, int dtype, int64_t ncols, const void* X,
+                              int64_t ldx, void* Y, int64_t ldy, void* stream);
 
 /* Built-in synthetic operators (HIP kernels; the handle is the `user` of
  * rsrs_op_matvec, which has the rsrs_matvec_fn signature):
@@ -144,37 +150,44 @@ typedef int (*rsrs_matvec_fn)(void* user, int transpose, int64_t ncols, const do
  *                 (param unused; dim 3)
  *  RSRS_OP_LOG2D_SKEW  LOG2D plus param2 * (x_i - x_j)_0 / |x_i - x_j|^2
  *                 (non-symmetric)
- * pts: host n x dim (user order); copied to the device. */
+ * pts: host n x dim (user order); copied to the device.  The kernel matrix is
+ * materialised on the device in FP64 at creation (n^2 doubles); an FP32 copy
+ * (n^2 floats) is added at the first RSRS_F32 product, whose product is then
+ * an FP32 MFMA GEMM with FP32 accumulation. */
 enum { RSRS_OP_LOG2D = 1, RSRS_OP_INVR3D = 2, RSRS_OP_LOG2D_SKEW = 3 };
 rsrs_status rsrs_op_create_kernel(int kind, const double* pts, int64_t n, int dim,
                                   double param, double param2, rsrs_operator_t** out);
 /* Explicit matrix: A is a device n x n row-major array (leading dimension
- * lda), borrowed (must outlive the operator). */
+ * lda), borrowed (must outlive the operator).  RSRS_F64 products only. */
 rsrs_status rsrs_op_create_dense(const double* A, int64_t n, int64_t lda, rsrs_operator_t** out);
 /* 7-point -div(a grad u) on the n^3 interior nodes of the grid h = 1/(n+1)
  * (x fastest), face coefficient = mean of the two node values, Dirichlet
- * nodes eliminated; coef: host (n+2)^3 node values indexed [z][y][x]. */
+ * nodes eliminated; coef: host (n+2)^3 node values indexed [z][y][x].
+ * RSRS_F32 products read and write float and accumulate in FP64. */
 rsrs_status rsrs_op_create_poisson7(int n, const double* coef, rsrs_operator_t** out);
-int rsrs_op_matvec(void* op, int transpose, int64_t ncols, const double* X, int64_t ldx,
-                   double* Y, int64_t ldy, void* stream);
+int rsrs_op_matvec(void* op, int transpose, int dtype, int64_t ncols, const void* X, int64_t ldx,
+                   void* Y, int64_t ldy, void* stream);
 void rsrs_op_destroy(rsrs_operator_t* op);
 
 /* ------------------------------------------------------------------------
  * Samples {Y, Z, Omega, Psi} (Algorithm 1, Require).  Stored by the library
- * in tree order, row-major N x s FP64 on the device.
+ * in tree order, row-major N x s on the device, element type dtype
+ * (RSRS_F64, or RSRS_F32 for the mixed-precision factorization).
  * ---------------------------------------------------------------------- */
 /* Copy caller-provided device sketches (user order, row-major, leading
- * dimension ld >= s) into library-owned tree-ordered storage.  The caller's
- * arrays are not modified. */
-rsrs_status rsrs_samples_wrap(const rsrs_tree_t* t, const double* Y, const double* Z,
-                              const double* Omega, const double* Psi, int64_t ld, int64_t s,
+ * dimension ld >= s, element type dtype) into library-owned tree-ordered
+ * storage.  The caller's arrays are not modified. */
+rsrs_status rsrs_samples_wrap(const rsrs_tree_t* t, int dtype, const void* Y, const void* Z,
+                              const void* Omega, const void* Psi, int64_t ld, int64_t s,
                               void* stream, rsrs_samples_t** out);
 /* Draw Omega, Psi on the device with Philox-4x32-10 (Salmon et al., SC'11)
  * and Box-Muller, then Y = A Omega and Z = A^T Psi through `mv`.  Element
  * (user row i, column j) of Omega uses counter (i, j, 0, seed_hi) and key
- * (seed_lo, 0x2311); Psi uses stream word 1 in place of 0. */
+ * (seed_lo, 0x2311); Psi uses stream word 1 in place of 0.  With dtype
+ * RSRS_F32 the FP64 normal is rounded to float and `mv` is asked for FP32
+ * products of the rounded test matrices. */
 rsrs_status rsrs_sample(const rsrs_tree_t* t, rsrs_matvec_fn mv, void* user, int64_t s,
-                        uint64_t seed, void* stream, rsrs_samples_t** out);
+                        uint64_t seed, int dtype, void* stream, rsrs_samples_t** out);
 void rsrs_samples_destroy(rsrs_samples_t* smp);
 
 /* Fill a device array with standard normals from the generator above:
@@ -188,13 +201,25 @@ rsrs_status rsrs_gaussian(double* out, int64_t nrows, int64_t ncols, int64_t ld,
  *  s < rsrs_samples_required(t, k, p)  -> RSRS_E_SAMPLES
  *  singular pivot block / root block   -> RSRS_E_SINGULAR
  *  non-finite value in the samples     -> RSRS_E_NUMERIC
+ *  precision / sample dtype mismatch   -> RSRS_E_INVALID
  * The factor is device-resident and owned by the caller.
+ *
+ * Precision.  RSRS_PREC_F64: FP64 samples, FP64 arithmetic and factor.
+ * RSRS_PREC_F32_MIXED: FP32 samples and an FP32 stored factor; every product
+ * of sketch-sized operands (Gram matrices, projections, extraction,
+ * multipliers, sparsification and elimination updates) runs on FP32 MFMA with
+ * FP32 accumulation, while the rank decisions stay FP64: the Gram matrices
+ * are written and Cholesky-factored in FP64, the column-pivoted QR of the ID
+ * works on an FP64 copy of the projected sketch, and X_RR and the root block
+ * are inverted by FP64 Gauss-Jordan with partial pivoting.  Solves with such a
+ * factor take and return FP64 blocks and compute in FP32; accuracy is
+ * recovered by rsrs_solve_refine with the FP64 black-box residual.
  * ---------------------------------------------------------------------- */
-enum { RSRS_PREC_F64 = 0 };
+enum { RSRS_PREC_F64 = 0, RSRS_PREC_F32_MIXED = 1 };
 typedef struct {
   int k;            /* fixed rank (k_B = min(k, b)) */
   int p;            /* oversampling used in the sample check; < 0 -> p = k */
-  int precision;    /* RSRS_PREC_F64 */
+  int precision;    /* RSRS_PREC_F64 (FP64 samples) or RSRS_PREC_F32_MIXED (FP32 samples) */
   int reproject;    /* extra projection passes in the nullification (0 or 1; default 1) */
 } rsrs_factor_opts;
 
@@ -206,7 +231,9 @@ typedef struct {
   int64_t n, s, k;
   int64_t nboxes;          /* processed boxes */
   int64_t root_size;       /* |B_t| */
-  int64_t stored_doubles;  /* T, X_RR, X_RR^{-1}, K_U, K_L, root */
+  int64_t stored_values;   /* T, X_RR, X_RR^{-1}, K_U, K_L, root (elements) */
+  int64_t stored_bytes;    /* stored_values times the element size */
+  int precision;           /* RSRS_PREC_* of the factorization */
   double flops;            /* algorithmic flop count of this factorization */
   double factor_ms;        /* wall time of rsrs_factor (stream synchronised) */
 } rsrs_factor_info;
@@ -215,7 +242,8 @@ rsrs_status rsrs_factor_get_info(const rsrs_factor_t* f, rsrs_factor_info* out);
 /* Per-box export for verification (box i in processing order).  Sizes first,
  * then copies into caller host buffers (any pointer may be NULL to skip):
  * Ba (b), Na (n), S (k), R (r) as tree positions; T r x k, XRR r x r,
- * KU r x (k+n), KL (k+n) x r, row-major. */
+ * KU r x (k+n), KL (k+n) x r, row-major FP64 (converted from FP32 for a
+ * mixed-precision factor). */
 rsrs_status rsrs_factor_box_sizes(const rsrs_factor_t* f, int64_t i, int64_t* box, int32_t* level,
                                   int32_t* colour, int64_t* b, int64_t* n, int64_t* r,
                                   int64_t* k);

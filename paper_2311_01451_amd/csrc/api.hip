@@ -20,6 +20,8 @@ rsrs_status factor_impl(const rsrs_tree_t* th, rsrs_samples_t* smp, const rsrs_f
 rsrs_status apply_factor(const rsrs_factor_t* F, int op, int transpose, int64_t w, const double* Fin,
                          int64_t ldf, double* Uout, int64_t ldu, hipStream_t st);
 
+static int64_t dtype_size(int dtype) { return dtype == RSRS_F64 ? 8 : (dtype == RSRS_F32 ? 4 : 0); }
+
 static rsrs_status invalid(const char* msg) {
   set_error(msg);
   return RSRS_E_INVALID;
@@ -128,7 +130,7 @@ rsrs_status rsrs_op_create_kernel(int kind, const double* pts, int64_t n, int di
   op->n = n;
   op->lda = n;
   op->symmetric = kind != RSRS_OP_LOG2D_SKEW;
-  KernelOp ko;
+  KernelOp& ko = op->kop;
   ko.kind = kind;
   ko.dim = dim;
   ko.n = n;
@@ -142,7 +144,7 @@ rsrs_status rsrs_op_create_kernel(int kind, const double* pts, int64_t n, int di
     set_error("hipMemcpy of points failed");
     return RSRS_E_HIP;
   }
-  s = kernel_materialise(nullptr, ko, op->owned.as<double>());
+  s = kernel_materialise<double>(nullptr, ko, op->owned.as<double>());
   if (s == RSRS_OK && hipDeviceSynchronize() != hipSuccess) s = RSRS_E_HIP;
   if (s != RSRS_OK) { delete op; return s; }
   op->A = op->owned.as<double>();
@@ -199,13 +201,19 @@ rsrs_status rsrs_op_create_poisson7(int n, const double* coef, rsrs_operator_t**
   return RSRS_OK;
 }
 
-int rsrs_op_matvec(void* opv, int transpose, int64_t ncols, const double* X, int64_t ldx, double* Y,
-                   int64_t ldy, void* stream) {
+int rsrs_op_matvec(void* opv, int transpose, int dtype, int64_t ncols, const void* X, int64_t ldx,
+                   void* Y, int64_t ldy, void* stream) {
   auto op = static_cast<rsrs_operator_t*>(opv);
-  if (!op || !X || !Y || ncols < 0) return 1;
+  if (!op || !X || !Y || ncols < 0 || dtype_size(dtype) == 0) return 1;
   if (ncols == 0) return 0;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (op->kind == 20) return poisson_matvec(st, op->pois, ncols, X, ldx, Y, ldy) == RSRS_OK ? 0 : 1;
+  if (op->kind == 20) {
+    if (dtype == RSRS_F64)
+      return poisson_matvec<double>(st, op->pois, ncols, static_cast<const double*>(X), ldx,
+                                    static_cast<double*>(Y), ldy) == RSRS_OK ? 0 : 1;
+    return poisson_matvec<float>(st, op->pois, ncols, static_cast<const float*>(X), ldx,
+                                 static_cast<float*>(Y), ldy) == RSRS_OK ? 0 : 1;
+  }
   if (!op->up_ready) {
     if (op->up.init((size_t)1 << 20, st) != RSRS_OK) return 1;
     op->up_ready = true;
@@ -215,22 +223,38 @@ int rsrs_op_matvec(void* opv, int transpose, int64_t ncols, const double* X, int
     op->up.st = st;
   }
   const int n = (int)op->n;
-  std::vector<GemmDesc> d{gdesc(op->A, nullptr, op->lda, X, nullptr, ldx, Y, nullptr, ldy, n,
-                                (int)ncols, n)};
   const int ta = (transpose && !op->symmetric) ? 1 : 0;
-  return gemm(op->up, st, d, ta, 0, GM_FULL, ncols <= 16 ? GS_64x16 : GS_64x64, "operator") == RSRS_OK ? 0 : 1;
+  const GemmShape shp = ncols <= 16 ? GS_64x16 : GS_64x64;
+  if (dtype == RSRS_F64) {
+    std::vector<GemmDesc> d{gdesc(op->A, nullptr, op->lda, static_cast<const double*>(X), nullptr, ldx,
+                                  static_cast<double*>(Y), nullptr, ldy, n, (int)ncols, n)};
+    return gemm(op->up, st, d, ta, 0, GM_FULL, shp, "operator") == RSRS_OK ? 0 : 1;
+  }
+  if (op->kind == 10) {
+    set_error("a borrowed dense operator provides FP64 products only");
+    return 1;
+  }
+  if (!op->owned32.p) {   // FP32 kernel matrix, entries rounded from the FP64 formula
+    if (op->owned32.alloc((size_t)op->n * op->n * 4) != RSRS_OK) return 1;
+    if (kernel_materialise<float>(st, op->kop, op->owned32.as<float>()) != RSRS_OK) return 1;
+  }
+  std::vector<GemmDescT<float, float>> d{gdescT<float, float>(
+      op->owned32.as<float>(), nullptr, op->n, static_cast<const float*>(X), nullptr, ldx,
+      static_cast<float*>(Y), nullptr, ldy, n, (int)ncols, n)};
+  return gemm<float, float>(op->up, st, d, ta, 0, GM_FULL, shp, "operator") == RSRS_OK ? 0 : 1;
 }
 
 void rsrs_op_destroy(rsrs_operator_t* op) { delete op; }
 
 // ------------------------------------------------------------------ samples
-static rsrs_status new_samples(const rsrs_tree_t* th, int64_t s, rsrs_samples_t** out) {
+static rsrs_status new_samples(const rsrs_tree_t* th, int64_t s, int dtype, rsrs_samples_t** out) {
   auto smp = new rsrs_samples_t();
   smp->tree = th;
   smp->n = th->t.n;
   smp->s = s;
   smp->ld = round_up(s, 16);
-  const size_t bytes = (size_t)smp->n * smp->ld * 8;
+  smp->dtype = dtype;
+  const size_t bytes = (size_t)smp->n * smp->ld * dtype_size(dtype);
   rsrs_status st = smp->Y.alloc(bytes);
   if (st == RSRS_OK) st = smp->Z.alloc(bytes);
   if (st == RSRS_OK) st = smp->Om.alloc(bytes);
@@ -240,14 +264,28 @@ static rsrs_status new_samples(const rsrs_tree_t* th, int64_t s, rsrs_samples_t*
   return RSRS_OK;
 }
 
-rsrs_status rsrs_samples_wrap(const rsrs_tree_t* th, const double* Y, const double* Z, const double* Om,
-                              const double* Psi, int64_t ld, int64_t s, void* stream,
+extern "C++" {
+template <typename T>
+static void gather_samples(hipStream_t st, rsrs_samples_t* smp, const void* Y, const void* Z,
+                           const void* Om, const void* Psi, int64_t ld, const int64_t* pp) {
+  const int64_t s = smp->s;
+  gather_rows<T, T>(st, smp->Y.as<T>(), smp->ld, static_cast<const T*>(Y), ld, pp, smp->n, s);
+  gather_rows<T, T>(st, smp->Z.as<T>(), smp->ld, static_cast<const T*>(Z), ld, pp, smp->n, s);
+  gather_rows<T, T>(st, smp->Om.as<T>(), smp->ld, static_cast<const T*>(Om), ld, pp, smp->n, s);
+  gather_rows<T, T>(st, smp->Psi.as<T>(), smp->ld, static_cast<const T*>(Psi), ld, pp, smp->n, s);
+}
+
+}  // extern "C++"
+
+rsrs_status rsrs_samples_wrap(const rsrs_tree_t* th, int dtype, const void* Y, const void* Z,
+                              const void* Om, const void* Psi, int64_t ld, int64_t s, void* stream,
                               rsrs_samples_t** out) {
   if (!th || !Y || !Z || !Om || !Psi || !out || s < 1 || ld < s) return invalid("bad samples arguments");
+  if (dtype_size(dtype) == 0) return invalid("unknown dtype");
   *out = nullptr;
   hipStream_t st = static_cast<hipStream_t>(stream);
   rsrs_samples_t* smp = nullptr;
-  RSRS_TRY(new_samples(th, s, &smp));
+  RSRS_TRY(new_samples(th, s, dtype, &smp));
   DevBuf perm;
   rsrs_status r = perm.alloc((size_t)smp->n * 8);
   if (r != RSRS_OK) { delete smp; return r; }
@@ -257,10 +295,8 @@ rsrs_status rsrs_samples_wrap(const rsrs_tree_t* th, const double* Y, const doub
     return RSRS_E_HIP;
   }
   const int64_t* pp = perm.as<int64_t>();
-  gather_rows(st, smp->Y.as<double>(), smp->ld, Y, ld, pp, smp->n, s);
-  gather_rows(st, smp->Z.as<double>(), smp->ld, Z, ld, pp, smp->n, s);
-  gather_rows(st, smp->Om.as<double>(), smp->ld, Om, ld, pp, smp->n, s);
-  gather_rows(st, smp->Psi.as<double>(), smp->ld, Psi, ld, pp, smp->n, s);
+  if (dtype == RSRS_F64) gather_samples<double>(st, smp, Y, Z, Om, Psi, ld, pp);
+  else gather_samples<float>(st, smp, Y, Z, Om, Psi, ld, pp);
   if (hipStreamSynchronize(st) != hipSuccess) {
     delete smp;
     set_error("stream synchronisation failed");
@@ -270,37 +306,48 @@ rsrs_status rsrs_samples_wrap(const rsrs_tree_t* th, const double* Y, const doub
   return RSRS_OK;
 }
 
-rsrs_status rsrs_sample(const rsrs_tree_t* th, rsrs_matvec_fn mv, void* user, int64_t s, uint64_t seed,
-                        void* stream, rsrs_samples_t** out) {
-  if (!th || !mv || !out || s < 1) return invalid("bad sample arguments");
-  *out = nullptr;
+extern "C++" {
+template <typename T>
+static rsrs_status sample_t(const rsrs_tree_t* th, rsrs_matvec_fn mv, void* user, uint64_t seed,
+                            void* stream, rsrs_samples_t* smp) {
   hipStream_t st = static_cast<hipStream_t>(stream);
-  rsrs_samples_t* smp = nullptr;
-  RSRS_TRY(new_samples(th, s, &smp));
+  const int64_t s = smp->s;
   DevBuf tu, ty, perm;
-  const size_t bytes = (size_t)smp->n * smp->ld * 8;
-  rsrs_status r = tu.alloc(bytes);
-  if (r == RSRS_OK) r = ty.alloc(bytes);
-  if (r == RSRS_OK) r = perm.alloc((size_t)smp->n * 8);
-  if (r != RSRS_OK) { delete smp; return r; }
-  (void)hipMemcpyAsync(perm.p, th->t.perm.data(), (size_t)smp->n * 8, hipMemcpyHostToDevice, st);
+  const size_t bytes = (size_t)smp->n * smp->ld * sizeof(T);
+  RSRS_TRY(tu.alloc(bytes));
+  RSRS_TRY(ty.alloc(bytes));
+  RSRS_TRY(perm.alloc((size_t)smp->n * 8));
+  RSRS_HIP(hipMemcpyAsync(perm.p, th->t.perm.data(), (size_t)smp->n * 8, hipMemcpyHostToDevice, st));
   const int64_t* pp = perm.as<int64_t>();
   for (int side = 0; side < 2; ++side) {
-    philox_normal(st, tu.as<double>(), smp->n, s, smp->ld, seed, (uint32_t)side);
-    if (mv(user, side, s, tu.as<double>(), smp->ld, ty.as<double>(), smp->ld, stream) != 0) {
+    philox_normal<T>(st, tu.as<T>(), smp->n, s, smp->ld, seed, (uint32_t)side);
+    if (mv(user, side, smp->dtype, s, tu.as<T>(), smp->ld, ty.as<T>(), smp->ld, stream) != 0) {
       (void)hipStreamSynchronize(st);
-      delete smp;
       set_error("matvec callback returned nonzero");
       return RSRS_E_CALLBACK;
     }
-    gather_rows(st, (side ? smp->Psi : smp->Om).as<double>(), smp->ld, tu.as<double>(), smp->ld, pp, smp->n, s);
-    gather_rows(st, (side ? smp->Z : smp->Y).as<double>(), smp->ld, ty.as<double>(), smp->ld, pp, smp->n, s);
+    gather_rows<T, T>(st, (side ? smp->Psi : smp->Om).as<T>(), smp->ld, tu.as<T>(), smp->ld, pp, smp->n, s);
+    gather_rows<T, T>(st, (side ? smp->Z : smp->Y).as<T>(), smp->ld, ty.as<T>(), smp->ld, pp, smp->n, s);
   }
   if (hipStreamSynchronize(st) != hipSuccess) {
-    delete smp;
     set_error(std::string("sampling failed: ") + hipGetErrorString(hipGetLastError()));
     return RSRS_E_HIP;
   }
+  return RSRS_OK;
+}
+
+}  // extern "C++"
+
+rsrs_status rsrs_sample(const rsrs_tree_t* th, rsrs_matvec_fn mv, void* user, int64_t s, uint64_t seed,
+                        int dtype, void* stream, rsrs_samples_t** out) {
+  if (!th || !mv || !out || s < 1) return invalid("bad sample arguments");
+  if (dtype_size(dtype) == 0) return invalid("unknown dtype");
+  *out = nullptr;
+  rsrs_samples_t* smp = nullptr;
+  RSRS_TRY(new_samples(th, s, dtype, &smp));
+  const rsrs_status r = dtype == RSRS_F64 ? sample_t<double>(th, mv, user, seed, stream, smp)
+                                          : sample_t<float>(th, mv, user, seed, stream, smp);
+  if (r != RSRS_OK) { delete smp; return r; }
   *out = smp;
   return RSRS_OK;
 }
@@ -310,7 +357,7 @@ void rsrs_samples_destroy(rsrs_samples_t* smp) { delete smp; }
 rsrs_status rsrs_gaussian(double* out, int64_t nrows, int64_t ncols, int64_t ld, uint64_t seed,
                           uint32_t word, void* stream) {
   if (!out || nrows < 0 || ncols < 0 || ld < ncols) return invalid("bad gaussian arguments");
-  philox_normal(static_cast<hipStream_t>(stream), out, nrows, ncols, ld, seed, word);
+  philox_normal<double>(static_cast<hipStream_t>(stream), out, nrows, ncols, ld, seed, word);
   if (hipGetLastError() != hipSuccess) { set_error("philox launch failed"); return RSRS_E_HIP; }
   return RSRS_OK;
 }
@@ -332,7 +379,9 @@ rsrs_status rsrs_factor_get_info(const rsrs_factor_t* f, rsrs_factor_info* out) 
   out->k = f->k;
   out->nboxes = (int64_t)f->boxes.size();
   out->root_size = f->nt;
-  out->stored_doubles = f->stored_doubles;
+  out->stored_values = f->stored_values;
+  out->stored_bytes = f->stored_values * f->esz;
+  out->precision = f->precision;
   out->flops = f->flops;
   out->factor_ms = f->factor_ms;
   return RSRS_OK;
@@ -358,11 +407,22 @@ static rsrs_status d2h(void* dst, const void* src, size_t bytes) {
   return RSRS_OK;
 }
 
-// rows x cols block with device leading dimension ld into a compact host block
-static rsrs_status d2h2(double* dst, int64_t cols, const double* src, int64_t ld, int64_t rows) {
+// rows x cols block (element offset off of the factor store, leading
+// dimension ld) into a compact host FP64 block; FP32 stores are converted.
+static rsrs_status d2h2(const rsrs_factor_t* f, double* dst, int64_t cols, int64_t off, int64_t ld,
+                        int64_t rows) {
   if (!dst || rows == 0 || cols == 0) return RSRS_OK;
-  RSRS_HIP(hipMemcpy2D(dst, (size_t)cols * 8, src, (size_t)ld * 8, (size_t)cols * 8, (size_t)rows,
+  const size_t es = (size_t)f->esz;
+  const char* src = static_cast<const char*>(f->dstore.p) + off * es;
+  if (es == 8) {
+    RSRS_HIP(hipMemcpy2D(dst, (size_t)cols * 8, src, (size_t)ld * 8, (size_t)cols * 8, (size_t)rows,
+                         hipMemcpyDeviceToHost));
+    return RSRS_OK;
+  }
+  std::vector<float> tmp((size_t)rows * cols);
+  RSRS_HIP(hipMemcpy2D(tmp.data(), (size_t)cols * 4, src, (size_t)ld * 4, (size_t)cols * 4, (size_t)rows,
                        hipMemcpyDeviceToHost));
+  for (size_t i = 0; i < tmp.size(); ++i) dst[i] = (double)tmp[i];
   return RSRS_OK;
 }
 
@@ -376,10 +436,10 @@ rsrs_status rsrs_factor_box_copy(const rsrs_factor_t* f, int64_t i, int64_t* Ba,
   RSRS_TRY(d2h(Na, f->i() + B.oNa, (size_t)B.n * 8));
   RSRS_TRY(d2h(S, f->i() + B.oS, (size_t)B.k * 8));
   RSRS_TRY(d2h(R, f->i() + B.oR, (size_t)B.r * 8));
-  RSRS_TRY(d2h2(T, B.k, f->d() + B.oT, B.ldT, B.r));
-  RSRS_TRY(d2h2(XRR, B.r, f->d() + B.oXRR, B.ldR, B.r));
-  RSRS_TRY(d2h2(KU, kn, f->d() + B.oKU, B.ldKU, B.r));
-  RSRS_TRY(d2h2(KL, B.r, f->d() + B.oKL, B.ldR, kn));
+  RSRS_TRY(d2h2(f, T, B.k, B.oT, B.ldT, B.r));
+  RSRS_TRY(d2h2(f, XRR, B.r, B.oXRR, B.ldR, B.r));
+  RSRS_TRY(d2h2(f, KU, kn, B.oKU, B.ldKU, B.r));
+  RSRS_TRY(d2h2(f, KL, B.r, B.oKL, B.ldR, kn));
   return RSRS_OK;
 }
 
@@ -388,7 +448,7 @@ rsrs_status rsrs_factor_root_copy(const rsrs_factor_t* f, int64_t* nt, int64_t* 
   RSRS_HIP(hipDeviceSynchronize());
   if (nt) *nt = f->nt;
   RSRS_TRY(d2h(Bt, f->i() + f->oBt, (size_t)f->nt * 8));
-  RSRS_TRY(d2h(At, f->d() + f->oAt, (size_t)f->nt * f->nt * 8));
+  RSRS_TRY(d2h2(f, At, f->nt, f->oAt, f->nt, f->nt));
   return RSRS_OK;
 }
 
@@ -424,7 +484,7 @@ rsrs_status rsrs_solve_refine(const rsrs_factor_t* f, rsrs_matvec_fn mv, void* u
   double rel = 0.0;
   int it = 0;
   for (;;) {
-    if (mv(user, 0, w, U, ldu, r, w, stream) != 0) {
+    if (mv(user, 0, RSRS_F64, w, U, ldu, r, w, stream) != 0) {
       set_error("matvec callback returned nonzero");
       return RSRS_E_CALLBACK;
     }

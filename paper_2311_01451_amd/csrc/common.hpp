@@ -30,9 +30,9 @@ struct Status {
     }                                                                           \
   } while (0)
 
-#define RSRS_TRY(expr)                     \
+#define RSRS_TRY(...)                      \
   do {                                     \
-    rsrs_status s_ = (expr);               \
+    rsrs_status s_ = (__VA_ARGS__);        \
     if (s_ != RSRS_OK) return s_;          \
   } while (0)
 

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <type_traits>
 
 #include "kernels.hpp"
 #include "profile.hpp"
@@ -55,19 +56,23 @@ rsrs_status Uploader::reset() {
 // ---------------------------------------------------------------- GEMM dispatch
 static thread_local const char* g_site = nullptr;
 
-static const char* gemm_tag(int ta, int tb, int mode, int bm, int bn) {
+// Tag "gemm[32]_<form>_<mode>_<BM>x<BN>[:<site>]"; "gemm32" marks FP32 operands.
+static const char* gemm_tag(bool f32, int ta, int tb, int mode, int bm, int bn) {
   static const char* forms[2][2] = {{"nn", "nt"}, {"tn", "tt"}};
   static const char* modes[5] = {"full", "syrk", "bntlow", "bnnlow", "alow"};
   static thread_local char buf[48];
+  const char* g = f32 ? "gemm32" : "gemm";
   if (g_site)
-    std::snprintf(buf, sizeof(buf), "gemm_%s_%s_%dx%d:%s", forms[ta][tb], modes[mode], bm, bn, g_site);
+    std::snprintf(buf, sizeof(buf), "%s_%s_%s_%dx%d:%s", g, forms[ta][tb], modes[mode], bm, bn, g_site);
   else
-    std::snprintf(buf, sizeof(buf), "gemm_%s_%s_%dx%d", forms[ta][tb], modes[mode], bm, bn);
+    std::snprintf(buf, sizeof(buf), "%s_%s_%s_%dx%d", g, forms[ta][tb], modes[mode], bm, bn);
   return buf;
 }
 
 // Algorithmic flops and bytes of one batched launch.
-static void gemm_work(const std::vector<GemmDesc>& descs, int mode, double* flops, double* bytes) {
+template <typename TI, typename TO>
+static void gemm_work(const std::vector<GemmDescT<TI, TO>>& descs, int mode, double* flops,
+                      double* bytes) {
   double f = 0.0, b = 0.0;
   for (const auto& d : descs) {
     if (d.M <= 0 || d.N <= 0) continue;
@@ -76,24 +81,31 @@ static void gemm_work(const std::vector<GemmDesc>& descs, int mode, double* flop
     if (mode == GM_SYRK_L) ff = M * (N + 1.0) * K;
     if (mode == GM_B_NT_LOW || mode == GM_B_NN_LOW || mode == GM_A_LOW) ff = M * N * K;
     f += ff;
-    b += 8.0 * (M * K + K * N + M * N * (d.beta != 0.0 ? 2.0 : 1.0));
+    b += sizeof(TI) * (M * K + K * N) + sizeof(TO) * M * N * (d.beta != 0.0 ? 2.0 : 1.0);
   }
   *flops = f;
   *bytes = b;
 }
 
-// 16-byte loads need even leading dimensions and 16-byte aligned bases.
-static bool vec2_ok(const std::vector<GemmDesc>& descs) {
+// 16-byte loads need leading dimensions that are multiples of the vector
+// width and 16-byte aligned bases.
+template <typename TI, typename TO>
+static bool vec_ok(const std::vector<GemmDescT<TI, TO>>& descs) {
+  constexpr int64_t vw = 16 / sizeof(TI);
   for (const auto& d : descs) {
     if (d.M <= 0 || d.N <= 0) continue;
-    if ((d.lda & 1) || (d.ldb & 1)) return false;
+    if ((d.lda % vw) || (d.ldb % vw)) return false;
     if (((uintptr_t)d.A & 15) || ((uintptr_t)d.B & 15)) return false;
   }
   return true;
 }
 
-template <int BM, int BN, int WM, int WN, int TA, int TB, int MODE>
-static rsrs_status launch_gemm(Uploader& up, hipStream_t st, const std::vector<GemmDesc>& descs) {
+template <typename TI, typename TO, int BM, int BN, int WM, int WN, int TA, int TB, int MODE>
+static rsrs_status launch_gemm(Uploader& up, hipStream_t st,
+                               const std::vector<GemmDescT<TI, TO>>& descs) {
+  constexpr int VW = 16 / (int)sizeof(TI);
+  constexpr int NT = 64 * WM * WN;
+  constexpr bool can_vec = BN * 16 / NT >= VW && BM * 16 / NT >= VW;
   int64_t tiles = 0;
   for (const auto& d : descs)
     if (d.M > 0 && d.N > 0) {
@@ -103,69 +115,84 @@ static rsrs_status launch_gemm(Uploader& up, hipStream_t st, const std::vector<G
   if (tiles == 0) return RSRS_OK;
   double pf = 0.0, pb = 0.0;
   if (prof_on()) gemm_work(descs, MODE, &pf, &pb);
-  const bool v2 = (BN * 16 / (64 * WM * WN) >= 2) && vec2_ok(descs);
+  const bool vec = can_vec && vec_ok(descs);
   for (size_t b0 = 0; b0 < descs.size(); b0 += 65535) {
     const size_t nb = std::min<size_t>(65535, descs.size() - b0);
-    std::vector<GemmDesc> part(descs.begin() + b0, descs.begin() + b0 + nb);
-    GemmDesc* dd = nullptr;
+    std::vector<GemmDescT<TI, TO>> part(descs.begin() + b0, descs.begin() + b0 + nb);
+    GemmDescT<TI, TO>* dd = nullptr;
     RSRS_TRY(up.put_vec(part, &dd));
     dim3 grid((unsigned)round_up(tiles, 8), (unsigned)nb);
-    ProfScope ps(st, gemm_tag(TA, TB, MODE, BM, BN), b0 == 0 ? pf : 0.0, b0 == 0 ? pb : 0.0);
-    if constexpr (BN * 16 / (64 * WM * WN) >= 2 && BM * 16 / (64 * WM * WN) >= 2) {
-      if (v2) {
-        hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WM, WN, TA, TB, MODE, 2>), grid, dim3(64 * WM * WN), 0, st, dd);
+    ProfScope ps(st, gemm_tag(sizeof(TI) == 4, TA, TB, MODE, BM, BN), b0 == 0 ? pf : 0.0,
+                 b0 == 0 ? pb : 0.0);
+    if constexpr (can_vec) {
+      if (vec) {
+        hipLaunchKernelGGL((gemm_kernel<TI, TO, BM, BN, WM, WN, TA, TB, MODE, VW>), grid, dim3(NT), 0, st, dd);
       } else {
-        hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WM, WN, TA, TB, MODE, 1>), grid, dim3(64 * WM * WN), 0, st, dd);
+        hipLaunchKernelGGL((gemm_kernel<TI, TO, BM, BN, WM, WN, TA, TB, MODE, 1>), grid, dim3(NT), 0, st, dd);
       }
     } else {
-      hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WM, WN, TA, TB, MODE, 1>), grid, dim3(64 * WM * WN), 0, st, dd);
+      hipLaunchKernelGGL((gemm_kernel<TI, TO, BM, BN, WM, WN, TA, TB, MODE, 1>), grid, dim3(NT), 0, st, dd);
     }
     RSRS_HIP(hipGetLastError());
   }
   return RSRS_OK;
 }
 
-template <int BM, int BN, int WM, int WN>
-static rsrs_status gemm_shape(Uploader& up, hipStream_t st, const std::vector<GemmDesc>& descs,
-                              int ta, int tb, int mode) {
+template <typename TI, typename TO, int BM, int BN, int WM, int WN>
+static rsrs_status gemm_shape(Uploader& up, hipStream_t st,
+                              const std::vector<GemmDescT<TI, TO>>& descs, int ta, int tb,
+                              int mode) {
 #define RSRS_G(TA, TB, MODE)                                                       \
   if (ta == TA && tb == TB && mode == MODE)                                        \
-    return launch_gemm<BM, BN, WM, WN, TA, TB, MODE>(up, st, descs);
-  RSRS_G(0, 0, GM_FULL)
-  RSRS_G(0, 1, GM_FULL)
-  RSRS_G(1, 0, GM_FULL)
-  RSRS_G(1, 1, GM_FULL)
+    return launch_gemm<TI, TO, BM, BN, WM, WN, TA, TB, MODE>(up, st, descs);
+  if constexpr (std::is_same<TI, TO>::value) {
+    RSRS_G(0, 0, GM_FULL)
+    RSRS_G(0, 1, GM_FULL)
+    RSRS_G(1, 0, GM_FULL)
+    RSRS_G(1, 1, GM_FULL)
+    RSRS_G(0, 1, GM_B_NT_LOW)
+    RSRS_G(0, 0, GM_B_NN_LOW)
+    RSRS_G(0, 0, GM_A_LOW)
+  }
   RSRS_G(0, 1, GM_SYRK_L)
-  RSRS_G(0, 1, GM_B_NT_LOW)
-  RSRS_G(0, 0, GM_B_NN_LOW)
-  RSRS_G(0, 0, GM_A_LOW)
 #undef RSRS_G
   set_error("unsupported GEMM form");
   return RSRS_E_UNSUPPORTED;
 }
 
 // Tile choice, measured on MI355X: 128 x 128 tiles on 8 waves (each wave
-// 64 x 32, 4 waves per SIMD) reach 50+ TFLOP/s on the large products; they
-// are used whenever the batch still yields >= 256 such tiles, otherwise
+// 64 x 32, 4 waves per SIMD) reach 50+ TFLOP/s on the large FP64 products;
+// they are used whenever the batch still yields >= 256 such tiles, otherwise
 // 64 x 64 tiles on 4 waves keep the chip busy; narrow right-hand sides use
-// 64 x 16.
-rsrs_status gemm(Uploader& up, hipStream_t st, const std::vector<GemmDesc>& descs, int ta, int tb,
-                 int mode, GemmShape shape, const char* site) {
+// 64 x 16.  Mixed-type launches (FP32 operands, FP64 result) exist for the
+// Gram matrices only.
+template <typename TI, typename TO>
+rsrs_status gemm(Uploader& up, hipStream_t st, const std::vector<GemmDescT<TI, TO>>& descs, int ta,
+                 int tb, int mode, GemmShape shape, const char* site) {
   if (descs.empty()) return RSRS_OK;
   struct SiteGuard {
     explicit SiteGuard(const char* s) { g_site = s; }
     ~SiteGuard() { g_site = nullptr; }
   } guard(site);
-  if (shape == GS_64x16 && mode == GM_FULL) return gemm_shape<64, 16, 4, 1>(up, st, descs, ta, tb, mode);
+  if constexpr (std::is_same<TI, TO>::value) {
+    if (shape == GS_64x16 && mode == GM_FULL) return gemm_shape<TI, TO, 64, 16, 4, 1>(up, st, descs, ta, tb, mode);
+  }
   int64_t t128 = 0;
   for (const auto& d : descs) {
     if (d.M <= 0 || d.N <= 0) continue;
     const int64_t tm = (d.M + 127) / 128, tn = (d.N + 127) / 128;
     t128 += mode == GM_SYRK_L ? tm * (tm + 1) / 2 : tm * tn;
   }
-  if (t128 >= 256) return gemm_shape<128, 128, 2, 4>(up, st, descs, ta, tb, mode);
-  return gemm_shape<64, 64, 2, 2>(up, st, descs, ta, tb, mode);
+  if (t128 >= 256) return gemm_shape<TI, TO, 128, 128, 2, 4>(up, st, descs, ta, tb, mode);
+  return gemm_shape<TI, TO, 64, 64, 2, 2>(up, st, descs, ta, tb, mode);
 }
+
+template rsrs_status gemm<double, double>(Uploader&, hipStream_t, const std::vector<GemmDescT<double, double>>&,
+                                          int, int, int, GemmShape, const char*);
+template rsrs_status gemm<float, float>(Uploader&, hipStream_t, const std::vector<GemmDescT<float, float>>&,
+                                        int, int, int, GemmShape, const char*);
+template rsrs_status gemm<float, double>(Uploader&, hipStream_t, const std::vector<GemmDescT<float, double>>&,
+                                         int, int, int, GemmShape, const char*);
 
 // ---------------------------------------------------------------- Cholesky leaf
 // One workgroup per 64x64 (or smaller) diagonal block: unblocked right-looking
@@ -525,65 +552,83 @@ rsrs_status gje_inverse(Uploader& up, hipStream_t st, const std::vector<GjeDesc>
 }
 
 // ---------------------------------------------------------------- copies
-__global__ void copy2d_kernel(const Copy2D* __restrict__ e) {
-  const Copy2D d = e[blockIdx.y];
+template <typename TS, typename TD>
+__global__ void copy2d_kernel(const Copy2DT<TS, TD>* __restrict__ e) {
+  const Copy2DT<TS, TD> d = e[blockIdx.y];
   const int64_t total = (int64_t)d.rows * d.cols;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = idx / d.cols, c = idx % d.cols;
-    const double v = d.alpha * d.src[i * d.lds + c];
-    if (d.accumulate) d.dst[i * d.ldd + c] += v;
-    else d.dst[i * d.ldd + c] = v;
+    const double v = d.alpha * (double)d.src[i * d.lds + c];
+    if (d.accumulate) d.dst[i * d.ldd + c] = (TD)((double)d.dst[i * d.ldd + c] + v);
+    else d.dst[i * d.ldd + c] = (TD)v;
   }
 }
 
-rsrs_status copy2d(Uploader& up, hipStream_t st, const std::vector<Copy2D>& e) {
+template <typename TS, typename TD>
+rsrs_status copy2d(Uploader& up, hipStream_t st, const std::vector<Copy2DT<TS, TD>>& e) {
   if (e.empty()) return RSRS_OK;
   int64_t mx = 0;
   for (const auto& x : e) mx = std::max<int64_t>(mx, (int64_t)x.rows * x.cols);
   if (mx == 0) return RSRS_OK;
-  Copy2D* de = nullptr;
+  Copy2DT<TS, TD>* de = nullptr;
   RSRS_TRY(up.put_vec(e, &de));
   const unsigned gx = (unsigned)std::min<int64_t>((mx + 255) / 256, 4096);
   ProfScope ps(st, "copy2d");
-  hipLaunchKernelGGL(copy2d_kernel, dim3(gx, (unsigned)e.size()), dim3(256), 0, st, de);
+  hipLaunchKernelGGL((copy2d_kernel<TS, TD>), dim3(gx, (unsigned)e.size()), dim3(256), 0, st, de);
   RSRS_HIP(hipGetLastError());
   return RSRS_OK;
 }
 
-__global__ void gather_rows_kernel(double* dst, int64_t ldd, const double* src, int64_t lds,
+template <typename TS, typename TD>
+__global__ void gather_rows_kernel(TD* dst, int64_t ldd, const TS* src, int64_t lds,
                                    const int64_t* idx, int64_t nrows, int64_t ncols) {
   for (int64_t i = blockIdx.x; i < nrows; i += gridDim.x) {
-    const double* s = src + idx[i] * lds;
-    double* d = dst + i * ldd;
-    for (int64_t c = threadIdx.x; c < ncols; c += blockDim.x) d[c] = s[c];
+    const TS* s = src + idx[i] * lds;
+    TD* d = dst + i * ldd;
+    for (int64_t c = threadIdx.x; c < ncols; c += blockDim.x) d[c] = (TD)s[c];
   }
 }
-__global__ void scatter_rows_kernel(double* dst, int64_t ldd, const double* src, int64_t lds,
+template <typename TS, typename TD>
+__global__ void scatter_rows_kernel(TD* dst, int64_t ldd, const TS* src, int64_t lds,
                                     const int64_t* idx, int64_t nrows, int64_t ncols) {
   for (int64_t i = blockIdx.x; i < nrows; i += gridDim.x) {
-    const double* s = src + i * lds;
-    double* d = dst + idx[i] * ldd;
-    for (int64_t c = threadIdx.x; c < ncols; c += blockDim.x) d[c] = s[c];
+    const TS* s = src + i * lds;
+    TD* d = dst + idx[i] * ldd;
+    for (int64_t c = threadIdx.x; c < ncols; c += blockDim.x) d[c] = (TD)s[c];
   }
 }
 
-void gather_rows(hipStream_t st, double* dst, int64_t ldd, const double* src, int64_t lds,
+template <typename TS, typename TD>
+void gather_rows(hipStream_t st, TD* dst, int64_t ldd, const TS* src, int64_t lds,
                  const int64_t* idx, int64_t nrows, int64_t ncols) {
   if (nrows <= 0 || ncols <= 0) return;
   const unsigned g = (unsigned)std::min<int64_t>(nrows, 65535);
   const unsigned b = ncols >= 256 ? 256 : (ncols >= 64 ? 64 : 32);
-  ProfScope ps(st, "gather_rows", 0.0, 16.0 * nrows * ncols);
-  hipLaunchKernelGGL(gather_rows_kernel, dim3(g), dim3(b), 0, st, dst, ldd, src, lds, idx, nrows, ncols);
+  ProfScope ps(st, "gather_rows", 0.0, (double)(sizeof(TS) + sizeof(TD)) * nrows * ncols);
+  hipLaunchKernelGGL((gather_rows_kernel<TS, TD>), dim3(g), dim3(b), 0, st, dst, ldd, src, lds, idx, nrows, ncols);
 }
-void scatter_rows(hipStream_t st, double* dst, int64_t ldd, const double* src, int64_t lds,
+template <typename TS, typename TD>
+void scatter_rows(hipStream_t st, TD* dst, int64_t ldd, const TS* src, int64_t lds,
                   const int64_t* idx, int64_t nrows, int64_t ncols) {
   if (nrows <= 0 || ncols <= 0) return;
   const unsigned g = (unsigned)std::min<int64_t>(nrows, 65535);
   const unsigned b = ncols >= 256 ? 256 : (ncols >= 64 ? 64 : 32);
-  ProfScope ps(st, "scatter_rows", 0.0, 16.0 * nrows * ncols);
-  hipLaunchKernelGGL(scatter_rows_kernel, dim3(g), dim3(b), 0, st, dst, ldd, src, lds, idx, nrows, ncols);
+  ProfScope ps(st, "scatter_rows", 0.0, (double)(sizeof(TS) + sizeof(TD)) * nrows * ncols);
+  hipLaunchKernelGGL((scatter_rows_kernel<TS, TD>), dim3(g), dim3(b), 0, st, dst, ldd, src, lds, idx, nrows, ncols);
 }
+
+#define RSRS_PAIR(TS, TD)                                                                          \
+  template rsrs_status copy2d<TS, TD>(Uploader&, hipStream_t, const std::vector<Copy2DT<TS, TD>>&); \
+  template void gather_rows<TS, TD>(hipStream_t, TD*, int64_t, const TS*, int64_t, const int64_t*,  \
+                                    int64_t, int64_t);                                              \
+  template void scatter_rows<TS, TD>(hipStream_t, TD*, int64_t, const TS*, int64_t, const int64_t*, \
+                                     int64_t, int64_t);
+RSRS_PAIR(double, double)
+RSRS_PAIR(double, float)
+RSRS_PAIR(float, double)
+RSRS_PAIR(float, float)
+#undef RSRS_PAIR
 
 __global__ void fill_kernel(double* p, int64_t n, double v) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -595,21 +640,25 @@ void fill(hipStream_t st, double* p, int64_t n, double v) {
   hipLaunchKernelGGL(fill_kernel, dim3(g), dim3(256), 0, st, p, n, v);
 }
 
-__global__ void finite_kernel(const double* p, int64_t rows, int64_t cols, int64_t ld, int* flag) {
+template <typename T>
+__global__ void finite_kernel(const T* p, int64_t rows, int64_t cols, int64_t ld, int* flag) {
   bool bad = false;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < rows * cols;
        idx += (int64_t)gridDim.x * blockDim.x) {
-    const double v = p[(idx / cols) * ld + idx % cols];
+    const T v = p[(idx / cols) * ld + idx % cols];
     if (!isfinite(v)) bad = true;
   }
   if (bad) atomicOr(flag, 4);
 }
-void check_finite(hipStream_t st, const double* p, int64_t rows, int64_t cols, int64_t ld, int* flag) {
+template <typename T>
+void check_finite(hipStream_t st, const T* p, int64_t rows, int64_t cols, int64_t ld, int* flag) {
   if (rows <= 0 || cols <= 0) return;
   const unsigned g = (unsigned)std::min<int64_t>((rows * cols + 255) / 256, 8192);
-  ProfScope ps(st, "check_finite", 0.0, 8.0 * rows * cols);
-  hipLaunchKernelGGL(finite_kernel, dim3(g), dim3(256), 0, st, p, rows, cols, ld, flag);
+  ProfScope ps(st, "check_finite", 0.0, (double)sizeof(T) * rows * cols);
+  hipLaunchKernelGGL((finite_kernel<T>), dim3(g), dim3(256), 0, st, p, rows, cols, ld, flag);
 }
+template void check_finite<double>(hipStream_t, const double*, int64_t, int64_t, int64_t, int*);
+template void check_finite<float>(hipStream_t, const float*, int64_t, int64_t, int64_t, int*);
 
 // column sums of squares: stage 1 -> partial[g][w], stage 2 -> out[w]
 __global__ void colsq1_kernel(const double* x, int64_t n, int64_t w, int64_t ld, double* partial) {

@@ -22,6 +22,16 @@
 //           K_L = X_{SN,R} X_RR^{-1}; then the sketch updates of Algorithm 1:
 //           E, F (sparsify) followed by L, U (eliminate).
 //  root     A_t = Y_Bt pinv(Omega_Bt) by the same Gram route, then A_t^{-1}.
+//
+// Precision.  The whole class of operations is templated on the element type
+// T of the samples and of the stored factor.  T = double is plain FP64.  With
+// T = float (the mixed-precision factorization) every product of sketch-sized
+// operands runs on FP32 MFMA with FP32 accumulation, while the decisions stay
+// FP64: the Gram matrices are accumulated from FP32 operands straight into
+// FP64 storage and factored (Cholesky, inverse factor) in FP64, the pivoted
+// QR of the ID runs on an FP64 copy of M, and X_RR and A_t are inverted by
+// FP64 Gauss-Jordan with partial pivoting; the results are rounded to FP32
+// for the products that use them.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -101,43 +111,51 @@ struct Bump {
   }
 };
 
-// Workspace bytes of one box (b, l) in a class.
+// Workspace bytes of one box (b, l) in a class, samples of element type T.
+template <typename T>
 size_t box_ws_bytes(int64_t b, int64_t l, int64_t k, int64_t sp) {
+  constexpr bool mixed = sizeof(T) != sizeof(double);
   const int64_t lp = round_up(l, 16);
   const int64_t r = b - k;
   int64_t dbl = 4 * l * lp        // G, L for both sides
-                + 6 * b * lp      // P, W, X for both sides
-                + 2 * b * sp      // M_Y, M_Z
                 + 2 * b + b * k   // norms, R coefficients
-                + 4 * r * lp      // XR, Xp for both sides
                 + 2 * r * r;      // Gauss-Jordan work
+  int64_t tel = 6 * b * lp        // P, W, X for both sides
+                + 2 * b * sp      // M_Y, M_Z
+                + 4 * r * lp;     // XR, Xp for both sides
+  if (mixed) {
+    dbl += b * sp                 // FP64 copy of M for the ID
+           + r * round_up(k, 4)   // T as computed by the ID
+           + 2 * r * r;           // X_RR and its inverse in FP64
+    tel += 2 * l * lp;            // rounded inverse factors
+  }
   int64_t ints = b + k;           // sel, piv (int32)
   int64_t i64 = k + b;            // Spos, Rpos
-  return (size_t)(dbl * 8 + ints * 4 + i64 * 8 + 24 * 256);
+  return (size_t)(dbl * 8 + tel * sizeof(T) + ints * 4 + i64 * 8 + 32 * 256);
 }
 
+template <typename T>
 struct BoxWs {
   int64_t lp;
-  double *GO, *GP, *LO, *LP, *PY, *WY, *XY, *PZ, *WZ, *XZ, *MY, *MZ, *norms, *Rc;
-  double *XRy, *XRz, *Xpy, *Xpz, *gje;
+  double *GO, *GP, *LO, *LP, *norms, *Rc, *gje;
+  T *LOt, *LPt;                 // inverse factors in T (alias LO, LP when T = double)
+  T *PY, *WY, *XY, *PZ, *WZ, *XZ, *MY, *MZ;
+  T *XRy, *XRz, *Xpy, *Xpz;
+  double *Md, *Td, *XRRd, *Xinvd;   // FP64 copies (mixed precision only)
   int32_t *sel, *piv;
   int64_t *Spos, *Rpos;
 };
 
-}  // namespace
-
-rsrs_status factor_impl(const rsrs_tree_t* th, rsrs_samples_t* smp, const rsrs_factor_opts* o,
-                        hipStream_t st, rsrs_factor_t** out) {
+template <typename T>
+rsrs_status factor_t(const rsrs_tree_t* th, rsrs_samples_t* smp, const rsrs_factor_opts* o,
+                     hipStream_t st, rsrs_factor_t** out) {
+  constexpr bool mixed = sizeof(T) != sizeof(double);
+  constexpr int64_t al = 16 / (int64_t)sizeof(T);   // elements per 16 bytes
   auto t0 = std::chrono::steady_clock::now();
   const Tree& t = th->t;
   const int k = o->k;
   const int p = o->p < 0 ? k : o->p;
   const int reproject = o->reproject;
-  if (k < 1) { set_error("k must be >= 1"); return RSRS_E_INVALID; }
-  if (o->precision != RSRS_PREC_F64) { set_error("only RSRS_PREC_F64 is implemented"); return RSRS_E_UNSUPPORTED; }
-  if (smp->consumed) { set_error("samples were already consumed by a factorization"); return RSRS_E_INVALID; }
-  if (smp->tree != th) { set_error("samples belong to another tree"); return RSRS_E_INVALID; }
-  if (k > 256) { set_error("k > 256 is not supported"); return RSRS_E_UNSUPPORTED; }
   Schedule sch;
   make_schedule(t, k, sch);
   const int64_t need = samples_required(t, sch, k, p);
@@ -147,15 +165,17 @@ rsrs_status factor_impl(const rsrs_tree_t* th, rsrs_samples_t* smp, const rsrs_f
     return RSRS_E_SAMPLES;
   }
   const int64_t s = smp->s, sld = smp->ld, n = t.n;
-  double* Y = smp->Y.as<double>();
-  double* Z = smp->Z.as<double>();
-  double* Om = smp->Om.as<double>();
-  double* Psi = smp->Psi.as<double>();
+  T* Y = smp->Y.as<T>();
+  T* Z = smp->Z.as<T>();
+  T* Om = smp->Om.as<T>();
+  T* Psi = smp->Psi.as<T>();
 
   auto F = std::make_unique<rsrs_factor_t>();
   F->n = n;
   F->s = s;
   F->k = k;
+  F->precision = o->precision;
+  F->esz = (int)sizeof(T);
 
   // ---- storage layout from the schedule (sizes are fixed by the count model)
   int64_t dsz = 0, isz = 0;
@@ -174,20 +194,20 @@ rsrs_status factor_impl(const rsrs_tree_t* th, rsrs_samples_t* smp, const rsrs_f
         r.n = sch.l_count[b] - r.b;
         r.k = k;
         r.r = r.b - k;
-        r.ldT = round_up(k, 2);
-        r.ldR = round_up(r.r, 2);
-        r.ldKU = round_up(k + r.n, 2);
-        r.oT = round_up(dsz, 2); dsz = r.oT + r.r * r.ldT;
-        r.oXRR = round_up(dsz, 2); dsz = r.oXRR + r.r * r.ldR;
-        r.oXinv = round_up(dsz, 2); dsz = r.oXinv + r.r * r.ldR;
-        r.oKU = round_up(dsz, 2); dsz = r.oKU + r.r * r.ldKU;
-        r.oKL = round_up(dsz, 2); dsz = r.oKL + (k + r.n) * r.ldR;
+        r.ldT = round_up(k, al);
+        r.ldR = round_up(r.r, al);
+        r.ldKU = round_up(k + r.n, al);
+        r.oT = round_up(dsz, al); dsz = r.oT + r.r * r.ldT;
+        r.oXRR = round_up(dsz, al); dsz = r.oXRR + r.r * r.ldR;
+        r.oXinv = round_up(dsz, al); dsz = r.oXinv + r.r * r.ldR;
+        r.oKU = round_up(dsz, al); dsz = r.oKU + r.r * r.ldKU;
+        r.oKL = round_up(dsz, al); dsz = r.oKL + (k + r.n) * r.ldR;
         r.oR = isz; isz += r.r;
         r.oS = isz; isz += k;
         r.oNa = isz; isz += r.n;
         r.oBa = isz; isz += r.b + r.n;   // Ba followed by a second copy of Na
         F->boxes.push_back(r);
-        ws += box_ws_bytes(r.b, r.b + r.n, k, sld);
+        ws += box_ws_bytes<T>(r.b, r.b + r.n, k, sld);
       }
       g.count = (int64_t)F->boxes.size() - g.first;
       F->groups.push_back(g);
@@ -196,14 +216,16 @@ rsrs_status factor_impl(const rsrs_tree_t* th, rsrs_samples_t* smp, const rsrs_f
   }
   F->nt = sch.root_count;
   F->oBt = isz; isz += F->nt;
-  F->oAt = round_up(dsz, 2); dsz = F->oAt + F->nt * F->nt;
-  F->oAtinv = round_up(dsz, 2); dsz = F->oAtinv + F->nt * F->nt;
-  F->stored_doubles = dsz;
+  F->oAt = round_up(dsz, al); dsz = F->oAt + F->nt * F->nt;
+  F->oAtinv = round_up(dsz, al); dsz = F->oAtinv + F->nt * F->nt;
+  F->stored_values = dsz;
   const int64_t ntp = round_up(F->nt, 16);
-  const size_t root_ws = (size_t)(4 * F->nt * ntp + F->nt * round_up(s, 16) + 2 * F->nt * F->nt) * 8 + 8 * 256;
+  size_t root_ws = (size_t)(4 * F->nt * ntp + F->nt * round_up(s, 16) + 2 * F->nt * F->nt) * 8 + 8 * 256;
+  if (mixed)   // FP64 copies of Y_Bt, Omega_Bt, A_t, A_t^{-1}
+    root_ws += (size_t)(2 * F->nt * round_up(s, 16) + 2 * F->nt * F->nt) * 8 + 4 * 256;
   ws_max = std::max(ws_max, root_ws);
 
-  RSRS_TRY(F->dstore.alloc((size_t)std::max<int64_t>(dsz, 1) * 8));
+  RSRS_TRY(F->dstore.alloc((size_t)std::max<int64_t>(dsz, 1) * sizeof(T)));
   RSRS_TRY(F->istore.alloc((size_t)std::max<int64_t>(isz, 1) * 8));
   RSRS_TRY(F->perm.alloc((size_t)n * 8));
   DevBuf ws, flagbuf;
@@ -211,7 +233,7 @@ rsrs_status factor_impl(const rsrs_tree_t* th, rsrs_samples_t* smp, const rsrs_f
   RSRS_TRY(flagbuf.alloc(256));
   int* flag = flagbuf.as<int>();
   RSRS_HIP(hipMemsetAsync(flag, 0, sizeof(int), st));
-  double* dS = F->dstore.as<double>();
+  T* dS = F->dstore.as<T>();
   int64_t* iS = F->istore.as<int64_t>();
 
   Uploader up;
@@ -296,35 +318,45 @@ rsrs_status factor_impl(const rsrs_tree_t* th, rsrs_samples_t* smp, const rsrs_f
       }
       // ---- workspace
       Bump bump{ws.as<char>(), 0, ws.bytes};
-      std::vector<BoxWs> W(nb);
+      std::vector<BoxWs<T>> W(nb);
       for (int64_t q = 0; q < nb; ++q) {
         const BoxRec& R = F->boxes[g.first + q];
         const int64_t l = R.b + R.n, lp = round_up(l, 16), b = R.b, r = R.r;
-        BoxWs& w = W[q];
+        BoxWs<T>& w = W[q];
         w.lp = lp;
         w.GO = bump.take<double>(l * lp); w.GP = bump.take<double>(l * lp);
         w.LO = bump.take<double>(l * lp); w.LP = bump.take<double>(l * lp);
-        w.PY = bump.take<double>(b * lp); w.WY = bump.take<double>(b * lp); w.XY = bump.take<double>(b * lp);
-        w.PZ = bump.take<double>(b * lp); w.WZ = bump.take<double>(b * lp); w.XZ = bump.take<double>(b * lp);
-        w.MY = bump.take<double>(b * sld); w.MZ = bump.take<double>(b * sld);
+        w.PY = bump.take<T>(b * lp); w.WY = bump.take<T>(b * lp); w.XY = bump.take<T>(b * lp);
+        w.PZ = bump.take<T>(b * lp); w.WZ = bump.take<T>(b * lp); w.XZ = bump.take<T>(b * lp);
+        w.MY = bump.take<T>(b * sld); w.MZ = bump.take<T>(b * sld);
         w.norms = bump.take<double>(2 * b); w.Rc = bump.take<double>(b * k);
-        w.XRy = bump.take<double>(r * lp); w.XRz = bump.take<double>(r * lp);
-        w.Xpy = bump.take<double>(r * lp); w.Xpz = bump.take<double>(r * lp);
+        w.XRy = bump.take<T>(r * lp); w.XRz = bump.take<T>(r * lp);
+        w.Xpy = bump.take<T>(r * lp); w.Xpz = bump.take<T>(r * lp);
         w.gje = bump.take<double>(2 * r * r);
         w.sel = bump.take<int32_t>(b); w.piv = bump.take<int32_t>(k);
         w.Spos = bump.take<int64_t>(k); w.Rpos = bump.take<int64_t>(b);
+        if constexpr (mixed) {
+          w.LOt = bump.take<T>(l * lp); w.LPt = bump.take<T>(l * lp);
+          w.Md = bump.take<double>(b * sld);
+          w.Td = bump.take<double>(r * round_up(k, 4));
+          w.XRRd = bump.take<double>(r * r); w.Xinvd = bump.take<double>(r * r);
+        } else {
+          w.LOt = reinterpret_cast<T*>(w.LO); w.LPt = reinterpret_cast<T*>(w.LP);
+          w.Md = w.Td = w.XRRd = w.Xinvd = nullptr;
+        }
       }
-      // ---- phase A: Gram matrices
-      std::vector<GemmDesc> gd;
+      if (bump.off > bump.cap) { set_error("internal: workspace overflow"); return RSRS_E_INVALID; }
+      // ---- phase A: Gram matrices (FP64 storage in both precisions)
+      std::vector<GemmDescT<T, double>> gd;
       std::vector<CholMat> cm;
       int lmax = 0;
       for (int64_t q = 0; q < nb; ++q) {
         const BoxRec& R = F->boxes[g.first + q];
-        const BoxWs& w = W[q];
+        const BoxWs<T>& w = W[q];
         const int l = (int)(R.b + R.n);
         const int64_t* idxC = iS + R.oBa;
-        gd.push_back(gdesc(Om, idxC, sld, Om, idxC, sld, w.GO, nullptr, w.lp, l, l, (int)s));
-        gd.push_back(gdesc(Psi, idxC, sld, Psi, idxC, sld, w.GP, nullptr, w.lp, l, l, (int)s));
+        gd.push_back(gdescT<T, double>(Om, idxC, sld, Om, idxC, sld, w.GO, nullptr, w.lp, l, l, (int)s));
+        gd.push_back(gdescT<T, double>(Psi, idxC, sld, Psi, idxC, sld, w.GP, nullptr, w.lp, l, l, (int)s));
         cm.push_back(CholMat{w.GO, w.LO, w.lp, l});
         cm.push_back(CholMat{w.GP, w.LP, w.lp, l});
         lmax = std::max(lmax, l);
@@ -333,62 +365,88 @@ rsrs_status factor_impl(const rsrs_tree_t* th, rsrs_samples_t* smp, const rsrs_f
                  + 2.0 * (2.0 / 3.0) * dl * dl * dl               // Cholesky + inverse factor
                  + (1.0 + reproject) * 2.0 * (4.0 * db * dl * ds + 2.0 * db * dl * dl);  // projections
       }
-      RSRS_TRY(gemm(up, st, gd, 0, 1, GM_SYRK_L, GS_64x64, "gram"));
+      RSRS_TRY(gemm<T, double>(up, st, gd, 0, 1, GM_SYRK_L, GS_64x64, "gram"));
       RSRS_TRY(rchol(up, st, cm, 0, lmax, flag));
-      // ---- projections (eq. nullYZ) and least-squares coefficients
-      for (int pass = 0; pass <= reproject; ++pass) {
-        std::vector<GemmDesc> gp, gw, gx, gm;
-        std::vector<Copy2D> acc;
+      if constexpr (mixed) {   // inverse factors rounded for the FP32 products
+        std::vector<Copy2DT<double, T>> lc;
         for (int64_t q = 0; q < nb; ++q) {
           const BoxRec& R = F->boxes[g.first + q];
-          const BoxWs& w = W[q];
+          const BoxWs<T>& w = W[q];
+          const int l = (int)(R.b + R.n);
+          lc.push_back(Copy2DT<double, T>{w.LO, w.LOt, w.lp, w.lp, l, l, 1.0, 0, 0});
+          lc.push_back(Copy2DT<double, T>{w.LP, w.LPt, w.lp, w.lp, l, l, 1.0, 0, 0});
+        }
+        RSRS_TRY(copy2d<double, T>(up, st, lc));
+      }
+      // ---- projections (eq. nullYZ) and least-squares coefficients
+      for (int pass = 0; pass <= reproject; ++pass) {
+        std::vector<GemmDescT<T, T>> gp, gw, gx, gm;
+        std::vector<Copy2DT<T, T>> acc;
+        for (int64_t q = 0; q < nb; ++q) {
+          const BoxRec& R = F->boxes[g.first + q];
+          const BoxWs<T>& w = W[q];
           const int l = (int)(R.b + R.n), b = (int)R.b;
           const int64_t* idxB = iS + R.oBa;
           const int64_t* idxC = iS + R.oBa;
           for (int side = 0; side < 2; ++side) {
-            double* Ysd = side ? Z : Y;
-            double* Tst = side ? Psi : Om;
-            double* Pb = side ? w.PZ : w.PY;
-            double* Wb = side ? w.WZ : w.WY;
-            double* Xb = side ? w.XZ : w.XY;
-            double* Mb = side ? w.MZ : w.MY;
-            double* Lb = side ? w.LP : w.LO;
-            double* Xout = pass == 0 ? Xb : Pb;   // second pass: correction into P
+            T* Ysd = side ? Z : Y;
+            T* Tst = side ? Psi : Om;
+            T* Pb = side ? w.PZ : w.PY;
+            T* Wb = side ? w.WZ : w.WY;
+            T* Xb = side ? w.XZ : w.XY;
+            T* Mb = side ? w.MZ : w.MY;
+            T* Lb = side ? w.LPt : w.LOt;
+            T* Xout = pass == 0 ? Xb : Pb;   // second pass: correction into P
             if (pass == 0)
-              gp.push_back(gdesc(Ysd, idxB, sld, Tst, idxC, sld, Pb, nullptr, w.lp, b, l, (int)s));
+              gp.push_back(gdescT<T, T>(Ysd, idxB, sld, Tst, idxC, sld, Pb, nullptr, w.lp, b, l, (int)s));
             else
-              gp.push_back(gdesc(Mb, nullptr, sld, Tst, idxC, sld, Pb, nullptr, w.lp, b, l, (int)s));
-            gw.push_back(gdesc(Pb, nullptr, w.lp, Lb, nullptr, w.lp, Wb, nullptr, w.lp, b, l, l));
-            gx.push_back(gdesc(Wb, nullptr, w.lp, Lb, nullptr, w.lp, Xout, nullptr, w.lp, b, l, l));
+              gp.push_back(gdescT<T, T>(Mb, nullptr, sld, Tst, idxC, sld, Pb, nullptr, w.lp, b, l, (int)s));
+            gw.push_back(gdescT<T, T>(Pb, nullptr, w.lp, Lb, nullptr, w.lp, Wb, nullptr, w.lp, b, l, l));
+            gx.push_back(gdescT<T, T>(Wb, nullptr, w.lp, Lb, nullptr, w.lp, Xout, nullptr, w.lp, b, l, l));
             if (pass == 0)
-              gm.push_back(gdesc(Xout, nullptr, w.lp, Tst, idxC, sld, Mb, nullptr, sld, b, (int)s, l,
-                                 -1.0, 1.0, Ysd, idxB, sld));
+              gm.push_back(gdescT<T, T>(Xout, nullptr, w.lp, Tst, idxC, sld, Mb, nullptr, sld, b, (int)s, l,
+                                        -1.0, 1.0, Ysd, idxB, sld));
             else
-              gm.push_back(gdesc(Xout, nullptr, w.lp, Tst, idxC, sld, Mb, nullptr, sld, b, (int)s, l,
-                                 -1.0, 1.0));
-            if (pass == 1) acc.push_back(Copy2D{Pb, Xb, w.lp, w.lp, b, l, 1.0, 1, 0});
+              gm.push_back(gdescT<T, T>(Xout, nullptr, w.lp, Tst, idxC, sld, Mb, nullptr, sld, b, (int)s, l,
+                                        -1.0, 1.0));
+            if (pass == 1) acc.push_back(Copy2DT<T, T>{Pb, Xb, w.lp, w.lp, b, l, 1.0, 1, 0});
           }
         }
-        RSRS_TRY(gemm(up, st, gp, 0, 1, GM_FULL, GS_64x64, "proj"));
-        RSRS_TRY(gemm(up, st, gw, 0, 1, GM_B_NT_LOW, GS_64x64, "proj"));
-        RSRS_TRY(gemm(up, st, gx, 0, 0, GM_B_NN_LOW, GS_64x64, "proj"));
-        RSRS_TRY(gemm(up, st, gm, 0, 0, GM_FULL, GS_64x64, "proj"));
-        RSRS_TRY(copy2d(up, st, acc));
+        RSRS_TRY(gemm<T, T>(up, st, gp, 0, 1, GM_FULL, GS_64x64, "proj"));
+        RSRS_TRY(gemm<T, T>(up, st, gw, 0, 1, GM_B_NT_LOW, GS_64x64, "proj"));
+        RSRS_TRY(gemm<T, T>(up, st, gx, 0, 0, GM_B_NN_LOW, GS_64x64, "proj"));
+        RSRS_TRY(gemm<T, T>(up, st, gm, 0, 0, GM_FULL, GS_64x64, "proj"));
+        RSRS_TRY(copy2d<T, T>(up, st, acc));
       }
       // ---- interpolative decomposition of M = M_Y + M_Z
       std::vector<IdDesc> idd;
       for (int64_t q = 0; q < nb; ++q) {
         const BoxRec& R = F->boxes[g.first + q];
-        const BoxWs& w = W[q];
+        const BoxWs<T>& w = W[q];
         IdDesc e{};
-        e.M = w.MY; e.MZ = w.MZ; e.ldm = sld; e.ldz = sld;
+        if constexpr (mixed) {
+          e.M = w.Md; e.MZ = nullptr; e.ldm = sld; e.ldz = sld;
+          e.MYf = w.MY; e.MZf = w.MZ; e.ldf = sld;
+          e.T = w.Td; e.ldt = (int)round_up(k, 4);
+        } else {
+          e.M = w.MY; e.MZ = w.MZ; e.ldm = sld; e.ldz = sld;
+          e.T = dS + R.oT; e.ldt = (int)R.ldT;
+        }
         e.norms = w.norms; e.sel = w.sel; e.Rc = w.Rc; e.piv = w.piv;
-        e.Spos = w.Spos; e.Rpos = w.Rpos; e.T = dS + R.oT;
-        e.b = (int)R.b; e.s = (int)s; e.k = k; e.ldt = (int)R.ldT;
+        e.Spos = w.Spos; e.Rpos = w.Rpos;
+        e.b = (int)R.b; e.s = (int)s; e.k = k;
         idd.push_back(e);
         flops += 4.0 * R.b * s * k;
       }
       RSRS_TRY(id_run(up, st, idd));
+      if constexpr (mixed) {   // T rounded into the factor store
+        std::vector<Copy2DT<double, T>> tc;
+        for (int64_t q = 0; q < nb; ++q) {
+          const BoxRec& R = F->boxes[g.first + q];
+          tc.push_back(Copy2DT<double, T>{W[q].Td, dS + R.oT, round_up(k, 4), R.ldT, (int)R.r, k, 1.0, 0, 0});
+        }
+        RSRS_TRY(copy2d<double, T>(up, st, tc));
+      }
       // ---- skeleton sets back to the host
       int64_t nposn = 0;
       for (int64_t q = 0; q < nb; ++q) nposn += F->boxes[g.first + q].b;
@@ -428,69 +486,79 @@ rsrs_status factor_impl(const rsrs_tree_t* th, rsrs_samples_t* smp, const rsrs_f
           o2 += R.b;
         }
       }
-      std::vector<GemmDesc> gxr;
-      std::vector<ColfixDesc> cf;
-      std::vector<Copy2D> cx;
+      std::vector<GemmDescT<T, T>> gxr;
+      std::vector<ColfixDescT<T>> cf;
+      std::vector<Copy2DT<T, T>> cx;
+      std::vector<Copy2DT<T, double>> cxd;
+      std::vector<Copy2DT<double, T>> cinv;
       std::vector<GjeDesc> gj;
       for (int64_t q = 0; q < nb; ++q) {
         const BoxRec& R = F->boxes[g.first + q];
-        const BoxWs& w = W[q];
+        const BoxWs<T>& w = W[q];
         const int l = (int)(R.b + R.n), r = (int)R.r;
         for (int side = 0; side < 2; ++side) {
-          double* Xb = side ? w.XZ : w.XY;
-          double* XR = side ? w.XRz : w.XRy;
-          double* Xp = side ? w.Xpz : w.Xpy;
-          gxr.push_back(gdesc(dS + R.oT, nullptr, R.ldT, Xb, w.Spos, w.lp, XR, nullptr, w.lp, r, l, k,
-                              -1.0, 1.0, Xb, w.Rpos, w.lp));
-          cf.push_back(ColfixDesc{XR, w.Spos, w.Rpos, dS + R.oT, Xp, w.lp, w.lp, R.ldT, r, k, (int)R.b, l});
+          T* Xb = side ? w.XZ : w.XY;
+          T* XR = side ? w.XRz : w.XRy;
+          T* Xp = side ? w.Xpz : w.Xpy;
+          gxr.push_back(gdescT<T, T>(dS + R.oT, nullptr, R.ldT, Xb, w.Spos, w.lp, XR, nullptr, w.lp, r, l, k,
+                                     -1.0, 1.0, Xb, w.Rpos, w.lp));
+          cf.push_back(ColfixDescT<T>{XR, w.Spos, w.Rpos, dS + R.oT, Xp, w.lp, w.lp, R.ldT, r, k, (int)R.b, l});
         }
-        cx.push_back(Copy2D{w.Xpy, dS + R.oXRR, w.lp, R.ldR, r, r, 1.0, 0, 0});
-        gj.push_back(GjeDesc{w.Xpy, w.gje, dS + R.oXinv, w.lp, R.ldR, r, 0});
+        cx.push_back(Copy2DT<T, T>{w.Xpy, dS + R.oXRR, w.lp, R.ldR, r, r, 1.0, 0, 0});
+        if constexpr (mixed) {   // FP64 Gauss-Jordan on X_RR, inverse rounded
+          cxd.push_back(Copy2DT<T, double>{w.Xpy, w.XRRd, w.lp, r, r, r, 1.0, 0, 0});
+          gj.push_back(GjeDesc{w.XRRd, w.gje, w.Xinvd, r, r, r, 0});
+          cinv.push_back(Copy2DT<double, T>{w.Xinvd, dS + R.oXinv, r, R.ldR, r, r, 1.0, 0, 0});
+        } else {
+          gj.push_back(GjeDesc{w.Xpy, w.gje, dS + R.oXinv, w.lp, R.ldR, r, 0});
+        }
         const double dr = r, dk = k, dn = (double)R.n, ds = (double)s;
         flops += 2.0 * (2.0 * dr * dk * l + 2.0 * dr * dr * dk) + 2.0 * dr * dr * dr +
                  2.0 * 2.0 * dr * dr * (dk + dn) + 4.0 * 2.0 * dr * dk * ds + 4.0 * 2.0 * dr * (dk + dn) * ds;
       }
-      RSRS_TRY(gemm(up, st, gxr, 0, 0, GM_FULL, GS_64x64, "extract"));
-      RSRS_TRY(colfix(up, st, cf));
-      RSRS_TRY(copy2d(up, st, cx));
+      RSRS_TRY(gemm<T, T>(up, st, gxr, 0, 0, GM_FULL, GS_64x64, "extract"));
+      RSRS_TRY(colfix<T>(up, st, cf));
+      RSRS_TRY(copy2d<T, T>(up, st, cx));
+      RSRS_TRY(copy2d<T, double>(up, st, cxd));
       RSRS_TRY(gje_inverse(up, st, gj, flag));
-      std::vector<GemmDesc> gku, gkl;
+      RSRS_TRY(copy2d<double, T>(up, st, cinv));
+      std::vector<GemmDescT<T, T>> gku, gkl;
       for (int64_t q = 0; q < nb; ++q) {
         const BoxRec& R = F->boxes[g.first + q];
-        const BoxWs& w = W[q];
+        const BoxWs<T>& w = W[q];
         const int r = (int)R.r, kn = (int)(k + R.n);
-        gku.push_back(gdesc(dS + R.oXinv, nullptr, R.ldR, w.Xpy + r, nullptr, w.lp, dS + R.oKU, nullptr, R.ldKU, r, kn, r));
-        gkl.push_back(gdesc(w.Xpz + r, nullptr, w.lp, dS + R.oXinv, nullptr, R.ldR, dS + R.oKL, nullptr, R.ldR, kn, r, r));
+        gku.push_back(gdescT<T, T>(dS + R.oXinv, nullptr, R.ldR, w.Xpy + r, nullptr, w.lp, dS + R.oKU, nullptr, R.ldKU, r, kn, r));
+        gkl.push_back(gdescT<T, T>(w.Xpz + r, nullptr, w.lp, dS + R.oXinv, nullptr, R.ldR, dS + R.oKL, nullptr, R.ldR, kn, r, r));
       }
-      RSRS_TRY(gemm(up, st, gku, 0, 0, GM_FULL, GS_64x64, "mult"));
-      RSRS_TRY(gemm(up, st, gkl, 1, 0, GM_FULL, GS_64x64, "mult"));
+      RSRS_TRY(gemm<T, T>(up, st, gku, 0, 0, GM_FULL, GS_64x64, "mult"));
+      RSRS_TRY(gemm<T, T>(up, st, gkl, 1, 0, GM_FULL, GS_64x64, "mult"));
       // ---- sketch updates: sparsify (E, F) then eliminate (L, U)
-      std::vector<GemmDesc> s0, s1, e0, e1, e0b, e1b;
+      std::vector<GemmDescT<T, T>> s0, s1, e0, e1, e0b, e1b;
       for (int64_t q = 0; q < nb; ++q) {
         const BoxRec& R = F->boxes[g.first + q];
         const int r = (int)R.r, kn = (int)(k + R.n);
         const int64_t* gR = iS + R.oR;
         const int64_t* gS = iS + R.oS;
         const int64_t* gSN = iS + R.oS;
-        const double* T = dS + R.oT;
-        const double* KU = dS + R.oKU;
-        const double* KL = dS + R.oKL;
+        const T* Tm = dS + R.oT;
+        const T* KU = dS + R.oKU;
+        const T* KL = dS + R.oKL;
         const int64_t lT = R.ldT, lR = R.ldR, lU = R.ldKU;
-        s0.push_back(gdesc(T, nullptr, lT, Y, gS, sld, Y, gR, sld, r, (int)s, k, -1.0, 1.0));
-        s0.push_back(gdesc(T, nullptr, lT, Z, gS, sld, Z, gR, sld, r, (int)s, k, -1.0, 1.0));
-        s1.push_back(gdesc(T, nullptr, lT, Om, gR, sld, Om, gS, sld, k, (int)s, r, 1.0, 1.0));
-        s1.push_back(gdesc(T, nullptr, lT, Psi, gR, sld, Psi, gS, sld, k, (int)s, r, 1.0, 1.0));
-        e0.push_back(gdesc(KL, nullptr, lR, Y, gR, sld, Y, gSN, sld, kn, (int)s, r, -1.0, 1.0));
-        e0b.push_back(gdesc(KU, nullptr, lU, Om, gSN, sld, Om, gR, sld, r, (int)s, kn, 1.0, 1.0));
-        e1.push_back(gdesc(KU, nullptr, lU, Z, gR, sld, Z, gSN, sld, kn, (int)s, r, -1.0, 1.0));
-        e1b.push_back(gdesc(KL, nullptr, lR, Psi, gSN, sld, Psi, gR, sld, r, (int)s, kn, 1.0, 1.0));
+        s0.push_back(gdescT<T, T>(Tm, nullptr, lT, Y, gS, sld, Y, gR, sld, r, (int)s, k, -1.0, 1.0));
+        s0.push_back(gdescT<T, T>(Tm, nullptr, lT, Z, gS, sld, Z, gR, sld, r, (int)s, k, -1.0, 1.0));
+        s1.push_back(gdescT<T, T>(Tm, nullptr, lT, Om, gR, sld, Om, gS, sld, k, (int)s, r, 1.0, 1.0));
+        s1.push_back(gdescT<T, T>(Tm, nullptr, lT, Psi, gR, sld, Psi, gS, sld, k, (int)s, r, 1.0, 1.0));
+        e0.push_back(gdescT<T, T>(KL, nullptr, lR, Y, gR, sld, Y, gSN, sld, kn, (int)s, r, -1.0, 1.0));
+        e0b.push_back(gdescT<T, T>(KU, nullptr, lU, Om, gSN, sld, Om, gR, sld, r, (int)s, kn, 1.0, 1.0));
+        e1.push_back(gdescT<T, T>(KU, nullptr, lU, Z, gR, sld, Z, gSN, sld, kn, (int)s, r, -1.0, 1.0));
+        e1b.push_back(gdescT<T, T>(KL, nullptr, lR, Psi, gSN, sld, Psi, gR, sld, r, (int)s, kn, 1.0, 1.0));
       }
-      RSRS_TRY(gemm(up, st, s0, 0, 0, GM_FULL, GS_64x64, "sparsify"));
-      RSRS_TRY(gemm(up, st, s1, 1, 0, GM_FULL, GS_64x64, "sparsify"));
-      RSRS_TRY(gemm(up, st, e0, 0, 0, GM_FULL, GS_64x64, "elim"));
-      RSRS_TRY(gemm(up, st, e1, 1, 0, GM_FULL, GS_64x64, "elim"));
-      RSRS_TRY(gemm(up, st, e0b, 0, 0, GM_FULL, GS_64x64, "elim_r"));
-      RSRS_TRY(gemm(up, st, e1b, 1, 0, GM_FULL, GS_64x64, "elim_r"));
+      RSRS_TRY(gemm<T, T>(up, st, s0, 0, 0, GM_FULL, GS_64x64, "sparsify"));
+      RSRS_TRY(gemm<T, T>(up, st, s1, 1, 0, GM_FULL, GS_64x64, "sparsify"));
+      RSRS_TRY(gemm<T, T>(up, st, e0, 0, 0, GM_FULL, GS_64x64, "elim"));
+      RSRS_TRY(gemm<T, T>(up, st, e1, 1, 0, GM_FULL, GS_64x64, "elim"));
+      RSRS_TRY(gemm<T, T>(up, st, e0b, 0, 0, GM_FULL, GS_64x64, "elim_r"));
+      RSRS_TRY(gemm<T, T>(up, st, e1b, 1, 0, GM_FULL, GS_64x64, "elim_r"));
     }
     for (int64_t b : lb) remaining[b] = cur[b];
   }
@@ -517,20 +585,48 @@ rsrs_status factor_impl(const rsrs_tree_t* th, rsrs_samples_t* smp, const rsrs_f
     double* Wb = bump.take<double>(nt * ntp);
     double* Rres = bump.take<double>(nt * round_up(s, 16));
     double* gw = bump.take<double>(2 * (int64_t)nt * nt);
-    double* At = dS + F->oAt;
-    RSRS_TRY(gemm(up, st, {gdesc(Om, iBt, sld, Om, iBt, sld, G, nullptr, ntp, nt, nt, (int)s)}, 0, 1, GM_SYRK_L));
+    // FP64 operands of the root: the samples themselves (rows iBt), or FP64
+    // copies of the rows B_t in mixed precision
+    const double* Yr;
+    const double* Or;
+    const int64_t* ir;
+    int64_t rld;
+    double* At;
+    double* Atinv;
+    if constexpr (mixed) {
+      const int64_t sp = round_up(s, 16);
+      double* Yd = bump.take<double>(nt * sp);
+      double* Od = bump.take<double>(nt * sp);
+      At = bump.take<double>((int64_t)nt * nt);
+      Atinv = bump.take<double>((int64_t)nt * nt);
+      gather_rows<T, double>(st, Yd, sp, Y, sld, iBt, nt, s);
+      gather_rows<T, double>(st, Od, sp, Om, sld, iBt, nt, s);
+      Yr = Yd; Or = Od; ir = nullptr; rld = sp;
+    } else {
+      Yr = reinterpret_cast<const double*>(Y);
+      Or = reinterpret_cast<const double*>(Om);
+      ir = iBt; rld = sld;
+      At = reinterpret_cast<double*>(dS + F->oAt);
+      Atinv = reinterpret_cast<double*>(dS + F->oAtinv);
+    }
+    if (bump.off > bump.cap) { set_error("internal: root workspace overflow"); return RSRS_E_INVALID; }
+    RSRS_TRY(gemm(up, st, {gdesc(Or, ir, rld, Or, ir, rld, G, nullptr, ntp, nt, nt, (int)s)}, 0, 1, GM_SYRK_L));
     RSRS_TRY(rchol(up, st, {CholMat{G, L, ntp, nt}}, 0, nt, flag));
-    RSRS_TRY(gemm(up, st, {gdesc(Y, iBt, sld, Om, iBt, sld, P, nullptr, ntp, nt, nt, (int)s)}, 0, 1, GM_FULL));
+    RSRS_TRY(gemm(up, st, {gdesc(Yr, ir, rld, Or, ir, rld, P, nullptr, ntp, nt, nt, (int)s)}, 0, 1, GM_FULL));
     RSRS_TRY(gemm(up, st, {gdesc(P, nullptr, ntp, L, nullptr, ntp, Wb, nullptr, ntp, nt, nt, nt)}, 0, 1, GM_B_NT_LOW));
     RSRS_TRY(gemm(up, st, {gdesc(Wb, nullptr, ntp, L, nullptr, ntp, At, nullptr, nt, nt, nt, nt)}, 0, 0, GM_B_NN_LOW));
     if (reproject) {
       const int64_t rp = round_up(s, 16);
-      RSRS_TRY(gemm(up, st, {gdesc(At, nullptr, nt, Om, iBt, sld, Rres, nullptr, rp, nt, (int)s, nt, -1.0, 1.0, Y, iBt, sld)}, 0, 0, GM_FULL));
-      RSRS_TRY(gemm(up, st, {gdesc(Rres, nullptr, rp, Om, iBt, sld, P, nullptr, ntp, nt, nt, (int)s)}, 0, 1, GM_FULL));
+      RSRS_TRY(gemm(up, st, {gdesc(At, nullptr, nt, Or, ir, rld, Rres, nullptr, rp, nt, (int)s, nt, -1.0, 1.0, Yr, ir, rld)}, 0, 0, GM_FULL));
+      RSRS_TRY(gemm(up, st, {gdesc(Rres, nullptr, rp, Or, ir, rld, P, nullptr, ntp, nt, nt, (int)s)}, 0, 1, GM_FULL));
       RSRS_TRY(gemm(up, st, {gdesc(P, nullptr, ntp, L, nullptr, ntp, Wb, nullptr, ntp, nt, nt, nt)}, 0, 1, GM_B_NT_LOW));
       RSRS_TRY(gemm(up, st, {gdesc(Wb, nullptr, ntp, L, nullptr, ntp, At, nullptr, nt, nt, nt, nt, 1.0, 1.0)}, 0, 0, GM_B_NN_LOW));
     }
-    RSRS_TRY(gje_inverse(up, st, {GjeDesc{At, gw, dS + F->oAtinv, nt, nt, nt, 0}}, flag));
+    RSRS_TRY(gje_inverse(up, st, {GjeDesc{At, gw, Atinv, nt, nt, nt, 0}}, flag));
+    if constexpr (mixed) {
+      RSRS_TRY(copy2d<double, T>(up, st, {Copy2DT<double, T>{At, dS + F->oAt, nt, nt, nt, nt, 1.0, 0, 0},
+                                          Copy2DT<double, T>{Atinv, dS + F->oAtinv, nt, nt, nt, nt, 1.0, 0, 0}}));
+    }
     const double dt = nt;
     flops += dt * dt * s + (2.0 / 3.0) * dt * dt * dt + (1 + reproject) * (2.0 * dt * dt * s + 2.0 * dt * dt * dt) + 2.0 * dt * dt * dt;
   }
@@ -546,6 +642,28 @@ rsrs_status factor_impl(const rsrs_tree_t* th, rsrs_samples_t* smp, const rsrs_f
   F->factor_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   *out = F.release();
   return RSRS_OK;
+}
+
+}  // namespace
+
+rsrs_status factor_impl(const rsrs_tree_t* th, rsrs_samples_t* smp, const rsrs_factor_opts* o,
+                        hipStream_t st, rsrs_factor_t** out) {
+  const int k = o->k;
+  if (k < 1) { set_error("k must be >= 1"); return RSRS_E_INVALID; }
+  if (smp->consumed) { set_error("samples were already consumed by a factorization"); return RSRS_E_INVALID; }
+  if (smp->tree != th) { set_error("samples belong to another tree"); return RSRS_E_INVALID; }
+  if (k > 256) { set_error("k > 256 is not supported"); return RSRS_E_UNSUPPORTED; }
+  if (o->reproject < 0 || o->reproject > 1) { set_error("reproject must be 0 or 1"); return RSRS_E_INVALID; }
+  if (o->precision == RSRS_PREC_F64) {
+    if (smp->dtype != RSRS_F64) { set_error("FP64 factorization needs FP64 samples"); return RSRS_E_INVALID; }
+    return factor_t<double>(th, smp, o, st, out);
+  }
+  if (o->precision == RSRS_PREC_F32_MIXED) {
+    if (smp->dtype != RSRS_F32) { set_error("mixed-precision factorization needs FP32 samples"); return RSRS_E_INVALID; }
+    return factor_t<float>(th, smp, o, st, out);
+  }
+  set_error("unknown precision");
+  return RSRS_E_UNSUPPORTED;
 }
 
 }  // namespace rsrs

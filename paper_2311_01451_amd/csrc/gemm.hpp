@@ -1,6 +1,11 @@
-// Batched FP64 GEMM on CDNA MFMA (v_mfma_f64_16x16x4f64) with row gathers.
+// Batched GEMM on CDNA MFMA with row gathers, FP64 (v_mfma_f64_16x16x4f64)
+// or FP32 (v_mfma_f32_16x16x4f32, FP32 accumulation).
 //
 //   C[ic(m), n] = alpha * sum_kk A(m, kk) B(kk, n) + beta * Cin[icin(m), n]
+//
+// Operands A, B have element type TI (double or float, which also selects
+// the MFMA); C and Cin have element type TO (double or float), so an FP32
+// product can be written straight into FP64 storage.
 //
 // Operand forms (compile time):
 //   TA = 0 : A(m, kk) = A[ia(m)  * lda + kk]   (rows gathered, K contiguous)
@@ -20,10 +25,10 @@
 // and each holds (BM/WM/16) x (BN/WN/16) 16x16 FP64 accumulator blocks.  The
 // K loop is software pipelined: the next BK-slice of A and B is fetched into
 // registers while the current one is multiplied out of LDS, and LDS is double
-// buffered so one barrier per slice suffices.  With VEC = 2 every global
-// access is a 16-byte load along the operand's contiguous dimension (the host
-// selects it only when all leading dimensions are even and all base pointers
-// 16-byte aligned).  The batch index is blockIdx.y;
+// buffered so one barrier per slice suffices.  With VEC = 16 / sizeof(TI)
+// every global access is a 16-byte load along the operand's contiguous
+// dimension (the host selects it only when all leading dimensions are
+// multiples of VEC and all base pointers 16-byte aligned).  The batch index is blockIdx.y;
 // blockIdx.x enumerates tiles of the largest entry and entries with fewer
 // tiles return early.  Consecutive workgroups land on different XCDs, so the
 // tile index is remapped to give each XCD a contiguous range of tiles (rows of
@@ -35,26 +40,66 @@
 
 namespace rsrs {
 
-struct GemmDesc {
-  const double* A;
+template <typename TI, typename TO>
+struct GemmDescT {
+  const TI* A;
   const int64_t* ia;
-  const double* B;
+  const TI* B;
   const int64_t* ib;
-  const double* Cin;
+  const TO* Cin;
   const int64_t* icin;
-  double* C;
+  TO* C;
   const int64_t* ic;
   int64_t lda, ldb, ldcin, ldc;
   int M, N, K, pad_;
   double alpha, beta;
 };
+using GemmDesc = GemmDescT<double, double>;
 
 enum GemmMode { GM_FULL = 0, GM_SYRK_L = 1, GM_B_NT_LOW = 2, GM_B_NN_LOW = 3, GM_A_LOW = 4 };
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 
-template <int BM, int BN, int WM, int WN, int TA, int TB, int MODE, int VEC>
-__global__ __launch_bounds__(64 * WM * WN) void gemm_f64_kernel(const GemmDesc* __restrict__ descs) {
+// Per element type: accumulator, MFMA and the row of result register v of a
+// lane in row group q = lane / 16 (the FP64 instruction interleaves the rows
+// differently from the FP32 one; both checked by probes on gfx950).
+template <typename TI> struct Mfma;
+template <> struct Mfma<double> {
+  using acc_t = v4d;
+  static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int v, int q) { return 4 * v + q; }
+};
+template <> struct Mfma<float> {
+  using acc_t = v4f;
+  static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int v, int q) { return 4 * q + v; }
+};
+
+// 16-byte load of VEC consecutive elements (VEC * sizeof(T) == 16).
+template <typename T, int VEC>
+__device__ __forceinline__ void load16(const T* p, T (&out)[VEC]) {
+  if constexpr (sizeof(T) == 8) {
+    const double2 v = *reinterpret_cast<const double2*>(p);
+    out[0] = v.x;
+    out[VEC - 1] = v.y;
+  } else {
+    const float4 v = *reinterpret_cast<const float4*>(p);
+    out[0] = v.x;
+    out[1 % VEC] = v.y;
+    out[2 % VEC] = v.z;
+    out[3 % VEC] = v.w;
+  }
+}
+
+template <typename TI, typename TO, int BM, int BN, int WM, int WN, int TA, int TB, int MODE, int VEC>
+__global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmDescT<TI, TO>* __restrict__ descs) {
+  using acc_t = typename Mfma<TI>::acc_t;
+  constexpr int VW = 16 / (int)sizeof(TI);   // elements per 16-byte load
   constexpr int NT = 64 * WM * WN;    // threads per workgroup
   constexpr int BK = 16;
   constexpr int PA = BM + 2;
@@ -67,10 +112,11 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_f64_kernel(const GemmDesc* 
   static_assert(FM >= 1 && FN >= 1, "tile too small");
   static_assert(NA >= 1 && NB >= 1 && NA * NT * VEC == BM * BK && NB * NT * VEC == BN * BK,
                 "tile split");
-  __shared__ double As[2][BK * PA];
-  __shared__ double Bs[2][BK * PB];
+  static_assert(VEC == 1 || VEC == VW, "VEC is 1 or one 16-byte load");
+  __shared__ TI As[2][BK * PA];
+  __shared__ TI Bs[2][BK * PB];
 
-  const GemmDesc d = descs[blockIdx.y];
+  const GemmDescT<TI, TO> d = descs[blockIdx.y];
   const int tm = (d.M + BM - 1) / BM;
   const int tn = (d.N + BN - 1) / BN;
   // SYRK_L (M == N, BM == BN) enumerates only the lower-triangle tiles
@@ -106,8 +152,8 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_f64_kernel(const GemmDesc* 
   // Fetch coordinates (fixed across slices).  Each thread reads VEC
   // consecutive elements along the contiguous dimension of its operand.
   int am[NA], ak[NA], bn_[NB], bk[NB];
-  const double* arowp[NA];
-  const double* browp[NB];
+  const TI* arowp[NA];
+  const TI* browp[NB];
 #pragma unroll
   for (int q = 0; q < NA; ++q) {
     const int e = (tid + q * NT) * VEC;
@@ -139,7 +185,7 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_f64_kernel(const GemmDesc* 
     bnext[q] = (TB == 0 && gk < kend) ? (d.ib ? d.ib[gk] : (int64_t)gk) : 0;
   }
 
-  double ra[NA][VEC], rb[NB][VEC];
+  TI ra[NA][VEC], rb[NB][VEC];
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < NA; ++q) {
@@ -148,31 +194,27 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_f64_kernel(const GemmDesc* 
         // VEC consecutive k of row gm
         bool full = gm < d.M && gk + VEC - 1 < kend;
         if (MODE == GM_A_LOW) full = full && gk + VEC - 1 <= gm;
-        if (VEC == 2 && full) {
-          const double2 v = *reinterpret_cast<const double2*>(arowp[q] + gk);
-          ra[q][0] = v.x;
-          ra[q][VEC - 1] = v.y;
+        if (VEC > 1 && full) {
+          load16<TI, VEC>(arowp[q] + gk, ra[q]);
         } else {
 #pragma unroll
           for (int u = 0; u < VEC; ++u) {
             bool ok = gm < d.M && gk + u < kend;
             if (MODE == GM_A_LOW) ok = ok && gk + u <= gm;
-            ra[q][u] = ok ? arowp[q][gk + u] : 0.0;
+            ra[q][u] = ok ? arowp[q][gk + u] : TI(0);
           }
         }
       } else {
         // VEC consecutive m of row gk (A stored K x M)
         const bool rowok = gk < kend;
-        const double* rp = d.A + anext[q] * d.lda;
+        const TI* rp = d.A + anext[q] * d.lda;
         const int gk2 = gk + BK;
         anext[q] = gk2 < kend ? (d.ia ? d.ia[gk2] : (int64_t)gk2) : 0;
-        if (VEC == 2 && rowok && gm + VEC - 1 < d.M) {
-          const double2 v = *reinterpret_cast<const double2*>(rp + gm);
-          ra[q][0] = v.x;
-          ra[q][VEC - 1] = v.y;
+        if (VEC > 1 && rowok && gm + VEC - 1 < d.M) {
+          load16<TI, VEC>(rp + gm, ra[q]);
         } else {
 #pragma unroll
-          for (int u = 0; u < VEC; ++u) ra[q][u] = (rowok && gm + u < d.M) ? rp[gm + u] : 0.0;
+          for (int u = 0; u < VEC; ++u) ra[q][u] = (rowok && gm + u < d.M) ? rp[gm + u] : TI(0);
         }
       }
     }
@@ -183,36 +225,32 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_f64_kernel(const GemmDesc* 
         // VEC consecutive k of row gn
         bool full = gn < d.N && gk + VEC - 1 < kend;
         if (MODE == GM_B_NT_LOW) full = full && gk + VEC - 1 <= gn;
-        if (VEC == 2 && full) {
-          const double2 v = *reinterpret_cast<const double2*>(browp[q] + gk);
-          rb[q][0] = v.x;
-          rb[q][VEC - 1] = v.y;
+        if (VEC > 1 && full) {
+          load16<TI, VEC>(browp[q] + gk, rb[q]);
         } else {
 #pragma unroll
           for (int u = 0; u < VEC; ++u) {
             bool ok = gn < d.N && gk + u < kend;
             if (MODE == GM_B_NT_LOW) ok = ok && gk + u <= gn;
-            rb[q][u] = ok ? browp[q][gk + u] : 0.0;
+            rb[q][u] = ok ? browp[q][gk + u] : TI(0);
           }
         }
       } else {
         // VEC consecutive n of row gk
         const bool rowok = gk < kend;
-        const double* rp = d.B + bnext[q] * d.ldb;
+        const TI* rp = d.B + bnext[q] * d.ldb;
         const int gk2 = gk + BK;
         bnext[q] = gk2 < kend ? (d.ib ? d.ib[gk2] : (int64_t)gk2) : 0;
         bool full = rowok && gn + VEC - 1 < d.N;
         if (MODE == GM_B_NN_LOW) full = full && gk >= gn + VEC - 1;
-        if (VEC == 2 && full) {
-          const double2 v = *reinterpret_cast<const double2*>(rp + gn);
-          rb[q][0] = v.x;
-          rb[q][VEC - 1] = v.y;
+        if (VEC > 1 && full) {
+          load16<TI, VEC>(rp + gn, rb[q]);
         } else {
 #pragma unroll
           for (int u = 0; u < VEC; ++u) {
             bool ok = rowok && gn + u < d.N;
             if (MODE == GM_B_NN_LOW) ok = ok && gk >= gn + u;
-            rb[q][u] = ok ? rp[gn + u] : 0.0;
+            rb[q][u] = ok ? rp[gn + u] : TI(0);
           }
         }
       }
@@ -235,11 +273,11 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_f64_kernel(const GemmDesc* 
       }
   };
 
-  v4d acc[FM][FN];
+  acc_t acc[FM][FN];
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < FN; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < FN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
   if (kbeg < kend) {
     fetch(kbeg);
@@ -250,11 +288,11 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_f64_kernel(const GemmDesc* 
   for (int k0 = kbeg; k0 < kend; k0 += BK) {
     const bool more = k0 + BK < kend;
     if (more) fetch(k0 + BK);
-    const double* as = As[buf];
-    const double* bs = Bs[buf];
+    const TI* as = As[buf];
+    const TI* bs = Bs[buf];
 #pragma unroll
     for (int kq = 0; kq < BK; kq += 4) {
-      double a[FM], b[FN];
+      TI a[FM], b[FN];
 #pragma unroll
       for (int i = 0; i < FM; ++i) a[i] = as[(kq + rowq) * PA + wm * (BM / WM) + i * 16 + coll];
 #pragma unroll
@@ -263,20 +301,20 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_f64_kernel(const GemmDesc* 
       for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = Mfma<TI>::mma(a[i], b[j], acc[i][j]);
     }
     if (more) stash(buf ^ 1);
     __syncthreads();
     buf ^= 1;
   }
 
-  // ---- epilogue: register v of lane l holds D[4*v + l/16][l % 16] of each
-  // 16x16 block (operands: A[l % 16][l / 16], B[l / 16][l % 16])
+  // ---- epilogue: register v of lane l holds D[Mfma::row(v, l/16)][l % 16]
+  // of each 16x16 block (operands: A[l % 16][l / 16], B[l / 16][l % 16])
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int gm = m0 + wm * (BM / WM) + i * 16 + v * 4 + rowq;
+      const int gm = m0 + wm * (BM / WM) + i * 16 + Mfma<TI>::row(v, rowq);
       if (gm >= d.M) continue;
       const int64_t ro = d.ic ? d.ic[gm] : gm;
       const int64_t rc = d.icin ? d.icin[gm] : gm;
@@ -284,9 +322,9 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_f64_kernel(const GemmDesc* 
       for (int j = 0; j < FN; ++j) {
         const int gn = n0 + wn * (BN / WN) + j * 16 + coll;
         if (gn < d.N) {
-          double out = d.alpha * acc[i][j][v];
-          if (d.beta != 0.0) out += d.beta * d.Cin[rc * d.ldcin + gn];
-          d.C[ro * d.ldc + gn] = out;
+          double out = d.alpha * (double)acc[i][j][v];
+          if (d.beta != 0.0) out += d.beta * (double)d.Cin[rc * d.ldcin + gn];
+          d.C[ro * d.ldc + gn] = (TO)out;
         }
       }
     }

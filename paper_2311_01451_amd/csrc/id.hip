@@ -36,13 +36,24 @@ __global__ __launch_bounds__(64) void id_init_kernel(const IdDesc* __restrict__ 
   if (i >= d.b) return;
   double* mi = d.M + (int64_t)i * d.ldm;
   double s = 0.0;
-  for (int c = threadIdx.x; c < d.s; c += 64) {
-    double v = mi[c];
-    if (d.MZ) {
-      v += d.MZ[(int64_t)i * d.ldz + c];
+  if (d.MYf) {
+    const float* fy = d.MYf + (int64_t)i * d.ldf;
+    const float* fz = d.MZf ? d.MZf + (int64_t)i * d.ldf : nullptr;
+    for (int c = threadIdx.x; c < d.s; c += 64) {
+      double v = (double)fy[c];
+      if (fz) v += (double)fz[c];
       mi[c] = v;
+      s += v * v;
     }
-    s += v * v;
+  } else {
+    for (int c = threadIdx.x; c < d.s; c += 64) {
+      double v = mi[c];
+      if (d.MZ) {
+        v += d.MZ[(int64_t)i * d.ldz + c];
+        mi[c] = v;
+      }
+      s += v * v;
+    }
   }
   s = wave_sum(s);
   if (threadIdx.x == 0) {
@@ -207,20 +218,21 @@ rsrs_status id_run(Uploader& up, hipStream_t st, const std::vector<IdDesc>& e) {
 //   c <  r      : XR[i][Rpos[c]] - sum_t XR[i][Spos[t]] T[c][t]
 //   c <  r + k  : XR[i][Spos[c - r]]
 //   otherwise   : XR[i][b + c - r - k]
-__global__ __launch_bounds__(256) void colfix_kernel(const ColfixDesc* __restrict__ e) {
-  const ColfixDesc d = e[blockIdx.y];
+template <typename T>
+__global__ __launch_bounds__(256) void colfix_kernel(const ColfixDescT<T>* __restrict__ e) {
+  const ColfixDescT<T> d = e[blockIdx.y];
   const int i = blockIdx.x;
   if (i >= d.r) return;
-  __shared__ double xs[256];
-  const double* xr = d.XR + (int64_t)i * d.ldx;
+  __shared__ T xs[256];
+  const T* xr = d.XR + (int64_t)i * d.ldx;
   for (int t = threadIdx.x; t < d.k; t += 256) xs[t] = xr[d.Spos[t]];
   __syncthreads();
-  double* out = d.Xp + (int64_t)i * d.ldp;
+  T* out = d.Xp + (int64_t)i * d.ldp;
   for (int c = threadIdx.x; c < d.l; c += 256) {
-    double v;
+    T v;
     if (c < d.r) {
       v = xr[d.Rpos[c]];
-      const double* tc = d.T + (int64_t)c * d.ldt;
+      const T* tc = d.T_ + (int64_t)c * d.ldt;
       for (int t = 0; t < d.k; ++t) v -= xs[t] * tc[t];
     } else if (c < d.r + d.k) {
       v = xs[c - d.r];
@@ -231,7 +243,8 @@ __global__ __launch_bounds__(256) void colfix_kernel(const ColfixDesc* __restric
   }
 }
 
-rsrs_status colfix(Uploader& up, hipStream_t st, const std::vector<ColfixDesc>& e) {
+template <typename T>
+rsrs_status colfix(Uploader& up, hipStream_t st, const std::vector<ColfixDescT<T>>& e) {
   if (e.empty()) return RSRS_OK;
   int rmax = 0;
   for (const auto& x : e) {
@@ -242,12 +255,14 @@ rsrs_status colfix(Uploader& up, hipStream_t st, const std::vector<ColfixDesc>& 
     rmax = std::max(rmax, x.r);
   }
   if (rmax == 0) return RSRS_OK;
-  ColfixDesc* de = nullptr;
+  ColfixDescT<T>* de = nullptr;
   RSRS_TRY(up.put_vec(e, &de));
   ProfScope ps(st, "colfix");
-  hipLaunchKernelGGL(colfix_kernel, dim3((unsigned)rmax, (unsigned)e.size()), dim3(256), 0, st, de);
+  hipLaunchKernelGGL((colfix_kernel<T>), dim3((unsigned)rmax, (unsigned)e.size()), dim3(256), 0, st, de);
   RSRS_HIP(hipGetLastError());
   return RSRS_OK;
 }
+template rsrs_status colfix<double>(Uploader&, hipStream_t, const std::vector<ColfixDescT<double>>&);
+template rsrs_status colfix<float>(Uploader&, hipStream_t, const std::vector<ColfixDescT<float>>&);
 
 }  // namespace rsrs

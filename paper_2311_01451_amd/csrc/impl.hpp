@@ -17,6 +17,7 @@ struct rsrs_tree_s {
 struct rsrs_samples_s {
   const rsrs_tree_t* tree = nullptr;
   int64_t n = 0, s = 0, ld = 0;
+  int dtype = RSRS_F64;         // element type of Y, Z, Om, Psi
   rsrs::DevBuf Y, Z, Om, Psi;   // tree order, row-major n x s (leading dimension ld)
   bool consumed = false;
 };
@@ -27,6 +28,8 @@ struct rsrs_operator_s {
   rsrs::DevBuf owned;        // explicit kernel matrix
   const double* A = nullptr; // matrix used by the GEMM matvec
   int64_t lda = 0;
+  rsrs::DevBuf owned32;      // FP32 kernel matrix (built at the first FP32 product)
+  rsrs::KernelOp kop;        // kernel description (kernel operators)
   bool symmetric = true;
   rsrs::Poisson7Op pois;
   rsrs::Uploader up;
@@ -40,8 +43,8 @@ struct BoxRec {
   int64_t box = 0;
   int level = 0, colour = 0;
   int64_t b = 0, n = 0, r = 0, k = 0;
-  int64_t oT = 0, oXRR = 0, oXinv = 0, oKU = 0, oKL = 0;   // doubles, 16-byte aligned
-  int64_t ldT = 0, ldR = 0, ldKU = 0;   // even leading dims: T, X_RR / X_RR^{-1} / K_L, K_U
+  int64_t oT = 0, oXRR = 0, oXinv = 0, oKU = 0, oKL = 0;   // elements, 16-byte aligned
+  int64_t ldT = 0, ldR = 0, ldKU = 0;   // 16-byte multiples: T, X_RR / X_RR^{-1} / K_L, K_U
   int64_t oR = 0, oS = 0, oSN = 0, oBa = 0, oNa = 0;       // int64 tree positions
 };
 
@@ -49,22 +52,25 @@ struct Group {  // one colour class: boxes [first, first+count) in processing or
   int64_t first = 0, count = 0;
 };
 
-rsrs_status kernel_materialise(hipStream_t st, const KernelOp& op, double* A);
+template <typename T>
+rsrs_status kernel_materialise(hipStream_t st, const KernelOp& op, T* A);
 
 }  // namespace rsrs
 
 struct rsrs_factor_s {
   int64_t n = 0, s = 0, k = 0;
+  int precision = RSRS_PREC_F64;
+  int esz = 8;                         // bytes per stored element (8 FP64, 4 FP32)
   rsrs::DevBuf dstore, istore, perm;   // perm: tree position -> user index
   std::vector<rsrs::BoxRec> boxes;
   std::vector<rsrs::Group> groups;
   int64_t nt = 0, oBt = 0, oAt = 0, oAtinv = 0;
-  int64_t stored_doubles = 0;
+  int64_t stored_values = 0;
   double flops = 0.0, factor_ms = 0.0;
   // solve workspace (grown on demand)
   mutable rsrs::DevBuf wx, wu, wt, wpart, wnorm;
   mutable rsrs::Uploader up;
   mutable bool up_ready = false;
-  const double* d() const { return dstore.as<double>(); }
+  template <typename T> const T* d() const { return dstore.as<T>(); }
   const int64_t* i() const { return istore.as<int64_t>(); }
 };

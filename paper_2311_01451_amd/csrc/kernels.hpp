@@ -33,8 +33,30 @@ struct Uploader {
 // ---- GEMM (gemm.hpp) -------------------------------------------------------
 enum GemmShape { GS_64x64 = 0, GS_64x16 = 1 };
 // `site` (optional) is appended to the measurement tag ("gemm_<form>:<site>").
-rsrs_status gemm(Uploader& up, hipStream_t st, const std::vector<GemmDesc>& descs, int ta,
+// Instantiated for <double, double>, <float, float> (all forms) and
+// <float, double> (SYRK_L only).
+template <typename TI, typename TO>
+rsrs_status gemm(Uploader& up, hipStream_t st, const std::vector<GemmDescT<TI, TO>>& descs, int ta,
                  int tb, int mode, GemmShape shape = GS_64x64, const char* site = nullptr);
+inline rsrs_status gemm(Uploader& up, hipStream_t st, const std::vector<GemmDesc>& descs, int ta,
+                        int tb, int mode, GemmShape shape = GS_64x64, const char* site = nullptr) {
+  return gemm<double, double>(up, st, descs, ta, tb, mode, shape, site);
+}
+template <typename TI, typename TO>
+inline GemmDescT<TI, TO> gdescT(const TI* A, const int64_t* ia, int64_t lda, const TI* B,
+                                const int64_t* ib, int64_t ldb, TO* C, const int64_t* ic,
+                                int64_t ldc, int M, int N, int K, double alpha = 1.0,
+                                double beta = 0.0, const TO* Cin = nullptr,
+                                const int64_t* icin = nullptr, int64_t ldcin = 0) {
+  GemmDescT<TI, TO> d{};
+  d.A = A; d.ia = ia; d.lda = lda;
+  d.B = B; d.ib = ib; d.ldb = ldb;
+  d.C = C; d.ic = ic; d.ldc = ldc;
+  d.Cin = Cin ? Cin : C; d.icin = Cin ? icin : ic; d.ldcin = Cin ? ldcin : ldc;
+  d.M = M; d.N = N; d.K = K;
+  d.alpha = alpha; d.beta = beta;
+  return d;
+}
 inline GemmDesc gdesc(const double* A, const int64_t* ia, int64_t lda, const double* B,
                       const int64_t* ib, int64_t ldb, double* C, const int64_t* ic, int64_t ldc,
                       int M, int N, int K, double alpha = 1.0, double beta = 0.0,
@@ -62,18 +84,29 @@ struct GjeDesc { const double* A; double* W; double* Ainv; int64_t lda, ldi; int
 // pivoting (W: n x 2n workspace).  flag[0] |= 2 on an exactly zero pivot.
 rsrs_status gje_inverse(Uploader& up, hipStream_t st, const std::vector<GjeDesc>& e, int* flag);
 
-struct Copy2D { const double* src; double* dst; int64_t lds, ldd; int rows, cols; double alpha; int accumulate, pad_; };
-// dst = alpha*src (accumulate = 0) or dst += alpha*src.
-rsrs_status copy2d(Uploader& up, hipStream_t st, const std::vector<Copy2D>& e);
+template <typename TS, typename TD>
+struct Copy2DT { const TS* src; TD* dst; int64_t lds, ldd; int rows, cols; double alpha; int accumulate, pad_; };
+using Copy2D = Copy2DT<double, double>;
+// dst = alpha*src (accumulate = 0) or dst += alpha*src, converting the element
+// type.  Instantiated for every pair of double / float.
+template <typename TS, typename TD>
+rsrs_status copy2d(Uploader& up, hipStream_t st, const std::vector<Copy2DT<TS, TD>>& e);
+inline rsrs_status copy2d(Uploader& up, hipStream_t st, const std::vector<Copy2D>& e) {
+  return copy2d<double, double>(up, st, e);
+}
 
-// Row permutations: dst[i] = src[idx[i]] (gather) / dst[idx[i]] = src[i] (scatter).
-void gather_rows(hipStream_t st, double* dst, int64_t ldd, const double* src, int64_t lds,
+// Row permutations: dst[i] = src[idx[i]] (gather) / dst[idx[i]] = src[i]
+// (scatter), converting the element type (double / float pairs).
+template <typename TS, typename TD>
+void gather_rows(hipStream_t st, TD* dst, int64_t ldd, const TS* src, int64_t lds,
                  const int64_t* idx, int64_t nrows, int64_t ncols);
-void scatter_rows(hipStream_t st, double* dst, int64_t ldd, const double* src, int64_t lds,
+template <typename TS, typename TD>
+void scatter_rows(hipStream_t st, TD* dst, int64_t ldd, const TS* src, int64_t lds,
                   const int64_t* idx, int64_t nrows, int64_t ncols);
 void fill(hipStream_t st, double* p, int64_t n, double v);
-// flag[0] |= 4 if any entry of the rows x cols block is NaN/Inf.
-void check_finite(hipStream_t st, const double* p, int64_t rows, int64_t cols, int64_t ld, int* flag);
+// flag[0] |= 4 if any entry of the rows x cols block is NaN/Inf (double / float).
+template <typename T>
+void check_finite(hipStream_t st, const T* p, int64_t rows, int64_t cols, int64_t ld, int* flag);
 // Column sums of squares of an N x w row-major block into out[w] (two-stage, deterministic).
 rsrs_status col_sumsq(hipStream_t st, const double* x, int64_t n, int64_t w, int64_t ld,
                       double* partial, double* out);
@@ -85,6 +118,11 @@ void sub2d(hipStream_t st, const double* f, int64_t ldf, const double* y, int64_
 struct IdDesc {
   double* M;          // b x s (the Y-side projection; the Z side is added in id_init)
   const double* MZ;   // b x s or null
+  // FP32 sources: when MYf is set, id_init writes M = MYf (+ MZf) in FP64
+  // (leading dimension ldf) and MZ is ignored; the pivoting runs in FP64.
+  const float* MYf;
+  const float* MZf;
+  int64_t ldf;
   int64_t ldm, ldz;
   double* norms;      // 2*b
   int32_t* sel;       // b
@@ -97,21 +135,27 @@ struct IdDesc {
 };
 rsrs_status id_run(Uploader& up, hipStream_t st, const std::vector<IdDesc>& e);
 
-struct ColfixDesc {
-  const double* XR;      // r x l (rows R of the least-squares coefficients, E applied)
+template <typename T>
+struct ColfixDescT {
+  const T* XR;           // r x l (rows R of the least-squares coefficients, E applied)
   const int64_t* Spos;   // k
   const int64_t* Rpos;   // r
-  const double* T;       // r x k
-  double* Xp;            // r x l, columns ordered [R, S, N]
+  const T* T_;           // r x k
+  T* Xp;                 // r x l, columns ordered [R, S, N]
   int64_t ldx, ldp, ldt;
   int r, k, b, l;
 };
+using ColfixDesc = ColfixDescT<double>;
 // Columns of the extracted block: right-multiply by G^{-1} (columns R -= columns S T^T)
-// and reorder to [R, S, N].
-rsrs_status colfix(Uploader& up, hipStream_t st, const std::vector<ColfixDesc>& e);
+// and reorder to [R, S, N] (double or float).
+template <typename T>
+rsrs_status colfix(Uploader& up, hipStream_t st, const std::vector<ColfixDescT<T>>& e);
 
 // ---- random numbers and operators (ops.hip) -------------------------------
-void philox_normal(hipStream_t st, double* out, int64_t nrows, int64_t ncols, int64_t ld,
+// Standard normals (double or float output; the float value is the rounded
+// double draw).
+template <typename T>
+void philox_normal(hipStream_t st, T* out, int64_t nrows, int64_t ncols, int64_t ld,
                    uint64_t seed, uint32_t word);
 struct KernelOp {
   int kind, dim;
@@ -123,7 +167,8 @@ struct Poisson7Op {
   int n;
   DevBuf coef;      // N x 7: diag, -x, +x, -y, +y, -z, +z couplings
 };
-rsrs_status poisson_matvec(hipStream_t st, const Poisson7Op& op, int64_t ncols, const double* X,
-                           int64_t ldx, double* Y, int64_t ldy);
+template <typename T>
+rsrs_status poisson_matvec(hipStream_t st, const Poisson7Op& op, int64_t ncols, const T* X,
+                           int64_t ldx, T* Y, int64_t ldy);
 
 }  // namespace rsrs

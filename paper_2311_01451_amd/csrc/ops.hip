@@ -40,7 +40,8 @@ __device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
   }
 }
 
-__global__ void philox_normal_kernel(double* out, int64_t nrows, int64_t ncols, int64_t ld,
+template <typename T>
+__global__ void philox_normal_kernel(T* out, int64_t nrows, int64_t ncols, int64_t ld,
                                      uint32_t seed_lo, uint32_t seed_hi, uint32_t word) {
   const int64_t total = nrows * ncols;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
@@ -52,21 +53,25 @@ __global__ void philox_normal_kernel(double* out, int64_t nrows, int64_t ncols, 
     const uint64_t b = ((uint64_t)c[2] << 21) ^ (uint64_t)(c[3] >> 11);
     const double u1 = ((double)(a & ((1ull << 53) - 1)) + 0.5) * 0x1.0p-53;
     const double u2 = ((double)(b & ((1ull << 53) - 1)) + 0.5) * 0x1.0p-53;
-    out[i * ld + j] = sqrt(-2.0 * log(u1)) * cospi(2.0 * u2);
+    out[i * ld + j] = (T)(sqrt(-2.0 * log(u1)) * cospi(2.0 * u2));
   }
 }
 
-void philox_normal(hipStream_t st, double* out, int64_t nrows, int64_t ncols, int64_t ld,
+template <typename T>
+void philox_normal(hipStream_t st, T* out, int64_t nrows, int64_t ncols, int64_t ld,
                    uint64_t seed, uint32_t word) {
   if (nrows <= 0 || ncols <= 0) return;
   const unsigned g = (unsigned)std::min<int64_t>((nrows * ncols + 255) / 256, 16384);
-  ProfScope ps(st, "philox_normal", 0.0, 8.0 * nrows * ncols);
-  hipLaunchKernelGGL(philox_normal_kernel, dim3(g), dim3(256), 0, st, out, nrows, ncols, ld,
+  ProfScope ps(st, "philox_normal", 0.0, (double)sizeof(T) * nrows * ncols);
+  hipLaunchKernelGGL((philox_normal_kernel<T>), dim3(g), dim3(256), 0, st, out, nrows, ncols, ld,
                      (uint32_t)seed, (uint32_t)(seed >> 32), word);
 }
+template void philox_normal<double>(hipStream_t, double*, int64_t, int64_t, int64_t, uint64_t, uint32_t);
+template void philox_normal<float>(hipStream_t, float*, int64_t, int64_t, int64_t, uint64_t, uint32_t);
 
 // Entry (i, j) of the kernel operators (see include/rsrs.h for the formulas).
-__global__ void kernel_matrix_kernel(double* A, int64_t n, int kind, int dim, const double* pts,
+template <typename T>
+__global__ void kernel_matrix_kernel(T* A, int64_t n, int kind, int dim, const double* pts,
                                      double p1, double p2) {
   const double two_pi = 6.283185307179586476925286766559;
   const double four_pi = 12.566370614359172953850573533118;
@@ -92,22 +97,26 @@ __global__ void kernel_matrix_kernel(double* A, int64_t n, int kind, int dim, co
         if (kind == 3) v += p2 * dx0 / r2;
       }
     }
-    A[idx] = v;
+    A[idx] = (T)v;
   }
 }
 
-rsrs_status kernel_materialise(hipStream_t st, const KernelOp& op, double* A) {
+template <typename T>
+rsrs_status kernel_materialise(hipStream_t st, const KernelOp& op, T* A) {
   const int64_t total = op.n * op.n;
   const unsigned g = (unsigned)std::min<int64_t>((total + 255) / 256, 65536);
-  hipLaunchKernelGGL(kernel_matrix_kernel, dim3(g), dim3(256), 0, st, A, op.n, op.kind, op.dim,
+  hipLaunchKernelGGL((kernel_matrix_kernel<T>), dim3(g), dim3(256), 0, st, A, op.n, op.kind, op.dim,
                      op.pts.as<double>(), op.p1, op.p2);
   RSRS_HIP(hipGetLastError());
   return RSRS_OK;
 }
+template rsrs_status kernel_materialise<double>(hipStream_t, const KernelOp&, double*);
+template rsrs_status kernel_materialise<float>(hipStream_t, const KernelOp&, float*);
 
 // 7-point stencil: Y[i][c] = sum_t coef[i][t] X[nbr_t(i)][c], t = 0 is the node itself.
-__global__ void poisson_kernel(const double* coef, int n, int64_t w, const double* X, int64_t ldx,
-                               double* Y, int64_t ldy) {
+template <typename T>
+__global__ void poisson_kernel(const double* coef, int n, int64_t w, const T* X, int64_t ldx,
+                               T* Y, int64_t ldy) {
   const int64_t N = (int64_t)n * n * n;
   const int64_t total = N * w;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
@@ -115,26 +124,29 @@ __global__ void poisson_kernel(const double* coef, int n, int64_t w, const doubl
     const int64_t i = idx / w, c = idx % w;
     const int x = (int)(i % n), y = (int)((i / n) % n), z = (int)(i / ((int64_t)n * n));
     const double* cf = coef + i * 7;
-    double v = cf[0] * X[i * ldx + c];
-    if (x > 0) v += cf[1] * X[(i - 1) * ldx + c];
-    if (x < n - 1) v += cf[2] * X[(i + 1) * ldx + c];
-    if (y > 0) v += cf[3] * X[(i - n) * ldx + c];
-    if (y < n - 1) v += cf[4] * X[(i + n) * ldx + c];
-    if (z > 0) v += cf[5] * X[(i - (int64_t)n * n) * ldx + c];
-    if (z < n - 1) v += cf[6] * X[(i + (int64_t)n * n) * ldx + c];
-    Y[i * ldy + c] = v;
+    double v = cf[0] * (double)X[i * ldx + c];
+    if (x > 0) v += cf[1] * (double)X[(i - 1) * ldx + c];
+    if (x < n - 1) v += cf[2] * (double)X[(i + 1) * ldx + c];
+    if (y > 0) v += cf[3] * (double)X[(i - n) * ldx + c];
+    if (y < n - 1) v += cf[4] * (double)X[(i + n) * ldx + c];
+    if (z > 0) v += cf[5] * (double)X[(i - (int64_t)n * n) * ldx + c];
+    if (z < n - 1) v += cf[6] * (double)X[(i + (int64_t)n * n) * ldx + c];
+    Y[i * ldy + c] = (T)v;
   }
 }
 
-rsrs_status poisson_matvec(hipStream_t st, const Poisson7Op& op, int64_t ncols, const double* X,
-                           int64_t ldx, double* Y, int64_t ldy) {
+template <typename T>
+rsrs_status poisson_matvec(hipStream_t st, const Poisson7Op& op, int64_t ncols, const T* X,
+                           int64_t ldx, T* Y, int64_t ldy) {
   const int64_t N = (int64_t)op.n * op.n * op.n;
   const unsigned g = (unsigned)std::min<int64_t>((N * ncols + 255) / 256, 65536);
-  ProfScope ps(st, "poisson7", 13.0 * N * ncols, 8.0 * (9.0 * N * ncols));
-  hipLaunchKernelGGL(poisson_kernel, dim3(g), dim3(256), 0, st, op.coef.as<double>(), op.n, ncols,
+  ProfScope ps(st, "poisson7", 13.0 * N * ncols, 56.0 * N + 2.0 * sizeof(T) * N * ncols);
+  hipLaunchKernelGGL((poisson_kernel<T>), dim3(g), dim3(256), 0, st, op.coef.as<double>(), op.n, ncols,
                      X, ldx, Y, ldy);
   RSRS_HIP(hipGetLastError());
   return RSRS_OK;
 }
+template rsrs_status poisson_matvec<double>(hipStream_t, const Poisson7Op&, int64_t, const double*, int64_t, double*, int64_t);
+template rsrs_status poisson_matvec<float>(hipStream_t, const Poisson7Op&, int64_t, const float*, int64_t, float*, int64_t);
 
 }  // namespace rsrs

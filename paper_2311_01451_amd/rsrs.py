@@ -1,8 +1,9 @@
 """Thin Python binding of ``include/rsrs.h`` (ctypes).
 
 Argument marshalling only: every step of the method runs in ``librsrs.so``.
-PyTorch supplies device memory (``torch.float64`` CUDA/HIP tensors, row-major
-N x w with ``stride(0)`` as leading dimension) and the current HIP stream.
+PyTorch supplies device memory (``torch.float64`` CUDA/HIP tensors, or
+``torch.float32`` for FP32 sketches, row-major N x w with ``stride(0)`` as
+leading dimension) and the current HIP stream.
 The functions carry the names of the C entry points; small handle classes own
 the C handles and free them on garbage collection.
 
@@ -24,6 +25,9 @@ RSRS_OP_LOG2D = 1
 RSRS_OP_INVR3D = 2
 RSRS_OP_LOG2D_SKEW = 3
 RSRS_PREC_F64 = 0
+RSRS_PREC_F32_MIXED = 1
+RSRS_F64 = 0
+RSRS_F32 = 1
 
 STATUS = {0: "RSRS_OK", 1: "RSRS_E_INVALID", 2: "RSRS_E_SAMPLES", 3: "RSRS_E_SINGULAR",
           4: "RSRS_E_CALLBACK", 5: "RSRS_E_NUMERIC", 6: "RSRS_E_NOMEM", 7: "RSRS_E_HIP",
@@ -57,8 +61,8 @@ class FactorOpts(C.Structure):
 
 class FactorInfo(C.Structure):
     _fields_ = [("n", C.c_int64), ("s", C.c_int64), ("k", C.c_int64), ("nboxes", C.c_int64),
-                ("root_size", C.c_int64), ("stored_doubles", C.c_int64), ("flops", C.c_double),
-                ("factor_ms", C.c_double)]
+                ("root_size", C.c_int64), ("stored_values", C.c_int64), ("stored_bytes", C.c_int64),
+                ("precision", C.c_int), ("flops", C.c_double), ("factor_ms", C.c_double)]
 
 
 class ProfileEntry(C.Structure):
@@ -66,7 +70,7 @@ class ProfileEntry(C.Structure):
                 ("flops", C.c_double), ("bytes", C.c_double)]
 
 
-MATVEC_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int, C.c_int64, C.c_void_p, C.c_int64,
+MATVEC_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int, C.c_int, C.c_int64, C.c_void_p, C.c_int64,
                         C.c_void_p, C.c_int64, C.c_void_p)
 
 EXPORTS = [
@@ -105,10 +109,10 @@ def lib():
         "rsrs_op_create_kernel": (i32, [i32, P(C.c_double), i64, i32, dbl, dbl, P(vp)]),
         "rsrs_op_create_dense": (i32, [vp, i64, i64, P(vp)]),
         "rsrs_op_create_poisson7": (i32, [i32, P(C.c_double), P(vp)]),
-        "rsrs_op_matvec": (i32, [vp, i32, i64, vp, i64, vp, i64, vp]),
+        "rsrs_op_matvec": (i32, [vp, i32, i32, i64, vp, i64, vp, i64, vp]),
         "rsrs_op_destroy": (None, [vp]),
-        "rsrs_samples_wrap": (i32, [vp, vp, vp, vp, vp, i64, i64, vp, P(vp)]),
-        "rsrs_sample": (i32, [vp, vp, vp, i64, C.c_uint64, vp, P(vp)]),
+        "rsrs_samples_wrap": (i32, [vp, i32, vp, vp, vp, vp, i64, i64, vp, P(vp)]),
+        "rsrs_sample": (i32, [vp, vp, vp, i64, C.c_uint64, i32, vp, P(vp)]),
         "rsrs_samples_destroy": (None, [vp]),
         "rsrs_gaussian": (i32, [vp, i64, i64, i64, C.c_uint64, C.c_uint32, vp]),
         "rsrs_factor": (i32, [vp, vp, P(FactorOpts), vp, P(vp)]),
@@ -147,13 +151,19 @@ def _stream(stream=None):
     return C.c_void_p(int(s.cuda_stream))
 
 
-def _dev(t, name="tensor"):
+def _dev(t, name="tensor", dtypes=("float64",)):
     import torch
-    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64):
-        raise TypeError(f"{name} must be a float64 device tensor")
+    ok = isinstance(t, torch.Tensor) and t.is_cuda and str(t.dtype).replace("torch.", "") in dtypes
+    if not ok:
+        raise TypeError(f"{name} must be a {' or '.join(dtypes)} device tensor")
     if t.dim() != 2 or t.stride(1) != 1:
         raise TypeError(f"{name} must be 2-D row-major (stride(1) == 1)")
     return C.c_void_p(t.data_ptr()), t.stride(0)
+
+
+def _dtype_code(t) -> int:
+    import torch
+    return RSRS_F32 if t.dtype == torch.float32 else RSRS_F64
 
 
 # --------------------------------------------------------------------------- tree
@@ -262,12 +272,16 @@ class Operator:
         return C.cast(lib().rsrs_op_matvec, C.c_void_p)
 
     def matvec(self, X, transpose: bool = False, out=None, stream=None):
+        """A X or A^T X for an FP64 or FP32 device block X (same type out)."""
         import torch
-        px, ldx = _dev(X, "X")
+        px, ldx = _dev(X, "X", ("float64", "float32"))
         if out is None:
             out = torch.empty_like(X)
-        py, ldy = _dev(out, "out")
-        st = lib().rsrs_op_matvec(self._h, int(transpose), X.shape[1], px, ldx, py, ldy, _stream(stream))
+        if out.dtype != X.dtype:
+            raise TypeError("out must have the dtype of X")
+        py, ldy = _dev(out, "out", ("float64", "float32"))
+        st = lib().rsrs_op_matvec(self._h, int(transpose), _dtype_code(X), X.shape[1], px, ldx, py,
+                                  ldy, _stream(stream))
         if st != 0:
             raise RSRSError(4, "rsrs_op_matvec failed: " + lib().rsrs_last_error().decode())
         return out
@@ -316,24 +330,27 @@ class Samples:
 
 
 def rsrs_samples_wrap(tree: Tree, Y, Z, Om, Psi, stream=None) -> Samples:
+    """Sketches as FP64 or FP32 device tensors (all four of one dtype)."""
     ptrs = []
     ld = None
     for name, t in (("Y", Y), ("Z", Z), ("Omega", Om), ("Psi", Psi)):
-        p, l = _dev(t, name)
+        p, l = _dev(t, name, ("float64", "float32"))
         if ld is None:
             ld = l
-        if l != ld or t.shape != Y.shape:
-            raise TypeError("sketches must share shape and leading dimension")
+        if l != ld or t.shape != Y.shape or t.dtype != Y.dtype:
+            raise TypeError("sketches must share shape, dtype and leading dimension")
         ptrs.append(p)
     h = C.c_void_p()
-    _check(lib().rsrs_samples_wrap(tree.handle, *ptrs, ld, Y.shape[1], _stream(stream), C.byref(h)))
+    _check(lib().rsrs_samples_wrap(tree.handle, _dtype_code(Y), *ptrs, ld, Y.shape[1],
+                                   _stream(stream), C.byref(h)))
     return Samples(h, Y.shape[1])
 
 
-def rsrs_sample(tree: Tree, op: Operator, s: int, seed: int, stream=None) -> Samples:
+def rsrs_sample(tree: Tree, op: Operator, s: int, seed: int, dtype: int = RSRS_F64,
+                stream=None) -> Samples:
     h = C.c_void_p()
-    _check(lib().rsrs_sample(tree.handle, Operator.fn_ptr(), op.handle, s, seed, _stream(stream),
-                             C.byref(h)))
+    _check(lib().rsrs_sample(tree.handle, Operator.fn_ptr(), op.handle, s, seed, dtype,
+                             _stream(stream), C.byref(h)))
     return Samples(h, s)
 
 

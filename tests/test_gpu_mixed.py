@@ -1,0 +1,180 @@
+"""GPU: the mixed-precision path (FP32 samples, FP32 MFMA products, FP64
+pivots and inverses) through the C ABI.
+
+The FP32 products are pinned element by element against the rigorous
+rounding bound of an FP32 dot product of length K,
+|fl(x.y) - x.y| <= K u sum |x_i y_i|  (u = 2^-24),
+applied to the FP32-rounded operands (so a wrong lane layout or a dropped
+tile fails by orders of magnitude).  The factorization is judged by what the
+method promises for it: a factor of the same operator whose one-shot
+residual is small, and iterative refinement with the FP64 black-box residual
+that reaches the FP64 bar; its solutions are compared with the FP64 oracle's
+and with a dense solve.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import operators as oop  # noqa: E402
+from oracle import rsrs as orr  # noqa: E402
+from oracle import tree as ot  # noqa: E402
+from paper_2311_01451_amd import inputs, rsrs  # noqa: E402
+
+U32 = 2.0 ** -24
+
+
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def dev(a, dt=torch.float64):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+
+
+def relres(A, u, f):
+    r = f - A @ u
+    return float(np.max(np.linalg.norm(r, axis=0) / np.linalg.norm(f, axis=0)))
+
+
+def test_fp32_operator_products_within_rounding_bound():
+    need_gpu()
+    n = 40
+    pts = inputs.grid2d(n)
+    N = n * n
+    A32 = oop.log2d(pts, 1.0 / n).astype(np.float32).astype(np.float64)
+    op = rsrs.rsrs_op_create_kernel(rsrs.RSRS_OP_LOG2D, pts, 1.0 / n)
+    for w in (1, 16, 77, 300):
+        print(f"[fp32 operator] N={N} w={w}", flush=True)
+        X = np.random.default_rng(w).standard_normal((N, w)).astype(np.float32)
+        Y = op.matvec(dev(X, torch.float32)).cpu().numpy().astype(np.float64)
+        Xd = X.astype(np.float64)
+        exact = A32 @ Xd
+        bound = 1.0001 * N * U32 * (np.abs(A32) @ np.abs(Xd)) + 1e-30
+        assert np.all(np.abs(Y - exact) <= bound), float(np.max(np.abs(Y - exact) / bound))
+    # skewed (non-symmetric) kernel: the transposed product reads A column-wise
+    Ask = oop.log2d_skew(pts, 1.0 / n, 0.3).astype(np.float32).astype(np.float64)
+    opk = rsrs.rsrs_op_create_kernel(rsrs.RSRS_OP_LOG2D_SKEW, pts, 1.0 / n, 0.3)
+    X = np.random.default_rng(5).standard_normal((N, 64)).astype(np.float32)
+    Xd = X.astype(np.float64)
+    for tr in (False, True):
+        M = Ask.T if tr else Ask
+        Y = opk.matvec(dev(X, torch.float32), transpose=tr).cpu().numpy().astype(np.float64)
+        bound = 1.0001 * N * U32 * (np.abs(M) @ np.abs(Xd)) + 1e-30
+        assert np.all(np.abs(Y - M @ Xd) <= bound)
+
+
+def test_fp32_poisson_product():
+    need_gpu()
+    n = 12
+    coef = inputs.smooth_log_coefficient(n + 2)
+    op = rsrs.rsrs_op_create_poisson7(n, coef)
+    A = oop.poisson7(n, coef)
+    X = np.random.default_rng(3).standard_normal((n ** 3, 9)).astype(np.float32)
+    Xd = X.astype(np.float64)
+    Y = op.matvec(dev(X, torch.float32)).cpu().numpy().astype(np.float64)
+    exact = A @ Xd
+    # FP64 accumulation of FP32 inputs, then one rounding of the result to FP32
+    assert np.all(np.abs(Y - exact) <= U32 * np.abs(exact) + 1e-14 * (abs(A) @ np.abs(Xd)))
+
+
+def _mixed_problem(n, m, k, seed_off=0):
+    pts = inputs.grid2d(n)
+    N = n * n
+    A = oop.log2d(pts, 1.0 / n)
+    tc = rsrs.rsrs_build_tree(pts, m)
+    s = tc.samples_required(k, k)
+    Om, Psi = inputs.test_matrices(N, s, seed_off)
+    # FP32 test matrices; both sides use exactly these values
+    Om = Om.astype(np.float32).astype(np.float64)
+    Psi = Psi.astype(np.float32).astype(np.float64)
+    Y, Z = A @ Om, A.T @ Psi
+    return pts, A, tc, s, Om, Psi, Y, Z
+
+
+def test_mixed_factor_refines_to_fp64_accuracy():
+    """Mixed factor of the 32x32 log-kernel problem (k=16) against the FP64 oracle."""
+    need_gpu()
+    n, m, k = 32, 32, 16
+    pts, A, tc, s, Om, Psi, Y, Z = _mixed_problem(n, m, k)
+    N = n * n
+    print(f"[mixed] N={N} k={k} s={s}", flush=True)
+    f32 = lambda a: dev(a, torch.float32)
+    smp = rsrs.rsrs_samples_wrap(tc, f32(Y), f32(Z), f32(Om), f32(Psi))
+    F = rsrs.rsrs_factor(tc, smp, k, precision=rsrs.RSRS_PREC_F32_MIXED)
+    info = F.info()
+    assert info["precision"] == rsrs.RSRS_PREC_F32_MIXED
+    assert info["stored_bytes"] == 4 * info["stored_values"]
+    Fo = orr.factor(ot.build_tree(pts, m), Y, Z, Om, Psi, k)
+    f = inputs.rhs(N, 3)
+    u1 = F.solve(dev(f)).cpu().numpy()
+    uo = orr.solve(Fo, f)
+    r1 = relres(A, u1, f)
+    err_vs_oracle = float(np.linalg.norm(u1 - uo) / np.linalg.norm(uo))
+    cond = np.linalg.cond(A)
+    eps_o = orr.relerr(Fo, A)
+    print(f"[mixed] one-shot residual {r1:.2e}, |u_mixed - u_oracle|/|u_oracle| {err_vs_oracle:.2e}, "
+          f"oracle relerr {eps_o:.2e}, cond {cond:.2f}", flush=True)
+    # the solution difference is bounded by the two residuals through cond(A)
+    ro = relres(A, uo, f)
+    assert err_vs_oracle <= 1.01 * cond * (r1 + ro) + 1e-12
+    assert r1 < 1e-3
+    # apply is the inverse of solve to FP32 working accuracy
+    fa = F.apply(F.solve(dev(f))).cpu().numpy()
+    assert np.linalg.norm(fa - f) / np.linalg.norm(f) < 1e-5
+    ft = F.apply(F.solve(dev(f), transpose=True), transpose=True).cpu().numpy()
+    assert np.linalg.norm(ft - f) / np.linalg.norm(f) < 1e-5
+    # refinement with the FP64 black box: the 1e-6 bar of the mixed path and
+    # the 1e-10 bar of the FP64 path
+    op = rsrs.rsrs_op_create_dense(dev(A))
+    for tol in (1e-6, 1e-10):
+        u, rel, it = rsrs.rsrs_solve_refine(F, op, dev(f), tol=tol, maxit=30)
+        u = u.cpu().numpy()
+        print(f"[mixed] refine tol {tol:g}: residual {rel:.2e} after {it} corrections", flush=True)
+        assert rel <= tol
+        assert relres(A, u, f) <= 1.5 * tol
+        ue = np.linalg.solve(A, f)
+        assert np.linalg.norm(u - ue) / np.linalg.norm(ue) <= 1.5 * cond * tol
+
+
+def test_mixed_sampling_path_64x64():
+    """rsrs_sample in FP32 through the kernel operator, mixed factor, refinement
+    (64x64 grid, leaf 64, k = p = 32, s = s_required)."""
+    need_gpu()
+    n, m, k = 64, 64, 32
+    pts = inputs.grid2d(n)
+    N = n * n
+    A = oop.log2d(pts, 1.0 / n)
+    tc = rsrs.rsrs_build_tree(pts, m)
+    s = tc.samples_required(k, k)
+    print(f"[mixed sample] N={N} k={k} s={s}", flush=True)
+    op = rsrs.rsrs_op_create_kernel(rsrs.RSRS_OP_LOG2D, pts, 1.0 / n)
+    smp = rsrs.rsrs_sample(tc, op, s, inputs.BASE_SEED, dtype=rsrs.RSRS_F32)
+    F = rsrs.rsrs_factor(tc, smp, k, precision=rsrs.RSRS_PREC_F32_MIXED)
+    f = inputs.rhs(N, 16)
+    u1 = F.solve(dev(f)).cpu().numpy()
+    r1 = relres(A, u1, f)
+    u, rel, it = rsrs.rsrs_solve_refine(F, op, dev(f), tol=1e-6, maxit=30)
+    print(f"[mixed sample] one-shot residual {r1:.2e}; refined {rel:.2e} after {it}", flush=True)
+    assert r1 < 1e-3 and rel <= 1e-6
+    assert relres(A, u.cpu().numpy(), f) <= 1.5e-6
+    # FP64 path on the same operator and seed, for the record and as a check
+    smp64 = rsrs.rsrs_sample(tc, op, s, inputs.BASE_SEED, dtype=rsrs.RSRS_F64)
+    F64 = rsrs.rsrs_factor(tc, smp64, k)
+    u64 = F64.solve(dev(f)).cpu().numpy()
+    d = float(np.linalg.norm(u1 - u64) / np.linalg.norm(u64))
+    print(f"[mixed sample] |u_mixed - u_fp64| / |u_fp64| = {d:.2e}", flush=True)
+    assert d <= 1.01 * np.linalg.cond(A) * (r1 + relres(A, u64, f)) + 1e-12
+
+
+def test_mixed_rejects_fp64_samples_and_vice_versa():
+    need_gpu()
+    n, m, k = 16, 16, 8
+    pts, A, tc, s, Om, Psi, Y, Z = _mixed_problem(n, m, k)
+    f32 = lambda a: dev(a, torch.float32)
+    smp = rsrs.rsrs_samples_wrap(tc, f32(Y), f32(Z), f32(Om), f32(Psi))
+    with pytest.raises(rsrs.RSRSError) as e:
+        rsrs.rsrs_factor(tc, smp, k)
+    assert e.value.status == 1

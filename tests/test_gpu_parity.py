@@ -300,6 +300,11 @@ def test_errors_reported():
     # a matvec callback that reports failure
     fail = rsrs.MATVEC_FN(lambda *a: 1)
     h = C.c_void_p()
-    st = rsrs.lib().rsrs_sample(tc.handle, C.cast(fail, C.c_void_p), None, need, 1,
+    st = rsrs.lib().rsrs_sample(tc.handle, C.cast(fail, C.c_void_p), None, need, 1, rsrs.RSRS_F64,
                                 rsrs._stream(), C.byref(h))
     assert st == 4
+    # precision and sample type must agree
+    smp = rsrs.rsrs_samples_wrap(tc, dA @ dev(Om), dA.T.contiguous() @ dev(Psi), dev(Om), dev(Psi))
+    with pytest.raises(rsrs.RSRSError) as e:
+        rsrs.rsrs_factor(tc, smp, 8, precision=rsrs.RSRS_PREC_F32_MIXED)
+    assert e.value.status == 1
