@@ -3,17 +3,19 @@
 
 Workload: 2D log-kernel operator A_ij = delta_ij + h^2 (-log|x_i - x_j| / 2 pi),
 A_ii = 1 + h^2/2, on the 256 x 256 cell-centred grid of [0,1]^2 (N = 65,536,
-h = 1/256), quadtree leaf 64, rank k = 64, p = k, FP64 end to end, 16
-right-hand sides N(0,1).  The configured s = 640 is below the sample count the
-method requires (s >= |B_a| + |N_a| + k + p for every box), so the step runs
-at s = max(640, s_required) and reports both.
+h = 1/256), quadtree leaf 64, rank k = 64, p = k, 16 right-hand sides
+N(0,1).  The configured s = 640 is below the sample count the method requires
+(s >= |B_a| + |N_a| + k + p for every box), so the step runs at
+s = max(640, s_required) and reports both.
 
 One step = the whole hot path on one batch: build the tree, draw Omega/Psi
 and sample Y = A Omega, Z = A^T Psi through the operator, factor (Algorithm
-1), solve the 16 right-hand sides and refine through the operator until the
-relative residual is <= 1e-6.  value = right-hand-side columns solved per
-second of step time.  The operator itself (the black box) is built once
-outside the timed region.
+1), solve the 16 right-hand sides and refine with the FP64 residual of the
+operator until the relative residual is <= 1e-6.  It runs in two precisions:
+mixed (FP32 samples and MFMA products, FP64 pivots, inverses and residuals)
+and plain FP64.  value = right-hand-side columns solved per second of step
+time of the mixed path; the FP64 path is reported beside it ("fp64").  The
+operator itself (the black box) is built once outside the timed region.
 
 Prints ONE JSON line (rank 0).  Extra fields: per-phase times, p50/p99 solve
 latency of the resident factor, the roofline of the dominant kernel measured
@@ -36,6 +38,7 @@ if ROOT not in sys.path:
 
 METRIC = "factor s + solved RHS cols/s at rel. residual 1e-6, mixed vs FP64; p99 solve ms"
 PEAK_FP64_TFLOPS = 78.6
+PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 
 GRID_N = 256
@@ -48,14 +51,16 @@ TOL = 1e-6
 
 def workload_config(s_req: int, s_eff: int) -> dict:
     return {"workload": f"2D log-kernel operator on a {GRID_N}x{GRID_N} grid (N={GRID_N**2}), "
-                        f"quadtree leaf {LEAF}, k=p={K}, FP64, {NRHS} RHS, residual <= {TOL:g}",
+                        f"quadtree leaf {LEAF}, k=p={K}, {NRHS} RHS, residual <= {TOL:g} "
+                        "(FP64 residual), mixed precision vs FP64",
             "N": GRID_N ** 2, "leaf": LEAF, "k": K, "p": K, "s_configured": S_CFG,
             "s_required": s_req, "s": s_eff, "nrhs": NRHS, "tol": TOL,
-            "precision": "fp64"}
+            "precision": "fp32-mixed (FP32 samples and MFMA products; FP64 Cholesky, "
+                         "pivoted QR, Gauss-Jordan and residuals); fp64 beside it"}
 
 
 def gpu_bench(steps: int, warmup: int, do_profile: bool, latency_reps: int = 40,
-              calib_copy_mib: int = 0):
+              calib_copy_mib: int = 0, mixed: bool = False, ctx: dict | None = None):
     import torch
     from paper_2311_01451_amd import inputs, rsrs
 
@@ -68,10 +73,17 @@ def gpu_bench(steps: int, warmup: int, do_profile: bool, latency_reps: int = 40,
         torch.cuda.synchronize()
         del src, dst
 
+    ctx = {} if ctx is None else ctx
     pts = inputs.grid2d(GRID_N)
     h = 1.0 / GRID_N
-    op = rsrs.rsrs_op_create_kernel(rsrs.RSRS_OP_LOG2D, pts, h)
-    f = torch.tensor(inputs.rhs(GRID_N ** 2, NRHS), dtype=torch.float64, device="cuda")
+    if "op" not in ctx:
+        ctx["op"] = rsrs.rsrs_op_create_kernel(rsrs.RSRS_OP_LOG2D, pts, h)
+        ctx["f"] = torch.tensor(inputs.rhs(GRID_N ** 2, NRHS), dtype=torch.float64, device="cuda")
+    op, f = ctx["op"], ctx["f"]
+    dtype = rsrs.RSRS_F32 if mixed else rsrs.RSRS_F64
+    prec = rsrs.RSRS_PREC_F32_MIXED if mixed else rsrs.RSRS_PREC_F64
+    if mixed:   # the FP32 copy of the kernel matrix is part of the operator, built once
+        op.matvec(torch.zeros((GRID_N ** 2, 1), dtype=torch.float32, device="cuda"))
     torch.cuda.synchronize()
 
     def step(record):
@@ -80,18 +92,20 @@ def gpu_bench(steps: int, warmup: int, do_profile: bool, latency_reps: int = 40,
         s_req = tree.samples_required(K, K)
         s_eff = max(S_CFG, s_req)
         t1 = time.perf_counter()
-        smp = rsrs.rsrs_sample(tree, op, s_eff, inputs.BASE_SEED)
+        smp = rsrs.rsrs_sample(tree, op, s_eff, inputs.BASE_SEED, dtype=dtype)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        F = rsrs.rsrs_factor(tree, smp, K)
+        F = rsrs.rsrs_factor(tree, smp, K, precision=prec)
         torch.cuda.synchronize()
         t3 = time.perf_counter()
-        u, rel, it = rsrs.rsrs_solve_refine(F, op, f, tol=TOL, maxit=10)
+        u, rel, it = rsrs.rsrs_solve_refine(F, op, f, tol=TOL, maxit=30)
         torch.cuda.synchronize()
         t4 = time.perf_counter()
+        u1 = F.solve(f)
+        torch.cuda.synchronize()
         record.append(dict(tree=t1 - t0, sample=t2 - t1, factor=t3 - t2, solve=t4 - t3,
                            relres=rel, iters=it, s_req=s_req, s_eff=s_eff,
-                           flops=F.info()["flops"]))
+                           flops=F.info()["flops"], u=u, u1=u1))
         return F
 
     warm = []
@@ -123,6 +137,9 @@ def gpu_bench(steps: int, warmup: int, do_profile: bool, latency_reps: int = 40,
         torch.cuda.synchronize()
         lat.append((time.perf_counter() - a) * 1e3)
     lat = np.array(lat[5:] if len(lat) > 5 else lat)
+    # one-shot residual of the last factor (FP64 residual through the operator)
+    r = f - op.matvec(rec[-1]["u1"])
+    rec[-1]["relres_oneshot"] = float((r.norm(dim=0) / f.norm(dim=0)).max())
     return rec, elapsed, prof, lat
 
 
@@ -167,7 +184,8 @@ def roofline_from_profile(prof: dict, steps: int) -> dict | None:
     e = prof[tag]
     if e["flops"] > 0:
         ach = e["flops"] / (e["ms"] * 1e-3) / 1e12
-        bound, peak, unit = "mfma", PEAK_FP64_TFLOPS, "TFLOP/s"
+        peak = PEAK_FP32_TFLOPS if tag.startswith("gemm32") else PEAK_FP64_TFLOPS
+        bound, unit = "mfma", "TFLOP/s"
     else:
         ach = e["bytes"] / (e["ms"] * 1e-3) / 1e9
         bound, peak, unit = "hbm", PEAK_HBM_GBS, "GB/s"
@@ -260,40 +278,60 @@ def main():
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {a.gpus}); "
-              "the multi-GPU sharding is described in DESIGN.md but not run", file=sys.stderr)
+              "a sharded run across GPUs is not part of this benchmark", file=sys.stderr)
         sys.exit(2)
-    rec, elapsed, prof, lat = gpu_bench(a.steps, a.warmup, not a.no_profile, a.latency_reps,
-                                        a.calib_copy_mib)
+    ctx = {}
+    runs = {}
+    for name, mixed in (("mixed", True), ("fp64", False)):
+        runs[name] = gpu_bench(a.steps, a.warmup, not a.no_profile, a.latency_reps,
+                               a.calib_copy_mib if name == "mixed" else 0, mixed, ctx)
+    ua, ub = runs["mixed"][0][-1]["u"], runs["fp64"][0][-1]["u"]
+    diff = float(((ua - ub).norm() / ub.norm()).item())
+
+    def summary(rec, elapsed, prof, lat, steps):
+        return {
+            "value": round(NRHS * steps / elapsed, 4),
+            "ms_per_step": round(elapsed / steps * 1e3, 3),
+            "factor_s": round(float(np.mean([r["factor"] for r in rec])), 4),
+            "sample_s": round(float(np.mean([r["sample"] for r in rec])), 4),
+            "solve_refine_ms": round(float(np.mean([r["solve"] for r in rec])) * 1e3, 3),
+            "refine_iters": int(rec[-1]["iters"]),
+            "relres": rec[-1]["relres"],
+            "relres_oneshot": rec[-1]["relres_oneshot"],
+            "factor_tflops_algorithmic": round(rec[-1]["flops"] / np.mean([r["factor"] for r in rec]) / 1e12, 3),
+            "solve_ms_p50": round(float(np.percentile(lat, 50)), 3),
+            "solve_ms_p99": round(float(np.percentile(lat, 99)), 3),
+            "solve_cols_per_s": round(NRHS / (float(np.median(lat)) * 1e-3), 1),
+            "roofline": roofline_from_profile(prof, steps),
+            "kernels": {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
+                            "tflops": round(v["flops"] / max(v["ms"], 1e-9) / 1e9, 3)}
+                        for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"])[:12]},
+        }
+
+    sm = summary(*runs["mixed"], a.steps)
+    s64 = summary(*runs["fp64"], a.steps)
+    rec = runs["mixed"][0]
     s_req, s_eff = rec[-1]["s_req"], rec[-1]["s_eff"]
-    ms = elapsed / a.steps * 1e3
     out = {
         "metric": METRIC,
-        "value": round(NRHS * a.steps / elapsed, 4),
+        "value": sm["value"],
         "unit": "RHS cols/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": round(ms, 3),
+        "ms_per_step": sm["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32",
         "data": "synthetic",
         "config": workload_config(s_req, s_eff),
-        "factor_s": round(float(np.mean([r["factor"] for r in rec])), 4),
-        "sample_s": round(float(np.mean([r["sample"] for r in rec])), 4),
-        "solve_refine_ms": round(float(np.mean([r["solve"] for r in rec])) * 1e3, 3),
-        "refine_iters": int(rec[-1]["iters"]),
-        "relres": rec[-1]["relres"],
-        "factor_tflops_algorithmic": round(rec[-1]["flops"] / np.mean([r["factor"] for r in rec]) / 1e12, 3),
-        "solve_ms_p50": round(float(np.percentile(lat, 50)), 3),
-        "solve_ms_p99": round(float(np.percentile(lat, 99)), 3),
-        "solve_cols_per_s": round(NRHS / (float(np.median(lat)) * 1e-3), 1),
-        "roofline": roofline_from_profile(prof, a.steps),
-        "kernels": {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
-                        "tflops": round(v["flops"] / max(v["ms"], 1e-9) / 1e9, 3)}
-                    for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"])[:12]},
     }
+    out.update({k: v for k, v in sm.items() if k not in ("value", "ms_per_step")})
+    out["fp64"] = s64
+    out["mixed_vs_fp64"] = {"speedup": round(sm["value"] / s64["value"], 3),
+                            "factor_speedup": round(s64["factor_s"] / sm["factor_s"], 3),
+                            "solution_rel_diff": diff}
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(s_eff)
     print(json.dumps(out))
