@@ -225,6 +225,19 @@ typedef struct {
 
 rsrs_status rsrs_factor(const rsrs_tree_t* t, rsrs_samples_t* smp, const rsrs_factor_opts* opts,
                         void* stream, rsrs_factor_t** out);
+/* Many independent problems factored together (Algorithm 1 on each): trees,
+ * samples and opts are arrays of nprob entries (each problem its own N, tree,
+ * s and k; all of one precision); out receives nprob factors.  The problems
+ * advance through their colour classes in lock step, class t of every
+ * problem that has one running in the same batched launches, so the whole
+ * batch takes as many host synchronisations as its longest member has colour
+ * classes.  Each factor equals the one rsrs_factor computes for that problem
+ * alone.  On any error no factor is returned (out[i] = NULL), the error
+ * message names the problem, and every sample set that had passed validation
+ * counts as consumed. */
+rsrs_status rsrs_factor_batched(int64_t nprob, const rsrs_tree_t* const* trees,
+                                rsrs_samples_t* const* samples, const rsrs_factor_opts* opts,
+                                void* stream, rsrs_factor_t** out);
 void rsrs_factor_destroy(rsrs_factor_t* f);
 
 typedef struct {

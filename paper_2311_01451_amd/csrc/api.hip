@@ -17,6 +17,8 @@ void set_required_s(int64_t s) { g_req_s = s; }
 
 rsrs_status factor_impl(const rsrs_tree_t* th, rsrs_samples_t* smp, const rsrs_factor_opts* o,
                         hipStream_t st, rsrs_factor_t** out);
+rsrs_status factor_batch_impl(int64_t nprob, const rsrs_tree_t* const* trees, rsrs_samples_t* const* smps,
+                              const rsrs_factor_opts* opts, hipStream_t st, rsrs_factor_t** out);
 rsrs_status apply_factor(const rsrs_factor_t* F, int op, int transpose, int64_t w, const double* Fin,
                          int64_t ldf, double* Uout, int64_t ldu, hipStream_t st);
 
@@ -368,6 +370,13 @@ rsrs_status rsrs_factor(const rsrs_tree_t* t, rsrs_samples_t* smp, const rsrs_fa
   if (!t || !smp || !opts || !out) return invalid("null argument");
   *out = nullptr;
   return factor_impl(t, smp, opts, static_cast<hipStream_t>(stream), out);
+}
+
+rsrs_status rsrs_factor_batched(int64_t nprob, const rsrs_tree_t* const* trees,
+                                rsrs_samples_t* const* samples, const rsrs_factor_opts* opts,
+                                void* stream, rsrs_factor_t** out) {
+  if (nprob < 1 || !trees || !samples || !opts || !out) return invalid("bad batched factor arguments");
+  return factor_batch_impl(nprob, trees, samples, opts, static_cast<hipStream_t>(stream), out);
 }
 
 void rsrs_factor_destroy(rsrs_factor_t* f) { delete f; }

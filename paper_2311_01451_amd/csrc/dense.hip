@@ -509,30 +509,28 @@ __global__ void gje_copyout_kernel(const GjeDesc* __restrict__ e, int phase) {
   }
 }
 
-rsrs_status gje_inverse(Uploader& up, hipStream_t st, const std::vector<GjeDesc>& e, int* flag) {
+// The variant is chosen per matrix by its own size (register kernels for
+// n <= 64 / 128 / 192, the global two-launch form above), so a matrix is
+// inverted by the same instruction sequence whatever else is in the batch.
+static rsrs_status gje_group(Uploader& up, hipStream_t st, const std::vector<GjeDesc>& e, int* flag,
+                             int variant) {
   if (e.empty()) return RSRS_OK;
-  int nmax = 0;
-  for (const auto& x : e) {
-    if (x.n > 65536) {
-      set_error("Gauss-Jordan block too large");
-      return RSRS_E_UNSUPPORTED;
-    }
-    nmax = std::max(nmax, x.n);
-  }
   GjeDesc* de = nullptr;
   RSRS_TRY(up.put_vec(e, &de));
   const unsigned nb = (unsigned)e.size();
-  if (nmax <= 192) {
+  if (variant < 3) {
     ProfScope ps(st, "gauss_jordan_reg");
-    if (nmax <= 64)
+    if (variant == 0)
       hipLaunchKernelGGL(gje_reg_kernel<2>, dim3(nb), dim3(1024), 0, st, de, flag);
-    else if (nmax <= 128)
+    else if (variant == 1)
       hipLaunchKernelGGL(gje_reg_kernel<4>, dim3(nb), dim3(1024), 0, st, de, flag);
     else
       hipLaunchKernelGGL(gje_reg_kernel<6>, dim3(nb), dim3(1024), 0, st, de, flag);
     RSRS_HIP(hipGetLastError());
     return RSRS_OK;
   }
+  int nmax = 0;
+  for (const auto& x : e) nmax = std::max(nmax, x.n);
   // large blocks: snapshots of (pivot row, multiplier column) per matrix
   const int64_t stride = round_up(3 * (int64_t)nmax, 64);
   DevBuf snap;
@@ -548,6 +546,20 @@ rsrs_status gje_inverse(Uploader& up, hipStream_t st, const std::vector<GjeDesc>
   RSRS_HIP(hipGetLastError());
   // the snapshot buffer must outlive the launches
   RSRS_HIP(hipStreamSynchronize(st));
+  return RSRS_OK;
+}
+
+rsrs_status gje_inverse(Uploader& up, hipStream_t st, const std::vector<GjeDesc>& e, int* flag) {
+  if (e.empty()) return RSRS_OK;
+  std::vector<GjeDesc> grp[4];
+  for (const auto& x : e) {
+    if (x.n > 65536) {
+      set_error("Gauss-Jordan block too large");
+      return RSRS_E_UNSUPPORTED;
+    }
+    grp[x.n <= 64 ? 0 : x.n <= 128 ? 1 : x.n <= 192 ? 2 : 3].push_back(x);
+  }
+  for (int v = 0; v < 4; ++v) RSRS_TRY(gje_group(up, st, grp[v], flag, v));
   return RSRS_OK;
 }
 

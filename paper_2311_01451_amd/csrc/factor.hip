@@ -41,6 +41,8 @@
 #include <unordered_map>
 
 #include "impl.hpp"
+#include <memory>
+#include <string>
 
 namespace rsrs {
 
@@ -56,7 +58,10 @@ struct CholMat {
 constexpr int kLeaf = 64;
 
 // Recursive Cholesky with inverse factor on the index range [a, b) shared by
-// all matrices of the batch (each clipped to its own size n).
+// all matrices of the batch (each clipped to its own size n).  Callers pass
+// a range of 64 * 2^j indices (chol_span), so every split point depends only
+// on the position, never on the other matrices of the batch: a matrix gets
+// the same blocking, and the same rounding, alone or batched.
 rsrs_status rchol(Uploader& up, hipStream_t st, const std::vector<CholMat>& mats, int a, int b,
                   int* flag) {
   if (b - a <= kLeaf) {
@@ -98,6 +103,13 @@ rsrs_status rchol(Uploader& up, hipStream_t st, const std::vector<CholMat>& mats
   RSRS_TRY(rchol(up, st, mats, h, b, flag));
   RSRS_TRY(gemm(up, st, g5, 0, 0, GM_A_LOW, GS_64x64, "chol"));
   return RSRS_OK;
+}
+
+// Smallest range 64 * 2^j covering n indices.
+int chol_span(int n) {
+  int w = kLeaf;
+  while (w < n) w *= 2;
+  return w;
 }
 
 struct Bump {
@@ -146,131 +158,44 @@ struct BoxWs {
   int64_t *Spos, *Rpos;
 };
 
+// One problem of a factorization.  Problems advance through their colour
+// classes in lock step (class t of every problem that has one), so several
+// independent problems share every launch; a single problem is the special
+// case of one job.
 template <typename T>
-rsrs_status factor_t(const rsrs_tree_t* th, rsrs_samples_t* smp, const rsrs_factor_opts* o,
-                     hipStream_t st, rsrs_factor_t** out) {
-  constexpr bool mixed = sizeof(T) != sizeof(double);
-  constexpr int64_t al = 16 / (int64_t)sizeof(T);   // elements per 16 bytes
-  auto t0 = std::chrono::steady_clock::now();
-  const Tree& t = th->t;
-  const int k = o->k;
-  const int p = o->p < 0 ? k : o->p;
-  const int reproject = o->reproject;
+struct Job {
+  static constexpr bool mixed = sizeof(T) != sizeof(double);
+  static constexpr int64_t al = 16 / (int64_t)sizeof(T);   // elements per 16 bytes
+  const rsrs_tree_t* th = nullptr;
+  rsrs_samples_t* smp = nullptr;
+  int k = 0, p = 0, reproject = 1;
   Schedule sch;
-  make_schedule(t, k, sch);
-  const int64_t need = samples_required(t, sch, k, p);
-  if (smp->s < need) {
-    set_required_s(need);
-    set_error("s = " + std::to_string(smp->s) + " is below the required " + std::to_string(need));
-    return RSRS_E_SAMPLES;
-  }
-  const int64_t s = smp->s, sld = smp->ld, n = t.n;
-  T* Y = smp->Y.as<T>();
-  T* Z = smp->Z.as<T>();
-  T* Om = smp->Om.as<T>();
-  T* Psi = smp->Psi.as<T>();
-
-  auto F = std::make_unique<rsrs_factor_t>();
-  F->n = n;
-  F->s = s;
-  F->k = k;
-  F->precision = o->precision;
-  F->esz = (int)sizeof(T);
-
-  // ---- storage layout from the schedule (sizes are fixed by the count model)
-  int64_t dsz = 0, isz = 0;
-  size_t ws_max = 0;
-  for (size_t li = 0; li < sch.levels.size(); ++li) {
-    for (size_t c = 0; c < sch.classes[li].size(); ++c) {
-      Group g;
-      g.first = (int64_t)F->boxes.size();
-      size_t ws = 0;
-      for (int64_t b : sch.classes[li][c]) {
-        BoxRec r;
-        r.box = b;
-        r.level = sch.levels[li];
-        r.colour = (int)c;
-        r.b = sch.b_count[b];
-        r.n = sch.l_count[b] - r.b;
-        r.k = k;
-        r.r = r.b - k;
-        r.ldT = round_up(k, al);
-        r.ldR = round_up(r.r, al);
-        r.ldKU = round_up(k + r.n, al);
-        r.oT = round_up(dsz, al); dsz = r.oT + r.r * r.ldT;
-        r.oXRR = round_up(dsz, al); dsz = r.oXRR + r.r * r.ldR;
-        r.oXinv = round_up(dsz, al); dsz = r.oXinv + r.r * r.ldR;
-        r.oKU = round_up(dsz, al); dsz = r.oKU + r.r * r.ldKU;
-        r.oKL = round_up(dsz, al); dsz = r.oKL + (k + r.n) * r.ldR;
-        r.oR = isz; isz += r.r;
-        r.oS = isz; isz += k;
-        r.oNa = isz; isz += r.n;
-        r.oBa = isz; isz += r.b + r.n;   // Ba followed by a second copy of Na
-        F->boxes.push_back(r);
-        ws += box_ws_bytes<T>(r.b, r.b + r.n, k, sld);
-      }
-      g.count = (int64_t)F->boxes.size() - g.first;
-      F->groups.push_back(g);
-      ws_max = std::max(ws_max, ws);
-    }
-  }
-  F->nt = sch.root_count;
-  F->oBt = isz; isz += F->nt;
-  F->oAt = round_up(dsz, al); dsz = F->oAt + F->nt * F->nt;
-  F->oAtinv = round_up(dsz, al); dsz = F->oAtinv + F->nt * F->nt;
-  F->stored_values = dsz;
-  const int64_t ntp = round_up(F->nt, 16);
-  size_t root_ws = (size_t)(4 * F->nt * ntp + F->nt * round_up(s, 16) + 2 * F->nt * F->nt) * 8 + 8 * 256;
-  if (mixed)   // FP64 copies of Y_Bt, Omega_Bt, A_t, A_t^{-1}
-    root_ws += (size_t)(2 * F->nt * round_up(s, 16) + 2 * F->nt * F->nt) * 8 + 4 * 256;
-  ws_max = std::max(ws_max, root_ws);
-
-  RSRS_TRY(F->dstore.alloc((size_t)std::max<int64_t>(dsz, 1) * sizeof(T)));
-  RSRS_TRY(F->istore.alloc((size_t)std::max<int64_t>(isz, 1) * 8));
-  RSRS_TRY(F->perm.alloc((size_t)n * 8));
-  DevBuf ws, flagbuf;
-  RSRS_TRY(ws.alloc(ws_max));
-  RSRS_TRY(flagbuf.alloc(256));
-  int* flag = flagbuf.as<int>();
-  RSRS_HIP(hipMemsetAsync(flag, 0, sizeof(int), st));
-  T* dS = F->dstore.as<T>();
-  int64_t* iS = F->istore.as<int64_t>();
-
-  Uploader up;
-  RSRS_TRY(up.init((size_t)64 << 20, st));
-  RSRS_HIP(hipMemcpyAsync(F->perm.p, t.perm.data(), (size_t)n * 8, hipMemcpyHostToDevice, st));
-  // non-finite samples are rejected up front
-  check_finite(st, Y, n, s, sld, flag);
-  check_finite(st, Z, n, s, sld, flag);
-  check_finite(st, Om, n, s, sld, flag);
-  check_finite(st, Psi, n, s, sld, flag);
-  RSRS_TRY(up.reset());
-  {
-    int hflag = 0;
-    RSRS_HIP(hipMemcpy(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost));
-    if (hflag & 4) { set_error("non-finite value in the samples"); return RSRS_E_NUMERIC; }
-  }
-
-  // staging for index uploads into the factor store
-  HostBuf hidx;
-  RSRS_TRY(hidx.alloc((size_t)std::max<int64_t>(isz, 1) * 8));
-  int64_t* hI = hidx.as<int64_t>();
-  HostBuf hpos;
-
+  std::unique_ptr<rsrs_factor_t> F;
+  T *Y = nullptr, *Z = nullptr, *Om = nullptr, *Psi = nullptr;
+  int64_t s = 0, sld = 0, n = 0;
+  T* dS = nullptr;
+  int64_t* iS = nullptr;
+  HostBuf hidx;                 // staging of the index lists uploaded to istore
+  int64_t* hI = nullptr;
+  std::vector<std::vector<int64_t>> cur, remaining;
+  size_t li = 0, ci = 0;        // level index and class index of the next class
+  std::unordered_map<int64_t, size_t> pos;
+  std::vector<std::vector<int64_t>> Ba, Na;   // active sets of the current class
+  std::vector<size_t> class_ws;               // workspace bytes of each class
+  size_t root_ws = 0;
   double flops = 0.0;
-  const int64_t nbox = t.nbox();
-  std::vector<std::vector<int64_t>> cur(nbox), remaining(nbox);
-  auto leaf_range = [&](int64_t b) {
-    std::vector<int64_t> v((size_t)t.npts(b));
-    std::iota(v.begin(), v.end(), t.pt_begin[b]);
-    return v;
-  };
 
-  size_t gi = 0;
-  for (size_t li = 0; li < sch.levels.size(); ++li) {
-    const int lev = sch.levels[li];
-    const auto& lb = t.level_boxes[lev];
-    std::unordered_map<int64_t, size_t> pos;
+  const Tree& tree() const { return th->t; }
+  std::vector<int64_t> leaf_range(int64_t b) const {
+    std::vector<int64_t> v((size_t)tree().npts(b));
+    std::iota(v.begin(), v.end(), tree().pt_begin[b]);
+    return v;
+  }
+  // Active set of every box of the level about to run, from its children.
+  void enter_level() {
+    const Tree& t = tree();
+    const auto& lb = t.level_boxes[sch.levels[li]];
+    pos.clear();
     for (size_t i = 0; i < lb.size(); ++i) {
       const int64_t b = lb[i];
       pos[b] = i;
@@ -286,215 +211,399 @@ rsrs_status factor_t(const rsrs_tree_t* th, rsrs_samples_t* smp, const rsrs_fact
         cur[b] = std::move(v);
       }
     }
-    auto active_of = [&](int64_t x) -> const std::vector<int64_t>& {
-      if (t.level[x] < lev && cur[x].empty()) cur[x] = leaf_range(x);
-      return cur[x];
-    };
-    for (size_t c = 0; c < sch.classes[li].size(); ++c, ++gi) {
-      const Group& g = F->groups[gi];
-      const int64_t nb = g.count;
-      // ---- host index lists and factor-store uploads (Ba, Na, Na copy)
-      std::vector<std::vector<int64_t>> Ba(nb), Na(nb);
-      for (int64_t q = 0; q < nb; ++q) {
-        BoxRec& R = F->boxes[g.first + q];
-        const size_t ip = pos.at(R.box);
-        Ba[q] = cur[R.box];
+  }
+  void leave_level() {
+    for (int64_t b : tree().level_boxes[sch.levels[li]]) remaining[b] = cur[b];
+    ++li;
+    ci = 0;
+  }
+  // Levels without processed boxes keep every point active.
+  void settle() {
+    while (li < sch.levels.size() && sch.classes[li].empty()) {
+      enter_level();
+      leave_level();
+    }
+    if (li < sch.levels.size() && ci == 0) enter_level();
+  }
+  const std::vector<int64_t>& active_of(int64_t x) {
+    if (tree().level[x] < sch.levels[li] && cur[x].empty()) cur[x] = leaf_range(x);
+    return cur[x];
+  }
+};
+
+template <typename T>
+rsrs_status job_init(Job<T>& J, const rsrs_tree_t* th, rsrs_samples_t* smp,
+                     const rsrs_factor_opts* o) {
+  constexpr int64_t al = Job<T>::al;
+  constexpr bool mixed = Job<T>::mixed;
+  J.th = th;
+  J.smp = smp;
+  J.k = o->k;
+  J.p = o->p < 0 ? J.k : o->p;
+  J.reproject = o->reproject;
+  const Tree& t = th->t;
+  const int k = J.k;
+  make_schedule(t, k, J.sch);
+  const int64_t need = samples_required(t, J.sch, k, J.p);
+  if (smp->s < need) {
+    set_required_s(need);
+    set_error("s = " + std::to_string(smp->s) + " is below the required " + std::to_string(need));
+    return RSRS_E_SAMPLES;
+  }
+  J.s = smp->s;
+  J.sld = smp->ld;
+  J.n = t.n;
+  J.Y = smp->Y.as<T>();
+  J.Z = smp->Z.as<T>();
+  J.Om = smp->Om.as<T>();
+  J.Psi = smp->Psi.as<T>();
+  J.F = std::make_unique<rsrs_factor_t>();
+  rsrs_factor_t* F = J.F.get();
+  F->n = J.n;
+  F->s = J.s;
+  F->k = k;
+  F->precision = o->precision;
+  F->esz = (int)sizeof(T);
+
+  // storage layout from the schedule (sizes are fixed by the count model)
+  int64_t dsz = 0, isz = 0;
+  for (size_t li = 0; li < J.sch.levels.size(); ++li) {
+    for (size_t c = 0; c < J.sch.classes[li].size(); ++c) {
+      Group g;
+      g.first = (int64_t)F->boxes.size();
+      size_t ws = 0;
+      for (int64_t b : J.sch.classes[li][c]) {
+        BoxRec r;
+        r.box = b;
+        r.level = J.sch.levels[li];
+        r.colour = (int)c;
+        r.b = J.sch.b_count[b];
+        r.n = J.sch.l_count[b] - r.b;
+        r.k = k;
+        r.r = r.b - k;
+        r.ldT = round_up(k, al);
+        r.ldR = round_up(r.r, al);
+        r.ldKU = round_up(k + r.n, al);
+        r.oT = round_up(dsz, al); dsz = r.oT + r.r * r.ldT;
+        r.oXRR = round_up(dsz, al); dsz = r.oXRR + r.r * r.ldR;
+        r.oXinv = round_up(dsz, al); dsz = r.oXinv + r.r * r.ldR;
+        r.oKU = round_up(dsz, al); dsz = r.oKU + r.r * r.ldKU;
+        r.oKL = round_up(dsz, al); dsz = r.oKL + (k + r.n) * r.ldR;
+        r.oR = isz; isz += r.r;
+        r.oS = isz; isz += k;
+        r.oNa = isz; isz += r.n;
+        r.oBa = isz; isz += r.b + r.n;   // Ba followed by a second copy of Na
+        F->boxes.push_back(r);
+        ws += box_ws_bytes<T>(r.b, r.b + r.n, k, J.sld);
+      }
+      g.count = (int64_t)F->boxes.size() - g.first;
+      F->groups.push_back(g);
+      J.class_ws.push_back(ws);
+    }
+  }
+  F->nt = J.sch.root_count;
+  F->oBt = isz; isz += F->nt;
+  F->oAt = round_up(dsz, al); dsz = F->oAt + F->nt * F->nt;
+  F->oAtinv = round_up(dsz, al); dsz = F->oAtinv + F->nt * F->nt;
+  F->stored_values = dsz;
+  const int64_t ntp = round_up(F->nt, 16);
+  J.root_ws = (size_t)(4 * F->nt * ntp + F->nt * round_up(J.s, 16) + 2 * F->nt * F->nt) * 8 + 8 * 256;
+  if (mixed)   // FP64 copies of Y_Bt, Omega_Bt, A_t, A_t^{-1}
+    J.root_ws += (size_t)(2 * F->nt * round_up(J.s, 16) + 2 * F->nt * F->nt) * 8 + 4 * 256;
+
+  RSRS_TRY(F->dstore.alloc((size_t)std::max<int64_t>(dsz, 1) * sizeof(T)));
+  RSRS_TRY(F->istore.alloc((size_t)std::max<int64_t>(isz, 1) * 8));
+  RSRS_TRY(F->perm.alloc((size_t)J.n * 8));
+  RSRS_TRY(J.hidx.alloc((size_t)std::max<int64_t>(isz, 1) * 8));
+  J.hI = J.hidx.template as<int64_t>();
+  J.dS = F->dstore.template as<T>();
+  J.iS = F->istore.template as<int64_t>();
+  J.cur.assign((size_t)t.nbox(), {});
+  J.remaining.assign((size_t)t.nbox(), {});
+  J.settle();
+  return RSRS_OK;
+}
+
+// Per-box work item of one step: the job it belongs to, its record and workspace.
+template <typename T>
+struct Item {
+  Job<T>* J;
+  BoxRec* R;
+  BoxWs<T> w;
+};
+
+template <typename T>
+rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
+  constexpr bool mixed = Job<T>::mixed;
+  auto t0 = std::chrono::steady_clock::now();
+  size_t nsteps = 0, ws_max = 0, root_total = 0;
+  for (auto& J : jobs) nsteps = std::max(nsteps, J.F->groups.size());
+  for (size_t t = 0; t < nsteps; ++t) {
+    size_t w = 0;
+    for (auto& J : jobs)
+      if (t < J.class_ws.size()) w += J.class_ws[t];
+    ws_max = std::max(ws_max, w);
+  }
+  for (auto& J : jobs) root_total += J.root_ws;
+  ws_max = std::max(ws_max, root_total);
+
+  DevBuf ws, flagbuf;
+  RSRS_TRY(ws.alloc(ws_max));
+  RSRS_TRY(flagbuf.alloc(256));
+  int* flag = flagbuf.as<int>();
+  RSRS_HIP(hipMemsetAsync(flag, 0, sizeof(int), st));
+  Uploader up;
+  RSRS_TRY(up.init((size_t)64 << 20, st));
+  for (auto& J : jobs) {
+    RSRS_HIP(hipMemcpyAsync(J.F->perm.p, J.tree().perm.data(), (size_t)J.n * 8, hipMemcpyHostToDevice, st));
+    // non-finite samples are rejected up front
+    check_finite(st, J.Y, J.n, J.s, J.sld, flag);
+    check_finite(st, J.Z, J.n, J.s, J.sld, flag);
+    check_finite(st, J.Om, J.n, J.s, J.sld, flag);
+    check_finite(st, J.Psi, J.n, J.s, J.sld, flag);
+  }
+  RSRS_TRY(up.reset());
+  {
+    int hflag = 0;
+    RSRS_HIP(hipMemcpy(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost));
+    if (hflag & 4) { set_error("non-finite value in the samples"); return RSRS_E_NUMERIC; }
+  }
+  // from here on the samples are modified in place
+  for (auto& J : jobs) J.smp->consumed = true;
+
+  HostBuf hpos;
+  for (size_t t = 0; t < nsteps; ++t) {
+    // ---- host index lists and factor-store uploads (Ba, Na, Na copy)
+    std::vector<Item<T>> items;
+    for (auto& J : jobs) {
+      if (t >= J.F->groups.size()) continue;
+      const Tree& tr = J.tree();
+      const Group& g = J.F->groups[t];
+      const int lev = J.sch.levels[J.li];
+      J.Ba.assign((size_t)g.count, {});
+      J.Na.assign((size_t)g.count, {});
+      for (int64_t q = 0; q < g.count; ++q) {
+        BoxRec& R = J.F->boxes[g.first + q];
+        const size_t ip = J.pos.at(R.box);
+        J.Ba[q] = J.cur[R.box];
         std::vector<int64_t> v;
-        for (int64_t j = t.nb_off[lev][ip]; j < t.nb_off[lev][ip + 1]; ++j) {
-          const auto& a = active_of(t.nb_ids[lev][j]);
+        for (int64_t j = tr.nb_off[lev][ip]; j < tr.nb_off[lev][ip + 1]; ++j) {
+          const auto& a = J.active_of(tr.nb_ids[lev][j]);
           v.insert(v.end(), a.begin(), a.end());
         }
         std::sort(v.begin(), v.end());
-        Na[q] = std::move(v);
-        if ((int64_t)Ba[q].size() != R.b || (int64_t)Na[q].size() != R.n) {
+        J.Na[q] = std::move(v);
+        if ((int64_t)J.Ba[q].size() != R.b || (int64_t)J.Na[q].size() != R.n) {
           set_error("internal: active sets disagree with the count model");
           return RSRS_E_INVALID;
         }
-        std::memcpy(hI + R.oNa, Na[q].data(), R.n * 8);
-        std::memcpy(hI + R.oBa, Ba[q].data(), R.b * 8);
-        std::memcpy(hI + R.oBa + R.b, Na[q].data(), R.n * 8);
-        RSRS_HIP(hipMemcpyAsync(iS + R.oNa, hI + R.oNa, (size_t)(R.n + R.b + R.n) * 8,
+        std::memcpy(J.hI + R.oNa, J.Na[q].data(), R.n * 8);
+        std::memcpy(J.hI + R.oBa, J.Ba[q].data(), R.b * 8);
+        std::memcpy(J.hI + R.oBa + R.b, J.Na[q].data(), R.n * 8);
+        RSRS_HIP(hipMemcpyAsync(J.iS + R.oNa, J.hI + R.oNa, (size_t)(R.n + R.b + R.n) * 8,
                                 hipMemcpyHostToDevice, st));
+        items.push_back(Item<T>{&J, &R, {}});
       }
-      // ---- workspace
-      Bump bump{ws.as<char>(), 0, ws.bytes};
-      std::vector<BoxWs<T>> W(nb);
-      for (int64_t q = 0; q < nb; ++q) {
-        const BoxRec& R = F->boxes[g.first + q];
-        const int64_t l = R.b + R.n, lp = round_up(l, 16), b = R.b, r = R.r;
-        BoxWs<T>& w = W[q];
-        w.lp = lp;
-        w.GO = bump.take<double>(l * lp); w.GP = bump.take<double>(l * lp);
-        w.LO = bump.take<double>(l * lp); w.LP = bump.take<double>(l * lp);
-        w.PY = bump.take<T>(b * lp); w.WY = bump.take<T>(b * lp); w.XY = bump.take<T>(b * lp);
-        w.PZ = bump.take<T>(b * lp); w.WZ = bump.take<T>(b * lp); w.XZ = bump.take<T>(b * lp);
-        w.MY = bump.take<T>(b * sld); w.MZ = bump.take<T>(b * sld);
-        w.norms = bump.take<double>(2 * b); w.Rc = bump.take<double>(b * k);
-        w.XRy = bump.take<T>(r * lp); w.XRz = bump.take<T>(r * lp);
-        w.Xpy = bump.take<T>(r * lp); w.Xpz = bump.take<T>(r * lp);
-        w.gje = bump.take<double>(2 * r * r);
-        w.sel = bump.take<int32_t>(b); w.piv = bump.take<int32_t>(k);
-        w.Spos = bump.take<int64_t>(k); w.Rpos = bump.take<int64_t>(b);
-        if constexpr (mixed) {
-          w.LOt = bump.take<T>(l * lp); w.LPt = bump.take<T>(l * lp);
-          w.Md = bump.take<double>(b * sld);
-          w.Td = bump.take<double>(r * round_up(k, 4));
-          w.XRRd = bump.take<double>(r * r); w.Xinvd = bump.take<double>(r * r);
-        } else {
-          w.LOt = reinterpret_cast<T*>(w.LO); w.LPt = reinterpret_cast<T*>(w.LP);
-          w.Md = w.Td = w.XRRd = w.Xinvd = nullptr;
-        }
+    }
+    // ---- workspace
+    Bump bump{ws.as<char>(), 0, ws.bytes};
+    for (auto& it : items) {
+      const BoxRec& R = *it.R;
+      const int k = it.J->k;
+      const int64_t sld = it.J->sld;
+      const int64_t l = R.b + R.n, lp = round_up(l, 16), b = R.b, r = R.r;
+      BoxWs<T>& w = it.w;
+      w.lp = lp;
+      w.GO = bump.take<double>(l * lp); w.GP = bump.take<double>(l * lp);
+      w.LO = bump.take<double>(l * lp); w.LP = bump.take<double>(l * lp);
+      w.PY = bump.take<T>(b * lp); w.WY = bump.take<T>(b * lp); w.XY = bump.take<T>(b * lp);
+      w.PZ = bump.take<T>(b * lp); w.WZ = bump.take<T>(b * lp); w.XZ = bump.take<T>(b * lp);
+      w.MY = bump.take<T>(b * sld); w.MZ = bump.take<T>(b * sld);
+      w.norms = bump.take<double>(2 * b); w.Rc = bump.take<double>(b * k);
+      w.XRy = bump.take<T>(r * lp); w.XRz = bump.take<T>(r * lp);
+      w.Xpy = bump.take<T>(r * lp); w.Xpz = bump.take<T>(r * lp);
+      w.gje = bump.take<double>(2 * r * r);
+      w.sel = bump.take<int32_t>(b); w.piv = bump.take<int32_t>(k);
+      w.Spos = bump.take<int64_t>(k); w.Rpos = bump.take<int64_t>(b);
+      if constexpr (mixed) {
+        w.LOt = bump.take<T>(l * lp); w.LPt = bump.take<T>(l * lp);
+        w.Md = bump.take<double>(b * sld);
+        w.Td = bump.take<double>(r * round_up(k, 4));
+        w.XRRd = bump.take<double>(r * r); w.Xinvd = bump.take<double>(r * r);
+      } else {
+        w.LOt = reinterpret_cast<T*>(w.LO); w.LPt = reinterpret_cast<T*>(w.LP);
+        w.Md = w.Td = w.XRRd = w.Xinvd = nullptr;
       }
-      if (bump.off > bump.cap) { set_error("internal: workspace overflow"); return RSRS_E_INVALID; }
-      // ---- phase A: Gram matrices (FP64 storage in both precisions)
+    }
+    if (bump.off > bump.cap) { set_error("internal: workspace overflow"); return RSRS_E_INVALID; }
+
+    // ---- phase A: Gram matrices (FP64 storage in both precisions)
+    {
       std::vector<GemmDescT<T, double>> gd;
       std::vector<CholMat> cm;
       int lmax = 0;
-      for (int64_t q = 0; q < nb; ++q) {
-        const BoxRec& R = F->boxes[g.first + q];
-        const BoxWs<T>& w = W[q];
+      for (auto& it : items) {
+        const BoxRec& R = *it.R;
+        const Job<T>& J = *it.J;
+        const BoxWs<T>& w = it.w;
         const int l = (int)(R.b + R.n);
-        const int64_t* idxC = iS + R.oBa;
-        gd.push_back(gdescT<T, double>(Om, idxC, sld, Om, idxC, sld, w.GO, nullptr, w.lp, l, l, (int)s));
-        gd.push_back(gdescT<T, double>(Psi, idxC, sld, Psi, idxC, sld, w.GP, nullptr, w.lp, l, l, (int)s));
+        const int64_t* idxC = J.iS + R.oBa;
+        gd.push_back(gdescT<T, double>(J.Om, idxC, J.sld, J.Om, idxC, J.sld, w.GO, nullptr, w.lp, l, l, (int)J.s));
+        gd.push_back(gdescT<T, double>(J.Psi, idxC, J.sld, J.Psi, idxC, J.sld, w.GP, nullptr, w.lp, l, l, (int)J.s));
         cm.push_back(CholMat{w.GO, w.LO, w.lp, l});
         cm.push_back(CholMat{w.GP, w.LP, w.lp, l});
         lmax = std::max(lmax, l);
-        const double dl = l, db = (double)R.b, ds = (double)s;
-        flops += 2.0 * dl * dl * ds                               // two Gram matrices
-                 + 2.0 * (2.0 / 3.0) * dl * dl * dl               // Cholesky + inverse factor
-                 + (1.0 + reproject) * 2.0 * (4.0 * db * dl * ds + 2.0 * db * dl * dl);  // projections
+        const double dl = l, db = (double)R.b, ds = (double)J.s;
+        it.J->flops += 2.0 * dl * dl * ds                               // two Gram matrices
+                       + 2.0 * (2.0 / 3.0) * dl * dl * dl               // Cholesky + inverse factor
+                       + (1.0 + J.reproject) * 2.0 * (4.0 * db * dl * ds + 2.0 * db * dl * dl);  // projections
       }
       RSRS_TRY(gemm<T, double>(up, st, gd, 0, 1, GM_SYRK_L, GS_64x64, "gram"));
-      RSRS_TRY(rchol(up, st, cm, 0, lmax, flag));
+      RSRS_TRY(rchol(up, st, cm, 0, chol_span(lmax), flag));
       if constexpr (mixed) {   // inverse factors rounded for the FP32 products
         std::vector<Copy2DT<double, T>> lc;
-        for (int64_t q = 0; q < nb; ++q) {
-          const BoxRec& R = F->boxes[g.first + q];
-          const BoxWs<T>& w = W[q];
-          const int l = (int)(R.b + R.n);
-          lc.push_back(Copy2DT<double, T>{w.LO, w.LOt, w.lp, w.lp, l, l, 1.0, 0, 0});
-          lc.push_back(Copy2DT<double, T>{w.LP, w.LPt, w.lp, w.lp, l, l, 1.0, 0, 0});
+        for (auto& it : items) {
+          const int l = (int)(it.R->b + it.R->n);
+          lc.push_back(Copy2DT<double, T>{it.w.LO, it.w.LOt, it.w.lp, it.w.lp, l, l, 1.0, 0, 0});
+          lc.push_back(Copy2DT<double, T>{it.w.LP, it.w.LPt, it.w.lp, it.w.lp, l, l, 1.0, 0, 0});
         }
         RSRS_TRY(copy2d<double, T>(up, st, lc));
       }
-      // ---- projections (eq. nullYZ) and least-squares coefficients
-      for (int pass = 0; pass <= reproject; ++pass) {
-        std::vector<GemmDescT<T, T>> gp, gw, gx, gm;
-        std::vector<Copy2DT<T, T>> acc;
-        for (int64_t q = 0; q < nb; ++q) {
-          const BoxRec& R = F->boxes[g.first + q];
-          const BoxWs<T>& w = W[q];
-          const int l = (int)(R.b + R.n), b = (int)R.b;
-          const int64_t* idxB = iS + R.oBa;
-          const int64_t* idxC = iS + R.oBa;
-          for (int side = 0; side < 2; ++side) {
-            T* Ysd = side ? Z : Y;
-            T* Tst = side ? Psi : Om;
-            T* Pb = side ? w.PZ : w.PY;
-            T* Wb = side ? w.WZ : w.WY;
-            T* Xb = side ? w.XZ : w.XY;
-            T* Mb = side ? w.MZ : w.MY;
-            T* Lb = side ? w.LPt : w.LOt;
-            T* Xout = pass == 0 ? Xb : Pb;   // second pass: correction into P
-            if (pass == 0)
-              gp.push_back(gdescT<T, T>(Ysd, idxB, sld, Tst, idxC, sld, Pb, nullptr, w.lp, b, l, (int)s));
-            else
-              gp.push_back(gdescT<T, T>(Mb, nullptr, sld, Tst, idxC, sld, Pb, nullptr, w.lp, b, l, (int)s));
-            gw.push_back(gdescT<T, T>(Pb, nullptr, w.lp, Lb, nullptr, w.lp, Wb, nullptr, w.lp, b, l, l));
-            gx.push_back(gdescT<T, T>(Wb, nullptr, w.lp, Lb, nullptr, w.lp, Xout, nullptr, w.lp, b, l, l));
-            if (pass == 0)
-              gm.push_back(gdescT<T, T>(Xout, nullptr, w.lp, Tst, idxC, sld, Mb, nullptr, sld, b, (int)s, l,
-                                        -1.0, 1.0, Ysd, idxB, sld));
-            else
-              gm.push_back(gdescT<T, T>(Xout, nullptr, w.lp, Tst, idxC, sld, Mb, nullptr, sld, b, (int)s, l,
-                                        -1.0, 1.0));
-            if (pass == 1) acc.push_back(Copy2DT<T, T>{Pb, Xb, w.lp, w.lp, b, l, 1.0, 1, 0});
-          }
+    }
+    // ---- projections (eq. nullYZ) and least-squares coefficients
+    for (int pass = 0; pass <= 1; ++pass) {
+      std::vector<GemmDescT<T, T>> gp, gw, gx, gm;
+      std::vector<Copy2DT<T, T>> acc;
+      for (auto& it : items) {
+        const Job<T>& J = *it.J;
+        if (pass > J.reproject) continue;
+        const BoxRec& R = *it.R;
+        const BoxWs<T>& w = it.w;
+        const int l = (int)(R.b + R.n), b = (int)R.b;
+        const int64_t* idxB = J.iS + R.oBa;
+        const int64_t* idxC = J.iS + R.oBa;
+        const int64_t sld = J.sld;
+        for (int side = 0; side < 2; ++side) {
+          T* Ysd = side ? J.Z : J.Y;
+          T* Tst = side ? J.Psi : J.Om;
+          T* Pb = side ? w.PZ : w.PY;
+          T* Wb = side ? w.WZ : w.WY;
+          T* Xb = side ? w.XZ : w.XY;
+          T* Mb = side ? w.MZ : w.MY;
+          T* Lb = side ? w.LPt : w.LOt;
+          T* Xout = pass == 0 ? Xb : Pb;   // second pass: correction into P
+          if (pass == 0)
+            gp.push_back(gdescT<T, T>(Ysd, idxB, sld, Tst, idxC, sld, Pb, nullptr, w.lp, b, l, (int)J.s));
+          else
+            gp.push_back(gdescT<T, T>(Mb, nullptr, sld, Tst, idxC, sld, Pb, nullptr, w.lp, b, l, (int)J.s));
+          gw.push_back(gdescT<T, T>(Pb, nullptr, w.lp, Lb, nullptr, w.lp, Wb, nullptr, w.lp, b, l, l));
+          gx.push_back(gdescT<T, T>(Wb, nullptr, w.lp, Lb, nullptr, w.lp, Xout, nullptr, w.lp, b, l, l));
+          if (pass == 0)
+            gm.push_back(gdescT<T, T>(Xout, nullptr, w.lp, Tst, idxC, sld, Mb, nullptr, sld, b, (int)J.s, l,
+                                      -1.0, 1.0, Ysd, idxB, sld));
+          else
+            gm.push_back(gdescT<T, T>(Xout, nullptr, w.lp, Tst, idxC, sld, Mb, nullptr, sld, b, (int)J.s, l,
+                                      -1.0, 1.0));
+          if (pass == 1) acc.push_back(Copy2DT<T, T>{Pb, Xb, w.lp, w.lp, b, l, 1.0, 1, 0});
         }
-        RSRS_TRY(gemm<T, T>(up, st, gp, 0, 1, GM_FULL, GS_64x64, "proj"));
-        RSRS_TRY(gemm<T, T>(up, st, gw, 0, 1, GM_B_NT_LOW, GS_64x64, "proj"));
-        RSRS_TRY(gemm<T, T>(up, st, gx, 0, 0, GM_B_NN_LOW, GS_64x64, "proj"));
-        RSRS_TRY(gemm<T, T>(up, st, gm, 0, 0, GM_FULL, GS_64x64, "proj"));
-        RSRS_TRY(copy2d<T, T>(up, st, acc));
       }
-      // ---- interpolative decomposition of M = M_Y + M_Z
+      if (gp.empty()) continue;
+      RSRS_TRY(gemm<T, T>(up, st, gp, 0, 1, GM_FULL, GS_64x64, "proj"));
+      RSRS_TRY(gemm<T, T>(up, st, gw, 0, 1, GM_B_NT_LOW, GS_64x64, "proj"));
+      RSRS_TRY(gemm<T, T>(up, st, gx, 0, 0, GM_B_NN_LOW, GS_64x64, "proj"));
+      RSRS_TRY(gemm<T, T>(up, st, gm, 0, 0, GM_FULL, GS_64x64, "proj"));
+      RSRS_TRY(copy2d<T, T>(up, st, acc));
+    }
+    // ---- interpolative decomposition of M = M_Y + M_Z
+    {
       std::vector<IdDesc> idd;
-      for (int64_t q = 0; q < nb; ++q) {
-        const BoxRec& R = F->boxes[g.first + q];
-        const BoxWs<T>& w = W[q];
+      for (auto& it : items) {
+        const BoxRec& R = *it.R;
+        const Job<T>& J = *it.J;
+        const BoxWs<T>& w = it.w;
         IdDesc e{};
         if constexpr (mixed) {
-          e.M = w.Md; e.MZ = nullptr; e.ldm = sld; e.ldz = sld;
-          e.MYf = w.MY; e.MZf = w.MZ; e.ldf = sld;
-          e.T = w.Td; e.ldt = (int)round_up(k, 4);
+          e.M = w.Md; e.MZ = nullptr; e.ldm = J.sld; e.ldz = J.sld;
+          e.MYf = w.MY; e.MZf = w.MZ; e.ldf = J.sld;
+          e.T = w.Td; e.ldt = (int)round_up(J.k, 4);
         } else {
-          e.M = w.MY; e.MZ = w.MZ; e.ldm = sld; e.ldz = sld;
-          e.T = dS + R.oT; e.ldt = (int)R.ldT;
+          e.M = w.MY; e.MZ = w.MZ; e.ldm = J.sld; e.ldz = J.sld;
+          e.T = J.dS + R.oT; e.ldt = (int)R.ldT;
         }
         e.norms = w.norms; e.sel = w.sel; e.Rc = w.Rc; e.piv = w.piv;
         e.Spos = w.Spos; e.Rpos = w.Rpos;
-        e.b = (int)R.b; e.s = (int)s; e.k = k;
+        e.b = (int)R.b; e.s = (int)J.s; e.k = J.k;
         idd.push_back(e);
-        flops += 4.0 * R.b * s * k;
+        it.J->flops += 4.0 * R.b * J.s * J.k;
       }
       RSRS_TRY(id_run(up, st, idd));
       if constexpr (mixed) {   // T rounded into the factor store
         std::vector<Copy2DT<double, T>> tc;
-        for (int64_t q = 0; q < nb; ++q) {
-          const BoxRec& R = F->boxes[g.first + q];
-          tc.push_back(Copy2DT<double, T>{W[q].Td, dS + R.oT, round_up(k, 4), R.ldT, (int)R.r, k, 1.0, 0, 0});
+        for (auto& it : items) {
+          const BoxRec& R = *it.R;
+          const int k = it.J->k;
+          tc.push_back(Copy2DT<double, T>{it.w.Td, it.J->dS + R.oT, round_up(k, 4), R.ldT, (int)R.r, k, 1.0, 0, 0});
         }
         RSRS_TRY(copy2d<double, T>(up, st, tc));
       }
-      // ---- skeleton sets back to the host
+    }
+    // ---- skeleton sets back to the host
+    {
       int64_t nposn = 0;
-      for (int64_t q = 0; q < nb; ++q) nposn += F->boxes[g.first + q].b;
+      for (auto& it : items) nposn += it.R->b;
       RSRS_TRY(hpos.alloc((size_t)nposn * 8));
-      {
-        int64_t o2 = 0;
-        for (int64_t q = 0; q < nb; ++q) {
-          const BoxRec& R = F->boxes[g.first + q];
-          RSRS_HIP(hipMemcpyAsync(hpos.as<int64_t>() + o2, W[q].Spos, (size_t)k * 8, hipMemcpyDeviceToHost, st));
-          RSRS_HIP(hipMemcpyAsync(hpos.as<int64_t>() + o2 + k, W[q].Rpos, (size_t)R.r * 8, hipMemcpyDeviceToHost, st));
-          o2 += R.b;
-        }
+      int64_t o2 = 0;
+      for (auto& it : items) {
+        const BoxRec& R = *it.R;
+        const int k = it.J->k;
+        RSRS_HIP(hipMemcpyAsync(hpos.as<int64_t>() + o2, it.w.Spos, (size_t)k * 8, hipMemcpyDeviceToHost, st));
+        RSRS_HIP(hipMemcpyAsync(hpos.as<int64_t>() + o2 + k, it.w.Rpos, (size_t)R.r * 8, hipMemcpyDeviceToHost, st));
+        o2 += R.b;
       }
-      RSRS_TRY(up.reset());
-      {
-        int hflag = 0;
-        RSRS_HIP(hipMemcpy(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost));
-        if (hflag & 1) {
-          set_error("Gram matrix of a test-matrix panel is not positive definite (rank-deficient panel)");
-          return RSRS_E_SINGULAR;
-        }
+    }
+    RSRS_TRY(up.reset());
+    {
+      int hflag = 0;
+      RSRS_HIP(hipMemcpy(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost));
+      if (hflag & 1) {
+        set_error("Gram matrix of a test-matrix panel is not positive definite (rank-deficient panel)");
+        return RSRS_E_SINGULAR;
       }
-      // ---- phase B: global R / S / SN lists
-      {
-        int64_t o2 = 0;
-        for (int64_t q = 0; q < nb; ++q) {
-          BoxRec& R = F->boxes[g.first + q];
-          const int64_t* sp = hpos.as<int64_t>() + o2;
-          const int64_t* rp = sp + k;
-          std::vector<int64_t> Sg(k), Rg(R.r);
-          for (int j = 0; j < k; ++j) Sg[j] = Ba[q][sp[j]];
-          for (int64_t j = 0; j < R.r; ++j) Rg[j] = Ba[q][rp[j]];
-          std::memcpy(hI + R.oR, Rg.data(), R.r * 8);
-          std::memcpy(hI + R.oS, Sg.data(), (size_t)k * 8);
-          RSRS_HIP(hipMemcpyAsync(iS + R.oR, hI + R.oR, (size_t)(R.r + k) * 8, hipMemcpyHostToDevice, st));
-          cur[R.box] = std::move(Sg);
-          o2 += R.b;
-        }
+    }
+    // ---- phase B: global R / S / SN lists
+    {
+      int64_t o2 = 0;
+      std::unordered_map<Job<T>*, int64_t> qidx;
+      for (auto& it : items) {
+        Job<T>& J = *it.J;
+        BoxRec& R = *it.R;
+        const int k = J.k;
+        const int64_t q = qidx[&J]++;
+        const int64_t* sp = hpos.as<int64_t>() + o2;
+        const int64_t* rp = sp + k;
+        std::vector<int64_t> Sg(k), Rg(R.r);
+        for (int j = 0; j < k; ++j) Sg[j] = J.Ba[q][sp[j]];
+        for (int64_t j = 0; j < R.r; ++j) Rg[j] = J.Ba[q][rp[j]];
+        std::memcpy(J.hI + R.oR, Rg.data(), R.r * 8);
+        std::memcpy(J.hI + R.oS, Sg.data(), (size_t)k * 8);
+        RSRS_HIP(hipMemcpyAsync(J.iS + R.oR, J.hI + R.oR, (size_t)(R.r + k) * 8, hipMemcpyHostToDevice, st));
+        J.cur[R.box] = std::move(Sg);
+        o2 += R.b;
       }
+    }
+    {
       std::vector<GemmDescT<T, T>> gxr;
       std::vector<ColfixDescT<T>> cf;
       std::vector<Copy2DT<T, T>> cx;
       std::vector<Copy2DT<T, double>> cxd;
       std::vector<Copy2DT<double, T>> cinv;
       std::vector<GjeDesc> gj;
-      for (int64_t q = 0; q < nb; ++q) {
-        const BoxRec& R = F->boxes[g.first + q];
-        const BoxWs<T>& w = W[q];
+      for (auto& it : items) {
+        const BoxRec& R = *it.R;
+        Job<T>& J = *it.J;
+        const BoxWs<T>& w = it.w;
+        const int k = J.k;
+        T* dS = J.dS;
         const int l = (int)(R.b + R.n), r = (int)R.r;
         for (int side = 0; side < 2; ++side) {
           T* Xb = side ? w.XZ : w.XY;
@@ -510,11 +619,12 @@ rsrs_status factor_t(const rsrs_tree_t* th, rsrs_samples_t* smp, const rsrs_fact
           gj.push_back(GjeDesc{w.XRRd, w.gje, w.Xinvd, r, r, r, 0});
           cinv.push_back(Copy2DT<double, T>{w.Xinvd, dS + R.oXinv, r, R.ldR, r, r, 1.0, 0, 0});
         } else {
-          gj.push_back(GjeDesc{w.Xpy, w.gje, dS + R.oXinv, w.lp, R.ldR, r, 0});
+          gj.push_back(GjeDesc{reinterpret_cast<const double*>(w.Xpy), w.gje,
+                               reinterpret_cast<double*>(dS + R.oXinv), w.lp, R.ldR, r, 0});
         }
-        const double dr = r, dk = k, dn = (double)R.n, ds = (double)s;
-        flops += 2.0 * (2.0 * dr * dk * l + 2.0 * dr * dr * dk) + 2.0 * dr * dr * dr +
-                 2.0 * 2.0 * dr * dr * (dk + dn) + 4.0 * 2.0 * dr * dk * ds + 4.0 * 2.0 * dr * (dk + dn) * ds;
+        const double dr = r, dk = k, dn = (double)R.n, ds = (double)J.s;
+        J.flops += 2.0 * (2.0 * dr * dk * l + 2.0 * dr * dr * dk) + 2.0 * dr * dr * dr +
+                   2.0 * 2.0 * dr * dr * (dk + dn) + 4.0 * 2.0 * dr * dk * ds + 4.0 * 2.0 * dr * (dk + dn) * ds;
       }
       RSRS_TRY(gemm<T, T>(up, st, gxr, 0, 0, GM_FULL, GS_64x64, "extract"));
       RSRS_TRY(colfix<T>(up, st, cf));
@@ -522,36 +632,44 @@ rsrs_status factor_t(const rsrs_tree_t* th, rsrs_samples_t* smp, const rsrs_fact
       RSRS_TRY(copy2d<T, double>(up, st, cxd));
       RSRS_TRY(gje_inverse(up, st, gj, flag));
       RSRS_TRY(copy2d<double, T>(up, st, cinv));
+    }
+    {
       std::vector<GemmDescT<T, T>> gku, gkl;
-      for (int64_t q = 0; q < nb; ++q) {
-        const BoxRec& R = F->boxes[g.first + q];
-        const BoxWs<T>& w = W[q];
-        const int r = (int)R.r, kn = (int)(k + R.n);
+      for (auto& it : items) {
+        const BoxRec& R = *it.R;
+        const BoxWs<T>& w = it.w;
+        T* dS = it.J->dS;
+        const int r = (int)R.r, kn = (int)(it.J->k + R.n);
         gku.push_back(gdescT<T, T>(dS + R.oXinv, nullptr, R.ldR, w.Xpy + r, nullptr, w.lp, dS + R.oKU, nullptr, R.ldKU, r, kn, r));
         gkl.push_back(gdescT<T, T>(w.Xpz + r, nullptr, w.lp, dS + R.oXinv, nullptr, R.ldR, dS + R.oKL, nullptr, R.ldR, kn, r, r));
       }
       RSRS_TRY(gemm<T, T>(up, st, gku, 0, 0, GM_FULL, GS_64x64, "mult"));
       RSRS_TRY(gemm<T, T>(up, st, gkl, 1, 0, GM_FULL, GS_64x64, "mult"));
-      // ---- sketch updates: sparsify (E, F) then eliminate (L, U)
+    }
+    // ---- sketch updates: sparsify (E, F) then eliminate (L, U)
+    {
       std::vector<GemmDescT<T, T>> s0, s1, e0, e1, e0b, e1b;
-      for (int64_t q = 0; q < nb; ++q) {
-        const BoxRec& R = F->boxes[g.first + q];
+      for (auto& it : items) {
+        const BoxRec& R = *it.R;
+        const Job<T>& J = *it.J;
+        const int k = J.k, s = (int)J.s;
+        const int64_t sld = J.sld;
         const int r = (int)R.r, kn = (int)(k + R.n);
-        const int64_t* gR = iS + R.oR;
-        const int64_t* gS = iS + R.oS;
-        const int64_t* gSN = iS + R.oS;
-        const T* Tm = dS + R.oT;
-        const T* KU = dS + R.oKU;
-        const T* KL = dS + R.oKL;
+        const int64_t* gR = J.iS + R.oR;
+        const int64_t* gS = J.iS + R.oS;
+        const int64_t* gSN = J.iS + R.oS;
+        const T* Tm = J.dS + R.oT;
+        const T* KU = J.dS + R.oKU;
+        const T* KL = J.dS + R.oKL;
         const int64_t lT = R.ldT, lR = R.ldR, lU = R.ldKU;
-        s0.push_back(gdescT<T, T>(Tm, nullptr, lT, Y, gS, sld, Y, gR, sld, r, (int)s, k, -1.0, 1.0));
-        s0.push_back(gdescT<T, T>(Tm, nullptr, lT, Z, gS, sld, Z, gR, sld, r, (int)s, k, -1.0, 1.0));
-        s1.push_back(gdescT<T, T>(Tm, nullptr, lT, Om, gR, sld, Om, gS, sld, k, (int)s, r, 1.0, 1.0));
-        s1.push_back(gdescT<T, T>(Tm, nullptr, lT, Psi, gR, sld, Psi, gS, sld, k, (int)s, r, 1.0, 1.0));
-        e0.push_back(gdescT<T, T>(KL, nullptr, lR, Y, gR, sld, Y, gSN, sld, kn, (int)s, r, -1.0, 1.0));
-        e0b.push_back(gdescT<T, T>(KU, nullptr, lU, Om, gSN, sld, Om, gR, sld, r, (int)s, kn, 1.0, 1.0));
-        e1.push_back(gdescT<T, T>(KU, nullptr, lU, Z, gR, sld, Z, gSN, sld, kn, (int)s, r, -1.0, 1.0));
-        e1b.push_back(gdescT<T, T>(KL, nullptr, lR, Psi, gSN, sld, Psi, gR, sld, r, (int)s, kn, 1.0, 1.0));
+        s0.push_back(gdescT<T, T>(Tm, nullptr, lT, J.Y, gS, sld, J.Y, gR, sld, r, s, k, -1.0, 1.0));
+        s0.push_back(gdescT<T, T>(Tm, nullptr, lT, J.Z, gS, sld, J.Z, gR, sld, r, s, k, -1.0, 1.0));
+        s1.push_back(gdescT<T, T>(Tm, nullptr, lT, J.Om, gR, sld, J.Om, gS, sld, k, s, r, 1.0, 1.0));
+        s1.push_back(gdescT<T, T>(Tm, nullptr, lT, J.Psi, gR, sld, J.Psi, gS, sld, k, s, r, 1.0, 1.0));
+        e0.push_back(gdescT<T, T>(KL, nullptr, lR, J.Y, gR, sld, J.Y, gSN, sld, kn, s, r, -1.0, 1.0));
+        e0b.push_back(gdescT<T, T>(KU, nullptr, lU, J.Om, gSN, sld, J.Om, gR, sld, r, s, kn, 1.0, 1.0));
+        e1.push_back(gdescT<T, T>(KU, nullptr, lU, J.Z, gR, sld, J.Z, gSN, sld, kn, s, r, -1.0, 1.0));
+        e1b.push_back(gdescT<T, T>(KL, nullptr, lR, J.Psi, gSN, sld, J.Psi, gR, sld, r, s, kn, 1.0, 1.0));
       }
       RSRS_TRY(gemm<T, T>(up, st, s0, 0, 0, GM_FULL, GS_64x64, "sparsify"));
       RSRS_TRY(gemm<T, T>(up, st, s1, 1, 0, GM_FULL, GS_64x64, "sparsify"));
@@ -560,75 +678,124 @@ rsrs_status factor_t(const rsrs_tree_t* th, rsrs_samples_t* smp, const rsrs_fact
       RSRS_TRY(gemm<T, T>(up, st, e0b, 0, 0, GM_FULL, GS_64x64, "elim_r"));
       RSRS_TRY(gemm<T, T>(up, st, e1b, 1, 0, GM_FULL, GS_64x64, "elim_r"));
     }
-    for (int64_t b : lb) remaining[b] = cur[b];
+    // ---- advance every job past this class
+    for (auto& J : jobs) {
+      if (t >= J.F->groups.size()) continue;
+      ++J.ci;
+      if (J.ci == J.sch.classes[J.li].size()) {
+        J.leave_level();
+        J.settle();
+      }
+    }
   }
 
-  // ---- root: A_t = Y_Bt pinv(Omega_Bt)
+  // ---- roots: A_t = Y_Bt pinv(Omega_Bt), all problems in the same launches
   {
-    std::vector<int64_t> Bt;
-    if (t.nlevels == 0) {
-      Bt.resize(n);
-      std::iota(Bt.begin(), Bt.end(), 0);
-    } else {
-      for (int64_t b : t.level_boxes[1]) Bt.insert(Bt.end(), remaining[b].begin(), remaining[b].end());
-      std::sort(Bt.begin(), Bt.end());
-    }
-    if ((int64_t)Bt.size() != F->nt) { set_error("internal: root size mismatch"); return RSRS_E_INVALID; }
-    const int nt = (int)F->nt;
-    std::memcpy(hI + F->oBt, Bt.data(), (size_t)nt * 8);
-    RSRS_HIP(hipMemcpyAsync(iS + F->oBt, hI + F->oBt, (size_t)nt * 8, hipMemcpyHostToDevice, st));
-    const int64_t* iBt = iS + F->oBt;
     Bump bump{ws.as<char>(), 0, ws.bytes};
-    double* G = bump.take<double>(nt * ntp);
-    double* L = bump.take<double>(nt * ntp);
-    double* P = bump.take<double>(nt * ntp);
-    double* Wb = bump.take<double>(nt * ntp);
-    double* Rres = bump.take<double>(nt * round_up(s, 16));
-    double* gw = bump.take<double>(2 * (int64_t)nt * nt);
-    // FP64 operands of the root: the samples themselves (rows iBt), or FP64
-    // copies of the rows B_t in mixed precision
-    const double* Yr;
-    const double* Or;
-    const int64_t* ir;
-    int64_t rld;
-    double* At;
-    double* Atinv;
-    if constexpr (mixed) {
-      const int64_t sp = round_up(s, 16);
-      double* Yd = bump.take<double>(nt * sp);
-      double* Od = bump.take<double>(nt * sp);
-      At = bump.take<double>((int64_t)nt * nt);
-      Atinv = bump.take<double>((int64_t)nt * nt);
-      gather_rows<T, double>(st, Yd, sp, Y, sld, iBt, nt, s);
-      gather_rows<T, double>(st, Od, sp, Om, sld, iBt, nt, s);
-      Yr = Yd; Or = Od; ir = nullptr; rld = sp;
-    } else {
-      Yr = reinterpret_cast<const double*>(Y);
-      Or = reinterpret_cast<const double*>(Om);
-      ir = iBt; rld = sld;
-      At = reinterpret_cast<double*>(dS + F->oAt);
-      Atinv = reinterpret_cast<double*>(dS + F->oAtinv);
+    struct Root {
+      const double *Yr, *Or;
+      const int64_t* ir;
+      int64_t rld, ntp, rp;
+      double *G, *L, *P, *Wb, *Rres, *gw, *At, *Atinv;
+      int nt, s, reproject;
+    };
+    std::vector<Root> roots;
+    for (auto& J : jobs) {
+      rsrs_factor_t* F = J.F.get();
+      const Tree& tr = J.tree();
+      std::vector<int64_t> Bt;
+      if (tr.nlevels == 0) {
+        Bt.resize((size_t)J.n);
+        std::iota(Bt.begin(), Bt.end(), 0);
+      } else {
+        for (int64_t b : tr.level_boxes[1]) Bt.insert(Bt.end(), J.remaining[b].begin(), J.remaining[b].end());
+        std::sort(Bt.begin(), Bt.end());
+      }
+      if ((int64_t)Bt.size() != F->nt) { set_error("internal: root size mismatch"); return RSRS_E_INVALID; }
+      Root R{};
+      R.nt = (int)F->nt;
+      R.s = (int)J.s;
+      R.reproject = J.reproject;
+      const int nt = R.nt;
+      std::memcpy(J.hI + F->oBt, Bt.data(), (size_t)nt * 8);
+      RSRS_HIP(hipMemcpyAsync(J.iS + F->oBt, J.hI + F->oBt, (size_t)nt * 8, hipMemcpyHostToDevice, st));
+      const int64_t* iBt = J.iS + F->oBt;
+      R.ntp = round_up(nt, 16);
+      R.rp = round_up(J.s, 16);
+      R.G = bump.take<double>(nt * R.ntp);
+      R.L = bump.take<double>(nt * R.ntp);
+      R.P = bump.take<double>(nt * R.ntp);
+      R.Wb = bump.take<double>(nt * R.ntp);
+      R.Rres = bump.take<double>(nt * R.rp);
+      R.gw = bump.take<double>(2 * (int64_t)nt * nt);
+      // FP64 operands of the root: the samples themselves (rows iBt), or FP64
+      // copies of the rows B_t in mixed precision
+      if constexpr (mixed) {
+        double* Yd = bump.take<double>(nt * R.rp);
+        double* Od = bump.take<double>(nt * R.rp);
+        R.At = bump.take<double>((int64_t)nt * nt);
+        R.Atinv = bump.take<double>((int64_t)nt * nt);
+        gather_rows<T, double>(st, Yd, R.rp, J.Y, J.sld, iBt, nt, J.s);
+        gather_rows<T, double>(st, Od, R.rp, J.Om, J.sld, iBt, nt, J.s);
+        R.Yr = Yd; R.Or = Od; R.ir = nullptr; R.rld = R.rp;
+      } else {
+        R.Yr = reinterpret_cast<const double*>(J.Y);
+        R.Or = reinterpret_cast<const double*>(J.Om);
+        R.ir = iBt; R.rld = J.sld;
+        R.At = reinterpret_cast<double*>(J.dS + F->oAt);
+        R.Atinv = reinterpret_cast<double*>(J.dS + F->oAtinv);
+      }
+      roots.push_back(R);
+      const double dt = nt;
+      J.flops += dt * dt * J.s + (2.0 / 3.0) * dt * dt * dt +
+                 (1 + J.reproject) * (2.0 * dt * dt * J.s + 2.0 * dt * dt * dt) + 2.0 * dt * dt * dt;
     }
     if (bump.off > bump.cap) { set_error("internal: root workspace overflow"); return RSRS_E_INVALID; }
-    RSRS_TRY(gemm(up, st, {gdesc(Or, ir, rld, Or, ir, rld, G, nullptr, ntp, nt, nt, (int)s)}, 0, 1, GM_SYRK_L));
-    RSRS_TRY(rchol(up, st, {CholMat{G, L, ntp, nt}}, 0, nt, flag));
-    RSRS_TRY(gemm(up, st, {gdesc(Yr, ir, rld, Or, ir, rld, P, nullptr, ntp, nt, nt, (int)s)}, 0, 1, GM_FULL));
-    RSRS_TRY(gemm(up, st, {gdesc(P, nullptr, ntp, L, nullptr, ntp, Wb, nullptr, ntp, nt, nt, nt)}, 0, 1, GM_B_NT_LOW));
-    RSRS_TRY(gemm(up, st, {gdesc(Wb, nullptr, ntp, L, nullptr, ntp, At, nullptr, nt, nt, nt, nt)}, 0, 0, GM_B_NN_LOW));
-    if (reproject) {
-      const int64_t rp = round_up(s, 16);
-      RSRS_TRY(gemm(up, st, {gdesc(At, nullptr, nt, Or, ir, rld, Rres, nullptr, rp, nt, (int)s, nt, -1.0, 1.0, Yr, ir, rld)}, 0, 0, GM_FULL));
-      RSRS_TRY(gemm(up, st, {gdesc(Rres, nullptr, rp, Or, ir, rld, P, nullptr, ntp, nt, nt, (int)s)}, 0, 1, GM_FULL));
-      RSRS_TRY(gemm(up, st, {gdesc(P, nullptr, ntp, L, nullptr, ntp, Wb, nullptr, ntp, nt, nt, nt)}, 0, 1, GM_B_NT_LOW));
-      RSRS_TRY(gemm(up, st, {gdesc(Wb, nullptr, ntp, L, nullptr, ntp, At, nullptr, nt, nt, nt, nt, 1.0, 1.0)}, 0, 0, GM_B_NN_LOW));
+    std::vector<GemmDesc> g0, g1, g2, g3;
+    std::vector<CholMat> cm;
+    int ntmax = 0;
+    for (auto& R : roots) {
+      g0.push_back(gdesc(R.Or, R.ir, R.rld, R.Or, R.ir, R.rld, R.G, nullptr, R.ntp, R.nt, R.nt, R.s));
+      cm.push_back(CholMat{R.G, R.L, R.ntp, R.nt});
+      g1.push_back(gdesc(R.Yr, R.ir, R.rld, R.Or, R.ir, R.rld, R.P, nullptr, R.ntp, R.nt, R.nt, R.s));
+      g2.push_back(gdesc(R.P, nullptr, R.ntp, R.L, nullptr, R.ntp, R.Wb, nullptr, R.ntp, R.nt, R.nt, R.nt));
+      g3.push_back(gdesc(R.Wb, nullptr, R.ntp, R.L, nullptr, R.ntp, R.At, nullptr, R.nt, R.nt, R.nt, R.nt));
+      ntmax = std::max(ntmax, R.nt);
     }
-    RSRS_TRY(gje_inverse(up, st, {GjeDesc{At, gw, Atinv, nt, nt, nt, 0}}, flag));
+    RSRS_TRY(gemm(up, st, g0, 0, 1, GM_SYRK_L));
+    RSRS_TRY(rchol(up, st, cm, 0, chol_span(ntmax), flag));
+    RSRS_TRY(gemm(up, st, g1, 0, 1, GM_FULL));
+    RSRS_TRY(gemm(up, st, g2, 0, 1, GM_B_NT_LOW));
+    RSRS_TRY(gemm(up, st, g3, 0, 0, GM_B_NN_LOW));
+    {
+      std::vector<GemmDesc> h0, h1, h2, h3;
+      for (auto& R : roots) {
+        if (!R.reproject) continue;
+        h0.push_back(gdesc(R.At, nullptr, R.nt, R.Or, R.ir, R.rld, R.Rres, nullptr, R.rp, R.nt, R.s, R.nt,
+                           -1.0, 1.0, R.Yr, R.ir, R.rld));
+        h1.push_back(gdesc(R.Rres, nullptr, R.rp, R.Or, R.ir, R.rld, R.P, nullptr, R.ntp, R.nt, R.nt, R.s));
+        h2.push_back(gdesc(R.P, nullptr, R.ntp, R.L, nullptr, R.ntp, R.Wb, nullptr, R.ntp, R.nt, R.nt, R.nt));
+        h3.push_back(gdesc(R.Wb, nullptr, R.ntp, R.L, nullptr, R.ntp, R.At, nullptr, R.nt, R.nt, R.nt, R.nt,
+                           1.0, 1.0));
+      }
+      RSRS_TRY(gemm(up, st, h0, 0, 0, GM_FULL));
+      RSRS_TRY(gemm(up, st, h1, 0, 1, GM_FULL));
+      RSRS_TRY(gemm(up, st, h2, 0, 1, GM_B_NT_LOW));
+      RSRS_TRY(gemm(up, st, h3, 0, 0, GM_B_NN_LOW));
+    }
+    std::vector<GjeDesc> gj;
+    for (auto& R : roots) gj.push_back(GjeDesc{R.At, R.gw, R.Atinv, R.nt, R.nt, R.nt, 0});
+    RSRS_TRY(gje_inverse(up, st, gj, flag));
     if constexpr (mixed) {
-      RSRS_TRY(copy2d<double, T>(up, st, {Copy2DT<double, T>{At, dS + F->oAt, nt, nt, nt, nt, 1.0, 0, 0},
-                                          Copy2DT<double, T>{Atinv, dS + F->oAtinv, nt, nt, nt, nt, 1.0, 0, 0}}));
+      std::vector<Copy2DT<double, T>> cp;
+      for (size_t j = 0; j < jobs.size(); ++j) {
+        const Root& R = roots[j];
+        rsrs_factor_t* F = jobs[j].F.get();
+        cp.push_back(Copy2DT<double, T>{R.At, jobs[j].dS + F->oAt, R.nt, R.nt, R.nt, R.nt, 1.0, 0, 0});
+        cp.push_back(Copy2DT<double, T>{R.Atinv, jobs[j].dS + F->oAtinv, R.nt, R.nt, R.nt, R.nt, 1.0, 0, 0});
+      }
+      RSRS_TRY(copy2d<double, T>(up, st, cp));
     }
-    const double dt = nt;
-    flops += dt * dt * s + (2.0 / 3.0) * dt * dt * dt + (1 + reproject) * (2.0 * dt * dt * s + 2.0 * dt * dt * dt) + 2.0 * dt * dt * dt;
   }
   RSRS_TRY(up.reset());
   {
@@ -637,33 +804,68 @@ rsrs_status factor_t(const rsrs_tree_t* th, rsrs_samples_t* smp, const rsrs_fact
     if (hflag & 1) { set_error("Gram matrix of the root panel is not positive definite"); return RSRS_E_SINGULAR; }
     if (hflag & 2) { set_error("singular pivot block X_RR or root block"); return RSRS_E_SINGULAR; }
   }
-  smp->consumed = true;
-  F->flops = flops;
-  F->factor_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-  *out = F.release();
+  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  for (auto& J : jobs) {
+    J.F->flops = J.flops;
+    J.F->factor_ms = ms;
+  }
+  return RSRS_OK;
+}
+
+template <typename T>
+rsrs_status factor_batch_t(int64_t nprob, const rsrs_tree_t* const* trees, rsrs_samples_t* const* smps,
+                           const rsrs_factor_opts* opts, hipStream_t st, rsrs_factor_t** out) {
+  std::vector<Job<T>> jobs((size_t)nprob);
+  for (int64_t i = 0; i < nprob; ++i) {
+    const rsrs_status r = job_init<T>(jobs[i], trees[i], smps[i], &opts[i]);
+    if (r != RSRS_OK) {
+      if (nprob > 1) set_error("problem " + std::to_string(i) + ": " + rsrs_last_error());
+      return r;
+    }
+  }
+  RSRS_TRY(factor_many<T>(jobs, st));
+  for (int64_t i = 0; i < nprob; ++i) out[i] = jobs[i].F.release();
   return RSRS_OK;
 }
 
 }  // namespace
 
-rsrs_status factor_impl(const rsrs_tree_t* th, rsrs_samples_t* smp, const rsrs_factor_opts* o,
-                        hipStream_t st, rsrs_factor_t** out) {
-  const int k = o->k;
-  if (k < 1) { set_error("k must be >= 1"); return RSRS_E_INVALID; }
-  if (smp->consumed) { set_error("samples were already consumed by a factorization"); return RSRS_E_INVALID; }
-  if (smp->tree != th) { set_error("samples belong to another tree"); return RSRS_E_INVALID; }
-  if (k > 256) { set_error("k > 256 is not supported"); return RSRS_E_UNSUPPORTED; }
-  if (o->reproject < 0 || o->reproject > 1) { set_error("reproject must be 0 or 1"); return RSRS_E_INVALID; }
-  if (o->precision == RSRS_PREC_F64) {
-    if (smp->dtype != RSRS_F64) { set_error("FP64 factorization needs FP64 samples"); return RSRS_E_INVALID; }
-    return factor_t<double>(th, smp, o, st, out);
+rsrs_status factor_batch_impl(int64_t nprob, const rsrs_tree_t* const* trees, rsrs_samples_t* const* smps,
+                              const rsrs_factor_opts* opts, hipStream_t st, rsrs_factor_t** out) {
+  if (nprob < 1) { set_error("need at least one problem"); return RSRS_E_INVALID; }
+  for (int64_t i = 0; i < nprob; ++i) out[i] = nullptr;
+  const int prec = opts[0].precision;
+  for (int64_t i = 0; i < nprob; ++i) {
+    const rsrs_factor_opts* o = &opts[i];
+    const rsrs_samples_t* smp = smps[i];
+    const std::string who = nprob > 1 ? "problem " + std::to_string(i) + ": " : std::string();
+    if (!trees[i] || !smp) { set_error(who + "null tree or samples"); return RSRS_E_INVALID; }
+    if (o->k < 1) { set_error(who + "k must be >= 1"); return RSRS_E_INVALID; }
+    if (smp->consumed) { set_error(who + "samples were already consumed by a factorization"); return RSRS_E_INVALID; }
+    if (smp->tree != trees[i]) { set_error(who + "samples belong to another tree"); return RSRS_E_INVALID; }
+    if (o->k > 256) { set_error(who + "k > 256 is not supported"); return RSRS_E_UNSUPPORTED; }
+    if (o->reproject < 0 || o->reproject > 1) { set_error(who + "reproject must be 0 or 1"); return RSRS_E_INVALID; }
+    if (o->precision != prec) { set_error(who + "all problems of a batch need the same precision"); return RSRS_E_INVALID; }
+    for (int64_t j = 0; j < i; ++j)
+      if (smps[j] == smp) { set_error(who + "the same samples appear twice"); return RSRS_E_INVALID; }
+    if (prec == RSRS_PREC_F64 && smp->dtype != RSRS_F64) {
+      set_error(who + "FP64 factorization needs FP64 samples");
+      return RSRS_E_INVALID;
+    }
+    if (prec == RSRS_PREC_F32_MIXED && smp->dtype != RSRS_F32) {
+      set_error(who + "mixed-precision factorization needs FP32 samples");
+      return RSRS_E_INVALID;
+    }
   }
-  if (o->precision == RSRS_PREC_F32_MIXED) {
-    if (smp->dtype != RSRS_F32) { set_error("mixed-precision factorization needs FP32 samples"); return RSRS_E_INVALID; }
-    return factor_t<float>(th, smp, o, st, out);
-  }
+  if (prec == RSRS_PREC_F64) return factor_batch_t<double>(nprob, trees, smps, opts, st, out);
+  if (prec == RSRS_PREC_F32_MIXED) return factor_batch_t<float>(nprob, trees, smps, opts, st, out);
   set_error("unknown precision");
   return RSRS_E_UNSUPPORTED;
+}
+
+rsrs_status factor_impl(const rsrs_tree_t* th, rsrs_samples_t* smp, const rsrs_factor_opts* o,
+                        hipStream_t st, rsrs_factor_t** out) {
+  return factor_batch_impl(1, &th, &smp, o, st, out);
 }
 
 }  // namespace rsrs

@@ -78,7 +78,8 @@ EXPORTS = [
     "rsrs_tree_destroy", "rsrs_tree_get_info", "rsrs_tree_neighbours", "rsrs_tree_schedule",
     "rsrs_samples_required", "rsrs_op_create_kernel", "rsrs_op_create_dense",
     "rsrs_op_create_poisson7", "rsrs_op_matvec", "rsrs_op_destroy", "rsrs_samples_wrap",
-    "rsrs_sample", "rsrs_samples_destroy", "rsrs_gaussian", "rsrs_factor", "rsrs_factor_destroy",
+    "rsrs_sample", "rsrs_samples_destroy", "rsrs_gaussian", "rsrs_factor", "rsrs_factor_batched",
+    "rsrs_factor_destroy",
     "rsrs_factor_get_info", "rsrs_factor_box_sizes", "rsrs_factor_box_copy",
     "rsrs_factor_root_copy", "rsrs_solve", "rsrs_apply", "rsrs_solve_refine",
     "rsrs_profile_enable", "rsrs_profile_reset", "rsrs_profile_read",
@@ -116,6 +117,7 @@ def lib():
         "rsrs_samples_destroy": (None, [vp]),
         "rsrs_gaussian": (i32, [vp, i64, i64, i64, C.c_uint64, C.c_uint32, vp]),
         "rsrs_factor": (i32, [vp, vp, P(FactorOpts), vp, P(vp)]),
+        "rsrs_factor_batched": (i32, [i64, P(vp), P(vp), P(FactorOpts), vp, P(vp)]),
         "rsrs_factor_destroy": (None, [vp]),
         "rsrs_factor_get_info": (i32, [vp, P(FactorInfo)]),
         "rsrs_factor_box_sizes": (i32, [vp, i64, P(i64), P(C.c_int32), P(C.c_int32), P(i64),
@@ -426,6 +428,20 @@ def rsrs_factor(tree: Tree, samples: Samples, k: int, p: int = -1, reproject: in
     h = C.c_void_p()
     _check(lib().rsrs_factor(tree.handle, samples.handle, C.byref(o), _stream(stream), C.byref(h)))
     return Factor(h, keep=tree)
+
+
+def rsrs_factor_batched(trees, samples, ks, p: int = -1, reproject: int = 1,
+                        precision: int = RSRS_PREC_F64, stream=None) -> list:
+    """Factor independent problems together; ks gives each problem's rank."""
+    n = len(trees)
+    if len(samples) != n or len(ks) != n:
+        raise ValueError("trees, samples and ks must have the same length")
+    th = (C.c_void_p * n)(*[t.handle for t in trees])
+    sh = (C.c_void_p * n)(*[x.handle for x in samples])
+    opts = (FactorOpts * n)(*[FactorOpts(int(k), p, precision, reproject) for k in ks])
+    outs = (C.c_void_p * n)()
+    _check(lib().rsrs_factor_batched(n, th, sh, opts, _stream(stream), outs))
+    return [Factor(C.c_void_p(outs[i]), keep=trees[i]) for i in range(n)]
 
 
 def rsrs_solve(f: Factor, F, transpose=False, out=None, stream=None):
