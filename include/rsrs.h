@@ -42,13 +42,15 @@ typedef enum {
   RSRS_E_NUMERIC = 5,      /* NaN or Inf met in samples or residuals              */
   RSRS_E_NOMEM = 6,        /* device allocation failed                            */
   RSRS_E_HIP = 7,          /* HIP runtime error                                   */
-  RSRS_E_UNSUPPORTED = 8   /* option not implemented                              */
+  RSRS_E_UNSUPPORTED = 8,  /* option not implemented                              */
+  RSRS_E_TIMEOUT = 9       /* a server wait ran out of time (request still pending) */
 } rsrs_status;
 
 typedef struct rsrs_tree_s rsrs_tree_t;
 typedef struct rsrs_samples_s rsrs_samples_t;
 typedef struct rsrs_factor_s rsrs_factor_t;
 typedef struct rsrs_operator_s rsrs_operator_t;
+typedef struct rsrs_server_s rsrs_server_t;
 
 const char* rsrs_status_string(rsrs_status st);
 const char* rsrs_last_error(void);
@@ -288,6 +290,67 @@ rsrs_status rsrs_solve_refine(const rsrs_factor_t* f, rsrs_matvec_fn mv, void* u
                               const double* F, int64_t ldf, double* U, int64_t ldu, double tol,
                               int maxit, double* relres, int* iters, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Serving (continuous batching).  The method factors once from one set of
+ * sketches and then solves many right-hand sides (Sec. 1, Sec. 4.4); the
+ * server keeps factorizations resident on the device and serves a stream of
+ * requests with two worker threads, each on its own HIP stream:
+ *  - solve requests for a resident factor are batched: the oldest pending
+ *    request and every other pending request for the same factor, in arrival
+ *    order, while the batch has at most max_batch_cols columns, are solved by
+ *    one apply of the factor; requests arriving meanwhile join the next
+ *    batch.  Each result equals the solve of that request alone (the columns
+ *    of a batch are computed independently by the same kernels).
+ *  - factor requests (tree, black-box operator, s, seed, options) are
+ *    admitted in arrival order when the device bytes they need (estimated
+ *    from the schedule: samples, sampling buffers, workspace, stored factor)
+ *    fit in hbm_budget next to the resident factors and the factorizations in
+ *    flight; they run on the second stream, overlapping with solve batches,
+ *    and the factor becomes resident (result id of the ticket).
+ * Budget 0 means unlimited.  A resident factor is charged its stored bytes
+ * plus the solve workspace of a full batch.  Device blocks passed to a
+ * request must stay valid until its ticket completes; a tree or operator
+ * passed to a factor request must outlive it and must not be used by the
+ * caller while the request runs.  All functions are thread-safe.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  int64_t hbm_budget;      /* bytes; 0 = unlimited */
+  int64_t max_batch_cols;  /* columns per batched solve (>= 1) */
+} rsrs_server_opts;
+rsrs_status rsrs_server_create(const rsrs_server_opts* opts, rsrs_server_t** out);
+/* Finishes every pending request, then frees the resident factors. */
+void rsrs_server_destroy(rsrs_server_t* sv);
+/* Makes a factor resident (the server takes ownership); RSRS_E_NOMEM if it
+ * does not fit in the budget (ownership stays with the caller then). */
+rsrs_status rsrs_server_add_factor(rsrs_server_t* sv, rsrs_factor_t* f, int64_t* id);
+/* Frees a resident factor once its in-flight batch is done; later requests
+ * for it fail with RSRS_E_INVALID. */
+rsrs_status rsrs_server_release_factor(rsrs_server_t* sv, int64_t id);
+/* Queues U = A_approx^{-1} F for resident factor id (device N x nrhs blocks,
+ * user order, FP64); *ticket identifies the request. */
+rsrs_status rsrs_server_submit_solve(rsrs_server_t* sv, int64_t id, int64_t nrhs, const double* F,
+                                     int64_t ldf, double* U, int64_t ldu, int64_t* ticket);
+/* Queues sampling (rsrs_sample with dtype) and factorization (opts); fails at
+ * once with RSRS_E_SAMPLES if s is too small and RSRS_E_NOMEM if the request
+ * alone exceeds the budget. */
+rsrs_status rsrs_server_submit_factor(rsrs_server_t* sv, const rsrs_tree_t* t, rsrs_matvec_fn mv,
+                                      void* user, int64_t s, uint64_t seed, int dtype,
+                                      const rsrs_factor_opts* opts, int64_t* ticket);
+/* Waits for a ticket (timeout_ms < 0: no limit; RSRS_E_TIMEOUT leaves it
+ * pending) and returns the request's status; *result receives the resident
+ * id of a factor request, *latency_ms submit-to-completion time.  A ticket
+ * can be waited for once. */
+rsrs_status rsrs_server_wait(rsrs_server_t* sv, int64_t ticket, double timeout_ms, int64_t* result,
+                             double* latency_ms);
+typedef struct {
+  int64_t solves_done, factors_done, batches, cols_done;
+  int64_t hbm_in_use, hbm_peak;          /* bytes charged to the budget */
+  int64_t resident_factors, queued_solves, queued_factors;
+  double solve_p50_ms, solve_p99_ms;     /* submit-to-completion latency */
+  double factor_p50_ms, factor_p99_ms;
+} rsrs_server_stats;
+/* Counters since creation or the last reset (reset != 0 clears them). */
+rsrs_status rsrs_server_get_stats(rsrs_server_t* sv, int reset, rsrs_server_stats* out);
 /* ------------------------------------------------------------------------
  * Measurement.  While enabled (process-wide), every kernel launch of the
  * library is bracketed by HIP events recorded on the launch's own stream and

@@ -46,6 +46,7 @@ const char* rsrs_status_string(rsrs_status st) {
     case RSRS_E_NOMEM: return "out of device memory";
     case RSRS_E_HIP: return "HIP runtime error";
     case RSRS_E_UNSUPPORTED: return "unsupported option";
+    case RSRS_E_TIMEOUT: return "timed out";
   }
   return "unknown status";
 }

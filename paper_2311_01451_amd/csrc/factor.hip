@@ -868,4 +868,42 @@ rsrs_status factor_impl(const rsrs_tree_t* th, rsrs_samples_t* smp, const rsrs_f
   return factor_batch_impl(1, &th, &smp, o, st, out);
 }
 
+// Device bytes of a factorization of tree t with s samples: the stored factor
+// (*stored) and the peak of everything alive while it is computed (samples
+// excluded): stored factor, class workspace, descriptor staging.
+size_t factor_bytes_estimate(const rsrs_tree_t* th, int k, int p, int64_t s, int precision,
+                             size_t* stored) {
+  const Tree& t = th->t;
+  const bool mixed = precision == RSRS_PREC_F32_MIXED;
+  const int64_t esz = mixed ? 4 : 8, al = 16 / esz, sld = round_up(s, 16);
+  (void)p;
+  Schedule sch;
+  make_schedule(t, k, sch);
+  int64_t dsz = 0, isz = 0;
+  size_t ws_max = 0;
+  for (size_t li = 0; li < sch.levels.size(); ++li)
+    for (const auto& cls : sch.classes[li]) {
+      size_t ws = 0;
+      for (int64_t b : cls) {
+        const int64_t bb = sch.b_count[b], n = sch.l_count[b] - bb, r = bb - k;
+        dsz = round_up(dsz, al) + r * round_up(k, al);
+        dsz = round_up(dsz, al) + 2 * r * round_up(r, al);
+        dsz = round_up(dsz, al) + r * round_up(k + n, al);
+        dsz = round_up(dsz, al) + (k + n) * round_up(r, al);
+        isz += r + k + n + bb + n;
+        ws += mixed ? box_ws_bytes<float>(bb, bb + n, k, sld) : box_ws_bytes<double>(bb, bb + n, k, sld);
+      }
+      ws_max = std::max(ws_max, ws);
+    }
+  const int64_t nt = sch.root_count;
+  dsz = round_up(dsz, al) + 2 * nt * nt;
+  isz += nt;
+  size_t root_ws = (size_t)(4 * nt * round_up(nt, 16) + nt * sld + 2 * nt * nt) * 8 + 8 * 256;
+  if (mixed) root_ws += (size_t)(2 * nt * sld + 2 * nt * nt) * 8 + 4 * 256;
+  ws_max = std::max(ws_max, root_ws);
+  const size_t st = (size_t)dsz * esz + (size_t)isz * 8 + (size_t)t.n * 8;
+  if (stored) *stored = st;
+  return st + ws_max + ((size_t)64 << 20);
+}
+
 }  // namespace rsrs

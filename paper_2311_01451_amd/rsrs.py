@@ -31,7 +31,7 @@ RSRS_F32 = 1
 
 STATUS = {0: "RSRS_OK", 1: "RSRS_E_INVALID", 2: "RSRS_E_SAMPLES", 3: "RSRS_E_SINGULAR",
           4: "RSRS_E_CALLBACK", 5: "RSRS_E_NUMERIC", 6: "RSRS_E_NOMEM", 7: "RSRS_E_HIP",
-          8: "RSRS_E_UNSUPPORTED"}
+          8: "RSRS_E_UNSUPPORTED", 9: "RSRS_E_TIMEOUT"}
 
 
 class RSRSError(RuntimeError):
@@ -65,6 +65,19 @@ class FactorInfo(C.Structure):
                 ("precision", C.c_int), ("flops", C.c_double), ("factor_ms", C.c_double)]
 
 
+class ServerOpts(C.Structure):
+    _fields_ = [("hbm_budget", C.c_int64), ("max_batch_cols", C.c_int64)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("solves_done", C.c_int64), ("factors_done", C.c_int64), ("batches", C.c_int64),
+                ("cols_done", C.c_int64), ("hbm_in_use", C.c_int64), ("hbm_peak", C.c_int64),
+                ("resident_factors", C.c_int64), ("queued_solves", C.c_int64),
+                ("queued_factors", C.c_int64), ("solve_p50_ms", C.c_double),
+                ("solve_p99_ms", C.c_double), ("factor_p50_ms", C.c_double),
+                ("factor_p99_ms", C.c_double)]
+
+
 class ProfileEntry(C.Structure):
     _fields_ = [("tag", C.c_char * 48), ("launches", C.c_int64), ("ms", C.c_double),
                 ("flops", C.c_double), ("bytes", C.c_double)]
@@ -83,6 +96,9 @@ EXPORTS = [
     "rsrs_factor_get_info", "rsrs_factor_box_sizes", "rsrs_factor_box_copy",
     "rsrs_factor_root_copy", "rsrs_solve", "rsrs_apply", "rsrs_solve_refine",
     "rsrs_profile_enable", "rsrs_profile_reset", "rsrs_profile_read",
+    "rsrs_server_create", "rsrs_server_destroy", "rsrs_server_add_factor",
+    "rsrs_server_release_factor", "rsrs_server_submit_solve", "rsrs_server_submit_factor",
+    "rsrs_server_wait", "rsrs_server_get_stats",
 ]
 
 
@@ -128,6 +144,15 @@ def lib():
         "rsrs_apply": (i32, [vp, i32, i64, vp, i64, vp, i64, vp]),
         "rsrs_solve_refine": (i32, [vp, vp, vp, i64, vp, i64, vp, i64, dbl, i32, P(dbl),
                                     P(i32), vp]),
+        "rsrs_server_create": (i32, [P(ServerOpts), P(vp)]),
+        "rsrs_server_destroy": (None, [vp]),
+        "rsrs_server_add_factor": (i32, [vp, vp, P(i64)]),
+        "rsrs_server_release_factor": (i32, [vp, i64]),
+        "rsrs_server_submit_solve": (i32, [vp, i64, i64, vp, i64, vp, i64, P(i64)]),
+        "rsrs_server_submit_factor": (i32, [vp, vp, vp, vp, i64, C.c_uint64, i32, P(FactorOpts),
+                                            P(i64)]),
+        "rsrs_server_wait": (i32, [vp, i64, dbl, P(i64), P(dbl)]),
+        "rsrs_server_get_stats": (i32, [vp, i32, P(ServerStats)]),
         "rsrs_profile_enable": (None, [i32]),
         "rsrs_profile_reset": (None, []),
         "rsrs_profile_read": (i32, [P(ProfileEntry), i32]),
@@ -476,6 +501,80 @@ def rsrs_solve_refine(f: Factor, op: Operator, F, tol: float = 1e-10, maxit: int
     _check(lib().rsrs_solve_refine(f.handle, Operator.fn_ptr(), op.handle, F.shape[1], pf, ldf, pu, ldu,
                                    tol, maxit, C.byref(rel), C.byref(it), _stream(stream)))
     return out, rel.value, it.value
+
+
+# --------------------------------------------------------------------------- serving
+class Server:
+    """Continuous-batching server (rsrs_server_*): resident factors, batched
+    solves, budget-admitted factorizations.  Device tensors handed to a request
+    are kept alive here until the request has been waited for."""
+
+    def __init__(self, hbm_budget: int = 0, max_batch_cols: int = 1024):
+        o = ServerOpts(int(hbm_budget), int(max_batch_cols))
+        h = C.c_void_p()
+        _check(lib().rsrs_server_create(C.byref(o), C.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.rsrs_server_destroy(h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add_factor(self, f: Factor) -> int:
+        fid = C.c_int64()
+        _check(lib().rsrs_server_add_factor(self._h, f.handle, C.byref(fid)))
+        f._h = None   # owned by the server now
+        return fid.value
+
+    def release(self, fid: int):
+        _check(lib().rsrs_server_release_factor(self._h, int(fid)))
+
+    def submit_solve(self, fid: int, F, out=None) -> tuple:
+        import torch
+        pf, ldf = _dev(F, "F")
+        if out is None:
+            out = torch.empty_like(F)
+        pu, ldu = _dev(out, "out")
+        t = C.c_int64()
+        _check(lib().rsrs_server_submit_solve(self._h, int(fid), F.shape[1], pf, ldf, pu, ldu,
+                                              C.byref(t)))
+        self._keep[t.value] = (F, out)
+        return t.value, out
+
+    def submit_factor(self, tree: Tree, op: Operator, s: int, seed: int, k: int,
+                      precision: int = RSRS_PREC_F64, p: int = -1, reproject: int = 1) -> int:
+        dtype = RSRS_F64 if precision == RSRS_PREC_F64 else RSRS_F32
+        o = FactorOpts(int(k), p, precision, reproject)
+        t = C.c_int64()
+        _check(lib().rsrs_server_submit_factor(self._h, tree.handle, Operator.fn_ptr(), op.handle,
+                                               int(s), int(seed), dtype, C.byref(o), C.byref(t)))
+        self._keep[t.value] = (tree, op)
+        return t.value
+
+    def wait(self, ticket: int, timeout_ms: float = -1.0):
+        """(result id or -1, latency in ms); raises RSRSError on a failed request."""
+        res = C.c_int64()
+        lat = C.c_double()
+        st = lib().rsrs_server_wait(self._h, int(ticket), float(timeout_ms), C.byref(res),
+                                    C.byref(lat))
+        if st != 9:
+            self._keep.pop(int(ticket), None)
+        _check(st)
+        return res.value, lat.value
+
+    def stats(self, reset: bool = False) -> dict:
+        s = ServerStats()
+        _check(lib().rsrs_server_get_stats(self._h, int(reset), C.byref(s)))
+        return {f: getattr(s, f) for f, _ in ServerStats._fields_}
 
 
 # --------------------------------------------------------------------------- measurement
