@@ -265,6 +265,175 @@ def cpu_baseline(s_eff: int) -> dict:
             "est_step_s": round(est, 1)}
 
 
+def serving_bench(duration_s: float, load: float = 0.7) -> dict:
+    """Serving workload: a resident mixed-precision factor of the 3D kernel
+    A_ij = delta_ij + (1/N) / (4 pi |x_i - x_j|) on N = 32768 uniform random
+    points in [0,1]^3 (adaptive octree, leaf 64, k = p = 128), behind the
+    continuous-batching server with a 24 GB HBM budget.  A Poisson stream of
+    requests: 90% solves with widths uniform in {1, 4, 16, 64, 256} (N(0,1)
+    entries), 10% new-factor requests for 64 x 64 jittered-grid log-kernel
+    operators (k = p = 32, mixed precision), each used for one 16-column solve
+    and then released.  The arrival rate is `load` times the saturated solve
+    request rate measured first with a burst."""
+    import threading
+
+    import torch
+    from paper_2311_01451_amd import inputs, rsrs
+
+    rng = np.random.default_rng(inputs.BASE_SEED + 5)
+    N, K4 = 32768, 128
+    pts = inputs.uniform_points(N, 3)
+    t0 = time.perf_counter()
+    op = rsrs.rsrs_op_create_kernel(rsrs.RSRS_OP_INVR3D, pts)
+    tree = rsrs.rsrs_build_tree(pts, LEAF)
+    s_req = tree.samples_required(K4, K4)
+    s = max(2048, s_req)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    smp = rsrs.rsrs_sample(tree, op, s, inputs.BASE_SEED, dtype=rsrs.RSRS_F32)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    F = rsrs.rsrs_factor(tree, smp, K4, precision=rsrs.RSRS_PREC_F32_MIXED)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    del smp
+    f16 = torch.tensor(inputs.rhs(N, 16), dtype=torch.float64, device="cuda")
+    _, rel, it = rsrs.rsrs_solve_refine(F, op, f16, tol=TOL, maxit=30)
+    fi = F.info()
+    budget = 24 << 30
+    sv = rsrs.Server(hbm_budget=budget, max_batch_cols=1024)
+    fid = sv.add_factor(F)
+    widths = [1, 4, 16, 64, 256]
+    pool = {w: torch.randn((N, w), dtype=torch.float64, device="cuda") for w in widths}
+    # operators for the new-factor requests (built up front: creating one
+    # synchronises the device, which would stall the arrival process)
+    n0 = 64
+    small = []
+    for j in range(8):
+        p0 = inputs.jittered_grid2d(n0, seed_offset=500 + j)
+        t0s = rsrs.rsrs_build_tree(p0, LEAF)
+        small.append((t0s, rsrs.rsrs_op_create_kernel(rsrs.RSRS_OP_LOG2D, p0, 1.0 / n0),
+                      t0s.samples_required(32, 32)))
+    f0 = torch.tensor(inputs.rhs(n0 * n0, 16), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+
+    # saturated solve throughput: a burst of solve requests only
+    burst = [int(rng.choice(widths)) for _ in range(200)]
+    sv.stats(reset=True)
+    a = time.perf_counter()
+    tk = [sv.submit_solve(fid, pool[w], torch.empty_like(pool[w]))[0] for w in burst]
+    for t in tk:
+        sv.wait(t)
+    sat_s = time.perf_counter() - a
+    sat = sv.stats(reset=True)
+
+    jnext = [0]
+
+    def submit_factor():
+        t0s, op0, s0 = small[jnext[0] % len(small)]
+        jnext[0] += 1
+        return sv.submit_factor(t0s, op0, s0, inputs.BASE_SEED + jnext[0], 32,
+                                precision=rsrs.RSRS_PREC_F32_MIXED)
+
+    def use_and_release(t):
+        fid2, lat = sv.wait(t)
+        tk2, _ = sv.submit_solve(fid2, f0)
+        sv.wait(tk2)
+        sv.release(fid2)
+        return lat
+
+    # saturated rate of the request mix (90% solves, 10% new factors)
+    kinds = [rng.random() < 0.1 for _ in range(300)]
+    a = time.perf_counter()
+    tk, fk = [], []
+    for is_f in kinds:
+        if is_f:
+            fk.append(submit_factor())
+        else:
+            w = int(rng.choice(widths))
+            tk.append(sv.submit_solve(fid, pool[w], torch.empty_like(pool[w]))[0])
+    for t in tk:
+        sv.wait(t)
+    for t in fk:
+        use_and_release(t)
+    mix_s = time.perf_counter() - a
+    sv.stats(reset=True)
+    mix_rate = len(kinds) / mix_s
+    lam = load * mix_rate
+
+    # Poisson stream at `load` times the saturated rate of the mix
+    lock = threading.Lock()
+    fact_tickets = []
+    done_submitting = threading.Event()
+
+    def factor_client():
+        while True:
+            with lock:
+                t = fact_tickets.pop(0) if fact_tickets else None
+            if t is None:
+                if done_submitting.is_set():
+                    with lock:
+                        if not fact_tickets:
+                            return
+                    continue
+                time.sleep(0.001)
+                continue
+            use_and_release(t)
+
+    th = threading.Thread(target=factor_client)
+    th.start()
+    tickets = []
+    nfact = 0
+    start = time.perf_counter()
+    tnext = start
+    while True:
+        tnext += rng.exponential(1.0 / lam)
+        if tnext - start > duration_s:
+            break
+        d = tnext - time.perf_counter()
+        if d > 0:
+            time.sleep(d)
+        if rng.random() < 0.1:
+            t = submit_factor()
+            with lock:
+                fact_tickets.append(t)
+            nfact += 1
+        else:
+            w = int(rng.choice(widths))
+            tickets.append(sv.submit_solve(fid, pool[w], torch.empty_like(pool[w]))[0])
+    for t in tickets:
+        sv.wait(t)
+    solves_end = time.perf_counter()
+    done_submitting.set()
+    th.join()
+    elapsed = time.perf_counter() - start
+    st = sv.stats()
+    sv.close()
+    return {
+        "workload": f"3D kernel delta_ij + (1/N)/(4 pi r), N={N} uniform random points, adaptive octree "
+                    f"leaf {LEAF}, k=p={K4}, s={s} (configured 2048, required {s_req}), mixed precision, "
+                    "resident; Poisson stream of solves (widths {1,4,16,64,256}) with 10% new-factor "
+                    "requests (64x64 jittered log kernel, k=32), HBM budget 24 GB",
+        "factor_s": round(t3 - t2, 3), "sample_s": round(t2 - t1, 3),
+        "factor_tflops_algorithmic": round(fi["flops"] / (t3 - t2) / 1e12, 3),
+        "stored_gb": round(fi["stored_bytes"] / 1e9, 3),
+        "refine": {"relres": rel, "iters": it},
+        "saturated_solves": {"requests_per_s": round(len(burst) / sat_s, 1),
+                      "cols_per_s": round(sat["cols_done"] / sat_s, 1),
+                      "solve_p50_ms": round(sat["solve_p50_ms"], 3),
+                      "solve_p99_ms": round(sat["solve_p99_ms"], 3),
+                      "mean_batch_cols": round(sat["cols_done"] / max(sat["batches"], 1), 1)},
+        "saturated_mix_requests_per_s": round(mix_rate, 1),
+        "load": load, "arrival_rate_per_s": round(lam, 1), "duration_s": round(elapsed, 2),
+        "solves": st["solves_done"], "factors": st["factors_done"], "factor_requests": nfact,
+        "cols_per_s": round(st["cols_done"] / (solves_end - start), 1),
+        "solve_p50_ms": round(st["solve_p50_ms"], 3), "solve_p99_ms": round(st["solve_p99_ms"], 3),
+        "factor_p50_ms": round(st["factor_p50_ms"], 3), "factor_p99_ms": round(st["factor_p99_ms"], 3),
+        "mean_batch_cols": round(st["cols_done"] / max(st["batches"], 1), 1),
+        "hbm_peak_gb": round(st["hbm_peak"] / 1e9, 3),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -275,11 +444,19 @@ def main():
     ap.add_argument("--latency-reps", type=int, default=40)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run a plain device copy of this size first (counter calibration)")
+    ap.add_argument("--serving", type=float, default=0.0,
+                    help="run only the serving workload for this many seconds and print its line")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {a.gpus}); "
               "a sharded run across GPUs is not part of this benchmark", file=sys.stderr)
         sys.exit(2)
+    if a.serving > 0:
+        out = {"metric": "serving: p50/p99 solve latency (ms) and RHS cols/s under Poisson arrivals",
+               "n_gpus": 1, "data": "synthetic"}
+        out.update(serving_bench(a.serving))
+        print(json.dumps(out))
+        return
     ctx = {}
     runs = {}
     for name, mixed in (("mixed", True), ("fp64", False)):

@@ -306,7 +306,10 @@ rsrs_status rsrs_solve_refine(const rsrs_factor_t* f, rsrs_matvec_fn mv, void* u
  *    from the schedule: samples, sampling buffers, workspace, stored factor)
  *    fit in hbm_budget next to the resident factors and the factorizations in
  *    flight; they run on the second stream, overlapping with solve batches,
- *    and the factor becomes resident (result id of the ticket).
+ *    and the factor becomes resident (result id of the ticket).  Requests
+ *    admitted together (up to 64, same precision) are factored as one
+ *    rsrs_factor_batched batch; if that batch fails, each of its requests is
+ *    sampled and factored again alone, so only the faulty one fails.
  * Budget 0 means unlimited.  A resident factor is charged its stored bytes
  * plus the solve workspace of a full batch.  Device blocks passed to a
  * request must stay valid until its ticket completes; a tree or operator

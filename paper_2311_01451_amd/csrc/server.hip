@@ -16,6 +16,9 @@
 //    allocation) fit in the HBM budget next to what is resident and in
 //    flight; it is then sampled and factored on the second stream, so its
 //    work overlaps with solve batches on the device, and becomes resident.
+//    Requests admitted together (same precision) are factored as one batch
+//    of independent problems (rsrs_factor_batched), the factor-side analogue
+//    of the solve batches.
 // Releasing a factor returns its bytes to the budget once its in-flight
 // batch is done.  Every column of a batch is computed by the same kernels,
 // per column, as a solve of that request alone.
@@ -40,11 +43,15 @@ rsrs_status apply_factor(const rsrs_factor_t* F, int op, int transpose, int64_t 
                          int64_t ldf, double* Uout, int64_t ldu, hipStream_t st);
 size_t factor_bytes_estimate(const rsrs_tree_t* th, int k, int p, int64_t s, int precision,
                              size_t* stored);
+rsrs_status factor_batch_impl(int64_t nprob, const rsrs_tree_t* const* trees, rsrs_samples_t* const* smps,
+                              const rsrs_factor_opts* opts, hipStream_t st, rsrs_factor_t** out);
 }  // namespace rsrs
 
 using namespace rsrs;
 
 namespace {
+
+constexpr int kMaxFactorBatch = 64;   // factor requests merged into one batched factorization
 
 double now_ms() {
   return std::chrono::duration<double, std::milli>(
@@ -226,34 +233,89 @@ struct rsrs_server_s {
         cv_done.notify_all();
         break;
       }
-      Fact r = qf.front();
-      qf.pop_front();
-      use(r.est);
+      // every queued request that fits next to it (same precision, in order)
+      std::vector<Fact> group;
+      int64_t charged = 0;
+      while (!qf.empty() && (int)group.size() < kMaxFactorBatch &&
+             qf.front().o.precision == (group.empty() ? qf.front().o.precision : group[0].o.precision) &&
+             (budget <= 0 || in_use + charged + qf.front().est <= budget)) {
+        group.push_back(qf.front());
+        charged += qf.front().est;
+        qf.pop_front();
+      }
+      use(charged);
       lk.unlock();
 
-      rsrs_samples_t* smp = nullptr;
-      rsrs_factor_t* F = nullptr;
-      rsrs_status st = rsrs_sample(r.t, r.mv, r.user, r.s, r.seed, r.dtype, s_factor, &smp);
-      if (st == RSRS_OK) st = factor_impl(r.t, smp, &r.o, s_factor, &F);
-      const std::string msg = st == RSRS_OK ? std::string() : std::string(rsrs_last_error());
-      rsrs_samples_destroy(smp);
+      std::vector<rsrs_factor_t*> Fs(group.size(), nullptr);
+      std::vector<rsrs_status> sts(group.size(), RSRS_OK);
+      std::vector<std::string> msgs(group.size());
+      run_group(group, Fs, sts, msgs);
       const double t = now_ms();
 
       lk.lock();
-      use(-r.est);
-      int64_t fid = -1;
-      if (st == RSRS_OK) {
-        // stored factor plus the solve workspace a full batch allocates in it
-        const int64_t bytes = F->stored_values * F->esz + (F->n * 8) +
-                              2 * F->n * max_cols * (int64_t)F->esz;
-        fid = next_fid++;
-        res[fid] = Resident{F, bytes, 0, false};
-        use(bytes);
+      use(-charged);
+      for (size_t i = 0; i < group.size(); ++i) {
+        int64_t fid = -1;
+        if (sts[i] == RSRS_OK) {
+          rsrs_factor_t* F = Fs[i];
+          // stored factor plus the solve workspace a full batch allocates in it
+          const int64_t bytes = F->stored_values * F->esz + (F->n * 8) +
+                                2 * F->n * max_cols * (int64_t)F->esz;
+          fid = next_fid++;
+          res[fid] = Resident{F, bytes, 0, false};
+          use(bytes);
+        }
+        finish(group[i].ticket, sts[i], msgs[i], fid, t);
       }
-      finish(r.ticket, st, msg, fid, t);
       cv_done.notify_all();
       cv_factor.notify_all();
     }
+  }
+
+  // Samples every request of the group and factors them together
+  // (rsrs_factor_batched).  If the batch fails, each request is sampled and
+  // factored again on its own, so only the request at fault reports the error.
+  void run_group(const std::vector<Fact>& group, std::vector<rsrs_factor_t*>& Fs,
+                 std::vector<rsrs_status>& sts, std::vector<std::string>& msgs) {
+    const size_t m = group.size();
+    std::vector<rsrs_samples_t*> smp(m, nullptr);
+    std::vector<const rsrs_tree_t*> trees;
+    std::vector<rsrs_samples_t*> ok_smp;
+    std::vector<rsrs_factor_opts> opts;
+    std::vector<size_t> idx;
+    for (size_t i = 0; i < m; ++i) {
+      const Fact& r = group[i];
+      sts[i] = rsrs_sample(r.t, r.mv, r.user, r.s, r.seed, r.dtype, s_factor, &smp[i]);
+      if (sts[i] != RSRS_OK) {
+        msgs[i] = rsrs_last_error();
+        continue;
+      }
+      trees.push_back(r.t);
+      ok_smp.push_back(smp[i]);
+      opts.push_back(r.o);
+      idx.push_back(i);
+    }
+    if (!idx.empty()) {
+      std::vector<rsrs_factor_t*> out(idx.size(), nullptr);
+      const rsrs_status st = factor_batch_impl((int64_t)idx.size(), trees.data(), ok_smp.data(), opts.data(),
+                                               s_factor, out.data());
+      if (st == RSRS_OK) {
+        for (size_t j = 0; j < idx.size(); ++j) Fs[idx[j]] = out[j];
+      } else if (idx.size() == 1) {
+        sts[idx[0]] = st;
+        msgs[idx[0]] = rsrs_last_error();
+      } else {
+        for (size_t j : idx) {
+          const Fact& r = group[j];
+          rsrs_samples_destroy(smp[j]);
+          smp[j] = nullptr;
+          sts[j] = rsrs_sample(r.t, r.mv, r.user, r.s, r.seed, r.dtype, s_factor, &smp[j]);
+          if (sts[j] == RSRS_OK) sts[j] = factor_impl(r.t, smp[j], &r.o, s_factor, &Fs[j]);
+          if (sts[j] != RSRS_OK) msgs[j] = rsrs_last_error();
+        }
+      }
+    }
+    for (auto* x : smp) rsrs_samples_destroy(x);
   }
 };
 
