@@ -12,9 +12,11 @@ One step = the whole hot path on one batch: build the tree, draw Omega/Psi
 and sample Y = A Omega, Z = A^T Psi through the operator, factor (Algorithm
 1), solve the 16 right-hand sides and refine with the FP64 residual of the
 operator until the relative residual is <= 1e-6.  It runs in two precisions:
-mixed (FP32 samples and MFMA products, FP64 pivots, inverses and residuals)
-and plain FP64.  value = right-hand-side columns solved per second of step
-time of the mixed path; the FP64 path is reported beside it ("fp64").  The
+mixed (BF16 sample products with FP32 accumulation, FP32 sketches and MFMA
+products in the factorization, FP64 pivots, inverses and residuals), the same
+with FP32 sample products, and plain FP64.  value = right-hand-side columns
+solved per second of step time of the first; the others are reported beside
+it ("mixed_fp32_samples", "fp64").  The
 operator itself (the black box) is built once outside the timed region.
 
 Prints ONE JSON line (rank 0).  Extra fields: per-phase times, p50/p99 solve
@@ -55,12 +57,13 @@ def workload_config(s_req: int, s_eff: int) -> dict:
                         "(FP64 residual), mixed precision vs FP64",
             "N": GRID_N ** 2, "leaf": LEAF, "k": K, "p": K, "s_configured": S_CFG,
             "s_required": s_req, "s": s_eff, "nrhs": NRHS, "tol": TOL,
-            "precision": "fp32-mixed (FP32 samples and MFMA products; FP64 Cholesky, "
-                         "pivoted QR, Gauss-Jordan and residuals); fp64 beside it"}
+            "precision": "mixed: BF16 sample products (FP32 accumulation), FP32 sketches and MFMA "
+                         "products in the factorization, FP64 Cholesky, pivoted QR, Gauss-Jordan "
+                         "and residuals; the FP32-sample mixed path and the FP64 path beside it"}
 
 
 def gpu_bench(steps: int, warmup: int, do_profile: bool, latency_reps: int = 40,
-              calib_copy_mib: int = 0, mixed: bool = False, ctx: dict | None = None):
+              calib_copy_mib: int = 0, mode: str = "fp64", ctx: dict | None = None):
     import torch
     from paper_2311_01451_amd import inputs, rsrs
 
@@ -80,10 +83,11 @@ def gpu_bench(steps: int, warmup: int, do_profile: bool, latency_reps: int = 40,
         ctx["op"] = rsrs.rsrs_op_create_kernel(rsrs.RSRS_OP_LOG2D, pts, h)
         ctx["f"] = torch.tensor(inputs.rhs(GRID_N ** 2, NRHS), dtype=torch.float64, device="cuda")
     op, f = ctx["op"], ctx["f"]
-    dtype = rsrs.RSRS_F32 if mixed else rsrs.RSRS_F64
+    mixed = mode != "fp64"
+    dtype = {"bf16": rsrs.RSRS_BF16, "fp32": rsrs.RSRS_F32, "fp64": rsrs.RSRS_F64}[mode]
     prec = rsrs.RSRS_PREC_F32_MIXED if mixed else rsrs.RSRS_PREC_F64
-    if mixed:   # the FP32 copy of the kernel matrix is part of the operator, built once
-        op.matvec(torch.zeros((GRID_N ** 2, 1), dtype=torch.float32, device="cuda"))
+    if mixed:   # the rounded copies of the kernel matrix belong to the operator, built once
+        op.matvec(torch.zeros((GRID_N ** 2, 8), dtype=torch.float32, device="cuda"), bf16=mode == "bf16")
     torch.cuda.synchronize()
 
     def step(record):
@@ -290,7 +294,7 @@ def serving_bench(duration_s: float, load: float = 0.7) -> dict:
     s = max(2048, s_req)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    smp = rsrs.rsrs_sample(tree, op, s, inputs.BASE_SEED, dtype=rsrs.RSRS_F32)
+    smp = rsrs.rsrs_sample(tree, op, s, inputs.BASE_SEED, dtype=rsrs.RSRS_BF16)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     F = rsrs.rsrs_factor(tree, smp, K4, precision=rsrs.RSRS_PREC_F32_MIXED)
@@ -333,7 +337,7 @@ def serving_bench(duration_s: float, load: float = 0.7) -> dict:
         t0s, op0, s0 = small[jnext[0] % len(small)]
         jnext[0] += 1
         return sv.submit_factor(t0s, op0, s0, inputs.BASE_SEED + jnext[0], 32,
-                                precision=rsrs.RSRS_PREC_F32_MIXED)
+                                precision=rsrs.RSRS_PREC_F32_MIXED, dtype=rsrs.RSRS_BF16)
 
     def use_and_release(t):
         fid2, lat = sv.wait(t)
@@ -411,7 +415,8 @@ def serving_bench(duration_s: float, load: float = 0.7) -> dict:
     sv.close()
     return {
         "workload": f"3D kernel delta_ij + (1/N)/(4 pi r), N={N} uniform random points, adaptive octree "
-                    f"leaf {LEAF}, k=p={K4}, s={s} (configured 2048, required {s_req}), mixed precision, "
+                    f"leaf {LEAF}, k=p={K4}, s={s} (configured 2048, required {s_req}), mixed precision "
+                    "(BF16 sample products), "
                     "resident; Poisson stream of solves (widths {1,4,16,64,256}) with 10% new-factor "
                     "requests (64x64 jittered log kernel, k=32), HBM budget 24 GB",
         "factor_s": round(t3 - t2, 3), "sample_s": round(t2 - t1, 3),
@@ -459,10 +464,10 @@ def main():
         return
     ctx = {}
     runs = {}
-    for name, mixed in (("mixed", True), ("fp64", False)):
-        runs[name] = gpu_bench(a.steps, a.warmup, not a.no_profile, a.latency_reps,
-                               a.calib_copy_mib if name == "mixed" else 0, mixed, ctx)
-    ua, ub = runs["mixed"][0][-1]["u"], runs["fp64"][0][-1]["u"]
+    for mode in ("bf16", "fp32", "fp64"):
+        runs[mode] = gpu_bench(a.steps, a.warmup, not a.no_profile, a.latency_reps,
+                               a.calib_copy_mib if mode == "bf16" else 0, mode, ctx)
+    ua, ub = runs["bf16"][0][-1]["u"], runs["fp64"][0][-1]["u"]
     diff = float(((ua - ub).norm() / ub.norm()).item())
 
     def summary(rec, elapsed, prof, lat, steps):
@@ -485,9 +490,10 @@ def main():
                         for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"])[:12]},
         }
 
-    sm = summary(*runs["mixed"], a.steps)
+    sm = summary(*runs["bf16"], a.steps)
+    s32 = summary(*runs["fp32"], a.steps)
     s64 = summary(*runs["fp64"], a.steps)
-    rec = runs["mixed"][0]
+    rec = runs["bf16"][0]
     s_req, s_eff = rec[-1]["s_req"], rec[-1]["s_eff"]
     out = {
         "metric": METRIC,
@@ -505,6 +511,7 @@ def main():
         "config": workload_config(s_req, s_eff),
     }
     out.update({k: v for k, v in sm.items() if k not in ("value", "ms_per_step")})
+    out["mixed_fp32_samples"] = s32
     out["fp64"] = s64
     out["mixed_vs_fp64"] = {"speedup": round(sm["value"] / s64["value"], 3),
                             "factor_speedup": round(s64["factor_s"] / sm["factor_s"], 3),

@@ -135,12 +135,15 @@ int64_t rsrs_samples_required(const rsrs_tree_t* t, int k, int p);
  * `stream`.  It returns 0 on success; any other value aborts the caller with
  * RSRS_E_CALLBACK.
  * ---------------------------------------------------------------------- */
-/* Element type of a device block: RSRS_F64 (double) or RSRS_F32 (float). */
-enum { RSRS_F64 = 0, RSRS_F32 = 1 };
-/* X and Y have element type `dtype`.  The library asks for RSRS_F32 products
- * only while sampling FP32 sketches (rsrs_sample with RSRS_F32); residuals of
- * rsrs_solve_refine are always requested in RSRS_F64.  A callback that does
- * not provide the requested type returns nonzero. */
+/* Element type of a device block: RSRS_F64 (double) or RSRS_F32 (float).
+ * RSRS_BF16 names float blocks whose values are BF16 numbers: a product
+ * requested with it may round the operator to BF16 and accumulate in FP32. */
+enum { RSRS_F64 = 0, RSRS_F32 = 1, RSRS_BF16 = 2 };
+/* X and Y have element type `dtype` (float for RSRS_BF16).  The library asks
+ * for RSRS_F32 / RSRS_BF16 products only while sampling FP32 sketches
+ * (rsrs_sample with that dtype); residuals of rsrs_solve_refine are always
+ * requested in RSRS_F64.  A callback that does not provide the requested
+ * type returns nonzero. */
 typedef int (*rsrs_matvec_fn)(void* user, int transpose, int dtype, int64_t ncols, const void* X,
                               int64_t ldx, void* Y, int64_t ldy, void* stream);
 
@@ -155,7 +158,9 @@ typedef int (*rsrs_matvec_fn)(void* user, int transpose, int dtype, int64_t ncol
  * pts: host n x dim (user order); copied to the device.  The kernel matrix is
  * materialised on the device in FP64 at creation (n^2 doubles); an FP32 copy
  * (n^2 floats) is added at the first RSRS_F32 product, whose product is then
- * an FP32 MFMA GEMM with FP32 accumulation. */
+ * an FP32 MFMA GEMM with FP32 accumulation, and a BF16 copy (n^2 x 2 bytes) at
+ * the first RSRS_BF16 product (BF16 MFMA, FP32 accumulation; n a multiple of
+ * 8; transposed products of the skewed kernel use the FP32 product). */
 enum { RSRS_OP_LOG2D = 1, RSRS_OP_INVR3D = 2, RSRS_OP_LOG2D_SKEW = 3 };
 rsrs_status rsrs_op_create_kernel(int kind, const double* pts, int64_t n, int dim,
                                   double param, double param2, rsrs_operator_t** out);
@@ -187,7 +192,9 @@ rsrs_status rsrs_samples_wrap(const rsrs_tree_t* t, int dtype, const void* Y, co
  * (user row i, column j) of Omega uses counter (i, j, 0, seed_hi) and key
  * (seed_lo, 0x2311); Psi uses stream word 1 in place of 0.  With dtype
  * RSRS_F32 the FP64 normal is rounded to float and `mv` is asked for FP32
- * products of the rounded test matrices. */
+ * products of the rounded test matrices; with RSRS_BF16 it is rounded
+ * further to BF16 (kept in float) and `mv` is asked for RSRS_BF16 products.
+ * Both give FP32 samples for RSRS_PREC_F32_MIXED. */
 rsrs_status rsrs_sample(const rsrs_tree_t* t, rsrs_matvec_fn mv, void* user, int64_t s,
                         uint64_t seed, int dtype, void* stream, rsrs_samples_t** out);
 void rsrs_samples_destroy(rsrs_samples_t* smp);

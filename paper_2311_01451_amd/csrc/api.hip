@@ -22,7 +22,9 @@ rsrs_status factor_batch_impl(int64_t nprob, const rsrs_tree_t* const* trees, rs
 rsrs_status apply_factor(const rsrs_factor_t* F, int op, int transpose, int64_t w, const double* Fin,
                          int64_t ldf, double* Uout, int64_t ldu, hipStream_t st);
 
-static int64_t dtype_size(int dtype) { return dtype == RSRS_F64 ? 8 : (dtype == RSRS_F32 ? 4 : 0); }
+static int64_t dtype_size(int dtype) {
+  return dtype == RSRS_F64 ? 8 : ((dtype == RSRS_F32 || dtype == RSRS_BF16) ? 4 : 0);
+}
 
 static rsrs_status invalid(const char* msg) {
   set_error(msg);
@@ -210,7 +212,7 @@ int rsrs_op_matvec(void* opv, int transpose, int dtype, int64_t ncols, const voi
   if (!op || !X || !Y || ncols < 0 || dtype_size(dtype) == 0) return 1;
   if (ncols == 0) return 0;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (op->kind == 20) {
+  if (op->kind == 20) {   // BF16 requests get the (more accurate) FP32 product
     if (dtype == RSRS_F64)
       return poisson_matvec<double>(st, op->pois, ncols, static_cast<const double*>(X), ldx,
                                     static_cast<double*>(Y), ldy) == RSRS_OK ? 0 : 1;
@@ -236,6 +238,18 @@ int rsrs_op_matvec(void* opv, int transpose, int dtype, int64_t ncols, const voi
   if (op->kind == 10) {
     set_error("a borrowed dense operator provides FP64 products only");
     return 1;
+  }
+  if (dtype == RSRS_BF16 && ta == 0 && op->n <= INT32_MAX && op->n % 8 == 0) {
+    // kernel matrix rounded to BF16, FP32 accumulation
+    if (!op->owned16.p) {
+      if (op->owned16.alloc((size_t)op->n * op->n * 2) != RSRS_OK) return 1;
+      if (bf16_from_f64(st, op->A, op->owned16.as<uint16_t>(), op->n * op->n) != RSRS_OK) return 1;
+    }
+    const int64_t ldt = round_up(op->n, 8);
+    if (op->xt16.alloc((size_t)ncols * ldt * 2) != RSRS_OK) return 1;
+    return gemm_bf16_op(st, op->owned16.as<uint16_t>(), op->n, op->n, op->n, static_cast<const float*>(X),
+                        ldx, ncols, static_cast<float*>(Y), ldy, op->xt16.as<uint16_t>(), ldt) == RSRS_OK
+               ? 0 : 1;
   }
   if (!op->owned32.p) {   // FP32 kernel matrix, entries rounded from the FP64 formula
     if (op->owned32.alloc((size_t)op->n * op->n * 4) != RSRS_OK) return 1;
@@ -312,7 +326,7 @@ rsrs_status rsrs_samples_wrap(const rsrs_tree_t* th, int dtype, const void* Y, c
 extern "C++" {
 template <typename T>
 static rsrs_status sample_t(const rsrs_tree_t* th, rsrs_matvec_fn mv, void* user, uint64_t seed,
-                            void* stream, rsrs_samples_t* smp) {
+                            int mv_dtype, void* stream, rsrs_samples_t* smp) {
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int64_t s = smp->s;
   DevBuf tu, ty, perm;
@@ -324,7 +338,10 @@ static rsrs_status sample_t(const rsrs_tree_t* th, rsrs_matvec_fn mv, void* user
   const int64_t* pp = perm.as<int64_t>();
   for (int side = 0; side < 2; ++side) {
     philox_normal<T>(st, tu.as<T>(), smp->n, s, smp->ld, seed, (uint32_t)side);
-    if (mv(user, side, smp->dtype, s, tu.as<T>(), smp->ld, ty.as<T>(), smp->ld, stream) != 0) {
+    if constexpr (sizeof(T) == 4) {
+      if (mv_dtype == RSRS_BF16) round_to_bf16_values(st, tu.as<float>(), smp->n, s, smp->ld);
+    }
+    if (mv(user, side, mv_dtype, s, tu.as<T>(), smp->ld, ty.as<T>(), smp->ld, stream) != 0) {
       (void)hipStreamSynchronize(st);
       set_error("matvec callback returned nonzero");
       return RSRS_E_CALLBACK;
@@ -347,9 +364,10 @@ rsrs_status rsrs_sample(const rsrs_tree_t* th, rsrs_matvec_fn mv, void* user, in
   if (dtype_size(dtype) == 0) return invalid("unknown dtype");
   *out = nullptr;
   rsrs_samples_t* smp = nullptr;
-  RSRS_TRY(new_samples(th, s, dtype, &smp));
-  const rsrs_status r = dtype == RSRS_F64 ? sample_t<double>(th, mv, user, seed, stream, smp)
-                                          : sample_t<float>(th, mv, user, seed, stream, smp);
+  // BF16 sampling keeps FP32 sketches (test matrices rounded to BF16 values)
+  RSRS_TRY(new_samples(th, s, dtype == RSRS_BF16 ? RSRS_F32 : dtype, &smp));
+  const rsrs_status r = dtype == RSRS_F64 ? sample_t<double>(th, mv, user, seed, dtype, stream, smp)
+                                          : sample_t<float>(th, mv, user, seed, dtype, stream, smp);
   if (r != RSRS_OK) { delete smp; return r; }
   *out = smp;
   return RSRS_OK;

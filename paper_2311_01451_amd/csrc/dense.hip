@@ -260,7 +260,9 @@ rsrs_status chol_leaf(Uploader& up, hipStream_t st, const std::vector<CholLeaf>&
   if (e.empty()) return RSRS_OK;
   CholLeaf* de = nullptr;
   RSRS_TRY(up.put_vec(e, &de));
-  ProfScope ps(st, "chol_leaf");
+  double fl = 0.0;
+  for (const auto& x : e) fl += (2.0 / 3.0) * x.n * x.n * x.n;   // factor + inverse, n^3/3 each
+  ProfScope ps(st, "chol_leaf", fl, 16.0 * 64 * 64 * e.size());
   hipLaunchKernelGGL(chol_leaf_kernel, dim3((unsigned)e.size()), dim3(256), 0, st, de, flag);
   RSRS_HIP(hipGetLastError());
   return RSRS_OK;

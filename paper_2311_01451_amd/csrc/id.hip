@@ -116,6 +116,71 @@ __global__ __launch_bounds__(64) void id_step_kernel(const IdDesc* __restrict__ 
   }
 }
 
+// Same step with the row and the pivot row held in registers (R doubles per
+// lane, s <= 64 R): one read of each and one write of the row per step
+// instead of two passes over both.
+template <int R>
+__global__ __launch_bounds__(64) void id_step_reg_kernel(const IdDesc* __restrict__ e, int j) {
+  const IdDesc d = e[blockIdx.y];
+  const int i = blockIdx.x;
+  if (i >= d.b || j >= d.k) return;
+  const int lane = threadIdx.x;
+  const double* cur = d.norms + (j & 1) * d.b;
+  double* nxt = d.norms + ((j + 1) & 1) * d.b;
+  double best = -1.0;
+  int bi = INT_MAX;
+  for (int x = lane; x < d.b; x += 64) {
+    if (d.sel[x] < j) continue;
+    const double v = cur[x];
+    if (bi == INT_MAX || v > best) { best = v; bi = x; }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ob = __shfl_xor(best, off, 64);
+    const int oi = __shfl_xor(bi, off, 64);
+    if (oi != INT_MAX && (bi == INT_MAX || ob > best || (ob == best && oi < bi))) { best = ob; bi = oi; }
+  }
+  const int p = bi;
+  const double pn2 = best > 0.0 ? best : 0.0;
+  const double pn = sqrt(pn2);
+  if (i == p) {
+    if (lane == 0) {
+      d.sel[p] = j;
+      d.piv[j] = p;
+      d.Rc[(int64_t)p * d.k + j] = pn;
+      nxt[p] = 0.0;
+    }
+    return;
+  }
+  if (d.sel[i] < j) return;
+  double* mi = d.M + (int64_t)i * d.ldm;
+  const double* mp = d.M + (int64_t)p * d.ldm;
+  double ri[R], rp[R];
+  double dot = 0.0;
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const int c = lane + 64 * u;
+    ri[u] = c < d.s ? mi[c] : 0.0;
+    rp[u] = c < d.s ? mp[c] : 0.0;
+    dot += ri[u] * rp[u];
+  }
+  dot = wave_sum(dot);
+  const double coef = pn2 > 0.0 ? dot / pn2 : 0.0;
+  double s = 0.0;
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const int c = lane + 64 * u;
+    const double v = ri[u] - coef * rp[u];
+    if (c < d.s) mi[c] = v;
+    s += c < d.s ? v * v : 0.0;
+  }
+  s = wave_sum(s);
+  if (lane == 0) {
+    d.Rc[(int64_t)i * d.k + j] = pn > 0.0 ? dot / pn : 0.0;
+    nxt[i] = s;
+  }
+}
+
 // S, R sorted; T = (R11^{-1} R12)^T written with columns in sorted-S order.
 // Positions come from a block-wide prefix count of the selected rows; R11
 // (k <= 64) is staged in LDS for the back substitutions, one thread per row of R.
@@ -180,8 +245,9 @@ __global__ __launch_bounds__(256) void id_finalize_kernel(const IdDesc* __restri
 
 rsrs_status id_run(Uploader& up, hipStream_t st, const std::vector<IdDesc>& e) {
   if (e.empty()) return RSRS_OK;
-  int bmax = 0, kmax = 0;
+  int bmax = 0, kmax = 0, smax = 0;
   for (const auto& x : e) {
+    smax = std::max(smax, x.s);
     if (x.k > 256 || x.b > 4352 || x.k >= x.b) {
       set_error("ID sizes out of range (need k < b <= 4352, k <= 256)");
       return RSRS_E_UNSUPPORTED;
@@ -201,9 +267,17 @@ rsrs_status id_run(Uploader& up, hipStream_t st, const std::vector<IdDesc>& e) {
     ProfScope ps(st, "id_init", 0.0, bstep);
     hipLaunchKernelGGL(id_init_kernel, dim3((unsigned)bmax, nb), dim3(64), 0, st, de);
   }
+  // register variant when every row fits (the summation order of the dot
+  // product and norm is then fixed by the lane layout, the same for all s)
+  const int nchunk = (smax + 63) / 64;
   for (int j = 0; j < kmax; ++j) {
     ProfScope ps(st, "id_step", fstep, bstep);
-    hipLaunchKernelGGL(id_step_kernel, dim3((unsigned)bmax, nb), dim3(64), 0, st, de, j);
+    if (nchunk <= 16)
+      hipLaunchKernelGGL(id_step_reg_kernel<16>, dim3((unsigned)bmax, nb), dim3(64), 0, st, de, j);
+    else if (nchunk <= 40)
+      hipLaunchKernelGGL(id_step_reg_kernel<40>, dim3((unsigned)bmax, nb), dim3(64), 0, st, de, j);
+    else
+      hipLaunchKernelGGL(id_step_kernel, dim3((unsigned)bmax, nb), dim3(64), 0, st, de, j);
   }
   {
     ProfScope ps(st, "id_finalize");

@@ -29,6 +29,8 @@ struct rsrs_operator_s {
   const double* A = nullptr; // matrix used by the GEMM matvec
   int64_t lda = 0;
   rsrs::DevBuf owned32;      // FP32 kernel matrix (built at the first FP32 product)
+  rsrs::DevBuf owned16;      // BF16 kernel matrix (built at the first BF16 product)
+  rsrs::DevBuf xt16;         // transposed BF16 copy of the right-hand block
   rsrs::KernelOp kop;        // kernel description (kernel operators)
   bool symmetric = true;
   rsrs::Poisson7Op pois;

@@ -157,6 +157,15 @@ rsrs_status colfix(Uploader& up, hipStream_t st, const std::vector<ColfixDescT<T
 template <typename T>
 void philox_normal(hipStream_t st, T* out, int64_t nrows, int64_t ncols, int64_t ld,
                    uint64_t seed, uint32_t word);
+// BF16 products (bf16.hip): Y (M x N float) = A (M x K bf16) X (K x N float
+// holding BF16 values), FP32 accumulation, with Xt (N x ldt bf16) as workspace.
+rsrs_status gemm_bf16_op(hipStream_t st, const uint16_t* A, int64_t lda, int64_t M, int64_t K,
+                         const float* X, int64_t ldx, int64_t N, float* Y, int64_t ldy, uint16_t* Xt,
+                         int64_t ldt);
+rsrs_status bf16_from_f64(hipStream_t st, const double* src, uint16_t* dst, int64_t n);
+// Rounds every entry of a float block to the nearest BF16 value (kept as float).
+void round_to_bf16_values(hipStream_t st, float* x, int64_t rows, int64_t cols, int64_t ld);
+
 struct KernelOp {
   int kind, dim;
   int64_t n;

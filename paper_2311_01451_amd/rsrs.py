@@ -28,6 +28,7 @@ RSRS_PREC_F64 = 0
 RSRS_PREC_F32_MIXED = 1
 RSRS_F64 = 0
 RSRS_F32 = 1
+RSRS_BF16 = 2
 
 STATUS = {0: "RSRS_OK", 1: "RSRS_E_INVALID", 2: "RSRS_E_SAMPLES", 3: "RSRS_E_SINGULAR",
           4: "RSRS_E_CALLBACK", 5: "RSRS_E_NUMERIC", 6: "RSRS_E_NOMEM", 7: "RSRS_E_HIP",
@@ -298,8 +299,9 @@ class Operator:
     def fn_ptr():
         return C.cast(lib().rsrs_op_matvec, C.c_void_p)
 
-    def matvec(self, X, transpose: bool = False, out=None, stream=None):
-        """A X or A^T X for an FP64 or FP32 device block X (same type out)."""
+    def matvec(self, X, transpose: bool = False, out=None, stream=None, bf16: bool = False):
+        """A X or A^T X for an FP64 or FP32 device block X (same type out);
+        bf16=True asks for the BF16 product of an FP32 block of BF16 values."""
         import torch
         px, ldx = _dev(X, "X", ("float64", "float32"))
         if out is None:
@@ -307,7 +309,8 @@ class Operator:
         if out.dtype != X.dtype:
             raise TypeError("out must have the dtype of X")
         py, ldy = _dev(out, "out", ("float64", "float32"))
-        st = lib().rsrs_op_matvec(self._h, int(transpose), _dtype_code(X), X.shape[1], px, ldx, py,
+        code = RSRS_BF16 if bf16 else _dtype_code(X)
+        st = lib().rsrs_op_matvec(self._h, int(transpose), code, X.shape[1], px, ldx, py,
                                   ldy, _stream(stream))
         if st != 0:
             raise RSRSError(4, "rsrs_op_matvec failed: " + lib().rsrs_last_error().decode())
@@ -551,8 +554,10 @@ class Server:
         return t.value, out
 
     def submit_factor(self, tree: Tree, op: Operator, s: int, seed: int, k: int,
-                      precision: int = RSRS_PREC_F64, p: int = -1, reproject: int = 1) -> int:
-        dtype = RSRS_F64 if precision == RSRS_PREC_F64 else RSRS_F32
+                      precision: int = RSRS_PREC_F64, p: int = -1, reproject: int = 1,
+                      dtype: int | None = None) -> int:
+        if dtype is None:
+            dtype = RSRS_F64 if precision == RSRS_PREC_F64 else RSRS_F32
         o = FactorOpts(int(k), p, precision, reproject)
         t = C.c_int64()
         _check(lib().rsrs_server_submit_factor(self._h, tree.handle, Operator.fn_ptr(), op.handle,

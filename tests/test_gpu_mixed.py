@@ -66,6 +66,54 @@ def test_fp32_operator_products_within_rounding_bound():
         assert np.all(np.abs(Y - M @ Xd) <= bound)
 
 
+def _bf16(x):
+    """Round to the nearest BF16 value (ties to even), through float32 as the
+    library does."""
+    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def test_bf16_operator_products_within_rounding_bound():
+    """BF16 products: A rounded to BF16, X of BF16 values, FP32 accumulation.
+    Each product of two BF16 numbers is exact in FP32, so the FP32 dot-product
+    bound applies to the rounded operands."""
+    need_gpu()
+    n = 40
+    pts = inputs.grid2d(n)
+    N = n * n
+    A16 = _bf16(oop.log2d(pts, 1.0 / n))
+    op = rsrs.rsrs_op_create_kernel(rsrs.RSRS_OP_LOG2D, pts, 1.0 / n)
+    for w in (1, 33, 130, 300):
+        print(f"[bf16 operator] N={N} w={w}", flush=True)
+        X = _bf16(np.random.default_rng(w).standard_normal((N, w)))
+        Y = op.matvec(dev(X, torch.float32), bf16=True).cpu().numpy().astype(np.float64)
+        exact = A16 @ X
+        bound = 1.0001 * N * U32 * (np.abs(A16) @ np.abs(X)) + 1e-30
+        assert np.all(np.abs(Y - exact) <= bound), float(np.max(np.abs(Y - exact) / bound))
+
+
+def test_bf16_sampling_mixed_factor_refines():
+    """rsrs_sample with BF16 products (64x64 grid, k = 32), mixed factor,
+    refinement with the FP64 operator to 1e-10."""
+    need_gpu()
+    n, m, k = 64, 64, 32
+    pts = inputs.grid2d(n)
+    N = n * n
+    A = oop.log2d(pts, 1.0 / n)
+    tc = rsrs.rsrs_build_tree(pts, m)
+    s = tc.samples_required(k, k)
+    op = rsrs.rsrs_op_create_kernel(rsrs.RSRS_OP_LOG2D, pts, 1.0 / n)
+    smp = rsrs.rsrs_sample(tc, op, s, inputs.BASE_SEED, dtype=rsrs.RSRS_BF16)
+    F = rsrs.rsrs_factor(tc, smp, k, precision=rsrs.RSRS_PREC_F32_MIXED)
+    f = inputs.rhs(N, 16)
+    r1 = relres(A, F.solve(dev(f)).cpu().numpy(), f)
+    u, rel, it = rsrs.rsrs_solve_refine(F, op, dev(f), tol=1e-10, maxit=30)
+    print(f"[bf16 sample] one-shot residual {r1:.2e}; refined {rel:.2e} after {it}", flush=True)
+    assert r1 < 1e-3 and rel <= 1e-10
+    assert relres(A, u.cpu().numpy(), f) <= 1.5e-10
+
+
 def test_fp32_poisson_product():
     need_gpu()
     n = 12
