@@ -28,6 +28,14 @@ Plain FP64 NumPy/SciPy, one box after another, in the order fixed by
   Psi_R += K_L^T Psi_SN.
 * Root (Algorithm 1, last step): A_t = Y_Bt pinv(Omega_Bt), LU with partial
   pivoting.
+* Symmetric variant (A = A^T; the paper notes U = L^T and F = E^T for it,
+  Sec. 2.2 and the remark after eq. Ainvfact): with Psi = Omega, Z = Y is
+  the same sketch, so only the Y / Omega side is kept.  The ID of
+  M_Y + M_Z = 2 M_Y equals the ID of M_Y (scaling by 2 is exact and does not
+  move CPQR pivots or T).  To make U = L^T exactly, X_RR is replaced by its
+  symmetric part (X_RR + X_RR^T)/2, K_U = X_RR^{-1} X_{R,SN} and
+  K_L = K_U^T; the root block is symmetrized the same way.  Elimination
+  updates Y_SN -= K_L Y_R and Omega_R += K_U Omega_SN only.
 """
 from __future__ import annotations
 
@@ -121,19 +129,25 @@ def row_id(M: np.ndarray, k: int, want_r11_min: bool = False):
 
 
 def factor(tree: otree.Tree, Y, Z, Om, Psi, k: int, p: int | None = None,
-           keep_M: bool = False, check_samples: bool = True, on_box=None) -> Factorization:
+           keep_M: bool = False, check_samples: bool = True, on_box=None,
+           symmetric: bool = False) -> Factorization:
     """Algorithm 1 on sketches given in user point order (N x s each).
 
     The caller's arrays are not modified; the oracle works on tree-ordered
     copies.  ``on_box(bf, Y, Z, Om, Psi)`` (optional) is called after each box
-    with the updated tree-ordered sketches, for invariant checks."""
+    with the updated tree-ordered sketches, for invariant checks.  With
+    ``symmetric`` (A = A^T) only Y and Om are used (Z, Psi may be None); see
+    the module docstring."""
     if p is None:
         p = k
     perm = tree.perm
     Y = np.array(Y, dtype=np.float64)[perm]
-    Z = np.array(Z, dtype=np.float64)[perm]
     Om = np.array(Om, dtype=np.float64)[perm]
-    Psi = np.array(Psi, dtype=np.float64)[perm]
+    if symmetric:
+        Z, Psi = Y, Om      # the same arrays: one side is updated
+    else:
+        Z = np.array(Z, dtype=np.float64)[perm]
+        Psi = np.array(Psi, dtype=np.float64)[perm]
     s = Y.shape[1]
     sch = otree.schedule(tree, k)
     if check_samples:
@@ -164,7 +178,7 @@ def factor(tree: otree.Tree, Y, Z, Om, Psi, k: int, p: int | None = None,
                 Na = np.sort(np.concatenate([cur[x] for x in nb[b].tolist()])) \
                     if len(nb[b]) else np.zeros(0, dtype=np.int64)
                 bf = _process_box(b, int(lev), int(sch.colour[b]), Ba, Na, Y, Z, Om, Psi,
-                                  k, keep_M)
+                                  k, keep_M, symmetric)
                 boxes_out.append(bf)
                 cur[b] = bf.S
                 if on_box is not None:
@@ -178,17 +192,21 @@ def factor(tree: otree.Tree, Y, Z, Om, Psi, k: int, p: int | None = None,
     else:
         Bt = np.sort(np.concatenate([remaining[int(b)] for b in tree.level_boxes[1]]))
     At = _right_pinv_apply(Y[Bt], Om[Bt])
+    if symmetric:
+        At = 0.5 * (At + At.T)
     return Factorization(tree=tree, k=k, p=p, s=s, boxes=boxes_out, Bt=Bt, At=At,
                          At_lu=sla.lu_factor(At), perm=perm)
 
 
-def _process_box(box, lev, colour, Ba, Na, Y, Z, Om, Psi, k, keep_M) -> BoxFactor:
+def _process_box(box, lev, colour, Ba, Na, Y, Z, Om, Psi, k, keep_M, symmetric=False) -> BoxFactor:
     b = Ba.shape[0]
     C = np.concatenate([Ba, Na])
     l = C.shape[0]
     s = Y.shape[1]
     if s - l < k:
         raise InsufficientSamples(f"box {box}: s - l = {s - l} < k = {k}")
+    if symmetric:
+        return _process_box_symmetric(box, lev, colour, Ba, Na, C, Y, Om, k, keep_M)
     # block nullification, eq. nullYZ (projector form, see module docstring)
     M = nullify(Y[Ba], Om[C]) + nullify(Z[Ba], Psi[C])
     norm_yz = float(np.sqrt(np.sum(Y[Ba] ** 2) + np.sum(Z[Ba] ** 2)))
@@ -219,6 +237,31 @@ def _process_box(box, lev, colour, Ba, Na, Y, Z, Om, Psi, k, keep_M) -> BoxFacto
     return BoxFactor(box=box, level=lev, colour=colour, Ba=Ba, Na=Na, S=Sg, R=Rg, T=T,
                      XRR=XRR, lu=lu, KU=KU, KL=KL, M=M if keep_M else None,
                      norm_yz=norm_yz, norm_m=float(np.linalg.norm(M)), r11_min=r11_min)
+
+
+def _process_box_symmetric(box, lev, colour, Ba, Na, C, Y, Om, k, keep_M) -> BoxFactor:
+    """One box of the symmetric variant (module docstring): the Y / Omega side
+    of the general step, X_RR symmetrized, K_L = K_U^T."""
+    M = nullify(Y[Ba], Om[C])
+    norm_yz = float(np.sqrt(2.0 * np.sum(Y[Ba] ** 2)))
+    S_pos, R_pos, T, r11_min = row_id(M, k, want_r11_min=True)
+    Sg = Ba[S_pos]
+    Rg = Ba[R_pos]
+    Y[Rg] -= T @ Y[Sg]
+    Om[Sg] += T.T @ Om[Rg]
+    Ch = np.concatenate([Rg, Sg, Na])
+    r = Rg.shape[0]
+    Xy = _right_pinv_apply(Y[Rg], Om[Ch])
+    XRR = 0.5 * (Xy[:, :r] + Xy[:, :r].T)
+    lu = sla.lu_factor(XRR)
+    KU = sla.lu_solve(lu, Xy[:, r:])
+    KL = KU.T.copy()
+    SN = np.concatenate([Sg, Na])
+    Y[SN] -= KL @ Y[Rg]
+    Om[Rg] += KU @ Om[SN]
+    return BoxFactor(box=box, level=lev, colour=colour, Ba=Ba, Na=Na, S=Sg, R=Rg, T=T,
+                     XRR=XRR, lu=lu, KU=KU, KL=KL, M=M if keep_M else None,
+                     norm_yz=norm_yz, norm_m=float(2.0 * np.linalg.norm(M)), r11_min=2.0 * r11_min)
 
 
 # ----------------------------------------------------------------------------

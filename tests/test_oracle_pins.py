@@ -326,6 +326,48 @@ def test_refinement_and_solve_error_bound():
     assert hist[-1] < 1e-13 and len(hist) <= 6
 
 
+def _exact_h2_symmetric(t, r, seed=5):
+    """Symmetric exactly-H2 matrix: symmetric leaf blocks + U U^T (rank r)."""
+    rng = np.random.default_rng(seed)
+    N = t.n
+    A = np.zeros((N, N))
+    for b in np.nonzero(t.is_leaf)[0]:
+        idx = t.perm[t.pt_begin[b]:t.pt_end[b]]
+        m = len(idx)
+        g = rng.standard_normal((m, m))
+        A[np.ix_(idx, idx)] = g + g.T + 2 * m * np.eye(m)
+    U = rng.standard_normal((N, r))
+    return A + U @ U.T
+
+
+def test_symmetric_variant():
+    """Symmetric variant (U = L^T, Sec. 2.2): on a symmetric operator it
+    (a) gives a symmetric approximate inverse: the solve equals its transpose,
+    (b) reaches the accuracy of the general path (trend, within 10x),
+    (c) is exact on an exactly H2 symmetric operator, and
+    (d) apply inverts solve."""
+    A, t, Om, Psi = _small_log_problem(n=32, m=32, k=12)
+    assert np.abs(A - A.T).max() == 0.0
+    Fs = orr.factor(t, A @ Om, None, Om, None, 12, symmetric=True)
+    Fg = orr.factor(t, A @ Om, A.T @ Psi, Om, Psi, 12)
+    f = inputs.rhs(A.shape[0], 3)
+    u = orr.solve(Fs, f)
+    assert np.abs(u - orr.solve(Fs, f, transpose=True)).max() < 1e-12 * np.abs(u).max()
+    for bf in Fs.boxes:
+        assert np.array_equal(bf.KL, bf.KU.T) and np.array_equal(bf.XRR, bf.XRR.T)
+    es, eg = orr.relerr(Fs, A), orr.relerr(Fg, A)
+    assert es < 10 * eg + 1e-14, (es, eg)
+    assert np.abs(orr.apply(Fs, u) - f).max() < 1e-12 * np.abs(f).max()
+    pts = inputs.grid2d(16)
+    th = ot.build_tree(pts, leaf_size=16)
+    H = _exact_h2_symmetric(th, r=3)
+    k = 6
+    s = ot.samples_required(th, k, k)
+    Om2, _ = inputs.test_matrices(256, s)
+    Fh = orr.factor(th, H @ Om2, None, Om2, None, k, symmetric=True)
+    assert orr.relerr(Fh, H) < 1e-11
+
+
 def test_insufficient_samples_raises():
     A, t, Om, Psi = _small_log_problem()
     with pytest.raises(orr.InsufficientSamples):
