@@ -11,12 +11,14 @@ s = max(640, s_required) and reports both.
 One step = the whole hot path on one batch: build the tree, draw Omega/Psi
 and sample Y = A Omega, Z = A^T Psi through the operator, factor (Algorithm
 1), solve the 16 right-hand sides and refine with the FP64 residual of the
-operator until the relative residual is <= 1e-6.  It runs in two precisions:
-mixed (BF16 sample products with FP32 accumulation, FP32 sketches and MFMA
-products in the factorization, FP64 pivots, inverses and residuals), the same
-with FP32 sample products, and plain FP64.  value = right-hand-side columns
-solved per second of step time of the first; the others are reported beside
-it ("mixed_fp32_samples", "fp64").  The
+operator until the relative residual is <= 1e-6.  The operator is symmetric,
+so the step uses the symmetric variant (U = L^T, one sketch side); it runs in
+two precisions: mixed (BF16 sample products with FP32 accumulation, FP32
+sketches and MFMA products in the factorization, FP64 pivots, inverses and
+residuals) and plain FP64, and both again with the general two-sided
+algorithm.  value = right-hand-side columns solved per second of step time
+of the mixed symmetric path; the others are reported beside it
+("mixed_general", "fp64", "fp64_general").  The
 operator itself (the black box) is built once outside the timed region.
 
 Prints ONE JSON line (rank 0).  Extra fields: per-phase times, p50/p99 solve
@@ -59,11 +61,14 @@ def workload_config(s_req: int, s_eff: int) -> dict:
             "s_required": s_req, "s": s_eff, "nrhs": NRHS, "tol": TOL,
             "precision": "mixed: BF16 sample products (FP32 accumulation), FP32 sketches and MFMA "
                          "products in the factorization, FP64 Cholesky, pivoted QR, Gauss-Jordan "
-                         "and residuals; the FP32-sample mixed path and the FP64 path beside it"}
+                         "and residuals; FP64 beside it",
+            "variant": "symmetric (A = A^T: U = L^T, one sketch side); the general two-sided "
+                       "algorithm is reported beside it"}
 
 
 def gpu_bench(steps: int, warmup: int, do_profile: bool, latency_reps: int = 40,
-              calib_copy_mib: int = 0, mode: str = "fp64", ctx: dict | None = None):
+              calib_copy_mib: int = 0, mode: str = "fp64", ctx: dict | None = None,
+              symmetric: bool = True):
     import torch
     from paper_2311_01451_amd import inputs, rsrs
 
@@ -96,10 +101,10 @@ def gpu_bench(steps: int, warmup: int, do_profile: bool, latency_reps: int = 40,
         s_req = tree.samples_required(K, K)
         s_eff = max(S_CFG, s_req)
         t1 = time.perf_counter()
-        smp = rsrs.rsrs_sample(tree, op, s_eff, inputs.BASE_SEED, dtype=dtype)
+        smp = rsrs.rsrs_sample(tree, op, s_eff, inputs.BASE_SEED, dtype=dtype, symmetric=symmetric)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        F = rsrs.rsrs_factor(tree, smp, K, precision=prec)
+        F = rsrs.rsrs_factor(tree, smp, K, precision=prec, symmetric=symmetric)
         torch.cuda.synchronize()
         t3 = time.perf_counter()
         u, rel, it = rsrs.rsrs_solve_refine(F, op, f, tol=TOL, maxit=30)
@@ -464,10 +469,12 @@ def main():
         return
     ctx = {}
     runs = {}
-    for mode in ("bf16", "fp32", "fp64"):
-        runs[mode] = gpu_bench(a.steps, a.warmup, not a.no_profile, a.latency_reps,
-                               a.calib_copy_mib if mode == "bf16" else 0, mode, ctx)
-    ua, ub = runs["bf16"][0][-1]["u"], runs["fp64"][0][-1]["u"]
+    plan = (("mixed", "bf16", True), ("mixed_general", "bf16", False),
+            ("fp64", "fp64", True), ("fp64_general", "fp64", False))
+    for name, mode, sym in plan:
+        runs[name] = gpu_bench(a.steps, a.warmup, not a.no_profile, a.latency_reps,
+                               a.calib_copy_mib if name == "mixed" else 0, mode, ctx, sym)
+    ua, ub = runs["mixed"][0][-1]["u"], runs["fp64"][0][-1]["u"]
     diff = float(((ua - ub).norm() / ub.norm()).item())
 
     def summary(rec, elapsed, prof, lat, steps):
@@ -490,10 +497,11 @@ def main():
                         for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"])[:12]},
         }
 
-    sm = summary(*runs["bf16"], a.steps)
-    s32 = summary(*runs["fp32"], a.steps)
+    sm = summary(*runs["mixed"], a.steps)
+    smg = summary(*runs["mixed_general"], a.steps)
     s64 = summary(*runs["fp64"], a.steps)
-    rec = runs["bf16"][0]
+    s64g = summary(*runs["fp64_general"], a.steps)
+    rec = runs["mixed"][0]
     s_req, s_eff = rec[-1]["s_req"], rec[-1]["s_eff"]
     out = {
         "metric": METRIC,
@@ -511,8 +519,9 @@ def main():
         "config": workload_config(s_req, s_eff),
     }
     out.update({k: v for k, v in sm.items() if k not in ("value", "ms_per_step")})
-    out["mixed_fp32_samples"] = s32
+    out["mixed_general"] = {k: v for k, v in smg.items() if k != "kernels"}
     out["fp64"] = s64
+    out["fp64_general"] = {k: v for k, v in s64g.items() if k != "kernels"}
     out["mixed_vs_fp64"] = {"speedup": round(sm["value"] / s64["value"], 3),
                             "factor_speedup": round(s64["factor_s"] / sm["factor_s"], 3),
                             "solution_rel_diff": diff}

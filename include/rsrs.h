@@ -197,6 +197,13 @@ rsrs_status rsrs_samples_wrap(const rsrs_tree_t* t, int dtype, const void* Y, co
  * Both give FP32 samples for RSRS_PREC_F32_MIXED. */
 rsrs_status rsrs_sample(const rsrs_tree_t* t, rsrs_matvec_fn mv, void* user, int64_t s,
                         uint64_t seed, int dtype, void* stream, rsrs_samples_t** out);
+/* Symmetric operators (A = A^T): only Omega and Y = A Omega are drawn /
+ * taken (Z = Y and Psi = Omega implicitly); for opts.symmetric = 1. */
+rsrs_status rsrs_sample_symmetric(const rsrs_tree_t* t, rsrs_matvec_fn mv, void* user, int64_t s,
+                                  uint64_t seed, int dtype, void* stream, rsrs_samples_t** out);
+rsrs_status rsrs_samples_wrap_symmetric(const rsrs_tree_t* t, int dtype, const void* Y,
+                                        const void* Omega, int64_t ld, int64_t s, void* stream,
+                                        rsrs_samples_t** out);
 void rsrs_samples_destroy(rsrs_samples_t* smp);
 
 /* Fill a device array with standard normals from the generator above:
@@ -223,6 +230,15 @@ rsrs_status rsrs_gaussian(double* out, int64_t nrows, int64_t ncols, int64_t ld,
  * are inverted by FP64 Gauss-Jordan with partial pivoting.  Solves with such a
  * factor take and return FP64 blocks and compute in FP32; accuracy is
  * recovered by rsrs_solve_refine with the FP64 black-box residual.
+ *
+ * Symmetric variant (opts.symmetric = 1, for A = A^T; U = L^T as noted in
+ * Sec. 2.2 and after eq. Ainvfact): with Psi = Omega the two sketches
+ * coincide, so only Y and Omega are used (samples from
+ * rsrs_sample_symmetric / rsrs_samples_wrap_symmetric, or the Y / Omega half
+ * of general samples).  Each box runs the Y / Omega side of the general step;
+ * X_RR and the root block are replaced by their symmetric parts and
+ * K_L = K_U^T, so the approximate inverse is exactly symmetric.  Symmetric
+ * samples with opts.symmetric = 0 -> RSRS_E_INVALID.
  * ---------------------------------------------------------------------- */
 enum { RSRS_PREC_F64 = 0, RSRS_PREC_F32_MIXED = 1 };
 typedef struct {
@@ -230,6 +246,7 @@ typedef struct {
   int p;            /* oversampling used in the sample check; < 0 -> p = k */
   int precision;    /* RSRS_PREC_F64 (FP64 samples) or RSRS_PREC_F32_MIXED (FP32 samples) */
   int reproject;    /* extra projection passes in the nullification (0 or 1; default 1) */
+  int symmetric;    /* 1: symmetric variant for A = A^T (see below); 0: general */
 } rsrs_factor_opts;
 
 rsrs_status rsrs_factor(const rsrs_tree_t* t, rsrs_samples_t* smp, const rsrs_factor_opts* opts,

@@ -264,18 +264,20 @@ int rsrs_op_matvec(void* opv, int transpose, int dtype, int64_t ncols, const voi
 void rsrs_op_destroy(rsrs_operator_t* op) { delete op; }
 
 // ------------------------------------------------------------------ samples
-static rsrs_status new_samples(const rsrs_tree_t* th, int64_t s, int dtype, rsrs_samples_t** out) {
+static rsrs_status new_samples(const rsrs_tree_t* th, int64_t s, int dtype, rsrs_samples_t** out,
+                               bool symmetric = false) {
   auto smp = new rsrs_samples_t();
   smp->tree = th;
   smp->n = th->t.n;
   smp->s = s;
   smp->ld = round_up(s, 16);
   smp->dtype = dtype;
+  smp->symmetric = symmetric;
   const size_t bytes = (size_t)smp->n * smp->ld * dtype_size(dtype);
   rsrs_status st = smp->Y.alloc(bytes);
-  if (st == RSRS_OK) st = smp->Z.alloc(bytes);
+  if (st == RSRS_OK && !symmetric) st = smp->Z.alloc(bytes);
   if (st == RSRS_OK) st = smp->Om.alloc(bytes);
-  if (st == RSRS_OK) st = smp->Psi.alloc(bytes);
+  if (st == RSRS_OK && !symmetric) st = smp->Psi.alloc(bytes);
   if (st != RSRS_OK) { delete smp; return st; }
   *out = smp;
   return RSRS_OK;
@@ -287,22 +289,24 @@ static void gather_samples(hipStream_t st, rsrs_samples_t* smp, const void* Y, c
                            const void* Om, const void* Psi, int64_t ld, const int64_t* pp) {
   const int64_t s = smp->s;
   gather_rows<T, T>(st, smp->Y.as<T>(), smp->ld, static_cast<const T*>(Y), ld, pp, smp->n, s);
-  gather_rows<T, T>(st, smp->Z.as<T>(), smp->ld, static_cast<const T*>(Z), ld, pp, smp->n, s);
   gather_rows<T, T>(st, smp->Om.as<T>(), smp->ld, static_cast<const T*>(Om), ld, pp, smp->n, s);
+  if (smp->symmetric) return;
+  gather_rows<T, T>(st, smp->Z.as<T>(), smp->ld, static_cast<const T*>(Z), ld, pp, smp->n, s);
   gather_rows<T, T>(st, smp->Psi.as<T>(), smp->ld, static_cast<const T*>(Psi), ld, pp, smp->n, s);
 }
 
 }  // extern "C++"
 
-rsrs_status rsrs_samples_wrap(const rsrs_tree_t* th, int dtype, const void* Y, const void* Z,
-                              const void* Om, const void* Psi, int64_t ld, int64_t s, void* stream,
-                              rsrs_samples_t** out) {
-  if (!th || !Y || !Z || !Om || !Psi || !out || s < 1 || ld < s) return invalid("bad samples arguments");
-  if (dtype_size(dtype) == 0) return invalid("unknown dtype");
+static rsrs_status wrap_impl(const rsrs_tree_t* th, int dtype, const void* Y, const void* Z,
+                             const void* Om, const void* Psi, int64_t ld, int64_t s, void* stream,
+                             rsrs_samples_t** out, bool symmetric) {
+  if (!th || !Y || !Om || (!symmetric && (!Z || !Psi)) || !out || s < 1 || ld < s)
+    return invalid("bad samples arguments");
+  if (dtype != RSRS_F64 && dtype != RSRS_F32) return invalid("unknown dtype");
   *out = nullptr;
   hipStream_t st = static_cast<hipStream_t>(stream);
   rsrs_samples_t* smp = nullptr;
-  RSRS_TRY(new_samples(th, s, dtype, &smp));
+  RSRS_TRY(new_samples(th, s, dtype, &smp, symmetric));
   DevBuf perm;
   rsrs_status r = perm.alloc((size_t)smp->n * 8);
   if (r != RSRS_OK) { delete smp; return r; }
@@ -323,6 +327,17 @@ rsrs_status rsrs_samples_wrap(const rsrs_tree_t* th, int dtype, const void* Y, c
   return RSRS_OK;
 }
 
+rsrs_status rsrs_samples_wrap(const rsrs_tree_t* th, int dtype, const void* Y, const void* Z,
+                              const void* Om, const void* Psi, int64_t ld, int64_t s, void* stream,
+                              rsrs_samples_t** out) {
+  return wrap_impl(th, dtype, Y, Z, Om, Psi, ld, s, stream, out, false);
+}
+
+rsrs_status rsrs_samples_wrap_symmetric(const rsrs_tree_t* th, int dtype, const void* Y, const void* Om,
+                                        int64_t ld, int64_t s, void* stream, rsrs_samples_t** out) {
+  return wrap_impl(th, dtype, Y, nullptr, Om, nullptr, ld, s, stream, out, true);
+}
+
 extern "C++" {
 template <typename T>
 static rsrs_status sample_t(const rsrs_tree_t* th, rsrs_matvec_fn mv, void* user, uint64_t seed,
@@ -336,7 +351,7 @@ static rsrs_status sample_t(const rsrs_tree_t* th, rsrs_matvec_fn mv, void* user
   RSRS_TRY(perm.alloc((size_t)smp->n * 8));
   RSRS_HIP(hipMemcpyAsync(perm.p, th->t.perm.data(), (size_t)smp->n * 8, hipMemcpyHostToDevice, st));
   const int64_t* pp = perm.as<int64_t>();
-  for (int side = 0; side < 2; ++side) {
+  for (int side = 0; side < (smp->symmetric ? 1 : 2); ++side) {
     philox_normal<T>(st, tu.as<T>(), smp->n, s, smp->ld, seed, (uint32_t)side);
     if constexpr (sizeof(T) == 4) {
       if (mv_dtype == RSRS_BF16) round_to_bf16_values(st, tu.as<float>(), smp->n, s, smp->ld);
@@ -358,19 +373,30 @@ static rsrs_status sample_t(const rsrs_tree_t* th, rsrs_matvec_fn mv, void* user
 
 }  // extern "C++"
 
-rsrs_status rsrs_sample(const rsrs_tree_t* th, rsrs_matvec_fn mv, void* user, int64_t s, uint64_t seed,
-                        int dtype, void* stream, rsrs_samples_t** out) {
+static rsrs_status sample_impl(const rsrs_tree_t* th, rsrs_matvec_fn mv, void* user, int64_t s,
+                               uint64_t seed, int dtype, void* stream, rsrs_samples_t** out,
+                               bool symmetric) {
   if (!th || !mv || !out || s < 1) return invalid("bad sample arguments");
   if (dtype_size(dtype) == 0) return invalid("unknown dtype");
   *out = nullptr;
   rsrs_samples_t* smp = nullptr;
   // BF16 sampling keeps FP32 sketches (test matrices rounded to BF16 values)
-  RSRS_TRY(new_samples(th, s, dtype == RSRS_BF16 ? RSRS_F32 : dtype, &smp));
+  RSRS_TRY(new_samples(th, s, dtype == RSRS_BF16 ? RSRS_F32 : dtype, &smp, symmetric));
   const rsrs_status r = dtype == RSRS_F64 ? sample_t<double>(th, mv, user, seed, dtype, stream, smp)
                                           : sample_t<float>(th, mv, user, seed, dtype, stream, smp);
   if (r != RSRS_OK) { delete smp; return r; }
   *out = smp;
   return RSRS_OK;
+}
+
+rsrs_status rsrs_sample(const rsrs_tree_t* th, rsrs_matvec_fn mv, void* user, int64_t s, uint64_t seed,
+                        int dtype, void* stream, rsrs_samples_t** out) {
+  return sample_impl(th, mv, user, s, seed, dtype, stream, out, false);
+}
+
+rsrs_status rsrs_sample_symmetric(const rsrs_tree_t* th, rsrs_matvec_fn mv, void* user, int64_t s,
+                                  uint64_t seed, int dtype, void* stream, rsrs_samples_t** out) {
+  return sample_impl(th, mv, user, s, seed, dtype, stream, out, true);
 }
 
 void rsrs_samples_destroy(rsrs_samples_t* smp) { delete smp; }

@@ -573,7 +573,7 @@ __global__ void copy2d_kernel(const Copy2DT<TS, TD>* __restrict__ e) {
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = idx / d.cols, c = idx % d.cols;
-    const double v = d.alpha * (double)d.src[i * d.lds + c];
+    const double v = d.alpha * (double)(d.trans ? d.src[c * d.lds + i] : d.src[i * d.lds + c]);
     if (d.accumulate) d.dst[i * d.ldd + c] = (TD)((double)d.dst[i * d.ldd + c] + v);
     else d.dst[i * d.ldd + c] = (TD)v;
   }
@@ -593,6 +593,37 @@ rsrs_status copy2d(Uploader& up, hipStream_t st, const std::vector<Copy2DT<TS, T
   RSRS_HIP(hipGetLastError());
   return RSRS_OK;
 }
+
+template <typename T>
+__global__ void sym_kernel(const SymDesc<T>* __restrict__ e) {
+  const SymDesc<T> d = e[blockIdx.y];
+  const int64_t total = (int64_t)d.n * d.n;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = idx / d.n, c = idx % d.n;
+    if (c >= i) continue;   // each pair once, by its lower element
+    const T v = (T)(0.5 * ((double)d.A[i * d.ld + c] + (double)d.A[c * d.ld + i]));
+    d.A[i * d.ld + c] = v;
+    d.A[c * d.ld + i] = v;
+  }
+}
+
+template <typename T>
+rsrs_status symmetrize(Uploader& up, hipStream_t st, const std::vector<SymDesc<T>>& e) {
+  if (e.empty()) return RSRS_OK;
+  int64_t mx = 0;
+  for (const auto& x : e) mx = std::max<int64_t>(mx, (int64_t)x.n * x.n);
+  if (mx == 0) return RSRS_OK;
+  SymDesc<T>* de = nullptr;
+  RSRS_TRY(up.put_vec(e, &de));
+  const unsigned gx = (unsigned)std::min<int64_t>((mx + 255) / 256, 1024);
+  ProfScope ps(st, "symmetrize");
+  hipLaunchKernelGGL((sym_kernel<T>), dim3(gx, (unsigned)e.size()), dim3(256), 0, st, de);
+  RSRS_HIP(hipGetLastError());
+  return RSRS_OK;
+}
+template rsrs_status symmetrize<double>(Uploader&, hipStream_t, const std::vector<SymDesc<double>>&);
+template rsrs_status symmetrize<float>(Uploader&, hipStream_t, const std::vector<SymDesc<float>>&);
 
 template <typename TS, typename TD>
 __global__ void gather_rows_kernel(TD* dst, int64_t ldd, const TS* src, int64_t lds,

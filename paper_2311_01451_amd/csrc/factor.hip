@@ -169,6 +169,7 @@ struct Job {
   const rsrs_tree_t* th = nullptr;
   rsrs_samples_t* smp = nullptr;
   int k = 0, p = 0, reproject = 1;
+  bool sym = false;             // symmetric variant: the Y / Omega side only
   Schedule sch;
   std::unique_ptr<rsrs_factor_t> F;
   T *Y = nullptr, *Z = nullptr, *Om = nullptr, *Psi = nullptr;
@@ -241,6 +242,7 @@ rsrs_status job_init(Job<T>& J, const rsrs_tree_t* th, rsrs_samples_t* smp,
   J.k = o->k;
   J.p = o->p < 0 ? J.k : o->p;
   J.reproject = o->reproject;
+  J.sym = o->symmetric != 0;
   const Tree& t = th->t;
   const int k = J.k;
   make_schedule(t, k, J.sch);
@@ -254,9 +256,9 @@ rsrs_status job_init(Job<T>& J, const rsrs_tree_t* th, rsrs_samples_t* smp,
   J.sld = smp->ld;
   J.n = t.n;
   J.Y = smp->Y.as<T>();
-  J.Z = smp->Z.as<T>();
   J.Om = smp->Om.as<T>();
-  J.Psi = smp->Psi.as<T>();
+  J.Z = J.sym ? J.Y : smp->Z.as<T>();
+  J.Psi = J.sym ? J.Om : smp->Psi.as<T>();
   J.F = std::make_unique<rsrs_factor_t>();
   rsrs_factor_t* F = J.F.get();
   F->n = J.n;
@@ -358,9 +360,11 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
     RSRS_HIP(hipMemcpyAsync(J.F->perm.p, J.tree().perm.data(), (size_t)J.n * 8, hipMemcpyHostToDevice, st));
     // non-finite samples are rejected up front
     check_finite(st, J.Y, J.n, J.s, J.sld, flag);
-    check_finite(st, J.Z, J.n, J.s, J.sld, flag);
     check_finite(st, J.Om, J.n, J.s, J.sld, flag);
-    check_finite(st, J.Psi, J.n, J.s, J.sld, flag);
+    if (!J.sym) {
+      check_finite(st, J.Z, J.n, J.s, J.sld, flag);
+      check_finite(st, J.Psi, J.n, J.s, J.sld, flag);
+    }
   }
   RSRS_TRY(up.reset());
   {
@@ -449,14 +453,16 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
         const int l = (int)(R.b + R.n);
         const int64_t* idxC = J.iS + R.oBa;
         gd.push_back(gdescT<T, double>(J.Om, idxC, J.sld, J.Om, idxC, J.sld, w.GO, nullptr, w.lp, l, l, (int)J.s));
-        gd.push_back(gdescT<T, double>(J.Psi, idxC, J.sld, J.Psi, idxC, J.sld, w.GP, nullptr, w.lp, l, l, (int)J.s));
         cm.push_back(CholMat{w.GO, w.LO, w.lp, l});
-        cm.push_back(CholMat{w.GP, w.LP, w.lp, l});
+        if (!J.sym) {
+          gd.push_back(gdescT<T, double>(J.Psi, idxC, J.sld, J.Psi, idxC, J.sld, w.GP, nullptr, w.lp, l, l, (int)J.s));
+          cm.push_back(CholMat{w.GP, w.LP, w.lp, l});
+        }
         lmax = std::max(lmax, l);
-        const double dl = l, db = (double)R.b, ds = (double)J.s;
-        it.J->flops += 2.0 * dl * dl * ds                               // two Gram matrices
-                       + 2.0 * (2.0 / 3.0) * dl * dl * dl               // Cholesky + inverse factor
-                       + (1.0 + J.reproject) * 2.0 * (4.0 * db * dl * ds + 2.0 * db * dl * dl);  // projections
+        const double dl = l, db = (double)R.b, ds = (double)J.s, sides = J.sym ? 1.0 : 2.0;
+        it.J->flops += sides * (dl * dl * ds                              // Gram matrices
+                                + (2.0 / 3.0) * dl * dl * dl              // Cholesky + inverse factor
+                                + (1.0 + J.reproject) * (4.0 * db * dl * ds + 2.0 * db * dl * dl));  // projections
       }
       RSRS_TRY(gemm<T, double>(up, st, gd, 0, 1, GM_SYRK_L, GS_64x64, "gram"));
       RSRS_TRY(rchol(up, st, cm, 0, chol_span(lmax), flag));
@@ -465,7 +471,8 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
         for (auto& it : items) {
           const int l = (int)(it.R->b + it.R->n);
           lc.push_back(Copy2DT<double, T>{it.w.LO, it.w.LOt, it.w.lp, it.w.lp, l, l, 1.0, 0, 0});
-          lc.push_back(Copy2DT<double, T>{it.w.LP, it.w.LPt, it.w.lp, it.w.lp, l, l, 1.0, 0, 0});
+          if (!it.J->sym)
+            lc.push_back(Copy2DT<double, T>{it.w.LP, it.w.LPt, it.w.lp, it.w.lp, l, l, 1.0, 0, 0});
         }
         RSRS_TRY(copy2d<double, T>(up, st, lc));
       }
@@ -483,7 +490,7 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
         const int64_t* idxB = J.iS + R.oBa;
         const int64_t* idxC = J.iS + R.oBa;
         const int64_t sld = J.sld;
-        for (int side = 0; side < 2; ++side) {
+        for (int side = 0; side < (J.sym ? 1 : 2); ++side) {
           T* Ysd = side ? J.Z : J.Y;
           T* Tst = side ? J.Psi : J.Om;
           T* Pb = side ? w.PZ : w.PY;
@@ -522,12 +529,13 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
         const Job<T>& J = *it.J;
         const BoxWs<T>& w = it.w;
         IdDesc e{};
+        // symmetric variant: M = M_Y (the ID of 2 M_Y is the same)
         if constexpr (mixed) {
           e.M = w.Md; e.MZ = nullptr; e.ldm = J.sld; e.ldz = J.sld;
-          e.MYf = w.MY; e.MZf = w.MZ; e.ldf = J.sld;
+          e.MYf = w.MY; e.MZf = J.sym ? nullptr : w.MZ; e.ldf = J.sld;
           e.T = w.Td; e.ldt = (int)round_up(J.k, 4);
         } else {
-          e.M = w.MY; e.MZ = w.MZ; e.ldm = J.sld; e.ldz = J.sld;
+          e.M = w.MY; e.MZ = J.sym ? nullptr : w.MZ; e.ldm = J.sld; e.ldz = J.sld;
           e.T = J.dS + R.oT; e.ldt = (int)R.ldT;
         }
         e.norms = w.norms; e.sel = w.sel; e.Rc = w.Rc; e.piv = w.piv;
@@ -598,6 +606,8 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
       std::vector<Copy2DT<T, double>> cxd;
       std::vector<Copy2DT<double, T>> cinv;
       std::vector<GjeDesc> gj;
+      std::vector<SymDesc<T>> symx;
+      std::vector<SymDesc<double>> symi;
       for (auto& it : items) {
         const BoxRec& R = *it.R;
         Job<T>& J = *it.J;
@@ -605,7 +615,12 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
         const int k = J.k;
         T* dS = J.dS;
         const int l = (int)(R.b + R.n), r = (int)R.r;
-        for (int side = 0; side < 2; ++side) {
+        if (J.sym) {   // symmetric part of X_RR, and of its inverse below
+          symx.push_back(SymDesc<T>{w.Xpy, w.lp, r, 0});
+          if constexpr (mixed) symi.push_back(SymDesc<double>{w.Xinvd, r, r, 0});
+          else symi.push_back(SymDesc<double>{reinterpret_cast<double*>(dS + R.oXinv), R.ldR, r, 0});
+        }
+        for (int side = 0; side < (J.sym ? 1 : 2); ++side) {
           T* Xb = side ? w.XZ : w.XY;
           T* XR = side ? w.XRz : w.XRy;
           T* Xp = side ? w.Xpz : w.Xpy;
@@ -622,29 +637,37 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
           gj.push_back(GjeDesc{reinterpret_cast<const double*>(w.Xpy), w.gje,
                                reinterpret_cast<double*>(dS + R.oXinv), w.lp, R.ldR, r, 0});
         }
-        const double dr = r, dk = k, dn = (double)R.n, ds = (double)J.s;
-        J.flops += 2.0 * (2.0 * dr * dk * l + 2.0 * dr * dr * dk) + 2.0 * dr * dr * dr +
-                   2.0 * 2.0 * dr * dr * (dk + dn) + 4.0 * 2.0 * dr * dk * ds + 4.0 * 2.0 * dr * (dk + dn) * ds;
+        const double dr = r, dk = k, dn = (double)R.n, ds = (double)J.s, sides = J.sym ? 1.0 : 2.0;
+        J.flops += sides * (2.0 * dr * dk * l + 2.0 * dr * dr * dk) + 2.0 * dr * dr * dr +
+                   sides * 2.0 * dr * dr * (dk + dn) + sides * 2.0 * 2.0 * dr * dk * ds +
+                   sides * 2.0 * 2.0 * dr * (dk + dn) * ds;
       }
       RSRS_TRY(gemm<T, T>(up, st, gxr, 0, 0, GM_FULL, GS_64x64, "extract"));
       RSRS_TRY(colfix<T>(up, st, cf));
+      RSRS_TRY(symmetrize<T>(up, st, symx));
       RSRS_TRY(copy2d<T, T>(up, st, cx));
       RSRS_TRY(copy2d<T, double>(up, st, cxd));
       RSRS_TRY(gje_inverse(up, st, gj, flag));
+      RSRS_TRY(symmetrize<double>(up, st, symi));
       RSRS_TRY(copy2d<double, T>(up, st, cinv));
     }
     {
       std::vector<GemmDescT<T, T>> gku, gkl;
+      std::vector<Copy2DT<T, T>> ktr;
       for (auto& it : items) {
         const BoxRec& R = *it.R;
         const BoxWs<T>& w = it.w;
         T* dS = it.J->dS;
         const int r = (int)R.r, kn = (int)(it.J->k + R.n);
         gku.push_back(gdescT<T, T>(dS + R.oXinv, nullptr, R.ldR, w.Xpy + r, nullptr, w.lp, dS + R.oKU, nullptr, R.ldKU, r, kn, r));
-        gkl.push_back(gdescT<T, T>(w.Xpz + r, nullptr, w.lp, dS + R.oXinv, nullptr, R.ldR, dS + R.oKL, nullptr, R.ldR, kn, r, r));
+        if (it.J->sym)   // K_L = K_U^T
+          ktr.push_back(Copy2DT<T, T>{dS + R.oKU, dS + R.oKL, R.ldKU, R.ldR, kn, r, 1.0, 0, 1});
+        else
+          gkl.push_back(gdescT<T, T>(w.Xpz + r, nullptr, w.lp, dS + R.oXinv, nullptr, R.ldR, dS + R.oKL, nullptr, R.ldR, kn, r, r));
       }
       RSRS_TRY(gemm<T, T>(up, st, gku, 0, 0, GM_FULL, GS_64x64, "mult"));
       RSRS_TRY(gemm<T, T>(up, st, gkl, 1, 0, GM_FULL, GS_64x64, "mult"));
+      RSRS_TRY(copy2d<T, T>(up, st, ktr));
     }
     // ---- sketch updates: sparsify (E, F) then eliminate (L, U)
     {
@@ -663,11 +686,12 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
         const T* KL = J.dS + R.oKL;
         const int64_t lT = R.ldT, lR = R.ldR, lU = R.ldKU;
         s0.push_back(gdescT<T, T>(Tm, nullptr, lT, J.Y, gS, sld, J.Y, gR, sld, r, s, k, -1.0, 1.0));
-        s0.push_back(gdescT<T, T>(Tm, nullptr, lT, J.Z, gS, sld, J.Z, gR, sld, r, s, k, -1.0, 1.0));
         s1.push_back(gdescT<T, T>(Tm, nullptr, lT, J.Om, gR, sld, J.Om, gS, sld, k, s, r, 1.0, 1.0));
-        s1.push_back(gdescT<T, T>(Tm, nullptr, lT, J.Psi, gR, sld, J.Psi, gS, sld, k, s, r, 1.0, 1.0));
         e0.push_back(gdescT<T, T>(KL, nullptr, lR, J.Y, gR, sld, J.Y, gSN, sld, kn, s, r, -1.0, 1.0));
         e0b.push_back(gdescT<T, T>(KU, nullptr, lU, J.Om, gSN, sld, J.Om, gR, sld, r, s, kn, 1.0, 1.0));
+        if (J.sym) continue;   // Z = Y and Psi = Omega: nothing more to update
+        s0.push_back(gdescT<T, T>(Tm, nullptr, lT, J.Z, gS, sld, J.Z, gR, sld, r, s, k, -1.0, 1.0));
+        s1.push_back(gdescT<T, T>(Tm, nullptr, lT, J.Psi, gR, sld, J.Psi, gS, sld, k, s, r, 1.0, 1.0));
         e1.push_back(gdescT<T, T>(KU, nullptr, lU, J.Z, gR, sld, J.Z, gSN, sld, kn, s, r, -1.0, 1.0));
         e1b.push_back(gdescT<T, T>(KL, nullptr, lR, J.Psi, gSN, sld, J.Psi, gR, sld, r, s, kn, 1.0, 1.0));
       }
@@ -784,8 +808,18 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
       RSRS_TRY(gemm(up, st, h3, 0, 0, GM_B_NN_LOW));
     }
     std::vector<GjeDesc> gj;
-    for (auto& R : roots) gj.push_back(GjeDesc{R.At, R.gw, R.Atinv, R.nt, R.nt, R.nt, 0});
+    std::vector<SymDesc<double>> sa, sai;
+    for (size_t q = 0; q < roots.size(); ++q) {
+      const Root& R = roots[q];
+      gj.push_back(GjeDesc{R.At, R.gw, R.Atinv, R.nt, R.nt, R.nt, 0});
+      if (jobs[q].sym) {
+        sa.push_back(SymDesc<double>{R.At, R.nt, R.nt, 0});
+        sai.push_back(SymDesc<double>{R.Atinv, R.nt, R.nt, 0});
+      }
+    }
+    RSRS_TRY(symmetrize<double>(up, st, sa));
     RSRS_TRY(gje_inverse(up, st, gj, flag));
+    RSRS_TRY(symmetrize<double>(up, st, sai));
     if constexpr (mixed) {
       std::vector<Copy2DT<double, T>> cp;
       for (size_t j = 0; j < jobs.size(); ++j) {
@@ -848,6 +882,10 @@ rsrs_status factor_batch_impl(int64_t nprob, const rsrs_tree_t* const* trees, rs
     if (o->precision != prec) { set_error(who + "all problems of a batch need the same precision"); return RSRS_E_INVALID; }
     for (int64_t j = 0; j < i; ++j)
       if (smps[j] == smp) { set_error(who + "the same samples appear twice"); return RSRS_E_INVALID; }
+    if (smp->symmetric && !o->symmetric) {
+      set_error(who + "symmetric samples need the symmetric variant (opts.symmetric = 1)");
+      return RSRS_E_INVALID;
+    }
     if (prec == RSRS_PREC_F64 && smp->dtype != RSRS_F64) {
       set_error(who + "FP64 factorization needs FP64 samples");
       return RSRS_E_INVALID;

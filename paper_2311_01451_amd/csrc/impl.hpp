@@ -18,6 +18,7 @@ struct rsrs_samples_s {
   const rsrs_tree_t* tree = nullptr;
   int64_t n = 0, s = 0, ld = 0;
   int dtype = RSRS_F64;         // element type of Y, Z, Om, Psi
+  bool symmetric = false;       // only Y and Om (Z = Y, Psi = Om implicitly)
   rsrs::DevBuf Y, Z, Om, Psi;   // tree order, row-major n x s (leading dimension ld)
   bool consumed = false;
 };

@@ -85,15 +85,22 @@ struct GjeDesc { const double* A; double* W; double* Ainv; int64_t lda, ldi; int
 rsrs_status gje_inverse(Uploader& up, hipStream_t st, const std::vector<GjeDesc>& e, int* flag);
 
 template <typename TS, typename TD>
-struct Copy2DT { const TS* src; TD* dst; int64_t lds, ldd; int rows, cols; double alpha; int accumulate, pad_; };
+struct Copy2DT { const TS* src; TD* dst; int64_t lds, ldd; int rows, cols; double alpha; int accumulate, trans; };
 using Copy2D = Copy2DT<double, double>;
 // dst = alpha*src (accumulate = 0) or dst += alpha*src, converting the element
-// type.  Instantiated for every pair of double / float.
+// type; with trans, src is read transposed (dst is rows x cols, src cols x rows).
+// Instantiated for every pair of double / float.
 template <typename TS, typename TD>
 rsrs_status copy2d(Uploader& up, hipStream_t st, const std::vector<Copy2DT<TS, TD>>& e);
 inline rsrs_status copy2d(Uploader& up, hipStream_t st, const std::vector<Copy2D>& e) {
   return copy2d<double, double>(up, st, e);
 }
+
+// In-place symmetric part A = (A + A^T) / 2 of n x n blocks (double / float).
+template <typename T>
+struct SymDesc { T* A; int64_t ld; int n, pad_; };
+template <typename T>
+rsrs_status symmetrize(Uploader& up, hipStream_t st, const std::vector<SymDesc<T>>& e);
 
 // Row permutations: dst[i] = src[idx[i]] (gather) / dst[idx[i]] = src[i]
 // (scatter), converting the element type (double / float pairs).

@@ -285,7 +285,7 @@ struct rsrs_server_s {
     std::vector<size_t> idx;
     for (size_t i = 0; i < m; ++i) {
       const Fact& r = group[i];
-      sts[i] = rsrs_sample(r.t, r.mv, r.user, r.s, r.seed, r.dtype, s_factor, &smp[i]);
+      sts[i] = (r.o.symmetric ? rsrs_sample_symmetric : rsrs_sample)(r.t, r.mv, r.user, r.s, r.seed, r.dtype, s_factor, &smp[i]);
       if (sts[i] != RSRS_OK) {
         msgs[i] = rsrs_last_error();
         continue;
@@ -309,7 +309,7 @@ struct rsrs_server_s {
           const Fact& r = group[j];
           rsrs_samples_destroy(smp[j]);
           smp[j] = nullptr;
-          sts[j] = rsrs_sample(r.t, r.mv, r.user, r.s, r.seed, r.dtype, s_factor, &smp[j]);
+          sts[j] = (r.o.symmetric ? rsrs_sample_symmetric : rsrs_sample)(r.t, r.mv, r.user, r.s, r.seed, r.dtype, s_factor, &smp[j]);
           if (sts[j] == RSRS_OK) sts[j] = factor_impl(r.t, smp[j], &r.o, s_factor, &Fs[j]);
           if (sts[j] != RSRS_OK) msgs[j] = rsrs_last_error();
         }

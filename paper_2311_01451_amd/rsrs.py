@@ -57,7 +57,8 @@ class TreeInfo(C.Structure):
 
 
 class FactorOpts(C.Structure):
-    _fields_ = [("k", C.c_int), ("p", C.c_int), ("precision", C.c_int), ("reproject", C.c_int)]
+    _fields_ = [("k", C.c_int), ("p", C.c_int), ("precision", C.c_int), ("reproject", C.c_int),
+                ("symmetric", C.c_int)]
 
 
 class FactorInfo(C.Structure):
@@ -92,7 +93,7 @@ EXPORTS = [
     "rsrs_tree_destroy", "rsrs_tree_get_info", "rsrs_tree_neighbours", "rsrs_tree_schedule",
     "rsrs_samples_required", "rsrs_op_create_kernel", "rsrs_op_create_dense",
     "rsrs_op_create_poisson7", "rsrs_op_matvec", "rsrs_op_destroy", "rsrs_samples_wrap",
-    "rsrs_sample", "rsrs_samples_destroy", "rsrs_gaussian", "rsrs_factor", "rsrs_factor_batched",
+    "rsrs_sample", "rsrs_sample_symmetric", "rsrs_samples_wrap_symmetric", "rsrs_samples_destroy", "rsrs_gaussian", "rsrs_factor", "rsrs_factor_batched",
     "rsrs_factor_destroy",
     "rsrs_factor_get_info", "rsrs_factor_box_sizes", "rsrs_factor_box_copy",
     "rsrs_factor_root_copy", "rsrs_solve", "rsrs_apply", "rsrs_solve_refine",
@@ -131,6 +132,8 @@ def lib():
         "rsrs_op_destroy": (None, [vp]),
         "rsrs_samples_wrap": (i32, [vp, i32, vp, vp, vp, vp, i64, i64, vp, P(vp)]),
         "rsrs_sample": (i32, [vp, vp, vp, i64, C.c_uint64, i32, vp, P(vp)]),
+        "rsrs_sample_symmetric": (i32, [vp, vp, vp, i64, C.c_uint64, i32, vp, P(vp)]),
+        "rsrs_samples_wrap_symmetric": (i32, [vp, i32, vp, vp, i64, i64, vp, P(vp)]),
         "rsrs_samples_destroy": (None, [vp]),
         "rsrs_gaussian": (i32, [vp, i64, i64, i64, C.c_uint64, C.c_uint32, vp]),
         "rsrs_factor": (i32, [vp, vp, P(FactorOpts), vp, P(vp)]),
@@ -360,7 +363,17 @@ class Samples:
 
 
 def rsrs_samples_wrap(tree: Tree, Y, Z, Om, Psi, stream=None) -> Samples:
-    """Sketches as FP64 or FP32 device tensors (all four of one dtype)."""
+    """Sketches as FP64 or FP32 device tensors (all four of one dtype); with
+    Z and Psi None, symmetric samples (rsrs_samples_wrap_symmetric)."""
+    if Z is None and Psi is None:
+        py_, ld = _dev(Y, "Y", ("float64", "float32"))
+        po, ldo = _dev(Om, "Omega", ("float64", "float32"))
+        if ldo != ld or Om.shape != Y.shape or Om.dtype != Y.dtype:
+            raise TypeError("sketches must share shape, dtype and leading dimension")
+        h = C.c_void_p()
+        _check(lib().rsrs_samples_wrap_symmetric(tree.handle, _dtype_code(Y), py_, po, ld, Y.shape[1],
+                                                 _stream(stream), C.byref(h)))
+        return Samples(h, Y.shape[1])
     ptrs = []
     ld = None
     for name, t in (("Y", Y), ("Z", Z), ("Omega", Om), ("Psi", Psi)):
@@ -377,10 +390,10 @@ def rsrs_samples_wrap(tree: Tree, Y, Z, Om, Psi, stream=None) -> Samples:
 
 
 def rsrs_sample(tree: Tree, op: Operator, s: int, seed: int, dtype: int = RSRS_F64,
-                stream=None) -> Samples:
+                stream=None, symmetric: bool = False) -> Samples:
     h = C.c_void_p()
-    _check(lib().rsrs_sample(tree.handle, Operator.fn_ptr(), op.handle, s, seed, dtype,
-                             _stream(stream), C.byref(h)))
+    fn = lib().rsrs_sample_symmetric if symmetric else lib().rsrs_sample
+    _check(fn(tree.handle, Operator.fn_ptr(), op.handle, s, seed, dtype, _stream(stream), C.byref(h)))
     return Samples(h, s)
 
 
@@ -451,22 +464,22 @@ class Factor:
 
 
 def rsrs_factor(tree: Tree, samples: Samples, k: int, p: int = -1, reproject: int = 1,
-                precision: int = RSRS_PREC_F64, stream=None) -> Factor:
-    o = FactorOpts(k, p, precision, reproject)
+                precision: int = RSRS_PREC_F64, stream=None, symmetric: bool = False) -> Factor:
+    o = FactorOpts(k, p, precision, reproject, int(symmetric))
     h = C.c_void_p()
     _check(lib().rsrs_factor(tree.handle, samples.handle, C.byref(o), _stream(stream), C.byref(h)))
     return Factor(h, keep=tree)
 
 
 def rsrs_factor_batched(trees, samples, ks, p: int = -1, reproject: int = 1,
-                        precision: int = RSRS_PREC_F64, stream=None) -> list:
+                        precision: int = RSRS_PREC_F64, stream=None, symmetric: bool = False) -> list:
     """Factor independent problems together; ks gives each problem's rank."""
     n = len(trees)
     if len(samples) != n or len(ks) != n:
         raise ValueError("trees, samples and ks must have the same length")
     th = (C.c_void_p * n)(*[t.handle for t in trees])
     sh = (C.c_void_p * n)(*[x.handle for x in samples])
-    opts = (FactorOpts * n)(*[FactorOpts(int(k), p, precision, reproject) for k in ks])
+    opts = (FactorOpts * n)(*[FactorOpts(int(k), p, precision, reproject, int(symmetric)) for k in ks])
     outs = (C.c_void_p * n)()
     _check(lib().rsrs_factor_batched(n, th, sh, opts, _stream(stream), outs))
     return [Factor(C.c_void_p(outs[i]), keep=trees[i]) for i in range(n)]
@@ -555,10 +568,10 @@ class Server:
 
     def submit_factor(self, tree: Tree, op: Operator, s: int, seed: int, k: int,
                       precision: int = RSRS_PREC_F64, p: int = -1, reproject: int = 1,
-                      dtype: int | None = None) -> int:
+                      dtype: int | None = None, symmetric: bool = False) -> int:
         if dtype is None:
             dtype = RSRS_F64 if precision == RSRS_PREC_F64 else RSRS_F32
-        o = FactorOpts(int(k), p, precision, reproject)
+        o = FactorOpts(int(k), p, precision, reproject, int(symmetric))
         t = C.c_int64()
         _check(lib().rsrs_server_submit_factor(self._h, tree.handle, Operator.fn_ptr(), op.handle,
                                                int(s), int(seed), dtype, C.byref(o), C.byref(t)))
