@@ -100,9 +100,11 @@ static bool vec_ok(const std::vector<GemmDescT<TI, TO>>& descs) {
   return true;
 }
 
+// Launch records of one batched product: the kernel instantiation, its grid
+// and the range of descriptors it reads (grid.y <= 65535 per record).
 template <typename TI, typename TO, int BM, int BN, int WM, int WN, int TA, int TB, int MODE>
-static rsrs_status launch_gemm(Uploader& up, hipStream_t st,
-                               const std::vector<GemmDescT<TI, TO>>& descs) {
+static void plan_shape(const std::vector<GemmDescT<TI, TO>>& descs, size_t base,
+                       std::vector<GemmLaunch>& out) {
   constexpr int VW = 16 / (int)sizeof(TI);
   constexpr int NT = 64 * WM * WN;
   constexpr bool can_vec = BN * 16 / NT >= VW && BM * 16 / NT >= VW;
@@ -112,39 +114,37 @@ static rsrs_status launch_gemm(Uploader& up, hipStream_t st,
       const int64_t tm = (d.M + BM - 1) / BM, tn = (d.N + BN - 1) / BN;
       tiles = std::max<int64_t>(tiles, MODE == GM_SYRK_L ? tm * (tm + 1) / 2 : tm * tn);
     }
-  if (tiles == 0) return RSRS_OK;
+  if (tiles == 0) return;
   double pf = 0.0, pb = 0.0;
   if (prof_on()) gemm_work(descs, MODE, &pf, &pb);
-  const bool vec = can_vec && vec_ok(descs);
-  for (size_t b0 = 0; b0 < descs.size(); b0 += 65535) {
-    const size_t nb = std::min<size_t>(65535, descs.size() - b0);
-    std::vector<GemmDescT<TI, TO>> part(descs.begin() + b0, descs.begin() + b0 + nb);
-    GemmDescT<TI, TO>* dd = nullptr;
-    RSRS_TRY(up.put_vec(part, &dd));
-    dim3 grid((unsigned)round_up(tiles, 8), (unsigned)nb);
-    ProfScope ps(st, gemm_tag(sizeof(TI) == 4, TA, TB, MODE, BM, BN), b0 == 0 ? pf : 0.0,
-                 b0 == 0 ? pb : 0.0);
-    if constexpr (can_vec) {
-      if (vec) {
-        hipLaunchKernelGGL((gemm_kernel<TI, TO, BM, BN, WM, WN, TA, TB, MODE, VW>), grid, dim3(NT), 0, st, dd);
-      } else {
-        hipLaunchKernelGGL((gemm_kernel<TI, TO, BM, BN, WM, WN, TA, TB, MODE, 1>), grid, dim3(NT), 0, st, dd);
-      }
-    } else {
-      hipLaunchKernelGGL((gemm_kernel<TI, TO, BM, BN, WM, WN, TA, TB, MODE, 1>), grid, dim3(NT), 0, st, dd);
-    }
-    RSRS_HIP(hipGetLastError());
+  const void* fn;
+  if constexpr (can_vec) {
+    fn = vec_ok(descs) ? reinterpret_cast<const void*>(&gemm_kernel<TI, TO, BM, BN, WM, WN, TA, TB, MODE, VW>)
+                       : reinterpret_cast<const void*>(&gemm_kernel<TI, TO, BM, BN, WM, WN, TA, TB, MODE, 1>);
+  } else {
+    fn = reinterpret_cast<const void*>(&gemm_kernel<TI, TO, BM, BN, WM, WN, TA, TB, MODE, 1>);
   }
-  return RSRS_OK;
+  for (size_t b0 = 0; b0 < descs.size(); b0 += 65535) {
+    GemmLaunch L{};
+    L.fn = fn;
+    L.grid = dim3((unsigned)round_up(tiles, 8), (unsigned)std::min<size_t>(65535, descs.size() - b0));
+    L.block = dim3(NT);
+    L.first = base + b0;
+    L.flops = b0 == 0 ? pf : 0.0;
+    L.bytes = b0 == 0 ? pb : 0.0;
+    std::snprintf(L.tag, sizeof(L.tag), "%s", gemm_tag(sizeof(TI) == 4, TA, TB, MODE, BM, BN));
+    out.push_back(L);
+  }
 }
 
 template <typename TI, typename TO, int BM, int BN, int WM, int WN>
-static rsrs_status gemm_shape(Uploader& up, hipStream_t st,
-                              const std::vector<GemmDescT<TI, TO>>& descs, int ta, int tb,
-                              int mode) {
+static rsrs_status plan_forms(const std::vector<GemmDescT<TI, TO>>& descs, size_t base, int ta, int tb,
+                              int mode, std::vector<GemmLaunch>& out) {
 #define RSRS_G(TA, TB, MODE)                                                       \
-  if (ta == TA && tb == TB && mode == MODE)                                        \
-    return launch_gemm<TI, TO, BM, BN, WM, WN, TA, TB, MODE>(up, st, descs);
+  if (ta == TA && tb == TB && mode == MODE) {                                      \
+    plan_shape<TI, TO, BM, BN, WM, WN, TA, TB, MODE>(descs, base, out);           \
+    return RSRS_OK;                                                                \
+  }
   if constexpr (std::is_same<TI, TO>::value) {
     RSRS_G(0, 0, GM_FULL)
     RSRS_G(0, 1, GM_FULL)
@@ -167,15 +167,15 @@ static rsrs_status gemm_shape(Uploader& up, hipStream_t st,
 // 64 x 16.  Mixed-type launches (FP32 operands, FP64 result) exist for the
 // Gram matrices only.
 template <typename TI, typename TO>
-rsrs_status gemm(Uploader& up, hipStream_t st, const std::vector<GemmDescT<TI, TO>>& descs, int ta,
-                 int tb, int mode, GemmShape shape, const char* site) {
+rsrs_status gemm_plan(const std::vector<GemmDescT<TI, TO>>& descs, size_t base, int ta, int tb, int mode,
+                      GemmShape shape, const char* site, std::vector<GemmLaunch>& out) {
   if (descs.empty()) return RSRS_OK;
   struct SiteGuard {
     explicit SiteGuard(const char* s) { g_site = s; }
     ~SiteGuard() { g_site = nullptr; }
   } guard(site);
   if constexpr (std::is_same<TI, TO>::value) {
-    if (shape == GS_64x16 && mode == GM_FULL) return gemm_shape<TI, TO, 64, 16, 4, 1>(up, st, descs, ta, tb, mode);
+    if (shape == GS_64x16 && mode == GM_FULL) return plan_forms<TI, TO, 64, 16, 4, 1>(descs, base, ta, tb, mode, out);
   }
   int64_t t128 = 0;
   for (const auto& d : descs) {
@@ -183,10 +183,35 @@ rsrs_status gemm(Uploader& up, hipStream_t st, const std::vector<GemmDescT<TI, T
     const int64_t tm = (d.M + 127) / 128, tn = (d.N + 127) / 128;
     t128 += mode == GM_SYRK_L ? tm * (tm + 1) / 2 : tm * tn;
   }
-  if (t128 >= 256) return gemm_shape<TI, TO, 128, 128, 2, 4>(up, st, descs, ta, tb, mode);
-  return gemm_shape<TI, TO, 64, 64, 2, 2>(up, st, descs, ta, tb, mode);
+  if (t128 >= 256) return plan_forms<TI, TO, 128, 128, 2, 4>(descs, base, ta, tb, mode, out);
+  return plan_forms<TI, TO, 64, 64, 2, 2>(descs, base, ta, tb, mode, out);
 }
 
+rsrs_status gemm_exec(const GemmLaunch& L, const void* descs, size_t desc_bytes, hipStream_t st) {
+  const void* p = static_cast<const char*>(descs) + L.first * desc_bytes;
+  void* args[] = {&p};
+  ProfScope ps(st, L.tag, L.flops, L.bytes);
+  RSRS_HIP(hipLaunchKernel(L.fn, L.grid, L.block, args, 0, st));
+  return RSRS_OK;
+}
+
+template <typename TI, typename TO>
+rsrs_status gemm(Uploader& up, hipStream_t st, const std::vector<GemmDescT<TI, TO>>& descs, int ta, int tb,
+                 int mode, GemmShape shape, const char* site) {
+  if (descs.empty()) return RSRS_OK;
+  std::vector<GemmLaunch> L;
+  RSRS_TRY(gemm_plan<TI, TO>(descs, 0, ta, tb, mode, shape, site, L));
+  if (L.empty()) return RSRS_OK;
+  GemmDescT<TI, TO>* dd = nullptr;
+  RSRS_TRY(up.put_vec(descs, &dd));
+  for (const auto& x : L) RSRS_TRY(gemm_exec(x, dd, sizeof(GemmDescT<TI, TO>), st));
+  return RSRS_OK;
+}
+
+template rsrs_status gemm_plan<double, double>(const std::vector<GemmDescT<double, double>>&, size_t, int, int,
+                                               int, GemmShape, const char*, std::vector<GemmLaunch>&);
+template rsrs_status gemm_plan<float, float>(const std::vector<GemmDescT<float, float>>&, size_t, int, int, int,
+                                             GemmShape, const char*, std::vector<GemmLaunch>&);
 template rsrs_status gemm<double, double>(Uploader&, hipStream_t, const std::vector<GemmDescT<double, double>>&,
                                           int, int, int, GemmShape, const char*);
 template rsrs_status gemm<float, float>(Uploader&, hipStream_t, const std::vector<GemmDescT<float, float>>&,

@@ -60,6 +60,23 @@ rsrs_status kernel_materialise(hipStream_t st, const KernelOp& op, T* A);
 
 }  // namespace rsrs
 
+namespace rsrs {
+// A solve or apply of one factor for a fixed width, captured as a HIP graph:
+// its own tree-ordered work blocks x, u (n x w, zero-initialised so padded
+// columns stay zero), the descriptors of every launch, and the graph.
+struct SolvePlan {
+  int op = 0, transpose = 0;
+  int64_t w = 0;
+  DevBuf x, u, descs;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~SolvePlan() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+};
+}  // namespace rsrs
+
 struct rsrs_factor_s {
   int64_t n = 0, s = 0, k = 0;
   int precision = RSRS_PREC_F64;
@@ -74,6 +91,12 @@ struct rsrs_factor_s {
   mutable rsrs::DevBuf wx, wu, wt, wpart, wnorm;
   mutable rsrs::Uploader up;
   mutable bool up_ready = false;
+  mutable std::vector<std::unique_ptr<rsrs::SolvePlan>> plans;   // captured solves
+  mutable hipStream_t capture_stream = nullptr;
+  ~rsrs_factor_s() {
+    plans.clear();
+    if (capture_stream) (void)hipStreamDestroy(capture_stream);
+  }
   template <typename T> const T* d() const { return dstore.as<T>(); }
   const int64_t* i() const { return istore.as<int64_t>(); }
 };

@@ -33,6 +33,22 @@ struct Uploader {
 // ---- GEMM (gemm.hpp) -------------------------------------------------------
 enum GemmShape { GS_64x64 = 0, GS_64x16 = 1 };
 // `site` (optional) is appended to the measurement tag ("gemm_<form>:<site>").
+// A batched product split into launch records: kernel, grid, and the first
+// descriptor (index into the caller's concatenated descriptor array) it reads.
+struct GemmLaunch {
+  const void* fn;
+  dim3 grid, block;
+  size_t first;
+  double flops, bytes;   // algorithmic work (for the measurement tags)
+  char tag[48];
+};
+// Plans descs (whose first element sits at index `base` of the caller's array);
+// instantiated for <double, double> and <float, float>.
+template <typename TI, typename TO>
+rsrs_status gemm_plan(const std::vector<GemmDescT<TI, TO>>& descs, size_t base, int ta, int tb, int mode,
+                      GemmShape shape, const char* site, std::vector<GemmLaunch>& out);
+// Launches one record; descs is the device copy of the caller's array.
+rsrs_status gemm_exec(const GemmLaunch& L, const void* descs, size_t desc_bytes, hipStream_t st);
 // Instantiated for <double, double>, <float, float> (all forms) and
 // <float, double> (SYRK_L only).
 template <typename TI, typename TO>

@@ -39,10 +39,14 @@ hipEvent_t get_event() {
 
 }  // namespace
 
-bool prof_on() { return g_on; }
+thread_local bool g_suspended = false;
+
+bool prof_on() { return g_on && !g_suspended; }
+
+void prof_suspend(bool s) { g_suspended = s; }
 
 int prof_begin(hipStream_t st) {
-  if (!g_on) return -1;
+  if (!g_on || g_suspended) return -1;
   std::lock_guard<std::mutex> lk(g_mu);
   Rec r{get_event(), get_event(), std::string(), 0.0, 0.0, false};
   if (!r.a || !r.b) return -1;

@@ -7,6 +7,9 @@
 namespace rsrs {
 
 bool prof_on();
+// Suspends accounting on the calling thread (launches recorded into a graph
+// are accounted as one replay instead).
+void prof_suspend(bool s);
 // Returns an opaque slot (or -1 when profiling is off); call prof_end after the launch.
 int prof_begin(hipStream_t st);
 void prof_end(int slot, hipStream_t st, const char* tag, double flops, double bytes);

@@ -8,11 +8,24 @@
 // launch over the class.  A mixed-precision factor is applied in FP32: the
 // FP64 input is rounded while it is permuted into tree order and the result
 // widened on the way out.
+//
+// Launch latency, not bandwidth, bounds a narrow solve (a few hundred small
+// launches per sweep), so by default the launch sequence of a factor is
+// captured once per (operation, transpose, width bucket) into a HIP graph
+// with pre-uploaded descriptors and its own work blocks, and replayed; the
+// width is padded to the bucket (16, 32, 64, ... 1024) with zero columns,
+// which do not touch the others.  Only the gather into tree order and the
+// scatter back run outside the graph.  Wider solves run the launches
+// directly.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 
 #include "impl.hpp"
+#include "profile.hpp"
+
+#include <memory>
+#include <string>
 
 namespace rsrs {
 
@@ -35,31 +48,19 @@ rsrs_status ensure_ws(const rsrs_factor_t* F, int64_t w, hipStream_t st) {
   return RSRS_OK;
 }
 
-template <typename T>
-rsrs_status apply_t(const rsrs_factor_t* F, int op, int transpose, int64_t w, const double* Fin,
-                    int64_t ldf, double* Uout, int64_t ldu, hipStream_t st) {
+// Every product of one apply, in order, handed to emit(descs, ta, tb, mode).
+template <typename T, class Emit>
+rsrs_status build_apply(const rsrs_factor_t* F, int op, int transpose, int64_t w, T* x, T* u, Emit&& emit) {
   using GD = GemmDescT<T, T>;
   auto gdesc = [](const T* A, const int64_t* ia, int64_t lda, const T* B, const int64_t* ib,
                   int64_t ldb, T* C, const int64_t* ic, int64_t ldc, int M, int N, int K,
                   double alpha = 1.0, double beta = 0.0) {
     return gdescT<T, T>(A, ia, lda, B, ib, ldb, C, ic, ldc, M, N, K, alpha, beta);
   };
-  auto gemm = [](Uploader& up, hipStream_t st, const std::vector<GD>& d, int ta, int tb, int mode,
-                 GemmShape shp, const char* site) {
-    return rsrs::gemm<T, T>(up, st, d, ta, tb, mode, shp, site);
-  };
-  RSRS_TRY(ensure_ws(F, w, st));
-  Uploader& up = F->up;
-  const GemmShape shp = w <= 16 ? GS_64x16 : GS_64x64;
-  T* x = F->wx.as<T>();
-  T* u = F->wu.as<T>();
   const T* dS = F->d<T>();
   const int64_t* iS = F->i();
-  const int64_t* perm = F->perm.as<int64_t>();
   const int W = (int)w;
   const int k = (int)F->k;
-  gather_rows<double, T>(st, x, w, Fin, ldf, perm, F->n, w);
-
   // first and second elementary step of the upward sweep (boxes in factor order)
   for (const Group& g : F->groups) {
     std::vector<GD> a0, a1;   // launches with TA = 0 / TA = 1
@@ -88,10 +89,10 @@ rsrs_status apply_t(const rsrs_factor_t* F, int op, int transpose, int64_t w, co
         b1.push_back(gdesc(KL, nullptr, lR, x, gSN, w, x, gR, w, r, W, kn, 1.0, 1.0));
       }
     }
-    RSRS_TRY(gemm(up, st, a0, 0, 0, GM_FULL, shp, "solve"));
-    RSRS_TRY(gemm(up, st, a1, 1, 0, GM_FULL, shp, "solve"));
-    RSRS_TRY(gemm(up, st, b0, 0, 0, GM_FULL, shp, "solve"));
-    RSRS_TRY(gemm(up, st, b1, 1, 0, GM_FULL, shp, "solve"));
+    RSRS_TRY(emit(a0, 0, 0, GM_FULL));
+    RSRS_TRY(emit(a1, 1, 0, GM_FULL));
+    RSRS_TRY(emit(b0, 0, 0, GM_FULL));
+    RSRS_TRY(emit(b1, 1, 0, GM_FULL));
   }
   // block-diagonal middle factor D (or D^{-1}), every R block and the root
   {
@@ -107,7 +108,7 @@ rsrs_status apply_t(const rsrs_factor_t* F, int op, int transpose, int64_t w, co
     const int64_t* gB = iS + F->oBt;
     dd.push_back(gdesc(dS + (op == OP_SOLVE ? F->oAtinv : F->oAt), nullptr, nt, x, gB, w, u, gB, w,
                        nt, W, nt));
-    RSRS_TRY(gemm(up, st, dd, ta, 0, GM_FULL, shp, "solve"));
+    RSRS_TRY(emit(dd, ta, 0, GM_FULL));
   }
   // downward sweep, boxes in reverse factor order
   for (size_t gi = F->groups.size(); gi-- > 0;) {
@@ -137,12 +138,104 @@ rsrs_status apply_t(const rsrs_factor_t* F, int op, int transpose, int64_t w, co
         b0.push_back(gdesc(Tm, nullptr, lT, u, gS, w, u, gR, w, r, W, k, 1.0, 1.0));
       }
     }
-    RSRS_TRY(gemm(up, st, a0, 0, 0, GM_FULL, shp, "solve"));
-    RSRS_TRY(gemm(up, st, a1, 1, 0, GM_FULL, shp, "solve"));
-    RSRS_TRY(gemm(up, st, b0, 0, 0, GM_FULL, shp, "solve"));
-    RSRS_TRY(gemm(up, st, b1, 1, 0, GM_FULL, shp, "solve"));
+    RSRS_TRY(emit(a0, 0, 0, GM_FULL));
+    RSRS_TRY(emit(a1, 1, 0, GM_FULL));
+    RSRS_TRY(emit(b0, 0, 0, GM_FULL));
+    RSRS_TRY(emit(b1, 1, 0, GM_FULL));
   }
+  return RSRS_OK;
+}
+
+template <typename T>
+rsrs_status apply_direct(const rsrs_factor_t* F, int op, int transpose, int64_t w, const double* Fin,
+                         int64_t ldf, double* Uout, int64_t ldu, hipStream_t st) {
+  RSRS_TRY(ensure_ws(F, w, st));
+  Uploader& up = F->up;
+  const GemmShape shp = w <= 16 ? GS_64x16 : GS_64x64;
+  T* x = F->wx.as<T>();
+  T* u = F->wu.as<T>();
+  const int64_t* perm = F->perm.as<int64_t>();
+  gather_rows<double, T>(st, x, w, Fin, ldf, perm, F->n, w);
+  RSRS_TRY(build_apply<T>(F, op, transpose, w, x, u,
+                          [&](const std::vector<GemmDescT<T, T>>& d, int ta, int tb, int mode) {
+                            return gemm<T, T>(up, st, d, ta, tb, mode, shp, "solve");
+                          }));
   scatter_rows<T, double>(st, Uout, ldu, u, w, perm, F->n, w);
+  RSRS_HIP(hipGetLastError());
+  return RSRS_OK;
+}
+
+bool g_graphs = true;
+constexpr int64_t kMaxGraphWidth = 1024;
+
+int64_t width_bucket(int64_t w) {
+  int64_t b = 16;
+  while (b < w) b *= 2;
+  return b;
+}
+
+template <typename T>
+rsrs_status make_plan(const rsrs_factor_t* F, int op, int transpose, int64_t wb, SolvePlan** out) {
+  auto P = std::make_unique<SolvePlan>();
+  P->op = op;
+  P->transpose = transpose;
+  P->w = wb;
+  const size_t bytes = (size_t)F->n * wb * sizeof(T);
+  RSRS_TRY(P->x.alloc(bytes));
+  RSRS_TRY(P->u.alloc(bytes));
+  RSRS_HIP(hipMemset(P->x.p, 0, bytes));
+  RSRS_HIP(hipMemset(P->u.p, 0, bytes));
+  const GemmShape shp = wb <= 16 ? GS_64x16 : GS_64x64;
+  std::vector<GemmDescT<T, T>> all;
+  std::vector<GemmLaunch> L;
+  RSRS_TRY(build_apply<T>(F, op, transpose, wb, P->x.as<T>(), P->u.as<T>(),
+                          [&](const std::vector<GemmDescT<T, T>>& d, int ta, int tb, int mode) {
+                            const size_t base = all.size();
+                            all.insert(all.end(), d.begin(), d.end());
+                            return gemm_plan<T, T>(d, base, ta, tb, mode, shp, "solve", L);
+                          }));
+  RSRS_TRY(P->descs.alloc(std::max<size_t>(all.size(), 1) * sizeof(GemmDescT<T, T>)));
+  if (!all.empty())
+    RSRS_HIP(hipMemcpy(P->descs.p, all.data(), all.size() * sizeof(GemmDescT<T, T>), hipMemcpyHostToDevice));
+  if (!F->capture_stream) RSRS_HIP(hipStreamCreateWithFlags(&F->capture_stream, hipStreamNonBlocking));
+  hipStream_t cs = F->capture_stream;
+  RSRS_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  prof_suspend(true);
+  rsrs_status st = RSRS_OK;
+  for (const auto& x : L) {
+    st = gemm_exec(x, P->descs.p, sizeof(GemmDescT<T, T>), cs);
+    if (st != RSRS_OK) break;
+  }
+  prof_suspend(false);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(cs, &g);
+  RSRS_TRY(st);
+  if (e != hipSuccess || !g) {
+    set_error(std::string("graph capture failed: ") + hipGetErrorString(e));
+    return RSRS_E_HIP;
+  }
+  P->graph = g;
+  RSRS_HIP(hipGraphInstantiate(&P->exec, g, nullptr, nullptr, 0));
+  F->plans.push_back(std::move(P));
+  *out = F->plans.back().get();
+  return RSRS_OK;
+}
+
+template <typename T>
+rsrs_status apply_graph(const rsrs_factor_t* F, int op, int transpose, int64_t w, const double* Fin,
+                        int64_t ldf, double* Uout, int64_t ldu, hipStream_t st) {
+  const int64_t wb = width_bucket(w);
+  SolvePlan* P = nullptr;
+  for (auto& q : F->plans)
+    if (q->op == op && q->transpose == transpose && q->w == wb) P = q.get();
+  if (!P) RSRS_TRY(make_plan<T>(F, op, transpose, wb, &P));
+  const int64_t* perm = F->perm.as<int64_t>();
+  gather_rows<double, T>(st, P->x.as<T>(), wb, Fin, ldf, perm, F->n, w);
+  {
+    ProfScope ps(st, "solve_graph");
+    RSRS_HIP(hipGraphLaunch(P->exec, st));
+  }
+  scatter_rows<T, double>(st, Uout, ldu, P->u.as<T>(), wb, perm, F->n, w);
   RSRS_HIP(hipGetLastError());
   return RSRS_OK;
 }
@@ -152,8 +245,18 @@ rsrs_status apply_t(const rsrs_factor_t* F, int op, int transpose, int64_t w, co
 rsrs_status apply_factor(const rsrs_factor_t* F, int op, int transpose, int64_t w, const double* Fin,
                          int64_t ldf, double* Uout, int64_t ldu, hipStream_t st) {
   if (w <= 0) return RSRS_OK;
-  if (F->esz == 4) return apply_t<float>(F, op, transpose, w, Fin, ldf, Uout, ldu, st);
-  return apply_t<double>(F, op, transpose, w, Fin, ldf, Uout, ldu, st);
+  if (g_graphs && w <= kMaxGraphWidth) {
+    if (F->esz == 4) return apply_graph<float>(F, op, transpose, w, Fin, ldf, Uout, ldu, st);
+    return apply_graph<double>(F, op, transpose, w, Fin, ldf, Uout, ldu, st);
+  }
+  if (F->esz == 4) return apply_direct<float>(F, op, transpose, w, Fin, ldf, Uout, ldu, st);
+  return apply_direct<double>(F, op, transpose, w, Fin, ldf, Uout, ldu, st);
 }
+
+}  // namespace rsrs
+
+extern "C" void rsrs_solve_graphs(int on) { rsrs::g_graphs = on != 0; }
+
+namespace rsrs {
 
 }  // namespace rsrs

@@ -97,7 +97,7 @@ EXPORTS = [
     "rsrs_factor_destroy",
     "rsrs_factor_get_info", "rsrs_factor_box_sizes", "rsrs_factor_box_copy",
     "rsrs_factor_root_copy", "rsrs_solve", "rsrs_apply", "rsrs_solve_refine",
-    "rsrs_profile_enable", "rsrs_profile_reset", "rsrs_profile_read",
+    "rsrs_profile_enable", "rsrs_profile_reset", "rsrs_profile_read", "rsrs_solve_graphs",
     "rsrs_server_create", "rsrs_server_destroy", "rsrs_server_add_factor",
     "rsrs_server_release_factor", "rsrs_server_submit_solve", "rsrs_server_submit_factor",
     "rsrs_server_wait", "rsrs_server_get_stats",
@@ -158,6 +158,7 @@ def lib():
         "rsrs_server_wait": (i32, [vp, i64, dbl, P(i64), P(dbl)]),
         "rsrs_server_get_stats": (i32, [vp, i32, P(ServerStats)]),
         "rsrs_profile_enable": (None, [i32]),
+        "rsrs_solve_graphs": (None, [i32]),
         "rsrs_profile_reset": (None, []),
         "rsrs_profile_read": (i32, [P(ProfileEntry), i32]),
     }
@@ -493,6 +494,11 @@ def rsrs_solve(f: Factor, F, transpose=False, out=None, stream=None):
     pu, ldu = _dev(out, "out")
     _check(lib().rsrs_solve(f.handle, int(transpose), F.shape[1], pf, ldf, pu, ldu, _stream(stream)))
     return out
+
+
+def rsrs_solve_graphs(on: bool = True):
+    """Replay captured HIP graphs for solves of up to 1024 columns (default on)."""
+    lib().rsrs_solve_graphs(int(on))
 
 
 def rsrs_apply(f: Factor, X, transpose=False, out=None, stream=None):

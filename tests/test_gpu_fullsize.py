@@ -1,0 +1,133 @@
+"""GPU parity at the full size of the benchmark workload (2D log kernel on
+the 256 x 256 grid, N = 65536, leaf 64, k = p = 64, s = s_required = 2432),
+in the launch configuration the benchmark times.
+
+The oracle cannot factor N = 65536 in a test, but the boxes of the first
+colour class of the first processed level see the initial sketches only (no
+earlier box has touched their rows), so the oracle can process sampled boxes
+of that class one by one from the same Omega (drawn on the device by the
+library's generator) and the same Y = A Omega.  Their skeletons, T, X_RR,
+K_U, K_L are compared with the GPU factor's by the conditioning-aware
+tolerance of the small parity tests.  At k = 64 most boxes' far fields have
+numerical rank below k, so their last pivots are chosen among rounding-level
+residuals and may legitimately differ; for every sampled box the GPU's
+interpolative decomposition is then judged on the oracle's own far-field
+sketch M: ||M_R - T M_S|| with the GPU's S, R, T must be as small as with
+the oracle's (within 10x, or at the rounding level of ||M||).  The whole factorization is then
+checked through properties that hold at any size: the FP64 residual reached
+by refinement (1e-10 for the FP64 path, 1e-6 for the mixed path).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import rsrs as orr  # noqa: E402
+from oracle import tree as ot  # noqa: E402
+from paper_2311_01451_amd import inputs, rsrs  # noqa: E402
+
+N_GRID, LEAF, K = 256, 64, 64
+
+
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _first_class_boxes(to, k, count):
+    sch = ot.schedule(to, k)
+    li = next(i for i, c in enumerate(sch.order) if c)
+    lev = sch.levels[li]
+    cls = sch.order[li][0]
+    step = max(1, len(cls) // count)
+    return sch, lev, cls, cls[::step][:count]
+
+
+@pytest.mark.parametrize("symmetric", [False, True])
+def test_fullsize_first_class_boxes_and_refinement(symmetric):
+    need_gpu()
+    pts = inputs.grid2d(N_GRID)
+    N = N_GRID ** 2
+    h = 1.0 / N_GRID
+    op = rsrs.rsrs_op_create_kernel(rsrs.RSRS_OP_LOG2D, pts, h)
+    tc = rsrs.rsrs_build_tree(pts, LEAF)
+    s = tc.samples_required(K, K)
+    print(f"[fullsize] N={N} k={K} s={s} symmetric={symmetric}", flush=True)
+    # the library's own draws: Omega (word 0), Psi (word 1), then the products
+    seed = inputs.BASE_SEED
+    Om = rsrs.rsrs_gaussian(N, s, seed, 0)
+    Y = op.matvec(Om)
+    if symmetric:
+        smp = rsrs.rsrs_samples_wrap(tc, Y, None, Om, None)
+    else:
+        Psi = rsrs.rsrs_gaussian(N, s, seed, 1)
+        Z = op.matvec(Psi, transpose=True)
+        smp = rsrs.rsrs_samples_wrap(tc, Y, Z, Om, Psi)
+    F = rsrs.rsrs_factor(tc, smp, K, symmetric=symmetric)
+    torch.cuda.synchronize()
+    # oracle on sampled boxes of the first class
+    to = ot.build_tree(pts, LEAF)
+    perm = to.perm
+    Yt = Y.cpu().numpy()[perm]
+    Omt = Om.cpu().numpy()[perm]
+    if symmetric:
+        Zt, Psit = Yt, Omt
+    else:
+        Zt = Z.cpu().numpy()[perm]
+        Psit = Psi.cpu().numpy()[perm]
+    del Y, Om
+    sch, lev, cls, sample = _first_class_boxes(to, K, 3)
+    nb = sch.nbrs[lev]
+    order = {int(F.box(i)["box"]): i for i in range(len(cls))}
+    max_pred = 0.0
+    for b in sample:
+        b = int(b)
+        Ba = np.arange(to.pt_begin[b], to.pt_end[b])
+        Na = np.sort(np.concatenate([np.arange(to.pt_begin[x], to.pt_end[x]) for x in nb[b].tolist()]))
+        bo = orr._process_box(b, lev, int(sch.colour[b]), Ba, Na, Yt, Zt, Omt, Psit, K, True, symmetric)
+        bg = F.box(order[b])
+        assert np.array_equal(bg["Ba"], bo.Ba) and np.array_equal(bg["Na"], bo.Na)
+        # the ID of each side on the oracle's far-field sketch
+        M = bo.M
+        sg, rg = np.searchsorted(Ba, bg["S"]), np.searchsorted(Ba, bg["R"])
+        so, ro = np.searchsorted(Ba, bo.S), np.searchsorted(Ba, bo.R)
+        res_g = np.linalg.norm(M[rg] - bg["T"] @ M[sg])
+        res_o = np.linalg.norm(M[ro] - bo.T @ M[so])
+        print(f"[fullsize] box {b}: ID residual on the oracle's sketch {res_g:.2e} "
+              f"(oracle {res_o:.2e}, ||M|| {np.linalg.norm(M):.2e})", flush=True)
+        assert res_g <= 10.0 * res_o + 1e-12 * np.linalg.norm(M)
+        noise_limited = bo.r11_min < 1e-11 * bo.norm_yz
+        if not np.array_equal(bg["S"], bo.S):
+            assert noise_limited
+            print(f"[fullsize] box {b}: skeletons differ at rounding-level pivots", flush=True)
+            continue
+        pred = 1e-16 * bo.norm_yz / bo.r11_min * (1.0 + np.abs(bo.T).max())
+        max_pred = max(max_pred, pred)
+        errs = [np.abs(bg["T"] - bo.T).max()]
+        for key in ("XRR", "KU", "KL"):
+            ref = getattr(bo, key)
+            errs.append(np.abs(bg[key] - ref).max() / np.abs(ref).max())
+        print(f"[fullsize] box {b} (l={len(Ba) + len(Na)}): errors {max(errs):.2e}, "
+              f"predicted {pred:.2e}", flush=True)
+        assert max(errs) < 100.0 * pred
+    # properties of the whole factorization: FP64 residual through refinement
+    f = torch.tensor(inputs.rhs(N, 4), dtype=torch.float64, device="cuda")
+    u, rel, it = rsrs.rsrs_solve_refine(F, op, f, tol=1e-10, maxit=10)
+    print(f"[fullsize] FP64 refinement: {rel:.2e} after {it}", flush=True)
+    assert rel <= 1e-10
+
+
+def test_fullsize_mixed_bf16_reaches_1e6():
+    need_gpu()
+    pts = inputs.grid2d(N_GRID)
+    N = N_GRID ** 2
+    op = rsrs.rsrs_op_create_kernel(rsrs.RSRS_OP_LOG2D, pts, 1.0 / N_GRID)
+    tc = rsrs.rsrs_build_tree(pts, LEAF)
+    s = tc.samples_required(K, K)
+    smp = rsrs.rsrs_sample(tc, op, s, inputs.BASE_SEED, dtype=rsrs.RSRS_BF16, symmetric=True)
+    F = rsrs.rsrs_factor(tc, smp, K, precision=rsrs.RSRS_PREC_F32_MIXED, symmetric=True)
+    f = torch.tensor(inputs.rhs(N, 16), dtype=torch.float64, device="cuda")
+    u, rel, it = rsrs.rsrs_solve_refine(F, op, f, tol=1e-6, maxit=10)
+    print(f"[fullsize mixed] residual {rel:.2e} after {it}", flush=True)
+    assert rel <= 1e-6
