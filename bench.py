@@ -43,6 +43,7 @@ if ROOT not in sys.path:
 METRIC = "factor s + solved RHS cols/s at rel. residual 1e-6, mixed vs FP64; p99 solve ms"
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
+PEAK_BF16_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
 
 GRID_N = 256
@@ -121,8 +122,22 @@ def gpu_bench(steps: int, warmup: int, do_profile: bool, latency_reps: int = 40,
     for _ in range(warmup):
         F = step(warm)
         del F
+    prof_all, dominant = {}, None
     if do_profile:
+        # one untimed step with every launch bracketed: the per-kernel
+        # breakdown, and the kernel with the largest share of GPU time
         rsrs.rsrs_profile_reset()
+        rsrs.rsrs_profile_filter(None)
+        rsrs.rsrs_profile_enable(True)
+        F = step([])
+        del F
+        rsrs.rsrs_profile_enable(False)
+        prof_all = rsrs.rsrs_profile_read()
+        rsrs.rsrs_profile_reset()
+        merged = by_kernel(prof_all)
+        dominant = max(merged, key=lambda t: merged[t]["ms"])
+        # the timed steps bracket only that kernel's launches
+        rsrs.rsrs_profile_filter(dominant)
         rsrs.rsrs_profile_enable(True)
     rec = []
     torch.cuda.synchronize()
@@ -136,6 +151,7 @@ def gpu_bench(steps: int, warmup: int, do_profile: bool, latency_reps: int = 40,
         rsrs.rsrs_profile_enable(False)
         prof = rsrs.rsrs_profile_read()
         rsrs.rsrs_profile_reset()
+        rsrs.rsrs_profile_filter(None)
 
     # solve latency of the resident factor (16 RHS per request)
     lat = []
@@ -149,7 +165,7 @@ def gpu_bench(steps: int, warmup: int, do_profile: bool, latency_reps: int = 40,
     # one-shot residual of the last factor (FP64 residual through the operator)
     r = f - op.matvec(rec[-1]["u1"])
     rec[-1]["relres_oneshot"] = float((r.norm(dim=0) / f.norm(dim=0)).max())
-    return rec, elapsed, prof, lat
+    return rec, elapsed, (prof, prof_all), lat
 
 
 def by_kernel(prof: dict) -> dict:
@@ -185,26 +201,41 @@ def measured_traffic(tag: str):
     return round(t["fetch_bytes_per_launch"] + t["write_bytes_per_launch"], 1)
 
 
-def roofline_from_profile(prof: dict, steps: int) -> dict | None:
-    if not prof:
+def roofline_from_profile(prof: dict, prof_all: dict, steps: int) -> dict | None:
+    """Roofline of the kernel with the largest share of GPU time in the
+    profiled step, from its launches in the timed steps (HIP events on the
+    launch stream).  GEMM forms run on MFMA (peak of their operand type);
+    other kernels with a flop count are plain FP64 vector arithmetic; the
+    rest are priced by their algorithmic bytes against HBM."""
+    if not prof or not prof_all:
         return None
-    prof = by_kernel(prof)
-    tag = max(prof, key=lambda t: prof[t]["ms"])
+    prof, prof_all = by_kernel(prof), by_kernel(prof_all)
+    tag = max(prof_all, key=lambda t: prof_all[t]["ms"])
+    if tag not in prof:
+        return None
     e = prof[tag]
     if e["flops"] > 0:
         ach = e["flops"] / (e["ms"] * 1e-3) / 1e12
-        peak = PEAK_FP32_TFLOPS if tag.startswith("gemm32") else PEAK_FP64_TFLOPS
-        bound, unit = "mfma", "TFLOP/s"
+        if tag.startswith("gemm_bf16"):
+            bound, peak = "mfma", PEAK_BF16_TFLOPS
+        elif tag.startswith("gemm32"):
+            bound, peak = "mfma", PEAK_FP32_TFLOPS
+        elif tag.startswith("gemm"):
+            bound, peak = "mfma", PEAK_FP64_TFLOPS
+        else:
+            bound, peak = "alu", PEAK_FP64_TFLOPS
+        unit = "TFLOP/s"
     else:
         ach = e["bytes"] / (e["ms"] * 1e-3) / 1e9
         bound, peak, unit = "hbm", PEAK_HBM_GBS, "GB/s"
-    total_ms = sum(v["ms"] for v in prof.values())
+    total_ms = sum(v["ms"] for v in prof_all.values())
     return {"bound": bound, "achieved": round(ach, 3), "peak": peak, "unit": unit,
             "frac": round(ach / peak, 4), "traffic": measured_traffic(tag), "kernel": tag,
             "launches_per_step": e["launches"] / steps,
             "avg_launch_ms": e["ms"] / e["launches"],
             "algorithmic_flops_per_launch": e["flops"] / e["launches"],
-            "share_of_kernel_time": round(e["ms"] / total_ms, 4)}
+            "algorithmic_bytes_per_launch": e["bytes"] / e["launches"],
+            "share_of_kernel_time": round(prof_all[tag]["ms"] / total_ms, 4)}
 
 
 def cpu_baseline(s_eff: int) -> dict:
@@ -454,6 +485,8 @@ def main():
     ap.add_argument("--latency-reps", type=int, default=40)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run a plain device copy of this size first (counter calibration)")
+    ap.add_argument("--modes", default="mixed,mixed_general,fp64,fp64_general",
+                    help="comma list of the precision/variant runs (the first is the headline)")
     ap.add_argument("--serving", type=float, default=0.0,
                     help="run only the serving workload for this many seconds and print its line")
     a = ap.parse_args()
@@ -471,13 +504,14 @@ def main():
     runs = {}
     plan = (("mixed", "bf16", True), ("mixed_general", "bf16", False),
             ("fp64", "fp64", True), ("fp64_general", "fp64", False))
+    want = a.modes.split(",")
     for name, mode, sym in plan:
+        if name not in want:
+            continue
         runs[name] = gpu_bench(a.steps, a.warmup, not a.no_profile, a.latency_reps,
                                a.calib_copy_mib if name == "mixed" else 0, mode, ctx, sym)
-    ua, ub = runs["mixed"][0][-1]["u"], runs["fp64"][0][-1]["u"]
-    diff = float(((ua - ub).norm() / ub.norm()).item())
-
-    def summary(rec, elapsed, prof, lat, steps):
+    def summary(rec, elapsed, profs, lat, steps):
+        prof, prof_all = profs
         return {
             "value": round(NRHS * steps / elapsed, 4),
             "ms_per_step": round(elapsed / steps * 1e3, 3),
@@ -491,16 +525,18 @@ def main():
             "solve_ms_p50": round(float(np.percentile(lat, 50)), 3),
             "solve_ms_p99": round(float(np.percentile(lat, 99)), 3),
             "solve_cols_per_s": round(NRHS / (float(np.median(lat)) * 1e-3), 1),
-            "roofline": roofline_from_profile(prof, steps),
-            "kernels": {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
-                            "tflops": round(v["flops"] / max(v["ms"], 1e-9) / 1e9, 3)}
-                        for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"])[:12]},
+            "roofline": roofline_from_profile(prof, prof_all, steps),
+            "kernels_one_step": {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
+                                     "tflops": round(v["flops"] / max(v["ms"], 1e-9) / 1e9, 3)}
+                                 for k, v in sorted(prof_all.items(), key=lambda kv: -kv[1]["ms"])[:14]},
+            "gpu_ms_one_step": round(sum(v["ms"] for v in prof_all.values()), 3),
         }
 
-    sm = summary(*runs["mixed"], a.steps)
-    smg = summary(*runs["mixed_general"], a.steps)
-    s64 = summary(*runs["fp64"], a.steps)
-    s64g = summary(*runs["fp64_general"], a.steps)
+    if "mixed" not in runs:
+        print("bench.py: the headline run 'mixed' must be among --modes", file=sys.stderr)
+        sys.exit(2)
+    sums = {name: summary(*r, a.steps) for name, r in runs.items()}
+    sm = sums["mixed"]
     rec = runs["mixed"][0]
     s_req, s_eff = rec[-1]["s_req"], rec[-1]["s_eff"]
     out = {
@@ -519,12 +555,15 @@ def main():
         "config": workload_config(s_req, s_eff),
     }
     out.update({k: v for k, v in sm.items() if k not in ("value", "ms_per_step")})
-    out["mixed_general"] = {k: v for k, v in smg.items() if k != "kernels"}
-    out["fp64"] = s64
-    out["fp64_general"] = {k: v for k, v in s64g.items() if k != "kernels"}
-    out["mixed_vs_fp64"] = {"speedup": round(sm["value"] / s64["value"], 3),
-                            "factor_speedup": round(s64["factor_s"] / sm["factor_s"], 3),
-                            "solution_rel_diff": diff}
+    for name in ("mixed_general", "fp64", "fp64_general"):
+        if name in sums:
+            keep = name == "fp64"
+            out[name] = {k: v for k, v in sums[name].items() if keep or k != "kernels_one_step"}
+    if "fp64" in runs:
+        ua, ub = runs["mixed"][0][-1]["u"], runs["fp64"][0][-1]["u"]
+        out["mixed_vs_fp64"] = {"speedup": round(sm["value"] / sums["fp64"]["value"], 3),
+                                "factor_speedup": round(sums["fp64"]["factor_s"] / sm["factor_s"], 3),
+                                "solution_rel_diff": float(((ua - ub).norm() / ub.norm()).item())}
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(s_eff)
     print(json.dumps(out))

@@ -395,6 +395,9 @@ rsrs_status rsrs_server_get_stats(rsrs_server_t* sv, int reset, rsrs_server_stat
  * forms) and 8(MK + KN + MN [+ MN read when accumulating]) bytes.
  * rsrs_profile_read synchronises the device, fills up to `max` entries and
  * returns the number of tags (or -1 on error); rsrs_profile_reset clears.
+ * rsrs_profile_filter restricts recording to tags beginning with `prefix`
+ * (NULL or "" records every launch), so that a single kernel can be timed
+ * without bracketing every other launch; the string is copied.
  * ---------------------------------------------------------------------- */
 typedef struct {
   char tag[48];
@@ -405,6 +408,7 @@ typedef struct {
 } rsrs_profile_entry;
 void rsrs_profile_enable(int on);
 void rsrs_profile_reset(void);
+void rsrs_profile_filter(const char* prefix);
 int rsrs_profile_read(rsrs_profile_entry* out, int max);
 
 #ifdef __cplusplus

@@ -219,88 +219,17 @@ template rsrs_status gemm<float, float>(Uploader&, hipStream_t, const std::vecto
 template rsrs_status gemm<float, double>(Uploader&, hipStream_t, const std::vector<GemmDescT<float, double>>&,
                                          int, int, int, GemmShape, const char*);
 
-// ---------------------------------------------------------------- Cholesky leaf
-// One workgroup per 64x64 (or smaller) diagonal block: unblocked right-looking
-// Cholesky in LDS, then the inverse of the factor by forward substitution.
-__global__ __launch_bounds__(256) void chol_leaf_kernel(const CholLeaf* __restrict__ e, int* flag) {
-  constexpr int NB = 64;
-  __shared__ double L[NB][NB + 1];
-  __shared__ double X[NB][NB + 1];
-  const CholLeaf d = e[blockIdx.x];
-  const int n = d.n;
-  const int tid = threadIdx.x;
-  for (int idx = tid; idx < NB * NB; idx += 256) {
-    const int i = idx / NB, j = idx % NB;
-    double v = 0.0;
-    if (i < n && j <= i) v = d.G[(int64_t)i * d.ld + j];
-    L[i][j] = v;
-    X[i][j] = (i == j) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  // right-looking Cholesky: column j scaled by sqrt of its pivot, then a
-  // rank-1 update of the trailing lower triangle
-  for (int j = 0; j < n; ++j) {
-    double v = L[j][j];
-    __syncthreads();
-    if (!(v > 0.0)) {
-      if (tid == 0) atomicOr(flag, 1);
-      v = 1.0;
-    }
-    const double dj = sqrt(v);
-    const double inv = 1.0 / dj;
-    if (tid == 0) L[j][j] = dj;
-    for (int i = j + 1 + tid; i < n; i += 256) L[i][j] *= inv;
-    __syncthreads();
-    const int m = n - j - 1;
-    for (int idx = tid; idx < m * m; idx += 256) {
-      const int ii = idx / m, cc = idx - ii * m;
-      if (cc <= ii) {
-        const int i = j + 1 + ii, c = j + 1 + cc;
-        L[i][c] -= L[i][j] * L[c][j];
-      }
-    }
-    __syncthreads();
-  }
-  // X = L^{-1}, right-looking: row t of X is final once divided by L[t][t];
-  // rows below then drop L[i][t] times it (columns c <= t)
-  for (int t = 0; t < n; ++t) {
-    const double inv = 1.0 / L[t][t];
-    if (tid <= t) X[t][tid] *= inv;
-    __syncthreads();
-    const int m = n - t - 1, w = t + 1;
-    for (int idx = tid; idx < m * w; idx += 256) {
-      const int ii = idx / w, c = idx - ii * w;
-      const int i = t + 1 + ii;
-      X[i][c] -= L[i][t] * X[t][c];
-    }
-    __syncthreads();
-  }
-  for (int idx = tid; idx < n * n; idx += 256) {
-    const int i = idx / n, j = idx % n;
-    d.Li[(int64_t)i * d.ld + j] = j <= i ? X[i][j] : 0.0;
-  }
-}
-
-rsrs_status chol_leaf(Uploader& up, hipStream_t st, const std::vector<CholLeaf>& e, int* flag) {
-  if (e.empty()) return RSRS_OK;
-  CholLeaf* de = nullptr;
-  RSRS_TRY(up.put_vec(e, &de));
-  double fl = 0.0;
-  for (const auto& x : e) fl += (2.0 / 3.0) * x.n * x.n * x.n;   // factor + inverse, n^3/3 each
-  ProfScope ps(st, "chol_leaf", fl, 16.0 * 64 * 64 * e.size());
-  hipLaunchKernelGGL(chol_leaf_kernel, dim3((unsigned)e.size()), dim3(256), 0, st, de, flag);
-  RSRS_HIP(hipGetLastError());
-  return RSRS_OK;
-}
 
 // ---------------------------------------------------------------- Gauss-Jordan
-// In-place Gauss-Jordan with partial pivoting, the matrix held in registers:
+// Gauss-Jordan inversion with partial pivoting, the matrix held in registers:
 // 1024 threads as a 32 x 32 grid, thread (ti, tc) owning rows ti + 32a and
-// columns tc + 32b (a, b < R).  Per step: pivot search in column j, row swap
-// through LDS, pivot row and multiplier column broadcast through LDS, rank-1
-// update of the owned elements.  The row swaps make the result (P A)^{-1};
-// the inverse of A follows by applying the swaps to the columns in reverse
-// order, done here as one permuted write-out.
+// columns tc + 32b (a, b < R).  Pivoting is implicit (rows are never
+// swapped): step j publishes column j to LDS, every wave finds the pivot row
+// p itself (largest |a_ij| over rows not yet used, lowest index on ties) by a
+// shuffle reduction, the owners of row p publish it, and every element is
+// updated branch-free; column and row buffers alternate by step parity, so a
+// step costs two barriers.  With pivot rows p_j the working matrix W ends as
+// A^{-1}[i][c] = W[p_i][q_c], q the inverse permutation, applied on write-out.
 template <int R>
 __global__ __launch_bounds__(1024) void gje_reg_kernel(const GjeDesc* __restrict__ e, int* flag) {
   constexpr int NMAX = 32 * R;
@@ -308,14 +237,12 @@ __global__ __launch_bounds__(1024) void gje_reg_kernel(const GjeDesc* __restrict
   const int n = d.n;
   const int tid = threadIdx.x;
   const int ti = tid >> 5, tc = tid & 31;
-  __shared__ double prow[NMAX];
-  __shared__ double fcol[NMAX];
-  __shared__ double swp[2][NMAX];
-  __shared__ double cmax[32];
-  __shared__ int cidx[32];
+  const int lane = tid & 63;
+  __shared__ double colb[2][NMAX];
+  __shared__ double rowb[2][NMAX];
+  __shared__ int usedf[NMAX];
   __shared__ int piv[NMAX];
-  __shared__ int colpos[NMAX];
-  __shared__ int pivot_row;
+  __shared__ int qinv[NMAX];
   double a[R][R];
 #pragma unroll
   for (int x = 0; x < R; ++x)
@@ -324,133 +251,88 @@ __global__ __launch_bounds__(1024) void gje_reg_kernel(const GjeDesc* __restrict
       const int i = ti + 32 * x, c = tc + 32 * y;
       a[x][y] = (i < n && c < n) ? d.A[(int64_t)i * d.lda + c] : 0.0;
     }
+  for (int i = tid; i < NMAX; i += 1024) usedf[i] = 0;
+  __syncthreads();
   for (int j = 0; j < n; ++j) {
-    const int jb = j >> 5, jc = j & 31;
-    // pivot search: threads of column j (tc == jc) scan their rows >= j
+    double* colv = colb[j & 1];
+    double* rowv = rowb[j & 1];
+    const int jy = j >> 5, jc = j & 31;
     if (tc == jc) {
-      double best = -1.0;
-      int bi = n;
 #pragma unroll
       for (int x = 0; x < R; ++x) {
-        const int i = ti + 32 * x;
-        if (i >= j && i < n) {
-          double v = 0.0;
+        double v = 0.0;
 #pragma unroll
-          for (int y = 0; y < R; ++y) if (y == jb) v = fabs(a[x][y]);
-          if (v > best) { best = v; bi = i; }
-        }
-      }
-      cmax[ti] = best;
-      cidx[ti] = bi;
-    }
-    __syncthreads();
-    if (tid < 64) {
-      double best = tid < 32 ? cmax[tid] : -1.0;
-      int bi = tid < 32 ? cidx[tid] : n;
-#pragma unroll
-      for (int off = 16; off > 0; off >>= 1) {
-        const double ob = __shfl_xor(best, off, 64);
-        const int oi = __shfl_xor(bi, off, 64);
-        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-      }
-      if (tid == 0) {
-        if (!(best > 0.0)) {
-          atomicOr(flag, 2);
-          bi = j;
-        }
-        pivot_row = bi;
-        piv[j] = bi;
+        for (int y = 0; y < R; ++y) v = (y == jy) ? a[x][y] : v;
+        colv[ti + 32 * x] = v;
       }
     }
     __syncthreads();
-    const int p = pivot_row;
-    // swap rows j and p through LDS
-    if (p != j) {
-      const int xj = j >> 5, xp = p >> 5;
-      if (ti == (j & 31))
-#pragma unroll
-        for (int y = 0; y < R; ++y) {
-          double v = 0.0;
-#pragma unroll
-          for (int x = 0; x < R; ++x) if (x == xj) v = a[x][y];
-          swp[0][tc + 32 * y] = v;
-        }
-      if (ti == (p & 31))
-#pragma unroll
-        for (int y = 0; y < R; ++y) {
-          double v = 0.0;
-#pragma unroll
-          for (int x = 0; x < R; ++x) if (x == xp) v = a[x][y];
-          swp[1][tc + 32 * y] = v;
-        }
-      __syncthreads();
-      if (ti == (j & 31))
-#pragma unroll
-        for (int y = 0; y < R; ++y)
-#pragma unroll
-          for (int x = 0; x < R; ++x) if (x == xj) a[x][y] = swp[1][tc + 32 * y];
-      if (ti == (p & 31))
-#pragma unroll
-        for (int y = 0; y < R; ++y)
-#pragma unroll
-          for (int x = 0; x < R; ++x) if (x == xp) a[x][y] = swp[0][tc + 32 * y];
-      __syncthreads();
+    // the first candidate is always taken, so the pivots form a permutation
+    double best = -1.0;
+    int bi = NMAX;
+    for (int i = lane; i < n; i += 64) {
+      const double v = fabs(colv[i]);
+      const bool take = !usedf[i] && (bi == NMAX || v > best);
+      best = take ? v : best;
+      bi = take ? i : bi;
     }
-    // pivot row (scaled) and multiplier column to LDS
-    if (ti == jc || tc == jc) {
 #pragma unroll
-      for (int x = 0; x < R; ++x)
-#pragma unroll
-        for (int y = 0; y < R; ++y) {
-          const int i = ti + 32 * x, c = tc + 32 * y;
-          if (i == j) prow[c] = a[x][y];
-          if (c == j) fcol[i] = a[x][y];
-        }
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ob = __shfl_xor(best, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      const bool take = oi != NMAX && (bi == NMAX || ob > best || (ob == best && oi < bi));
+      best = take ? ob : best;
+      bi = take ? oi : bi;
     }
-    __syncthreads();
-    const double pv = prow[j];
-    const double inv = pv != 0.0 ? 1.0 / pv : 0.0;
-    // a[i][c] <- a[i][c] - fcol[i] * prow[c] / pv for i != j; row j scaled;
-    // column j becomes the inverse's column: -fcol[i] / pv, and 1/pv at (j, j)
-#pragma unroll
-    for (int x = 0; x < R; ++x) {
-      const int i = ti + 32 * x;
-      const double fi = fcol[i];
+    const int p = bi;
+    if (!(best > 0.0) && tid == 0) atomicOr(flag, 2);
+    const int px = p >> 5;
+    if (ti == (p & 31)) {
 #pragma unroll
       for (int y = 0; y < R; ++y) {
-        const int c = tc + 32 * y;
-        double v = a[x][y];
-        if (i == j) {
-          v = (c == j) ? inv : v * inv;
-        } else if (c == j) {
-          v = -fi * inv;
-        } else {
-          v -= fi * inv * prow[c];
-        }
-        a[x][y] = v;
+        double v = 0.0;
+#pragma unroll
+        for (int x = 0; x < R; ++x) v = (x == px) ? a[x][y] : v;
+        rowv[tc + 32 * y] = v;
       }
     }
     __syncthreads();
-  }
-  // undo the row swaps on the columns: final[:, x] = stored[:, arr[x]]
-  if (tid == 0) {
-    for (int c = 0; c < n; ++c) colpos[c] = c;
-    for (int j = n - 1; j >= 0; --j) {
-      const int q = piv[j];
-      const int t = colpos[j];
-      colpos[j] = colpos[q];
-      colpos[q] = t;
+    if (tid == 0) {
+      usedf[p] = 1;
+      piv[j] = p;
     }
-    // colpos[x] = stored column placed at x; invert into fcol as int via piv
-    for (int x = 0; x < n; ++x) piv[colpos[x]] = x;
+    const double pv = colv[p];
+    const double inv = pv != 0.0 ? 1.0 / pv : 0.0;
+    double rv[R], prow[R], fi[R];
+    bool isj[R], isp[R];
+#pragma unroll
+    for (int y = 0; y < R; ++y) {
+      rv[y] = rowv[tc + 32 * y];
+      isj[y] = (tc + 32 * y) == j;
+      prow[y] = isj[y] ? inv : rv[y] * inv;   // new pivot row (column j: 1 / pivot)
+    }
+#pragma unroll
+    for (int x = 0; x < R; ++x) {
+      fi[x] = colv[ti + 32 * x] * inv;
+      isp[x] = (ti + 32 * x) == p;
+    }
+#pragma unroll
+    for (int x = 0; x < R; ++x)
+#pragma unroll
+      for (int y = 0; y < R; ++y) {
+        const double g = isj[y] ? -fi[x] : a[x][y] - fi[x] * rv[y];
+        a[x][y] = isp[x] ? prow[y] : g;
+      }
   }
+  __syncthreads();
+  for (int j = tid; j < n; j += 1024) qinv[piv[j]] = j;
   __syncthreads();
 #pragma unroll
   for (int x = 0; x < R; ++x)
 #pragma unroll
     for (int y = 0; y < R; ++y) {
-      const int i = ti + 32 * x, c = tc + 32 * y;
-      if (i < n && c < n) d.Ainv[(int64_t)i * d.ldi + piv[c]] = a[x][y];
+      const int ri = ti + 32 * x, ci = tc + 32 * y;
+      if (ri < n && ci < n) d.Ainv[(int64_t)qinv[ri] * d.ldi + piv[ci]] = a[x][y];
     }
 }
 

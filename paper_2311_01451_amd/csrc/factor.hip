@@ -48,70 +48,6 @@ namespace rsrs {
 
 namespace {
 
-struct CholMat {
-  double* G;
-  double* L;
-  int64_t ld;
-  int n;
-};
-
-constexpr int kLeaf = 64;
-
-// Recursive Cholesky with inverse factor on the index range [a, b) shared by
-// all matrices of the batch (each clipped to its own size n).  Callers pass
-// a range of 64 * 2^j indices (chol_span), so every split point depends only
-// on the position, never on the other matrices of the batch: a matrix gets
-// the same blocking, and the same rounding, alone or batched.
-rsrs_status rchol(Uploader& up, hipStream_t st, const std::vector<CholMat>& mats, int a, int b,
-                  int* flag) {
-  if (b - a <= kLeaf) {
-    std::vector<CholLeaf> e;
-    for (const auto& m : mats) {
-      const int hi = std::min(b, m.n);
-      if (hi <= a) continue;
-      e.push_back(CholLeaf{m.G + (int64_t)a * m.ld + a, m.L + (int64_t)a * m.ld + a, m.ld, hi - a, 0});
-    }
-    return chol_leaf(up, st, e, flag);
-  }
-  const int nblk = (b - a + kLeaf - 1) / kLeaf;
-  const int h = a + kLeaf * ((nblk + 1) / 2);
-  RSRS_TRY(rchol(up, st, mats, a, h, flag));
-  std::vector<GemmDesc> g1, g2, g4, g5;
-  for (const auto& m : mats) {
-    const int hi = std::min(b, m.n);
-    if (hi <= h) continue;
-    const int rows = hi - h, w = h - a;
-    double* G21 = m.G + (int64_t)h * m.ld + a;
-    double* L11 = m.L + (int64_t)a * m.ld + a;
-    double* L21 = m.L + (int64_t)h * m.ld + a;
-    double* G22 = m.G + (int64_t)h * m.ld + h;
-    double* L22 = m.L + (int64_t)h * m.ld + h;
-    // (1) T1 = A21 L11^{-T} -> L21 slot
-    g1.push_back(gdesc(G21, nullptr, m.ld, L11, nullptr, m.ld, L21, nullptr, m.ld, rows, w, w));
-    // (2) A22 -= T1 T1^T (lower)
-    g2.push_back(gdesc(L21, nullptr, m.ld, L21, nullptr, m.ld, G22, nullptr, m.ld, rows, rows, w,
-                       -1.0, 1.0));
-    // (4) W = T1 L11^{-1} -> G21 slot (A21 is dead)
-    g4.push_back(gdesc(L21, nullptr, m.ld, L11, nullptr, m.ld, G21, nullptr, m.ld, rows, w, w));
-    // (5) L21^{-1} block = -L22^{-1} W
-    g5.push_back(gdesc(L22, nullptr, m.ld, G21, nullptr, m.ld, L21, nullptr, m.ld, rows, w, rows,
-                       -1.0, 0.0));
-  }
-  RSRS_TRY(gemm(up, st, g1, 0, 1, GM_B_NT_LOW, GS_64x64, "chol"));
-  RSRS_TRY(gemm(up, st, g2, 0, 1, GM_SYRK_L, GS_64x64, "chol"));
-  RSRS_TRY(gemm(up, st, g4, 0, 0, GM_B_NN_LOW, GS_64x64, "chol"));
-  RSRS_TRY(rchol(up, st, mats, h, b, flag));
-  RSRS_TRY(gemm(up, st, g5, 0, 0, GM_A_LOW, GS_64x64, "chol"));
-  return RSRS_OK;
-}
-
-// Smallest range 64 * 2^j covering n indices.
-int chol_span(int n) {
-  int w = kLeaf;
-  while (w < n) w *= 2;
-  return w;
-}
-
 struct Bump {
   char* base = nullptr;
   size_t off = 0, cap = 0;
@@ -445,27 +381,26 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
     {
       std::vector<GemmDescT<T, double>> gd;
       std::vector<CholMat> cm;
-      int lmax = 0;
       for (auto& it : items) {
         const BoxRec& R = *it.R;
         const Job<T>& J = *it.J;
         const BoxWs<T>& w = it.w;
         const int l = (int)(R.b + R.n);
         const int64_t* idxC = J.iS + R.oBa;
-        gd.push_back(gdescT<T, double>(J.Om, idxC, J.sld, J.Om, idxC, J.sld, w.GO, nullptr, w.lp, l, l, (int)J.s));
-        cm.push_back(CholMat{w.GO, w.LO, w.lp, l});
+        // the Gram matrix is factored in place: L^{-1} lands where it is used
+        gd.push_back(gdescT<T, double>(J.Om, idxC, J.sld, J.Om, idxC, J.sld, w.LO, nullptr, w.lp, l, l, (int)J.s));
+        cm.push_back(CholMat{w.LO, w.GO, w.lp, l});
         if (!J.sym) {
-          gd.push_back(gdescT<T, double>(J.Psi, idxC, J.sld, J.Psi, idxC, J.sld, w.GP, nullptr, w.lp, l, l, (int)J.s));
-          cm.push_back(CholMat{w.GP, w.LP, w.lp, l});
+          gd.push_back(gdescT<T, double>(J.Psi, idxC, J.sld, J.Psi, idxC, J.sld, w.LP, nullptr, w.lp, l, l, (int)J.s));
+          cm.push_back(CholMat{w.LP, w.GP, w.lp, l});
         }
-        lmax = std::max(lmax, l);
         const double dl = l, db = (double)R.b, ds = (double)J.s, sides = J.sym ? 1.0 : 2.0;
         it.J->flops += sides * (dl * dl * ds                              // Gram matrices
                                 + (2.0 / 3.0) * dl * dl * dl              // Cholesky + inverse factor
                                 + (1.0 + J.reproject) * (4.0 * db * dl * ds + 2.0 * db * dl * dl));  // projections
       }
       RSRS_TRY(gemm<T, double>(up, st, gd, 0, 1, GM_SYRK_L, GS_64x64, "gram"));
-      RSRS_TRY(rchol(up, st, cm, 0, chol_span(lmax), flag));
+      RSRS_TRY(chol_inverse(up, st, cm, flag));
       if constexpr (mixed) {   // inverse factors rounded for the FP32 products
         std::vector<Copy2DT<double, T>> lc;
         for (auto& it : items) {
@@ -777,17 +712,15 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
     if (bump.off > bump.cap) { set_error("internal: root workspace overflow"); return RSRS_E_INVALID; }
     std::vector<GemmDesc> g0, g1, g2, g3;
     std::vector<CholMat> cm;
-    int ntmax = 0;
     for (auto& R : roots) {
-      g0.push_back(gdesc(R.Or, R.ir, R.rld, R.Or, R.ir, R.rld, R.G, nullptr, R.ntp, R.nt, R.nt, R.s));
-      cm.push_back(CholMat{R.G, R.L, R.ntp, R.nt});
+      g0.push_back(gdesc(R.Or, R.ir, R.rld, R.Or, R.ir, R.rld, R.L, nullptr, R.ntp, R.nt, R.nt, R.s));
+      cm.push_back(CholMat{R.L, R.G, R.ntp, R.nt});
       g1.push_back(gdesc(R.Yr, R.ir, R.rld, R.Or, R.ir, R.rld, R.P, nullptr, R.ntp, R.nt, R.nt, R.s));
       g2.push_back(gdesc(R.P, nullptr, R.ntp, R.L, nullptr, R.ntp, R.Wb, nullptr, R.ntp, R.nt, R.nt, R.nt));
       g3.push_back(gdesc(R.Wb, nullptr, R.ntp, R.L, nullptr, R.ntp, R.At, nullptr, R.nt, R.nt, R.nt, R.nt));
-      ntmax = std::max(ntmax, R.nt);
     }
     RSRS_TRY(gemm(up, st, g0, 0, 1, GM_SYRK_L));
-    RSRS_TRY(rchol(up, st, cm, 0, chol_span(ntmax), flag));
+    RSRS_TRY(chol_inverse(up, st, cm, flag));
     RSRS_TRY(gemm(up, st, g1, 0, 1, GM_FULL));
     RSRS_TRY(gemm(up, st, g2, 0, 1, GM_B_NT_LOW));
     RSRS_TRY(gemm(up, st, g3, 0, 0, GM_B_NN_LOW));

@@ -118,30 +118,54 @@ __global__ __launch_bounds__(64) void id_step_kernel(const IdDesc* __restrict__ 
 
 // Same step with the row and the pivot row held in registers (R doubles per
 // lane, s <= 64 R): one read of each and one write of the row per step
-// instead of two passes over both.
+// instead of two passes over both.  Four rows per workgroup (one per wave);
+// the row is requested before the pivot search so that its load overlaps
+// the search, and the search itself loads all candidates at once.
 template <int R>
-__global__ __launch_bounds__(64) void id_step_reg_kernel(const IdDesc* __restrict__ e, int j) {
+__global__ __launch_bounds__(256) void id_step_reg_kernel(const IdDesc* __restrict__ e, int j) {
   const IdDesc d = e[blockIdx.y];
-  const int i = blockIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int i = 4 * blockIdx.x + (threadIdx.x >> 6);
   if (i >= d.b || j >= d.k) return;
-  const int lane = threadIdx.x;
+  double* mi = d.M + (int64_t)i * d.ldm;
+  double ri[R];
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const int c = lane + 64 * u;
+    ri[u] = c < d.s ? mi[c] : 0.0;
+  }
   const double* cur = d.norms + (j & 1) * d.b;
   double* nxt = d.norms + ((j + 1) & 1) * d.b;
+  // pivot: argmax over rows not selected before step j (lowest index on ties;
+  // the first candidate is always taken, so a NaN norm cannot leave bi unset)
   double best = -1.0;
   int bi = INT_MAX;
-  for (int x = lane; x < d.b; x += 64) {
-    if (d.sel[x] < j) continue;
-    const double v = cur[x];
-    if (bi == INT_MAX || v > best) { best = v; bi = x; }
+  for (int x0 = 0; x0 < d.b; x0 += 256) {
+    int sv[4];
+    double nv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int x = x0 + lane + 64 * u;
+      sv[u] = x < d.b ? d.sel[x] : -1;
+      nv[u] = x < d.b ? cur[x] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const bool take = sv[u] >= j && (bi == INT_MAX || nv[u] > best);
+      best = take ? nv[u] : best;
+      bi = take ? x0 + lane + 64 * u : bi;
+    }
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     const double ob = __shfl_xor(best, off, 64);
     const int oi = __shfl_xor(bi, off, 64);
-    if (oi != INT_MAX && (bi == INT_MAX || ob > best || (ob == best && oi < bi))) { best = ob; bi = oi; }
+    const bool take = oi != INT_MAX && (bi == INT_MAX || ob > best || (ob == best && oi < bi));
+    best = take ? ob : best;
+    bi = take ? oi : bi;
   }
-  const int p = bi;
-  const double pn2 = best > 0.0 ? best : 0.0;
+  const int p = bi;   // always a valid row: b - j > 0 candidates remain for j < k < b
+  const double pn2 = best > 0.0 ? best : 0.0;   // also maps NaN to 0
   const double pn = sqrt(pn2);
   if (i == p) {
     if (lane == 0) {
@@ -153,17 +177,16 @@ __global__ __launch_bounds__(64) void id_step_reg_kernel(const IdDesc* __restric
     return;
   }
   if (d.sel[i] < j) return;
-  double* mi = d.M + (int64_t)i * d.ldm;
   const double* mp = d.M + (int64_t)p * d.ldm;
-  double ri[R], rp[R];
+  double rp[R];
   double dot = 0.0;
 #pragma unroll
   for (int u = 0; u < R; ++u) {
     const int c = lane + 64 * u;
-    ri[u] = c < d.s ? mi[c] : 0.0;
     rp[u] = c < d.s ? mp[c] : 0.0;
-    dot += ri[u] * rp[u];
   }
+#pragma unroll
+  for (int u = 0; u < R; ++u) dot += ri[u] * rp[u];
   dot = wave_sum(dot);
   const double coef = pn2 > 0.0 ? dot / pn2 : 0.0;
   double s = 0.0;
@@ -182,8 +205,9 @@ __global__ __launch_bounds__(64) void id_step_reg_kernel(const IdDesc* __restric
 }
 
 // S, R sorted; T = (R11^{-1} R12)^T written with columns in sorted-S order.
-// Positions come from a block-wide prefix count of the selected rows; R11
-// (k <= 64) is staged in LDS for the back substitutions, one thread per row of R.
+// Positions come from a block-wide prefix count of the selected rows; for
+// k <= 64, R11 is staged in LDS and each thread solves for one row of R with
+// the solution in registers (larger k reads R11 from global memory).
 __global__ __launch_bounds__(256) void id_finalize_kernel(const IdDesc* __restrict__ e) {
   const IdDesc d = e[blockIdx.x];
   const int b = d.b, k = d.k, r = b - k;
@@ -219,12 +243,44 @@ __global__ __launch_bounds__(256) void id_finalize_kernel(const IdDesc* __restri
   }
   __syncthreads();
   for (int t = tid; t < k; t += 256) rank_of_step[t] = pre[d.piv[t]];
-  const bool lds = k <= KL;
-  if (lds)
-    for (int idx = tid; idx < k * k; idx += 256) {
-      const int t = idx / k, u = idx % k;
-      R11[idx] = t <= u ? d.Rc[(int64_t)d.piv[u] * k + t] : 0.0;
+  if (k <= KL) {
+    // R11 padded to 64 x 64 (identity beyond k); each thread keeps its
+    // solution in registers, the padding adding exact zeros
+    for (int idx = tid; idx < KL * KL; idx += 256) {
+      const int t = idx / KL, u = idx % KL;
+      double v = (t == u) ? 1.0 : 0.0;
+      if (t < k && u < k) v = t <= u ? d.Rc[(int64_t)d.piv[u] * k + t] : 0.0;
+      R11[idx] = v;
     }
+    __syncthreads();
+    for (int q = tid; q < r; q += 256) {
+      const int i = (int)d.Rpos[q];
+      const double* cr = d.Rc + (int64_t)i * k;
+      double* Tq = d.T + (int64_t)q * d.ldt;
+      // back substitution R11 x = c, R11[t][u] = Rc[p_u][t] (t <= u), in
+      // place: c[t] becomes x[t] once rows t + 1.. are done.  The scheduling
+      // fences keep the LDS reads of R11 from being hoisted en masse.
+      double c[KL];
+#pragma unroll
+      for (int t = 0; t < KL; ++t) c[t] = t < k ? cr[t] : 0.0;
+#pragma unroll
+      for (int t = KL - 1; t >= 0; --t) {
+        double acc = c[t];
+#pragma unroll
+        for (int u = t + 1; u < KL; ++u) {
+          acc -= R11[t * KL + u] * c[u];
+          if (((u - t) & 7) == 0) __builtin_amdgcn_sched_barrier(0);
+        }
+        const double diag = R11[t * KL + t];
+        c[t] = diag != 0.0 ? acc / diag : 0.0;
+        __builtin_amdgcn_sched_barrier(0);
+      }
+#pragma unroll
+      for (int t = 0; t < KL; ++t)
+        if (t < k) Tq[rank_of_step[t]] = c[t];
+    }
+    return;
+  }
   __syncthreads();
   for (int q = tid; q < r; q += 256) {
     const int i = (int)d.Rpos[q];
@@ -233,11 +289,8 @@ __global__ __launch_bounds__(256) void id_finalize_kernel(const IdDesc* __restri
     // back substitution R11 x = c, R11[t][u] = Rc[p_u][t] (t <= u)
     for (int t = k - 1; t >= 0; --t) {
       double acc = cr[t];
-      for (int u = t + 1; u < k; ++u) {
-        const double rtu = lds ? R11[t * k + u] : d.Rc[(int64_t)d.piv[u] * k + t];
-        acc -= rtu * Tq[rank_of_step[u]];
-      }
-      const double diag = lds ? R11[t * k + t] : d.Rc[(int64_t)d.piv[t] * k + t];
+      for (int u = t + 1; u < k; ++u) acc -= d.Rc[(int64_t)d.piv[u] * k + t] * Tq[rank_of_step[u]];
+      const double diag = d.Rc[(int64_t)d.piv[t] * k + t];
       Tq[rank_of_step[t]] = diag != 0.0 ? acc / diag : 0.0;
     }
   }
@@ -272,10 +325,11 @@ rsrs_status id_run(Uploader& up, hipStream_t st, const std::vector<IdDesc>& e) {
   const int nchunk = (smax + 63) / 64;
   for (int j = 0; j < kmax; ++j) {
     ProfScope ps(st, "id_step", fstep, bstep);
+    const unsigned g4 = (unsigned)((bmax + 3) / 4);
     if (nchunk <= 16)
-      hipLaunchKernelGGL(id_step_reg_kernel<16>, dim3((unsigned)bmax, nb), dim3(64), 0, st, de, j);
+      hipLaunchKernelGGL(id_step_reg_kernel<16>, dim3(g4, nb), dim3(256), 0, st, de, j);
     else if (nchunk <= 40)
-      hipLaunchKernelGGL(id_step_reg_kernel<40>, dim3((unsigned)bmax, nb), dim3(64), 0, st, de, j);
+      hipLaunchKernelGGL(id_step_reg_kernel<40>, dim3(g4, nb), dim3(256), 0, st, de, j);
     else
       hipLaunchKernelGGL(id_step_kernel, dim3((unsigned)bmax, nb), dim3(64), 0, st, de, j);
   }

@@ -61,7 +61,7 @@ rsrs_status kernel_materialise(hipStream_t st, const KernelOp& op, T* A);
 }  // namespace rsrs
 
 namespace rsrs {
-// A solve or apply of one factor for a fixed width, captured as a HIP graph:
+// A solve or apply of one factor for a fixed width, held as a HIP graph:
 // its own tree-ordered work blocks x, u (n x w, zero-initialised so padded
 // columns stay zero), the descriptors of every launch, and the graph.
 struct SolvePlan {
@@ -91,12 +91,8 @@ struct rsrs_factor_s {
   mutable rsrs::DevBuf wx, wu, wt, wpart, wnorm;
   mutable rsrs::Uploader up;
   mutable bool up_ready = false;
-  mutable std::vector<std::unique_ptr<rsrs::SolvePlan>> plans;   // captured solves
-  mutable hipStream_t capture_stream = nullptr;
-  ~rsrs_factor_s() {
-    plans.clear();
-    if (capture_stream) (void)hipStreamDestroy(capture_stream);
-  }
+  mutable std::vector<std::unique_ptr<rsrs::SolvePlan>> plans;   // solves as graphs
+  ~rsrs_factor_s() { plans.clear(); }
   template <typename T> const T* d() const { return dstore.as<T>(); }
   const int64_t* i() const { return istore.as<int64_t>(); }
 };

@@ -89,11 +89,13 @@ inline GemmDesc gdesc(const double* A, const int64_t* ia, int64_t lda, const dou
 }
 
 // ---- dense helpers (dense.hip) --------------------------------------------
-struct CholLeaf { double* G; double* Li; int64_t ld; int n; int pad_; };
-// Cholesky of each n x n (n <= 64) lower block G and the inverse of its factor
-// into Li (full block, zeros above the diagonal).  flag[0] |= 1 when a pivot
-// is not positive.
-rsrs_status chol_leaf(Uploader& up, hipStream_t st, const std::vector<CholLeaf>& e, int* flag);
+struct CholMat { double* G; double* W; int64_t ld; int n; };
+// Cholesky G = L L^T of each n x n matrix (lower part of G read) and the
+// inverse factor: on return G holds L^{-1} in its lower part (the upper part
+// of its 64 x 64 diagonal blocks zero, the rest of the upper part
+// unspecified); W (same shape) is scratch.  flag[0] |= 1 when a pivot is not
+// positive.
+rsrs_status chol_inverse(Uploader& up, hipStream_t st, const std::vector<CholMat>& mats, int* flag);
 
 struct GjeDesc { const double* A; double* W; double* Ainv; int64_t lda, ldi; int n, pad_; };
 // Inverse of each n x n matrix by Gauss-Jordan elimination with partial

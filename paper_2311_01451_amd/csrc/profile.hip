@@ -25,6 +25,7 @@ std::mutex g_mu;
 bool g_on = false;
 std::vector<Rec> g_recs;
 std::vector<hipEvent_t> g_pool;
+std::string g_filter;   // kernel-name prefix of the launches to record ("" = all)
 
 hipEvent_t get_event() {
   if (!g_pool.empty()) {
@@ -39,15 +40,12 @@ hipEvent_t get_event() {
 
 }  // namespace
 
-thread_local bool g_suspended = false;
+bool prof_on() { return g_on; }
 
-bool prof_on() { return g_on && !g_suspended; }
-
-void prof_suspend(bool s) { g_suspended = s; }
-
-int prof_begin(hipStream_t st) {
-  if (!g_on || g_suspended) return -1;
+int prof_begin(hipStream_t st, const char* tag) {
+  if (!g_on) return -1;
   std::lock_guard<std::mutex> lk(g_mu);
+  if (!g_filter.empty() && std::strncmp(tag, g_filter.c_str(), g_filter.size()) != 0) return -1;
   Rec r{get_event(), get_event(), std::string(), 0.0, 0.0, false};
   if (!r.a || !r.b) return -1;
   if (hipEventRecord(r.a, st) != hipSuccess) return -1;
@@ -71,6 +69,11 @@ void prof_end(int slot, hipStream_t st, const char* tag, double flops, double by
 extern "C" {
 
 void rsrs_profile_enable(int on) { rsrs::g_on = on != 0; }
+
+void rsrs_profile_filter(const char* prefix) {
+  std::lock_guard<std::mutex> lk(rsrs::g_mu);
+  rsrs::g_filter = prefix ? prefix : "";
+}
 
 void rsrs_profile_reset(void) {
   std::lock_guard<std::mutex> lk(rsrs::g_mu);

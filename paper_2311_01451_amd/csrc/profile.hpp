@@ -7,11 +7,8 @@
 namespace rsrs {
 
 bool prof_on();
-// Suspends accounting on the calling thread (launches recorded into a graph
-// are accounted as one replay instead).
-void prof_suspend(bool s);
 // Returns an opaque slot (or -1 when profiling is off); call prof_end after the launch.
-int prof_begin(hipStream_t st);
+int prof_begin(hipStream_t st, const char* tag);
 void prof_end(int slot, hipStream_t st, const char* tag, double flops, double bytes);
 
 // RAII helper around one launch.
@@ -21,7 +18,7 @@ struct ProfScope {
   const char* tag;
   double flops, bytes;
   ProfScope(hipStream_t s, const char* t, double f = 0.0, double b = 0.0)
-      : slot(prof_begin(s)), st(s), tag(t), flops(f), bytes(b) {}
+      : slot(prof_begin(s, t)), st(s), tag(t), flops(f), bytes(b) {}
   ~ProfScope() { if (slot >= 0) prof_end(slot, st, tag, flops, bytes); }
 };
 

@@ -11,7 +11,7 @@
 //
 // Launch latency, not bandwidth, bounds a narrow solve (a few hundred small
 // launches per sweep), so by default the launch sequence of a factor is
-// captured once per (operation, transpose, width bucket) into a HIP graph
+// assembled once per (operation, transpose, width bucket) into a HIP graph
 // with pre-uploaded descriptors and its own work blocks, and replayed; the
 // width is padded to the bucket (16, 32, 64, ... 1024) with zero columns,
 // which do not touch the others.  Only the gather into tree order and the
@@ -197,22 +197,31 @@ rsrs_status make_plan(const rsrs_factor_t* F, int op, int transpose, int64_t wb,
   RSRS_TRY(P->descs.alloc(std::max<size_t>(all.size(), 1) * sizeof(GemmDescT<T, T>)));
   if (!all.empty())
     RSRS_HIP(hipMemcpy(P->descs.p, all.data(), all.size() * sizeof(GemmDescT<T, T>), hipMemcpyHostToDevice));
-  if (!F->capture_stream) RSRS_HIP(hipStreamCreateWithFlags(&F->capture_stream, hipStreamNonBlocking));
-  hipStream_t cs = F->capture_stream;
-  RSRS_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-  prof_suspend(true);
-  rsrs_status st = RSRS_OK;
-  for (const auto& x : L) {
-    st = gemm_exec(x, P->descs.p, sizeof(GemmDescT<T, T>), cs);
-    if (st != RSRS_OK) break;
-  }
-  prof_suspend(false);
+  // the graph is assembled node by node (a linear chain of the product
+  // launches), not captured from a stream: stream capture would be
+  // invalidated by allocations or synchronisations that other threads
+  // (other factorizations, a serving loop) make meanwhile
   hipGraph_t g = nullptr;
-  const hipError_t e = hipStreamEndCapture(cs, &g);
-  RSRS_TRY(st);
-  if (e != hipSuccess || !g) {
-    set_error(std::string("graph capture failed: ") + hipGetErrorString(e));
-    return RSRS_E_HIP;
+  RSRS_HIP(hipGraphCreate(&g, 0));
+  hipGraphNode_t prev = nullptr;
+  for (const auto& x : L) {
+    const void* p = static_cast<const char*>(P->descs.p) + x.first * sizeof(GemmDescT<T, T>);
+    void* args[] = {&p};
+    hipKernelNodeParams kp{};
+    kp.func = const_cast<void*>(x.fn);
+    kp.gridDim = x.grid;
+    kp.blockDim = x.block;
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = args;
+    kp.extra = nullptr;
+    hipGraphNode_t node = nullptr;
+    const hipError_t e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      set_error(std::string("graph assembly failed: ") + hipGetErrorString(e));
+      return RSRS_E_HIP;
+    }
+    prev = node;
   }
   P->graph = g;
   RSRS_HIP(hipGraphInstantiate(&P->exec, g, nullptr, nullptr, 0));

@@ -97,7 +97,7 @@ EXPORTS = [
     "rsrs_factor_destroy",
     "rsrs_factor_get_info", "rsrs_factor_box_sizes", "rsrs_factor_box_copy",
     "rsrs_factor_root_copy", "rsrs_solve", "rsrs_apply", "rsrs_solve_refine",
-    "rsrs_profile_enable", "rsrs_profile_reset", "rsrs_profile_read", "rsrs_solve_graphs",
+    "rsrs_profile_enable", "rsrs_profile_filter", "rsrs_profile_reset", "rsrs_profile_read", "rsrs_solve_graphs",
     "rsrs_server_create", "rsrs_server_destroy", "rsrs_server_add_factor",
     "rsrs_server_release_factor", "rsrs_server_submit_solve", "rsrs_server_submit_factor",
     "rsrs_server_wait", "rsrs_server_get_stats",
@@ -160,6 +160,7 @@ def lib():
         "rsrs_profile_enable": (None, [i32]),
         "rsrs_solve_graphs": (None, [i32]),
         "rsrs_profile_reset": (None, []),
+        "rsrs_profile_filter": (None, [C.c_char_p]),
         "rsrs_profile_read": (i32, [P(ProfileEntry), i32]),
     }
     for name, (res, args) in sig.items():
@@ -604,6 +605,11 @@ class Server:
 # --------------------------------------------------------------------------- measurement
 def rsrs_profile_enable(on: bool = True):
     lib().rsrs_profile_enable(int(on))
+
+
+def rsrs_profile_filter(prefix: str | None = None):
+    """Record only launches whose tag begins with `prefix` (None: all)."""
+    lib().rsrs_profile_filter(prefix.encode() if prefix else None)
 
 
 def rsrs_profile_reset():
