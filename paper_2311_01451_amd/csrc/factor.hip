@@ -23,6 +23,15 @@
 //           E, F (sparsify) followed by L, U (eliminate).
 //  root     A_t = Y_Bt pinv(Omega_Bt) by the same Gram route, then A_t^{-1}.
 //
+// Streams.  Phase B of a class (from the extraction to the sketch updates)
+// runs on a second stream.  It starts once the skeletons are known and the
+// test matrices are sparsified (Omega_S += T^T Omega_R, done on the main
+// stream, the only update the next class's Gram matrices depend on); the
+// main stream meanwhile forms the next class's Gram matrices and factors
+// them, and waits for phase B only before the next projections, which read
+// the updated Y / Z.  What phase B reads lives in a part of the workspace
+// that alternates between two buffers from class to class.
+//
 // Precision.  The whole class of operations is templated on the element type
 // T of the samples and of the stored factor.  T = double is plain FP64.  With
 // T = float (the mixed-precision factorization) every product of sketch-sized
@@ -59,27 +68,54 @@ struct Bump {
   }
 };
 
-// Workspace bytes of one box (b, l) in a class, samples of element type T.
+// A second stream and the two events that order it against the main one;
+// the destructor drains it, so no kernel outlives the workspace it reads.
+struct SideStream {
+  hipStream_t st = nullptr;
+  hipEvent_t eA = nullptr, eB = nullptr;
+  rsrs_status init() {
+    RSRS_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    RSRS_HIP(hipEventCreateWithFlags(&eA, hipEventDisableTiming));
+    RSRS_HIP(hipEventCreateWithFlags(&eB, hipEventDisableTiming));
+    return RSRS_OK;
+  }
+  ~SideStream() {
+    if (st) {
+      (void)hipStreamSynchronize(st);
+      (void)hipStreamDestroy(st);
+    }
+    if (eA) (void)hipEventDestroy(eA);
+    if (eB) (void)hipEventDestroy(eB);
+  }
+};
+
+// Workspace bytes of one box (b, l) in a class, samples of element type T,
+// in two parts: what only the projections and the ID use (*a), and what the
+// extraction and elimination read after them (*b).  The second part is held
+// twice, so that the next class's Gram matrices and Cholesky factorizations
+// can run while this class finishes.
 template <typename T>
-size_t box_ws_bytes(int64_t b, int64_t l, int64_t k, int64_t sp) {
+void box_ws_bytes(int64_t b, int64_t l, int64_t k, int64_t sp, size_t* a, size_t* bpart) {
   constexpr bool mixed = sizeof(T) != sizeof(double);
   const int64_t lp = round_up(l, 16);
   const int64_t r = b - k;
-  int64_t dbl = 4 * l * lp        // G, L for both sides
-                + 2 * b + b * k   // norms, R coefficients
-                + 2 * r * r;      // Gauss-Jordan work
-  int64_t tel = 6 * b * lp        // P, W, X for both sides
-                + 2 * b * sp      // M_Y, M_Z
-                + 4 * r * lp;     // XR, Xp for both sides
+  int64_t dblA = 4 * l * lp        // G, L for both sides
+                 + 2 * b + b * k;  // norms, R coefficients
+  int64_t telA = 4 * b * lp        // P, W for both sides
+                 + 2 * b * sp;     // M_Y, M_Z
+  int64_t dblB = 2 * r * r;        // Gauss-Jordan work
+  int64_t telB = 2 * b * lp        // X for both sides
+                 + 4 * r * lp;     // XR, Xp for both sides
   if (mixed) {
-    dbl += b * sp                 // FP64 copy of M for the ID
-           + r * round_up(k, 4)   // T as computed by the ID
-           + 2 * r * r;           // X_RR and its inverse in FP64
-    tel += 2 * l * lp;            // rounded inverse factors
+    dblA += b * sp                 // FP64 copy of M for the ID
+            + r * round_up(k, 4);  // T as computed by the ID
+    dblB += 2 * r * r;             // X_RR and its inverse in FP64
+    telA += 2 * l * lp;            // rounded inverse factors
   }
-  int64_t ints = b + k;           // sel, piv (int32)
-  int64_t i64 = k + b;            // Spos, Rpos
-  return (size_t)(dbl * 8 + tel * sizeof(T) + ints * 4 + i64 * 8 + 32 * 256);
+  const int64_t ints = b + k;      // sel, piv (int32)
+  const int64_t i64 = k + b;       // Spos, Rpos
+  *a = (size_t)(dblA * 8 + telA * sizeof(T) + ints * 4 + 20 * 256);
+  *bpart = (size_t)(dblB * 8 + telB * sizeof(T) + i64 * 8 + 12 * 256);
 }
 
 template <typename T>
@@ -118,7 +154,7 @@ struct Job {
   size_t li = 0, ci = 0;        // level index and class index of the next class
   std::unordered_map<int64_t, size_t> pos;
   std::vector<std::vector<int64_t>> Ba, Na;   // active sets of the current class
-  std::vector<size_t> class_ws;               // workspace bytes of each class
+  std::vector<size_t> class_ws, class_wsb;    // workspace bytes of each class (two parts)
   size_t root_ws = 0;
   double flops = 0.0;
 
@@ -209,7 +245,7 @@ rsrs_status job_init(Job<T>& J, const rsrs_tree_t* th, rsrs_samples_t* smp,
     for (size_t c = 0; c < J.sch.classes[li].size(); ++c) {
       Group g;
       g.first = (int64_t)F->boxes.size();
-      size_t ws = 0;
+      size_t ws = 0, wsb = 0;
       for (int64_t b : J.sch.classes[li][c]) {
         BoxRec r;
         r.box = b;
@@ -232,11 +268,15 @@ rsrs_status job_init(Job<T>& J, const rsrs_tree_t* th, rsrs_samples_t* smp,
         r.oNa = isz; isz += r.n;
         r.oBa = isz; isz += r.b + r.n;   // Ba followed by a second copy of Na
         F->boxes.push_back(r);
-        ws += box_ws_bytes<T>(r.b, r.b + r.n, k, J.sld);
+        size_t wa = 0, wb = 0;
+        box_ws_bytes<T>(r.b, r.b + r.n, k, J.sld, &wa, &wb);
+        ws += wa;
+        wsb += wb;
       }
       g.count = (int64_t)F->boxes.size() - g.first;
       F->groups.push_back(g);
       J.class_ws.push_back(ws);
+      J.class_wsb.push_back(wsb);
     }
   }
   F->nt = J.sch.root_count;
@@ -274,24 +314,40 @@ template <typename T>
 rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
   constexpr bool mixed = Job<T>::mixed;
   auto t0 = std::chrono::steady_clock::now();
-  size_t nsteps = 0, ws_max = 0, root_total = 0;
+  size_t nsteps = 0, ws_max = 0, wsb_max = 0, root_total = 0;
   for (auto& J : jobs) nsteps = std::max(nsteps, J.F->groups.size());
   for (size_t t = 0; t < nsteps; ++t) {
-    size_t w = 0;
+    size_t w = 0, wb = 0;
     for (auto& J : jobs)
-      if (t < J.class_ws.size()) w += J.class_ws[t];
+      if (t < J.class_ws.size()) {
+        w += J.class_ws[t];
+        wb += J.class_wsb[t];
+      }
     ws_max = std::max(ws_max, w);
+    wsb_max = std::max(wsb_max, wb);
   }
   for (auto& J : jobs) root_total += J.root_ws;
   ws_max = std::max(ws_max, root_total);
 
-  DevBuf ws, flagbuf;
+  DevBuf ws, wsb[2], flagbuf;
   RSRS_TRY(ws.alloc(ws_max));
+  RSRS_TRY(wsb[0].alloc(std::max<size_t>(wsb_max, 256)));
+  RSRS_TRY(wsb[1].alloc(std::max<size_t>(wsb_max, 256)));
   RSRS_TRY(flagbuf.alloc(256));
   int* flag = flagbuf.as<int>();
   RSRS_HIP(hipMemsetAsync(flag, 0, sizeof(int), st));
   Uploader up;
   RSRS_TRY(up.init((size_t)64 << 20, st));
+  // The extraction, Gauss-Jordan and sketch updates of a class run on a
+  // second stream (with its own descriptor uploads) while the main stream
+  // goes on with the next class's Gram matrices and Cholesky factorizations;
+  // the next projections wait for them (event eB), and they wait for the
+  // skeletons and the test-matrix sparsification of their class (event eA).
+  Uploader up2;   // declared first: destroyed after the side stream drains
+  SideStream side;
+  RSRS_TRY(side.init());
+  RSRS_TRY(up2.init((size_t)64 << 20, side.st));
+  const hipStream_t st2 = side.st;
   for (auto& J : jobs) {
     RSRS_HIP(hipMemcpyAsync(J.F->perm.p, J.tree().perm.data(), (size_t)J.n * 8, hipMemcpyHostToDevice, st));
     // non-finite samples are rejected up front
@@ -345,8 +401,10 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
         items.push_back(Item<T>{&J, &R, {}});
       }
     }
-    // ---- workspace
+    // ---- workspace: the part read by the extraction alternates between two
+    // buffers, the one it reads may still be in use by the previous class
     Bump bump{ws.as<char>(), 0, ws.bytes};
+    Bump bumpb{wsb[t & 1].as<char>(), 0, wsb[t & 1].bytes};
     for (auto& it : items) {
       const BoxRec& R = *it.R;
       const int k = it.J->k;
@@ -356,26 +414,30 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
       w.lp = lp;
       w.GO = bump.take<double>(l * lp); w.GP = bump.take<double>(l * lp);
       w.LO = bump.take<double>(l * lp); w.LP = bump.take<double>(l * lp);
-      w.PY = bump.take<T>(b * lp); w.WY = bump.take<T>(b * lp); w.XY = bump.take<T>(b * lp);
-      w.PZ = bump.take<T>(b * lp); w.WZ = bump.take<T>(b * lp); w.XZ = bump.take<T>(b * lp);
+      w.PY = bump.take<T>(b * lp); w.WY = bump.take<T>(b * lp);
+      w.PZ = bump.take<T>(b * lp); w.WZ = bump.take<T>(b * lp);
       w.MY = bump.take<T>(b * sld); w.MZ = bump.take<T>(b * sld);
       w.norms = bump.take<double>(2 * b); w.Rc = bump.take<double>(b * k);
-      w.XRy = bump.take<T>(r * lp); w.XRz = bump.take<T>(r * lp);
-      w.Xpy = bump.take<T>(r * lp); w.Xpz = bump.take<T>(r * lp);
-      w.gje = bump.take<double>(2 * r * r);
       w.sel = bump.take<int32_t>(b); w.piv = bump.take<int32_t>(k);
-      w.Spos = bump.take<int64_t>(k); w.Rpos = bump.take<int64_t>(b);
+      w.XY = bumpb.take<T>(b * lp); w.XZ = bumpb.take<T>(b * lp);
+      w.XRy = bumpb.take<T>(r * lp); w.XRz = bumpb.take<T>(r * lp);
+      w.Xpy = bumpb.take<T>(r * lp); w.Xpz = bumpb.take<T>(r * lp);
+      w.gje = bumpb.take<double>(2 * r * r);
+      w.Spos = bumpb.take<int64_t>(k); w.Rpos = bumpb.take<int64_t>(b);
       if constexpr (mixed) {
         w.LOt = bump.take<T>(l * lp); w.LPt = bump.take<T>(l * lp);
         w.Md = bump.take<double>(b * sld);
         w.Td = bump.take<double>(r * round_up(k, 4));
-        w.XRRd = bump.take<double>(r * r); w.Xinvd = bump.take<double>(r * r);
+        w.XRRd = bumpb.take<double>(r * r); w.Xinvd = bumpb.take<double>(r * r);
       } else {
         w.LOt = reinterpret_cast<T*>(w.LO); w.LPt = reinterpret_cast<T*>(w.LP);
         w.Md = w.Td = w.XRRd = w.Xinvd = nullptr;
       }
     }
-    if (bump.off > bump.cap) { set_error("internal: workspace overflow"); return RSRS_E_INVALID; }
+    if (bump.off > bump.cap || bumpb.off > bumpb.cap) {
+      set_error("internal: workspace overflow");
+      return RSRS_E_INVALID;
+    }
 
     // ---- phase A: Gram matrices (FP64 storage in both precisions)
     {
@@ -412,7 +474,9 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
         RSRS_TRY(copy2d<double, T>(up, st, lc));
       }
     }
-    // ---- projections (eq. nullYZ) and least-squares coefficients
+    // ---- projections (eq. nullYZ) and least-squares coefficients, once the
+    // previous class has updated the sketches
+    if (t > 0) RSRS_HIP(hipStreamWaitEvent(st, side.eB, 0));
     for (int pass = 0; pass <= 1; ++pass) {
       std::vector<GemmDescT<T, T>> gp, gw, gx, gm;
       std::vector<Copy2DT<T, T>> acc;
@@ -534,6 +598,26 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
         o2 += R.b;
       }
     }
+    // ---- test-matrix sparsification (F) on the main stream: the next
+    // class's Gram matrices read the updated rows S
+    {
+      std::vector<GemmDescT<T, T>> s1;
+      for (auto& it : items) {
+        const BoxRec& R = *it.R;
+        const Job<T>& J = *it.J;
+        const int k = J.k, s = (int)J.s;
+        const int r = (int)R.r;
+        const int64_t* gR = J.iS + R.oR;
+        const int64_t* gS = J.iS + R.oS;
+        const T* Tm = J.dS + R.oT;
+        s1.push_back(gdescT<T, T>(Tm, nullptr, R.ldT, J.Om, gR, J.sld, J.Om, gS, J.sld, k, s, r, 1.0, 1.0));
+        if (!J.sym)
+          s1.push_back(gdescT<T, T>(Tm, nullptr, R.ldT, J.Psi, gR, J.sld, J.Psi, gS, J.sld, k, s, r, 1.0, 1.0));
+      }
+      RSRS_TRY(gemm<T, T>(up, st, s1, 1, 0, GM_FULL, GS_64x64, "sparsify"));
+    }
+    RSRS_HIP(hipEventRecord(side.eA, st));
+    RSRS_HIP(hipStreamWaitEvent(st2, side.eA, 0));
     {
       std::vector<GemmDescT<T, T>> gxr;
       std::vector<ColfixDescT<T>> cf;
@@ -577,14 +661,14 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
                    sides * 2.0 * dr * dr * (dk + dn) + sides * 2.0 * 2.0 * dr * dk * ds +
                    sides * 2.0 * 2.0 * dr * (dk + dn) * ds;
       }
-      RSRS_TRY(gemm<T, T>(up, st, gxr, 0, 0, GM_FULL, GS_64x64, "extract"));
-      RSRS_TRY(colfix<T>(up, st, cf));
-      RSRS_TRY(symmetrize<T>(up, st, symx));
-      RSRS_TRY(copy2d<T, T>(up, st, cx));
-      RSRS_TRY(copy2d<T, double>(up, st, cxd));
-      RSRS_TRY(gje_inverse(up, st, gj, flag));
-      RSRS_TRY(symmetrize<double>(up, st, symi));
-      RSRS_TRY(copy2d<double, T>(up, st, cinv));
+      RSRS_TRY(gemm<T, T>(up2, st2, gxr, 0, 0, GM_FULL, GS_64x64, "extract"));
+      RSRS_TRY(colfix<T>(up2, st2, cf));
+      RSRS_TRY(symmetrize<T>(up2, st2, symx));
+      RSRS_TRY(copy2d<T, T>(up2, st2, cx));
+      RSRS_TRY(copy2d<T, double>(up2, st2, cxd));
+      RSRS_TRY(gje_inverse(up2, st2, gj, flag));
+      RSRS_TRY(symmetrize<double>(up2, st2, symi));
+      RSRS_TRY(copy2d<double, T>(up2, st2, cinv));
     }
     {
       std::vector<GemmDescT<T, T>> gku, gkl;
@@ -600,13 +684,13 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
         else
           gkl.push_back(gdescT<T, T>(w.Xpz + r, nullptr, w.lp, dS + R.oXinv, nullptr, R.ldR, dS + R.oKL, nullptr, R.ldR, kn, r, r));
       }
-      RSRS_TRY(gemm<T, T>(up, st, gku, 0, 0, GM_FULL, GS_64x64, "mult"));
-      RSRS_TRY(gemm<T, T>(up, st, gkl, 1, 0, GM_FULL, GS_64x64, "mult"));
-      RSRS_TRY(copy2d<T, T>(up, st, ktr));
+      RSRS_TRY(gemm<T, T>(up2, st2, gku, 0, 0, GM_FULL, GS_64x64, "mult"));
+      RSRS_TRY(gemm<T, T>(up2, st2, gkl, 1, 0, GM_FULL, GS_64x64, "mult"));
+      RSRS_TRY(copy2d<T, T>(up2, st2, ktr));
     }
-    // ---- sketch updates: sparsify (E, F) then eliminate (L, U)
+    // ---- sketch updates: sparsify (E) then eliminate (L, U)
     {
-      std::vector<GemmDescT<T, T>> s0, s1, e0, e1, e0b, e1b;
+      std::vector<GemmDescT<T, T>> s0, e0, e1, e0b, e1b;
       for (auto& it : items) {
         const BoxRec& R = *it.R;
         const Job<T>& J = *it.J;
@@ -621,22 +705,20 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
         const T* KL = J.dS + R.oKL;
         const int64_t lT = R.ldT, lR = R.ldR, lU = R.ldKU;
         s0.push_back(gdescT<T, T>(Tm, nullptr, lT, J.Y, gS, sld, J.Y, gR, sld, r, s, k, -1.0, 1.0));
-        s1.push_back(gdescT<T, T>(Tm, nullptr, lT, J.Om, gR, sld, J.Om, gS, sld, k, s, r, 1.0, 1.0));
         e0.push_back(gdescT<T, T>(KL, nullptr, lR, J.Y, gR, sld, J.Y, gSN, sld, kn, s, r, -1.0, 1.0));
         e0b.push_back(gdescT<T, T>(KU, nullptr, lU, J.Om, gSN, sld, J.Om, gR, sld, r, s, kn, 1.0, 1.0));
         if (J.sym) continue;   // Z = Y and Psi = Omega: nothing more to update
         s0.push_back(gdescT<T, T>(Tm, nullptr, lT, J.Z, gS, sld, J.Z, gR, sld, r, s, k, -1.0, 1.0));
-        s1.push_back(gdescT<T, T>(Tm, nullptr, lT, J.Psi, gR, sld, J.Psi, gS, sld, k, s, r, 1.0, 1.0));
         e1.push_back(gdescT<T, T>(KU, nullptr, lU, J.Z, gR, sld, J.Z, gSN, sld, kn, s, r, -1.0, 1.0));
         e1b.push_back(gdescT<T, T>(KL, nullptr, lR, J.Psi, gSN, sld, J.Psi, gR, sld, r, s, kn, 1.0, 1.0));
       }
-      RSRS_TRY(gemm<T, T>(up, st, s0, 0, 0, GM_FULL, GS_64x64, "sparsify"));
-      RSRS_TRY(gemm<T, T>(up, st, s1, 1, 0, GM_FULL, GS_64x64, "sparsify"));
-      RSRS_TRY(gemm<T, T>(up, st, e0, 0, 0, GM_FULL, GS_64x64, "elim"));
-      RSRS_TRY(gemm<T, T>(up, st, e1, 1, 0, GM_FULL, GS_64x64, "elim"));
-      RSRS_TRY(gemm<T, T>(up, st, e0b, 0, 0, GM_FULL, GS_64x64, "elim_r"));
-      RSRS_TRY(gemm<T, T>(up, st, e1b, 1, 0, GM_FULL, GS_64x64, "elim_r"));
+      RSRS_TRY(gemm<T, T>(up2, st2, s0, 0, 0, GM_FULL, GS_64x64, "sparsify"));
+      RSRS_TRY(gemm<T, T>(up2, st2, e0, 0, 0, GM_FULL, GS_64x64, "elim"));
+      RSRS_TRY(gemm<T, T>(up2, st2, e1, 1, 0, GM_FULL, GS_64x64, "elim"));
+      RSRS_TRY(gemm<T, T>(up2, st2, e0b, 0, 0, GM_FULL, GS_64x64, "elim_r"));
+      RSRS_TRY(gemm<T, T>(up2, st2, e1b, 1, 0, GM_FULL, GS_64x64, "elim_r"));
     }
+    RSRS_HIP(hipEventRecord(side.eB, st2));
     // ---- advance every job past this class
     for (auto& J : jobs) {
       if (t >= J.F->groups.size()) continue;
@@ -649,6 +731,7 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
   }
 
   // ---- roots: A_t = Y_Bt pinv(Omega_Bt), all problems in the same launches
+  if (nsteps > 0) RSRS_HIP(hipStreamWaitEvent(st, side.eB, 0));
   {
     Bump bump{ws.as<char>(), 0, ws.bytes};
     struct Root {
@@ -851,10 +934,10 @@ size_t factor_bytes_estimate(const rsrs_tree_t* th, int k, int p, int64_t s, int
   Schedule sch;
   make_schedule(t, k, sch);
   int64_t dsz = 0, isz = 0;
-  size_t ws_max = 0;
+  size_t ws_max = 0, wsb_max = 0;
   for (size_t li = 0; li < sch.levels.size(); ++li)
     for (const auto& cls : sch.classes[li]) {
-      size_t ws = 0;
+      size_t ws = 0, wsb = 0;
       for (int64_t b : cls) {
         const int64_t bb = sch.b_count[b], n = sch.l_count[b] - bb, r = bb - k;
         dsz = round_up(dsz, al) + r * round_up(k, al);
@@ -862,9 +945,14 @@ size_t factor_bytes_estimate(const rsrs_tree_t* th, int k, int p, int64_t s, int
         dsz = round_up(dsz, al) + r * round_up(k + n, al);
         dsz = round_up(dsz, al) + (k + n) * round_up(r, al);
         isz += r + k + n + bb + n;
-        ws += mixed ? box_ws_bytes<float>(bb, bb + n, k, sld) : box_ws_bytes<double>(bb, bb + n, k, sld);
+        size_t wa = 0, wb = 0;
+        if (mixed) box_ws_bytes<float>(bb, bb + n, k, sld, &wa, &wb);
+        else box_ws_bytes<double>(bb, bb + n, k, sld, &wa, &wb);
+        ws += wa;
+        wsb += wb;
       }
       ws_max = std::max(ws_max, ws);
+      wsb_max = std::max(wsb_max, wsb);
     }
   const int64_t nt = sch.root_count;
   dsz = round_up(dsz, al) + 2 * nt * nt;
@@ -874,7 +962,7 @@ size_t factor_bytes_estimate(const rsrs_tree_t* th, int k, int p, int64_t s, int
   ws_max = std::max(ws_max, root_ws);
   const size_t st = (size_t)dsz * esz + (size_t)isz * 8 + (size_t)t.n * 8;
   if (stored) *stored = st;
-  return st + ws_max + ((size_t)64 << 20);
+  return st + ws_max + 2 * std::max<size_t>(wsb_max, 256) + ((size_t)128 << 20);
 }
 
 }  // namespace rsrs
