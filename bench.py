@@ -179,22 +179,29 @@ def by_kernel(prof: dict) -> dict:
     return out
 
 
-# rocprof kernel names of the measured forms (tag -> template instantiation)
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_f64_128x128_nn_65k_log2d_traffic.json")
-TAG_TO_KERNEL = {"gemm_nn_full_128x128":
-                 "void rsrs::gemm_f64_kernel<128, 128, 2, 4, 0, 0, 0, 2>(rsrs::GemmDesc const*)"}
+# HBM traffic measured by rocprofv3 counters for the kernels that can be the
+# dominant one: tag -> committed summary (kernel name, bytes per launch and
+# the hash of the source the kernel was built from when measured)
+TRAFFIC_FILES = {
+    "id_step": os.path.join(ROOT, "profiles", "id_step_65k_log2d_mixed_traffic.json"),
+    "gemm_nn_full_128x128": os.path.join(ROOT, "profiles", "gemm_f64_nn_128x128_65k_log2d_fp64_traffic.json"),
+}
+# machine balance of MI355X in FP64 (flops per HBM byte): below it a kernel
+# is priced against HBM bandwidth
+MACHINE_BALANCE = 78.6e12 / 8.0e12
 
 
 def measured_traffic(tag: str):
     """HBM bytes per launch from the committed counter summary, or None when
-    the kernel differs or its source changed since the counters were taken."""
+    there is none for this kernel or its source changed since."""
     import hashlib
+    path = TRAFFIC_FILES.get(tag)
+    if not path:
+        return None
     try:
-        t = json.load(open(TRAFFIC_FILE))
+        t = json.load(open(path))
         src = open(os.path.join(ROOT, t["source"]), "rb").read()
     except (OSError, ValueError, KeyError):
-        return None
-    if TAG_TO_KERNEL.get(tag) != t.get("kernel"):
         return None
     if hashlib.sha256(src).hexdigest() != t.get("source_sha256"):
         return None
@@ -205,8 +212,8 @@ def roofline_from_profile(prof: dict, prof_all: dict, steps: int) -> dict | None
     """Roofline of the kernel with the largest share of GPU time in the
     profiled step, from its launches in the timed steps (HIP events on the
     launch stream).  GEMM forms run on MFMA (peak of their operand type);
-    other kernels with a flop count are plain FP64 vector arithmetic; the
-    rest are priced by their algorithmic bytes against HBM."""
+    kernels whose algorithmic flops per byte fall below the machine balance
+    are priced by their bytes against HBM; the rest are FP64 vector work."""
     if not prof or not prof_all:
         return None
     prof, prof_all = by_kernel(prof), by_kernel(prof_all)
@@ -214,7 +221,8 @@ def roofline_from_profile(prof: dict, prof_all: dict, steps: int) -> dict | None
     if tag not in prof:
         return None
     e = prof[tag]
-    if e["flops"] > 0:
+    streaming = e["bytes"] > 0 and e["flops"] < MACHINE_BALANCE * e["bytes"]
+    if tag.startswith("gemm") or (e["flops"] > 0 and not streaming):
         ach = e["flops"] / (e["ms"] * 1e-3) / 1e12
         if tag.startswith("gemm_bf16"):
             bound, peak = "mfma", PEAK_BF16_TFLOPS

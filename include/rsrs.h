@@ -302,7 +302,7 @@ rsrs_status rsrs_factor_root_copy(const rsrs_factor_t* f, int64_t* nt, int64_t* 
 rsrs_status rsrs_solve(const rsrs_factor_t* f, int transpose, int64_t nrhs, const double* F,
                        int64_t ldf, double* U, int64_t ldu, void* stream);
 /* Solves and applies of up to 1024 columns replay a HIP graph of the
- * factor's launch sequence, captured at the first call for each operation
+ * factor's launch sequence, assembled at the first call for each operation
  * and width bucket (16, 32, ..., 1024; narrower blocks are padded with zero
  * columns, which leave the others unchanged); the factor then keeps the
  * graph, its descriptors and work blocks of n x bucket elements (twice)

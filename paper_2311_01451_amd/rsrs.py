@@ -498,7 +498,7 @@ def rsrs_solve(f: Factor, F, transpose=False, out=None, stream=None):
 
 
 def rsrs_solve_graphs(on: bool = True):
-    """Replay captured HIP graphs for solves of up to 1024 columns (default on)."""
+    """Replay HIP graphs for solves of up to 1024 columns (default on)."""
     lib().rsrs_solve_graphs(int(on))
 
 

@@ -1,4 +1,4 @@
-"""GPU: solves replayed from captured HIP graphs equal direct launches.
+"""GPU: solves replayed from HIP graphs equal direct launches.
 
 Each graph replay is checked against the direct result, several times in a
 row with other work and synchronisations in between, for FP64 and mixed
