@@ -2,15 +2,19 @@
 // (the Gram matrices of the nullification step, eq. nullYZ, are factored so
 // that C^T G^{-1} becomes two triangular products).
 //
-// Right-looking by panels of 64 columns, two launches per panel:
+// Right-looking by panels of 64 columns with the trailing update deferred
+// over super-panels of four panels:
 //
+//   column j  (panels after the first of a super-panel) the column block j
+//             receives the earlier panels of its super-panel (narrow GEMM).
 //   panel j   one workgroup per (matrix, four 64-row blocks i >= j).  Each
 //             workgroup factors the diagonal block G_jj itself (so no
 //             workgroup waits for another), forms X_jj = L_jj^{-1}, and
 //             computes its blocks L_ij = G_ij X_jj^T; the workgroup holding
 //             i = j stores X_jj.
-//   update j  G_22 -= L_21 L_21^T on the trailing lower triangle (batched
-//             SYRK on the MFMA GEMM).
+//   trailing  after the last panel of a super-panel, G_22 -= L_21 L_21^T on
+//             the trailing lower triangle with the super-panel's 256 columns
+//             (batched SYRK on the MFMA GEMM).
 //
 // Inside a panel the 64 x 64 diagonal block is factored in eight steps of
 // 8 columns: the 64 lanes of one wave (one per row) each factor the 8 x 8
@@ -302,36 +306,60 @@ rsrs_status chol_inverse(Uploader& up, hipStream_t st, const std::vector<CholMat
   for (const auto& m : mats) nmax = std::max(nmax, m.n);
   if (nmax <= 0) return RSRS_OK;
   const int P = (nmax + PB - 1) / PB;
-  // ---- every launch's descriptors, built up front and uploaded together
+  // ---- every launch's descriptors, built up front and uploaded together.
+  // Trailing updates are deferred over super-panels of SP panels: before
+  // panel j only its own column block receives the earlier panels of the
+  // super-panel (a narrow GEMM), and after the last panel of a super-panel
+  // the trailing matrix receives all of them at once (a SYRK with K = 64 SP),
+  // which reads and writes the trailing matrix SP times less often.
+  constexpr int SP = 4;
   std::vector<CholPanel> tasks;
   std::vector<size_t> toff(P + 1);
   std::vector<double> pflops(P, 0.0);
-  std::vector<GemmDesc> upd;
-  std::vector<size_t> uoff(P + 1);
+  std::vector<GemmDesc> colu, trail;
+  std::vector<size_t> coff(P + 1), soff(P + 1);
   for (int j = 0; j < P; ++j) {
+    const int j0s = SP * (j / SP);
+    const bool last_of_sp = (j % SP == SP - 1);
     toff[j] = tasks.size();
-    uoff[j] = upd.size();
+    coff[j] = colu.size();
+    soff[j] = trail.size();
     for (const auto& m : mats) {
       const int Pm = (m.n + PB - 1) / PB;
       if (j >= Pm) continue;
+      const int rows = m.n - PB * j;
+      if (j > j0s) {
+        // column block j -= L[rows >= 64 j, panels j0s..j-1] L[block j, same]^T
+        double* Lr = m.G + (int64_t)PB * j * m.ld + PB * j0s;
+        double* Cj = m.G + (int64_t)PB * j * (m.ld + 1);
+        colu.push_back(gdesc(Lr, nullptr, m.ld, Lr, nullptr, m.ld, Cj, nullptr, m.ld, rows,
+                             std::min(PB, rows), PB * (j - j0s), -1.0, 1.0));
+      }
       for (int ib = j; ib < Pm; ib += RB) tasks.push_back(CholPanel{m.G, m.W, m.ld, m.n, j, ib, std::min(ib + RB, Pm)});
-      const double nj = std::min(PB, m.n - PB * j), below = m.n - PB * j - nj;
+      const double nj = std::min(PB, rows), below = rows - nj;
       pflops[j] += (2.0 / 3.0) * nj * nj * nj + below * nj * nj;
-      const int rows = m.n - PB * (j + 1);
-      if (rows > 0) {
-        double* Lj = m.G + (int64_t)PB * (j + 1) * m.ld + PB * j;
+      const int trows = m.n - PB * (j + 1);
+      if (trows > 0 && (last_of_sp || j == Pm - 1)) {
+        double* Ls = m.G + (int64_t)PB * (j + 1) * m.ld + PB * j0s;
         double* G22 = m.G + (int64_t)PB * (j + 1) * (m.ld + 1);
-        upd.push_back(gdesc(Lj, nullptr, m.ld, Lj, nullptr, m.ld, G22, nullptr, m.ld, rows, rows, PB, -1.0, 1.0));
+        trail.push_back(gdesc(Ls, nullptr, m.ld, Ls, nullptr, m.ld, G22, nullptr, m.ld, trows, trows,
+                              PB * (j + 1 - j0s), -1.0, 1.0));
       }
     }
   }
   toff[P] = tasks.size();
-  uoff[P] = upd.size();
-  std::vector<std::vector<GemmLaunch>> ul(P);
+  coff[P] = colu.size();
+  soff[P] = trail.size();
+  std::vector<std::vector<GemmLaunch>> cl(P), tl(P);
   for (int j = 0; j < P; ++j) {
-    if (uoff[j + 1] == uoff[j]) continue;
-    std::vector<GemmDesc> part(upd.begin() + uoff[j], upd.begin() + uoff[j + 1]);
-    RSRS_TRY(gemm_plan<double, double>(part, uoff[j], 0, 1, GM_SYRK_L, GS_64x64, "chol", ul[j]));
+    if (coff[j + 1] > coff[j]) {
+      std::vector<GemmDesc> part(colu.begin() + coff[j], colu.begin() + coff[j + 1]);
+      RSRS_TRY(gemm_plan<double, double>(part, coff[j], 0, 1, GM_FULL, GS_64x64_ONLY, "chol", cl[j]));
+    }
+    if (soff[j + 1] > soff[j]) {
+      std::vector<GemmDesc> part(trail.begin() + soff[j], trail.begin() + soff[j + 1]);
+      RSRS_TRY(gemm_plan<double, double>(part, soff[j], 0, 1, GM_SYRK_L, GS_64x64, "chol", tl[j]));
+    }
   }
   // diagonal inverses into G, then the doubling levels
   std::vector<Copy2D> diag;
@@ -365,20 +393,23 @@ rsrs_status chol_inverse(Uploader& up, hipStream_t st, const std::vector<CholMat
     inv.insert(inv.end(), x.begin(), x.end());
   }
   CholPanel* dt = nullptr;
-  GemmDesc* du = nullptr;
+  GemmDesc* dc = nullptr;
+  GemmDesc* ds = nullptr;
   GemmDesc* di = nullptr;
   RSRS_TRY(up.put_vec(tasks, &dt));
-  if (!upd.empty()) RSRS_TRY(up.put_vec(upd, &du));
+  if (!colu.empty()) RSRS_TRY(up.put_vec(colu, &dc));
+  if (!trail.empty()) RSRS_TRY(up.put_vec(trail, &ds));
   if (!inv.empty()) RSRS_TRY(up.put_vec(inv, &di));
   // ---- launches
   for (int j = 0; j < P; ++j) {
+    for (const auto& L : cl[j]) RSRS_TRY(gemm_exec(L, dc, sizeof(GemmDesc), st));
     const unsigned nt = (unsigned)(toff[j + 1] - toff[j]);
     {
       ProfScope ps(st, "chol_panel", pflops[j], 0.0);
       hipLaunchKernelGGL(chol_panel_kernel, dim3(nt), dim3(256), 0, st, dt + toff[j], flag);
       RSRS_HIP(hipGetLastError());
     }
-    for (const auto& L : ul[j]) RSRS_TRY(gemm_exec(L, du, sizeof(GemmDesc), st));
+    for (const auto& L : tl[j]) RSRS_TRY(gemm_exec(L, ds, sizeof(GemmDesc), st));
   }
   RSRS_TRY(copy2d<double, double>(up, st, diag));
   for (const auto& lv : il)

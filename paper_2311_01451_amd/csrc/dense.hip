@@ -177,6 +177,7 @@ rsrs_status gemm_plan(const std::vector<GemmDescT<TI, TO>>& descs, size_t base, 
   if constexpr (std::is_same<TI, TO>::value) {
     if (shape == GS_64x16 && mode == GM_FULL) return plan_forms<TI, TO, 64, 16, 4, 1>(descs, base, ta, tb, mode, out);
   }
+  if (shape == GS_64x64_ONLY) return plan_forms<TI, TO, 64, 64, 2, 2>(descs, base, ta, tb, mode, out);
   int64_t t128 = 0;
   for (const auto& d : descs) {
     if (d.M <= 0 || d.N <= 0) continue;

@@ -31,7 +31,9 @@ struct Uploader {
 };
 
 // ---- GEMM (gemm.hpp) -------------------------------------------------------
-enum GemmShape { GS_64x64 = 0, GS_64x16 = 1 };
+// GS_64x64: 64 x 64 tiles, or 128 x 128 when the launch has >= 256 of those;
+// GS_64x64_ONLY: always 64 x 64 (narrow outputs); GS_64x16: narrow solves.
+enum GemmShape { GS_64x64 = 0, GS_64x16 = 1, GS_64x64_ONLY = 2 };
 // `site` (optional) is appended to the measurement tag ("gemm_<form>:<site>").
 // A batched product split into launch records: kernel, grid, and the first
 // descriptor (index into the caller's concatenated descriptor array) it reads.
