@@ -38,9 +38,12 @@
 // operands runs on FP32 MFMA with FP32 accumulation, while the decisions stay
 // FP64: the Gram matrices are accumulated from FP32 operands straight into
 // FP64 storage and factored (Cholesky, inverse factor) in FP64, the pivoted
-// QR of the ID runs on an FP64 copy of M, and X_RR and A_t are inverted by
-// FP64 Gauss-Jordan with partial pivoting; the results are rounded to FP32
-// for the products that use them.
+// QR of the ID takes its dot products, norms and coefficients in FP64 (the
+// working rows of M stay FP32, like the sketches they come from: each
+// stored residual is rounded relative to its own size, far below the
+// rounding M already carries), and X_RR and A_t are inverted by FP64
+// Gauss-Jordan with partial pivoting; the results are rounded to FP32 for
+// the products that use them.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -107,8 +110,7 @@ void box_ws_bytes(int64_t b, int64_t l, int64_t k, int64_t sp, size_t* a, size_t
   int64_t telB = 2 * b * lp        // X for both sides
                  + 4 * r * lp;     // XR, Xp for both sides
   if (mixed) {
-    dblA += b * sp                 // FP64 copy of M for the ID
-            + r * round_up(k, 4);  // T as computed by the ID
+    dblA += r * round_up(k, 4);    // T as computed by the ID
     dblB += 2 * r * r;             // X_RR and its inverse in FP64
     telA += 2 * l * lp;            // rounded inverse factors
   }
@@ -125,7 +127,7 @@ struct BoxWs {
   T *LOt, *LPt;                 // inverse factors in T (alias LO, LP when T = double)
   T *PY, *WY, *XY, *PZ, *WZ, *XZ, *MY, *MZ;
   T *XRy, *XRz, *Xpy, *Xpz;
-  double *Md, *Td, *XRRd, *Xinvd;   // FP64 copies (mixed precision only)
+  double *Td, *XRRd, *Xinvd;   // FP64 copies (mixed precision only)
   int32_t *sel, *piv;
   int64_t *Spos, *Rpos;
 };
@@ -426,12 +428,11 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
       w.Spos = bumpb.take<int64_t>(k); w.Rpos = bumpb.take<int64_t>(b);
       if constexpr (mixed) {
         w.LOt = bump.take<T>(l * lp); w.LPt = bump.take<T>(l * lp);
-        w.Md = bump.take<double>(b * sld);
         w.Td = bump.take<double>(r * round_up(k, 4));
         w.XRRd = bumpb.take<double>(r * r); w.Xinvd = bumpb.take<double>(r * r);
       } else {
         w.LOt = reinterpret_cast<T*>(w.LO); w.LPt = reinterpret_cast<T*>(w.LP);
-        w.Md = w.Td = w.XRRd = w.Xinvd = nullptr;
+        w.Td = w.XRRd = w.Xinvd = nullptr;
       }
     }
     if (bump.off > bump.cap || bumpb.off > bumpb.cap) {
@@ -528,13 +529,12 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
         const Job<T>& J = *it.J;
         const BoxWs<T>& w = it.w;
         IdDesc e{};
-        // symmetric variant: M = M_Y (the ID of 2 M_Y is the same)
+        // symmetric variant: M = M_Y (the ID of 2 M_Y is the same).  The
+        // working rows keep the sketches' type; the pivoting is FP64.
+        e.M = w.MY; e.MZ = J.sym ? nullptr : w.MZ; e.ldm = J.sld; e.ldz = J.sld;
         if constexpr (mixed) {
-          e.M = w.Md; e.MZ = nullptr; e.ldm = J.sld; e.ldz = J.sld;
-          e.MYf = w.MY; e.MZf = J.sym ? nullptr : w.MZ; e.ldf = J.sld;
           e.T = w.Td; e.ldt = (int)round_up(J.k, 4);
         } else {
-          e.M = w.MY; e.MZ = J.sym ? nullptr : w.MZ; e.ldm = J.sld; e.ldz = J.sld;
           e.T = J.dS + R.oT; e.ldt = (int)R.ldT;
         }
         e.norms = w.norms; e.sel = w.sel; e.Rc = w.Rc; e.piv = w.piv;
@@ -543,7 +543,7 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
         idd.push_back(e);
         it.J->flops += 4.0 * R.b * J.s * J.k;
       }
-      RSRS_TRY(id_run(up, st, idd));
+      RSRS_TRY(id_run(up, st, idd, mixed));
       if constexpr (mixed) {   // T rounded into the factor store
         std::vector<Copy2DT<double, T>> tc;
         for (auto& it : items) {

@@ -30,30 +30,21 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+template <typename S>
 __global__ __launch_bounds__(64) void id_init_kernel(const IdDesc* __restrict__ e) {
   const IdDesc d = e[blockIdx.y];
   const int i = blockIdx.x;
   if (i >= d.b) return;
-  double* mi = d.M + (int64_t)i * d.ldm;
+  S* mi = static_cast<S*>(d.M) + (int64_t)i * d.ldm;
+  const S* mz = d.MZ ? static_cast<const S*>(d.MZ) + (int64_t)i * d.ldz : nullptr;
   double s = 0.0;
-  if (d.MYf) {
-    const float* fy = d.MYf + (int64_t)i * d.ldf;
-    const float* fz = d.MZf ? d.MZf + (int64_t)i * d.ldf : nullptr;
-    for (int c = threadIdx.x; c < d.s; c += 64) {
-      double v = (double)fy[c];
-      if (fz) v += (double)fz[c];
+  for (int c = threadIdx.x; c < d.s; c += 64) {
+    S v = mi[c];
+    if (mz) {
+      v = (S)((double)v + (double)mz[c]);
       mi[c] = v;
-      s += v * v;
     }
-  } else {
-    for (int c = threadIdx.x; c < d.s; c += 64) {
-      double v = mi[c];
-      if (d.MZ) {
-        v += d.MZ[(int64_t)i * d.ldz + c];
-        mi[c] = v;
-      }
-      s += v * v;
-    }
+    s += (double)v * (double)v;
   }
   s = wave_sum(s);
   if (threadIdx.x == 0) {
@@ -62,6 +53,7 @@ __global__ __launch_bounds__(64) void id_init_kernel(const IdDesc* __restrict__ 
   }
 }
 
+template <typename S>
 __global__ __launch_bounds__(64) void id_step_kernel(const IdDesc* __restrict__ e, int j) {
   const IdDesc d = e[blockIdx.y];
   const int i = blockIdx.x;
@@ -97,17 +89,17 @@ __global__ __launch_bounds__(64) void id_step_kernel(const IdDesc* __restrict__ 
     return;
   }
   if (d.sel[i] < j) return;  // selected at an earlier step
-  double* mi = d.M + (int64_t)i * d.ldm;
-  const double* mp = d.M + (int64_t)p * d.ldm;
+  S* mi = static_cast<S*>(d.M) + (int64_t)i * d.ldm;
+  const S* mp = static_cast<const S*>(d.M) + (int64_t)p * d.ldm;
   double dot = 0.0;
-  for (int c = lane; c < d.s; c += 64) dot += mi[c] * mp[c];
+  for (int c = lane; c < d.s; c += 64) dot += (double)mi[c] * (double)mp[c];
   dot = wave_sum(dot);
   const double coef = pn2 > 0.0 ? dot / pn2 : 0.0;
   double s = 0.0;
   for (int c = lane; c < d.s; c += 64) {
-    const double v = mi[c] - coef * mp[c];
+    const S v = (S)((double)mi[c] - coef * (double)mp[c]);
     mi[c] = v;
-    s += v * v;
+    s += (double)v * (double)v;
   }
   s = wave_sum(s);
   if (lane == 0) {
@@ -121,18 +113,22 @@ __global__ __launch_bounds__(64) void id_step_kernel(const IdDesc* __restrict__ 
 // instead of two passes over both.  Four rows per workgroup (one per wave);
 // the row is requested before the pivot search so that its load overlaps
 // the search, and the search itself loads all candidates at once.
-template <int R>
+template <typename S, int R>
 __global__ __launch_bounds__(256) void id_step_reg_kernel(const IdDesc* __restrict__ e, int j) {
   const IdDesc d = e[blockIdx.y];
   const int lane = threadIdx.x & 63;
   const int i = 4 * blockIdx.x + (threadIdx.x >> 6);
   if (i >= d.b || j >= d.k) return;
-  double* mi = d.M + (int64_t)i * d.ldm;
-  double ri[R];
+  // rows are kept in their storage type (converted to FP64 where used) and
+  // loaded unconditionally from a clamped column, so that all loads are in
+  // flight at once
+  S* mi = static_cast<S*>(d.M) + (int64_t)i * d.ldm;
+  S ri[R];
 #pragma unroll
   for (int u = 0; u < R; ++u) {
     const int c = lane + 64 * u;
-    ri[u] = c < d.s ? mi[c] : 0.0;
+    const S v = mi[min(c, d.s - 1)];
+    ri[u] = c < d.s ? v : S(0);
   }
   const double* cur = d.norms + (j & 1) * d.b;
   double* nxt = d.norms + ((j + 1) & 1) * d.b;
@@ -177,25 +173,26 @@ __global__ __launch_bounds__(256) void id_step_reg_kernel(const IdDesc* __restri
     return;
   }
   if (d.sel[i] < j) return;
-  const double* mp = d.M + (int64_t)p * d.ldm;
-  double rp[R];
+  const S* mp = static_cast<const S*>(d.M) + (int64_t)p * d.ldm;
+  S rp[R];
   double dot = 0.0;
 #pragma unroll
   for (int u = 0; u < R; ++u) {
     const int c = lane + 64 * u;
-    rp[u] = c < d.s ? mp[c] : 0.0;
+    const S v = mp[min(c, d.s - 1)];
+    rp[u] = c < d.s ? v : S(0);
   }
 #pragma unroll
-  for (int u = 0; u < R; ++u) dot += ri[u] * rp[u];
+  for (int u = 0; u < R; ++u) dot += (double)ri[u] * (double)rp[u];
   dot = wave_sum(dot);
   const double coef = pn2 > 0.0 ? dot / pn2 : 0.0;
   double s = 0.0;
 #pragma unroll
   for (int u = 0; u < R; ++u) {
     const int c = lane + 64 * u;
-    const double v = ri[u] - coef * rp[u];
+    const S v = (S)((double)ri[u] - coef * (double)rp[u]);   // the norm is that of the stored row
     if (c < d.s) mi[c] = v;
-    s += c < d.s ? v * v : 0.0;
+    s += c < d.s ? (double)v * (double)v : 0.0;
   }
   s = wave_sum(s);
   if (lane == 0) {
@@ -296,7 +293,29 @@ __global__ __launch_bounds__(256) void id_finalize_kernel(const IdDesc* __restri
   }
 }
 
-rsrs_status id_run(Uploader& up, hipStream_t st, const std::vector<IdDesc>& e) {
+template <typename S>
+static void id_launch(hipStream_t st, const IdDesc* de, unsigned nb, int bmax, int kmax, int smax, double fstep,
+                      double bstep) {
+  {
+    ProfScope ps(st, "id_init", 0.0, bstep);
+    hipLaunchKernelGGL(id_init_kernel<S>, dim3((unsigned)bmax, nb), dim3(64), 0, st, de);
+  }
+  // register variant when every row fits (the summation order of the dot
+  // product and norm is then fixed by the lane layout, the same for all s)
+  const int nchunk = (smax + 63) / 64;
+  for (int j = 0; j < kmax; ++j) {
+    ProfScope ps(st, "id_step", fstep, bstep);
+    const unsigned g4 = (unsigned)((bmax + 3) / 4);
+    if (nchunk <= 16)
+      hipLaunchKernelGGL((id_step_reg_kernel<S, 16>), dim3(g4, nb), dim3(256), 0, st, de, j);
+    else if (nchunk <= 40)
+      hipLaunchKernelGGL((id_step_reg_kernel<S, 40>), dim3(g4, nb), dim3(256), 0, st, de, j);
+    else
+      hipLaunchKernelGGL(id_step_kernel<S>, dim3((unsigned)bmax, nb), dim3(64), 0, st, de, j);
+  }
+}
+
+rsrs_status id_run(Uploader& up, hipStream_t st, const std::vector<IdDesc>& e, bool fp32) {
   if (e.empty()) return RSRS_OK;
   int bmax = 0, kmax = 0, smax = 0;
   for (const auto& x : e) {
@@ -311,28 +330,14 @@ rsrs_status id_run(Uploader& up, hipStream_t st, const std::vector<IdDesc>& e) {
   IdDesc* de = nullptr;
   RSRS_TRY(up.put_vec(e, &de));
   const unsigned nb = (unsigned)e.size();
+  const double esz = fp32 ? 4.0 : 8.0;
   double fstep = 0.0, bstep = 0.0;
   for (const auto& x : e) {
     fstep += 4.0 * x.b * x.s;
-    bstep += 16.0 * x.b * x.s;
+    bstep += 2.0 * esz * x.b * x.s;   // read and write every row
   }
-  {
-    ProfScope ps(st, "id_init", 0.0, bstep);
-    hipLaunchKernelGGL(id_init_kernel, dim3((unsigned)bmax, nb), dim3(64), 0, st, de);
-  }
-  // register variant when every row fits (the summation order of the dot
-  // product and norm is then fixed by the lane layout, the same for all s)
-  const int nchunk = (smax + 63) / 64;
-  for (int j = 0; j < kmax; ++j) {
-    ProfScope ps(st, "id_step", fstep, bstep);
-    const unsigned g4 = (unsigned)((bmax + 3) / 4);
-    if (nchunk <= 16)
-      hipLaunchKernelGGL(id_step_reg_kernel<16>, dim3(g4, nb), dim3(256), 0, st, de, j);
-    else if (nchunk <= 40)
-      hipLaunchKernelGGL(id_step_reg_kernel<40>, dim3(g4, nb), dim3(256), 0, st, de, j);
-    else
-      hipLaunchKernelGGL(id_step_kernel, dim3((unsigned)bmax, nb), dim3(64), 0, st, de, j);
-  }
+  if (fp32) id_launch<float>(st, de, nb, bmax, kmax, smax, fstep, bstep);
+  else id_launch<double>(st, de, nb, bmax, kmax, smax, fstep, bstep);
   {
     ProfScope ps(st, "id_finalize");
     hipLaunchKernelGGL(id_finalize_kernel, dim3(nb), dim3(256), 0, st, de);

@@ -143,13 +143,12 @@ void sub2d(hipStream_t st, const double* f, int64_t ldf, const double* y, int64_
 
 // ---- interpolative decomposition (id.hip) ---------------------------------
 struct IdDesc {
-  double* M;          // b x s (the Y-side projection; the Z side is added in id_init)
-  const double* MZ;   // b x s or null
-  // FP32 sources: when MYf is set, id_init writes M = MYf (+ MZf) in FP64
-  // (leading dimension ldf) and MZ is ignored; the pivoting runs in FP64.
-  const float* MYf;
-  const float* MZf;
-  int64_t ldf;
+  // Working rows, b x s, FP64 or FP32 storage (all descriptors of one call
+  // alike): the Y-side projection, overwritten by the residuals; MZ (same
+  // type, or null) is added to it by the first launch.  Dot products, norms
+  // and coefficients are FP64 in both cases.
+  void* M;
+  const void* MZ;
   int64_t ldm, ldz;
   double* norms;      // 2*b
   int32_t* sel;       // b
@@ -160,7 +159,8 @@ struct IdDesc {
   double* T;          // (b-k) x k, row-major, leading dimension ldt
   int b, s, k, ldt;
 };
-rsrs_status id_run(Uploader& up, hipStream_t st, const std::vector<IdDesc>& e);
+// fp32: the working rows are FP32 (otherwise FP64).
+rsrs_status id_run(Uploader& up, hipStream_t st, const std::vector<IdDesc>& e, bool fp32);
 
 template <typename T>
 struct ColfixDescT {
