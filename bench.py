@@ -54,12 +54,13 @@ NRHS = 16
 TOL = 1e-6
 
 
-def workload_config(s_req: int, s_eff: int) -> dict:
+def workload_config(s_req: int, s_eff: int, reproject: int) -> dict:
     return {"workload": f"2D log-kernel operator on a {GRID_N}x{GRID_N} grid (N={GRID_N**2}), "
                         f"quadtree leaf {LEAF}, k=p={K}, {NRHS} RHS, residual <= {TOL:g} "
                         "(FP64 residual), mixed precision vs FP64",
             "N": GRID_N ** 2, "leaf": LEAF, "k": K, "p": K, "s_configured": S_CFG,
             "s_required": s_req, "s": s_eff, "nrhs": NRHS, "tol": TOL,
+            "projection_passes": 1 + reproject,
             "precision": "mixed: BF16 sample products (FP32 accumulation), FP32 sketches and MFMA "
                          "products in the factorization, FP64 Cholesky, pivoted QR, Gauss-Jordan "
                          "and residuals; FP64 beside it",
@@ -69,7 +70,7 @@ def workload_config(s_req: int, s_eff: int) -> dict:
 
 def gpu_bench(steps: int, warmup: int, do_profile: bool, latency_reps: int = 40,
               calib_copy_mib: int = 0, mode: str = "fp64", ctx: dict | None = None,
-              symmetric: bool = True):
+              symmetric: bool = True, reproject: int = 0):
     import torch
     from paper_2311_01451_amd import inputs, rsrs
 
@@ -105,7 +106,7 @@ def gpu_bench(steps: int, warmup: int, do_profile: bool, latency_reps: int = 40,
         smp = rsrs.rsrs_sample(tree, op, s_eff, inputs.BASE_SEED, dtype=dtype, symmetric=symmetric)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        F = rsrs.rsrs_factor(tree, smp, K, precision=prec, symmetric=symmetric)
+        F = rsrs.rsrs_factor(tree, smp, K, precision=prec, symmetric=symmetric, reproject=reproject)
         torch.cuda.synchronize()
         t3 = time.perf_counter()
         u, rel, it = rsrs.rsrs_solve_refine(F, op, f, tol=TOL, maxit=30)
@@ -492,6 +493,9 @@ def main():
     ap.add_argument("--latency-reps", type=int, default=40)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run a plain device copy of this size first (counter calibration)")
+    ap.add_argument("--reproject", type=int, default=0, choices=(0, 1),
+                    help="second projection pass in the factorization (the refinement reaches "
+                         "the tolerance in one step either way)")
     ap.add_argument("--modes", default="mixed,mixed_general,fp64,fp64_general",
                     help="comma list of the precision/variant runs (the first is the headline)")
     ap.add_argument("--serving", type=float, default=0.0,
@@ -516,7 +520,7 @@ def main():
         if name not in want:
             continue
         runs[name] = gpu_bench(a.steps, a.warmup, not a.no_profile, a.latency_reps,
-                               a.calib_copy_mib if name == "mixed" else 0, mode, ctx, sym)
+                               a.calib_copy_mib if name == "mixed" else 0, mode, ctx, sym, a.reproject)
     def summary(rec, elapsed, profs, lat, steps):
         prof, prof_all = profs
         return {
@@ -559,7 +563,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": workload_config(s_req, s_eff),
+        "config": workload_config(s_req, s_eff, a.reproject),
     }
     out.update({k: v for k, v in sm.items() if k not in ("value", "ms_per_step")})
     for name in ("mixed_general", "fp64", "fp64_general"):

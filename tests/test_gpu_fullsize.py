@@ -118,7 +118,11 @@ def test_fullsize_first_class_boxes_and_refinement(symmetric):
     assert rel <= 1e-10
 
 
-def test_fullsize_mixed_bf16_reaches_1e6():
+@pytest.mark.parametrize("reproject", [1, 0])
+def test_fullsize_mixed_bf16_reaches_1e6(reproject):
+    """The benchmark's configuration: mixed precision, symmetric variant, with
+    and without the second projection pass; one refinement step must reach
+    the tolerance from the one-shot residual either way."""
     need_gpu()
     pts = inputs.grid2d(N_GRID)
     N = N_GRID ** 2
@@ -126,8 +130,11 @@ def test_fullsize_mixed_bf16_reaches_1e6():
     tc = rsrs.rsrs_build_tree(pts, LEAF)
     s = tc.samples_required(K, K)
     smp = rsrs.rsrs_sample(tc, op, s, inputs.BASE_SEED, dtype=rsrs.RSRS_BF16, symmetric=True)
-    F = rsrs.rsrs_factor(tc, smp, K, precision=rsrs.RSRS_PREC_F32_MIXED, symmetric=True)
+    F = rsrs.rsrs_factor(tc, smp, K, precision=rsrs.RSRS_PREC_F32_MIXED, symmetric=True, reproject=reproject)
     f = torch.tensor(inputs.rhs(N, 16), dtype=torch.float64, device="cuda")
+    r = f - op.matvec(F.solve(f))
+    one = float((r.norm(dim=0) / f.norm(dim=0)).max())
     u, rel, it = rsrs.rsrs_solve_refine(F, op, f, tol=1e-6, maxit=10)
-    print(f"[fullsize mixed] residual {rel:.2e} after {it}", flush=True)
-    assert rel <= 1e-6
+    print(f"[fullsize mixed, reproject={reproject}] one-shot {one:.2e}, residual {rel:.2e} after {it}", flush=True)
+    assert one <= (1e-4 if reproject else 1e-3)
+    assert rel <= 1e-6 and it <= 1
