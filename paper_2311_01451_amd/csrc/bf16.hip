@@ -149,6 +149,113 @@ __global__ __launch_bounds__(NT) void gemm_bf16_nt_kernel(Bf16Desc d) {
     }
 }
 
+// The same product on 256 x 256 tiles: 8 waves as 2 x 4, each wave 128 x 64
+// (8 x 4 MFMA tiles), so that every fragment read from LDS feeds 4 or 8
+// MFMAs; LDS traffic per MFMA is half that of the 128 x 128 form, about the
+// MFMA time itself.  Double-buffered LDS (144 KiB: one workgroup per CU),
+// next slice prefetched into registers, XCD-aware tile order.
+constexpr int WBM = 256, WBN = 256;
+
+__global__ __launch_bounds__(NT) void gemm_bf16_nt256_kernel(Bf16Desc d) {
+  __shared__ __attribute__((aligned(16))) uint16_t lds[2 * (WBM + WBN) * LDR];
+  uint16_t* As0 = lds;
+  uint16_t* Bs0 = lds + 2 * WBM * LDR;
+  const int tm = (d.M + WBM - 1) / WBM, tn = (d.N + WBN - 1) / WBN;
+  const int per = gridDim.x >> 3;
+  const int t = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (t >= tm * tn) return;
+  const int m0 = (t / tn) * WBM, n0 = (t % tn) * WBN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 2, wn = wave & 3;   // 2 x 4 waves, each 128 x 64
+  const int q = lane >> 4, c16 = lane & 15;
+
+  // fetch mapping: 4 chunks of 8 k per operand per thread
+  int fr[4], fk[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int e = tid + i * NT;   // 0..2047
+    fr[i] = e >> 3;               // row 0..255
+    fk[i] = (e & 7) * 8;          // k offset 0..56
+  }
+  uint4 ra[4], rb[4];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int gk = k0 + fk[i];
+      const int gm = m0 + fr[i], gn = n0 + fr[i];
+      uint4 va = {0u, 0u, 0u, 0u}, vb = {0u, 0u, 0u, 0u};
+      if (gm < d.M && gk + 8 <= d.K) va = *reinterpret_cast<const uint4*>(d.A + gm * d.lda + gk);
+      else if (gm < d.M) {
+        uint16_t tmp[8];
+        for (int u = 0; u < 8; ++u) tmp[u] = gk + u < d.K ? d.A[gm * d.lda + gk + u] : (uint16_t)0;
+        va = *reinterpret_cast<const uint4*>(tmp);
+      }
+      if (gn < d.N && gk + 8 <= d.K) vb = *reinterpret_cast<const uint4*>(d.Bt + gn * d.ldb + gk);
+      else if (gn < d.N) {
+        uint16_t tmp[8];
+        for (int u = 0; u < 8; ++u) tmp[u] = gk + u < d.K ? d.Bt[gn * d.ldb + gk + u] : (uint16_t)0;
+        vb = *reinterpret_cast<const uint4*>(tmp);
+      }
+      ra[i] = va;
+      rb[i] = vb;
+    }
+  };
+  auto stash = [&](int b) {
+    uint16_t* as = As0 + b * WBM * LDR;
+    uint16_t* bs = Bs0 + b * WBN * LDR;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      *reinterpret_cast<uint4*>(&as[fr[i] * LDR + fk[i]]) = ra[i];
+      *reinterpret_cast<uint4*>(&bs[fr[i] * LDR + fk[i]]) = rb[i];
+    }
+  };
+
+  v4f acc[8][4];
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = 0; k0 < d.K; k0 += BK) {
+    const bool more = k0 + BK < d.K;
+    if (more) fetch(k0 + BK);
+    const uint16_t* as = As0 + buf * WBM * LDR;
+    const uint16_t* bs = Bs0 + buf * WBN * LDR;
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 32) {
+      v8bf b[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        b[j] = *reinterpret_cast<const v8bf*>(&bs[(wn * 64 + j * 16 + c16) * LDR + kk + q * 8]);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const v8bf a = *reinterpret_cast<const v8bf*>(&as[(wm * 128 + i * 16 + c16) * LDR + kk + q * 8]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[j], acc[i][j], 0, 0, 0);
+      }
+    }
+    if (more) stash(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int gm = m0 + wm * 128 + i * 16 + 4 * q + v;
+      if (gm >= d.M) continue;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int gn = n0 + wn * 64 + j * 16 + c16;
+        if (gn < d.N) d.C[(int64_t)gm * d.ldc + gn] = acc[i][j][v];
+      }
+    }
+}
+
 // X (rows x cols float, leading dimension ldx) -> Xt (cols x rows bf16,
 // leading dimension ldt), 64 x 64 tiles through LDS.
 __global__ __launch_bounds__(256) void transpose_bf16_kernel(const float* X, int64_t ldx, uint16_t* Xt,
@@ -212,8 +319,16 @@ rsrs_status gemm_bf16_op(hipStream_t st, const uint16_t* A, int64_t lda, int64_t
     hipLaunchKernelGGL(transpose_bf16_kernel, g, dim3(256), 0, st, X, ldx, Xt, ldt, K, N);
   }
   Bf16Desc d{A, Xt, Y, lda, ldt, ldy, (int)M, (int)N, (int)K};
+  const double fl = 2.0 * M * N * K, by = 2.0 * (M * K + N * K) + 4.0 * M * N;
+  if (M >= WBM && N >= WBN) {
+    const int64_t tiles = ((M + WBM - 1) / WBM) * ((N + WBN - 1) / WBN);
+    ProfScope ps(st, "gemm_bf16_nt_256x256:operator", fl, by);
+    hipLaunchKernelGGL(gemm_bf16_nt256_kernel, dim3((unsigned)round_up(tiles, 8)), dim3(NT), 0, st, d);
+    RSRS_HIP(hipGetLastError());
+    return RSRS_OK;
+  }
   const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
-  ProfScope ps(st, "gemm_bf16_nt_128x128:operator", 2.0 * M * N * K, 2.0 * (M * K + N * K) + 4.0 * M * N);
+  ProfScope ps(st, "gemm_bf16_nt_128x128:operator", fl, by);
   hipLaunchKernelGGL(gemm_bf16_nt_kernel, dim3((unsigned)round_up(tiles, 8)), dim3(NT), 0, st, d);
   RSRS_HIP(hipGetLastError());
   return RSRS_OK;
