@@ -101,7 +101,9 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmDescT<TI, 
   using acc_t = typename Mfma<TI>::acc_t;
   constexpr int VW = 16 / (int)sizeof(TI);   // elements per 16-byte load
   constexpr int NT = 64 * WM * WN;    // threads per workgroup
-  constexpr int BK = 16;
+  // K slice: 32 for FP32 operands on wide tiles (the MFMA work of one slice
+  // then covers a global-load round trip), 16 otherwise
+  constexpr int BK = (sizeof(TI) == 4 && BN >= 64) ? 32 : 16;
   constexpr int PA = BM + 2;
   constexpr int PB = BN + 2;
   constexpr int FM = BM / WM / 16;
