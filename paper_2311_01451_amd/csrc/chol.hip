@@ -7,7 +7,7 @@
 //
 //   column j  (panels after the first of a super-panel) the column block j
 //             receives the earlier panels of its super-panel (narrow GEMM).
-//   panel j   one workgroup per (matrix, four 64-row blocks i >= j).  Each
+//   panel j   one workgroup per (matrix, two 64-row blocks i >= j).  Each
 //             workgroup factors the diagonal block G_jj itself (so no
 //             workgroup waits for another), forms X_jj = L_jj^{-1}, and
 //             computes its blocks L_ij = G_ij X_jj^T; the workgroup holding
@@ -47,7 +47,7 @@ namespace {
 
 constexpr int PB = 64;        // panel width
 constexpr int PP = PB + 1;    // LDS row pitch (doubles)
-constexpr int RB = 4;         // row blocks per workgroup
+constexpr int RB = 2;         // row blocks per workgroup
 
 struct CholPanel {
   double* G;   // the matrix (lower part); receives L_ij, i > j

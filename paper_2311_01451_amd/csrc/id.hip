@@ -113,22 +113,38 @@ __global__ __launch_bounds__(64) void id_step_kernel(const IdDesc* __restrict__ 
 // instead of two passes over both.  Four rows per workgroup (one per wave);
 // the row is requested before the pivot search so that its load overlaps
 // the search, and the search itself loads all candidates at once.
-template <typename S, int R>
+// V consecutive elements at p (V = 1, or 2 with p 8-byte aligned).
+template <typename S, int V>
+__device__ __forceinline__ void load_v(const S* p, S (&out)[V]) {
+  if constexpr (V == 2) {
+    static_assert(sizeof(S) == 4, "pairs of FP32 values");
+    const float2 v = *reinterpret_cast<const float2*>(p);
+    out[0] = v.x;
+    out[1] = v.y;
+  } else {
+    out[0] = p[0];
+  }
+}
+
+template <typename S, int R, int V>
 __global__ __launch_bounds__(256) void id_step_reg_kernel(const IdDesc* __restrict__ e, int j) {
   const IdDesc d = e[blockIdx.y];
   const int lane = threadIdx.x & 63;
   const int i = 4 * blockIdx.x + (threadIdx.x >> 6);
   if (i >= d.b || j >= d.k) return;
-  // rows are kept in their storage type (converted to FP64 where used) and
-  // loaded unconditionally from a clamped column, so that all loads are in
-  // flight at once
+  // Rows are kept in their storage type (converted to FP64 where used); lane
+  // l holds columns V l + 64 V u + t.  Loads come from a clamped chunk
+  // (s is a multiple of V), unconditionally, so that all are in flight at
+  // once; FP32 rows move two columns per load.
   S* mi = static_cast<S*>(d.M) + (int64_t)i * d.ldm;
-  S ri[R];
+  S ri[R][V];
 #pragma unroll
   for (int u = 0; u < R; ++u) {
-    const int c = lane + 64 * u;
-    const S v = mi[min(c, d.s - 1)];
-    ri[u] = c < d.s ? v : S(0);
+    const int c = V * lane + 64 * V * u;
+    S v[V];
+    load_v<S, V>(mi + min(c, d.s - V), v);
+#pragma unroll
+    for (int t = 0; t < V; ++t) ri[u][t] = c < d.s ? v[t] : S(0);
   }
   const double* cur = d.norms + (j & 1) * d.b;
   double* nxt = d.norms + ((j + 1) & 1) * d.b;
@@ -174,25 +190,36 @@ __global__ __launch_bounds__(256) void id_step_reg_kernel(const IdDesc* __restri
   }
   if (d.sel[i] < j) return;
   const S* mp = static_cast<const S*>(d.M) + (int64_t)p * d.ldm;
-  S rp[R];
-  double dot = 0.0;
+  S rp[R][V];
 #pragma unroll
   for (int u = 0; u < R; ++u) {
-    const int c = lane + 64 * u;
-    const S v = mp[min(c, d.s - 1)];
-    rp[u] = c < d.s ? v : S(0);
-  }
+    const int c = V * lane + 64 * V * u;
+    S v[V];
+    load_v<S, V>(mp + min(c, d.s - V), v);
 #pragma unroll
-  for (int u = 0; u < R; ++u) dot += (double)ri[u] * (double)rp[u];
+    for (int t = 0; t < V; ++t) rp[u][t] = c < d.s ? v[t] : S(0);
+  }
+  double dot = 0.0;
+#pragma unroll
+  for (int u = 0; u < R; ++u)
+#pragma unroll
+    for (int t = 0; t < V; ++t) dot += (double)ri[u][t] * (double)rp[u][t];
   dot = wave_sum(dot);
   const double coef = pn2 > 0.0 ? dot / pn2 : 0.0;
   double s = 0.0;
 #pragma unroll
   for (int u = 0; u < R; ++u) {
-    const int c = lane + 64 * u;
-    const S v = (S)((double)ri[u] - coef * (double)rp[u]);   // the norm is that of the stored row
-    if (c < d.s) mi[c] = v;
-    s += c < d.s ? (double)v * (double)v : 0.0;
+    const int c = V * lane + 64 * V * u;
+    S v[V];
+#pragma unroll
+    for (int t = 0; t < V; ++t) {
+      v[t] = (S)((double)ri[u][t] - coef * (double)rp[u][t]);   // the norm is that of the stored row
+      s += c < d.s ? (double)v[t] * (double)v[t] : 0.0;
+    }
+    if (c < d.s) {
+      if constexpr (V == 2) *reinterpret_cast<float2*>(mi + c) = make_float2(v[0], v[1]);
+      else mi[c] = v[0];
+    }
   }
   s = wave_sum(s);
   if (lane == 0) {
@@ -294,22 +321,25 @@ __global__ __launch_bounds__(256) void id_finalize_kernel(const IdDesc* __restri
 }
 
 template <typename S>
-static void id_launch(hipStream_t st, const IdDesc* de, unsigned nb, int bmax, int kmax, int smax, double fstep,
-                      double bstep) {
+static void id_launch(hipStream_t st, const IdDesc* de, unsigned nb, int bmax, int kmax, int smax, bool pairs,
+                      double fstep, double bstep) {
   {
     ProfScope ps(st, "id_init", 0.0, bstep);
     hipLaunchKernelGGL(id_init_kernel<S>, dim3((unsigned)bmax, nb), dim3(64), 0, st, de);
   }
   // register variant when every row fits (the summation order of the dot
-  // product and norm is then fixed by the lane layout, the same for all s)
+  // product and norm is then fixed by the lane layout, the same for all s);
+  // FP32 rows of even length and leading dimension move two columns per load
   const int nchunk = (smax + 63) / 64;
   for (int j = 0; j < kmax; ++j) {
     ProfScope ps(st, "id_step", fstep, bstep);
     const unsigned g4 = (unsigned)((bmax + 3) / 4);
-    if (nchunk <= 16)
-      hipLaunchKernelGGL((id_step_reg_kernel<S, 16>), dim3(g4, nb), dim3(256), 0, st, de, j);
+    if (pairs && nchunk <= 40)
+      hipLaunchKernelGGL((id_step_reg_kernel<S, 20, (sizeof(S) == 4 ? 2 : 1)>), dim3(g4, nb), dim3(256), 0, st, de, j);
+    else if (nchunk <= 16)
+      hipLaunchKernelGGL((id_step_reg_kernel<S, 16, 1>), dim3(g4, nb), dim3(256), 0, st, de, j);
     else if (nchunk <= 40)
-      hipLaunchKernelGGL((id_step_reg_kernel<S, 40>), dim3(g4, nb), dim3(256), 0, st, de, j);
+      hipLaunchKernelGGL((id_step_reg_kernel<S, 40, 1>), dim3(g4, nb), dim3(256), 0, st, de, j);
     else
       hipLaunchKernelGGL(id_step_kernel<S>, dim3((unsigned)bmax, nb), dim3(64), 0, st, de, j);
   }
@@ -336,8 +366,11 @@ rsrs_status id_run(Uploader& up, hipStream_t st, const std::vector<IdDesc>& e, b
     fstep += 4.0 * x.b * x.s;
     bstep += 2.0 * esz * x.b * x.s;   // read and write every row
   }
-  if (fp32) id_launch<float>(st, de, nb, bmax, kmax, smax, fstep, bstep);
-  else id_launch<double>(st, de, nb, bmax, kmax, smax, fstep, bstep);
+  bool pairs = fp32;
+  for (const auto& x : e)
+    pairs = pairs && x.s % 2 == 0 && x.ldm % 2 == 0 && ((uintptr_t)x.M & 7) == 0;
+  if (fp32) id_launch<float>(st, de, nb, bmax, kmax, smax, pairs, fstep, bstep);
+  else id_launch<double>(st, de, nb, bmax, kmax, smax, false, fstep, bstep);
   {
     ProfScope ps(st, "id_finalize");
     hipLaunchKernelGGL(id_finalize_kernel, dim3(nb), dim3(256), 0, st, de);
