@@ -230,6 +230,12 @@ int rsrs_op_matvec(void* opv, int transpose, int dtype, int64_t ncols, const voi
   const int n = (int)op->n;
   const int ta = (transpose && !op->symmetric) ? 1 : 0;
   const GemmShape shp = ncols <= 16 ? GS_64x16 : GS_64x64;
+  if (dtype == RSRS_F64 && ta == 0 && skinny_f64_ok(op->A, op->lda, n, n, ncols)) {
+    // narrow products (refinement residuals) stream the matrix once
+    if (op->skinny.bytes < skinny_f64_scratch(n) && op->skinny.alloc(skinny_f64_scratch(n)) != RSRS_OK) return 1;
+    return skinny_f64(st, op->A, op->lda, n, n, static_cast<const double*>(X), ldx, ncols, static_cast<double*>(Y),
+                      ldy, op->skinny.as<double>()) == RSRS_OK ? 0 : 1;
+  }
   if (dtype == RSRS_F64) {
     std::vector<GemmDesc> d{gdesc(op->A, nullptr, op->lda, static_cast<const double*>(X), nullptr, ldx,
                                   static_cast<double*>(Y), nullptr, ldy, n, (int)ncols, n)};

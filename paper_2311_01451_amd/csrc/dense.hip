@@ -658,4 +658,120 @@ void sub2d(hipStream_t st, const double* f, int64_t ldf, const double* y, int64_
   hipLaunchKernelGGL(sub2d_kernel, dim3(g), dim3(256), 0, st, f, ldf, y, ldy, z, ldz, n, w);
 }
 
+// ---------------------------------------------------------------- skinny product
+// Y = A X for a dense row-major A (M x K) and a narrow X (K x N, N <= 16),
+// all FP64: the product streams A once, so it is HBM-bound.  K is split into
+// chunks whose slice of X (1 MB) stays in L2 while every row block streams
+// its rows of A straight into registers; each wave forms a 16 x 16 tile on
+// FP64 MFMA, lane (m, q) holding row m and 32 consecutive k (so the k of a
+// lane's operand in MFMA j is 32 q + j; X is staged in LDS in the same
+// order); the partial tiles of the chunks are summed in chunk order by a
+// second launch, so the result does not depend on the schedule.
+namespace {
+constexpr int SK_RM = 64;    // rows per workgroup (16 per wave)
+constexpr int SK_KC = 128;   // k per iteration
+
+__global__ __launch_bounds__(256) void skinny_f64_kernel(const double* __restrict__ A, int64_t lda, int M,
+                                                         const double* __restrict__ X, int64_t ldx, int N,
+                                                         double* __restrict__ P, int klen) {
+  __shared__ double Xs[2][SK_KC * 16];
+  const int ks = blockIdx.y;
+  const int k_lo = ks * klen;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m = lane & 15, q = lane >> 4;
+  const int r0 = blockIdx.x * SK_RM + wave * 16;
+  const double* arow = A + (int64_t)min(r0 + m, M - 1) * lda + k_lo + 32 * q;
+  double ar[2][32];
+  double xr[8];
+  auto load_a = [&](int it, double (&dst)[32]) {
+    const double2* src = reinterpret_cast<const double2*>(arow + (int64_t)it * SK_KC);
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const double2 v = src[t];
+      dst[2 * t] = v.x;
+      dst[2 * t + 1] = v.y;
+    }
+  };
+  auto load_x = [&](int it) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int e = tid * 8 + t, k = k_lo + it * SK_KC + e / 16, n = e % 16;
+      xr[t] = n < N ? X[(int64_t)k * ldx + n] : 0.0;
+    }
+  };
+  auto stash_x = [&](int b) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) Xs[b][tid * 8 + t] = xr[t];
+  };
+  const int iters = klen / SK_KC;   // even
+  v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+  // one iteration: prefetch the next slice into the other register set and
+  // LDS buffer, multiply the current one (register sets named statically)
+  auto step = [&](int it, int cb, double (&cur)[32], double (&nxt)[32]) {
+    const bool more = it + 1 < iters;
+    if (more) {
+      load_a(it + 1, nxt);
+      load_x(it + 1);
+    }
+#pragma unroll
+    for (int j = 0; j < 32; ++j)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(cur[j], Xs[cb][(32 * q + j) * 16 + m], acc, 0, 0, 0);
+    if (more) stash_x(cb ^ 1);
+    __syncthreads();
+  };
+  load_a(0, ar[0]);
+  load_x(0);
+  stash_x(0);
+  __syncthreads();
+  for (int it = 0; it < iters; it += 2) {
+    step(it, 0, ar[0], ar[1]);
+    step(it + 1, 1, ar[1], ar[0]);
+  }
+  // D[4 v + q][m]: row r0 + 4 v + q, column m
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int r = r0 + 4 * v + q;
+    if (r < M && m < N) P[((int64_t)ks * M + r) * 16 + m] = acc[v];
+  }
+}
+
+__global__ void skinny_sum_kernel(const double* __restrict__ P, int M, int N, int ksplit, double* Y, int64_t ldy) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)M * 16) return;
+  const int r = (int)(e / 16), n = (int)(e % 16);
+  if (n >= N) return;
+  double s = 0.0;
+  for (int t = 0; t < ksplit; ++t) s += P[((int64_t)t * M + r) * 16 + n];
+  Y[(int64_t)r * ldy + n] = s;
+}
+}  // namespace
+
+bool skinny_f64_ok(const double* A, int64_t lda, int64_t M, int64_t K, int64_t N) {
+  return N >= 1 && N <= 16 && M >= 1 && M <= INT32_MAX && K % (16 * SK_KC) == 0 && K > 0 && K <= INT32_MAX &&
+         lda % 2 == 0 && ((uintptr_t)A & 15) == 0;
+}
+
+size_t skinny_f64_scratch(int64_t M) { return (size_t)8 * M * 16 * sizeof(double); }
+
+rsrs_status skinny_f64(hipStream_t st, const double* A, int64_t lda, int64_t M, int64_t K, const double* X,
+                       int64_t ldx, int64_t N, double* Y, int64_t ldy, double* scratch) {
+  if (!skinny_f64_ok(A, lda, M, K, N)) {
+    set_error("skinny product: unsupported shape or alignment");
+    return RSRS_E_INVALID;
+  }
+  constexpr int ksplit = 8;
+  const int klen = (int)(K / ksplit);
+  {
+    ProfScope ps(st, "skinny_f64:operator", 2.0 * M * N * K, 8.0 * (M * K + K * N));
+    hipLaunchKernelGGL(skinny_f64_kernel, dim3((unsigned)((M + SK_RM - 1) / SK_RM), ksplit), dim3(256), 0, st,
+                       A, lda, (int)M, X, ldx, (int)N, scratch, klen);
+    RSRS_HIP(hipGetLastError());
+  }
+  const int64_t tot = M * 16;
+  hipLaunchKernelGGL(skinny_sum_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, scratch, (int)M,
+                     (int)N, ksplit, Y, ldy);
+  RSRS_HIP(hipGetLastError());
+  return RSRS_OK;
+}
+
 }  // namespace rsrs

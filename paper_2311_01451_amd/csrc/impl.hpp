@@ -32,6 +32,7 @@ struct rsrs_operator_s {
   rsrs::DevBuf owned32;      // FP32 kernel matrix (built at the first FP32 product)
   rsrs::DevBuf owned16;      // BF16 kernel matrix (built at the first BF16 product)
   rsrs::DevBuf xt16;         // transposed BF16 copy of the right-hand block
+  rsrs::DevBuf skinny;       // partial products of narrow FP64 products
   rsrs::KernelOp kop;        // kernel description (kernel operators)
   bool symmetric = true;
   rsrs::Poisson7Op pois;

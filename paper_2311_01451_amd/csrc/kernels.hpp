@@ -104,6 +104,14 @@ struct GjeDesc { const double* A; double* W; double* Ainv; int64_t lda, ldi; int
 // pivoting (W: n x 2n workspace).  flag[0] |= 2 on an exactly zero pivot.
 rsrs_status gje_inverse(Uploader& up, hipStream_t st, const std::vector<GjeDesc>& e, int* flag);
 
+// Y (M x N) = A (M x K) X (K x N), FP64, for narrow X (N <= 16) on a dense
+// row-major A: K split in 8 chunks (K a multiple of 2048), partial products
+// in scratch (skinny_f64_scratch(M) bytes) summed in chunk order.
+bool skinny_f64_ok(const double* A, int64_t lda, int64_t M, int64_t K, int64_t N);
+size_t skinny_f64_scratch(int64_t M);
+rsrs_status skinny_f64(hipStream_t st, const double* A, int64_t lda, int64_t M, int64_t K, const double* X,
+                       int64_t ldx, int64_t N, double* Y, int64_t ldy, double* scratch);
+
 template <typename TS, typename TD>
 struct Copy2DT { const TS* src; TD* dst; int64_t lds, ldd; int rows, cols; double alpha; int accumulate, trans; };
 using Copy2D = Copy2DT<double, double>;

@@ -179,6 +179,29 @@ def test_kernel_operators_match_oracle():
     assert relmax(op.matvec(dev(X[:400])).cpu().numpy(), oop.inv_r3d(p3) @ X[:400]) < 1e-13
 
 
+def test_narrow_fp64_products_stream_the_operator():
+    """FP64 products with at most 16 columns on operators whose size is a
+    multiple of 2048 take the split-K streaming kernel; against the dense
+    oracle operator, for widths 1..16 (the refinement residuals' shape) and
+    the transposed product (general GEMM path) of a skewed kernel."""
+    need_gpu()
+    n = 64
+    pts = inputs.grid2d(n)
+    h = 1.0 / n
+    A = oop.log2d(pts, h)
+    op = rsrs.rsrs_op_create_kernel(rsrs.RSRS_OP_LOG2D, pts, h)
+    rng = np.random.default_rng(5)
+    for w in (1, 3, 16):
+        X = rng.standard_normal((n * n, w))
+        for _ in range(2):   # the scratch is reused by the second call
+            assert relmax(op.matvec(dev(X)).cpu().numpy(), A @ X) < 1e-13, w
+    As = oop.log2d_skew(pts, h, 3e-3)
+    ops = rsrs.rsrs_op_create_kernel(rsrs.RSRS_OP_LOG2D_SKEW, pts, h, 3e-3)
+    X = rng.standard_normal((n * n, 7))
+    assert relmax(ops.matvec(dev(X)).cpu().numpy(), As @ X) < 1e-13
+    assert relmax(ops.matvec(dev(X), transpose=True).cpu().numpy(), As.T @ X) < 1e-13
+
+
 def _log_problem(n, m, k, skew=0.0, **kw):
     pts = inputs.grid2d(n)
     A = oop.log2d(pts, 1.0 / n) if skew == 0.0 else oop.log2d_skew(pts, 1.0 / n, skew)
