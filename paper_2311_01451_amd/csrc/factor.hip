@@ -312,6 +312,18 @@ struct Item {
   BoxWs<T> w;
 };
 
+// One upload of a class's index lists (the boxes' R, S, N_a, B_a, N_a slots
+// are contiguous in the index store, box after box).
+template <typename T>
+rsrs_status upload_class_lists(Job<T>& J, const Group& g, hipStream_t st) {
+  if (g.count <= 0) return RSRS_OK;
+  const BoxRec& a = J.F->boxes[g.first];
+  const BoxRec& z = J.F->boxes[g.first + g.count - 1];
+  const int64_t lo = a.oR, hi = z.oBa + z.b + z.n;
+  RSRS_HIP(hipMemcpyAsync(J.iS + lo, J.hI + lo, (size_t)(hi - lo) * 8, hipMemcpyHostToDevice, st));
+  return RSRS_OK;
+}
+
 template <typename T>
 rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
   constexpr bool mixed = Job<T>::mixed;
@@ -398,15 +410,22 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
         std::memcpy(J.hI + R.oNa, J.Na[q].data(), R.n * 8);
         std::memcpy(J.hI + R.oBa, J.Ba[q].data(), R.b * 8);
         std::memcpy(J.hI + R.oBa + R.b, J.Na[q].data(), R.n * 8);
-        RSRS_HIP(hipMemcpyAsync(J.iS + R.oNa, J.hI + R.oNa, (size_t)(R.n + R.b + R.n) * 8,
-                                hipMemcpyHostToDevice, st));
         items.push_back(Item<T>{&J, &R, {}});
       }
+      // the class's index lists are contiguous: one upload (its R / S slots
+      // are filled and uploaded again once the skeletons are known)
+      RSRS_TRY(upload_class_lists(J, g, st));
     }
     // ---- workspace: the part read by the extraction alternates between two
     // buffers, the one it reads may still be in use by the previous class
     Bump bump{ws.as<char>(), 0, ws.bytes};
     Bump bumpb{wsb[t & 1].as<char>(), 0, wsb[t & 1].bytes};
+    // skeleton / redundant positions of all boxes back to back (S then R,
+    // b entries per box), so that one copy brings them to the host
+    int64_t npos = 0;
+    for (auto& it : items) npos += it.R->b;
+    int64_t* posall = bumpb.take<int64_t>(npos);
+    int64_t pofs = 0;
     for (auto& it : items) {
       const BoxRec& R = *it.R;
       const int k = it.J->k;
@@ -425,7 +444,8 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
       w.XRy = bumpb.take<T>(r * lp); w.XRz = bumpb.take<T>(r * lp);
       w.Xpy = bumpb.take<T>(r * lp); w.Xpz = bumpb.take<T>(r * lp);
       w.gje = bumpb.take<double>(2 * r * r);
-      w.Spos = bumpb.take<int64_t>(k); w.Rpos = bumpb.take<int64_t>(b);
+      w.Spos = posall + pofs; w.Rpos = w.Spos + k;
+      pofs += b;
       if constexpr (mixed) {
         w.LOt = bump.take<T>(l * lp); w.LPt = bump.take<T>(l * lp);
         w.Td = bump.take<double>(r * round_up(k, 4));
@@ -554,20 +574,9 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
         RSRS_TRY(copy2d<double, T>(up, st, tc));
       }
     }
-    // ---- skeleton sets back to the host
-    {
-      int64_t nposn = 0;
-      for (auto& it : items) nposn += it.R->b;
-      RSRS_TRY(hpos.alloc((size_t)nposn * 8));
-      int64_t o2 = 0;
-      for (auto& it : items) {
-        const BoxRec& R = *it.R;
-        const int k = it.J->k;
-        RSRS_HIP(hipMemcpyAsync(hpos.as<int64_t>() + o2, it.w.Spos, (size_t)k * 8, hipMemcpyDeviceToHost, st));
-        RSRS_HIP(hipMemcpyAsync(hpos.as<int64_t>() + o2 + k, it.w.Rpos, (size_t)R.r * 8, hipMemcpyDeviceToHost, st));
-        o2 += R.b;
-      }
-    }
+    // ---- skeleton sets back to the host (one copy, positions back to back)
+    RSRS_TRY(hpos.alloc((size_t)std::max<int64_t>(npos, 1) * 8));
+    RSRS_HIP(hipMemcpyAsync(hpos.as<int64_t>(), posall, (size_t)npos * 8, hipMemcpyDeviceToHost, st));
     RSRS_TRY(up.reset());
     {
       int hflag = 0;
@@ -593,10 +602,11 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
         for (int64_t j = 0; j < R.r; ++j) Rg[j] = J.Ba[q][rp[j]];
         std::memcpy(J.hI + R.oR, Rg.data(), R.r * 8);
         std::memcpy(J.hI + R.oS, Sg.data(), (size_t)k * 8);
-        RSRS_HIP(hipMemcpyAsync(J.iS + R.oR, J.hI + R.oR, (size_t)(R.r + k) * 8, hipMemcpyHostToDevice, st));
         J.cur[R.box] = std::move(Sg);
         o2 += R.b;
       }
+      for (auto& J : jobs)
+        if (t < J.F->groups.size()) RSRS_TRY(upload_class_lists(J, J.F->groups[t], st));
     }
     // ---- test-matrix sparsification (F) on the main stream: the next
     // class's Gram matrices read the updated rows S
