@@ -396,12 +396,19 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
         BoxRec& R = J.F->boxes[g.first + q];
         const size_t ip = J.pos.at(R.box);
         J.Ba[q] = J.cur[R.box];
+        // neighbours own disjoint point ranges and keep their active points
+        // sorted, so visiting them by range start yields a sorted list
+        std::vector<int64_t> nbs(tr.nb_ids[lev].begin() + tr.nb_off[lev][ip],
+                                 tr.nb_ids[lev].begin() + tr.nb_off[lev][ip + 1]);
+        std::sort(nbs.begin(), nbs.end(),
+                  [&](int64_t x, int64_t y) { return tr.pt_begin[x] < tr.pt_begin[y]; });
         std::vector<int64_t> v;
-        for (int64_t j = tr.nb_off[lev][ip]; j < tr.nb_off[lev][ip + 1]; ++j) {
-          const auto& a = J.active_of(tr.nb_ids[lev][j]);
+        v.reserve((size_t)R.n);
+        for (int64_t x : nbs) {
+          const auto& a = J.active_of(x);
           v.insert(v.end(), a.begin(), a.end());
         }
-        std::sort(v.begin(), v.end());
+        if (!std::is_sorted(v.begin(), v.end())) std::sort(v.begin(), v.end());
         J.Na[q] = std::move(v);
         if ((int64_t)J.Ba[q].size() != R.b || (int64_t)J.Na[q].size() != R.n) {
           set_error("internal: active sets disagree with the count model");
