@@ -19,14 +19,18 @@
 // Inside a panel the 64 x 64 diagonal block is factored in eight steps of
 // 8 columns: the 64 lanes of one wave (one per row) each factor the 8 x 8
 // diagonal block in registers (reciprocal square roots by the hardware
-// estimate and two Newton steps), rows below form their entries of L by
+// estimate and Newton steps), rows below form their entries of L by
 // forward substitution and rows inside the block their row of its inverse,
-// then the waves apply the rank-8 update on FP64 MFMA; two barriers per
+// then the waves apply the rank-8 update on MFMA; two barriers per
 // step.  The
 // inverse of the 64 x 64 factor follows from the 8 x 8 ones by doubling,
 //   [A 0; C D]^{-1} = [A^{-1} 0; -D^{-1} C A^{-1}  D^{-1}],
-// and the off-diagonal blocks are G_ij X_jj^T on FP64 MFMA, the next block's
+// and the off-diagonal blocks are G_ij X_jj^T on MFMA, the next block's
 // loads in flight during each product.
+//
+// Element type T = double (FP64 MFMA) or float (FP32 MFMA, FP32
+// accumulation; the Gram matrices of the FP32 path are formed in FP32, so
+// their factorization in FP32 adds a backward error of the same order).
 //
 // After the panels, L^{-1} of the whole matrix is assembled by the same
 // doubling on 64 * 2^t blocks with batched GEMMs (log2(n / 64) levels, two
@@ -46,18 +50,20 @@ namespace rsrs {
 namespace {
 
 constexpr int PB = 64;        // panel width
-constexpr int PP = PB + 1;    // LDS row pitch (doubles)
+constexpr int PP = PB + 1;    // LDS row pitch (elements)
 constexpr int RB = 2;         // row blocks per workgroup
 
+template <typename T>
 struct CholPanel {
-  double* G;   // the matrix (lower part); receives L_ij, i > j
-  double* X;   // scratch of the same shape; receives X_jj
+  T* G;   // the matrix (lower part); receives L_ij, i > j
+  T* X;   // scratch of the same shape; receives X_jj
   int64_t ld;
   int n, j, ib, ie;   // panel j, row blocks [ib, ie)
 };
 
-// 1 / sqrt(d) from the hardware estimate and two Newton steps
-// y <- y + y (1 - d y^2) / 2 (each step doubles the correct bits).
+// 1 / sqrt(d) from the hardware estimate and Newton steps
+// y <- y + y (1 - d y^2) / 2 (each step doubles the correct bits): two from
+// the FP64 estimate, one from the FP32 one (good to about one ulp).
 __device__ __forceinline__ double rsqrt_nr(double d) {
   double y = __builtin_amdgcn_rsq(d);
 #pragma unroll
@@ -67,18 +73,23 @@ __device__ __forceinline__ double rsqrt_nr(double d) {
   }
   return y;
 }
+__device__ __forceinline__ float rsqrt_nr(float d) {
+  float y = __builtin_amdgcn_rsqf(d);
+  const float e = fmaf(-(d * y), y, 1.0f);
+  return fmaf(0.5f * y, e, y);
+}
 
 // One doubling step of the in-block inverse for h = 8 or 16 (64 / (2h)
 // pairs of h-blocks), one output per thread and pass.
-template <int H>
-__device__ __forceinline__ void doubling_small(const double* La, double* Xa, double* Vs, int tid) {
+template <typename T, int H>
+__device__ __forceinline__ void doubling_small(const T* La, T* Xa, T* Vs, int tid) {
   constexpr int NP = PB / (2 * H), TOT = NP * H * H;
 #pragma unroll
   for (int x0 = 0; x0 < TOT; x0 += 256) {
     const int x = x0 + tid;
     const int p = x / (H * H), dd = (x / H) % H, aa = x % H;
     const int A0 = 2 * H * p, D0 = A0 + H;
-    double acc = 0.0;
+    T acc = 0;
 #pragma unroll
     for (int t = 0; t < H; ++t) acc = fma(La[(D0 + dd) * PP + A0 + t], Xa[(A0 + t) * PP + A0 + aa], acc);
     Vs[x] = acc;
@@ -89,7 +100,7 @@ __device__ __forceinline__ void doubling_small(const double* La, double* Xa, dou
     const int x = x0 + tid;
     const int p = x / (H * H), dd = (x / H) % H, aa = x % H;
     const int A0 = 2 * H * p, D0 = A0 + H;
-    double acc = 0.0;
+    T acc = 0;
 #pragma unroll
     for (int t = 0; t < H; ++t) acc = fma(Xa[(D0 + dd) * PP + D0 + t], Vs[p * H * H + t * H + aa], acc);
     Xa[(D0 + dd) * PP + A0 + aa] = -acc;
@@ -97,29 +108,32 @@ __device__ __forceinline__ void doubling_small(const double* La, double* Xa, dou
   __syncthreads();
 }
 
-__global__ __launch_bounds__(256, 2) void chol_panel_kernel(const CholPanel* __restrict__ e, int* flag) {
-  __shared__ double La[PB * PP];   // diagonal block -> L_jj; later the off-diagonal blocks
-  __shared__ double Xa[PB * PP];   // X_jj = L_jj^{-1}
-  __shared__ double Vs[32 * 33];   // products of the doubling steps
-  const CholPanel d = e[blockIdx.x];
+template <typename T>
+__global__ __launch_bounds__(256, 2) void chol_panel_kernel(const CholPanel<T>* __restrict__ e, int* flag) {
+  using MM = Mfma<T>;
+  using acc_t = typename MM::acc_t;
+  __shared__ T La[PB * PP];   // diagonal block -> L_jj; later the off-diagonal blocks
+  __shared__ T Xa[PB * PP];   // X_jj = L_jj^{-1}
+  __shared__ T Vs[32 * 33];   // products of the doubling steps
+  const CholPanel<T> d = e[blockIdx.x];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t ld = d.ld;
   const int j0 = PB * d.j;
   const int nj = min(PB, d.n - j0);
   {
     // lower part of the diagonal block, identity beyond n, zero above
-    const double* g = d.G + (int64_t)j0 * ld + j0;
-    double v[16];
+    const T* g = d.G + (int64_t)j0 * ld + j0;
+    T v[16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
       const int x = tid + 256 * u, r = x >> 6, c = x & 63;
-      v[u] = (r < nj && c <= r) ? g[(int64_t)r * ld + c] : ((r == c) ? 1.0 : 0.0);
+      v[u] = (r < nj && c <= r) ? g[(int64_t)r * ld + c] : T((r == c) ? 1 : 0);
     }
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
       const int x = tid + 256 * u;
       La[(x >> 6) * PP + (x & 63)] = v[u];
-      if ((x & 63) > (x >> 6)) Xa[(x >> 6) * PP + (x & 63)] = 0.0;   // Xa stays zero above the diagonal
+      if ((x & 63) > (x >> 6)) Xa[(x >> 6) * PP + (x & 63)] = T(0);   // Xa stays zero above the diagonal
     }
   }
   __syncthreads();
@@ -132,20 +146,20 @@ __global__ __launch_bounds__(256, 2) void chol_panel_kernel(const CholPanel* __r
   for (int s = 0; s < 8; ++s) {
     const int b = 8 * s;
     if (wave == 0) {
-      double D[8][8];
+      T D[8][8];
 #pragma unroll
       for (int i = 0; i < 8; ++i)
 #pragma unroll
         for (int k = 0; k <= i; ++k) D[i][k] = La[(b + i) * PP + b + k];
-      double y[8];
+      T y[8];
 #pragma unroll
       for (int jj = 0; jj < 8; ++jj) {
-        double dd = D[jj][jj];
-        if (!(dd > 0.0)) {   // same in every lane
+        T dd = D[jj][jj];
+        if (!(dd > T(0))) {   // same in every lane
           bad = true;
-          dd = 1.0;
+          dd = T(1);
         }
-        const double yy = rsqrt_nr(dd);
+        const T yy = rsqrt_nr(dd);
         y[jj] = yy;
         D[jj][jj] = dd * yy;
 #pragma unroll
@@ -158,10 +172,10 @@ __global__ __launch_bounds__(256, 2) void chol_panel_kernel(const CholPanel* __r
       const int r = lane;
       if (r >= b + 8) {
         // l = a L_bb^{-T} by forward substitution
-        double l[8];
+        T l[8];
 #pragma unroll
         for (int jj = 0; jj < 8; ++jj) {
-          double acc = La[r * PP + b + jj];
+          T acc = La[r * PP + b + jj];
 #pragma unroll
           for (int k = 0; k < jj; ++k) acc = fma(-l[k], D[jj][k], acc);
           l[jj] = acc * y[jj];
@@ -171,10 +185,10 @@ __global__ __launch_bounds__(256, 2) void chol_panel_kernel(const CholPanel* __r
       } else if (r >= b) {
         // row i of L_bb^{-1}: x L_bb = e_i, from the last column back
         const int i = r - b;
-        double x[8];
+        T x[8];
 #pragma unroll
         for (int jj = 7; jj >= 0; --jj) {
-          double acc = (jj == i) ? 1.0 : 0.0;
+          T acc = T((jj == i) ? 1 : 0);
 #pragma unroll
           for (int k = jj + 1; k < 8; ++k) acc = fma(-x[k], D[k][jj], acc);
           x[jj] = acc * y[jj];
@@ -185,7 +199,7 @@ __global__ __launch_bounds__(256, 2) void chol_panel_kernel(const CholPanel* __r
     }
     __syncthreads();
     {
-      // rank-8 update of rows and columns >= b + 8 (lower part) on FP64 MFMA:
+      // rank-8 update of rows and columns >= b + 8 (lower part) on MFMA:
       // the 16 x 16 tiles meeting that region, round-robin over the waves;
       // tile rows above b + 8 read the diagonal block's rows and are masked
       const int q4 = lane >> 4, c16 = lane & 15;
@@ -194,14 +208,13 @@ __global__ __launch_bounds__(256, 2) void chol_panel_kernel(const CholPanel* __r
       for (int ti = t0; ti < 4; ++ti)
         for (int tj = t0; tj <= ti; ++tj, ++idx) {
           if ((idx & 3) != wave) continue;
-          v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+          acc_t acc = acc_t{0, 0, 0, 0};
 #pragma unroll
           for (int k0 = 0; k0 < 8; k0 += 4)
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(La[(16 * ti + c16) * PP + b + k0 + q4],
-                                                       La[(16 * tj + c16) * PP + b + k0 + q4], acc, 0, 0, 0);
+            acc = MM::mma(La[(16 * ti + c16) * PP + b + k0 + q4], La[(16 * tj + c16) * PP + b + k0 + q4], acc);
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int r = 16 * ti + 4 * v + q4, c = 16 * tj + c16;
+            const int r = 16 * ti + MM::row(v, q4), c = 16 * tj + c16;
             if (c >= b + 8 && c <= r) La[r * PP + c] -= acc[v];
           }
         }
@@ -211,30 +224,28 @@ __global__ __launch_bounds__(256, 2) void chol_panel_kernel(const CholPanel* __r
   // ---- inverse of the 64 x 64 factor from the 8 x 8 ones by doubling: for
   // the pair (A, D) of h-blocks, V = C X_AA into Vs, then X_DA = -X_DD V.
   // The upper part of Xa is zero, so every product runs over full blocks.
-  doubling_small<8>(La, Xa, Vs, tid);
-  doubling_small<16>(La, Xa, Vs, tid);
+  doubling_small<T, 8>(La, Xa, Vs, tid);
+  doubling_small<T, 16>(La, Xa, Vs, tid);
   {
-    // h = 32 on FP64 MFMA, wave w: the 16 x 16 tile (w / 2, w % 2)
+    // h = 32 on MFMA, wave w: the 16 x 16 tile (w / 2, w % 2)
     const int tm = wave >> 1, tn = wave & 1, q = lane >> 4, c16 = lane & 15;
-    v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+    acc_t acc = acc_t{0, 0, 0, 0};
 #pragma unroll
     for (int k0 = 0; k0 < 32; k0 += 4)
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(La[(32 + 16 * tm + c16) * PP + k0 + q],
-                                                 Xa[(k0 + q) * PP + 16 * tn + c16], acc, 0, 0, 0);
+      acc = MM::mma(La[(32 + 16 * tm + c16) * PP + k0 + q], Xa[(k0 + q) * PP + 16 * tn + c16], acc);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) Vs[(16 * tm + 4 * v + q) * 33 + 16 * tn + c16] = acc[v];
+    for (int v = 0; v < 4; ++v) Vs[(16 * tm + MM::row(v, q)) * 33 + 16 * tn + c16] = acc[v];
     __syncthreads();
-    acc = v4d{0.0, 0.0, 0.0, 0.0};
+    acc = acc_t{0, 0, 0, 0};
 #pragma unroll
     for (int k0 = 0; k0 < 32; k0 += 4)
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Xa[(32 + 16 * tm + c16) * PP + 32 + k0 + q],
-                                                 Vs[(k0 + q) * 33 + 16 * tn + c16], acc, 0, 0, 0);
+      acc = MM::mma(Xa[(32 + 16 * tm + c16) * PP + 32 + k0 + q], Vs[(k0 + q) * 33 + 16 * tn + c16], acc);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) Xa[(32 + 16 * tm + 4 * v + q) * PP + 16 * tn + c16] = -acc[v];
+    for (int v = 0; v < 4; ++v) Xa[(32 + 16 * tm + MM::row(v, q)) * PP + 16 * tn + c16] = -acc[v];
     __syncthreads();
   }
   if (d.ib == d.j) {
-    double* xo = d.X + (int64_t)j0 * ld + j0;
+    T* xo = d.X + (int64_t)j0 * ld + j0;
     for (int x = tid; x < PB * PB; x += 256) {
       const int r = x >> 6, c = x & 63;
       if (r < nj && c < nj) xo[(int64_t)r * ld + c] = Xa[r * PP + c];
@@ -242,24 +253,24 @@ __global__ __launch_bounds__(256, 2) void chol_panel_kernel(const CholPanel* __r
     if (bad && tid == 0) atomicOr(flag, 1);
   }
   // ---- off-diagonal blocks L_ij = G_ij X_jj^T (panel j is full here) on
-  // FP64 MFMA: wave w computes rows 32 (w / 2).., columns 32 (w % 2)..
+  // MFMA: wave w computes rows 32 (w / 2).., columns 32 (w % 2)..
   const int wm = wave >> 1, wn = wave & 1, q = lane >> 4, c16 = lane & 15;
   int i = max(d.ib, d.j + 1);
-  double pf[16];
+  T pf[16];
   auto fetch = [&](int ib) {
     const int ni = min(PB, d.n - PB * ib);
-    const double* src = d.G + (int64_t)PB * ib * ld + j0;
+    const T* src = d.G + (int64_t)PB * ib * ld + j0;
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
       const int x = tid + 256 * u, r = x >> 6, c = x & 63;
-      pf[u] = (r < ni) ? src[(int64_t)r * ld + c] : 0.0;
+      pf[u] = (r < ni) ? src[(int64_t)r * ld + c] : T(0);
     }
   };
   if (i < d.ie) fetch(i);
   for (; i < d.ie; ++i) {
     const int i0 = PB * i;
     const int ni = min(PB, d.n - i0);
-    double* gi = d.G + (int64_t)i0 * ld + j0;
+    T* gi = d.G + (int64_t)i0 * ld + j0;
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
       const int x = tid + 256 * u;
@@ -267,14 +278,14 @@ __global__ __launch_bounds__(256, 2) void chol_panel_kernel(const CholPanel* __r
     }
     __syncthreads();
     if (i + 1 < d.ie) fetch(i + 1);   // in flight during the product
-    v4d acc[2][2];
+    acc_t acc[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int bb = 0; bb < 2; ++bb) acc[a][bb] = v4d{0.0, 0.0, 0.0, 0.0};
+      for (int bb = 0; bb < 2; ++bb) acc[a][bb] = acc_t{0, 0, 0, 0};
 #pragma unroll 4
     for (int k0 = 0; k0 < PB; k0 += 4) {
-      double av[2], bv[2];
+      T av[2], bv[2];
 #pragma unroll
       for (int a = 0; a < 2; ++a) av[a] = La[(32 * wm + 16 * a + c16) * PP + k0 + q];
 #pragma unroll
@@ -283,13 +294,13 @@ __global__ __launch_bounds__(256, 2) void chol_panel_kernel(const CholPanel* __r
       for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int bb = 0; bb < 2; ++bb)
-          acc[a][bb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[bb], acc[a][bb], 0, 0, 0);
+          acc[a][bb] = MM::mma(av[a], bv[bb], acc[a][bb]);
     }
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int r = 32 * wm + 16 * a + 4 * v + q;   // FP64 MFMA result row
+        const int r = 32 * wm + 16 * a + MM::row(v, q);
         if (r < ni) {
 #pragma unroll
           for (int bb = 0; bb < 2; ++bb) gi[(int64_t)r * ld + 32 * wn + 16 * bb + c16] = acc[a][bb][v];
@@ -301,7 +312,9 @@ __global__ __launch_bounds__(256, 2) void chol_panel_kernel(const CholPanel* __r
 
 }  // namespace
 
-rsrs_status chol_inverse(Uploader& up, hipStream_t st, const std::vector<CholMat>& mats, int* flag) {
+template <typename T>
+rsrs_status chol_inverse(Uploader& up, hipStream_t st, const std::vector<CholMatT<T>>& mats, int* flag) {
+  using GD = GemmDescT<T, T>;
   int nmax = 0;
   for (const auto& m : mats) nmax = std::max(nmax, m.n);
   if (nmax <= 0) return RSRS_OK;
@@ -313,10 +326,10 @@ rsrs_status chol_inverse(Uploader& up, hipStream_t st, const std::vector<CholMat
   // the trailing matrix receives all of them at once (a SYRK with K = 64 SP),
   // which reads and writes the trailing matrix SP times less often.
   constexpr int SP = 4;
-  std::vector<CholPanel> tasks;
+  std::vector<CholPanel<T>> tasks;
   std::vector<size_t> toff(P + 1);
   std::vector<double> pflops(P, 0.0);
-  std::vector<GemmDesc> colu, trail;
+  std::vector<GD> colu, trail;
   std::vector<size_t> coff(P + 1), soff(P + 1);
   for (int j = 0; j < P; ++j) {
     const int j0s = SP * (j / SP);
@@ -330,19 +343,19 @@ rsrs_status chol_inverse(Uploader& up, hipStream_t st, const std::vector<CholMat
       const int rows = m.n - PB * j;
       if (j > j0s) {
         // column block j -= L[rows >= 64 j, panels j0s..j-1] L[block j, same]^T
-        double* Lr = m.G + (int64_t)PB * j * m.ld + PB * j0s;
-        double* Cj = m.G + (int64_t)PB * j * (m.ld + 1);
-        colu.push_back(gdesc(Lr, nullptr, m.ld, Lr, nullptr, m.ld, Cj, nullptr, m.ld, rows,
+        T* Lr = m.G + (int64_t)PB * j * m.ld + PB * j0s;
+        T* Cj = m.G + (int64_t)PB * j * (m.ld + 1);
+        colu.push_back(gdescT<T, T>(Lr, nullptr, m.ld, Lr, nullptr, m.ld, Cj, nullptr, m.ld, rows,
                              std::min(PB, rows), PB * (j - j0s), -1.0, 1.0));
       }
-      for (int ib = j; ib < Pm; ib += RB) tasks.push_back(CholPanel{m.G, m.W, m.ld, m.n, j, ib, std::min(ib + RB, Pm)});
+      for (int ib = j; ib < Pm; ib += RB) tasks.push_back(CholPanel<T>{m.G, m.W, m.ld, m.n, j, ib, std::min(ib + RB, Pm)});
       const double nj = std::min(PB, rows), below = rows - nj;
       pflops[j] += (2.0 / 3.0) * nj * nj * nj + below * nj * nj;
       const int trows = m.n - PB * (j + 1);
       if (trows > 0 && (last_of_sp || j == Pm - 1)) {
-        double* Ls = m.G + (int64_t)PB * (j + 1) * m.ld + PB * j0s;
-        double* G22 = m.G + (int64_t)PB * (j + 1) * (m.ld + 1);
-        trail.push_back(gdesc(Ls, nullptr, m.ld, Ls, nullptr, m.ld, G22, nullptr, m.ld, trows, trows,
+        T* Ls = m.G + (int64_t)PB * (j + 1) * m.ld + PB * j0s;
+        T* G22 = m.G + (int64_t)PB * (j + 1) * (m.ld + 1);
+        trail.push_back(gdescT<T, T>(Ls, nullptr, m.ld, Ls, nullptr, m.ld, G22, nullptr, m.ld, trows, trows,
                               PB * (j + 1 - j0s), -1.0, 1.0));
       }
     }
@@ -353,68 +366,71 @@ rsrs_status chol_inverse(Uploader& up, hipStream_t st, const std::vector<CholMat
   std::vector<std::vector<GemmLaunch>> cl(P), tl(P);
   for (int j = 0; j < P; ++j) {
     if (coff[j + 1] > coff[j]) {
-      std::vector<GemmDesc> part(colu.begin() + coff[j], colu.begin() + coff[j + 1]);
-      RSRS_TRY(gemm_plan<double, double>(part, coff[j], 0, 1, GM_FULL, GS_64x64_ONLY, "chol", cl[j]));
+      std::vector<GD> part(colu.begin() + coff[j], colu.begin() + coff[j + 1]);
+      RSRS_TRY(gemm_plan<T, T>(part, coff[j], 0, 1, GM_FULL, GS_64x64_ONLY, "chol", cl[j]));
     }
     if (soff[j + 1] > soff[j]) {
-      std::vector<GemmDesc> part(trail.begin() + soff[j], trail.begin() + soff[j + 1]);
-      RSRS_TRY(gemm_plan<double, double>(part, soff[j], 0, 1, GM_SYRK_L, GS_64x64, "chol", tl[j]));
+      std::vector<GD> part(trail.begin() + soff[j], trail.begin() + soff[j + 1]);
+      RSRS_TRY(gemm_plan<T, T>(part, soff[j], 0, 1, GM_SYRK_L, GS_64x64, "chol", tl[j]));
     }
   }
   // diagonal inverses into G, then the doubling levels
-  std::vector<Copy2D> diag;
+  std::vector<Copy2DT<T, T>> diag;
   for (const auto& m : mats)
     for (int j0 = 0; j0 < m.n; j0 += PB) {
       const int nj = std::min(PB, m.n - j0);
-      diag.push_back(Copy2D{m.W + (int64_t)j0 * (m.ld + 1), m.G + (int64_t)j0 * (m.ld + 1), m.ld, m.ld, nj, nj,
+      diag.push_back(Copy2DT<T, T>{m.W + (int64_t)j0 * (m.ld + 1), m.G + (int64_t)j0 * (m.ld + 1), m.ld, m.ld, nj, nj,
                             1.0, 0, 0});
     }
-  std::vector<GemmDesc> inv;
+  std::vector<GD> inv;
   std::vector<std::vector<GemmLaunch>> il;
   for (int h = PB; h < nmax; h *= 2) {
-    std::vector<GemmDesc> v, x;
+    std::vector<GD> v, x;
     for (const auto& m : mats)
       for (int a0 = 0; a0 + h < m.n; a0 += 2 * h) {
         const int D0 = a0 + h, nd = std::min(h, m.n - D0);
-        double* XDD = m.G + (int64_t)D0 * (m.ld + 1);
-        double* C = m.G + (int64_t)D0 * m.ld + a0;
-        double* V = m.W + (int64_t)D0 * m.ld + a0;
-        double* XAA = m.G + (int64_t)a0 * (m.ld + 1);
+        T* XDD = m.G + (int64_t)D0 * (m.ld + 1);
+        T* C = m.G + (int64_t)D0 * m.ld + a0;
+        T* V = m.W + (int64_t)D0 * m.ld + a0;
+        T* XAA = m.G + (int64_t)a0 * (m.ld + 1);
         // V = X_DD C (X_DD lower), then X_DA = -V X_AA (X_AA lower) over C
-        v.push_back(gdesc(XDD, nullptr, m.ld, C, nullptr, m.ld, V, nullptr, m.ld, nd, h, nd));
-        x.push_back(gdesc(V, nullptr, m.ld, XAA, nullptr, m.ld, C, nullptr, m.ld, nd, h, h, -1.0, 0.0));
+        v.push_back(gdescT<T, T>(XDD, nullptr, m.ld, C, nullptr, m.ld, V, nullptr, m.ld, nd, h, nd));
+        x.push_back(gdescT<T, T>(V, nullptr, m.ld, XAA, nullptr, m.ld, C, nullptr, m.ld, nd, h, h, -1.0, 0.0));
       }
     if (v.empty()) continue;
     il.emplace_back();
-    RSRS_TRY(gemm_plan<double, double>(v, inv.size(), 0, 0, GM_A_LOW, GS_64x64, "cholinv", il.back()));
+    RSRS_TRY(gemm_plan<T, T>(v, inv.size(), 0, 0, GM_A_LOW, GS_64x64, "cholinv", il.back()));
     inv.insert(inv.end(), v.begin(), v.end());
     il.emplace_back();
-    RSRS_TRY(gemm_plan<double, double>(x, inv.size(), 0, 0, GM_B_NN_LOW, GS_64x64, "cholinv", il.back()));
+    RSRS_TRY(gemm_plan<T, T>(x, inv.size(), 0, 0, GM_B_NN_LOW, GS_64x64, "cholinv", il.back()));
     inv.insert(inv.end(), x.begin(), x.end());
   }
-  CholPanel* dt = nullptr;
-  GemmDesc* dc = nullptr;
-  GemmDesc* ds = nullptr;
-  GemmDesc* di = nullptr;
+  CholPanel<T>* dt = nullptr;
+  GD* dc = nullptr;
+  GD* ds = nullptr;
+  GD* di = nullptr;
   RSRS_TRY(up.put_vec(tasks, &dt));
   if (!colu.empty()) RSRS_TRY(up.put_vec(colu, &dc));
   if (!trail.empty()) RSRS_TRY(up.put_vec(trail, &ds));
   if (!inv.empty()) RSRS_TRY(up.put_vec(inv, &di));
   // ---- launches
   for (int j = 0; j < P; ++j) {
-    for (const auto& L : cl[j]) RSRS_TRY(gemm_exec(L, dc, sizeof(GemmDesc), st));
+    for (const auto& L : cl[j]) RSRS_TRY(gemm_exec(L, dc, sizeof(GD), st));
     const unsigned nt = (unsigned)(toff[j + 1] - toff[j]);
     {
       ProfScope ps(st, "chol_panel", pflops[j], 0.0);
-      hipLaunchKernelGGL(chol_panel_kernel, dim3(nt), dim3(256), 0, st, dt + toff[j], flag);
+      hipLaunchKernelGGL(chol_panel_kernel<T>, dim3(nt), dim3(256), 0, st, dt + toff[j], flag);
       RSRS_HIP(hipGetLastError());
     }
-    for (const auto& L : tl[j]) RSRS_TRY(gemm_exec(L, ds, sizeof(GemmDesc), st));
+    for (const auto& L : tl[j]) RSRS_TRY(gemm_exec(L, ds, sizeof(GD), st));
   }
-  RSRS_TRY(copy2d<double, double>(up, st, diag));
+  RSRS_TRY(copy2d<T, T>(up, st, diag));
   for (const auto& lv : il)
-    for (const auto& L : lv) RSRS_TRY(gemm_exec(L, di, sizeof(GemmDesc), st));
+    for (const auto& L : lv) RSRS_TRY(gemm_exec(L, di, sizeof(GD), st));
   return RSRS_OK;
 }
+
+template rsrs_status chol_inverse<double>(Uploader&, hipStream_t, const std::vector<CholMatT<double>>&, int*);
+template rsrs_status chol_inverse<float>(Uploader&, hipStream_t, const std::vector<CholMatT<float>>&, int*);
 
 }  // namespace rsrs

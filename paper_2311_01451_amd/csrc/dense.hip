@@ -164,8 +164,7 @@ static rsrs_status plan_forms(const std::vector<GemmDescT<TI, TO>>& descs, size_
 // 64 x 32, 4 waves per SIMD) reach 50+ TFLOP/s on the large FP64 products;
 // they are used whenever the batch still yields >= 256 such tiles, otherwise
 // 64 x 64 tiles on 4 waves keep the chip busy; narrow right-hand sides use
-// 64 x 16.  Mixed-type launches (FP32 operands, FP64 result) exist for the
-// Gram matrices only.
+// 64 x 16.
 template <typename TI, typename TO>
 rsrs_status gemm_plan(const std::vector<GemmDescT<TI, TO>>& descs, size_t base, int ta, int tb, int mode,
                       GemmShape shape, const char* site, std::vector<GemmLaunch>& out) {
@@ -217,8 +216,6 @@ template rsrs_status gemm<double, double>(Uploader&, hipStream_t, const std::vec
                                           int, int, int, GemmShape, const char*);
 template rsrs_status gemm<float, float>(Uploader&, hipStream_t, const std::vector<GemmDescT<float, float>>&,
                                         int, int, int, GemmShape, const char*);
-template rsrs_status gemm<float, double>(Uploader&, hipStream_t, const std::vector<GemmDescT<float, double>>&,
-                                         int, int, int, GemmShape, const char*);
 
 
 // ---------------------------------------------------------------- Gauss-Jordan

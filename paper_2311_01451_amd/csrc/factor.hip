@@ -35,10 +35,11 @@
 // Precision.  The whole class of operations is templated on the element type
 // T of the samples and of the stored factor.  T = double is plain FP64.  With
 // T = float (the mixed-precision factorization) every product of sketch-sized
-// operands runs on FP32 MFMA with FP32 accumulation, while the decisions stay
-// FP64: the Gram matrices are accumulated from FP32 operands straight into
-// FP64 storage and factored (Cholesky, inverse factor) in FP64, the pivoted
-// QR of the ID takes its dot products, norms and coefficients in FP64 (the
+// operands runs on FP32 MFMA with FP32 accumulation, and so do the Gram
+// matrices and their factorization (Cholesky, inverse factor): the Gram
+// entries already carry an FP32 accumulation error, and the FP32 Cholesky
+// adds a backward error of the same order.  The decisions stay FP64: the
+// pivoted QR of the ID takes its dot products, norms and coefficients in FP64 (the
 // working rows of M stay FP32, like the sketches they come from: each
 // stored residual is rounded relative to its own size, far below the
 // rounding M already carries), and X_RR and A_t are inverted by FP64
@@ -102,9 +103,9 @@ void box_ws_bytes(int64_t b, int64_t l, int64_t k, int64_t sp, size_t* a, size_t
   constexpr bool mixed = sizeof(T) != sizeof(double);
   const int64_t lp = round_up(l, 16);
   const int64_t r = b - k;
-  int64_t dblA = 4 * l * lp        // G, L for both sides
-                 + 2 * b + b * k;  // norms, R coefficients
-  int64_t telA = 4 * b * lp        // P, W for both sides
+  int64_t dblA = 2 * b + b * k;    // norms, R coefficients
+  int64_t telA = 4 * l * lp        // Gram matrices / inverse factors, scratch, both sides
+                 + 4 * b * lp      // P, W for both sides
                  + 2 * b * sp;     // M_Y, M_Z
   int64_t dblB = 2 * r * r;        // Gauss-Jordan work
   int64_t telB = 2 * b * lp        // X for both sides
@@ -112,7 +113,6 @@ void box_ws_bytes(int64_t b, int64_t l, int64_t k, int64_t sp, size_t* a, size_t
   if (mixed) {
     dblA += r * round_up(k, 4);    // T as computed by the ID
     dblB += 2 * r * r;             // X_RR and its inverse in FP64
-    telA += 2 * l * lp;            // rounded inverse factors
   }
   const int64_t ints = b + k;      // sel, piv (int32)
   const int64_t i64 = k + b;       // Spos, Rpos
@@ -123,8 +123,8 @@ void box_ws_bytes(int64_t b, int64_t l, int64_t k, int64_t sp, size_t* a, size_t
 template <typename T>
 struct BoxWs {
   int64_t lp;
-  double *GO, *GP, *LO, *LP, *norms, *Rc, *gje;
-  T *LOt, *LPt;                 // inverse factors in T (alias LO, LP when T = double)
+  T *GO, *GP, *LO, *LP;         // Gram matrices -> inverse factors (L), scratch (G)
+  double *norms, *Rc, *gje;
   T *PY, *WY, *XY, *PZ, *WZ, *XZ, *MY, *MZ;
   T *XRy, *XRz, *Xpy, *Xpz;
   double *Td, *XRRd, *Xinvd;   // FP64 copies (mixed precision only)
@@ -440,8 +440,8 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
       const int64_t l = R.b + R.n, lp = round_up(l, 16), b = R.b, r = R.r;
       BoxWs<T>& w = it.w;
       w.lp = lp;
-      w.GO = bump.take<double>(l * lp); w.GP = bump.take<double>(l * lp);
-      w.LO = bump.take<double>(l * lp); w.LP = bump.take<double>(l * lp);
+      w.GO = bump.take<T>(l * lp); w.GP = bump.take<T>(l * lp);
+      w.LO = bump.take<T>(l * lp); w.LP = bump.take<T>(l * lp);
       w.PY = bump.take<T>(b * lp); w.WY = bump.take<T>(b * lp);
       w.PZ = bump.take<T>(b * lp); w.WZ = bump.take<T>(b * lp);
       w.MY = bump.take<T>(b * sld); w.MZ = bump.take<T>(b * sld);
@@ -454,11 +454,9 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
       w.Spos = posall + pofs; w.Rpos = w.Spos + k;
       pofs += b;
       if constexpr (mixed) {
-        w.LOt = bump.take<T>(l * lp); w.LPt = bump.take<T>(l * lp);
         w.Td = bump.take<double>(r * round_up(k, 4));
         w.XRRd = bumpb.take<double>(r * r); w.Xinvd = bumpb.take<double>(r * r);
       } else {
-        w.LOt = reinterpret_cast<T*>(w.LO); w.LPt = reinterpret_cast<T*>(w.LP);
         w.Td = w.XRRd = w.Xinvd = nullptr;
       }
     }
@@ -467,10 +465,11 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
       return RSRS_E_INVALID;
     }
 
-    // ---- phase A: Gram matrices (FP64 storage in both precisions)
+    // ---- phase A: Gram matrices and their inverse factors, in T (FP32
+    // products and FP32 factorization on the FP32 path)
     {
-      std::vector<GemmDescT<T, double>> gd;
-      std::vector<CholMat> cm;
+      std::vector<GemmDescT<T, T>> gd;
+      std::vector<CholMatT<T>> cm;
       for (auto& it : items) {
         const BoxRec& R = *it.R;
         const Job<T>& J = *it.J;
@@ -478,29 +477,19 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
         const int l = (int)(R.b + R.n);
         const int64_t* idxC = J.iS + R.oBa;
         // the Gram matrix is factored in place: L^{-1} lands where it is used
-        gd.push_back(gdescT<T, double>(J.Om, idxC, J.sld, J.Om, idxC, J.sld, w.LO, nullptr, w.lp, l, l, (int)J.s));
-        cm.push_back(CholMat{w.LO, w.GO, w.lp, l});
+        gd.push_back(gdescT<T, T>(J.Om, idxC, J.sld, J.Om, idxC, J.sld, w.LO, nullptr, w.lp, l, l, (int)J.s));
+        cm.push_back(CholMatT<T>{w.LO, w.GO, w.lp, l});
         if (!J.sym) {
-          gd.push_back(gdescT<T, double>(J.Psi, idxC, J.sld, J.Psi, idxC, J.sld, w.LP, nullptr, w.lp, l, l, (int)J.s));
-          cm.push_back(CholMat{w.LP, w.GP, w.lp, l});
+          gd.push_back(gdescT<T, T>(J.Psi, idxC, J.sld, J.Psi, idxC, J.sld, w.LP, nullptr, w.lp, l, l, (int)J.s));
+          cm.push_back(CholMatT<T>{w.LP, w.GP, w.lp, l});
         }
         const double dl = l, db = (double)R.b, ds = (double)J.s, sides = J.sym ? 1.0 : 2.0;
         it.J->flops += sides * (dl * dl * ds                              // Gram matrices
                                 + (2.0 / 3.0) * dl * dl * dl              // Cholesky + inverse factor
                                 + (1.0 + J.reproject) * (4.0 * db * dl * ds + 2.0 * db * dl * dl));  // projections
       }
-      RSRS_TRY(gemm<T, double>(up, st, gd, 0, 1, GM_SYRK_L, GS_64x64, "gram"));
-      RSRS_TRY(chol_inverse(up, st, cm, flag));
-      if constexpr (mixed) {   // inverse factors rounded for the FP32 products
-        std::vector<Copy2DT<double, T>> lc;
-        for (auto& it : items) {
-          const int l = (int)(it.R->b + it.R->n);
-          lc.push_back(Copy2DT<double, T>{it.w.LO, it.w.LOt, it.w.lp, it.w.lp, l, l, 1.0, 0, 0});
-          if (!it.J->sym)
-            lc.push_back(Copy2DT<double, T>{it.w.LP, it.w.LPt, it.w.lp, it.w.lp, l, l, 1.0, 0, 0});
-        }
-        RSRS_TRY(copy2d<double, T>(up, st, lc));
-      }
+      RSRS_TRY(gemm<T, T>(up, st, gd, 0, 1, GM_SYRK_L, GS_64x64, "gram"));
+      RSRS_TRY(chol_inverse<T>(up, st, cm, flag));
     }
     // ---- projections (eq. nullYZ) and least-squares coefficients, once the
     // previous class has updated the sketches
@@ -524,7 +513,7 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
           T* Wb = side ? w.WZ : w.WY;
           T* Xb = side ? w.XZ : w.XY;
           T* Mb = side ? w.MZ : w.MY;
-          T* Lb = side ? w.LPt : w.LOt;
+          T* Lb = side ? w.LP : w.LO;
           T* Xout = pass == 0 ? Xb : Pb;   // second pass: correction into P
           if (pass == 0)
             gp.push_back(gdescT<T, T>(Ysd, idxB, sld, Tst, idxC, sld, Pb, nullptr, w.lp, b, l, (int)J.s));
@@ -820,7 +809,7 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
       g3.push_back(gdesc(R.Wb, nullptr, R.ntp, R.L, nullptr, R.ntp, R.At, nullptr, R.nt, R.nt, R.nt, R.nt));
     }
     RSRS_TRY(gemm(up, st, g0, 0, 1, GM_SYRK_L));
-    RSRS_TRY(chol_inverse(up, st, cm, flag));
+    RSRS_TRY(chol_inverse<double>(up, st, cm, flag));
     RSRS_TRY(gemm(up, st, g1, 0, 1, GM_FULL));
     RSRS_TRY(gemm(up, st, g2, 0, 1, GM_B_NT_LOW));
     RSRS_TRY(gemm(up, st, g3, 0, 0, GM_B_NN_LOW));

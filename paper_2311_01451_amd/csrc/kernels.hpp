@@ -51,8 +51,7 @@ rsrs_status gemm_plan(const std::vector<GemmDescT<TI, TO>>& descs, size_t base, 
                       GemmShape shape, const char* site, std::vector<GemmLaunch>& out);
 // Launches one record; descs is the device copy of the caller's array.
 rsrs_status gemm_exec(const GemmLaunch& L, const void* descs, size_t desc_bytes, hipStream_t st);
-// Instantiated for <double, double>, <float, float> (all forms) and
-// <float, double> (SYRK_L only).
+// Instantiated for <double, double> and <float, float> (all forms).
 template <typename TI, typename TO>
 rsrs_status gemm(Uploader& up, hipStream_t st, const std::vector<GemmDescT<TI, TO>>& descs, int ta,
                  int tb, int mode, GemmShape shape = GS_64x64, const char* site = nullptr);
@@ -91,13 +90,15 @@ inline GemmDesc gdesc(const double* A, const int64_t* ia, int64_t lda, const dou
 }
 
 // ---- dense helpers (dense.hip) --------------------------------------------
-struct CholMat { double* G; double* W; int64_t ld; int n; };
+template <typename T> struct CholMatT { T* G; T* W; int64_t ld; int n; };
+using CholMat = CholMatT<double>;
 // Cholesky G = L L^T of each n x n matrix (lower part of G read) and the
 // inverse factor: on return G holds L^{-1} in its lower part (the upper part
 // of its 64 x 64 diagonal blocks zero, the rest of the upper part
 // unspecified); W (same shape) is scratch.  flag[0] |= 1 when a pivot is not
-// positive.
-rsrs_status chol_inverse(Uploader& up, hipStream_t st, const std::vector<CholMat>& mats, int* flag);
+// positive.  Instantiated for double and float (FP64 / FP32 MFMA).
+template <typename T>
+rsrs_status chol_inverse(Uploader& up, hipStream_t st, const std::vector<CholMatT<T>>& mats, int* flag);
 
 struct GjeDesc { const double* A; double* W; double* Ainv; int64_t lda, ldi; int n, pad_; };
 // Inverse of each n x n matrix by Gauss-Jordan elimination with partial
