@@ -265,6 +265,13 @@ rsrs_status rsrs_factor_batched(int64_t nprob, const rsrs_tree_t* const* trees,
                                 rsrs_samples_t* const* samples, const rsrs_factor_opts* opts,
                                 void* stream, rsrs_factor_t** out);
 void rsrs_factor_destroy(rsrs_factor_t* f);
+/* A factorization's scratch (device workspace, pinned staging of its
+ * uploads) is kept when it returns and reused by the next factorization of
+ * a similar size on the same device, which saves milliseconds of allocation
+ * and release per call; at most 16 buffers and 32 GiB are kept, the oldest
+ * released first.  rsrs_release_cached frees every kept buffer (call it with
+ * no factorization running). */
+void rsrs_release_cached(void);
 
 typedef struct {
   int64_t n, s, k;

@@ -78,12 +78,15 @@ struct HostBuf {
   HostBuf() = default;
   HostBuf(const HostBuf&) = delete;
   HostBuf& operator=(const HostBuf&) = delete;
-  ~HostBuf() { if (p) (void)hipHostFree(p); }
-  rsrs_status alloc(size_t nbytes) {
-    if (nbytes <= bytes && p) return RSRS_OK;
+  ~HostBuf() { release(); }
+  void release() {
     if (p) (void)hipHostFree(p);
     p = nullptr;
     bytes = 0;
+  }
+  rsrs_status alloc(size_t nbytes) {
+    if (nbytes <= bytes && p) return RSRS_OK;
+    release();
     if (nbytes == 0) return RSRS_OK;
     hipError_t e = hipHostMalloc(&p, nbytes, hipHostMallocDefault);
     if (e != hipSuccess) {
@@ -96,6 +99,15 @@ struct HostBuf {
   }
   template <class T> T* as() const { return reinterpret_cast<T*>(p); }
 };
+
+// Scratch reuse across factorizations (pool.hip): pool_alloc takes a kept
+// buffer of a similar size on the current device, or allocates;
+// pool_return keeps the buffer for a later call.  A buffer may be returned
+// only once no queued work uses it.
+rsrs_status pool_alloc(DevBuf& b, size_t nbytes);
+rsrs_status pool_alloc(HostBuf& b, size_t nbytes);
+void pool_return(DevBuf& b);
+void pool_return(HostBuf& b);
 
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 

@@ -14,12 +14,23 @@
 namespace rsrs {
 
 // ---------------------------------------------------------------- uploader
-rsrs_status Uploader::init(size_t bytes, hipStream_t stream) {
+rsrs_status Uploader::init(size_t bytes, hipStream_t stream, bool pooled) {
   st = stream;
   off = 0;
+  if (pooled) {
+    RSRS_TRY(pool_alloc(h, bytes));
+    RSRS_TRY(pool_alloc(d, bytes));
+    return RSRS_OK;
+  }
   RSRS_TRY(h.alloc(bytes));
   RSRS_TRY(d.alloc(bytes));
   return RSRS_OK;
+}
+
+void Uploader::recycle() {
+  pool_return(h);
+  pool_return(d);
+  off = 0;
 }
 
 rsrs_status Uploader::put(const void* src, size_t n, void** dev) {

@@ -294,7 +294,7 @@ rsrs_status job_init(Job<T>& J, const rsrs_tree_t* th, rsrs_samples_t* smp,
   RSRS_TRY(F->dstore.alloc((size_t)std::max<int64_t>(dsz, 1) * sizeof(T)));
   RSRS_TRY(F->istore.alloc((size_t)std::max<int64_t>(isz, 1) * 8));
   RSRS_TRY(F->perm.alloc((size_t)J.n * 8));
-  RSRS_TRY(J.hidx.alloc((size_t)std::max<int64_t>(isz, 1) * 8));
+  RSRS_TRY(pool_alloc(J.hidx, (size_t)std::max<int64_t>(isz, 1) * 8));
   J.hI = J.hidx.template as<int64_t>();
   J.dS = F->dstore.template as<T>();
   J.iS = F->istore.template as<int64_t>();
@@ -328,30 +328,33 @@ template <typename T>
 rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
   constexpr bool mixed = Job<T>::mixed;
   auto t0 = std::chrono::steady_clock::now();
-  size_t nsteps = 0, ws_max = 0, wsb_max = 0, root_total = 0;
+  size_t nsteps = 0, ws_max = 0, wsb_max = 0, root_total = 0, pos_max = 1;
   for (auto& J : jobs) nsteps = std::max(nsteps, J.F->groups.size());
   for (size_t t = 0; t < nsteps; ++t) {
-    size_t w = 0, wb = 0;
+    size_t w = 0, wb = 0, np = 0;
     for (auto& J : jobs)
       if (t < J.class_ws.size()) {
         w += J.class_ws[t];
         wb += J.class_wsb[t];
+        const Group& g = J.F->groups[t];
+        for (int64_t q = 0; q < g.count; ++q) np += (size_t)J.F->boxes[g.first + q].b;
       }
     ws_max = std::max(ws_max, w);
     wsb_max = std::max(wsb_max, wb);
+    pos_max = std::max(pos_max, np);
   }
   for (auto& J : jobs) root_total += J.root_ws;
   ws_max = std::max(ws_max, root_total);
 
   DevBuf ws, wsb[2], flagbuf;
-  RSRS_TRY(ws.alloc(ws_max));
-  RSRS_TRY(wsb[0].alloc(std::max<size_t>(wsb_max, 256)));
-  RSRS_TRY(wsb[1].alloc(std::max<size_t>(wsb_max, 256)));
+  RSRS_TRY(pool_alloc(ws, ws_max));
+  RSRS_TRY(pool_alloc(wsb[0], std::max<size_t>(wsb_max, 256)));
+  RSRS_TRY(pool_alloc(wsb[1], std::max<size_t>(wsb_max, 256)));
   RSRS_TRY(flagbuf.alloc(256));
   int* flag = flagbuf.as<int>();
   RSRS_HIP(hipMemsetAsync(flag, 0, sizeof(int), st));
   Uploader up;
-  RSRS_TRY(up.init((size_t)64 << 20, st));
+  RSRS_TRY(up.init((size_t)64 << 20, st, true));
   // The extraction, Gauss-Jordan and sketch updates of a class run on a
   // second stream (with its own descriptor uploads) while the main stream
   // goes on with the next class's Gram matrices and Cholesky factorizations;
@@ -360,7 +363,7 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
   Uploader up2;   // declared first: destroyed after the side stream drains
   SideStream side;
   RSRS_TRY(side.init());
-  RSRS_TRY(up2.init((size_t)64 << 20, side.st));
+  RSRS_TRY(up2.init((size_t)64 << 20, side.st, true));
   const hipStream_t st2 = side.st;
   for (auto& J : jobs) {
     RSRS_HIP(hipMemcpyAsync(J.F->perm.p, J.tree().perm.data(), (size_t)J.n * 8, hipMemcpyHostToDevice, st));
@@ -381,7 +384,8 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
   // from here on the samples are modified in place
   for (auto& J : jobs) J.smp->consumed = true;
 
-  HostBuf hpos;
+  HostBuf hpos;   // skeleton positions of a class, read back
+  RSRS_TRY(pool_alloc(hpos, pos_max * 8));
   for (size_t t = 0; t < nsteps; ++t) {
     // ---- host index lists and factor-store uploads (Ba, Na, Na copy)
     std::vector<Item<T>> items;
@@ -431,6 +435,10 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
     // b entries per box), so that one copy brings them to the host
     int64_t npos = 0;
     for (auto& it : items) npos += it.R->b;
+    if ((size_t)npos > pos_max) {
+      set_error("internal: skeleton position count exceeds its plan");
+      return RSRS_E_INVALID;
+    }
     int64_t* posall = bumpb.take<int64_t>(npos);
     int64_t pofs = 0;
     for (auto& it : items) {
@@ -571,7 +579,6 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
       }
     }
     // ---- skeleton sets back to the host (one copy, positions back to back)
-    RSRS_TRY(hpos.alloc((size_t)std::max<int64_t>(npos, 1) * 8));
     RSRS_HIP(hipMemcpyAsync(hpos.as<int64_t>(), posall, (size_t)npos * 8, hipMemcpyDeviceToHost, st));
     RSRS_TRY(up.reset());
     {
@@ -865,6 +872,17 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
     J.F->flops = J.flops;
     J.F->factor_ms = ms;
   }
+  // every launch has completed: the scratch goes back to the pool for the
+  // next factorization
+  RSRS_HIP(hipStreamSynchronize(st2));
+  RSRS_HIP(hipStreamSynchronize(st));
+  pool_return(ws);
+  pool_return(wsb[0]);
+  pool_return(wsb[1]);
+  pool_return(hpos);
+  up.recycle();
+  up2.recycle();
+  for (auto& J : jobs) pool_return(J.hidx);
   return RSRS_OK;
 }
 

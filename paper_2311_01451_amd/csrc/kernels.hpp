@@ -18,7 +18,8 @@ struct Uploader {
   DevBuf d;
   size_t off = 0;
   hipStream_t st = nullptr;
-  rsrs_status init(size_t bytes, hipStream_t stream);
+  // pooled: staging taken from (and later recycled into) the scratch pool
+  rsrs_status init(size_t bytes, hipStream_t stream, bool pooled = false);
   // Copies n bytes to device; *dev receives the device address.
   rsrs_status put(const void* src, size_t n, void** dev);
   template <class T> rsrs_status put_vec(const std::vector<T>& v, T** dev) {
@@ -28,6 +29,7 @@ struct Uploader {
     return s;
   }
   rsrs_status reset();  // synchronises the stream, then recycles the space
+  void recycle();       // hands both buffers to the scratch pool (stream drained)
 };
 
 // ---- GEMM (gemm.hpp) -------------------------------------------------------

@@ -94,7 +94,7 @@ EXPORTS = [
     "rsrs_samples_required", "rsrs_op_create_kernel", "rsrs_op_create_dense",
     "rsrs_op_create_poisson7", "rsrs_op_matvec", "rsrs_op_destroy", "rsrs_samples_wrap",
     "rsrs_sample", "rsrs_sample_symmetric", "rsrs_samples_wrap_symmetric", "rsrs_samples_destroy", "rsrs_gaussian", "rsrs_factor", "rsrs_factor_batched",
-    "rsrs_factor_destroy",
+    "rsrs_factor_destroy", "rsrs_release_cached",
     "rsrs_factor_get_info", "rsrs_factor_box_sizes", "rsrs_factor_box_copy",
     "rsrs_factor_root_copy", "rsrs_solve", "rsrs_apply", "rsrs_solve_refine",
     "rsrs_profile_enable", "rsrs_profile_filter", "rsrs_profile_reset", "rsrs_profile_read", "rsrs_solve_graphs",
@@ -158,6 +158,7 @@ def lib():
         "rsrs_server_wait": (i32, [vp, i64, dbl, P(i64), P(dbl)]),
         "rsrs_server_get_stats": (i32, [vp, i32, P(ServerStats)]),
         "rsrs_profile_enable": (None, [i32]),
+        "rsrs_release_cached": (None, []),
         "rsrs_solve_graphs": (None, [i32]),
         "rsrs_profile_reset": (None, []),
         "rsrs_profile_filter": (None, [C.c_char_p]),
@@ -600,6 +601,11 @@ class Server:
         s = ServerStats()
         _check(lib().rsrs_server_get_stats(self._h, int(reset), C.byref(s)))
         return {f: getattr(s, f) for f, _ in ServerStats._fields_}
+
+
+def rsrs_release_cached():
+    """Free the factorization scratch kept for reuse by later factorizations."""
+    lib().rsrs_release_cached()
 
 
 # --------------------------------------------------------------------------- measurement
