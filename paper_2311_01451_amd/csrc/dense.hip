@@ -345,85 +345,94 @@ __global__ __launch_bounds__(1024) void gje_reg_kernel(const GjeDesc* __restrict
     }
 }
 
-// Gauss-Jordan for blocks too large for registers: the working matrix W
-// (n x 2n, [A | I]) stays in global memory and every step is two launches
-// over all column blocks: (a) one workgroup per matrix finds the pivot of
-// column j, swaps rows j and p and snapshots the scaled pivot row and the
-// multiplier column; (b) every workgroup updates its column block from the
-// snapshots.  The snapshots make the update free of read/write races.
-__global__ __launch_bounds__(256) void gje_pivot_kernel(const GjeDesc* __restrict__ e, double* snap,
-                                                        int64_t snap_stride, int j, int* flag) {
-  const GjeDesc d = e[blockIdx.x];
+// Gauss-Jordan for blocks too large for registers, one launch per pivot
+// step.  The working matrix alternates between the two n x n halves of W
+// (step j reads what step j - 1 wrote, the first step reads A), so no
+// workgroup reads what another writes in the same launch.  Every workgroup
+// of a matrix finds the pivot of column j itself (same data, same reduction
+// order: all agree) and updates its 64 columns; pivoting is implicit as in
+// the register kernel (rows are never swapped; the rows already used, known
+// from the recorded pivots, are skipped), and the write-out applies the
+// permutation.
+__global__ __launch_bounds__(256) void gje_step_kernel(const GjeDesc* __restrict__ e, int* pivs,
+                                                       int64_t pstride, int j, int* flag) {
+  const GjeDesc d = e[blockIdx.y];
   const int n = d.n;
-  if (j >= n) return;
-  const int n2 = 2 * n;
-  double* W = d.W;
-  double* prow = snap + blockIdx.x * snap_stride;   // 2n
-  double* fcol = prow + n2;                         // n
+  const int c0 = blockIdx.x * 64;
+  if (j >= n || c0 >= n) return;   // uniform per workgroup, before any barrier
+  const int64_t nn = (int64_t)n * n;
+  const double* in = j == 0 ? d.A : d.W + ((j - 1) & 1) * nn;
+  const int64_t ldi = j == 0 ? d.lda : n;
+  double* out = d.W + (j & 1) * nn;
+  int* piv = pivs + blockIdx.y * pstride;
+  __shared__ unsigned used[2048];   // one bit per row (n <= 65536)
   __shared__ double rv[256];
   __shared__ int ri[256];
   const int tid = threadIdx.x;
+  const int words = (n + 31) >> 5;
+  for (int w = tid; w < words; w += 256) used[w] = 0u;
+  __syncthreads();
+  for (int t = tid; t < j; t += 256) {
+    const int r = piv[t];
+    atomicOr(&used[r >> 5], 1u << (r & 31));
+  }
+  __syncthreads();
+  // pivot: largest |a_ij| over unused rows, lowest index on ties; the first
+  // unused row is taken when all are zero, so the pivots form a permutation
   double best = -1.0;
   int bi = n;
-  for (int i = j + tid; i < n; i += 256) {
-    const double v = fabs(W[(int64_t)i * n2 + j]);
-    if (v > best) { best = v; bi = i; }
+  for (int i = tid; i < n; i += 256) {
+    const bool free_row = !((used[i >> 5] >> (i & 31)) & 1u);
+    const double v = fabs(in[(int64_t)i * ldi + j]);
+    const bool take = free_row && (bi == n || v > best);
+    best = take ? v : best;
+    bi = take ? i : bi;
   }
   rv[tid] = best;
   ri[tid] = bi;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if (tid < w) {
-      const double o = rv[tid + w];
+      const double ob = rv[tid + w];
       const int oi = ri[tid + w];
-      if (o > rv[tid] || (o == rv[tid] && oi < ri[tid])) { rv[tid] = o; ri[tid] = oi; }
+      const int cb = ri[tid];
+      if (oi != n && (cb == n || ob > rv[tid] || (ob == rv[tid] && oi < cb))) {
+        rv[tid] = ob;
+        ri[tid] = oi;
+      }
     }
     __syncthreads();
   }
-  int p = ri[0];
-  if (!(rv[0] > 0.0)) {
-    if (tid == 0) atomicOr(flag, 2);
-    p = j;
+  const int p = ri[0];
+  if (blockIdx.x == 0 && tid == 0) {
+    if (!(rv[0] > 0.0)) atomicOr(flag, 2);
+    piv[j] = p;   // read by later launches only
   }
-  if (p != j)
-    for (int c = tid; c < n2; c += 256) {
-      const double a = W[(int64_t)j * n2 + c];
-      W[(int64_t)j * n2 + c] = W[(int64_t)p * n2 + c];
-      W[(int64_t)p * n2 + c] = a;
-    }
-  __syncthreads();
-  const double pv = W[(int64_t)j * n2 + j];
+  const double pv = in[(int64_t)p * ldi + j];
   const double inv = pv != 0.0 ? 1.0 / pv : 0.0;
-  for (int c = tid; c < n2; c += 256) prow[c] = W[(int64_t)j * n2 + c] * inv;
-  for (int i = tid; i < n; i += 256) fcol[i] = W[(int64_t)i * n2 + j];
+  // thread (wave, lane): column c0 + lane, rows wave, wave + 4, ...
+  const int c = c0 + (tid & 63);
+  if (c >= n) return;   // no barrier follows
+  const bool isj = c == j;
+  const double rp = in[(int64_t)p * ldi + c];
+  const double prow = isj ? inv : rp * inv;
+  for (int i = tid >> 6; i < n; i += 4) {
+    const double fi = in[(int64_t)i * ldi + j] * inv;
+    const double g = isj ? -fi : in[(int64_t)i * ldi + c] - fi * rp;
+    out[(int64_t)i * n + c] = (i == p) ? prow : g;
+  }
 }
 
-__global__ __launch_bounds__(256) void gje_update_kernel(const GjeDesc* __restrict__ e, const double* snap,
-                                                         int64_t snap_stride, int j) {
+// A^{-1}[i][piv[c]] = W[piv[i]][c] from the half of W the last step wrote.
+__global__ __launch_bounds__(256) void gje_out_kernel(const GjeDesc* __restrict__ e, const int* pivs,
+                                                      int64_t pstride) {
   const GjeDesc d = e[blockIdx.y];
   const int n = d.n;
-  if (j >= n) return;
-  const int n2 = 2 * n;
-  const int c = blockIdx.x * 64 + (threadIdx.x & 63);
-  if (c >= n2) return;
-  const double* prow = snap + blockIdx.y * snap_stride;
-  const double* fcol = prow + n2;
-  const double pc = prow[c];
-  for (int i = threadIdx.x >> 6; i < n; i += 4) {
-    double* w = d.W + (int64_t)i * n2 + c;
-    *w = (i == j) ? pc : *w - fcol[i] * pc;
-  }
-}
-
-__global__ void gje_copyout_kernel(const GjeDesc* __restrict__ e, int phase) {
-  const GjeDesc d = e[blockIdx.y];
-  const int n = d.n, n2 = 2 * n;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < (int64_t)n * n;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(idx / n), c = (int)(idx % n);
-    if (phase == 0) d.W[(int64_t)i * n2 + c] = d.A[(int64_t)i * d.lda + c],
-                    d.W[(int64_t)i * n2 + n + c] = (i == c) ? 1.0 : 0.0;
-    else d.Ainv[(int64_t)i * d.ldi + c] = d.W[(int64_t)i * n2 + n + c];
+  const double* w = d.W + ((n - 1) & 1) * (int64_t)n * n;
+  const int* piv = pivs + blockIdx.y * pstride;
+  for (int i = blockIdx.x; i < n; i += gridDim.x) {
+    const double* src = w + (int64_t)piv[i] * n;
+    for (int c = threadIdx.x; c < n; c += 256) d.Ainv[(int64_t)i * d.ldi + piv[c]] = src[c];
   }
 }
 
@@ -449,20 +458,18 @@ static rsrs_status gje_group(Uploader& up, hipStream_t st, const std::vector<Gje
   }
   int nmax = 0;
   for (const auto& x : e) nmax = std::max(nmax, x.n);
-  // large blocks: snapshots of (pivot row, multiplier column) per matrix
-  const int64_t stride = round_up(3 * (int64_t)nmax, 64);
-  DevBuf snap;
-  RSRS_TRY(snap.alloc((size_t)stride * nb * 8));
+  // large blocks: the pivot rows of each matrix, recorded step by step
+  const int64_t stride = round_up((int64_t)nmax, 64);
+  DevBuf pivs;
+  RSRS_TRY(pivs.alloc((size_t)stride * nb * sizeof(int)));
   ProfScope ps(st, "gauss_jordan_big");
-  const unsigned cblk = (unsigned)((2 * nmax + 63) / 64);
-  hipLaunchKernelGGL(gje_copyout_kernel, dim3(256, nb), dim3(256), 0, st, de, 0);
-  for (int j = 0; j < nmax; ++j) {
-    hipLaunchKernelGGL(gje_pivot_kernel, dim3(nb), dim3(256), 0, st, de, snap.as<double>(), stride, j, flag);
-    hipLaunchKernelGGL(gje_update_kernel, dim3(cblk, nb), dim3(256), 0, st, de, snap.as<double>(), stride, j);
-  }
-  hipLaunchKernelGGL(gje_copyout_kernel, dim3(256, nb), dim3(256), 0, st, de, 1);
+  const unsigned cblk = (unsigned)((nmax + 63) / 64);
+  for (int j = 0; j < nmax; ++j)
+    hipLaunchKernelGGL(gje_step_kernel, dim3(cblk, nb), dim3(256), 0, st, de, pivs.as<int>(), stride, j, flag);
+  hipLaunchKernelGGL(gje_out_kernel, dim3((unsigned)std::min(nmax, 1024), nb), dim3(256), 0, st, de,
+                     pivs.as<int>(), stride);
   RSRS_HIP(hipGetLastError());
-  // the snapshot buffer must outlive the launches
+  // the pivot buffer must outlive the launches
   RSRS_HIP(hipStreamSynchronize(st));
   return RSRS_OK;
 }

@@ -104,7 +104,7 @@ rsrs_status chol_inverse(Uploader& up, hipStream_t st, const std::vector<CholMat
 
 struct GjeDesc { const double* A; double* W; double* Ainv; int64_t lda, ldi; int n, pad_; };
 // Inverse of each n x n matrix by Gauss-Jordan elimination with partial
-// pivoting (W: n x 2n workspace).  flag[0] |= 2 on an exactly zero pivot.
+// pivoting (W: 2 n^2 workspace).  flag[0] |= 2 on an exactly zero pivot.
 rsrs_status gje_inverse(Uploader& up, hipStream_t st, const std::vector<GjeDesc>& e, int* flag);
 
 // Y (M x N) = A (M x K) X (K x N), FP64, for narrow X (N <= 16) on a dense

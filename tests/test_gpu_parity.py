@@ -237,6 +237,22 @@ def test_parity_small_log_kernel():
     _solution_checks(P)
 
 
+def test_parity_root_above_register_size():
+    """A 224 x 224 root block (4 boxes x k = 56), beyond the register
+    Gauss-Jordan kernels (n <= 192): inverted by the one-launch-per-step
+    form; the root block, solve and apply must match the oracle."""
+    need_gpu()
+    P = _log_problem(64, 64, 56)
+    worst, ncmp = compare_boxes(P)
+    print(f"[parity] {ncmp} boxes, worst error / predicted {worst:.2f}")
+    Bt, At = P.F.root()
+    assert len(Bt) == 224
+    if ncmp == len(P.Fo.boxes):   # else rounding-level pivots: solutions only
+        assert np.array_equal(Bt, P.Fo.Bt)
+        assert relmax(At, P.Fo.At) < 100.0 * P.max_pred
+    _solution_checks(P)
+
+
 def test_parity_nonsymmetric_operator():
     need_gpu()
     P = _log_problem(32, 32, 16, skew=5e-3)
