@@ -30,7 +30,9 @@
 // main stream meanwhile forms the next class's Gram matrices and factors
 // them, and waits for phase B only before the next projections, which read
 // the updated Y / Z.  What phase B reads lives in a part of the workspace
-// that alternates between two buffers from class to class.
+// that alternates between two buffers from class to class.  Phase B's
+// launches are enqueued by a second host thread, so that the calling
+// thread builds the next class's index lists meanwhile.
 //
 // Precision.  The whole class of operations is templated on the element type
 // T of the samples and of the stored factor.  T = double is plain FP64.  With
@@ -49,8 +51,12 @@
 
 #include <algorithm>
 #include <chrono>
+#include <condition_variable>
 #include <cstring>
+#include <functional>
+#include <mutex>
 #include <numeric>
+#include <thread>
 #include <unordered_map>
 
 #include "impl.hpp"
@@ -90,6 +96,82 @@ struct SideStream {
     }
     if (eA) (void)hipEventDestroy(eA);
     if (eB) (void)hipEventDestroy(eB);
+  }
+};
+
+// A host thread that enqueues phase B of a class on the side stream while
+// the calling thread goes on with the next class (the HIP calls that
+// enqueue phase B's launches and uploads take hundreds of microseconds of
+// host time per class).  One task at a time; join() waits until the task
+// has been enqueued and returns its status (and error message).  The
+// destructor lets a running task finish.
+struct EnqueueWorker {
+  std::thread th;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::function<rsrs_status()> task;
+  bool has_task = false, busy = false, quit = false;
+  rsrs_status status = RSRS_OK;
+  std::string err;
+  int dev = 0;
+
+  rsrs_status start() {
+    RSRS_HIP(hipGetDevice(&dev));
+    try {
+      th = std::thread([this] { loop(); });
+    } catch (...) {
+      set_error("could not start the enqueue thread");
+      return RSRS_E_INVALID;
+    }
+    return RSRS_OK;
+  }
+  void loop() {
+    (void)hipSetDevice(dev);
+    for (;;) {
+      std::function<rsrs_status()> f;
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        cv.wait(lk, [&] { return has_task || quit; });
+        if (!has_task) return;
+        f = std::move(task);
+        has_task = false;
+      }
+      const rsrs_status s = f();
+      std::string e = s == RSRS_OK ? std::string() : std::string(rsrs_last_error());
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        if (status == RSRS_OK) {
+          status = s;
+          err = std::move(e);
+        }
+        busy = false;
+      }
+      cv.notify_all();
+    }
+  }
+  void submit(std::function<rsrs_status()> f) {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      task = std::move(f);
+      has_task = true;
+      busy = true;
+    }
+    cv.notify_all();
+  }
+  rsrs_status join() {
+    std::unique_lock<std::mutex> lk(mu);
+    cv.wait(lk, [&] { return !busy; });
+    const rsrs_status s = status;
+    if (s != RSRS_OK) set_error(err);
+    return s;
+  }
+  ~EnqueueWorker() {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      quit = true;
+    }
+    cv.notify_all();
+    if (th.joinable()) th.join();
   }
 };
 
@@ -159,6 +241,7 @@ struct Job {
   std::vector<size_t> class_ws, class_wsb;    // workspace bytes of each class (two parts)
   size_t root_ws = 0;
   double flops = 0.0;
+  double flops_b = 0.0;   // phase B's share (accumulated by the enqueue thread)
 
   const Tree& tree() const { return th->t; }
   std::vector<int64_t> leaf_range(int64_t b) const {
@@ -365,6 +448,8 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
   RSRS_TRY(side.init());
   RSRS_TRY(up2.init((size_t)64 << 20, side.st, true));
   const hipStream_t st2 = side.st;
+  EnqueueWorker worker;   // declared after up2 / side: finishes before they go
+  RSRS_TRY(worker.start());
   for (auto& J : jobs) {
     RSRS_HIP(hipMemcpyAsync(J.F->perm.p, J.tree().perm.data(), (size_t)J.n * 8, hipMemcpyHostToDevice, st));
     // non-finite samples are rejected up front
@@ -501,7 +586,10 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
     }
     // ---- projections (eq. nullYZ) and least-squares coefficients, once the
     // previous class has updated the sketches
-    if (t > 0) RSRS_HIP(hipStreamWaitEvent(st, side.eB, 0));
+    if (t > 0) {
+      RSRS_TRY(worker.join());   // phase B of the previous class is enqueued
+      RSRS_HIP(hipStreamWaitEvent(st, side.eB, 0));
+    }
     for (int pass = 0; pass <= 1; ++pass) {
       std::vector<GemmDescT<T, T>> gp, gw, gx, gm;
       std::vector<Copy2DT<T, T>> acc;
@@ -631,107 +719,111 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
     }
     RSRS_HIP(hipEventRecord(side.eA, st));
     RSRS_HIP(hipStreamWaitEvent(st2, side.eA, 0));
-    {
-      std::vector<GemmDescT<T, T>> gxr;
-      std::vector<ColfixDescT<T>> cf;
-      std::vector<Copy2DT<T, T>> cx;
-      std::vector<Copy2DT<T, double>> cxd;
-      std::vector<Copy2DT<double, T>> cinv;
-      std::vector<GjeDesc> gj;
-      std::vector<SymDesc<T>> symx;
-      std::vector<SymDesc<double>> symi;
-      for (auto& it : items) {
-        const BoxRec& R = *it.R;
-        Job<T>& J = *it.J;
-        const BoxWs<T>& w = it.w;
-        const int k = J.k;
-        T* dS = J.dS;
-        const int l = (int)(R.b + R.n), r = (int)R.r;
-        if (J.sym) {   // symmetric part of X_RR, and of its inverse below
-          symx.push_back(SymDesc<T>{w.Xpy, w.lp, r, 0});
-          if constexpr (mixed) symi.push_back(SymDesc<double>{w.Xinvd, r, r, 0});
-          else symi.push_back(SymDesc<double>{reinterpret_cast<double*>(dS + R.oXinv), R.ldR, r, 0});
+    // phase B of this class, enqueued on the side stream by the worker
+    worker.submit([&, items = std::move(items)]() -> rsrs_status {
+      {
+        std::vector<GemmDescT<T, T>> gxr;
+        std::vector<ColfixDescT<T>> cf;
+        std::vector<Copy2DT<T, T>> cx;
+        std::vector<Copy2DT<T, double>> cxd;
+        std::vector<Copy2DT<double, T>> cinv;
+        std::vector<GjeDesc> gj;
+        std::vector<SymDesc<T>> symx;
+        std::vector<SymDesc<double>> symi;
+        for (auto& it : items) {
+          const BoxRec& R = *it.R;
+          Job<T>& J = *it.J;
+          const BoxWs<T>& w = it.w;
+          const int k = J.k;
+          T* dS = J.dS;
+          const int l = (int)(R.b + R.n), r = (int)R.r;
+          if (J.sym) {   // symmetric part of X_RR, and of its inverse below
+            symx.push_back(SymDesc<T>{w.Xpy, w.lp, r, 0});
+            if constexpr (mixed) symi.push_back(SymDesc<double>{w.Xinvd, r, r, 0});
+            else symi.push_back(SymDesc<double>{reinterpret_cast<double*>(dS + R.oXinv), R.ldR, r, 0});
+          }
+          for (int side = 0; side < (J.sym ? 1 : 2); ++side) {
+            T* Xb = side ? w.XZ : w.XY;
+            T* XR = side ? w.XRz : w.XRy;
+            T* Xp = side ? w.Xpz : w.Xpy;
+            gxr.push_back(gdescT<T, T>(dS + R.oT, nullptr, R.ldT, Xb, w.Spos, w.lp, XR, nullptr, w.lp, r, l, k,
+                                       -1.0, 1.0, Xb, w.Rpos, w.lp));
+            cf.push_back(ColfixDescT<T>{XR, w.Spos, w.Rpos, dS + R.oT, Xp, w.lp, w.lp, R.ldT, r, k, (int)R.b, l});
+          }
+          cx.push_back(Copy2DT<T, T>{w.Xpy, dS + R.oXRR, w.lp, R.ldR, r, r, 1.0, 0, 0});
+          if constexpr (mixed) {   // FP64 Gauss-Jordan on X_RR, inverse rounded
+            cxd.push_back(Copy2DT<T, double>{w.Xpy, w.XRRd, w.lp, r, r, r, 1.0, 0, 0});
+            gj.push_back(GjeDesc{w.XRRd, w.gje, w.Xinvd, r, r, r, 0});
+            cinv.push_back(Copy2DT<double, T>{w.Xinvd, dS + R.oXinv, r, R.ldR, r, r, 1.0, 0, 0});
+          } else {
+            gj.push_back(GjeDesc{reinterpret_cast<const double*>(w.Xpy), w.gje,
+                                 reinterpret_cast<double*>(dS + R.oXinv), w.lp, R.ldR, r, 0});
+          }
+          const double dr = r, dk = k, dn = (double)R.n, ds = (double)J.s, sides = J.sym ? 1.0 : 2.0;
+          J.flops_b += sides * (2.0 * dr * dk * l + 2.0 * dr * dr * dk) + 2.0 * dr * dr * dr +
+                     sides * 2.0 * dr * dr * (dk + dn) + sides * 2.0 * 2.0 * dr * dk * ds +
+                     sides * 2.0 * 2.0 * dr * (dk + dn) * ds;
         }
-        for (int side = 0; side < (J.sym ? 1 : 2); ++side) {
-          T* Xb = side ? w.XZ : w.XY;
-          T* XR = side ? w.XRz : w.XRy;
-          T* Xp = side ? w.Xpz : w.Xpy;
-          gxr.push_back(gdescT<T, T>(dS + R.oT, nullptr, R.ldT, Xb, w.Spos, w.lp, XR, nullptr, w.lp, r, l, k,
-                                     -1.0, 1.0, Xb, w.Rpos, w.lp));
-          cf.push_back(ColfixDescT<T>{XR, w.Spos, w.Rpos, dS + R.oT, Xp, w.lp, w.lp, R.ldT, r, k, (int)R.b, l});
+        RSRS_TRY(gemm<T, T>(up2, st2, gxr, 0, 0, GM_FULL, GS_64x64, "extract"));
+        RSRS_TRY(colfix<T>(up2, st2, cf));
+        RSRS_TRY(symmetrize<T>(up2, st2, symx));
+        RSRS_TRY(copy2d<T, T>(up2, st2, cx));
+        RSRS_TRY(copy2d<T, double>(up2, st2, cxd));
+        RSRS_TRY(gje_inverse(up2, st2, gj, flag));
+        RSRS_TRY(symmetrize<double>(up2, st2, symi));
+        RSRS_TRY(copy2d<double, T>(up2, st2, cinv));
+      }
+      {
+        std::vector<GemmDescT<T, T>> gku, gkl;
+        std::vector<Copy2DT<T, T>> ktr;
+        for (auto& it : items) {
+          const BoxRec& R = *it.R;
+          const BoxWs<T>& w = it.w;
+          T* dS = it.J->dS;
+          const int r = (int)R.r, kn = (int)(it.J->k + R.n);
+          gku.push_back(gdescT<T, T>(dS + R.oXinv, nullptr, R.ldR, w.Xpy + r, nullptr, w.lp, dS + R.oKU, nullptr, R.ldKU, r, kn, r));
+          if (it.J->sym)   // K_L = K_U^T
+            ktr.push_back(Copy2DT<T, T>{dS + R.oKU, dS + R.oKL, R.ldKU, R.ldR, kn, r, 1.0, 0, 1});
+          else
+            gkl.push_back(gdescT<T, T>(w.Xpz + r, nullptr, w.lp, dS + R.oXinv, nullptr, R.ldR, dS + R.oKL, nullptr, R.ldR, kn, r, r));
         }
-        cx.push_back(Copy2DT<T, T>{w.Xpy, dS + R.oXRR, w.lp, R.ldR, r, r, 1.0, 0, 0});
-        if constexpr (mixed) {   // FP64 Gauss-Jordan on X_RR, inverse rounded
-          cxd.push_back(Copy2DT<T, double>{w.Xpy, w.XRRd, w.lp, r, r, r, 1.0, 0, 0});
-          gj.push_back(GjeDesc{w.XRRd, w.gje, w.Xinvd, r, r, r, 0});
-          cinv.push_back(Copy2DT<double, T>{w.Xinvd, dS + R.oXinv, r, R.ldR, r, r, 1.0, 0, 0});
-        } else {
-          gj.push_back(GjeDesc{reinterpret_cast<const double*>(w.Xpy), w.gje,
-                               reinterpret_cast<double*>(dS + R.oXinv), w.lp, R.ldR, r, 0});
+        RSRS_TRY(gemm<T, T>(up2, st2, gku, 0, 0, GM_FULL, GS_64x64, "mult"));
+        RSRS_TRY(gemm<T, T>(up2, st2, gkl, 1, 0, GM_FULL, GS_64x64, "mult"));
+        RSRS_TRY(copy2d<T, T>(up2, st2, ktr));
+      }
+      // ---- sketch updates: sparsify (E) then eliminate (L, U)
+      {
+        std::vector<GemmDescT<T, T>> s0, e0, e1, e0b, e1b;
+        for (auto& it : items) {
+          const BoxRec& R = *it.R;
+          const Job<T>& J = *it.J;
+          const int k = J.k, s = (int)J.s;
+          const int64_t sld = J.sld;
+          const int r = (int)R.r, kn = (int)(k + R.n);
+          const int64_t* gR = J.iS + R.oR;
+          const int64_t* gS = J.iS + R.oS;
+          const int64_t* gSN = J.iS + R.oS;
+          const T* Tm = J.dS + R.oT;
+          const T* KU = J.dS + R.oKU;
+          const T* KL = J.dS + R.oKL;
+          const int64_t lT = R.ldT, lR = R.ldR, lU = R.ldKU;
+          s0.push_back(gdescT<T, T>(Tm, nullptr, lT, J.Y, gS, sld, J.Y, gR, sld, r, s, k, -1.0, 1.0));
+          e0.push_back(gdescT<T, T>(KL, nullptr, lR, J.Y, gR, sld, J.Y, gSN, sld, kn, s, r, -1.0, 1.0));
+          e0b.push_back(gdescT<T, T>(KU, nullptr, lU, J.Om, gSN, sld, J.Om, gR, sld, r, s, kn, 1.0, 1.0));
+          if (J.sym) continue;   // Z = Y and Psi = Omega: nothing more to update
+          s0.push_back(gdescT<T, T>(Tm, nullptr, lT, J.Z, gS, sld, J.Z, gR, sld, r, s, k, -1.0, 1.0));
+          e1.push_back(gdescT<T, T>(KU, nullptr, lU, J.Z, gR, sld, J.Z, gSN, sld, kn, s, r, -1.0, 1.0));
+          e1b.push_back(gdescT<T, T>(KL, nullptr, lR, J.Psi, gSN, sld, J.Psi, gR, sld, r, s, kn, 1.0, 1.0));
         }
-        const double dr = r, dk = k, dn = (double)R.n, ds = (double)J.s, sides = J.sym ? 1.0 : 2.0;
-        J.flops += sides * (2.0 * dr * dk * l + 2.0 * dr * dr * dk) + 2.0 * dr * dr * dr +
-                   sides * 2.0 * dr * dr * (dk + dn) + sides * 2.0 * 2.0 * dr * dk * ds +
-                   sides * 2.0 * 2.0 * dr * (dk + dn) * ds;
+        RSRS_TRY(gemm<T, T>(up2, st2, s0, 0, 0, GM_FULL, GS_64x64, "sparsify"));
+        RSRS_TRY(gemm<T, T>(up2, st2, e0, 0, 0, GM_FULL, GS_64x64, "elim"));
+        RSRS_TRY(gemm<T, T>(up2, st2, e1, 1, 0, GM_FULL, GS_64x64, "elim"));
+        RSRS_TRY(gemm<T, T>(up2, st2, e0b, 0, 0, GM_FULL, GS_64x64, "elim_r"));
+        RSRS_TRY(gemm<T, T>(up2, st2, e1b, 1, 0, GM_FULL, GS_64x64, "elim_r"));
       }
-      RSRS_TRY(gemm<T, T>(up2, st2, gxr, 0, 0, GM_FULL, GS_64x64, "extract"));
-      RSRS_TRY(colfix<T>(up2, st2, cf));
-      RSRS_TRY(symmetrize<T>(up2, st2, symx));
-      RSRS_TRY(copy2d<T, T>(up2, st2, cx));
-      RSRS_TRY(copy2d<T, double>(up2, st2, cxd));
-      RSRS_TRY(gje_inverse(up2, st2, gj, flag));
-      RSRS_TRY(symmetrize<double>(up2, st2, symi));
-      RSRS_TRY(copy2d<double, T>(up2, st2, cinv));
-    }
-    {
-      std::vector<GemmDescT<T, T>> gku, gkl;
-      std::vector<Copy2DT<T, T>> ktr;
-      for (auto& it : items) {
-        const BoxRec& R = *it.R;
-        const BoxWs<T>& w = it.w;
-        T* dS = it.J->dS;
-        const int r = (int)R.r, kn = (int)(it.J->k + R.n);
-        gku.push_back(gdescT<T, T>(dS + R.oXinv, nullptr, R.ldR, w.Xpy + r, nullptr, w.lp, dS + R.oKU, nullptr, R.ldKU, r, kn, r));
-        if (it.J->sym)   // K_L = K_U^T
-          ktr.push_back(Copy2DT<T, T>{dS + R.oKU, dS + R.oKL, R.ldKU, R.ldR, kn, r, 1.0, 0, 1});
-        else
-          gkl.push_back(gdescT<T, T>(w.Xpz + r, nullptr, w.lp, dS + R.oXinv, nullptr, R.ldR, dS + R.oKL, nullptr, R.ldR, kn, r, r));
-      }
-      RSRS_TRY(gemm<T, T>(up2, st2, gku, 0, 0, GM_FULL, GS_64x64, "mult"));
-      RSRS_TRY(gemm<T, T>(up2, st2, gkl, 1, 0, GM_FULL, GS_64x64, "mult"));
-      RSRS_TRY(copy2d<T, T>(up2, st2, ktr));
-    }
-    // ---- sketch updates: sparsify (E) then eliminate (L, U)
-    {
-      std::vector<GemmDescT<T, T>> s0, e0, e1, e0b, e1b;
-      for (auto& it : items) {
-        const BoxRec& R = *it.R;
-        const Job<T>& J = *it.J;
-        const int k = J.k, s = (int)J.s;
-        const int64_t sld = J.sld;
-        const int r = (int)R.r, kn = (int)(k + R.n);
-        const int64_t* gR = J.iS + R.oR;
-        const int64_t* gS = J.iS + R.oS;
-        const int64_t* gSN = J.iS + R.oS;
-        const T* Tm = J.dS + R.oT;
-        const T* KU = J.dS + R.oKU;
-        const T* KL = J.dS + R.oKL;
-        const int64_t lT = R.ldT, lR = R.ldR, lU = R.ldKU;
-        s0.push_back(gdescT<T, T>(Tm, nullptr, lT, J.Y, gS, sld, J.Y, gR, sld, r, s, k, -1.0, 1.0));
-        e0.push_back(gdescT<T, T>(KL, nullptr, lR, J.Y, gR, sld, J.Y, gSN, sld, kn, s, r, -1.0, 1.0));
-        e0b.push_back(gdescT<T, T>(KU, nullptr, lU, J.Om, gSN, sld, J.Om, gR, sld, r, s, kn, 1.0, 1.0));
-        if (J.sym) continue;   // Z = Y and Psi = Omega: nothing more to update
-        s0.push_back(gdescT<T, T>(Tm, nullptr, lT, J.Z, gS, sld, J.Z, gR, sld, r, s, k, -1.0, 1.0));
-        e1.push_back(gdescT<T, T>(KU, nullptr, lU, J.Z, gR, sld, J.Z, gSN, sld, kn, s, r, -1.0, 1.0));
-        e1b.push_back(gdescT<T, T>(KL, nullptr, lR, J.Psi, gSN, sld, J.Psi, gR, sld, r, s, kn, 1.0, 1.0));
-      }
-      RSRS_TRY(gemm<T, T>(up2, st2, s0, 0, 0, GM_FULL, GS_64x64, "sparsify"));
-      RSRS_TRY(gemm<T, T>(up2, st2, e0, 0, 0, GM_FULL, GS_64x64, "elim"));
-      RSRS_TRY(gemm<T, T>(up2, st2, e1, 1, 0, GM_FULL, GS_64x64, "elim"));
-      RSRS_TRY(gemm<T, T>(up2, st2, e0b, 0, 0, GM_FULL, GS_64x64, "elim_r"));
-      RSRS_TRY(gemm<T, T>(up2, st2, e1b, 1, 0, GM_FULL, GS_64x64, "elim_r"));
-    }
-    RSRS_HIP(hipEventRecord(side.eB, st2));
+      RSRS_HIP(hipEventRecord(side.eB, st2));
+      return RSRS_OK;
+    });
     // ---- advance every job past this class
     for (auto& J : jobs) {
       if (t >= J.F->groups.size()) continue;
@@ -744,6 +836,7 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
   }
 
   // ---- roots: A_t = Y_Bt pinv(Omega_Bt), all problems in the same launches
+  RSRS_TRY(worker.join());
   if (nsteps > 0) RSRS_HIP(hipStreamWaitEvent(st, side.eB, 0));
   {
     Bump bump{ws.as<char>(), 0, ws.bytes};
@@ -869,7 +962,7 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
   }
   const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   for (auto& J : jobs) {
-    J.F->flops = J.flops;
+    J.F->flops = J.flops + J.flops_b;
     J.F->factor_ms = ms;
   }
   // every launch has completed: the scratch goes back to the pool for the
