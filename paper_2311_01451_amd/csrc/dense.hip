@@ -445,8 +445,15 @@ static rsrs_status gje_group(Uploader& up, hipStream_t st, const std::vector<Gje
   GjeDesc* de = nullptr;
   RSRS_TRY(up.put_vec(e, &de));
   const unsigned nb = (unsigned)e.size();
+  // algorithmic work: 2 n^3 flops per inversion (n^3 multiply-adds), one
+  // FP64 read of A and one write of its inverse
+  double gf = 0.0, gb = 0.0;
+  for (const auto& x : e) {
+    gf += 2.0 * (double)x.n * x.n * x.n;
+    gb += 16.0 * (double)x.n * x.n;
+  }
   if (variant < 3) {
-    ProfScope ps(st, "gauss_jordan_reg");
+    ProfScope ps(st, "gauss_jordan_reg", gf, gb);
     if (variant == 0)
       hipLaunchKernelGGL(gje_reg_kernel<2>, dim3(nb), dim3(1024), 0, st, de, flag);
     else if (variant == 1)
@@ -462,7 +469,7 @@ static rsrs_status gje_group(Uploader& up, hipStream_t st, const std::vector<Gje
   const int64_t stride = round_up((int64_t)nmax, 64);
   DevBuf pivs;
   RSRS_TRY(pivs.alloc((size_t)stride * nb * sizeof(int)));
-  ProfScope ps(st, "gauss_jordan_big");
+  ProfScope ps(st, "gauss_jordan_big", gf, gb);
   const unsigned cblk = (unsigned)((nmax + 63) / 64);
   for (int j = 0; j < nmax; ++j)
     hipLaunchKernelGGL(gje_step_kernel, dim3(cblk, nb), dim3(256), 0, st, de, pivs.as<int>(), stride, j, flag);

@@ -80,14 +80,39 @@ struct Bump {
 
 // A second stream and the two events that order it against the main one;
 // the destructor drains it, so no kernel outlives the workspace it reads.
+// The side stream and its two events.  Creating a stream costs a fraction
+// of a millisecond, so a drained one is kept per device for the next
+// factorization (recycle()); one that is not recycled is destroyed.
 struct SideStream {
   hipStream_t st = nullptr;
   hipEvent_t eA = nullptr, eB = nullptr;
+  int dev = 0;
+  struct Kept { hipStream_t st; hipEvent_t eA, eB; int dev; };
+  static std::mutex& kept_mu() { static std::mutex m; return m; }
+  static std::vector<Kept>& kept() { static auto* v = new std::vector<Kept>(); return *v; }
   rsrs_status init() {
+    RSRS_HIP(hipGetDevice(&dev));
+    {
+      std::lock_guard<std::mutex> lk(kept_mu());
+      auto& v = kept();
+      for (size_t i = 0; i < v.size(); ++i)
+        if (v[i].dev == dev) {
+          st = v[i].st; eA = v[i].eA; eB = v[i].eB;
+          v.erase(v.begin() + (std::ptrdiff_t)i);
+          return RSRS_OK;
+        }
+    }
     RSRS_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
     RSRS_HIP(hipEventCreateWithFlags(&eA, hipEventDisableTiming));
     RSRS_HIP(hipEventCreateWithFlags(&eB, hipEventDisableTiming));
     return RSRS_OK;
+  }
+  // the stream must be drained; keeps at most four per process
+  void recycle() {
+    std::lock_guard<std::mutex> lk(kept_mu());
+    if (kept().size() >= 4 || !st || !eA || !eB) return;
+    kept().push_back(Kept{st, eA, eB, dev});
+    st = nullptr; eA = eB = nullptr;
   }
   ~SideStream() {
     if (st) {
@@ -237,7 +262,6 @@ struct Job {
   std::vector<std::vector<int64_t>> cur, remaining;
   size_t li = 0, ci = 0;        // level index and class index of the next class
   std::unordered_map<int64_t, size_t> pos;
-  std::vector<std::vector<int64_t>> Ba, Na;   // active sets of the current class
   std::vector<size_t> class_ws, class_wsb;    // workspace bytes of each class (two parts)
   size_t root_ws = 0;
   double flops = 0.0;
@@ -450,8 +474,18 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
   const hipStream_t st2 = side.st;
   EnqueueWorker worker;   // declared after up2 / side: finishes before they go
   RSRS_TRY(worker.start());
+  HostBuf hperm;   // pinned staging of the permutations
+  {
+    size_t tot = 0;
+    for (auto& J : jobs) tot += (size_t)J.n;
+    RSRS_TRY(pool_alloc(hperm, std::max<size_t>(tot, 1) * 8));
+  }
+  size_t pofs0 = 0;
   for (auto& J : jobs) {
-    RSRS_HIP(hipMemcpyAsync(J.F->perm.p, J.tree().perm.data(), (size_t)J.n * 8, hipMemcpyHostToDevice, st));
+    int64_t* hp = hperm.as<int64_t>() + pofs0;
+    pofs0 += (size_t)J.n;
+    std::memcpy(hp, J.tree().perm.data(), (size_t)J.n * 8);
+    RSRS_HIP(hipMemcpyAsync(J.F->perm.p, hp, (size_t)J.n * 8, hipMemcpyHostToDevice, st));
     // non-finite samples are rejected up front
     check_finite(st, J.Y, J.n, J.s, J.sld, flag);
     check_finite(st, J.Om, J.n, J.s, J.sld, flag);
@@ -469,43 +503,48 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
   // from here on the samples are modified in place
   for (auto& J : jobs) J.smp->consumed = true;
 
-  HostBuf hpos;   // skeleton positions of a class, read back
-  RSRS_TRY(pool_alloc(hpos, pos_max * 8));
+  HostBuf hpos;   // skeleton positions of a class, read back, then the flag word
+  RSRS_TRY(pool_alloc(hpos, (pos_max + 1) * 8));
+  int* hflag_slot = reinterpret_cast<int*>(hpos.as<int64_t>() + pos_max);
   for (size_t t = 0; t < nsteps; ++t) {
     // ---- host index lists and factor-store uploads (Ba, Na, Na copy)
     std::vector<Item<T>> items;
+    std::vector<int64_t> nbs;
     for (auto& J : jobs) {
       if (t >= J.F->groups.size()) continue;
       const Tree& tr = J.tree();
       const Group& g = J.F->groups[t];
       const int lev = J.sch.levels[J.li];
-      J.Ba.assign((size_t)g.count, {});
-      J.Na.assign((size_t)g.count, {});
       for (int64_t q = 0; q < g.count; ++q) {
         BoxRec& R = J.F->boxes[g.first + q];
         const size_t ip = J.pos.at(R.box);
-        J.Ba[q] = J.cur[R.box];
-        // neighbours own disjoint point ranges and keep their active points
-        // sorted, so visiting them by range start yields a sorted list
-        std::vector<int64_t> nbs(tr.nb_ids[lev].begin() + tr.nb_off[lev][ip],
-                                 tr.nb_ids[lev].begin() + tr.nb_off[lev][ip + 1]);
-        std::sort(nbs.begin(), nbs.end(),
-                  [&](int64_t x, int64_t y) { return tr.pt_begin[x] < tr.pt_begin[y]; });
-        std::vector<int64_t> v;
-        v.reserve((size_t)R.n);
-        for (int64_t x : nbs) {
-          const auto& a = J.active_of(x);
-          v.insert(v.end(), a.begin(), a.end());
-        }
-        if (!std::is_sorted(v.begin(), v.end())) std::sort(v.begin(), v.end());
-        J.Na[q] = std::move(v);
-        if ((int64_t)J.Ba[q].size() != R.b || (int64_t)J.Na[q].size() != R.n) {
+        const std::vector<int64_t>& ba = J.cur[R.box];
+        // N_a straight into the staging slots.  Neighbours own disjoint point
+        // ranges and keep their active points sorted, so visiting them by
+        // range start yields a sorted list.
+        if ((int64_t)ba.size() != R.b) {
           set_error("internal: active sets disagree with the count model");
           return RSRS_E_INVALID;
         }
-        std::memcpy(J.hI + R.oNa, J.Na[q].data(), R.n * 8);
-        std::memcpy(J.hI + R.oBa, J.Ba[q].data(), R.b * 8);
-        std::memcpy(J.hI + R.oBa + R.b, J.Na[q].data(), R.n * 8);
+        nbs.assign(tr.nb_ids[lev].begin() + tr.nb_off[lev][ip], tr.nb_ids[lev].begin() + tr.nb_off[lev][ip + 1]);
+        std::sort(nbs.begin(), nbs.end(), [&](int64_t x, int64_t y) { return tr.pt_begin[x] < tr.pt_begin[y]; });
+        const int64_t nn = (int64_t)nbs.size();
+        int64_t* na = J.hI + R.oNa;
+        int64_t cnt = 0;
+        bool over = false;
+        for (int64_t u = 0; u < nn && !over; ++u) {
+          const auto& a = J.active_of(nbs[u]);
+          over = cnt + (int64_t)a.size() > R.n;
+          if (!over) std::memcpy(na + cnt, a.data(), a.size() * 8);
+          cnt += (int64_t)a.size();
+        }
+        if (over || cnt != R.n) {
+          set_error("internal: active sets disagree with the count model");
+          return RSRS_E_INVALID;
+        }
+        if (!std::is_sorted(na, na + cnt)) std::sort(na, na + cnt);
+        std::memcpy(J.hI + R.oBa, ba.data(), R.b * 8);
+        std::memcpy(J.hI + R.oBa + R.b, na, R.n * 8);
         items.push_back(Item<T>{&J, &R, {}});
       }
       // the class's index lists are contiguous: one upload (its R / S slots
@@ -667,11 +706,13 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
       }
     }
     // ---- skeleton sets back to the host (one copy, positions back to back)
+    // and the flag word behind them, so that one synchronisation brings both
+    *hflag_slot = 0;
     RSRS_HIP(hipMemcpyAsync(hpos.as<int64_t>(), posall, (size_t)npos * 8, hipMemcpyDeviceToHost, st));
+    RSRS_HIP(hipMemcpyAsync(hflag_slot, flag, sizeof(int), hipMemcpyDeviceToHost, st));
     RSRS_TRY(up.reset());
     {
-      int hflag = 0;
-      RSRS_HIP(hipMemcpy(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost));
+      const int hflag = *hflag_slot;
       if (hflag & 1) {
         set_error("Gram matrix of a test-matrix panel is not positive definite (rank-deficient panel)");
         return RSRS_E_SINGULAR;
@@ -680,17 +721,16 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
     // ---- phase B: global R / S / SN lists
     {
       int64_t o2 = 0;
-      std::unordered_map<Job<T>*, int64_t> qidx;
       for (auto& it : items) {
         Job<T>& J = *it.J;
         BoxRec& R = *it.R;
         const int k = J.k;
-        const int64_t q = qidx[&J]++;
         const int64_t* sp = hpos.as<int64_t>() + o2;
         const int64_t* rp = sp + k;
         std::vector<int64_t> Sg(k), Rg(R.r);
-        for (int j = 0; j < k; ++j) Sg[j] = J.Ba[q][sp[j]];
-        for (int64_t j = 0; j < R.r; ++j) Rg[j] = J.Ba[q][rp[j]];
+        const int64_t* ba = J.hI + R.oBa;   // B_a as staged for the upload
+        for (int j = 0; j < k; ++j) Sg[j] = ba[sp[j]];
+        for (int64_t j = 0; j < R.r; ++j) Rg[j] = ba[rp[j]];
         std::memcpy(J.hI + R.oR, Rg.data(), R.r * 8);
         std::memcpy(J.hI + R.oS, Sg.data(), (size_t)k * 8);
         J.cur[R.box] = std::move(Sg);
@@ -973,6 +1013,8 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
   pool_return(wsb[0]);
   pool_return(wsb[1]);
   pool_return(hpos);
+  pool_return(hperm);
+  side.recycle();
   up.recycle();
   up2.recycle();
   for (auto& J : jobs) pool_return(J.hidx);

@@ -13,6 +13,7 @@
 // One launch per step, one wave per row.  Norms are double-buffered by step
 // parity so that every wave of a step sees the same pivot; rows other than
 // the pivot are only written by their own wave, and the pivot row is only read.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -330,18 +331,23 @@ static void id_launch(hipStream_t st, const IdDesc* de, unsigned nb, int bmax, i
   // register variant when every row fits (the summation order of the dot
   // product and norm is then fixed by the lane layout, the same for all s);
   // FP32 rows of even length and leading dimension move two columns per load
+  // The steps are many short launches: when measured, each carries its own
+  // start / stop events instead of two separate event records.
   const int nchunk = (smax + 63) / 64;
   for (int j = 0; j < kmax; ++j) {
-    ProfScope ps(st, "id_step", fstep, bstep);
+    hipEvent_t ea, eb;
+    const int slot = prof_begin_ext("id_step", &ea, &eb);
     const unsigned g4 = (unsigned)((bmax + 3) / 4);
     if (pairs && nchunk <= 40)
-      hipLaunchKernelGGL((id_step_reg_kernel<S, 20, (sizeof(S) == 4 ? 2 : 1)>), dim3(g4, nb), dim3(256), 0, st, de, j);
+      hipExtLaunchKernelGGL((id_step_reg_kernel<S, 20, (sizeof(S) == 4 ? 2 : 1)>), dim3(g4, nb), dim3(256), 0, st,
+                            ea, eb, 0, de, j);
     else if (nchunk <= 16)
-      hipLaunchKernelGGL((id_step_reg_kernel<S, 16, 1>), dim3(g4, nb), dim3(256), 0, st, de, j);
+      hipExtLaunchKernelGGL((id_step_reg_kernel<S, 16, 1>), dim3(g4, nb), dim3(256), 0, st, ea, eb, 0, de, j);
     else if (nchunk <= 40)
-      hipLaunchKernelGGL((id_step_reg_kernel<S, 40, 1>), dim3(g4, nb), dim3(256), 0, st, de, j);
+      hipExtLaunchKernelGGL((id_step_reg_kernel<S, 40, 1>), dim3(g4, nb), dim3(256), 0, st, ea, eb, 0, de, j);
     else
-      hipLaunchKernelGGL(id_step_kernel<S>, dim3((unsigned)bmax, nb), dim3(64), 0, st, de, j);
+      hipExtLaunchKernelGGL(id_step_kernel<S>, dim3((unsigned)bmax, nb), dim3(64), 0, st, ea, eb, 0, de, j);
+    if (slot >= 0) prof_end_ext(slot, "id_step", fstep, bstep);
   }
 }
 

@@ -53,6 +53,29 @@ int prof_begin(hipStream_t st, const char* tag) {
   return (int)g_recs.size() - 1;
 }
 
+int prof_begin_ext(const char* tag, hipEvent_t* start, hipEvent_t* stop) {
+  *start = *stop = nullptr;
+  if (!g_on) return -1;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!g_filter.empty() && std::strncmp(tag, g_filter.c_str(), g_filter.size()) != 0) return -1;
+  Rec r{get_event(), get_event(), std::string(), 0.0, 0.0, false};
+  if (!r.a || !r.b) return -1;
+  g_recs.push_back(r);
+  *start = r.a;
+  *stop = r.b;
+  return (int)g_recs.size() - 1;
+}
+
+void prof_end_ext(int slot, const char* tag, double flops, double bytes) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (slot < 0 || slot >= (int)g_recs.size()) return;
+  Rec& r = g_recs[slot];
+  r.tag = tag;
+  r.flops = flops;
+  r.bytes = bytes;
+  r.done = true;
+}
+
 void prof_end(int slot, hipStream_t st, const char* tag, double flops, double bytes) {
   std::lock_guard<std::mutex> lk(g_mu);
   if (slot < 0 || slot >= (int)g_recs.size()) return;
