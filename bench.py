@@ -186,6 +186,7 @@ TRAFFIC_FILES = {
     "id_step": os.path.join(ROOT, "profiles", "id_step_65k_log2d_mixed_traffic.json"),
     "gemm32_nn_full_128x128": os.path.join(ROOT, "profiles", "gemm32_nn_128x128_65k_log2d_mixed_traffic.json"),
     "gemm_nn_full_128x128": os.path.join(ROOT, "profiles", "gemm_f64_nn_128x128_65k_log2d_fp64_traffic.json"),
+    "gauss_jordan_reg": os.path.join(ROOT, "profiles", "gje_reg_65k_log2d_mixed_traffic.json"),
 }
 # machine balance of MI355X in FP64 (flops per HBM byte): below it a kernel
 # is priced against HBM bandwidth

@@ -685,10 +685,12 @@ void sub2d(hipStream_t st, const double* f, int64_t ldf, const double* y, int64_
 // all FP64: the product streams A once, so it is HBM-bound.  K is split into
 // chunks whose slice of X (1 MB) stays in L2 while every row block streams
 // its rows of A straight into registers; each wave forms a 16 x 16 tile on
-// FP64 MFMA, lane (m, q) holding row m and 32 consecutive k (so the k of a
-// lane's operand in MFMA j is 32 q + j; X is staged in LDS in the same
-// order); the partial tiles of the chunks are summed in chunk order by a
-// second launch, so the result does not depend on the schedule.
+// FP64 MFMA.  Lane (m, q) holds row m; its load t brings k = 8 t + 2 q and
+// the next, so that the four lanes of a row read 64 contiguous bytes per
+// load (the k of a lane's operand in MFMA j is 8 (j / 2) + 2 q + j % 2; X is
+// staged in LDS in the same order); the partial tiles of the chunks are
+// summed in chunk order by a second launch, so the result does not depend
+// on the schedule.
 namespace {
 constexpr int SK_RM = 64;    // rows per workgroup (16 per wave)
 constexpr int SK_KC = 128;   // k per iteration
@@ -702,14 +704,14 @@ __global__ __launch_bounds__(256) void skinny_f64_kernel(const double* __restric
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m = lane & 15, q = lane >> 4;
   const int r0 = blockIdx.x * SK_RM + wave * 16;
-  const double* arow = A + (int64_t)min(r0 + m, M - 1) * lda + k_lo + 32 * q;
+  const double* arow = A + (int64_t)min(r0 + m, M - 1) * lda + k_lo + 2 * q;
   double ar[2][32];
   double xr[8];
   auto load_a = [&](int it, double (&dst)[32]) {
-    const double2* src = reinterpret_cast<const double2*>(arow + (int64_t)it * SK_KC);
+    const double* src = arow + (int64_t)it * SK_KC;
 #pragma unroll
     for (int t = 0; t < 16; ++t) {
-      const double2 v = src[t];
+      const double2 v = *reinterpret_cast<const double2*>(src + 8 * t);
       dst[2 * t] = v.x;
       dst[2 * t + 1] = v.y;
     }
@@ -737,7 +739,8 @@ __global__ __launch_bounds__(256) void skinny_f64_kernel(const double* __restric
     }
 #pragma unroll
     for (int j = 0; j < 32; ++j)
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(cur[j], Xs[cb][(32 * q + j) * 16 + m], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(cur[j], Xs[cb][(8 * (j >> 1) + 2 * q + (j & 1)) * 16 + m], acc, 0,
+                                                 0, 0);
     if (more) stash_x(cb ^ 1);
     __syncthreads();
   };
