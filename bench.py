@@ -61,9 +61,9 @@ def workload_config(s_req: int, s_eff: int, reproject: int) -> dict:
             "N": GRID_N ** 2, "leaf": LEAF, "k": K, "p": K, "s_configured": S_CFG,
             "s_required": s_req, "s": s_eff, "nrhs": NRHS, "tol": TOL,
             "projection_passes": 1 + reproject,
-            "precision": "mixed: BF16 sample products (FP32 accumulation), FP32 sketches and MFMA "
-                         "products in the factorization, FP64 Cholesky, pivoted QR, Gauss-Jordan "
-                         "and residuals; FP64 beside it",
+            "precision": "mixed: BF16 sample products (FP32 accumulation), FP32 sketches, MFMA "
+                         "products and Gram Cholesky in the factorization, FP64 pivoted-QR "
+                         "decisions, Gauss-Jordan and residuals; FP64 beside it",
             "variant": "symmetric (A = A^T: U = L^T, one sketch side); the general two-sided "
                        "algorithm is reported beside it"}
 
