@@ -224,10 +224,11 @@ rsrs_status rsrs_gaussian(double* out, int64_t nrows, int64_t ncols, int64_t ld,
  * RSRS_PREC_F32_MIXED: FP32 samples and an FP32 stored factor; every product
  * of sketch-sized operands (Gram matrices, projections, extraction,
  * multipliers, sparsification and elimination updates) runs on FP32 MFMA with
- * FP32 accumulation, while the rank decisions stay FP64: the Gram matrices
- * are written and Cholesky-factored in FP64, the column-pivoted QR of the ID
- * works on an FP64 copy of the projected sketch, and X_RR and the root block
- * are inverted by FP64 Gauss-Jordan with partial pivoting.  Solves with such a
+ * FP32 accumulation, and the Gram matrices are Cholesky-factored in FP32,
+ * while the rank decisions stay FP64: the column-pivoted QR of the ID keeps
+ * the projected sketch's rows in FP32 but takes its dot products, norms and
+ * coefficients in FP64, and X_RR and the root block are inverted by FP64
+ * Gauss-Jordan with partial pivoting.  Solves with such a
  * factor take and return FP64 blocks and compute in FP32; accuracy is
  * recovered by rsrs_solve_refine with the FP64 black-box residual.
  *
