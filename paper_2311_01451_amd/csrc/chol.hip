@@ -59,7 +59,60 @@ struct CholPanel {
   T* X;   // scratch of the same shape; receives X_jj
   int64_t ld;
   int n, j, ib, ie;   // panel j, row blocks [ib, ie)
+  int t0;             // panels t0..j-1 still to subtract from column block j (FUSED)
 };
+
+// acc += A B^T for 64 x 64 blocks in LDS (pitch PP), wave w holding rows
+// 32 (w / 2).., columns 32 (w % 2)..: the layout of every product below.
+template <typename T>
+__device__ __forceinline__ void mma_abt(const T* A, const T* B, typename Mfma<T>::acc_t (&acc)[2][2], int wm,
+                                        int wn, int q, int c16) {
+#pragma unroll 4
+  for (int k0 = 0; k0 < PB; k0 += 4) {
+    T av[2], bv[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) av[a] = A[(32 * wm + 16 * a + c16) * PP + k0 + q];
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb) bv[bb] = B[(32 * wn + 16 * bb + c16) * PP + k0 + q];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int bb = 0; bb < 2; ++bb) acc[a][bb] = Mfma<T>::mma(av[a], bv[bb], acc[a][bb]);
+  }
+}
+
+// rows [0, rows) of the 64 x 64 block at src (leading dimension ld) into
+// LDS, zero below
+template <typename T>
+__device__ __forceinline__ void load_block(T* dst, const T* src, int64_t ld, int rows, int tid) {
+  T v[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int x = tid + 256 * u, r = x >> 6, c = x & 63;
+    v[u] = r < rows ? src[(int64_t)r * ld + c] : T(0);
+  }
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int x = tid + 256 * u;
+    dst[(x >> 6) * PP + (x & 63)] = v[u];
+  }
+}
+
+// La[r][c] -= acc at the wave's result positions, rows below `rows` only
+// (lower part only when `lower`)
+template <typename T>
+__device__ __forceinline__ void sub_acc(T* La, const typename Mfma<T>::acc_t (&acc)[2][2], int rows, bool lower,
+                                        int wm, int wn, int q, int c16) {
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 32 * wm + 16 * a + Mfma<T>::row(v, q), c = 32 * wn + 16 * bb + c16;
+        if (r < rows && (!lower || c <= r)) La[r * PP + c] -= acc[a][bb][v];
+      }
+}
 
 // 1 / sqrt(d) from the hardware estimate and Newton steps
 // y <- y + y (1 - d y^2) / 2 (each step doubles the correct bits): two from
@@ -108,18 +161,51 @@ __device__ __forceinline__ void doubling_small(const T* La, T* Xa, T* Vs, int ti
   __syncthreads();
 }
 
-template <typename T>
+// FUSED: the workgroup first subtracts the earlier panels t0..j-1 of the
+// super-panel from its blocks of column block j (diagonal block and its row
+// blocks), L_it L_jt^T on MFMA with the results kept in registers, instead
+// of a separate narrow GEMM launch before the panel.
+template <typename T, bool FUSED>
 __global__ __launch_bounds__(256, 2) void chol_panel_kernel(const CholPanel<T>* __restrict__ e, int* flag) {
   using MM = Mfma<T>;
   using acc_t = typename MM::acc_t;
   __shared__ T La[PB * PP];   // diagonal block -> L_jj; later the off-diagonal blocks
   __shared__ T Xa[PB * PP];   // X_jj = L_jj^{-1}
   __shared__ T Vs[32 * 33];   // products of the doubling steps
+  __shared__ T Lj[FUSED ? PB * PP : 1];   // L_jt of the pending panels
   const CholPanel<T> d = e[blockIdx.x];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t ld = d.ld;
   const int j0 = PB * d.j;
   const int nj = min(PB, d.n - j0);
+  const int wm = wave >> 1, wn = wave & 1, q = lane >> 4, c16 = lane & 15;
+  const int ifirst = max(d.ib, d.j + 1);
+  acc_t ad[2][2], ao[RB][2][2];   // pending updates of the diagonal and the row blocks
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb) {
+      ad[a][bb] = acc_t{0, 0, 0, 0};
+#pragma unroll
+      for (int b = 0; b < RB; ++b) ao[b][a][bb] = acc_t{0, 0, 0, 0};
+    }
+  if constexpr (FUSED) {
+    for (int t = d.t0; t < d.j; ++t) {
+      load_block(Lj, d.G + (int64_t)j0 * ld + PB * t, ld, nj, tid);
+      __syncthreads();
+      mma_abt(Lj, Lj, ad, wm, wn, q, c16);
+#pragma unroll
+      for (int b = 0; b < RB; ++b) {
+        const int i = ifirst + b;
+        if (i >= d.ie) break;   // the same in every thread
+        load_block(La, d.G + (int64_t)PB * i * ld + PB * t, ld, min(PB, d.n - PB * i), tid);
+        __syncthreads();
+        mma_abt(La, Lj, ao[b], wm, wn, q, c16);
+        __syncthreads();
+      }
+      __syncthreads();
+    }
+  }
   {
     // lower part of the diagonal block, identity beyond n, zero above
     const T* g = d.G + (int64_t)j0 * ld + j0;
@@ -137,6 +223,12 @@ __global__ __launch_bounds__(256, 2) void chol_panel_kernel(const CholPanel<T>* 
     }
   }
   __syncthreads();
+  if constexpr (FUSED) {
+    if (d.t0 < d.j) {
+      sub_acc(La, ad, nj, true, wm, wn, q, c16);
+      __syncthreads();
+    }
+  }
   // ---- factorization in steps of 8 columns.  Wave 0, lane r = row r: every
   // lane factors the 8 x 8 diagonal block in registers (identical work, no
   // exchange), then rows below form their 8 entries of L and rows inside the
@@ -254,8 +346,6 @@ __global__ __launch_bounds__(256, 2) void chol_panel_kernel(const CholPanel<T>* 
   }
   // ---- off-diagonal blocks L_ij = G_ij X_jj^T (panel j is full here) on
   // MFMA: wave w computes rows 32 (w / 2).., columns 32 (w % 2)..
-  const int wm = wave >> 1, wn = wave & 1, q = lane >> 4, c16 = lane & 15;
-  int i = max(d.ib, d.j + 1);
   T pf[16];
   auto fetch = [&](int ib) {
     const int ni = min(PB, d.n - PB * ib);
@@ -266,8 +356,11 @@ __global__ __launch_bounds__(256, 2) void chol_panel_kernel(const CholPanel<T>* 
       pf[u] = (r < ni) ? src[(int64_t)r * ld + c] : T(0);
     }
   };
-  if (i < d.ie) fetch(i);
-  for (; i < d.ie; ++i) {
+  if (ifirst < d.ie) fetch(ifirst);
+#pragma unroll
+  for (int b = 0; b < RB; ++b) {
+    const int i = ifirst + b;
+    if (i >= d.ie) break;   // the same in every thread
     const int i0 = PB * i;
     const int ni = min(PB, d.n - i0);
     T* gi = d.G + (int64_t)i0 * ld + j0;
@@ -277,25 +370,19 @@ __global__ __launch_bounds__(256, 2) void chol_panel_kernel(const CholPanel<T>* 
       La[(x >> 6) * PP + (x & 63)] = pf[u];
     }
     __syncthreads();
+    if constexpr (FUSED) {
+      if (d.t0 < d.j) {
+        sub_acc(La, ao[b], ni, false, wm, wn, q, c16);
+        __syncthreads();
+      }
+    }
     if (i + 1 < d.ie) fetch(i + 1);   // in flight during the product
     acc_t acc[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
       for (int bb = 0; bb < 2; ++bb) acc[a][bb] = acc_t{0, 0, 0, 0};
-#pragma unroll 4
-    for (int k0 = 0; k0 < PB; k0 += 4) {
-      T av[2], bv[2];
-#pragma unroll
-      for (int a = 0; a < 2; ++a) av[a] = La[(32 * wm + 16 * a + c16) * PP + k0 + q];
-#pragma unroll
-      for (int bb = 0; bb < 2; ++bb) bv[bb] = Xa[(32 * wn + 16 * bb + c16) * PP + k0 + q];
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int bb = 0; bb < 2; ++bb)
-          acc[a][bb] = MM::mma(av[a], bv[bb], acc[a][bb]);
-    }
+    mma_abt(La, Xa, acc, wm, wn, q, c16);
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -326,6 +413,9 @@ rsrs_status chol_inverse(Uploader& up, hipStream_t st, const std::vector<CholMat
   // the trailing matrix receives all of them at once (a SYRK with K = 64 SP),
   // which reads and writes the trailing matrix SP times less often.
   constexpr int SP = 4;
+  // FP32: the column-block update is done by the panel kernel itself (its
+  // extra LDS block keeps two workgroups per CU only at 4-byte elements)
+  constexpr bool fused = sizeof(T) == 4;
   std::vector<CholPanel<T>> tasks;
   std::vector<size_t> toff(P + 1);
   std::vector<double> pflops(P, 0.0);
@@ -341,16 +431,18 @@ rsrs_status chol_inverse(Uploader& up, hipStream_t st, const std::vector<CholMat
       const int Pm = (m.n + PB - 1) / PB;
       if (j >= Pm) continue;
       const int rows = m.n - PB * j;
-      if (j > j0s) {
+      if (j > j0s && !fused) {
         // column block j -= L[rows >= 64 j, panels j0s..j-1] L[block j, same]^T
         T* Lr = m.G + (int64_t)PB * j * m.ld + PB * j0s;
         T* Cj = m.G + (int64_t)PB * j * (m.ld + 1);
         colu.push_back(gdescT<T, T>(Lr, nullptr, m.ld, Lr, nullptr, m.ld, Cj, nullptr, m.ld, rows,
                              std::min(PB, rows), PB * (j - j0s), -1.0, 1.0));
       }
-      for (int ib = j; ib < Pm; ib += RB) tasks.push_back(CholPanel<T>{m.G, m.W, m.ld, m.n, j, ib, std::min(ib + RB, Pm)});
+      for (int ib = j; ib < Pm; ib += RB)
+        tasks.push_back(CholPanel<T>{m.G, m.W, m.ld, m.n, j, ib, std::min(ib + RB, Pm), fused ? j0s : j});
       const double nj = std::min(PB, rows), below = rows - nj;
       pflops[j] += (2.0 / 3.0) * nj * nj * nj + below * nj * nj;
+      if (fused) pflops[j] += 2.0 * rows * nj * PB * (j - j0s);   // the column-block update
       const int trows = m.n - PB * (j + 1);
       if (trows > 0 && (last_of_sp || j == Pm - 1)) {
         T* Ls = m.G + (int64_t)PB * (j + 1) * m.ld + PB * j0s;
@@ -419,7 +511,7 @@ rsrs_status chol_inverse(Uploader& up, hipStream_t st, const std::vector<CholMat
     const unsigned nt = (unsigned)(toff[j + 1] - toff[j]);
     {
       ProfScope ps(st, "chol_panel", pflops[j], 0.0);
-      hipLaunchKernelGGL(chol_panel_kernel<T>, dim3(nt), dim3(256), 0, st, dt + toff[j], flag);
+      hipLaunchKernelGGL((chol_panel_kernel<T, fused>), dim3(nt), dim3(256), 0, st, dt + toff[j], flag);
       RSRS_HIP(hipGetLastError());
     }
     for (const auto& L : tl[j]) RSRS_TRY(gemm_exec(L, ds, sizeof(GD), st));
