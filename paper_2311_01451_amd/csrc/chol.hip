@@ -6,7 +6,9 @@
 // over super-panels of four panels:
 //
 //   column j  (panels after the first of a super-panel) the column block j
-//             receives the earlier panels of its super-panel (narrow GEMM).
+//             receives the earlier panels of its super-panel: a narrow GEMM
+//             launch in FP64; in FP32 the panel kernel's workgroups subtract
+//             them from their own blocks first (one more LDS block fits).
 //   panel j   one workgroup per (matrix, two 64-row blocks i >= j).  Each
 //             workgroup factors the diagonal block G_jj itself (so no
 //             workgroup waits for another), forms X_jj = L_jj^{-1}, and
