@@ -127,6 +127,22 @@ rsrs_status rsrs_tree_schedule(const rsrs_tree_t* t, int k, int32_t* colour, int
  * Returns -1 on invalid arguments. */
 int64_t rsrs_samples_required(const rsrs_tree_t* t, int k, int p);
 
+/* Algorithmic work of a fixed-rank factorization with s samples, as the
+ * cost analysis of Sec. 4.5 prices the steps of Algorithm 1 (the method's own
+ * operations, not the kernels that carry them out): per processed box with
+ * b active points, n active neighbour points, l = b + n, k_B = min(k, b),
+ * r = b - k_B,
+ *   2(4 s l^2 - 4/3 l^3) + 8 b s l + 4 s b k_B + 8 r k_B s + 4 r s l
+ *   + 2/3 r^3 + 4 r^2 (k_B + n) + 8 r (k_B + n) s  flops,
+ * esize (s (2l + 2b + 2n) + s (4b + 2n) + stored) bytes with
+ * r k_B + r^2 + 2 r (k_B + n) stored entries; symmetric != 0 halves the
+ * two-sided terms (all but the pivoted QR and the LU) and stores one
+ * multiplier.  The root adds (4 s t^2 - 4/3 t^3) + 2 s t^2 + t^3 + 2/3 t^3
+ * flops and t^2 stored entries, t = |B_t|.  A solve costs 2 flops per stored
+ * entry and right-hand side.  Outputs may be NULL.  esize is 4 or 8. */
+rsrs_status rsrs_work_model(const rsrs_tree_t* t, int k, int64_t s, int symmetric, int esize,
+                            double* flops, double* bytes, int64_t* stored_entries);
+
 /* ------------------------------------------------------------------------
  * Black-box operator access (Sec. 4, eq. rand_sample_setting).
  * The callback computes Y = A X (transpose = 0) or Y = A^T X (transpose = 1)

@@ -122,6 +122,15 @@ int64_t rsrs_samples_required(const rsrs_tree_t* th, int k, int p) {
   return samples_required(th->t, s, k, p);
 }
 
+rsrs_status rsrs_work_model(const rsrs_tree_t* th, int k, int64_t s, int symmetric, int esize,
+                            double* flops, double* bytes, int64_t* stored_entries) {
+  if (!th || k < 1 || s < 1 || (esize != 4 && esize != 8)) return invalid("bad tree, k, s or element size");
+  Schedule sc;
+  make_schedule(th->t, k, sc);
+  work_model(th->t, sc, k, s, symmetric != 0, esize, flops, bytes, stored_entries);
+  return RSRS_OK;
+}
+
 // ------------------------------------------------------------------ operators
 rsrs_status rsrs_op_create_kernel(int kind, const double* pts, int64_t n, int dim, double param,
                                   double param2, rsrs_operator_t** out) {

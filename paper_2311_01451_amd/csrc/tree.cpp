@@ -382,3 +382,48 @@ int64_t samples_required(const Tree& t, const Schedule& s, int k, int p) {
 }
 
 }  // namespace rsrs
+
+namespace rsrs {
+
+// Algorithmic work of a fixed-rank factorization (cost terms of Sec. 4.5 for
+// the steps of Algorithm 1), per processed box with b active points, n active
+// neighbour points, l = b + n, k_B = min(k, b), r = b - k_B:
+//   2(4 s l^2 - 4/3 l^3)   thin QR with Q of the two s x l test-matrix panels
+//   8 b s l                two projections;  4 s b k_B  pivoted QR, k_B steps
+//   8 r k_B s              sparsification;   4 r s l    two extractions
+//   2/3 r^3                LU of X_RR;       4 r^2 (k_B + n)  K_U, K_L
+//   8 r (k_B + n) s        elimination
+// bytes: e s (2l + 2b + 2n) read, e s (4b + 2n) written, e (stored entries)
+// with stored entries r k_B + r^2 + 2 r (k_B + n).  The symmetric variant
+// halves every two-sided term (not the pivoted QR or the LU) and stores one
+// multiplier.  The root adds a thin QR with Q of the s x |B_t| panel, the
+// product with Y, a triangular solve and an LU; it stores |B_t|^2 entries.
+void work_model(const Tree& t, const Schedule& sc, int k, int64_t s, bool sym, int esize,
+                double* flops, double* bytes, int64_t* stored) {
+  const double h = sym ? 0.5 : 1.0, ds = (double)s, e = (double)esize;
+  double f = 0.0, by = 0.0;
+  int64_t st = 0;
+  for (const auto& lev : sc.classes)
+    for (const auto& cl : lev)
+      for (int64_t bx : cl) {
+        const int64_t b = sc.b_count[bx], n = sc.l_count[bx] - b;
+        const int64_t kb = std::min<int64_t>(k, b), r = b - kb, l = b + n;
+        const double db = (double)b, dn = (double)n, dk = (double)kb, dr = (double)r, dl = (double)l;
+        f += h * 2.0 * (4.0 * ds * dl * dl - (4.0 / 3.0) * dl * dl * dl) + h * 8.0 * db * ds * dl +
+             4.0 * ds * db * dk + h * 8.0 * dr * dk * ds + h * 4.0 * dr * ds * dl +
+             (2.0 / 3.0) * dr * dr * dr + h * 4.0 * dr * dr * (dk + dn) + h * 8.0 * dr * (dk + dn) * ds;
+        const int64_t sb = r * kb + r * r + (sym ? 1 : 2) * r * (kb + n);
+        st += sb;
+        by += h * e * ds * (double)(2 * l + 2 * b + 2 * n) + h * e * ds * (double)(4 * b + 2 * n) + e * (double)sb;
+      }
+  const double nt = (double)sc.root_count;
+  f += (4.0 * ds * nt * nt - (4.0 / 3.0) * nt * nt * nt) + 2.0 * ds * nt * nt + nt * nt * nt +
+       (2.0 / 3.0) * nt * nt * nt;
+  st += sc.root_count * sc.root_count;
+  by += e * (2.0 * nt * ds + nt * nt);
+  if (flops) *flops = f;
+  if (bytes) *bytes = by;
+  if (stored) *stored = st;
+}
+
+}  // namespace rsrs

@@ -91,7 +91,7 @@ MATVEC_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int, C.c_int, C.c_int64, C.c_vo
 EXPORTS = [
     "rsrs_status_string", "rsrs_last_error", "rsrs_last_required_s", "rsrs_build_tree",
     "rsrs_tree_destroy", "rsrs_tree_get_info", "rsrs_tree_neighbours", "rsrs_tree_schedule",
-    "rsrs_samples_required", "rsrs_op_create_kernel", "rsrs_op_create_dense",
+    "rsrs_samples_required", "rsrs_work_model", "rsrs_op_create_kernel", "rsrs_op_create_dense",
     "rsrs_op_create_poisson7", "rsrs_op_matvec", "rsrs_op_destroy", "rsrs_samples_wrap",
     "rsrs_sample", "rsrs_sample_symmetric", "rsrs_samples_wrap_symmetric", "rsrs_samples_destroy", "rsrs_gaussian", "rsrs_factor", "rsrs_factor_batched",
     "rsrs_factor_destroy", "rsrs_release_cached",
@@ -125,6 +125,7 @@ def lib():
         "rsrs_tree_neighbours": (i32, [vp, i32, P(i64), P(P(i64)), P(P(i64)), P(P(i64))]),
         "rsrs_tree_schedule": (i32, [vp, i32, P(C.c_int32), P(i64), P(i64), P(i64)]),
         "rsrs_samples_required": (i64, [vp, i32, i32]),
+        "rsrs_work_model": (i32, [vp, i32, i64, i32, i32, P(dbl), P(dbl), P(i64)]),
         "rsrs_op_create_kernel": (i32, [i32, P(C.c_double), i64, i32, dbl, dbl, P(vp)]),
         "rsrs_op_create_dense": (i32, [vp, i64, i64, P(vp)]),
         "rsrs_op_create_poisson7": (i32, [i32, P(C.c_double), P(vp)]),
@@ -277,6 +278,14 @@ def rsrs_samples_required(tree: Tree, k: int, p: int) -> int:
     if v < 0:
         raise RSRSError(1, "invalid arguments to rsrs_samples_required")
     return int(v)
+
+
+def rsrs_work_model(tree: Tree, k: int, s: int, symmetric: bool = False, esize: int = 8) -> dict:
+    """Algorithmic flops, bytes and stored entries of a fixed-rank factorization."""
+    f, b, st = C.c_double(), C.c_double(), C.c_int64()
+    _check(lib().rsrs_work_model(tree.handle, k, s, int(symmetric), esize, C.byref(f), C.byref(b),
+                                 C.byref(st)))
+    return {"flops": f.value, "bytes": b.value, "stored_entries": st.value}
 
 
 # --------------------------------------------------------------------------- operators

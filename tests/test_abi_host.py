@@ -80,3 +80,23 @@ def test_invalid_arguments_are_reported():
     assert e.value.status == 1
     with pytest.raises(rsrs.RSRSError):
         rsrs.rsrs_build_tree(np.full((4, 2), np.nan), 4)
+
+
+@pytest.mark.parametrize("symmetric", [0, 1])
+def test_work_model_native_equals_oracle(symmetric):
+    """rsrs_work_model (the algorithmic counts behind the benchmark's
+    TFLOP/s figures) equals the oracle's work model (cost terms of Sec. 4.5)
+    on the 64^2 and 256^2 grids and an adaptive 3D tree."""
+    from oracle import flops as ofl
+    cases = [(inputs.grid2d(64), 64, 32, None), (inputs.grid2d(256), 64, 64, None),
+             (inputs.uniform_points(4096, 3), 64, 32, [0, 0, 0])]
+    for pts, m, k, lo in cases:
+        to = ot.build_tree(pts, m, lo=lo)
+        tc = rsrs.rsrs_build_tree(pts, m, root_lo=lo)
+        s = tc.samples_required(k, k)
+        for esize in (8, 4):
+            w = rsrs.rsrs_work_model(tc, k, s, bool(symmetric), esize)
+            o = ofl.factor_work(to, k, s, symmetric=bool(symmetric), esize=esize)
+            assert abs(w["flops"] - o.flops) <= 1e-12 * o.flops
+            assert abs(w["bytes"] - o.bytes_moved) <= 1e-12 * o.bytes_moved
+            assert w["stored_entries"] == o.stored_entries
