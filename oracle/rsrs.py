@@ -110,34 +110,59 @@ def nullify(YB: np.ndarray, C: np.ndarray) -> np.ndarray:
     return YB - (YB @ q) @ q.T
 
 
-def row_id(M: np.ndarray, k: int, want_r11_min: bool = False):
+def row_id(M: np.ndarray, k: int, want_r11_min: bool = False, rank_tol: float = 0.0,
+           ref_norm: float = 0.0):
     """Row interpolative decomposition of M (Sec. 2.3, eq. id_def) by greedy
     column-pivoted QR of M^T.  Returns (S_pos, R_pos, T) with positions sorted
-    ascending and T (r x k) such that M[R_pos] ~ T M[S_pos] (and, on request,
-    the smallest |diagonal| of R11)."""
+    ascending and T (r x k_B) such that M[R_pos] ~ T M[S_pos] (and, on request,
+    the smallest |diagonal| of R11).
+
+    Rank: k_B = min(k, b) pivots (the fixed rank of Sec. 4.5), or, with
+    rank_tol > 0, only the leading pivots whose |R_jj| exceeds
+    rank_tol * ref_norm (the numerical rank of the sketch relative to
+    ref_norm; the diagonal of a column-pivoted R does not increase, so this
+    stops at the first pivot at or below the threshold)."""
     _, Rf, piv = sla.qr(M.T, mode="economic", pivoting=True)
-    S_piv = piv[:k]
-    R_piv = piv[k:]
-    R11 = Rf[:k, :k]
-    R12 = Rf[:k, k:]
-    Tp = sla.solve_triangular(R11, R12, lower=False).T      # rows R_piv, cols S_piv
+    kb = min(k, M.shape[0])
+    if rank_tol > 0.0:
+        d = np.abs(np.diag(Rf))[:kb]
+        below = np.nonzero(d <= rank_tol * ref_norm)[0]
+        if below.size:
+            kb = int(below[0])
+    S_piv = piv[:kb]
+    R_piv = piv[kb:]
+    R11 = Rf[:kb, :kb]
+    R12 = Rf[:kb, kb:]
+    Tp = sla.solve_triangular(R11, R12, lower=False).T if kb else np.zeros((len(R_piv), 0))
     so = np.argsort(S_piv, kind="stable")
     ro = np.argsort(R_piv, kind="stable")
     if want_r11_min:
-        return S_piv[so], R_piv[ro], Tp[np.ix_(ro, so)], float(np.abs(np.diag(R11)).min())
+        r11 = float(np.abs(np.diag(R11)).min()) if kb else 0.0
+        return S_piv[so], R_piv[ro], Tp[np.ix_(ro, so)], r11
     return S_piv[so], R_piv[ro], Tp[np.ix_(ro, so)]
 
 
 def factor(tree: otree.Tree, Y, Z, Om, Psi, k: int, p: int | None = None,
            keep_M: bool = False, check_samples: bool = True, on_box=None,
-           symmetric: bool = False) -> Factorization:
+           symmetric: bool = False, id_mode: str = "sum", rank_tol: float = 0.0) -> Factorization:
     """Algorithm 1 on sketches given in user point order (N x s each).
 
     The caller's arrays are not modified; the oracle works on tree-ordered
     copies.  ``on_box(bf, Y, Z, Om, Psi)`` (optional) is called after each box
     with the updated tree-ordered sketches, for invariant checks.  With
     ``symmetric`` (A = A^T) only Y and Om are used (Z, Psi may be None); see
-    the module docstring."""
+    the module docstring.
+
+    ``id_mode``: "sum" takes the ID of M = M_Y + M_Z (Algorithm 1 writes the
+    sum); "concat" takes it of the concatenation [M_Y, M_Z] (the form of the
+    simultaneous skeletonization of Sec. 3.1, where one skeleton set serves
+    the rows and the columns).  For the symmetric variant both reduce to the
+    ID of M_Y.  ``rank_tol`` > 0 replaces the fixed rank by the numerical
+    rank of the ID's sketch relative to ||[Y_B Z_B]||_F (capped at k); the
+    boxes and their order stay those of the fixed-rank schedule, and a box
+    may then hold fewer than k (even no) active points when its level runs."""
+    if id_mode not in ("sum", "concat"):
+        raise ValueError("id_mode must be 'sum' or 'concat'")
     if p is None:
         p = k
     perm = tree.perm
@@ -178,7 +203,7 @@ def factor(tree: otree.Tree, Y, Z, Om, Psi, k: int, p: int | None = None,
                 Na = np.sort(np.concatenate([cur[x] for x in nb[b].tolist()])) \
                     if len(nb[b]) else np.zeros(0, dtype=np.int64)
                 bf = _process_box(b, int(lev), int(sch.colour[b]), Ba, Na, Y, Z, Om, Psi,
-                                  k, keep_M, symmetric)
+                                  k, keep_M, symmetric, id_mode, rank_tol)
                 boxes_out.append(bf)
                 cur[b] = bf.S
                 if on_box is not None:
@@ -191,29 +216,45 @@ def factor(tree: otree.Tree, Y, Z, Om, Psi, k: int, p: int | None = None,
         Bt = np.arange(tree.n)
     else:
         Bt = np.sort(np.concatenate([remaining[int(b)] for b in tree.level_boxes[1]]))
-    At = _right_pinv_apply(Y[Bt], Om[Bt])
+    At = _right_pinv_apply(Y[Bt], Om[Bt]) if len(Bt) else np.zeros((0, 0))
     if symmetric:
         At = 0.5 * (At + At.T)
     return Factorization(tree=tree, k=k, p=p, s=s, boxes=boxes_out, Bt=Bt, At=At,
-                         At_lu=sla.lu_factor(At), perm=perm)
+                         At_lu=sla.lu_factor(At) if len(Bt) else None, perm=perm)
 
 
-def _process_box(box, lev, colour, Ba, Na, Y, Z, Om, Psi, k, keep_M, symmetric=False) -> BoxFactor:
+def _empty_box(box, lev, colour, Ba, Na, S) -> BoxFactor:
+    """A box that eliminates nothing (no active points, or every point kept)."""
+    z = np.zeros(0, dtype=np.int64)
+    return BoxFactor(box=box, level=lev, colour=colour, Ba=Ba, Na=Na, S=S, R=z,
+                     T=np.zeros((0, len(S))), XRR=np.zeros((0, 0)), lu=None,
+                     KU=np.zeros((0, len(S) + len(Na))), KL=np.zeros((len(S) + len(Na), 0)))
+
+
+def _process_box(box, lev, colour, Ba, Na, Y, Z, Om, Psi, k, keep_M, symmetric=False,
+                 id_mode="sum", rank_tol=0.0) -> BoxFactor:
     b = Ba.shape[0]
     C = np.concatenate([Ba, Na])
     l = C.shape[0]
     s = Y.shape[1]
     if s - l < k:
         raise InsufficientSamples(f"box {box}: s - l = {s - l} < k = {k}")
+    if b == 0:
+        return _empty_box(box, lev, colour, Ba, Na, Ba)
     if symmetric:
-        return _process_box_symmetric(box, lev, colour, Ba, Na, C, Y, Om, k, keep_M)
+        return _process_box_symmetric(box, lev, colour, Ba, Na, C, Y, Om, k, keep_M, rank_tol)
     # block nullification, eq. nullYZ (projector form, see module docstring)
-    M = nullify(Y[Ba], Om[C]) + nullify(Z[Ba], Psi[C])
+    MY, MZ = nullify(Y[Ba], Om[C]), nullify(Z[Ba], Psi[C])
+    M = MY + MZ if id_mode == "sum" else np.concatenate([MY, MZ], axis=1)
     norm_yz = float(np.sqrt(np.sum(Y[Ba] ** 2) + np.sum(Z[Ba] ** 2)))
-    # row ID of the summed far-field sketch (Algorithm 1, "Compute the row-ID")
-    S_pos, R_pos, T, r11_min = row_id(M, k, want_r11_min=True)
+    # row ID of the far-field sketch (Algorithm 1, "Compute the row-ID")
+    S_pos, R_pos, T, r11_min = row_id(M, k, want_r11_min=True, rank_tol=rank_tol, ref_norm=norm_yz)
     Sg = Ba[S_pos]
     Rg = Ba[R_pos]
+    if len(Rg) == 0:
+        bf = _empty_box(box, lev, colour, Ba, Na, Sg)
+        bf.norm_yz, bf.norm_m, bf.r11_min = norm_yz, float(np.linalg.norm(M)), r11_min
+        return bf
     # sparsification matrices E, F applied to the sketches
     Y[Rg] -= T @ Y[Sg]
     Z[Rg] -= T @ Z[Sg]
@@ -239,14 +280,20 @@ def _process_box(box, lev, colour, Ba, Na, Y, Z, Om, Psi, k, keep_M, symmetric=F
                      norm_yz=norm_yz, norm_m=float(np.linalg.norm(M)), r11_min=r11_min)
 
 
-def _process_box_symmetric(box, lev, colour, Ba, Na, C, Y, Om, k, keep_M) -> BoxFactor:
+def _process_box_symmetric(box, lev, colour, Ba, Na, C, Y, Om, k, keep_M, rank_tol=0.0) -> BoxFactor:
     """One box of the symmetric variant (module docstring): the Y / Omega side
-    of the general step, X_RR symmetrized, K_L = K_U^T."""
+    of the general step, X_RR symmetrized, K_L = K_U^T.  The ID of M_Y equals
+    that of M_Y + M_Z = 2 M_Y, whose R is twice M_Y's: the rank threshold
+    rank_tol * ||[Y_B Z_B]|| is halved accordingly."""
     M = nullify(Y[Ba], Om[C])
     norm_yz = float(np.sqrt(2.0 * np.sum(Y[Ba] ** 2)))
-    S_pos, R_pos, T, r11_min = row_id(M, k, want_r11_min=True)
+    S_pos, R_pos, T, r11_min = row_id(M, k, want_r11_min=True, rank_tol=rank_tol, ref_norm=0.5 * norm_yz)
     Sg = Ba[S_pos]
     Rg = Ba[R_pos]
+    if len(Rg) == 0:
+        bf = _empty_box(box, lev, colour, Ba, Na, Sg)
+        bf.norm_yz, bf.norm_m, bf.r11_min = norm_yz, float(2.0 * np.linalg.norm(M)), 2.0 * r11_min
+        return bf
     Y[Rg] -= T @ Y[Sg]
     Om[Sg] += T.T @ Om[Rg]
     Ch = np.concatenate([Rg, Sg, Na])
@@ -287,8 +334,10 @@ def solve(F: Factorization, f, transpose: bool = False) -> np.ndarray:
             x[bf.SN] -= bf.KL @ x[bf.R]          # L
         u = np.empty_like(x)
         for bf in F.boxes:                       # D^{-1}
-            u[bf.R] = sla.lu_solve(bf.lu, x[bf.R])
-        u[F.Bt] = sla.lu_solve(F.At_lu, x[F.Bt])
+            if len(bf.R):
+                u[bf.R] = sla.lu_solve(bf.lu, x[bf.R])
+        if len(F.Bt):
+            u[F.Bt] = sla.lu_solve(F.At_lu, x[F.Bt])
         for bf in reversed(F.boxes):             # downward pass W_M^{-1} ... W_1^{-1}
             u[bf.R] -= bf.KU @ u[bf.SN]          # U
             u[bf.S] -= bf.T.T @ u[bf.R]          # F
@@ -298,8 +347,10 @@ def solve(F: Factorization, f, transpose: bool = False) -> np.ndarray:
             x[bf.SN] -= bf.KU.T @ x[bf.R]
         u = np.empty_like(x)
         for bf in F.boxes:
-            u[bf.R] = sla.lu_solve(bf.lu, x[bf.R], trans=1)
-        u[F.Bt] = sla.lu_solve(F.At_lu, x[F.Bt], trans=1)
+            if len(bf.R):
+                u[bf.R] = sla.lu_solve(bf.lu, x[bf.R], trans=1)
+        if len(F.Bt):
+            u[F.Bt] = sla.lu_solve(F.At_lu, x[F.Bt], trans=1)
         for bf in reversed(F.boxes):             # ... V_1^{-T}: L^T then E^T
             u[bf.R] -= bf.KL.T @ u[bf.SN]
             u[bf.S] -= bf.T.T @ u[bf.R]

@@ -43,7 +43,7 @@ def relmax(a, b):
 class Problem:
     """One operator + geometry, factored on both sides with identical inputs."""
 
-    def __init__(self, pts, A, m, k, lo=None, side=1.0, s=None, seed_off=0, reproject=1):
+    def __init__(self, pts, A, m, k, lo=None, side=1.0, s=None, seed_off=0, reproject=1, keep_M=False):
         print(f"[problem] N={len(pts)} m={m} k={k}", flush=True)
         self.pts, self.A, self.k = pts, A, k
         N = len(pts)
@@ -60,7 +60,8 @@ class Problem:
         smp = rsrs.rsrs_samples_wrap(self.tc, dY, dZ, dOm, dPsi)
         self.F = rsrs.rsrs_factor(self.tc, smp, k, reproject=reproject)
         torch.cuda.synchronize()
-        self.Fo = orr.factor(self.to, A @ Om, A.T @ Psi, Om, Psi, k)
+        self.Fo = orr.factor(self.to, A @ Om, A.T @ Psi, Om, Psi, k, keep_M=keep_M)
+        self.all_matched = False
 
 
 def compare_boxes(P, factor=100.0):
@@ -92,6 +93,7 @@ def compare_boxes(P, factor=100.0):
             assert noise_limited, (i, bo.norm_yz / bo.r11_min)
             print(f"[parity] box {i}: skeletons differ at rounding-level pivots; "
                   f"solutions compared instead", flush=True)
+            P.all_matched = False
             return worst, i
         assert np.array_equal(bg["R"], bo.R)
         # a box injects at most its own pred; the sketch updates (unit
@@ -105,14 +107,24 @@ def compare_boxes(P, factor=100.0):
         worst = max(worst, ratio)
         P.max_pred = max(P.max_pred, pred)
         assert ratio < factor, (i, errs, pred)
+    P.all_matched = True
     return worst, len(Fo.boxes)
 
 
 def solve_tolerance(P):
-    """eq. err_solve_cond: each approximate solution is within
-    2 eps cond / (1 - eps cond) of the exact one, eps = relerr of the oracle."""
-    eps = orr.relerr(P.Fo, P.A)
+    """Tolerance on ||u_gpu - u_oracle|| / ||u_oracle||.
+
+    When every box matched the oracle's (same skeletons, blocks within their
+    rounding bound) the two factorizations are the same one up to rounding,
+    and solutions must agree to 10 cond(A) 1e-10 (the FP64 parity bar).
+    After a logged divergence at rounding-level pivots the two are different,
+    equally valid factorizations; each solution is then within
+    2 eps cond / (1 - eps cond) of the exact one (eq. err_solve_cond, eps =
+    relerr of the oracle), so they differ by at most twice that."""
     cond = np.linalg.cond(P.A)
+    if P.all_matched:
+        return 10.0 * cond * 1e-10
+    eps = orr.relerr(P.Fo, P.A)
     assert eps * cond < 0.5
     return 2.0 * 2.0 * eps * cond / (1.0 - eps * cond) + 1e-12
 
@@ -211,6 +223,8 @@ def _log_problem(n, m, k, skew=0.0, **kw):
 def _solution_checks(P):
     N = len(P.pts)
     tol_oracle = solve_tolerance(P)
+    print(f"[parity] solutions compared to {tol_oracle:.1e} "
+          f"({'every box matched' if P.all_matched else 'after a rounding-level divergence'})", flush=True)
     f = inputs.rhs(N, 3)
     df = dev(f)
     for tr in (False, True):
@@ -302,15 +316,66 @@ def test_refinement_fp64_reaches_1e10():
     assert np.linalg.norm(res, axis=0).max() / np.linalg.norm(f.cpu().numpy(), axis=0).min() < 2e-10
 
 
+def _gpu_relerr(P):
+    """||A - A_approx|| / ||A|| of the GPU factor (dense, eq. error)."""
+    N = len(P.pts)
+    Aap = P.F.apply(dev(np.eye(N))).cpu().numpy()
+    return float(np.linalg.norm(P.A - Aap, 2) / np.linalg.norm(P.A, 2))
+
+
+def test_config0_geometry_every_box_matches():
+    """The 64x64 workload's geometry (leaf 64, 84 processed boxes) at k = 16,
+    where no box's far field falls to rounding level within k pivots: every
+    box's skeletons and blocks and the root must match the oracle's, the
+    solutions to the FP64 parity bar, and the GPU factor's relerr must be
+    the oracle's to within a factor 2."""
+    need_gpu()
+    P = _log_problem(64, 64, 16)
+    assert len(P.Fo.boxes) == 84
+    assert all(bo.r11_min >= 1e-11 * bo.norm_yz for bo in P.Fo.boxes)
+    worst, ncmp = compare_boxes(P)
+    print(f"[config0 k=16] {ncmp}/{len(P.Fo.boxes)} boxes compared, worst error / predicted {worst:.2f}",
+          flush=True)
+    assert ncmp == 84 and P.all_matched
+    Bt, At = P.F.root()
+    assert np.array_equal(Bt, P.Fo.Bt)
+    assert relmax(At, P.Fo.At) < 100.0 * P.max_pred
+    _solution_checks(P)
+    eg, eo = _gpu_relerr(P), orr.relerr(P.Fo, P.A)
+    print(f"[config0 k=16] relerr GPU {eg:.3e}, oracle {eo:.3e}", flush=True)
+    assert eg <= 2.0 * eo
+
+
 def test_config0_full_parity():
     """64x64 grid, log kernel, leaf 64, k = 32 at s = s_req (the configured
-    s = 320 is below the requirement)."""
+    s = 320 is below the requirement).  At this rank the far fields of the
+    boxes fall to rounding level before k pivots, so skeleton sets may part
+    from the oracle's at the first box; every box of the first colour class
+    (which sees the initial sketches only) is judged by its ID residual on
+    the oracle's own far-field sketch, and the whole factor by its relerr
+    against the oracle's and its refined residual."""
     need_gpu()
-    P = _log_problem(64, 64, 32)
+    P = _log_problem(64, 64, 32, keep_M=True)
     assert P.s == 832
     worst, ncmp = compare_boxes(P)
-    print(f"[config0] {ncmp} boxes compared, worst error / predicted {worst:.2f}")
+    print(f"[config0] {ncmp}/{len(P.Fo.boxes)} boxes compared, worst error / predicted {worst:.2f}",
+          flush=True)
+    first = [i for i, bo in enumerate(P.Fo.boxes)
+             if bo.level == P.Fo.boxes[0].level and bo.colour == P.Fo.boxes[0].colour]
+    assert len(first) >= 4
+    for i in first:
+        bo, bg = P.Fo.boxes[i], P.F.box(i)
+        M = bo.M
+        sg, rg = np.searchsorted(bo.Ba, bg["S"]), np.searchsorted(bo.Ba, bg["R"])
+        so, ro = np.searchsorted(bo.Ba, bo.S), np.searchsorted(bo.Ba, bo.R)
+        res_g = np.linalg.norm(M[rg] - bg["T"] @ M[sg])
+        res_o = np.linalg.norm(M[ro] - bo.T @ M[so])
+        assert res_g <= 10.0 * res_o + 1e-12 * np.linalg.norm(M), (i, res_g, res_o)
+    print(f"[config0] ID residuals of all {len(first)} first-class boxes within 10x the oracle's", flush=True)
     _solution_checks(P)
+    eg, eo = _gpu_relerr(P), orr.relerr(P.Fo, P.A)
+    print(f"[config0] relerr GPU {eg:.3e}, oracle {eo:.3e}", flush=True)
+    assert eg <= 2.0 * eo
     f = dev(inputs.rhs(4096, 1))
     u, rel, it = rsrs.rsrs_solve_refine(P.F, P.op, f, tol=1e-10, maxit=5)
     assert rel <= 1e-10

@@ -559,3 +559,75 @@ def test_work_model_matches_factor_shapes(symmetric):
     want = (2 * (4 * 400 * l * l - 4 / 3 * l ** 3) + 8 * 64 * 400 * l + 4 * 400 * 64 * 8 + 8 * r * 8 * 400
             + 4 * r * 400 * l + 2 / 3 * r ** 3 + 4 * r * r * 200 + 8 * r * 200 * 400)
     assert abs(w.flops - want) < 1e-9 * want
+
+
+# ---------------------------------------------------------------- ID options (rank tolerance, concatenation)
+
+def test_rank_tolerance_finds_the_exact_far_field_rank():
+    """rank_tol: on an exactly H2 operator (far-field rank <= 2r = 6 < k = 12)
+    each box keeps exactly as many skeletons as its far-field sketch has
+    rank (singular values of M with a gap of > 1e6 around it), never more
+    than k, and the factorization stays exact (relerr at rounding)."""
+    pts = inputs.grid2d(16)
+    t = ot.build_tree(pts, leaf_size=16)
+    A = exact_h2(t, r=3)
+    k = 12
+    s = ot.samples_required(t, k, k)
+    Om, Psi = inputs.test_matrices(256, s)
+    F = orr.factor(t, A @ Om, A.T @ Psi, Om, Psi, k, keep_M=True, rank_tol=1e-9)
+    assert len(F.boxes) == 20
+    for bf in F.boxes:
+        sv = np.linalg.svd(bf.M, compute_uv=False)
+        rank = int(np.sum(sv > 1e-9 * bf.norm_yz))
+        assert len(bf.S) == min(rank, k, len(bf.Ba)), (len(bf.S), rank)
+        if 0 < rank < len(sv):   # a clear gap: the rank is not a rounding decision
+            assert sv[rank] < 1e-12 * sv[0]
+        assert len(bf.S) <= 6
+    assert orr.relerr(F, A) < 1e-11
+
+
+def test_rank_tolerance_trend_and_fixed_rank_limit():
+    """A smaller tolerance keeps more skeletons and gives a smaller error;
+    a tolerance below every pivot reproduces the fixed-rank factorization
+    (same skeletons) and rank_tol = 0 is the fixed rank itself."""
+    A, t, Om, Psi = _small_log_problem(n=32, m=32, k=16)
+    Y, Z = A @ Om, A.T @ Psi
+    Ff = orr.factor(t, Y, Z, Om, Psi, 16)
+    F0 = orr.factor(t, Y, Z, Om, Psi, 16, rank_tol=1e-300)
+    assert all(np.array_equal(a.S, b.S) for a, b in zip(Ff.boxes, F0.boxes))
+    errs, kept = [], []
+    tols = (1e-5, 1e-7, 1e-9)
+    for tol in tols:
+        F = orr.factor(t, Y, Z, Om, Psi, 16, rank_tol=tol)
+        errs.append(orr.relerr(F, A))
+        kept.append(sum(len(bf.S) for bf in F.boxes))
+    assert kept[0] < kept[1] < kept[2] <= sum(len(bf.S) for bf in Ff.boxes)
+    assert errs[0] > errs[1] > errs[2]
+    assert all(e < 100 * tol for e, tol in zip(errs, tols)), errs
+
+
+def test_concatenated_id_option():
+    """id_mode = "concat": the ID of [M_Y, M_Z] (one skeleton set for the
+    rows and the columns, Sec. 3.1): it equals LAPACK's pivoted QR of that
+    concatenation on the first box, is exact on an exactly H2 operator, and
+    on the log kernel is as accurate as the summed sketch (within 10x)."""
+    A, t, Om, Psi = _small_log_problem(n=32, m=32, k=12, skew=2e-3)
+    Fc = orr.factor(t, A @ Om, A.T @ Psi, Om, Psi, 12, keep_M=True, id_mode="concat")
+    Fs = orr.factor(t, A @ Om, A.T @ Psi, Om, Psi, 12)
+    bf = Fc.boxes[0]
+    assert bf.M.shape[1] == 2 * Om.shape[1]
+    C = np.concatenate([bf.Ba, bf.Na])
+    P = t.perm
+    MY = orr.nullify((A @ Om)[P][bf.Ba], Om[P][C])
+    MZ = orr.nullify((A.T @ Psi)[P][bf.Ba], Psi[P][C])
+    _, _, piv = sla.qr(np.concatenate([MY, MZ], axis=1).T, pivoting=True)
+    assert np.array_equal(np.sort(bf.Ba[piv[:12]]), bf.S)
+    ec, es = orr.relerr(Fc, A), orr.relerr(Fs, A)
+    assert ec < 10 * es and es < 10 * ec, (ec, es)
+    pts = inputs.grid2d(16)
+    th = ot.build_tree(pts, leaf_size=16)
+    H = exact_h2(th, r=3)
+    s = ot.samples_required(th, 6, 6)
+    Om2, Psi2 = inputs.test_matrices(256, s)
+    Fh = orr.factor(th, H @ Om2, H.T @ Psi2, Om2, Psi2, 6, id_mode="concat")
+    assert orr.relerr(Fh, H) < 1e-11
