@@ -336,6 +336,21 @@ void rsrs_solve_graphs(int on);
 rsrs_status rsrs_apply(const rsrs_factor_t* f, int transpose, int64_t nrhs, const double* X,
                        int64_t ldx, double* Y, int64_t ldy, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): rsrs_solve
+ * with the same arguments and results, but no allocation of any kind on the
+ * device.  Its two tree-ordered work blocks (n x nrhs elements of the
+ * factor's type each, rounded up to 256 bytes) and the launch descriptors
+ * live in one fixed library array of 96 MiB per device, which every GPU the
+ * library runs on holds until the process ends; a call that needs more
+ * (e.g. more than ~6 M FP64 elements n x nrhs) fails with RSRS_E_INVALID
+ * and a message giving the bytes needed.  Every call on one GPU shares that
+ * array: calls that overlap on a GPU (different streams or threads) race and
+ * must be serialised by the caller.  Launches are direct (no graph); the
+ * descriptors are copied from pageable host memory on `stream`. */
+rsrs_status rsrs_solve_noalloc(const rsrs_factor_t* f, int transpose, int64_t nrhs, const double* F,
+                               int64_t ldf, double* U, int64_t ldu, void* stream);
+
 /* Iterative refinement u_{j+1} = u_j + A_approx^{-1} (f - A u_j) with the
  * residual from the black-box product mv (FP64), until
  * max_col ||f - A u||_2 / ||f||_2 <= tol or maxit corrections.  Returns

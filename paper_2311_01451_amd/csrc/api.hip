@@ -19,6 +19,8 @@ rsrs_status factor_impl(const rsrs_tree_t* th, rsrs_samples_t* smp, const rsrs_f
                         hipStream_t st, rsrs_factor_t** out);
 rsrs_status factor_batch_impl(int64_t nprob, const rsrs_tree_t* const* trees, rsrs_samples_t* const* smps,
                               const rsrs_factor_opts* opts, hipStream_t st, rsrs_factor_t** out);
+rsrs_status apply_factor_noalloc(const rsrs_factor_t* F, int op, int transpose, int64_t w, const double* Fin,
+                                 int64_t ldf, double* Uout, int64_t ldu, hipStream_t st);
 rsrs_status apply_factor(const rsrs_factor_t* F, int op, int transpose, int64_t w, const double* Fin,
                          int64_t ldf, double* Uout, int64_t ldu, hipStream_t st);
 
@@ -526,6 +528,12 @@ rsrs_status rsrs_solve(const rsrs_factor_t* f, int transpose, int64_t nrhs, cons
                        double* U, int64_t ldu, void* stream) {
   if (!f || !F || !U || nrhs < 0 || ldf < nrhs || ldu < nrhs) return invalid("bad solve arguments");
   return apply_factor(f, 0, transpose, nrhs, F, ldf, U, ldu, static_cast<hipStream_t>(stream));
+}
+
+rsrs_status rsrs_solve_noalloc(const rsrs_factor_t* f, int transpose, int64_t nrhs, const double* F,
+                               int64_t ldf, double* U, int64_t ldu, void* stream) {
+  if (!f || !F || !U || nrhs < 0 || ldf < nrhs || ldu < nrhs) return invalid("bad solve arguments");
+  return apply_factor_noalloc(f, 0, transpose, nrhs, F, ldf, U, ldu, static_cast<hipStream_t>(stream));
 }
 
 rsrs_status rsrs_apply(const rsrs_factor_t* f, int transpose, int64_t nrhs, const double* X, int64_t ldx,

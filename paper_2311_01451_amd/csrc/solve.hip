@@ -20,6 +20,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
+#include <unordered_map>
 
 #include "impl.hpp"
 #include "profile.hpp"
@@ -266,6 +268,89 @@ rsrs_status apply_factor(const rsrs_factor_t* F, int op, int transpose, int64_t 
 
 extern "C" void rsrs_solve_graphs(int on) { rsrs::g_graphs = on != 0; }
 
+// ---------------------------------------------------------------------------
+// Solves and applies that allocate nothing: the two tree-ordered work blocks
+// and the launch descriptors live in a fixed device array (`scratch`) that
+// every GPU the library runs on holds until the process ends.  In host code
+// `scratch` names a host-side stand-in, so its device address is looked up
+// once per device (hipGetSymbolAddress with that device current) and only
+// that address is handed to kernels and copies.  Nothing in it has to start
+// at zero: the gather writes every row of x that is read, and every row of u
+// is written (each point is in exactly one box's R or in B_t) before the
+// downward sweep reads it.  Calls that overlap on one GPU share the array and
+// race.
 namespace rsrs {
+namespace {
+
+constexpr size_t kNoallocScratchBytes = (size_t)96 << 20;
+__device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+std::mutex g_scratch_mu;
+std::unordered_map<int, void*> g_scratch_addr;   // device ordinal -> address of its copy
+
+rsrs_status scratch_address(void** out) {
+  int dev = 0;
+  RSRS_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_addr.find(dev);
+  if (it != g_scratch_addr.end()) {
+    *out = it->second;
+    return RSRS_OK;
+  }
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) {
+    set_error(std::string("hipGetSymbolAddress of the no-alloc scratch failed: ") + hipGetErrorString(e));
+    return RSRS_E_HIP;
+  }
+  g_scratch_addr[dev] = p;
+  *out = p;
+  return RSRS_OK;
+}
+
+template <typename T>
+rsrs_status apply_noalloc(const rsrs_factor_t* F, int op, int transpose, int64_t w, const double* Fin,
+                          int64_t ldf, double* Uout, int64_t ldu, hipStream_t st) {
+  unsigned char* base = nullptr;
+  RSRS_TRY(scratch_address(reinterpret_cast<void**>(&base)));
+  const size_t blk = (size_t)round_up((int64_t)((size_t)F->n * (size_t)w * sizeof(T)), 256);
+  T* x = reinterpret_cast<T*>(base);
+  T* u = reinterpret_cast<T*>(base + blk);
+  const GemmShape shp = w <= 16 ? GS_64x16 : GS_64x64;
+  std::vector<GemmDescT<T, T>> all;
+  std::vector<GemmLaunch> L;
+  RSRS_TRY(build_apply<T>(F, op, transpose, w, x, u,
+                          [&](const std::vector<GemmDescT<T, T>>& d, int ta, int tb, int mode) {
+                            const size_t b0 = all.size();
+                            all.insert(all.end(), d.begin(), d.end());
+                            return gemm_plan<T, T>(d, b0, ta, tb, mode, shp, "solve", L);
+                          }));
+  const size_t dbytes = all.size() * sizeof(GemmDescT<T, T>);
+  const size_t need = 2 * blk + dbytes;
+  if (need > kNoallocScratchBytes) {
+    set_error("the allocation-free solve needs " + std::to_string(need) + " bytes of scratch for n = " +
+              std::to_string(F->n) + " and " + std::to_string(w) + " columns; its fixed scratch holds " +
+              std::to_string(kNoallocScratchBytes) + " bytes (use fewer columns per call)");
+    return RSRS_E_INVALID;
+  }
+  void* descs = base + 2 * blk;
+  const int64_t* perm = F->perm.as<int64_t>();
+  gather_rows<double, T>(st, x, w, Fin, ldf, perm, F->n, w);
+  // pageable source: the call returns once the bytes have been staged
+  if (dbytes) RSRS_HIP(hipMemcpyAsync(descs, all.data(), dbytes, hipMemcpyHostToDevice, st));
+  for (const auto& l : L) RSRS_TRY(gemm_exec(l, descs, sizeof(GemmDescT<T, T>), st));
+  scatter_rows<T, double>(st, Uout, ldu, u, w, perm, F->n, w);
+  RSRS_HIP(hipGetLastError());
+  return RSRS_OK;
+}
+
+}  // namespace
+
+rsrs_status apply_factor_noalloc(const rsrs_factor_t* F, int op, int transpose, int64_t w, const double* Fin,
+                                 int64_t ldf, double* Uout, int64_t ldu, hipStream_t st) {
+  if (w <= 0) return RSRS_OK;
+  if (F->esz == 4) return apply_noalloc<float>(F, op, transpose, w, Fin, ldf, Uout, ldu, st);
+  return apply_noalloc<double>(F, op, transpose, w, Fin, ldf, Uout, ldu, st);
+}
 
 }  // namespace rsrs

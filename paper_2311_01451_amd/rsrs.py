@@ -96,7 +96,7 @@ EXPORTS = [
     "rsrs_sample", "rsrs_sample_symmetric", "rsrs_samples_wrap_symmetric", "rsrs_samples_destroy", "rsrs_gaussian", "rsrs_factor", "rsrs_factor_batched",
     "rsrs_factor_destroy", "rsrs_release_cached",
     "rsrs_factor_get_info", "rsrs_factor_box_sizes", "rsrs_factor_box_copy",
-    "rsrs_factor_root_copy", "rsrs_solve", "rsrs_apply", "rsrs_solve_refine",
+    "rsrs_factor_root_copy", "rsrs_solve", "rsrs_solve_noalloc", "rsrs_apply", "rsrs_solve_refine",
     "rsrs_profile_enable", "rsrs_profile_filter", "rsrs_profile_reset", "rsrs_profile_read", "rsrs_solve_graphs",
     "rsrs_server_create", "rsrs_server_destroy", "rsrs_server_add_factor",
     "rsrs_server_release_factor", "rsrs_server_submit_solve", "rsrs_server_submit_factor",
@@ -147,6 +147,7 @@ def lib():
         "rsrs_factor_root_copy": (i32, [vp, P(i64), vp, vp]),
         "rsrs_solve": (i32, [vp, i32, i64, vp, i64, vp, i64, vp]),
         "rsrs_apply": (i32, [vp, i32, i64, vp, i64, vp, i64, vp]),
+        "rsrs_solve_noalloc": (i32, [vp, i32, i64, vp, i64, vp, i64, vp]),
         "rsrs_solve_refine": (i32, [vp, vp, vp, i64, vp, i64, vp, i64, dbl, i32, P(dbl),
                                     P(i32), vp]),
         "rsrs_server_create": (i32, [P(ServerOpts), P(vp)]),
@@ -504,6 +505,14 @@ def rsrs_solve(f: Factor, F, transpose=False, out=None, stream=None):
         out = torch.empty_like(F)
     pu, ldu = _dev(out, "out")
     _check(lib().rsrs_solve(f.handle, int(transpose), F.shape[1], pf, ldf, pu, ldu, _stream(stream)))
+    return out
+
+
+def rsrs_solve_noalloc(f: Factor, F, out, transpose=False, stream=None):
+    """rsrs_solve without any device allocation (the caller provides ``out``)."""
+    pf, ldf = _dev(F, "F")
+    pu, ldu = _dev(out, "out")
+    _check(lib().rsrs_solve_noalloc(f.handle, int(transpose), F.shape[1], pf, ldf, pu, ldu, _stream(stream)))
     return out
 
 
