@@ -152,20 +152,31 @@ def gpu_bench(steps: int, warmup: int, do_profile: bool, latency_reps: int = 40,
         rsrs.rsrs_profile_reset()
         rsrs.rsrs_profile_filter(None)
 
-    # solve latency of the resident factor (16 RHS per request)
-    lat = []
+    # solve latency of the resident factor (16 RHS per request): one-shot
+    # solves, and solves refined to the tolerance through the operator
+    lat, latr = [], []
     for _ in range(latency_reps + 5):
         torch.cuda.synchronize()
         a = time.perf_counter()
         F.solve(f)
         torch.cuda.synchronize()
         lat.append((time.perf_counter() - a) * 1e3)
+    for _ in range(max(latency_reps // 4, 3) + 2):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        rsrs.rsrs_solve_refine(F, op, f, tol=TOL, maxit=30)
+        torch.cuda.synchronize()
+        latr.append((time.perf_counter() - a) * 1e3)
     lat = np.array(lat[5:] if len(lat) > 5 else lat)
+    latr = np.array(latr[2:])
     # one-shot residual of the last factor (FP64 residual through the
     # operator), outside the timed steps
     r = f - op.matvec(F.solve(f))
     rec[-1]["relres_oneshot"] = float((r.norm(dim=0) / f.norm(dim=0)).max())
-    return rec, elapsed, (prof, prof_all), lat
+    wm = rsrs.rsrs_work_model(rsrs.rsrs_build_tree(pts, LEAF), K, rec[-1]["s_eff"], symmetric,
+                              4 if mixed else 8)
+    rec[-1]["model_flops"] = wm["flops"]
+    return rec, elapsed, (prof, prof_all), (lat, latr)
 
 
 def by_kernel(prof: dict) -> dict:
@@ -210,19 +221,11 @@ def measured_traffic(tag: str):
     return round(t["fetch_bytes_per_launch"] + t["write_bytes_per_launch"], 1)
 
 
-def roofline_from_profile(prof: dict, prof_all: dict, steps: int) -> dict | None:
-    """Roofline of the kernel with the largest share of GPU time in the
-    profiled step, from its launches in the timed steps (HIP events on the
-    launch stream).  GEMM forms run on MFMA (peak of their operand type);
-    kernels whose algorithmic flops per byte fall below the machine balance
-    are priced by their bytes against HBM; the rest are FP64 vector work."""
-    if not prof or not prof_all:
-        return None
-    prof, prof_all = by_kernel(prof), by_kernel(prof_all)
-    tag = max(prof_all, key=lambda t: prof_all[t]["ms"])
-    if tag not in prof:
-        return None
-    e = prof[tag]
+def roofline_entry(tag: str, e: dict, total_ms: float, all_ms: float, steps: int) -> dict:
+    """Roofline of one kernel from its summed launches: GEMM forms run on
+    MFMA (peak of their operand type); kernels whose algorithmic flops per
+    byte fall below the machine balance are priced by their bytes against
+    HBM; the rest are FP64 vector work."""
     streaming = e["bytes"] > 0 and e["flops"] < MACHINE_BALANCE * e["bytes"]
     if tag.startswith("gemm") or (e["flops"] > 0 and not streaming):
         ach = e["flops"] / (e["ms"] * 1e-3) / 1e12
@@ -230,7 +233,7 @@ def roofline_from_profile(prof: dict, prof_all: dict, steps: int) -> dict | None
             bound, peak = "mfma", PEAK_BF16_TFLOPS
         elif tag.startswith("gemm32"):
             bound, peak = "mfma", PEAK_FP32_TFLOPS
-        elif tag.startswith("gemm"):
+        elif tag.startswith("gemm") or tag.startswith("gauss_jordan") or tag.startswith("chol"):
             bound, peak = "mfma", PEAK_FP64_TFLOPS
         else:
             bound, peak = "alu", PEAK_FP64_TFLOPS
@@ -238,25 +241,73 @@ def roofline_from_profile(prof: dict, prof_all: dict, steps: int) -> dict | None
     else:
         ach = e["bytes"] / (e["ms"] * 1e-3) / 1e9
         bound, peak, unit = "hbm", PEAK_HBM_GBS, "GB/s"
-    total_ms = sum(v["ms"] for v in prof_all.values())
     return {"bound": bound, "achieved": round(ach, 3), "peak": peak, "unit": unit,
             "frac": round(ach / peak, 4), "traffic": measured_traffic(tag), "kernel": tag,
             "launches_per_step": e["launches"] / steps,
             "avg_launch_ms": e["ms"] / e["launches"],
             "algorithmic_flops_per_launch": e["flops"] / e["launches"],
             "algorithmic_bytes_per_launch": e["bytes"] / e["launches"],
-            "share_of_kernel_time": round(prof_all[tag]["ms"] / total_ms, 4)}
+            "share_of_kernel_time": round(total_ms / all_ms, 4)}
 
 
-def cpu_baseline(s_eff: int) -> dict:
-    """The oracle, as it stands, on a bounded sample of the same workload:
-    the sketch rows of the first box of the first processed level (computed by
-    the oracle's dense operator rows), then that box's full Algorithm 1 step.
-    Both are extrapolated to the whole step: sampling by rows (N / rows),
-    factorization by the oracle's per-box cost model sum_B s l_B^2 (the
-    Householder QRs of the s x l panels dominate)."""
+def per_level_roofline(prof_all: dict) -> dict | None:
+    """Roofline of the factorization's own dominant kernel (operator products
+    and solves left out), from the profiled step (every launch bracketed)."""
+    if not prof_all:
+        return None
+    keep = {t: v for t, v in prof_all.items()
+            if not t.endswith(":operator") and not t.startswith("solve") and ":solve" not in t}
+    merged = by_kernel(keep)
+    if not merged:
+        return None
+    tag = max(merged, key=lambda t: merged[t]["ms"])
+    all_ms = sum(v["ms"] for v in by_kernel(prof_all).values())
+    out = roofline_entry(tag, merged[tag], merged[tag]["ms"], all_ms, 1)
+    out["timed"] = "profiled step (every launch bracketed by HIP events)"
+    return out
+
+
+def roofline_from_profile(prof: dict, prof_all: dict, steps: int) -> dict | None:
+    """Roofline of the kernel with the largest share of GPU time in the
+    profiled step, from its launches in the timed steps (HIP events on the
+    launch stream)."""
+    if not prof or not prof_all:
+        return None
+    prof, prof_all = by_kernel(prof), by_kernel(prof_all)
+    tag = max(prof_all, key=lambda t: prof_all[t]["ms"])
+    if tag not in prof:
+        return None
+    e = prof[tag]
+    total_ms = sum(v["ms"] for v in prof_all.values())
+    return roofline_entry(tag, e, prof_all[tag]["ms"], total_ms, steps)
+
+
+def host_info() -> dict:
+    """CPU model, usable cores and the BLAS the oracle runs on."""
     from threadpoolctl import threadpool_info
-    from oracle import operators as oop
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    blas = [{"api": d.get("internal_api"), "threads": d.get("num_threads")} for d in threadpool_info()]
+    return {"cpu_model": model, "nproc": len(os.sched_getaffinity(0)), "blas": blas}
+
+
+def cpu_baseline(s_eff: int, nbox: int = 4) -> dict:
+    """The oracle, as it stands, on a bounded sample of the same workload
+    (symmetric variant, the headline's): `nbox` boxes of the first colour
+    class of the first processed level, whose sketches are still the initial
+    ones, each with its sketch rows Y_B = A_B Omega formed from the oracle's
+    dense operator rows and its full step of Algorithm 1.  The measured
+    oracle rate (work of those boxes by the work model of Sec. 4.5 over their
+    time) prices the whole factorization, root and a 16-column solve; the
+    sampling is scaled by rows (N / sampled rows)."""
+    from threadpoolctl import threadpool_info
+    from oracle import flops as ofl
     from oracle import rsrs as orr
     from oracle import tree as ot
     from paper_2311_01451_amd import inputs
@@ -266,53 +317,55 @@ def cpu_baseline(s_eff: int) -> dict:
     h = 1.0 / GRID_N
     t = ot.build_tree(pts, LEAF)
     sch = ot.schedule(t, K)
-    lev = sch.levels[[i for i, c in enumerate(sch.order) if c][0]]
-    li = sch.levels.index(lev)
+    li = [i for i, c in enumerate(sch.order) if c][0]
+    lev = sch.levels[li]
     cls0 = sch.order[li][0]
-    box = max(cls0, key=lambda b: (int(sch.l_count[b]), -int(b)))
-    nb = sch.nbrs[lev][box]
-    Ba = np.arange(t.pt_begin[box], t.pt_end[box])
-    Na = np.sort(np.concatenate([np.arange(t.pt_begin[x], t.pt_end[x]) for x in nb]))
-    C = np.concatenate([Ba, Na])
-    rng = np.random.default_rng(inputs.BASE_SEED)
-    Om = np.zeros((N, s_eff))
-    Psi = np.zeros((N, s_eff))
-    Om_full = rng.standard_normal((N, s_eff))
-    Psi_full = rng.standard_normal((N, s_eff))
+    step = max(1, len(cls0) // nbox)
+    boxes = cls0[::step][:nbox]
     perm = t.perm
-    Om[:] = Om_full[perm]
-    Psi[:] = Psi_full[perm]
+    Om_full = inputs.gaussian(N, s_eff, 0)
+    Om = Om_full[perm]
     Y = np.zeros((N, s_eff))
-    Z = np.zeros((N, s_eff))
-    t0 = time.perf_counter()
-    # sampled sketch rows Y_C = A[C, :] Omega, Z_C = A^T[C, :] Psi (A symmetric here)
-    diff = pts[perm[C]][:, None, :] - pts[None, :, :]
-    r = np.sqrt(np.sum(diff * diff, axis=2))
-    with np.errstate(divide="ignore"):
-        Arows = (h * h) * (-np.log(r) / (2 * np.pi))
-    Arows[np.arange(len(C)), perm[C]] = 1.0 + 0.5 * h * h
-    Y[C] = Arows @ Om_full
-    Z[C] = Arows @ Psi_full
-    t_sample = time.perf_counter() - t0
-    del diff, r, Arows
-    t0 = time.perf_counter()
-    orr._process_box(box, lev, 0, Ba, Na, Y, Z, Om, Psi, K, False)
-    t_box = time.perf_counter() - t0
-    # per-box cost model over the whole factorization
-    model = lambda l: s_eff * float(l) ** 2
-    total = sum(model(sch.l_count[b]) for cls in sum(sch.order, []) for b in cls)
-    total += model(sch.root_count)
-    est_factor = t_box * total / model(len(C))
-    est_sample = t_sample * N / len(C)
-    est = est_factor + est_sample
+    t_sample = t_factor = 0.0
+    rows = 0
+    done = []
+    for box in boxes:
+        nb = sch.nbrs[lev][box]
+        Ba = np.arange(t.pt_begin[box], t.pt_end[box])
+        Na = np.sort(np.concatenate([np.arange(t.pt_begin[x], t.pt_end[x]) for x in nb]))
+        a = time.perf_counter()
+        # sketch rows of the box: rows of the kernel matrix times Omega
+        diff = pts[perm[Ba]][:, None, :] - pts[None, :, :]
+        r = np.sqrt(np.sum(diff * diff, axis=2))
+        with np.errstate(divide="ignore"):
+            Arows = (h * h) * (-np.log(r) / (2 * np.pi))
+        Arows[np.arange(len(Ba)), perm[Ba]] = 1.0 + 0.5 * h * h
+        Y[Ba] = Arows @ Om_full
+        t_sample += time.perf_counter() - a
+        rows += len(Ba)
+        del diff, r, Arows
+        a = time.perf_counter()
+        orr._process_box(int(box), lev, 0, Ba, Na, Y, Y, Om, Om, K, False, True)
+        t_factor += time.perf_counter() - a
+        done.append(ofl.box_work(len(Ba), len(Na), K, s_eff, symmetric=True))
+    rate = sum(w.flops for w in done) / t_factor
+    fw = ofl.factor_work(t, K, s_eff, symmetric=True)
+    sf, _ = ofl.solve_work(fw, NRHS)
+    est_factor = fw.flops / rate
+    est_solve = sf / rate
+    est_sample = t_sample * N / rows
+    est = est_factor + est_solve + est_sample
+    hi = host_info()
     threads = max((d.get("num_threads", 1) for d in threadpool_info()), default=1)
     return {"value": round(NRHS / est, 6), "unit": "RHS cols/s", "cores": int(threads),
             "kind": "oracle",
-            "sample": f"oracle sampling of {len(C)} sketch rows ({t_sample:.1f} s) and Algorithm 1 "
-                      f"on box {box} (level {lev}, l={len(C)}, {t_box:.1f} s), extrapolated by "
-                      f"rows and by the per-box model s*l^2: est. factor {est_factor:.0f} s, "
-                      f"sampling {est_sample:.0f} s; solve not included",
-            "est_step_s": round(est, 1)}
+            "sample": f"symmetric oracle on {len(done)} boxes of the first colour class of level {lev} "
+                      f"(b={done[0].b}, l={done[0].b + done[0].n}, s={s_eff}; {t_factor:.1f} s, "
+                      f"{rate / 1e9:.1f} GFLOP/s by the work model) and their {rows} sketch rows "
+                      f"({t_sample:.1f} s); whole step priced at that rate by the work model "
+                      f"(factor {fw.flops:.2e} flops -> {est_factor:.0f} s, 16-column solve "
+                      f"{est_solve:.2f} s) and sampling scaled by rows ({est_sample:.0f} s)",
+            "est_step_s": round(est, 1), "host": hi}
 
 
 def serving_bench(duration_s: float, load: float = 0.7) -> dict:
@@ -485,6 +538,87 @@ def serving_bench(duration_s: float, load: float = 0.7) -> dict:
     }
 
 
+def config0_leg(steps: int = 3) -> dict:
+    """Plain FP64 RSRS (general two-sided algorithm) on the 64 x 64 grid:
+    N = 4096, leaf 64, k = p = 32, s = max(320, s_required), 16 right-hand
+    sides refined to 1e-10 through the FP64 operator.  Factor time, RHS
+    columns per second of the whole step (sampling, factor, refined solve)."""
+    import torch
+    from paper_2311_01451_amd import inputs, rsrs
+
+    n, k = 64, 32
+    pts = inputs.grid2d(n)
+    op = rsrs.rsrs_op_create_kernel(rsrs.RSRS_OP_LOG2D, pts, 1.0 / n)
+    f = torch.tensor(inputs.rhs(n * n, NRHS), dtype=torch.float64, device="cuda")
+    rec = []
+    for it_ in range(steps + 1):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        tc = rsrs.rsrs_build_tree(pts, LEAF)
+        s = max(320, tc.samples_required(k, k))
+        smp = rsrs.rsrs_sample(tc, op, s, inputs.BASE_SEED, dtype=rsrs.RSRS_F64)
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        F = rsrs.rsrs_factor(tc, smp, k)
+        torch.cuda.synchronize()
+        c = time.perf_counter()
+        u, rel, its = rsrs.rsrs_solve_refine(F, op, f, tol=1e-10, maxit=10)
+        torch.cuda.synchronize()
+        d = time.perf_counter()
+        if it_ > 0:   # the first step warms up
+            rec.append((d - a, c - b, rel, its, s))
+    step_s = float(np.mean([r[0] for r in rec]))
+    return {"workload": "2D log kernel on the 64x64 grid (N=4096), leaf 64, k=p=32, FP64, general variant, "
+                        "16 RHS refined to 1e-10",
+            "s": rec[-1][4], "steps": steps, "cols_per_s": round(NRHS / step_s, 2),
+            "ms_per_step": round(step_s * 1e3, 3), "factor_s": round(float(np.mean([r[1] for r in rec])), 4),
+            "relres": rec[-1][2], "refine_iters": rec[-1][3]}
+
+
+def config2_leg() -> dict:
+    """3D variable-coefficient Poisson, mixed precision: 7-point
+    -div(a grad u) on the 48^3 interior grid (N = 110592), a = exp(box3(g)),
+    octree leaves of 4^3 nodes, k = p = 96, s = max(1200, s_required), FP32
+    samples through the sparse product, 16 right-hand sides refined to 1e-8
+    with the FP64 sparse residual.  One step (sampling, factor, refined
+    solve), with the fixed rank and with a rank tolerance of 1e-7."""
+    import torch
+    from paper_2311_01451_amd import inputs, rsrs
+
+    n, k = 48, 96
+    h = 1.0 / (n + 1)
+    pts = inputs.grid3d_interior(n)
+    coef = inputs.smooth_log_coefficient(n + 2)
+    op = rsrs.rsrs_op_create_poisson7(n, coef)
+    f = torch.tensor(inputs.rhs(n ** 3, NRHS), dtype=torch.float64, device="cuda")
+    out = {"workload": "3D Poisson -div(a grad u), 48^3 interior nodes (N=110592), leaves 4^3, k=p=96, "
+                       "mixed precision (FP32 samples and products, FP64 pivots and residual), 16 RHS "
+                       "refined to 1e-8"}
+    for label, tol in (("fixed_rank", 0.0), ("rank_tol_1e-7", 1e-7)):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        tc = rsrs.rsrs_build_tree(pts, LEAF, root_lo=[h / 2] * 3, root_side=64 * h)
+        s = max(1200, tc.samples_required(k, k))
+        smp = rsrs.rsrs_sample(tc, op, s, inputs.BASE_SEED, dtype=rsrs.RSRS_F32)
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        F = rsrs.rsrs_factor(tc, smp, k, precision=rsrs.RSRS_PREC_F32_MIXED, rank_tol=tol)
+        del smp
+        torch.cuda.synchronize()
+        c = time.perf_counter()
+        u, rel, its = rsrs.rsrs_solve_refine(F, op, f, tol=1e-8, maxit=30)
+        torch.cuda.synchronize()
+        d = time.perf_counter()
+        info = F.info()
+        out[label] = {"s": s, "sample_s": round(b - a, 3), "factor_s": round(c - b, 3),
+                      "solve_refine_s": round(d - c, 3), "cols_per_s": round(NRHS / (d - a), 3),
+                      "relres": rel, "refine_iters": its,
+                      "factor_tflops_algorithmic": round(info["flops"] / (c - b) / 1e12, 3),
+                      "stored_gb": round(info["stored_bytes"] / 1e9, 3)}
+        del F
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -502,6 +636,10 @@ def main():
                     help="comma list of the precision/variant runs (the first is the headline)")
     ap.add_argument("--serving", type=float, default=0.0,
                     help="run only the serving workload for this many seconds and print its line")
+    ap.add_argument("--serving-seconds", type=float, default=8.0,
+                    help="length of the Poisson stream of the serving leg in the default run")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="leave out the legs of the other workloads (configs 0, 2 and 4)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {a.gpus}); "
@@ -523,8 +661,10 @@ def main():
             continue
         runs[name] = gpu_bench(a.steps, a.warmup, not a.no_profile, a.latency_reps,
                                a.calib_copy_mib if name == "mixed" else 0, mode, ctx, sym, a.reproject)
-    def summary(rec, elapsed, profs, lat, steps):
+    def summary(rec, elapsed, profs, lats, steps):
         prof, prof_all = profs
+        lat, latr = lats
+        fs = float(np.mean([r["factor"] for r in rec]))
         return {
             "value": round(NRHS * steps / elapsed, 4),
             "ms_per_step": round(elapsed / steps * 1e3, 3),
@@ -534,11 +674,16 @@ def main():
             "refine_iters": int(rec[-1]["iters"]),
             "relres": rec[-1]["relres"],
             "relres_oneshot": rec[-1]["relres_oneshot"],
-            "factor_tflops_algorithmic": round(rec[-1]["flops"] / np.mean([r["factor"] for r in rec]) / 1e12, 3),
-            "solve_ms_p50": round(float(np.percentile(lat, 50)), 3),
-            "solve_ms_p99": round(float(np.percentile(lat, 99)), 3),
-            "solve_cols_per_s": round(NRHS / (float(np.median(lat)) * 1e-3), 1),
+            # the kernels' own flop count, and the method's (work model of Sec. 4.5)
+            "factor_tflops_algorithmic": round(rec[-1]["flops"] / fs / 1e12, 3),
+            "factor_tflops_work_model": round(rec[-1]["model_flops"] / fs / 1e12, 3),
+            "oneshot_solve_ms_p50": round(float(np.percentile(lat, 50)), 3),
+            "oneshot_solve_ms_p99": round(float(np.percentile(lat, 99)), 3),
+            "refined_solve_ms_p50": round(float(np.percentile(latr, 50)), 3),
+            "refined_solve_ms_p99": round(float(np.percentile(latr, 99)), 3),
+            "refined_solve_cols_per_s": round(NRHS / (float(np.median(latr)) * 1e-3), 1),
             "roofline": roofline_from_profile(prof, prof_all, steps),
+            "roofline_factor_kernel": per_level_roofline(prof_all),
             "kernels_one_step": {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
                                      "tflops": round(v["flops"] / max(v["ms"], 1e-9) / 1e9, 3)}
                                  for k, v in sorted(prof_all.items(), key=lambda kv: -kv[1]["ms"])[:14]},
@@ -563,7 +708,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "bf16+f32",
         "data": "synthetic",
         "config": workload_config(s_req, s_eff, a.reproject),
     }
@@ -577,6 +722,13 @@ def main():
         out["mixed_vs_fp64"] = {"speedup": round(sm["value"] / sums["fp64"]["value"], 3),
                                 "factor_speedup": round(sums["fp64"]["factor_s"] / sm["factor_s"], 3),
                                 "solution_rel_diff": float(((ua - ub).norm() / ub.norm()).item())}
+    if not a.no_configs:
+        import torch
+        out["configs"] = {}
+        for name, fn in (("config0_fp64", config0_leg), ("config2_poisson_mixed", config2_leg)):
+            out["configs"][name] = fn()
+            torch.cuda.synchronize()
+        out["configs"]["config4_serving"] = serving_bench(a.serving_seconds)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(s_eff)
     print(json.dumps(out))

@@ -258,12 +258,21 @@ rsrs_status rsrs_gaussian(double* out, int64_t nrows, int64_t ncols, int64_t ld,
  * samples with opts.symmetric = 0 -> RSRS_E_INVALID.
  * ---------------------------------------------------------------------- */
 enum { RSRS_PREC_F64 = 0, RSRS_PREC_F32_MIXED = 1 };
+/* Sketch the ID is taken of (Algorithm 1 writes the sum of the projected
+ * sketches; Sec. 3.1 skeletonizes rows and columns with one index set, the
+ * concatenated form).  The symmetric variant takes the ID of M_Y either way. */
+enum { RSRS_ID_SUM = 0, RSRS_ID_CONCAT = 1 };
 typedef struct {
-  int k;            /* fixed rank (k_B = min(k, b)) */
+  int k;            /* rank (k_B = min(k, b)); with rank_tol > 0 the cap on k_B */
   int p;            /* oversampling used in the sample check; < 0 -> p = k */
   int precision;    /* RSRS_PREC_F64 (FP64 samples) or RSRS_PREC_F32_MIXED (FP32 samples) */
   int reproject;    /* extra projection passes in the nullification (0 or 1; default 1) */
   int symmetric;    /* 1: symmetric variant for A = A^T (see below); 0: general */
+  int id_mode;      /* RSRS_ID_SUM (0): ID of M = M_Y + M_Z; RSRS_ID_CONCAT: of [M_Y, M_Z] */
+  double rank_tol;  /* 0: fixed rank.  > 0: k_B = the number of leading pivots of the
+                       column-pivoted QR whose |R_jj| exceeds rank_tol ||[Y_B Z_B]||_F
+                       (at most min(k, b)); boxes and their order stay those of the
+                       fixed-rank schedule, whose active counts bound the actual ones */
 } rsrs_factor_opts;
 
 rsrs_status rsrs_factor(const rsrs_tree_t* t, rsrs_samples_t* smp, const rsrs_factor_opts* opts,
@@ -381,8 +390,13 @@ rsrs_status rsrs_solve_refine(const rsrs_factor_t* f, rsrs_matvec_fn mv, void* u
  *    admitted together (up to 64, same precision) are factored as one
  *    rsrs_factor_batched batch; if that batch fails, each of its requests is
  *    sampled and factored again alone, so only the faulty one fails.
- * Budget 0 means unlimited.  A resident factor is charged its stored bytes
- * plus the solve workspace of a full batch.  Device blocks passed to a
+ * Budget 0 means unlimited.  A resident factor is charged its stored bytes,
+ * its permutation and the solve buffers a batch of up to max_batch_cols
+ * columns makes it hold (the per-width solve graphs' blocks in the factor's
+ * element type); the server's FP64 batch blocks are charged at their size;
+ * device memory the library keeps from finished factorizations for reuse
+ * counts against the budget when a factor request is admitted and is freed
+ * (oldest first) when the request would not fit otherwise.  Device blocks passed to a
  * request must stay valid until its ticket completes; a tree or operator
  * passed to a factor request must outlive it and must not be used by the
  * caller while the request runs.  All functions are thread-safe.
@@ -397,6 +411,14 @@ void rsrs_server_destroy(rsrs_server_t* sv);
 /* Makes a factor resident (the server takes ownership); RSRS_E_NOMEM if it
  * does not fit in the budget (ownership stays with the caller then). */
 rsrs_status rsrs_server_add_factor(rsrs_server_t* sv, rsrs_factor_t* f, int64_t* id);
+/* Served solves of resident factor id are refined (rsrs_solve_refine with
+ * the black-box product mv, user) until the batch's max_col relative
+ * residual is <= tol or maxit corrections are made; mv = NULL switches back
+ * to one-shot solves.  The latency of a request then includes its batch's
+ * refinement; the stats report the largest residual a batch ended with.
+ * mv and user must outlive the factor's residency. */
+rsrs_status rsrs_server_set_refine(rsrs_server_t* sv, int64_t id, rsrs_matvec_fn mv, void* user,
+                                   double tol, int maxit);
 /* Frees a resident factor once its in-flight batch is done; later requests
  * for it fail with RSRS_E_INVALID. */
 rsrs_status rsrs_server_release_factor(rsrs_server_t* sv, int64_t id);
@@ -422,6 +444,8 @@ typedef struct {
   int64_t resident_factors, queued_solves, queued_factors;
   double solve_p50_ms, solve_p99_ms;     /* submit-to-completion latency */
   double factor_p50_ms, factor_p99_ms;
+  int64_t refined_batches, refine_steps; /* batches served with refinement, corrections made */
+  double max_relres;                     /* largest residual a refined batch ended with */
 } rsrs_server_stats;
 /* Counters since creation or the last reset (reset != 0 clears them). */
 rsrs_status rsrs_server_get_stats(rsrs_server_t* sv, int reset, rsrs_server_stats* out);

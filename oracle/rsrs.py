@@ -70,6 +70,7 @@ class BoxFactor:
     norm_yz: float = 0.0
     norm_m: float = 0.0
     r11_min: float = 0.0
+    rdiag: np.ndarray = field(default=None, repr=False)   # |diag R| of the pivoted QR (first k+1)
 
     @property
     def SN(self) -> np.ndarray:
@@ -138,7 +139,7 @@ def row_id(M: np.ndarray, k: int, want_r11_min: bool = False, rank_tol: float = 
     ro = np.argsort(R_piv, kind="stable")
     if want_r11_min:
         r11 = float(np.abs(np.diag(R11)).min()) if kb else 0.0
-        return S_piv[so], R_piv[ro], Tp[np.ix_(ro, so)], r11
+        return S_piv[so], R_piv[ro], Tp[np.ix_(ro, so)], r11, np.abs(np.diag(Rf))[:k + 1]
     return S_piv[so], R_piv[ro], Tp[np.ix_(ro, so)]
 
 
@@ -248,12 +249,12 @@ def _process_box(box, lev, colour, Ba, Na, Y, Z, Om, Psi, k, keep_M, symmetric=F
     M = MY + MZ if id_mode == "sum" else np.concatenate([MY, MZ], axis=1)
     norm_yz = float(np.sqrt(np.sum(Y[Ba] ** 2) + np.sum(Z[Ba] ** 2)))
     # row ID of the far-field sketch (Algorithm 1, "Compute the row-ID")
-    S_pos, R_pos, T, r11_min = row_id(M, k, want_r11_min=True, rank_tol=rank_tol, ref_norm=norm_yz)
+    S_pos, R_pos, T, r11_min, rdiag = row_id(M, k, want_r11_min=True, rank_tol=rank_tol, ref_norm=norm_yz)
     Sg = Ba[S_pos]
     Rg = Ba[R_pos]
     if len(Rg) == 0:
         bf = _empty_box(box, lev, colour, Ba, Na, Sg)
-        bf.norm_yz, bf.norm_m, bf.r11_min = norm_yz, float(np.linalg.norm(M)), r11_min
+        bf.norm_yz, bf.norm_m, bf.r11_min, bf.rdiag = norm_yz, float(np.linalg.norm(M)), r11_min, rdiag
         return bf
     # sparsification matrices E, F applied to the sketches
     Y[Rg] -= T @ Y[Sg]
@@ -277,7 +278,7 @@ def _process_box(box, lev, colour, Ba, Na, Y, Z, Om, Psi, k, keep_M, symmetric=F
     Psi[Rg] += KL.T @ Psi[SN]
     return BoxFactor(box=box, level=lev, colour=colour, Ba=Ba, Na=Na, S=Sg, R=Rg, T=T,
                      XRR=XRR, lu=lu, KU=KU, KL=KL, M=M if keep_M else None,
-                     norm_yz=norm_yz, norm_m=float(np.linalg.norm(M)), r11_min=r11_min)
+                     norm_yz=norm_yz, norm_m=float(np.linalg.norm(M)), r11_min=r11_min, rdiag=rdiag)
 
 
 def _process_box_symmetric(box, lev, colour, Ba, Na, C, Y, Om, k, keep_M, rank_tol=0.0) -> BoxFactor:
@@ -287,12 +288,14 @@ def _process_box_symmetric(box, lev, colour, Ba, Na, C, Y, Om, k, keep_M, rank_t
     rank_tol * ||[Y_B Z_B]|| is halved accordingly."""
     M = nullify(Y[Ba], Om[C])
     norm_yz = float(np.sqrt(2.0 * np.sum(Y[Ba] ** 2)))
-    S_pos, R_pos, T, r11_min = row_id(M, k, want_r11_min=True, rank_tol=rank_tol, ref_norm=0.5 * norm_yz)
+    S_pos, R_pos, T, r11_min, rdiag = row_id(M, k, want_r11_min=True, rank_tol=rank_tol, ref_norm=0.5 * norm_yz)
+    rdiag = 2.0 * rdiag
     Sg = Ba[S_pos]
     Rg = Ba[R_pos]
     if len(Rg) == 0:
         bf = _empty_box(box, lev, colour, Ba, Na, Sg)
         bf.norm_yz, bf.norm_m, bf.r11_min = norm_yz, float(2.0 * np.linalg.norm(M)), 2.0 * r11_min
+        bf.rdiag = rdiag
         return bf
     Y[Rg] -= T @ Y[Sg]
     Om[Sg] += T.T @ Om[Rg]
@@ -308,7 +311,8 @@ def _process_box_symmetric(box, lev, colour, Ba, Na, C, Y, Om, k, keep_M, rank_t
     Om[Rg] += KU @ Om[SN]
     return BoxFactor(box=box, level=lev, colour=colour, Ba=Ba, Na=Na, S=Sg, R=Rg, T=T,
                      XRR=XRR, lu=lu, KU=KU, KL=KL, M=M if keep_M else None,
-                     norm_yz=norm_yz, norm_m=float(2.0 * np.linalg.norm(M)), r11_min=2.0 * r11_min)
+                     norm_yz=norm_yz, norm_m=float(2.0 * np.linalg.norm(M)), r11_min=2.0 * r11_min,
+                     rdiag=rdiag)
 
 
 # ----------------------------------------------------------------------------

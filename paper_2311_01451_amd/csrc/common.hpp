@@ -108,6 +108,10 @@ rsrs_status pool_alloc(DevBuf& b, size_t nbytes);
 rsrs_status pool_alloc(HostBuf& b, size_t nbytes);
 void pool_return(DevBuf& b);
 void pool_return(HostBuf& b);
+// Device bytes the pool keeps for device `dev`, and a trim of them (oldest
+// first) down to at most `keep` bytes.
+size_t pool_cached_device_bytes(int dev);
+void pool_trim_device(int dev, size_t keep);
 
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 

@@ -230,119 +230,315 @@ template rsrs_status gemm<float, float>(Uploader&, hipStream_t, const std::vecto
 
 
 // ---------------------------------------------------------------- Gauss-Jordan
-// Gauss-Jordan inversion with partial pivoting, the matrix held in registers:
-// 1024 threads as a 32 x 32 grid, thread (ti, tc) owning rows ti + 32a and
-// columns tc + 32b (a, b < R).  Pivoting is implicit (rows are never
-// swapped): step j publishes column j to LDS, every wave finds the pivot row
-// p itself (largest |a_ij| over rows not yet used, lowest index on ties) by a
-// shuffle reduction, the owners of row p publish it, and every element is
-// updated branch-free; column and row buffers alternate by step parity, so a
-// step costs two barriers.  With pivot rows p_j the working matrix W ends as
-// A^{-1}[i][c] = W[p_i][q_c], q the inverse permutation, applied on write-out.
-template <int R>
-__global__ __launch_bounds__(1024) void gje_reg_kernel(const GjeDesc* __restrict__ e, int* flag) {
-  constexpr int NMAX = 32 * R;
+// Gauss-Jordan inversion with partial pivoting, blocked by 16-column panels,
+// one workgroup of 8 waves per matrix of order n <= 16 NT (NT = 4, 8, 12),
+// padded with the identity to NP = 16 NT.  The matrix lives in registers as
+// NT x NT tiles of 16 x 16 in the accumulator layout of the FP64 MFMA
+// (register v of lane l holds tile row 4 v + l/16, column l%16): wave w
+// holds the TR x TC tiles of tile rows TR (w / 2) .. and tile columns
+// TC (w % 2) .., TR = NT / 4, TC = NT / 2.  Pivoting is implicit (rows are
+// never swapped): the pivot of column j is the largest |a_ij| over the rows
+// not used yet, lowest index on ties.
+//
+// Per panel J (columns 16 jt .. 16 jt + 15):
+//  1. the panel tiles go to LDS;
+//  2. one wave runs the 16 in-place Gauss-Jordan steps on the NP x 16 panel
+//     (pivot search, every other row reduced by the pivot row, the pivot row
+//     scaled, column j replaced by the inverse's column), recording the
+//     pivot rows P;
+//  3. every other column c takes the panel's 16 steps at once: the steps
+//     read column c only in the rows P, so x_c <- x_c + W x_c[P] with
+//     W = (factored panel) - E_P, E_P holding a 1 at (p_t, t); the waves
+//     holding rows P stage them in LDS and every tile gets W[rows] x_c[P]
+//     by four MFMAs (K = 16);
+//  4. the panel tiles take the factored panel back.
+// The pivots are those of the unblocked elimination (the panel steps see
+// up-to-date panel columns).  With pivot rows p_j the working matrix ends as
+// A^{-1}[i][c] = W[p_i][q_c], q the inverse permutation, applied on
+// write-out.  The identity padding never takes part: real columns pivot on
+// real rows (padded rows hold zeros there), padded columns on their own row.
+// Cross-lane moves of FP64 values by DPP (two 32-bit halves).  Lanes whose
+// source is outside the pattern keep `old`.
+template <int CTRL, int RMASK = 0xF>
+__device__ __forceinline__ double dpp_f64(double old, double x) {
+  const long long o = __double_as_longlong(old), v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp((int)o, (int)v, CTRL, RMASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(v >> 32), CTRL, RMASK, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+// Maximum over the 64 lanes (quad swaps, row half-mirror and mirror, then
+// the row broadcasts 15 and 31), read from lane 63 into every lane.
+__device__ __forceinline__ double wave_max_dpp(double v) {
+  v = fmax(v, dpp_f64<0xB1>(v, v));         // quad_perm [1, 0, 3, 2]
+  v = fmax(v, dpp_f64<0x4E>(v, v));         // quad_perm [2, 3, 0, 1]
+  v = fmax(v, dpp_f64<0x141>(v, v));        // row_half_mirror
+  v = fmax(v, dpp_f64<0x140>(v, v));        // row_mirror
+  v = fmax(v, dpp_f64<0x142, 0xA>(v, v));   // row_bcast:15
+  v = fmax(v, dpp_f64<0x143, 0xC>(v, v));   // row_bcast:31
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, 63), hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+// Every lane of a quad takes lane S of its quad (quad_perm [S, S, S, S]).
+template <int S>
+__device__ __forceinline__ double quad_bcast_dpp(double x) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)v, S * 0x55, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(v >> 32), S * 0x55, 0xF, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+// The same with the source lane chosen at run time (folded when it is known).
+__device__ __forceinline__ double quad_bcast_dpp_rt(double x, int s) {
+  switch (s) {
+    case 0: return quad_bcast_dpp<0>(x);
+    case 1: return quad_bcast_dpp<1>(x);
+    case 2: return quad_bcast_dpp<2>(x);
+    default: return quad_bcast_dpp<3>(x);
+  }
+}
+
+// The 16 Gauss-Jordan steps of one panel (columns 16 jt .. 16 jt + 15 of the
+// working matrix, or fewer: nsteps), run by waves 0..3 of the calling
+// workgroup (pw) on rows held in registers: wave w holds the rows
+// RL 16 w .. RL 16 w + RL 16 - 1, lane l the RL consecutive rows
+// row0 = RL (16 w + (l >> 2)) .. + RL - 1 in the panel columns 4 (l & 3) ..
+// + 3, so a lower lane holds lower rows.  Per step each wave offers its best
+// free row (value, index, the reciprocal of its pivot entry and the row
+// itself) in an LDS slot (two sets of four, by step parity), one barrier,
+// and every wave takes the same pivot from the four offers (largest value,
+// lowest row on ties); every other row is reduced by the pivot row, the
+// pivot row scaled, and column t replaced by the inverse's column (the
+// in-place form of the elimination).  Cross-lane moves are DPP.  Every
+// thread of the workgroup calls this (the barriers); on_pivot(t, p, |pivot|)
+// runs in lane 0 of wave 0 after each step.  Rows >= nrows hold zeros and
+// count as used.
+template <int RL, class OnPivot>
+__device__ __forceinline__ void gj_panel_steps(double (&rv)[RL][4], unsigned& used_mask, int row0, int wave,
+                                               int lane, bool pw, int nsteps, int nrows, double* OFF,
+                                               OnPivot&& on_pivot) {
+  const int cq = lane & 3;
+  const int NONE = 1 << 30;
+#pragma clang loop unroll(full)
+  for (int t = 0; t < 16; ++t) {
+    if (t >= nsteps) continue;   // uniform; the loop keeps its constant trip count (unrolled)
+    double* slot = OFF + (t & 1) * (4 * 20);
+    if (pw) {
+      // best free row of this wave in column t (lowest row on ties)
+      double best = -1.0, rcp = 0.0;
+      int bi = NONE;
+#pragma unroll
+      for (int i = 0; i < RL; ++i) {
+        const double x = rv[i][t & 3];
+        const double v = fabs(x);
+        const bool take = !((used_mask >> i) & 1u) && row0 + i < nrows && (bi == NONE || v > best);
+        best = take ? v : best;
+        bi = take ? row0 + i : bi;
+        rcp = take ? x : rcp;
+      }
+      // the reciprocal of this lane's candidate, in the shadow of the reduction
+      rcp = rcp != 0.0 ? 1.0 / rcp : 0.0;
+      if (cq != (t >> 2)) { best = -1.0; bi = NONE; }   // only the quad lanes holding column t
+      const double m = wave_max_dpp(best);
+      const unsigned long long hold = __ballot(bi != NONE && best == m);
+      const int cand = hold ? __builtin_amdgcn_readlane(bi, (int)__ffsll((long long)hold) - 1) : NONE;
+      // the four lanes holding row cand publish it
+      const int rel = cand - row0;
+      if (cand != NONE && rel >= 0 && rel < RL) {
+        double x[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          double y = rv[0][c];
+#pragma unroll
+          for (int ii = 1; ii < RL; ++ii) y = rel == ii ? rv[ii][c] : y;
+          x[c] = y;
+        }
+        double* dst = slot + wave * 20 + 4 + 4 * cq;
+        *reinterpret_cast<double2*>(dst) = make_double2(x[0], x[1]);
+        *reinterpret_cast<double2*>(dst + 2) = make_double2(x[2], x[3]);
+      }
+      if (lane == 0) {
+        slot[wave * 20 + 0] = m;
+        reinterpret_cast<int*>(slot + wave * 20 + 1)[0] = cand;
+      }
+      if (cand != NONE && cand == bi && cq == (t >> 2)) slot[wave * 20 + 2] = rcp;
+    }
+    __syncthreads();
+    if (pw) {
+      // the same choice in every wave: largest offer, lowest row on ties
+      double bv = -1.0;
+      int brow = NONE, bw = 0;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const double2 h = *reinterpret_cast<const double2*>(slot + w * 20);
+        const int r = (int)__double_as_longlong(h.y);   // the row index sits in the low word
+        const bool take = r != NONE && (brow == NONE || h.x > bv || (h.x == bv && r < brow));
+        bv = take ? h.x : bv;
+        brow = take ? r : brow;
+        bw = take ? w : bw;
+      }
+      const int p = __builtin_amdgcn_readfirstlane(brow);   // a free row always exists
+      bw = __builtin_amdgcn_readfirstlane(bw);
+      const double* win = slot + bw * 20;
+      const double inv = win[2];
+      const double2 y0 = *reinterpret_cast<const double2*>(win + 4 + 4 * cq);
+      const double2 y1 = *reinterpret_cast<const double2*>(win + 6 + 4 * cq);
+      const double pr[4] = {y0.x, y0.y, y1.x, y1.y};
+      const bool colq = cq == (t >> 2);   // this lane holds column t
+#pragma unroll
+      for (int i = 0; i < RL; ++i) {
+        // column t of this row, from the quad lane that holds it
+        const double ct = quad_bcast_dpp_rt(rv[i][t & 3], t >> 2) * inv;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) rv[i][c] -= ct * pr[c];
+        if (colq) rv[i][t & 3] = -ct;
+      }
+      // the pivot row: scaled by the pivot, its column t the reciprocal
+      const int rp = p - row0;
+#pragma unroll
+      for (int i = 0; i < RL; ++i)
+        if (rp == i) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) rv[i][c] = pr[c] * inv;
+          if (colq) rv[i][t & 3] = inv;
+          used_mask |= 1u << i;
+        }
+      if (wave == 0 && lane == 0) on_pivot(t, p, bv);
+    }
+  }
+}
+
+template <int NT>
+__global__ __launch_bounds__(512) void gje_blk_kernel(const GjeDesc* __restrict__ e, int* flag) {
+  constexpr int NP = 16 * NT;
+  constexpr int TR = NT / 4, TC = NT / 2;  // tile rows / columns per wave
+  constexpr int RW = NP / 4;               // panel rows per factoring wave
+  constexpr int PBS = 18;                  // row stride of the panel buffer (doubles, 16-byte rows)
+  constexpr int PRS = NP + 2;              // row stride of the pivot-row buffer
+  static_assert(NT % 4 == 0, "NT is a multiple of 4");
   const GjeDesc d = e[blockIdx.x];
   const int n = d.n;
-  const int tid = threadIdx.x;
-  const int ti = tid >> 5, tc = tid & 31;
-  const int lane = tid & 63;
-  __shared__ double colb[2][NMAX];
-  __shared__ double rowb[2][NMAX];
-  __shared__ int usedf[NMAX];
-  __shared__ int piv[NMAX];
-  __shared__ int qinv[NMAX];
-  double a[R][R];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int tr0 = TR * (wave >> 1), tc0 = TC * (wave & 1);   // first tile row / column
+  const int q = lane >> 4, c16 = lane & 15;
+  __shared__ __align__(16) double PB[NP * PBS];
+  __shared__ __align__(16) double PR[16 * PRS];
+  __shared__ __align__(16) double OFF[2 * 4 * 20];   // per step parity and wave: value, row, pad, the row
+  __shared__ int piv[NP];
+  __shared__ int qinv[NP];
+  __shared__ int usedf[NP];
+  __shared__ int bad;
+
+  v4d acc[TR][TC];
 #pragma unroll
-  for (int x = 0; x < R; ++x)
+  for (int a = 0; a < TR; ++a)
 #pragma unroll
-    for (int y = 0; y < R; ++y) {
-      const int i = ti + 32 * x, c = tc + 32 * y;
-      a[x][y] = (i < n && c < n) ? d.A[(int64_t)i * d.lda + c] : 0.0;
-    }
-  for (int i = tid; i < NMAX; i += 1024) usedf[i] = 0;
-  __syncthreads();
-  for (int j = 0; j < n; ++j) {
-    double* colv = colb[j & 1];
-    double* rowv = rowb[j & 1];
-    const int jy = j >> 5, jc = j & 31;
-    if (tc == jc) {
+    for (int b = 0; b < TC; ++b)
 #pragma unroll
-      for (int x = 0; x < R; ++x) {
-        double v = 0.0;
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * (tr0 + a) + 4 * v + q, col = 16 * (tc0 + b) + c16;
+        acc[a][b][v] = (row < n && col < n) ? d.A[(int64_t)row * d.lda + col] : (row == col ? 1.0 : 0.0);
+      }
+  for (int i = tid; i < NP; i += 512) {
+    usedf[i] = 0;
+    qinv[i] = NP;
+  }
+  if (tid == 0) bad = 0;
+
+  for (int jt = 0; jt < NT; ++jt) {
+    __syncthreads();   // the previous panel's readers of PB / PR are done
 #pragma unroll
-        for (int y = 0; y < R; ++y) v = (y == jy) ? a[x][y] : v;
-        colv[ti + 32 * x] = v;
+    for (int b = 0; b < TC; ++b)
+      if (tc0 + b == jt) {
+#pragma unroll
+        for (int a = 0; a < TR; ++a)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) PB[(16 * (tr0 + a) + 4 * v + q) * PBS + c16] = acc[a][b][v];
+      }
+    __syncthreads();
+    {
+      constexpr int RL = RW / 16;
+      const bool pw = wave < 4;
+      const int rg = lane >> 2, cq = lane & 3;
+      const int row0 = RW * wave + RL * rg;
+      double rv[RL][4];
+      unsigned used_mask = 0;   // bit i: row row0 + i already pivoted
+      if (pw) {
+#pragma unroll
+        for (int i = 0; i < RL; ++i) {
+          const double* src = PB + (row0 + i) * PBS + 4 * cq;
+          const double2 x0 = *reinterpret_cast<const double2*>(src);
+          const double2 x1 = *reinterpret_cast<const double2*>(src + 2);
+          rv[i][0] = x0.x; rv[i][1] = x0.y; rv[i][2] = x1.x; rv[i][3] = x1.y;
+          used_mask |= usedf[row0 + i] ? (1u << i) : 0u;
+        }
+      }
+      gj_panel_steps<RL>(rv, used_mask, row0, wave, lane, pw, 16, NP, OFF, [jt](int t, int p, double bv) {
+        if (!(bv > 0.0)) bad = 1;
+        usedf[p] = 1;
+        piv[16 * jt + t] = p;
+        qinv[p] = 16 * jt + t;
+      });
+      if (pw) {
+#pragma unroll
+        for (int i = 0; i < RL; ++i) {
+          double* dst = PB + (row0 + i) * PBS + 4 * cq;
+          *reinterpret_cast<double2*>(dst) = make_double2(rv[i][0], rv[i][1]);
+          *reinterpret_cast<double2*>(dst + 2) = make_double2(rv[i][2], rv[i][3]);
+        }
       }
     }
     __syncthreads();
-    // the first candidate is always taken, so the pivots form a permutation
-    double best = -1.0;
-    int bi = NMAX;
-    for (int i = lane; i < n; i += 64) {
-      const double v = fabs(colv[i]);
-      const bool take = !usedf[i] && (bi == NMAX || v > best);
-      best = take ? v : best;
-      bi = take ? i : bi;
-    }
+    // old values of the pivot rows in every column outside the panel, staged
+    // by the lanes holding them: qinv[row] is the elimination step of a row
+    // already pivoted, NP for the others
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ob = __shfl_xor(best, off, 64);
-      const int oi = __shfl_xor(bi, off, 64);
-      const bool take = oi != NMAX && (bi == NMAX || ob > best || (ob == best && oi < bi));
-      best = take ? ob : best;
-      bi = take ? oi : bi;
-    }
-    const int p = bi;
-    if (!(best > 0.0) && tid == 0) atomicOr(flag, 2);
-    const int px = p >> 5;
-    if (ti == (p & 31)) {
+    for (int a = 0; a < TR; ++a)
 #pragma unroll
-      for (int y = 0; y < R; ++y) {
-        double v = 0.0;
+      for (int v = 0; v < 4; ++v) {
+        const int t = qinv[16 * (tr0 + a) + 4 * v + q] - 16 * jt;
+        if (t < 0 || t >= 16) continue;
 #pragma unroll
-        for (int x = 0; x < R; ++x) v = (x == px) ? a[x][y] : v;
-        rowv[tc + 32 * y] = v;
+        for (int b = 0; b < TC; ++b)
+          if (tc0 + b != jt) PR[t * PRS + 16 * (tc0 + b) + c16] = acc[a][b][v];
       }
-    }
     __syncthreads();
-    if (tid == 0) {
-      usedf[p] = 1;
-      piv[j] = p;
-    }
-    const double pv = colv[p];
-    const double inv = pv != 0.0 ? 1.0 / pv : 0.0;
-    double rv[R], prow[R], fi[R];
-    bool isj[R], isp[R];
 #pragma unroll
-    for (int y = 0; y < R; ++y) {
-      rv[y] = rowv[tc + 32 * y];
-      isj[y] = (tc + 32 * y) == j;
-      prow[y] = isj[y] ? inv : rv[y] * inv;   // new pivot row (column j: 1 / pivot)
-    }
+    for (int a = 0; a < TR; ++a) {
+      const int row = 16 * (tr0 + a) + c16;
+      double wa[4];
+      const int trow = qinv[row] - 16 * jt;   // W = panel - E_P
 #pragma unroll
-    for (int x = 0; x < R; ++x) {
-      fi[x] = colv[ti + 32 * x] * inv;
-      isp[x] = (ti + 32 * x) == p;
-    }
-#pragma unroll
-    for (int x = 0; x < R; ++x)
-#pragma unroll
-      for (int y = 0; y < R; ++y) {
-        const double g = isj[y] ? -fi[x] : a[x][y] - fi[x] * rv[y];
-        a[x][y] = isp[x] ? prow[y] : g;
+      for (int kc = 0; kc < 4; ++kc) {
+        const int kk = 4 * kc + q;
+        wa[kc] = PB[row * PBS + kk] - (trow == kk ? 1.0 : 0.0);
       }
+#pragma unroll
+      for (int b = 0; b < TC; ++b) {
+        if (tc0 + b == jt) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[a][b][v] = PB[(16 * (tr0 + a) + 4 * v + q) * PBS + c16];
+        } else {
+#pragma unroll
+          for (int kc = 0; kc < 4; ++kc) {
+            const double x = PR[(4 * kc + q) * PRS + 16 * (tc0 + b) + c16];
+            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(wa[kc], x, acc[a][b], 0, 0, 0);
+          }
+        }
+      }
+    }
   }
   __syncthreads();
-  for (int j = tid; j < n; j += 1024) qinv[piv[j]] = j;
-  __syncthreads();
+  if (tid == 0 && bad) atomicOr(flag, 2);
 #pragma unroll
-  for (int x = 0; x < R; ++x)
+  for (int a = 0; a < TR; ++a)
 #pragma unroll
-    for (int y = 0; y < R; ++y) {
-      const int ri = ti + 32 * x, ci = tc + 32 * y;
-      if (ri < n && ci < n) d.Ainv[(int64_t)qinv[ri] * d.ldi + piv[ci]] = a[x][y];
-    }
+    for (int b = 0; b < TC; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * (tr0 + a) + 4 * v + q, col = 16 * (tc0 + b) + c16;
+        if (row < n && col < n) d.Ainv[(int64_t)qinv[row] * d.ldi + piv[col]] = acc[a][b][v];
+      }
 }
 
 // Gauss-Jordan for blocks too large for registers, one launch per pivot
@@ -436,8 +632,8 @@ __global__ __launch_bounds__(256) void gje_out_kernel(const GjeDesc* __restrict_
   }
 }
 
-// The variant is chosen per matrix by its own size (register kernels for
-// n <= 64 / 128 / 192, the global two-launch form above), so a matrix is
+// The variant is chosen per matrix by its own size (blocked kernels for
+// n <= 64 / 128 / 192, the one-launch-per-step form above), so a matrix is
 // inverted by the same instruction sequence whatever else is in the batch.
 static rsrs_status gje_group(Uploader& up, hipStream_t st, const std::vector<GjeDesc>& e, int* flag,
                              int variant) {
@@ -453,13 +649,13 @@ static rsrs_status gje_group(Uploader& up, hipStream_t st, const std::vector<Gje
     gb += 16.0 * (double)x.n * x.n;
   }
   if (variant < 3) {
-    ProfScope ps(st, "gauss_jordan_reg", gf, gb);
+    ProfScope ps(st, "gauss_jordan_blk", gf, gb);
     if (variant == 0)
-      hipLaunchKernelGGL(gje_reg_kernel<2>, dim3(nb), dim3(1024), 0, st, de, flag);
+      hipLaunchKernelGGL(gje_blk_kernel<4>, dim3(nb), dim3(512), 0, st, de, flag);
     else if (variant == 1)
-      hipLaunchKernelGGL(gje_reg_kernel<4>, dim3(nb), dim3(1024), 0, st, de, flag);
+      hipLaunchKernelGGL(gje_blk_kernel<8>, dim3(nb), dim3(512), 0, st, de, flag);
     else
-      hipLaunchKernelGGL(gje_reg_kernel<6>, dim3(nb), dim3(1024), 0, st, de, flag);
+      hipLaunchKernelGGL(gje_blk_kernel<12>, dim3(nb), dim3(512), 0, st, de, flag);
     RSRS_HIP(hipGetLastError());
     return RSRS_OK;
   }

@@ -8,12 +8,15 @@
 //
 //  phase A  Gram matrices G = C C^T of the test-matrix panels
 //           C_Omega = [Omega_Ba; Omega_Na], C_Psi likewise (l x s each);
-//           Cholesky G = L L^T and L^{-1} (recursive, GEMM-shaped);
+//           Cholesky G = L L^T with the inverse factor L^{-1} (panel kernel
+//           with deferred super-panel updates, chol.hip);
 //           least-squares coefficients X = Y_B pinv(C) = (Y_B C^T) L^{-T} L^{-1}
 //           and the far-field sketch M_Y = Y_B - X C_Omega, i.e. Y_B times the
 //           projector onto null(C_Omega) (eq. nullYZ); one optional second
 //           pass re-projects M_Y and refines X.  Same for Z / Psi.
-//           ID of M = M_Y + M_Z by pivoted Gram-Schmidt (Sec. 2.3).
+//           ID of M = M_Y + M_Z (or of [M_Y, M_Z]) by pivoted Gram-Schmidt
+//           (Sec. 2.3); k_B = k, or with a rank tolerance the number of
+//           pivots above it.
 //  phase B  Block extraction (eq. pinvYZ) from the same coefficients: since
 //           Y_hat_R = Y_R - T Y_S and Omega_hat_C = G_T Omega_C with
 //           G_T = I + e_S T^T e_R^T, Y_hat_R pinv(Omega_hat_C) =
@@ -51,6 +54,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <functional>
@@ -206,11 +210,10 @@ struct EnqueueWorker {
 // twice, so that the next class's Gram matrices and Cholesky factorizations
 // can run while this class finishes.
 template <typename T>
-void box_ws_bytes(int64_t b, int64_t l, int64_t k, int64_t sp, size_t* a, size_t* bpart) {
+void box_ws_bytes(int64_t b, int64_t l, int64_t k, int64_t r, int64_t sp, size_t* a, size_t* bpart) {
   constexpr bool mixed = sizeof(T) != sizeof(double);
   const int64_t lp = round_up(l, 16);
-  const int64_t r = b - k;
-  int64_t dblA = 2 * b + b * k;    // norms, R coefficients
+  int64_t dblA = 3 * b + b * k;    // norms, row norms of [Y_B Z_B], R coefficients
   int64_t telA = 4 * l * lp        // Gram matrices / inverse factors, scratch, both sides
                  + 4 * b * lp      // P, W for both sides
                  + 2 * b * sp;     // M_Y, M_Z
@@ -222,7 +225,7 @@ void box_ws_bytes(int64_t b, int64_t l, int64_t k, int64_t sp, size_t* a, size_t
     dblB += 2 * r * r;             // X_RR and its inverse in FP64
   }
   const int64_t ints = b + k;      // sel, piv (int32)
-  const int64_t i64 = k + b;       // Spos, Rpos
+  const int64_t i64 = k + b + 1;   // Spos, Rpos, k_B
   *a = (size_t)(dblA * 8 + telA * sizeof(T) + ints * 4 + 20 * 256);
   *bpart = (size_t)(dblB * 8 + telB * sizeof(T) + i64 * 8 + 12 * 256);
 }
@@ -236,7 +239,8 @@ struct BoxWs {
   T *XRy, *XRz, *Xpy, *Xpz;
   double *Td, *XRRd, *Xinvd;   // FP64 copies (mixed precision only)
   int32_t *sel, *piv;
-  int64_t *Spos, *Rpos;
+  int64_t *Spos, *Rpos, *kB;
+  int64_t mld;                  // leading dimension of M_Y, M_Z
 };
 
 // One problem of a factorization.  Problems advance through their colour
@@ -251,6 +255,8 @@ struct Job {
   rsrs_samples_t* smp = nullptr;
   int k = 0, p = 0, reproject = 1;
   bool sym = false;             // symmetric variant: the Y / Omega side only
+  bool concat = false;          // ID of [M_Y, M_Z] instead of M_Y + M_Z (general variant)
+  double rank_tol = 0.0;        // > 0: k_B from the pivots' size (storage planned for k_B = 0)
   Schedule sch;
   std::unique_ptr<rsrs_factor_t> F;
   T *Y = nullptr, *Z = nullptr, *Om = nullptr, *Psi = nullptr;
@@ -324,6 +330,9 @@ rsrs_status job_init(Job<T>& J, const rsrs_tree_t* th, rsrs_samples_t* smp,
   J.p = o->p < 0 ? J.k : o->p;
   J.reproject = o->reproject;
   J.sym = o->symmetric != 0;
+  J.concat = !J.sym && o->id_mode == RSRS_ID_CONCAT;
+  J.rank_tol = o->rank_tol;
+  const bool adaptive = J.rank_tol > 0.0;
   const Tree& t = th->t;
   const int k = J.k;
   make_schedule(t, k, J.sch);
@@ -364,21 +373,26 @@ rsrs_status job_init(Job<T>& J, const rsrs_tree_t* th, rsrs_samples_t* smp,
         r.n = J.sch.l_count[b] - r.b;
         r.k = k;
         r.r = r.b - k;
+        // with a rank tolerance the store is planned for the worst case
+        // k_B = 0 (r = b); the counts are the schedule's, an upper bound of
+        // the actual ones, which are set when the box's class runs
+        const int64_t rmax = adaptive ? r.b : r.r;
         r.ldT = round_up(k, al);
-        r.ldR = round_up(r.r, al);
+        r.ldR = round_up(rmax, al);
         r.ldKU = round_up(k + r.n, al);
-        r.oT = round_up(dsz, al); dsz = r.oT + r.r * r.ldT;
-        r.oXRR = round_up(dsz, al); dsz = r.oXRR + r.r * r.ldR;
-        r.oXinv = round_up(dsz, al); dsz = r.oXinv + r.r * r.ldR;
-        r.oKU = round_up(dsz, al); dsz = r.oKU + r.r * r.ldKU;
+        r.oT = round_up(dsz, al); dsz = r.oT + rmax * r.ldT;
+        r.oXRR = round_up(dsz, al); dsz = r.oXRR + rmax * r.ldR;
+        r.oXinv = round_up(dsz, al); dsz = r.oXinv + rmax * r.ldR;
+        r.oKU = round_up(dsz, al); dsz = r.oKU + rmax * r.ldKU;
         r.oKL = round_up(dsz, al); dsz = r.oKL + (k + r.n) * r.ldR;
-        r.oR = isz; isz += r.r;
+        // R list, then S ending where N_a begins (S || N_a is the list SN)
+        r.oR = isz; isz += rmax;
         r.oS = isz; isz += k;
         r.oNa = isz; isz += r.n;
         r.oBa = isz; isz += r.b + r.n;   // Ba followed by a second copy of Na
         F->boxes.push_back(r);
         size_t wa = 0, wb = 0;
-        box_ws_bytes<T>(r.b, r.b + r.n, k, J.sld, &wa, &wb);
+        box_ws_bytes<T>(r.b, r.b + r.n, k, rmax, J.sld, &wa, &wb);
         ws += wa;
         wsb += wb;
       }
@@ -444,7 +458,7 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
         w += J.class_ws[t];
         wb += J.class_wsb[t];
         const Group& g = J.F->groups[t];
-        for (int64_t q = 0; q < g.count; ++q) np += (size_t)J.F->boxes[g.first + q].b;
+        for (int64_t q = 0; q < g.count; ++q) np += (size_t)J.F->boxes[g.first + q].b + 1;
       }
     ws_max = std::max(ws_max, w);
     wsb_max = std::max(wsb_max, wb);
@@ -519,10 +533,12 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
         BoxRec& R = J.F->boxes[g.first + q];
         const size_t ip = J.pos.at(R.box);
         const std::vector<int64_t>& ba = J.cur[R.box];
+        const bool adaptive = J.rank_tol > 0.0;
         // N_a straight into the staging slots.  Neighbours own disjoint point
         // ranges and keep their active points sorted, so visiting them by
-        // range start yields a sorted list.
-        if ((int64_t)ba.size() != R.b) {
+        // range start yields a sorted list.  With a rank tolerance the
+        // schedule's counts bound the actual ones.
+        if (adaptive ? (int64_t)ba.size() > R.b : (int64_t)ba.size() != R.b) {
           set_error("internal: active sets disagree with the count model");
           return RSRS_E_INVALID;
         }
@@ -538,13 +554,23 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
           if (!over) std::memcpy(na + cnt, a.data(), a.size() * 8);
           cnt += (int64_t)a.size();
         }
-        if (over || cnt != R.n) {
+        if (over || (adaptive ? cnt > R.n : cnt != R.n)) {
           set_error("internal: active sets disagree with the count model");
           return RSRS_E_INVALID;
+        }
+        if (adaptive) {   // actual counts; k_B and r follow from the ID
+          R.b = (int64_t)ba.size();
+          R.n = cnt;
+          R.k = std::min<int64_t>(J.k, R.b);
+          R.r = R.b - R.k;
         }
         if (!std::is_sorted(na, na + cnt)) std::sort(na, na + cnt);
         std::memcpy(J.hI + R.oBa, ba.data(), R.b * 8);
         std::memcpy(J.hI + R.oBa + R.b, na, R.n * 8);
+        if (R.b == 0) {   // every point of the box was eliminated below: nothing to do
+          R.k = R.r = 0;
+          continue;
+        }
         items.push_back(Item<T>{&J, &R, {}});
       }
       // the class's index lists are contiguous: one upload (its R / S slots
@@ -556,9 +582,10 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
     Bump bump{ws.as<char>(), 0, ws.bytes};
     Bump bumpb{wsb[t & 1].as<char>(), 0, wsb[t & 1].bytes};
     // skeleton / redundant positions of all boxes back to back (S then R,
-    // b entries per box), so that one copy brings them to the host
+    // b entries per box, then the box's k_B), so that one copy brings them
+    // to the host
     int64_t npos = 0;
-    for (auto& it : items) npos += it.R->b;
+    for (auto& it : items) npos += it.R->b + 1;
     if ((size_t)npos > pos_max) {
       set_error("internal: skeleton position count exceeds its plan");
       return RSRS_E_INVALID;
@@ -569,22 +596,32 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
       const BoxRec& R = *it.R;
       const int k = it.J->k;
       const int64_t sld = it.J->sld;
-      const int64_t l = R.b + R.n, lp = round_up(l, 16), b = R.b, r = R.r;
+      // r is only known after the ID with a rank tolerance: room for r = b
+      const int64_t l = R.b + R.n, lp = round_up(l, 16), b = R.b,
+                    r = it.J->rank_tol > 0.0 ? R.b : R.r;
       BoxWs<T>& w = it.w;
       w.lp = lp;
       w.GO = bump.take<T>(l * lp); w.GP = bump.take<T>(l * lp);
       w.LO = bump.take<T>(l * lp); w.LP = bump.take<T>(l * lp);
       w.PY = bump.take<T>(b * lp); w.WY = bump.take<T>(b * lp);
       w.PZ = bump.take<T>(b * lp); w.WZ = bump.take<T>(b * lp);
-      w.MY = bump.take<T>(b * sld); w.MZ = bump.take<T>(b * sld);
-      w.norms = bump.take<double>(2 * b); w.Rc = bump.take<double>(b * k);
+      if (it.J->concat) {   // rows of [M_Y, M_Z] side by side: M_Z at column sld
+        w.MY = bump.take<T>(2 * b * sld);
+        w.MZ = w.MY + sld;
+        w.mld = 2 * sld;
+      } else {
+        w.MY = bump.take<T>(b * sld); w.MZ = bump.take<T>(b * sld);
+        w.mld = sld;
+      }
+      w.norms = bump.take<double>(3 * b); w.Rc = bump.take<double>(b * k);
       w.sel = bump.take<int32_t>(b); w.piv = bump.take<int32_t>(k);
       w.XY = bumpb.take<T>(b * lp); w.XZ = bumpb.take<T>(b * lp);
       w.XRy = bumpb.take<T>(r * lp); w.XRz = bumpb.take<T>(r * lp);
       w.Xpy = bumpb.take<T>(r * lp); w.Xpz = bumpb.take<T>(r * lp);
       w.gje = bumpb.take<double>(2 * r * r);
-      w.Spos = posall + pofs; w.Rpos = w.Spos + k;
-      pofs += b;
+      w.Spos = posall + pofs; w.Rpos = w.Spos + R.k;   // R positions follow the k_B skeletons
+      w.kB = posall + pofs + b;
+      pofs += b + 1;
       if constexpr (mixed) {
         w.Td = bump.take<double>(r * round_up(k, 4));
         w.XRRd = bumpb.take<double>(r * r); w.Xinvd = bumpb.take<double>(r * r);
@@ -629,6 +666,9 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
       RSRS_TRY(worker.join());   // phase B of the previous class is enqueued
       RSRS_HIP(hipStreamWaitEvent(st, side.eB, 0));
     }
+    for (auto& it : items)   // [M_Y, M_Z] rows: the columns s..sld of each half stay zero
+      if (it.J->concat && it.J->sld > it.J->s)
+        RSRS_HIP(hipMemsetAsync(it.w.MY, 0, (size_t)(2 * it.R->b * it.J->sld) * sizeof(T), st));
     for (int pass = 0; pass <= 1; ++pass) {
       std::vector<GemmDescT<T, T>> gp, gw, gx, gm;
       std::vector<Copy2DT<T, T>> acc;
@@ -653,14 +693,14 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
           if (pass == 0)
             gp.push_back(gdescT<T, T>(Ysd, idxB, sld, Tst, idxC, sld, Pb, nullptr, w.lp, b, l, (int)J.s));
           else
-            gp.push_back(gdescT<T, T>(Mb, nullptr, sld, Tst, idxC, sld, Pb, nullptr, w.lp, b, l, (int)J.s));
+            gp.push_back(gdescT<T, T>(Mb, nullptr, w.mld, Tst, idxC, sld, Pb, nullptr, w.lp, b, l, (int)J.s));
           gw.push_back(gdescT<T, T>(Pb, nullptr, w.lp, Lb, nullptr, w.lp, Wb, nullptr, w.lp, b, l, l));
           gx.push_back(gdescT<T, T>(Wb, nullptr, w.lp, Lb, nullptr, w.lp, Xout, nullptr, w.lp, b, l, l));
           if (pass == 0)
-            gm.push_back(gdescT<T, T>(Xout, nullptr, w.lp, Tst, idxC, sld, Mb, nullptr, sld, b, (int)J.s, l,
+            gm.push_back(gdescT<T, T>(Xout, nullptr, w.lp, Tst, idxC, sld, Mb, nullptr, w.mld, b, (int)J.s, l,
                                       -1.0, 1.0, Ysd, idxB, sld));
           else
-            gm.push_back(gdescT<T, T>(Xout, nullptr, w.lp, Tst, idxC, sld, Mb, nullptr, sld, b, (int)J.s, l,
+            gm.push_back(gdescT<T, T>(Xout, nullptr, w.lp, Tst, idxC, sld, Mb, nullptr, w.mld, b, (int)J.s, l,
                                       -1.0, 1.0));
           if (pass == 1) acc.push_back(Copy2DT<T, T>{Pb, Xb, w.lp, w.lp, b, l, 1.0, 1, 0});
         }
@@ -682,28 +722,29 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
         IdDesc e{};
         // symmetric variant: M = M_Y (the ID of 2 M_Y is the same).  The
         // working rows keep the sketches' type; the pivoting is FP64.
-        e.M = w.MY; e.MZ = J.sym ? nullptr : w.MZ; e.ldm = J.sld; e.ldz = J.sld;
+        // Concatenated sketches: one row of length sld + s, the padding
+        // columns between the halves zero.
+        e.M = w.MY;
+        e.MZ = (J.sym || J.concat) ? nullptr : w.MZ;
+        e.ldm = w.mld; e.ldz = w.mld;
         if constexpr (mixed) {
           e.T = w.Td; e.ldt = (int)round_up(J.k, 4);
         } else {
           e.T = J.dS + R.oT; e.ldt = (int)R.ldT;
         }
         e.norms = w.norms; e.sel = w.sel; e.Rc = w.Rc; e.piv = w.piv;
-        e.Spos = w.Spos; e.Rpos = w.Rpos;
-        e.b = (int)R.b; e.s = (int)J.s; e.k = J.k;
+        e.Spos = w.Spos; e.kB = w.kB;
+        e.b = (int)R.b; e.s = (int)(J.concat ? J.sld + J.s : J.s); e.k = (int)R.k;
+        // rank tolerance: |R_jj|^2 against rank_tol^2 ||[Y_B Z_B]||_F^2, whose
+        // row sums the first launch gathers from the sketches (Y_B only in
+        // the symmetric variant, whose R is half that of M_Y + M_Z = 2 M_Y)
+        e.tol2 = J.rank_tol > 0.0 ? J.rank_tol * J.rank_tol * (J.sym ? 0.25 * 2.0 : 1.0) : 0.0;
+        e.rowyz = w.norms + 2 * R.b;
+        e.Yg = J.Y; e.Zg = J.sym ? nullptr : J.Z; e.idx = J.iS + R.oBa; e.ldy = J.sld; e.sy = (int)J.s;
         idd.push_back(e);
-        it.J->flops += 4.0 * R.b * J.s * J.k;
+        it.J->flops += 4.0 * R.b * e.s * R.k;
       }
       RSRS_TRY(id_run(up, st, idd, mixed));
-      if constexpr (mixed) {   // T rounded into the factor store
-        std::vector<Copy2DT<double, T>> tc;
-        for (auto& it : items) {
-          const BoxRec& R = *it.R;
-          const int k = it.J->k;
-          tc.push_back(Copy2DT<double, T>{it.w.Td, it.J->dS + R.oT, round_up(k, 4), R.ldT, (int)R.r, k, 1.0, 0, 0});
-        }
-        RSRS_TRY(copy2d<double, T>(up, st, tc));
-      }
     }
     // ---- skeleton sets back to the host (one copy, positions back to back)
     // and the flag word behind them, so that one synchronisation brings both
@@ -718,27 +759,48 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
         return RSRS_E_SINGULAR;
       }
     }
-    // ---- phase B: global R / S / SN lists
+    // ---- phase B: global R / S / SN lists (k_B of each box from the ID)
     {
       int64_t o2 = 0;
       for (auto& it : items) {
         Job<T>& J = *it.J;
         BoxRec& R = *it.R;
-        const int k = J.k;
         const int64_t* sp = hpos.as<int64_t>() + o2;
-        const int64_t* rp = sp + k;
-        std::vector<int64_t> Sg(k), Rg(R.r);
+        const int64_t kb = sp[R.b];
+        if (kb < 0 || kb > R.k) {
+          set_error("internal: skeleton count out of range");
+          return RSRS_E_INVALID;
+        }
+        R.k = kb;
+        R.r = R.b - kb;
+        R.oS = R.oNa - kb;          // S ends where N_a begins: S || N_a = SN
+        it.w.Rpos = it.w.Spos + kb;
+        const int64_t* rp = sp + kb;
+        std::vector<int64_t> Sg((size_t)kb), Rg((size_t)R.r);
         const int64_t* ba = J.hI + R.oBa;   // B_a as staged for the upload
-        for (int j = 0; j < k; ++j) Sg[j] = ba[sp[j]];
+        for (int64_t j = 0; j < kb; ++j) Sg[j] = ba[sp[j]];
         for (int64_t j = 0; j < R.r; ++j) Rg[j] = ba[rp[j]];
         std::memcpy(J.hI + R.oR, Rg.data(), R.r * 8);
-        std::memcpy(J.hI + R.oS, Sg.data(), (size_t)k * 8);
+        std::memcpy(J.hI + R.oS, Sg.data(), (size_t)kb * 8);
         J.cur[R.box] = std::move(Sg);
-        o2 += R.b;
+        o2 += R.b + 1;
       }
       for (auto& J : jobs)
         if (t < J.F->groups.size()) RSRS_TRY(upload_class_lists(J, J.F->groups[t], st));
+      if constexpr (mixed) {   // T rounded into the factor store
+        std::vector<Copy2DT<double, T>> tc;
+        for (auto& it : items) {
+          const BoxRec& R = *it.R;
+          tc.push_back(Copy2DT<double, T>{it.w.Td, it.J->dS + R.oT, round_up(it.J->k, 4), R.ldT, (int)R.r,
+                                          (int)R.k, 1.0, 0, 0});
+        }
+        RSRS_TRY(copy2d<double, T>(up, st, tc));
+      }
     }
+    // boxes that keep every point (k_B = b) eliminate nothing: no sparsify,
+    // extraction or elimination work
+    items.erase(std::remove_if(items.begin(), items.end(), [](const Item<T>& it) { return it.R->r == 0; }),
+                items.end());
     // ---- test-matrix sparsification (F) on the main stream: the next
     // class's Gram matrices read the updated rows S
     {
@@ -746,8 +808,9 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
       for (auto& it : items) {
         const BoxRec& R = *it.R;
         const Job<T>& J = *it.J;
-        const int k = J.k, s = (int)J.s;
+        const int k = (int)R.k, s = (int)J.s;
         const int r = (int)R.r;
+        if (k == 0) continue;   // no skeletons: nothing to add to
         const int64_t* gR = J.iS + R.oR;
         const int64_t* gS = J.iS + R.oS;
         const T* Tm = J.dS + R.oT;
@@ -774,7 +837,7 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
           const BoxRec& R = *it.R;
           Job<T>& J = *it.J;
           const BoxWs<T>& w = it.w;
-          const int k = J.k;
+          const int k = (int)R.k;
           T* dS = J.dS;
           const int l = (int)(R.b + R.n), r = (int)R.r;
           if (J.sym) {   // symmetric part of X_RR, and of its inverse below
@@ -820,7 +883,8 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
           const BoxRec& R = *it.R;
           const BoxWs<T>& w = it.w;
           T* dS = it.J->dS;
-          const int r = (int)R.r, kn = (int)(it.J->k + R.n);
+          const int r = (int)R.r, kn = (int)(R.k + R.n);
+          if (kn == 0) continue;   // no skeletons and no neighbours: no multipliers
           gku.push_back(gdescT<T, T>(dS + R.oXinv, nullptr, R.ldR, w.Xpy + r, nullptr, w.lp, dS + R.oKU, nullptr, R.ldKU, r, kn, r));
           if (it.J->sym)   // K_L = K_U^T
             ktr.push_back(Copy2DT<T, T>{dS + R.oKU, dS + R.oKL, R.ldKU, R.ldR, kn, r, 1.0, 0, 1});
@@ -837,9 +901,10 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
         for (auto& it : items) {
           const BoxRec& R = *it.R;
           const Job<T>& J = *it.J;
-          const int k = J.k, s = (int)J.s;
+          const int k = (int)R.k, s = (int)J.s;
           const int64_t sld = J.sld;
           const int r = (int)R.r, kn = (int)(k + R.n);
+          if (kn == 0) continue;   // nothing outside R is coupled to it
           const int64_t* gR = J.iS + R.oR;
           const int64_t* gS = J.iS + R.oS;
           const int64_t* gSN = J.iS + R.oS;
@@ -847,11 +912,11 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
           const T* KU = J.dS + R.oKU;
           const T* KL = J.dS + R.oKL;
           const int64_t lT = R.ldT, lR = R.ldR, lU = R.ldKU;
-          s0.push_back(gdescT<T, T>(Tm, nullptr, lT, J.Y, gS, sld, J.Y, gR, sld, r, s, k, -1.0, 1.0));
+          if (k > 0) s0.push_back(gdescT<T, T>(Tm, nullptr, lT, J.Y, gS, sld, J.Y, gR, sld, r, s, k, -1.0, 1.0));
           e0.push_back(gdescT<T, T>(KL, nullptr, lR, J.Y, gR, sld, J.Y, gSN, sld, kn, s, r, -1.0, 1.0));
           e0b.push_back(gdescT<T, T>(KU, nullptr, lU, J.Om, gSN, sld, J.Om, gR, sld, r, s, kn, 1.0, 1.0));
           if (J.sym) continue;   // Z = Y and Psi = Omega: nothing more to update
-          s0.push_back(gdescT<T, T>(Tm, nullptr, lT, J.Z, gS, sld, J.Z, gR, sld, r, s, k, -1.0, 1.0));
+          if (k > 0) s0.push_back(gdescT<T, T>(Tm, nullptr, lT, J.Z, gS, sld, J.Z, gR, sld, r, s, k, -1.0, 1.0));
           e1.push_back(gdescT<T, T>(KU, nullptr, lU, J.Z, gR, sld, J.Z, gSN, sld, kn, s, r, -1.0, 1.0));
           e1b.push_back(gdescT<T, T>(KL, nullptr, lR, J.Psi, gSN, sld, J.Psi, gR, sld, r, s, kn, 1.0, 1.0));
         }
@@ -886,6 +951,7 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
       int64_t rld, ntp, rp;
       double *G, *L, *P, *Wb, *Rres, *gw, *At, *Atinv;
       int nt, s, reproject;
+      Job<T>* job;
     };
     std::vector<Root> roots;
     for (auto& J : jobs) {
@@ -899,8 +965,15 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
         for (int64_t b : tr.level_boxes[1]) Bt.insert(Bt.end(), J.remaining[b].begin(), J.remaining[b].end());
         std::sort(Bt.begin(), Bt.end());
       }
-      if ((int64_t)Bt.size() != F->nt) { set_error("internal: root size mismatch"); return RSRS_E_INVALID; }
+      // with a rank tolerance the schedule's root count bounds the actual one
+      if (J.rank_tol > 0.0 ? (int64_t)Bt.size() > F->nt : (int64_t)Bt.size() != F->nt) {
+        set_error("internal: root size mismatch");
+        return RSRS_E_INVALID;
+      }
+      F->nt = (int64_t)Bt.size();
+      if (F->nt == 0) continue;   // every point eliminated: no root block
       Root R{};
+      R.job = &J;
       R.nt = (int)F->nt;
       R.s = (int)J.s;
       R.reproject = J.reproject;
@@ -974,7 +1047,7 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
     for (size_t q = 0; q < roots.size(); ++q) {
       const Root& R = roots[q];
       gj.push_back(GjeDesc{R.At, R.gw, R.Atinv, R.nt, R.nt, R.nt, 0});
-      if (jobs[q].sym) {
+      if (R.job->sym) {
         sa.push_back(SymDesc<double>{R.At, R.nt, R.nt, 0});
         sai.push_back(SymDesc<double>{R.Atinv, R.nt, R.nt, 0});
       }
@@ -984,11 +1057,10 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
     RSRS_TRY(symmetrize<double>(up, st, sai));
     if constexpr (mixed) {
       std::vector<Copy2DT<double, T>> cp;
-      for (size_t j = 0; j < jobs.size(); ++j) {
-        const Root& R = roots[j];
-        rsrs_factor_t* F = jobs[j].F.get();
-        cp.push_back(Copy2DT<double, T>{R.At, jobs[j].dS + F->oAt, R.nt, R.nt, R.nt, R.nt, 1.0, 0, 0});
-        cp.push_back(Copy2DT<double, T>{R.Atinv, jobs[j].dS + F->oAtinv, R.nt, R.nt, R.nt, R.nt, 1.0, 0, 0});
+      for (const Root& R : roots) {
+        rsrs_factor_t* F = R.job->F.get();
+        cp.push_back(Copy2DT<double, T>{R.At, R.job->dS + F->oAt, R.nt, R.nt, R.nt, R.nt, 1.0, 0, 0});
+        cp.push_back(Copy2DT<double, T>{R.Atinv, R.job->dS + F->oAtinv, R.nt, R.nt, R.nt, R.nt, 1.0, 0, 0});
       }
       RSRS_TRY(copy2d<double, T>(up, st, cp));
     }
@@ -1054,6 +1126,14 @@ rsrs_status factor_batch_impl(int64_t nprob, const rsrs_tree_t* const* trees, rs
     if (smp->tree != trees[i]) { set_error(who + "samples belong to another tree"); return RSRS_E_INVALID; }
     if (o->k > 256) { set_error(who + "k > 256 is not supported"); return RSRS_E_UNSUPPORTED; }
     if (o->reproject < 0 || o->reproject > 1) { set_error(who + "reproject must be 0 or 1"); return RSRS_E_INVALID; }
+    if (o->id_mode != RSRS_ID_SUM && o->id_mode != RSRS_ID_CONCAT) {
+      set_error(who + "id_mode must be RSRS_ID_SUM or RSRS_ID_CONCAT");
+      return RSRS_E_INVALID;
+    }
+    if (!(o->rank_tol >= 0.0) || !std::isfinite(o->rank_tol)) {
+      set_error(who + "rank_tol must be finite and >= 0");
+      return RSRS_E_INVALID;
+    }
     if (o->precision != prec) { set_error(who + "all problems of a batch need the same precision"); return RSRS_E_INVALID; }
     for (int64_t j = 0; j < i; ++j)
       if (smps[j] == smp) { set_error(who + "the same samples appear twice"); return RSRS_E_INVALID; }
@@ -1085,7 +1165,7 @@ rsrs_status factor_impl(const rsrs_tree_t* th, rsrs_samples_t* smp, const rsrs_f
 // (*stored) and the peak of everything alive while it is computed (samples
 // excluded): stored factor, class workspace, descriptor staging.
 size_t factor_bytes_estimate(const rsrs_tree_t* th, int k, int p, int64_t s, int precision,
-                             size_t* stored) {
+                             size_t* stored, bool adaptive) {
   const Tree& t = th->t;
   const bool mixed = precision == RSRS_PREC_F32_MIXED;
   const int64_t esz = mixed ? 4 : 8, al = 16 / esz, sld = round_up(s, 16);
@@ -1098,15 +1178,15 @@ size_t factor_bytes_estimate(const rsrs_tree_t* th, int k, int p, int64_t s, int
     for (const auto& cls : sch.classes[li]) {
       size_t ws = 0, wsb = 0;
       for (int64_t b : cls) {
-        const int64_t bb = sch.b_count[b], n = sch.l_count[b] - bb, r = bb - k;
+        const int64_t bb = sch.b_count[b], n = sch.l_count[b] - bb, r = adaptive ? bb : bb - k;
         dsz = round_up(dsz, al) + r * round_up(k, al);
         dsz = round_up(dsz, al) + 2 * r * round_up(r, al);
         dsz = round_up(dsz, al) + r * round_up(k + n, al);
         dsz = round_up(dsz, al) + (k + n) * round_up(r, al);
         isz += r + k + n + bb + n;
         size_t wa = 0, wb = 0;
-        if (mixed) box_ws_bytes<float>(bb, bb + n, k, sld, &wa, &wb);
-        else box_ws_bytes<double>(bb, bb + n, k, sld, &wa, &wb);
+        if (mixed) box_ws_bytes<float>(bb, bb + n, k, r, sld, &wa, &wb);
+        else box_ws_bytes<double>(bb, bb + n, k, r, sld, &wa, &wb);
         ws += wa;
         wsb += wb;
       }

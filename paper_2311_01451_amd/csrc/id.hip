@@ -52,6 +52,22 @@ __global__ __launch_bounds__(64) void id_init_kernel(const IdDesc* __restrict__ 
     d.norms[i] = s;
     d.sel[i] = INT_MAX;
   }
+  if (d.tol2 > 0.0) {   // |[Y_B Z_B] row i|^2 for the rank threshold
+    const int64_t gi = d.idx[i];
+    const S* yr = static_cast<const S*>(d.Yg) + gi * d.ldy;
+    const S* zr = d.Zg ? static_cast<const S*>(d.Zg) + gi * d.ldy : nullptr;
+    double q = 0.0;
+    for (int c = threadIdx.x; c < d.sy; c += 64) {
+      const double y = (double)yr[c];
+      q += y * y;
+      if (zr) {
+        const double z = (double)zr[c];
+        q += z * z;
+      }
+    }
+    q = wave_sum(q);
+    if (threadIdx.x == 0) d.rowyz[i] = q;
+  }
 }
 
 template <typename S>
@@ -77,7 +93,7 @@ __global__ __launch_bounds__(64) void id_step_kernel(const IdDesc* __restrict__ 
     const int oi = __shfl_xor(bi, off, 64);
     if (oi != INT_MAX && (bi == INT_MAX || ob > best || (ob == best && oi < bi))) { best = ob; bi = oi; }
   }
-  const int p = bi;   // always a valid row: b - j > 0 candidates remain for j < k < b
+  const int p = bi;   // always a valid row: b - j > 0 candidates remain for j < k <= b
   const double pn2 = best > 0.0 ? best : 0.0;   // also maps NaN to 0
   const double pn = sqrt(pn2);
   if (i == p) {
@@ -177,7 +193,7 @@ __global__ __launch_bounds__(256) void id_step_reg_kernel(const IdDesc* __restri
     best = take ? ob : best;
     bi = take ? oi : bi;
   }
-  const int p = bi;   // always a valid row: b - j > 0 candidates remain for j < k < b
+  const int p = bi;   // always a valid row: b - j > 0 candidates remain for j < k <= b
   const double pn2 = best > 0.0 ? best : 0.0;   // also maps NaN to 0
   const double pn = sqrt(pn2);
   if (i == p) {
@@ -229,21 +245,48 @@ __global__ __launch_bounds__(256) void id_step_reg_kernel(const IdDesc* __restri
   }
 }
 
-// S, R sorted; T = (R11^{-1} R12)^T written with columns in sorted-S order.
-// Positions come from a block-wide prefix count of the selected rows; for
-// k <= 64, R11 is staged in LDS and each thread solves for one row of R with
-// the solution in registers (larger k reads R11 from global memory).
+// k_B (all k steps, or with a rank tolerance the leading steps whose pivot
+// norm exceeds the threshold), then S and R sorted; T = (R11^{-1} R12)^T
+// written with columns in sorted-S order.  Positions come from a block-wide
+// prefix count of the selected rows; for k_B <= 64, R11 is staged in LDS and
+// each thread solves for one row of R with the solution in registers (larger
+// k_B reads R11 from global memory).
 __global__ __launch_bounds__(256) void id_finalize_kernel(const IdDesc* __restrict__ e) {
   const IdDesc d = e[blockIdx.x];
-  const int b = d.b, k = d.k, r = b - k;
+  const int b = d.b, ks = d.k;   // ks: steps taken, also the row stride of Rc
   constexpr int KL = 64;
   __shared__ int pre[4352 + 1];       // pre[x] = number of selected rows < x
   __shared__ int cnt[256];
   __shared__ int rank_of_step[256];   // rank of pivot p_t inside sorted S
+  __shared__ double part[256];
+  __shared__ int kshared;
   __shared__ double R11[KL * KL];
   const int tid = threadIdx.x;
   const int seg = (b + 255) / 256;
   const int lo = min(b, tid * seg), hi = min(b, lo + seg);
+  if (d.tol2 > 0.0) {
+    // threshold from ||[Y_B Z_B]||_F^2, summed in a fixed order
+    double q = 0.0;
+    for (int x = lo; x < hi; ++x) q += d.rowyz[x];
+    part[tid] = q;
+    __syncthreads();
+    if (tid == 0) {
+      double tot = 0.0;
+      for (int u = 0; u < 256; ++u) tot += part[u];
+      const double thr2 = d.tol2 * tot;
+      int kb = ks;
+      for (int j = 0; j < ks; ++j) {
+        const double pn = d.Rc[(int64_t)d.piv[j] * ks + j];
+        if (pn * pn <= thr2) { kb = j; break; }
+      }
+      kshared = kb;
+    }
+  } else if (tid == 0) {
+    kshared = ks;
+  }
+  __syncthreads();
+  const int k = kshared, r = b - k;
+  if (tid == 0) *d.kB = k;
   int c = 0;
   for (int x = lo; x < hi; ++x) c += d.sel[x] < k ? 1 : 0;
   cnt[tid] = c;
@@ -262,11 +305,12 @@ __global__ __launch_bounds__(256) void id_finalize_kernel(const IdDesc* __restri
     for (int x = lo; x < hi; ++x) {
       pre[x] = run;
       if (d.sel[x] < k) d.Spos[run] = x;
-      else d.Rpos[x - run] = x;
+      else d.Spos[k + x - run] = x;
       run += d.sel[x] < k ? 1 : 0;
     }
   }
   __syncthreads();
+  if (k == 0) return;   // no skeletons: T has no columns
   for (int t = tid; t < k; t += 256) rank_of_step[t] = pre[d.piv[t]];
   if (k <= KL) {
     // R11 padded to 64 x 64 (identity beyond k); each thread keeps its
@@ -274,13 +318,13 @@ __global__ __launch_bounds__(256) void id_finalize_kernel(const IdDesc* __restri
     for (int idx = tid; idx < KL * KL; idx += 256) {
       const int t = idx / KL, u = idx % KL;
       double v = (t == u) ? 1.0 : 0.0;
-      if (t < k && u < k) v = t <= u ? d.Rc[(int64_t)d.piv[u] * k + t] : 0.0;
+      if (t < k && u < k) v = t <= u ? d.Rc[(int64_t)d.piv[u] * ks + t] : 0.0;
       R11[idx] = v;
     }
     __syncthreads();
     for (int q = tid; q < r; q += 256) {
-      const int i = (int)d.Rpos[q];
-      const double* cr = d.Rc + (int64_t)i * k;
+      const int i = (int)d.Spos[k + q];
+      const double* cr = d.Rc + (int64_t)i * ks;
       double* Tq = d.T + (int64_t)q * d.ldt;
       // back substitution R11 x = c, R11[t][u] = Rc[p_u][t] (t <= u), in
       // place: c[t] becomes x[t] once rows t + 1.. are done.  The scheduling
@@ -308,14 +352,14 @@ __global__ __launch_bounds__(256) void id_finalize_kernel(const IdDesc* __restri
   }
   __syncthreads();
   for (int q = tid; q < r; q += 256) {
-    const int i = (int)d.Rpos[q];
-    const double* cr = d.Rc + (int64_t)i * k;
+    const int i = (int)d.Spos[k + q];
+    const double* cr = d.Rc + (int64_t)i * ks;
     double* Tq = d.T + (int64_t)q * d.ldt;
     // back substitution R11 x = c, R11[t][u] = Rc[p_u][t] (t <= u)
     for (int t = k - 1; t >= 0; --t) {
       double acc = cr[t];
-      for (int u = t + 1; u < k; ++u) acc -= d.Rc[(int64_t)d.piv[u] * k + t] * Tq[rank_of_step[u]];
-      const double diag = d.Rc[(int64_t)d.piv[t] * k + t];
+      for (int u = t + 1; u < k; ++u) acc -= d.Rc[(int64_t)d.piv[u] * ks + t] * Tq[rank_of_step[u]];
+      const double diag = d.Rc[(int64_t)d.piv[t] * ks + t];
       Tq[rank_of_step[t]] = diag != 0.0 ? acc / diag : 0.0;
     }
   }
@@ -356,8 +400,8 @@ rsrs_status id_run(Uploader& up, hipStream_t st, const std::vector<IdDesc>& e, b
   int bmax = 0, kmax = 0, smax = 0;
   for (const auto& x : e) {
     smax = std::max(smax, x.s);
-    if (x.k > 256 || x.b > 4352 || x.k >= x.b) {
-      set_error("ID sizes out of range (need k < b <= 4352, k <= 256)");
+    if (x.k > 256 || x.b > 4352 || x.k > x.b || x.k < 1) {
+      set_error("ID sizes out of range (need 1 <= k <= b <= 4352, k <= 256)");
       return RSRS_E_UNSUPPORTED;
     }
     bmax = std::max(bmax, x.b);

@@ -165,12 +165,22 @@ struct IdDesc {
   int32_t* sel;       // b
   double* Rc;         // b x k
   int32_t* piv;       // k
-  int64_t* Spos;      // k, sorted
-  int64_t* Rpos;      // b-k, sorted
-  double* T;          // (b-k) x k, row-major, leading dimension ldt
-  int b, s, k, ldt;
+  int64_t* Spos;      // b: the k_B skeleton positions (sorted), then the b - k_B others (sorted)
+  int64_t* kB;        // out: k_B
+  double* T;          // (b - k_B) x k_B, row-major, leading dimension ldt
+  // Rank tolerance (tol2 > 0): k_B = the number of leading steps whose pivot
+  // norm^2 exceeds tol2 * sum_i rowyz[i]; rowyz[i] = |Y_B row i|^2 (+ |Z_B
+  // row i|^2), gathered by the first launch from rows idx of Yg (and Zg).
+  double tol2;
+  double* rowyz;      // b
+  const void* Yg;
+  const void* Zg;
+  const int64_t* idx;
+  int64_t ldy;
+  int sy;
+  int b, s, k, ldt;   // k: steps (k_B <= k <= b)
 };
-// fp32: the working rows are FP32 (otherwise FP64).
+
 rsrs_status id_run(Uploader& up, hipStream_t st, const std::vector<IdDesc>& e, bool fp32);
 
 template <typename T>

@@ -82,6 +82,36 @@ void give(void* p, size_t bytes, int dev) {
 
 }  // namespace
 
+size_t pool_cached_device_bytes(int dev) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  size_t t = 0;
+  for (const auto& e : cached())
+    if (e.dev == dev) t += e.bytes;
+  return t;
+}
+
+void pool_trim_device(int dev, size_t keep) {
+  std::vector<Entry> evict;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto& v = cached();
+    size_t t = 0;
+    for (const auto& e : v)
+      if (e.dev == dev) t += e.bytes;
+    // the oldest buffers of this device go first
+    for (size_t i = 0; i < v.size() && t > keep;) {
+      if (v[i].dev == dev) {
+        t -= v[i].bytes;
+        evict.push_back(v[i]);
+        v.erase(v.begin() + (std::ptrdiff_t)i);
+      } else {
+        ++i;
+      }
+    }
+  }
+  for (const auto& e : evict) free_entry(e);
+}
+
 rsrs_status pool_alloc(DevBuf& b, size_t nbytes) {
   b.release();
   if (nbytes == 0) return RSRS_OK;

@@ -42,7 +42,7 @@ rsrs_status factor_impl(const rsrs_tree_t* th, rsrs_samples_t* smp, const rsrs_f
 rsrs_status apply_factor(const rsrs_factor_t* F, int op, int transpose, int64_t w, const double* Fin,
                          int64_t ldf, double* Uout, int64_t ldu, hipStream_t st);
 size_t factor_bytes_estimate(const rsrs_tree_t* th, int k, int p, int64_t s, int precision,
-                             size_t* stored);
+                             size_t* stored, bool adaptive);
 rsrs_status factor_batch_impl(int64_t nprob, const rsrs_tree_t* const* trees, rsrs_samples_t* const* smps,
                               const rsrs_factor_opts* opts, hipStream_t st, rsrs_factor_t** out);
 }  // namespace rsrs
@@ -82,6 +82,11 @@ struct rsrs_server_s {
     int64_t bytes = 0;
     int inflight = 0;
     bool release_pending = false;
+    // refinement of served solves through the operator (mv null: one-shot)
+    rsrs_matvec_fn mv = nullptr;
+    void* user = nullptr;
+    double tol = 0.0;
+    int maxit = 0;
   };
   struct Solve {
     int64_t ticket, fid, w;
@@ -117,12 +122,30 @@ struct rsrs_server_s {
   int64_t in_use = 0, peak = 0;
   std::vector<double> lat_solve, lat_factor;
   int64_t batches = 0, cols_done = 0, solves_done = 0, factors_done = 0;
+  int64_t refined_batches = 0, refine_steps = 0;
+  double max_relres = 0.0;
   DevBuf Fb, Ub;
+  int64_t batch_bytes = 0;   // Fb + Ub as charged to the budget
   std::thread th_solve, th_factor;
 
   void use(int64_t d) {
     in_use += d;
     peak = std::max(peak, in_use);
+  }
+  // Device bytes a resident factor holds while served: the stored factor and
+  // its permutation, the solve graphs of every width bucket a batch of up to
+  // max_cols columns can use (two tree-ordered blocks of n x bucket elements
+  // each, in the factor's type) and, beyond the graph widths, the direct
+  // path's two blocks of n x max_cols.
+  int64_t resident_bytes(const rsrs_factor_t* F) const {
+    const int64_t n = F->n, e = F->esz;
+    int64_t plans = 0;
+    for (int64_t b = 16; b <= 1024; b *= 2) {
+      plans += 2 * n * b * e;
+      if (b >= max_cols) break;
+    }
+    const int64_t direct = max_cols > 1024 ? 2 * n * max_cols * e : 0;
+    return F->stored_values * e + n * 8 + plans + direct;
   }
   void free_resident(std::map<int64_t, Resident>::iterator it) {
     delete it->second.F;
@@ -175,12 +198,25 @@ struct rsrs_server_s {
       Resident& R = rit->second;
       ++R.inflight;
       const rsrs_factor_t* F = R.F;
+      const rsrs_matvec_fn rmv = R.mv;
+      void* ruser = R.user;
+      const double rtol = R.tol;
+      const int rmaxit = R.maxit;
       lk.unlock();
 
       const int64_t n = F->n;
       rsrs_status st = Fb.alloc((size_t)n * W * 8);
       if (st == RSRS_OK) st = Ub.alloc((size_t)n * W * 8);
+      {
+        // the FP64 batch blocks count against the budget at their size
+        std::lock_guard<std::mutex> g(mu);
+        const int64_t now = (int64_t)(Fb.bytes + Ub.bytes);
+        use(now - batch_bytes);
+        batch_bytes = now;
+      }
       std::string msg;
+      double relres = -1.0;
+      int iters = 0;
       if (st == RSRS_OK) {
         int64_t c0 = 0;
         for (const auto& r : batch) {
@@ -190,7 +226,13 @@ struct rsrs_server_s {
           c0 += r.w;
         }
       }
-      if (st == RSRS_OK) st = apply_factor(F, 0, 0, W, Fb.as<double>(), W, Ub.as<double>(), W, s_solve);
+      if (st == RSRS_OK) {
+        if (rmv)   // refined to the factor's tolerance through the black-box residual
+          st = rsrs_solve_refine(F, rmv, ruser, W, Fb.as<double>(), W, Ub.as<double>(), W, rtol, rmaxit, &relres,
+                                 &iters, s_solve);
+        else
+          st = apply_factor(F, 0, 0, W, Fb.as<double>(), W, Ub.as<double>(), W, s_solve);
+      }
       if (st == RSRS_OK) {
         int64_t c0 = 0;
         for (const auto& r : batch) {
@@ -208,6 +250,11 @@ struct rsrs_server_s {
       for (const auto& r : batch) finish(r.ticket, st, msg, -1, t);
       ++batches;
       cols_done += W;
+      if (rmv && st == RSRS_OK) {
+        ++refined_batches;
+        refine_steps += iters;
+        max_relres = std::max(max_relres, relres);
+      }
       auto it2 = res.find(fid);
       if (it2 != res.end()) {
         --it2->second.inflight;
@@ -221,7 +268,19 @@ struct rsrs_server_s {
     (void)hipSetDevice(device);
     for (;;) {
       std::unique_lock<std::mutex> lk(mu);
-      auto admissible = [&] { return budget <= 0 || in_use + qf.front().est <= budget; };
+      // device memory the scratch pool keeps from earlier factorizations
+      // counts too; it is trimmed when a request would not fit otherwise
+      auto admissible = [&] {
+        if (budget <= 0) return true;
+        const int64_t need = in_use + qf.front().est;
+        if (need > budget) return false;
+        int64_t cached = (int64_t)pool_cached_device_bytes(device);
+        if (need + cached > budget) {
+          pool_trim_device(device, (size_t)(budget - need));
+          cached = (int64_t)pool_cached_device_bytes(device);
+        }
+        return need + cached <= budget;
+      };
       cv_factor.wait(lk, [&] { return stop || (!qf.empty() && admissible()); });
       if (qf.empty()) break;
       if (!admissible()) {   // shutting down with requests that never fit
@@ -258,9 +317,7 @@ struct rsrs_server_s {
         int64_t fid = -1;
         if (sts[i] == RSRS_OK) {
           rsrs_factor_t* F = Fs[i];
-          // stored factor plus the solve workspace a full batch allocates in it
-          const int64_t bytes = F->stored_values * F->esz + (F->n * 8) +
-                                2 * F->n * max_cols * (int64_t)F->esz;
+          const int64_t bytes = resident_bytes(F);
           fid = next_fid++;
           res[fid] = Resident{F, bytes, 0, false};
           use(bytes);
@@ -369,7 +426,7 @@ rsrs_status rsrs_server_add_factor(rsrs_server_t* sv, rsrs_factor_t* f, int64_t*
     return RSRS_E_INVALID;
   }
   std::lock_guard<std::mutex> lk(sv->mu);
-  const int64_t bytes = f->stored_values * f->esz + f->n * 8 + 2 * f->n * sv->max_cols * (int64_t)f->esz;
+  const int64_t bytes = sv->resident_bytes(f);
   if (sv->budget > 0 && sv->in_use + bytes > sv->budget) {
     set_error("factor does not fit in the HBM budget");
     return RSRS_E_NOMEM;
@@ -377,6 +434,25 @@ rsrs_status rsrs_server_add_factor(rsrs_server_t* sv, rsrs_factor_t* f, int64_t*
   *id = sv->next_fid++;
   sv->res[*id] = rsrs_server_s::Resident{f, bytes, 0, false};
   sv->use(bytes);
+  return RSRS_OK;
+}
+
+rsrs_status rsrs_server_set_refine(rsrs_server_t* sv, int64_t id, rsrs_matvec_fn mv, void* user, double tol,
+                                   int maxit) {
+  if (!sv || (mv && (!(tol > 0.0) || maxit < 0))) {
+    set_error("bad refinement settings");
+    return RSRS_E_INVALID;
+  }
+  std::lock_guard<std::mutex> lk(sv->mu);
+  auto it = sv->res.find(id);
+  if (it == sv->res.end() || it->second.release_pending) {
+    set_error("unknown factor id");
+    return RSRS_E_INVALID;
+  }
+  it->second.mv = mv;
+  it->second.user = user;
+  it->second.tol = tol;
+  it->second.maxit = maxit;
   return RSRS_OK;
 }
 
@@ -439,7 +515,7 @@ rsrs_status rsrs_server_submit_factor(rsrs_server_t* sv, const rsrs_tree_t* t, r
   const int64_t esz = dtype == RSRS_F64 ? 8 : 4;
   const int64_t n = t->t.n;
   const int64_t est = 6 * n * round_up(s, 16) * esz + 8 * n +
-                      (int64_t)factor_bytes_estimate(t, o->k, o->p, s, o->precision, nullptr);
+                      (int64_t)factor_bytes_estimate(t, o->k, o->p, s, o->precision, nullptr, o->rank_tol > 0.0);
   std::lock_guard<std::mutex> lk(sv->mu);
   if (sv->budget > 0 && est > sv->budget) {
     set_error("factorization needs " + std::to_string(est) + " bytes, more than the HBM budget");
@@ -501,9 +577,14 @@ rsrs_status rsrs_server_get_stats(rsrs_server_t* sv, int reset, rsrs_server_stat
   out->solve_p50_ms = percentile(sv->lat_solve, 0.50);
   out->solve_p99_ms = percentile(sv->lat_solve, 0.99);
   out->factor_p50_ms = percentile(sv->lat_factor, 0.50);
+  out->refined_batches = sv->refined_batches;
+  out->refine_steps = sv->refine_steps;
+  out->max_relres = sv->max_relres;
   out->factor_p99_ms = percentile(sv->lat_factor, 0.99);
   if (reset) {
     sv->solves_done = sv->factors_done = sv->batches = sv->cols_done = 0;
+    sv->refined_batches = sv->refine_steps = 0;
+    sv->max_relres = 0.0;
     sv->lat_solve.clear();
     sv->lat_factor.clear();
     sv->peak = sv->in_use;

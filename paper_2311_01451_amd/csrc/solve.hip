@@ -62,14 +62,17 @@ rsrs_status build_apply(const rsrs_factor_t* F, int op, int transpose, int64_t w
   const T* dS = F->d<T>();
   const int64_t* iS = F->i();
   const int W = (int)w;
-  const int k = (int)F->k;
-  // first and second elementary step of the upward sweep (boxes in factor order)
+  // first and second elementary step of the upward sweep (boxes in factor
+  // order); k is each box's own skeleton count (k_B), and boxes that
+  // eliminate nothing (r = 0) have no factors
+
   for (const Group& g : F->groups) {
     std::vector<GD> a0, a1;   // launches with TA = 0 / TA = 1
     std::vector<GD> b0, b1;
     for (int64_t q = g.first; q < g.first + g.count; ++q) {
       const BoxRec& R = F->boxes[q];
-      const int r = (int)R.r, kn = (int)(k + R.n);
+      const int r = (int)R.r, k = (int)R.k, kn = (int)(R.k + R.n);
+      if (r == 0) continue;
       const int64_t* gR = iS + R.oR;
       const int64_t* gS = iS + R.oS;
       const int64_t* gSN = iS + R.oS;
@@ -102,14 +105,16 @@ rsrs_status build_apply(const rsrs_factor_t* F, int op, int transpose, int64_t w
     const int ta = transpose ? 1 : 0;
     for (const BoxRec& R : F->boxes) {
       const int r = (int)R.r;
+      if (r == 0) continue;
       const T* D = dS + (op == OP_SOLVE ? R.oXinv : R.oXRR);
       const int64_t* gR = iS + R.oR;
       dd.push_back(gdesc(D, nullptr, R.ldR, x, gR, w, u, gR, w, r, W, r));
     }
     const int nt = (int)F->nt;
     const int64_t* gB = iS + F->oBt;
-    dd.push_back(gdesc(dS + (op == OP_SOLVE ? F->oAtinv : F->oAt), nullptr, nt, x, gB, w, u, gB, w,
-                       nt, W, nt));
+    if (nt > 0)
+      dd.push_back(gdesc(dS + (op == OP_SOLVE ? F->oAtinv : F->oAt), nullptr, nt, x, gB, w, u, gB, w,
+                         nt, W, nt));
     RSRS_TRY(emit(dd, ta, 0, GM_FULL));
   }
   // downward sweep, boxes in reverse factor order
@@ -118,7 +123,8 @@ rsrs_status build_apply(const rsrs_factor_t* F, int op, int transpose, int64_t w
     std::vector<GD> a0, a1, b0, b1;
     for (int64_t q = g.first; q < g.first + g.count; ++q) {
       const BoxRec& R = F->boxes[q];
-      const int r = (int)R.r, kn = (int)(k + R.n);
+      const int r = (int)R.r, k = (int)R.k, kn = (int)(R.k + R.n);
+      if (r == 0) continue;
       const int64_t* gR = iS + R.oR;
       const int64_t* gS = iS + R.oS;
       const int64_t* gSN = iS + R.oS;

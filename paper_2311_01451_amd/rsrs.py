@@ -25,6 +25,7 @@ RSRS_OP_LOG2D = 1
 RSRS_OP_INVR3D = 2
 RSRS_OP_LOG2D_SKEW = 3
 RSRS_PREC_F64 = 0
+RSRS_ID_SUM, RSRS_ID_CONCAT = 0, 1
 RSRS_PREC_F32_MIXED = 1
 RSRS_F64 = 0
 RSRS_F32 = 1
@@ -58,7 +59,7 @@ class TreeInfo(C.Structure):
 
 class FactorOpts(C.Structure):
     _fields_ = [("k", C.c_int), ("p", C.c_int), ("precision", C.c_int), ("reproject", C.c_int),
-                ("symmetric", C.c_int)]
+                ("symmetric", C.c_int), ("id_mode", C.c_int), ("rank_tol", C.c_double)]
 
 
 class FactorInfo(C.Structure):
@@ -77,7 +78,8 @@ class ServerStats(C.Structure):
                 ("resident_factors", C.c_int64), ("queued_solves", C.c_int64),
                 ("queued_factors", C.c_int64), ("solve_p50_ms", C.c_double),
                 ("solve_p99_ms", C.c_double), ("factor_p50_ms", C.c_double),
-                ("factor_p99_ms", C.c_double)]
+                ("factor_p99_ms", C.c_double), ("refined_batches", C.c_int64),
+                ("refine_steps", C.c_int64), ("max_relres", C.c_double)]
 
 
 class ProfileEntry(C.Structure):
@@ -99,7 +101,7 @@ EXPORTS = [
     "rsrs_factor_root_copy", "rsrs_solve", "rsrs_solve_noalloc", "rsrs_apply", "rsrs_solve_refine",
     "rsrs_profile_enable", "rsrs_profile_filter", "rsrs_profile_reset", "rsrs_profile_read", "rsrs_solve_graphs",
     "rsrs_server_create", "rsrs_server_destroy", "rsrs_server_add_factor",
-    "rsrs_server_release_factor", "rsrs_server_submit_solve", "rsrs_server_submit_factor",
+    "rsrs_server_release_factor", "rsrs_server_set_refine", "rsrs_server_submit_solve", "rsrs_server_submit_factor",
     "rsrs_server_wait", "rsrs_server_get_stats",
 ]
 
@@ -154,6 +156,8 @@ def lib():
         "rsrs_server_destroy": (None, [vp]),
         "rsrs_server_add_factor": (i32, [vp, vp, P(i64)]),
         "rsrs_server_release_factor": (i32, [vp, i64]),
+        "rsrs_server_set_refine": (i32, [vp, i64, vp, vp, dbl, i32]),
+        "rsrs_server_set_refine": (i32, [vp, i64, vp, vp, dbl, i32]),
         "rsrs_server_submit_solve": (i32, [vp, i64, i64, vp, i64, vp, i64, P(i64)]),
         "rsrs_server_submit_factor": (i32, [vp, vp, vp, vp, i64, C.c_uint64, i32, P(FactorOpts),
                                             P(i64)]),
@@ -477,22 +481,25 @@ class Factor:
 
 
 def rsrs_factor(tree: Tree, samples: Samples, k: int, p: int = -1, reproject: int = 1,
-                precision: int = RSRS_PREC_F64, stream=None, symmetric: bool = False) -> Factor:
-    o = FactorOpts(k, p, precision, reproject, int(symmetric))
+                precision: int = RSRS_PREC_F64, stream=None, symmetric: bool = False,
+                id_mode: int = 0, rank_tol: float = 0.0) -> Factor:
+    o = FactorOpts(k, p, precision, reproject, int(symmetric), int(id_mode), float(rank_tol))
     h = C.c_void_p()
     _check(lib().rsrs_factor(tree.handle, samples.handle, C.byref(o), _stream(stream), C.byref(h)))
     return Factor(h, keep=tree)
 
 
 def rsrs_factor_batched(trees, samples, ks, p: int = -1, reproject: int = 1,
-                        precision: int = RSRS_PREC_F64, stream=None, symmetric: bool = False) -> list:
+                        precision: int = RSRS_PREC_F64, stream=None, symmetric: bool = False,
+                        id_mode: int = 0, rank_tol: float = 0.0) -> list:
     """Factor independent problems together; ks gives each problem's rank."""
     n = len(trees)
     if len(samples) != n or len(ks) != n:
         raise ValueError("trees, samples and ks must have the same length")
     th = (C.c_void_p * n)(*[t.handle for t in trees])
     sh = (C.c_void_p * n)(*[x.handle for x in samples])
-    opts = (FactorOpts * n)(*[FactorOpts(int(k), p, precision, reproject, int(symmetric)) for k in ks])
+    opts = (FactorOpts * n)(*[FactorOpts(int(k), p, precision, reproject, int(symmetric), int(id_mode),
+                                         float(rank_tol)) for k in ks])
     outs = (C.c_void_p * n)()
     _check(lib().rsrs_factor_batched(n, th, sh, opts, _stream(stream), outs))
     return [Factor(C.c_void_p(outs[i]), keep=trees[i]) for i in range(n)]
@@ -577,6 +584,15 @@ class Server:
         f._h = None   # owned by the server now
         return fid.value
 
+    def set_refine(self, fid: int, op: "Operator | None", tol: float = 1e-6, maxit: int = 10):
+        """Refine served solves of factor fid through op to tol (None: one-shot)."""
+        if op is None:
+            _check(lib().rsrs_server_set_refine(self._h, int(fid), None, None, 0.0, 0))
+        else:
+            self._keep[("refine", fid)] = op
+            _check(lib().rsrs_server_set_refine(self._h, int(fid), Operator.fn_ptr(), op.handle,
+                                                float(tol), int(maxit)))
+
     def release(self, fid: int):
         _check(lib().rsrs_server_release_factor(self._h, int(fid)))
 
@@ -594,10 +610,11 @@ class Server:
 
     def submit_factor(self, tree: Tree, op: Operator, s: int, seed: int, k: int,
                       precision: int = RSRS_PREC_F64, p: int = -1, reproject: int = 1,
-                      dtype: int | None = None, symmetric: bool = False) -> int:
+                      dtype: int | None = None, symmetric: bool = False, id_mode: int = 0,
+                      rank_tol: float = 0.0) -> int:
         if dtype is None:
             dtype = RSRS_F64 if precision == RSRS_PREC_F64 else RSRS_F32
-        o = FactorOpts(int(k), p, precision, reproject, int(symmetric))
+        o = FactorOpts(int(k), p, precision, reproject, int(symmetric), int(id_mode), float(rank_tol))
         t = C.c_int64()
         _check(lib().rsrs_server_submit_factor(self._h, tree.handle, Operator.fn_ptr(), op.handle,
                                                int(s), int(seed), dtype, C.byref(o), C.byref(t)))

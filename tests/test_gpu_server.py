@@ -136,3 +136,55 @@ def test_solves_overlap_a_running_factorization():
     sv.wait(tk)
     assert torch.isfinite(out).all()
     sv.close()
+
+
+def test_served_solves_refined_to_tolerance():
+    """With refinement attached to a resident factor, every served result
+    meets the tolerance through the operator's FP64 residual (mixed factor,
+    one-shot residual ~1e-5), alone and batched with other requests; the
+    stats report the refined batches and the largest residual."""
+    need_gpu()
+    P = _factor(48, 32, mixed=True, seed_off=4)
+    sv = rsrs.Server(hbm_budget=0, max_batch_cols=256)
+    fid = sv.add_factor(P["F"])
+    sv.set_refine(fid, P["op"], tol=1e-10, maxit=20)
+    rng = np.random.default_rng(12)
+    reqs = []
+    for w in (1, 4, 16, 64, 3):
+        f = dev(rng.standard_normal((P["N"], w)))
+        t, out = sv.submit_solve(fid, f)
+        reqs.append((f, t, out))
+    for f, t, out in reqs:
+        sv.wait(t)
+        r = f - P["op"].matvec(out)
+        rel = float((r.norm(dim=0) / f.norm(dim=0)).max())
+        assert rel <= 1e-10, rel
+    st = sv.stats()
+    print(f"[server refine] batches {st['refined_batches']}, corrections {st['refine_steps']}, "
+          f"max residual {st['max_relres']:.1e}", flush=True)
+    assert st["refined_batches"] >= 1 and st["max_relres"] <= 1e-10 and st["refine_steps"] >= 1
+    sv.close()
+
+
+def test_budget_counts_the_kept_scratch():
+    """Device memory kept by the library from finished factorizations counts
+    against the budget and is trimmed when a factor request would not fit
+    otherwise: with a budget just above one request's estimate, requests
+    submitted one after another are all admitted and served."""
+    need_gpu()
+    n, k = 48, 32
+    pts = inputs.jittered_grid2d(n, seed_offset=21)
+    tc = rsrs.rsrs_build_tree(pts, 64)
+    op = rsrs.rsrs_op_create_kernel(rsrs.RSRS_OP_LOG2D, pts, 1.0 / n)
+    s = tc.samples_required(k, k)
+    # a large factorization first leaves its scratch in the pool
+    big = _factor(96, 64, mixed=False, seed_off=5)
+    del big
+    sv = rsrs.Server(hbm_budget=1 << 30, max_batch_cols=64)
+    for j in range(3):
+        t = sv.submit_factor(tc, op, s, inputs.BASE_SEED + j, k)
+        fid, _ = sv.wait(t, timeout_ms=60000)
+        st = sv.stats()
+        assert st["hbm_peak"] <= 1 << 30
+        sv.release(fid)
+    sv.close()
