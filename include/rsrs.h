@@ -171,13 +171,18 @@ typedef int (*rsrs_matvec_fn)(void* user, int transpose, int dtype, int64_t ncol
  *                 (param unused; dim 3)
  *  RSRS_OP_LOG2D_SKEW  LOG2D plus param2 * (x_i - x_j)_0 / |x_i - x_j|^2
  *                 (non-symmetric)
+ *  RSRS_OP_LOG2D_FIRST  the first-kind log kernel (no identity term):
+ *                 A_ij = h^2 (-log|x_i - x_j| / (2 pi)), i != j, and
+ *                 A_ii = h^2 (-log h - c) / (2 pi), the kernel's mean over a
+ *                 cell of side h, c = (log 2 - 3 + pi/2) / 2 - log 2 the
+ *                 mean of log|u| over the unit square (param = h; dim 2)
  * pts: host n x dim (user order); copied to the device.  The kernel matrix is
  * materialised on the device in FP64 at creation (n^2 doubles); an FP32 copy
  * (n^2 floats) is added at the first RSRS_F32 product, whose product is then
  * an FP32 MFMA GEMM with FP32 accumulation, and a BF16 copy (n^2 x 2 bytes) at
  * the first RSRS_BF16 product (BF16 MFMA, FP32 accumulation; n a multiple of
  * 8; transposed products of the skewed kernel use the FP32 product). */
-enum { RSRS_OP_LOG2D = 1, RSRS_OP_INVR3D = 2, RSRS_OP_LOG2D_SKEW = 3 };
+enum { RSRS_OP_LOG2D = 1, RSRS_OP_INVR3D = 2, RSRS_OP_LOG2D_SKEW = 3, RSRS_OP_LOG2D_FIRST = 4 };
 rsrs_status rsrs_op_create_kernel(int kind, const double* pts, int64_t n, int dim,
                                   double param, double param2, rsrs_operator_t** out);
 /* Explicit matrix: A is a device n x n row-major array (leading dimension
@@ -369,6 +374,23 @@ rsrs_status rsrs_solve_noalloc(const rsrs_factor_t* f, int transpose, int64_t nr
 rsrs_status rsrs_solve_refine(const rsrs_factor_t* f, rsrs_matvec_fn mv, void* user, int64_t nrhs,
                               const double* F, int64_t ldf, double* U, int64_t ldu, double tol,
                               int maxit, double* relres, int* iters, void* stream);
+
+/* GMRES preconditioned by the factorization (Sec. 5, where the factorization
+ * is the preconditioner of GMRES and the iteration counts are reported):
+ * right preconditioning, GMRES on A M^{-1} y = f with M^{-1} = A_approx^{-1}
+ * (rsrs_solve) and u = M^{-1} y, so the residual minimised is the true one,
+ * through the black-box product mv (FP64).  Restarted every `restart`
+ * (1..64) steps from the true residual; each column is an independent run
+ * (columns advance in lock step, 64 at a time, sharing every solve and
+ * product); a column stops once its residual estimate is <= tol.  Returns
+ * RSRS_OK with *relres = max_col ||f - A u|| / ||f|| (true residual) and
+ * *iters = GMRES steps of the longest run, also when maxit is reached
+ * (compare *relres with tol).  For operators where the plain refinement of
+ * rsrs_solve_refine does not converge (||I - A_approx^{-1} A|| >= 1).
+ * Synchronises the stream once per step. */
+rsrs_status rsrs_solve_gmres(const rsrs_factor_t* f, rsrs_matvec_fn mv, void* user, int64_t nrhs,
+                             const double* F, int64_t ldf, double* U, int64_t ldu, double tol,
+                             int restart, int maxit, double* relres, int* iters, void* stream);
 
 /* ------------------------------------------------------------------------
  * Serving (continuous batching).  The method factors once from one set of

@@ -17,6 +17,12 @@ workloads used for measurement:
   coefficient = mean of the two node values, Dirichlet nodes eliminated.
 * ``log2d_skew``: ``log2d`` plus eps * (x_i - x_j)_0 / |x_i - x_j|^2, an
   antisymmetric part, so that A != A^T.
+* ``log2d_first``: the first-kind log kernel of Experiment 1 on a cell-centred
+  grid: A_ij = h^2 (-log|x_i - x_j| / (2 pi)) with no identity term, and the
+  diagonal the average of the kernel over the point's own cell,
+  A_ii = h^2 (-log h - c_sq) / (2 pi), c_sq = (1/h^2) int_cell log|y| dy / h
+  (the mean of log|u| over the unit square centred at 0):
+  c_sq = (log 2 - 3 + pi/2) / 2 - log 2.
 """
 from __future__ import annotations
 
@@ -50,6 +56,18 @@ def log2d_skew(points: np.ndarray, h: float, eps: float) -> np.ndarray:
         s = diff[:, :, 0] / (r * r)
     s[np.arange(n), np.arange(n)] = 0.0
     return a + eps * s
+
+
+LOG_MEAN_UNIT_SQUARE = 0.5 * (np.log(2.0) - 3.0 + 0.5 * np.pi) - np.log(2.0)
+
+
+def log2d_first(points: np.ndarray, h: float) -> np.ndarray:
+    _, r = _pairwise(points)
+    n = r.shape[0]
+    with np.errstate(divide="ignore"):
+        a = (h * h) * (-np.log(r) / (2.0 * np.pi))
+    a[np.arange(n), np.arange(n)] = (h * h) * (-np.log(h) - LOG_MEAN_UNIT_SQUARE) / (2.0 * np.pi)
+    return a
 
 
 def inv_r3d(points: np.ndarray) -> np.ndarray:

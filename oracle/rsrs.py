@@ -460,3 +460,75 @@ def _power(op, opt, n, iters, seed):
             return 0.0
         x = y / lam
     return float(np.sqrt(lam))
+
+
+# ----------------------------------------------------------------------------
+# Preconditioned GMRES (Sec. 5: the factorization as a preconditioner for
+# GMRES, counted in iterations n_iter).  Right preconditioning: GMRES on
+# A M^{-1} y = f with M^{-1} = A_approx^{-1} (the solve above), x = M^{-1} y,
+# so the residual GMRES minimises is the true one, f - A x.  Arnoldi by
+# modified Gram-Schmidt, Givens rotations for the least-squares problem,
+# restarted every `restart` steps from the true residual.
+# ----------------------------------------------------------------------------
+
+def gmres(F: Factorization, matvec, f, tol: float = 1e-10, restart: int = 30, maxit: int = 200):
+    """Returns (x, iterations per column, relative residual history per
+    column: the Arnoldi estimate after each step, then the true residual
+    at the end)."""
+    f, vec = _as2d(f)
+    n, w = f.shape
+    X = np.zeros_like(f)
+    iters, hists = [], []
+    for c in range(w):
+        b = f[:, c]
+        bn = np.linalg.norm(b)
+        x = np.zeros(n)
+        if bn == 0.0:
+            iters.append(0)
+            hists.append([0.0])
+            continue
+        r = b.copy()
+        beta = bn
+        it = 0
+        hist = [1.0]
+        while beta > tol * bn and it < maxit:
+            m = min(restart, maxit - it)
+            V = np.zeros((m + 1, n))
+            H = np.zeros((m + 1, m))
+            cs, sn = np.zeros(m), np.zeros(m)
+            g = np.zeros(m + 1)
+            g[0] = beta
+            V[0] = r / beta
+            j_done = 0
+            for j in range(m):
+                wv = matvec(solve(F, V[j]))
+                for i in range(j + 1):
+                    H[i, j] = wv @ V[i]
+                    wv = wv - H[i, j] * V[i]
+                H[j + 1, j] = np.linalg.norm(wv)
+                if H[j + 1, j] > 0.0:
+                    V[j + 1] = wv / H[j + 1, j]
+                for i in range(j):      # earlier rotations on the new column
+                    t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
+                    H[i + 1, j] = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]
+                    H[i, j] = t
+                den = np.hypot(H[j, j], H[j + 1, j])
+                cs[j], sn[j] = (H[j, j] / den, H[j + 1, j] / den) if den > 0.0 else (1.0, 0.0)
+                H[j, j] = den
+                H[j + 1, j] = 0.0
+                g[j + 1] = -sn[j] * g[j]
+                g[j] = cs[j] * g[j]
+                it += 1
+                j_done = j + 1
+                hist.append(abs(g[j + 1]) / bn)
+                if abs(g[j + 1]) <= tol * bn or it >= maxit:
+                    break
+            y = sla.solve_triangular(H[:j_done, :j_done], g[:j_done], lower=False)
+            x = x + solve(F, V[:j_done].T @ y)
+            r = b - matvec(x)
+            beta = np.linalg.norm(r)
+        hist.append(beta / bn)
+        X[:, c] = x
+        iters.append(it)
+        hists.append(hist)
+    return (X[:, 0] if vec else X), iters, hists

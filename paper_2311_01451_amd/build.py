@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librsrs.so")
-SOURCES = ["tree.cpp", "dense.hip", "id.hip", "ops.hip", "factor.hip", "solve.hip", "api.hip", "profile.hip", "server.hip", "bf16.hip", "chol.hip", "pool.hip"]
+SOURCES = ["tree.cpp", "dense.hip", "id.hip", "ops.hip", "factor.hip", "solve.hip", "api.hip", "profile.hip", "server.hip", "bf16.hip", "chol.hip", "pool.hip", "gmres.hip"]
 ARCH = os.environ.get("RSRS_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CFLAGS = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",

@@ -138,7 +138,7 @@ rsrs_status rsrs_op_create_kernel(int kind, const double* pts, int64_t n, int di
                                   double param2, rsrs_operator_t** out) {
   if (!pts || !out || n < 1) return invalid("bad operator arguments");
   if (!((kind == RSRS_OP_LOG2D && dim == 2) || (kind == RSRS_OP_LOG2D_SKEW && dim == 2) ||
-        (kind == RSRS_OP_INVR3D && dim == 3)))
+        (kind == RSRS_OP_LOG2D_FIRST && dim == 2) || (kind == RSRS_OP_INVR3D && dim == 3)))
     return invalid("unknown operator kind or wrong dimension");
   *out = nullptr;
   auto op = new rsrs_operator_t();

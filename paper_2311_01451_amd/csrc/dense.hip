@@ -2,6 +2,8 @@
 // copies, permutations and reductions (FP64).
 #include <hip/hip_runtime.h>
 
+#include <utility>
+
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -312,15 +314,12 @@ __device__ __forceinline__ double quad_bcast_dpp_rt(double x, int s) {
 // thread of the workgroup calls this (the barriers); on_pivot(t, p, |pivot|)
 // runs in lane 0 of wave 0 after each step.  Rows >= nrows hold zeros and
 // count as used.
-template <int RL, class OnPivot>
-__device__ __forceinline__ void gj_panel_steps(double (&rv)[RL][4], unsigned& used_mask, int row0, int wave,
-                                               int lane, bool pw, int nsteps, int nrows, double* OFF,
-                                               OnPivot&& on_pivot) {
+template <int RL, int t, class OnPivot>
+__device__ __forceinline__ void gj_panel_step(double (&rv)[RL][4], unsigned& used_mask, int row0, int wave,
+                                              int lane, bool pw, int nrows, double* OFF, OnPivot& on_pivot) {
   const int cq = lane & 3;
   const int NONE = 1 << 30;
-#pragma clang loop unroll(full)
-  for (int t = 0; t < 16; ++t) {
-    if (t >= nsteps) continue;   // uniform; the loop keeps its constant trip count (unrolled)
+  {
     double* slot = OFF + (t & 1) * (4 * 20);
     if (pw) {
       // best free row of this wave in column t (lowest row on ties)
@@ -344,13 +343,18 @@ __device__ __forceinline__ void gj_panel_steps(double (&rv)[RL][4], unsigned& us
       // the four lanes holding row cand publish it
       const int rel = cand - row0;
       if (cand != NONE && rel >= 0 && rel < RL) {
+        // row rel of this lane, picked by bit masks (a select chain over
+        // rv would be turned into an indexed load and push rv to memory)
         double x[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-          double y = rv[0][c];
+          unsigned long long y = 0;
 #pragma unroll
-          for (int ii = 1; ii < RL; ++ii) y = rel == ii ? rv[ii][c] : y;
-          x[c] = y;
+          for (int ii = 0; ii < RL; ++ii) {
+            const unsigned long long mask = 0ull - (unsigned long long)(rel == ii);
+            y |= (unsigned long long)__double_as_longlong(rv[ii][c]) & mask;
+          }
+          x[c] = __longlong_as_double((long long)y);
         }
         double* dst = slot + wave * 20 + 4 + 4 * cq;
         *reinterpret_cast<double2*>(dst) = make_double2(x[0], x[1]);
@@ -389,22 +393,43 @@ __device__ __forceinline__ void gj_panel_steps(double (&rv)[RL][4], unsigned& us
         // column t of this row, from the quad lane that holds it
         const double ct = quad_bcast_dpp_rt(rv[i][t & 3], t >> 2) * inv;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) rv[i][c] -= ct * pr[c];
-        if (colq) rv[i][t & 3] = -ct;
+        for (int c = 0; c < 4; ++c) rv[i][c] = (colq && c == (t & 3)) ? -ct : rv[i][c] - ct * pr[c];
       }
       // the pivot row: scaled by the pivot, its column t the reciprocal
+      // (selects, not stores under a branch: those would be merged into one
+      // store at a computed index and push rv out of registers)
       const int rp = p - row0;
 #pragma unroll
-      for (int i = 0; i < RL; ++i)
-        if (rp == i) {
+      for (int i = 0; i < RL; ++i) {
+        const bool mine = rp == i;
 #pragma unroll
-          for (int c = 0; c < 4; ++c) rv[i][c] = pr[c] * inv;
-          if (colq) rv[i][t & 3] = inv;
-          used_mask |= 1u << i;
+        for (int c = 0; c < 4; ++c) {
+          const double sc = (colq && c == (t & 3)) ? inv : pr[c] * inv;
+          rv[i][c] = mine ? sc : rv[i][c];
         }
+        used_mask |= mine ? (1u << i) : 0u;
+      }
       if (wave == 0 && lane == 0) on_pivot(t, p, bv);
     }
+  
   }
+}
+
+template <int RL, class OnPivot, int... T>
+__device__ __forceinline__ void gj_panel_all(double (&rv)[RL][4], unsigned& used_mask, int row0, int wave,
+                                             int lane, bool pw, int nsteps, int nrows, double* OFF,
+                                             OnPivot& on_pivot, std::integer_sequence<int, T...>) {
+  // one step per column, its index a constant (register indices stay static);
+  // nsteps is uniform, so every thread reaches the same barriers
+  ((T < nsteps ? gj_panel_step<RL, T>(rv, used_mask, row0, wave, lane, pw, nrows, OFF, on_pivot) : void()), ...);
+}
+
+template <int RL, class OnPivot>
+__device__ __forceinline__ void gj_panel_steps(double (&rv)[RL][4], unsigned& used_mask, int row0, int wave,
+                                               int lane, bool pw, int nsteps, int nrows, double* OFF,
+                                               OnPivot&& on_pivot) {
+  gj_panel_all<RL>(rv, used_mask, row0, wave, lane, pw, nsteps, nrows, OFF, on_pivot,
+                   std::make_integer_sequence<int, 16>{});
 }
 
 template <int NT>
@@ -541,6 +566,149 @@ __global__ __launch_bounds__(512) void gje_blk_kernel(const GjeDesc* __restrict_
       }
 }
 
+// Larger blocks (192 < n <= 1024): the same panel elimination, in global
+// memory, two launches per 16-column panel.  The working matrix X (n x n,
+// leading dimension n) is the first n^2 doubles of the workspace W, followed
+// by pos[n] (the elimination step of a pivoted row, n for a free one),
+// piv[n] (the pivot row of each step) and XP (16 x n: the old pivot rows of
+// the current panel).  The panel launch (one workgroup of four waves per
+// matrix, the panel's rows in registers, RL = NP / 64 rows per lane)
+// factors the panel with gj_panel_steps, writes it back and stages the old
+// pivot rows outside the panel; the update launch (64 x 64 tiles, FP64
+// MFMA) adds W XP to every other column, W = (factored panel) - E_P.
+struct GjeBig {
+  double* X;
+  int* pos;
+  int* piv;
+  double* XP;
+};
+__device__ __forceinline__ GjeBig gje_big_parts(const GjeDesc& d) {
+  GjeBig g;
+  const int64_t nn = (int64_t)d.n * d.n;
+  g.X = d.W;
+  g.pos = reinterpret_cast<int*>(d.W + nn);
+  g.piv = g.pos + d.n;
+  g.XP = d.W + nn + d.n;   // after 2n ints
+  return g;
+}
+
+__global__ __launch_bounds__(256) void gje_big_init_kernel(const GjeDesc* __restrict__ e) {
+  const GjeDesc d = e[blockIdx.y];
+  const int n = d.n;
+  const GjeBig g = gje_big_parts(d);
+  for (int r = blockIdx.x; r < n; r += gridDim.x) {
+    for (int c = threadIdx.x; c < n; c += 256) g.X[(int64_t)r * n + c] = d.A[(int64_t)r * d.lda + c];
+    if (threadIdx.x == 0) g.pos[r] = n;
+  }
+}
+
+template <int RL>
+__global__ __launch_bounds__(256) void gje_big_panel_kernel(const GjeDesc* __restrict__ e, int jt, int* flag) {
+  const GjeDesc d = e[blockIdx.x];
+  const int n = d.n;
+  const int c0 = 16 * jt;
+  if (c0 >= n) return;   // uniform: this matrix has no panel jt
+  const GjeBig g = gje_big_parts(d);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int rg = lane >> 2, cq = lane & 3;
+  const int row0 = RL * (16 * wave + rg);
+  const int ncols = min(16, n - c0);
+  __shared__ __align__(16) double OFF[2 * 4 * 20];
+  __shared__ int pnl[16];
+  double rv[RL][4];
+  unsigned used_mask = 0;
+#pragma unroll
+  for (int i = 0; i < RL; ++i) {
+    const int row = row0 + i;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int col = 4 * cq + c;
+      rv[i][c] = (row < n && col < ncols) ? g.X[(int64_t)row * n + c0 + col] : 0.0;
+    }
+    used_mask |= (row >= n || g.pos[row] < n) ? (1u << i) : 0u;
+  }
+  int* pos = g.pos;
+  int* piv = g.piv;
+  gj_panel_steps<RL>(rv, used_mask, row0, wave, lane, true, ncols, n, OFF,
+                     [=](int t, int p, double bv) {
+                       if (!(bv > 0.0)) atomicOr(flag, 2);
+                       pos[p] = c0 + t;
+                       piv[c0 + t] = p;
+                       pnl[t] = p;
+                     });
+#pragma unroll
+  for (int i = 0; i < RL; ++i) {
+    const int row = row0 + i;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int col = 4 * cq + c;
+      if (row < n && col < ncols) g.X[(int64_t)row * n + c0 + col] = rv[i][c];
+    }
+  }
+  __syncthreads();
+  // old pivot rows outside the panel (this launch writes only panel columns)
+  for (int t = 0; t < ncols; ++t) {
+    const double* src = g.X + (int64_t)pnl[t] * n;
+    for (int c = tid; c < n; c += 256)
+      if (c < c0 || c >= c0 + 16) g.XP[(int64_t)t * n + c] = src[c];
+  }
+}
+
+__global__ __launch_bounds__(256) void gje_big_update_kernel(const GjeDesc* __restrict__ e, int jt) {
+  const GjeDesc d = e[blockIdx.z];
+  const int n = d.n;
+  const int c0 = 16 * jt;
+  const int r0 = 64 * blockIdx.y, cb = 64 * blockIdx.x;
+  if (c0 >= n || r0 >= n || cb >= n) return;
+  const GjeBig g = gje_big_parts(d);
+  const int ncols = min(16, n - c0);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int q = lane >> 4, c16 = lane & 15;
+  const int arow = r0 + 16 * wave + c16;   // row of this lane's A operand
+  double a[4];
+  const int ap = arow < n ? g.pos[arow] : n;
+#pragma unroll
+  for (int kc = 0; kc < 4; ++kc) {
+    const int kk = 4 * kc + q;
+    a[kc] = (arow < n && kk < ncols) ? g.X[(int64_t)arow * n + c0 + kk] - (ap == c0 + kk ? 1.0 : 0.0) : 0.0;
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int tc = cb + 16 * j;
+    if (tc >= n || tc == c0) continue;   // beyond the matrix, or the panel itself
+    const int col = tc + c16;
+    v4d acc;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = r0 + 16 * wave + 4 * v + q;
+      acc[v] = (row < n && col < n) ? g.X[(int64_t)row * n + col] : 0.0;
+    }
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) {
+      const int kk = 4 * kc + q;
+      const double b = (kk < ncols && col < n) ? g.XP[(int64_t)kk * n + col] : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kc], b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = r0 + 16 * wave + 4 * v + q;
+      if (row < n && col < n) g.X[(int64_t)row * n + col] = acc[v];
+    }
+  }
+}
+
+// A^{-1}[i][piv[c]] = X[piv[i]][c].
+__global__ __launch_bounds__(256) void gje_big_out_kernel(const GjeDesc* __restrict__ e) {
+  const GjeDesc d = e[blockIdx.y];
+  const int n = d.n;
+  const GjeBig g = gje_big_parts(d);
+  for (int i = blockIdx.x; i < n; i += gridDim.x) {
+    const double* src = g.X + (int64_t)g.piv[i] * n;
+    for (int c = threadIdx.x; c < n; c += 256) d.Ainv[(int64_t)i * d.ldi + g.piv[c]] = src[c];
+  }
+}
+
 // Gauss-Jordan for blocks too large for registers, one launch per pivot
 // step.  The working matrix alternates between the two n x n halves of W
 // (step j reads what step j - 1 wrote, the first step reads A), so no
@@ -633,7 +801,8 @@ __global__ __launch_bounds__(256) void gje_out_kernel(const GjeDesc* __restrict_
 }
 
 // The variant is chosen per matrix by its own size (blocked kernels for
-// n <= 64 / 128 / 192, the one-launch-per-step form above), so a matrix is
+// n <= 64 / 128 / 192, panel and update launches up to 1024, the
+// one-launch-per-step form above beyond), so a matrix is
 // inverted by the same instruction sequence whatever else is in the batch.
 static rsrs_status gje_group(Uploader& up, hipStream_t st, const std::vector<GjeDesc>& e, int* flag,
                              int variant) {
@@ -661,11 +830,32 @@ static rsrs_status gje_group(Uploader& up, hipStream_t st, const std::vector<Gje
   }
   int nmax = 0;
   for (const auto& x : e) nmax = std::max(nmax, x.n);
-  // large blocks: the pivot rows of each matrix, recorded step by step
+  if (variant == 3) {   // 192 < n <= 1024: panel and update launches per 16 columns
+    ProfScope ps(st, "gauss_jordan_big", gf, gb);
+    const unsigned rb = (unsigned)((nmax + 63) / 64);
+    hipLaunchKernelGGL(gje_big_init_kernel, dim3((unsigned)std::min(nmax, 1024), nb), dim3(256), 0, st, de);
+    const int rl = (nmax + 63) / 64;
+    for (int jt = 0; jt * 16 < nmax; ++jt) {
+      if (rl <= 4)
+        hipLaunchKernelGGL(gje_big_panel_kernel<4>, dim3(nb), dim3(256), 0, st, de, jt, flag);
+      else if (rl <= 8)
+        hipLaunchKernelGGL(gje_big_panel_kernel<8>, dim3(nb), dim3(256), 0, st, de, jt, flag);
+      else if (rl <= 12)
+        hipLaunchKernelGGL(gje_big_panel_kernel<12>, dim3(nb), dim3(256), 0, st, de, jt, flag);
+      else
+        hipLaunchKernelGGL(gje_big_panel_kernel<16>, dim3(nb), dim3(256), 0, st, de, jt, flag);
+      hipLaunchKernelGGL(gje_big_update_kernel, dim3(rb, rb, nb), dim3(256), 0, st, de, jt);
+    }
+    hipLaunchKernelGGL(gje_big_out_kernel, dim3((unsigned)std::min(nmax, 1024), nb), dim3(256), 0, st, de);
+    RSRS_HIP(hipGetLastError());
+    return RSRS_OK;
+  }
+  // very large blocks: one launch per pivot step, the pivot rows of each
+  // matrix recorded step by step
   const int64_t stride = round_up((int64_t)nmax, 64);
   DevBuf pivs;
   RSRS_TRY(pivs.alloc((size_t)stride * nb * sizeof(int)));
-  ProfScope ps(st, "gauss_jordan_big", gf, gb);
+  ProfScope ps(st, "gauss_jordan_step", gf, gb);
   const unsigned cblk = (unsigned)((nmax + 63) / 64);
   for (int j = 0; j < nmax; ++j)
     hipLaunchKernelGGL(gje_step_kernel, dim3(cblk, nb), dim3(256), 0, st, de, pivs.as<int>(), stride, j, flag);
@@ -679,15 +869,15 @@ static rsrs_status gje_group(Uploader& up, hipStream_t st, const std::vector<Gje
 
 rsrs_status gje_inverse(Uploader& up, hipStream_t st, const std::vector<GjeDesc>& e, int* flag) {
   if (e.empty()) return RSRS_OK;
-  std::vector<GjeDesc> grp[4];
+  std::vector<GjeDesc> grp[5];
   for (const auto& x : e) {
     if (x.n > 65536) {
       set_error("Gauss-Jordan block too large");
       return RSRS_E_UNSUPPORTED;
     }
-    grp[x.n <= 64 ? 0 : x.n <= 128 ? 1 : x.n <= 192 ? 2 : 3].push_back(x);
+    grp[x.n <= 64 ? 0 : x.n <= 128 ? 1 : x.n <= 192 ? 2 : x.n <= 1024 ? 3 : 4].push_back(x);
   }
-  for (int v = 0; v < 4; ++v) RSRS_TRY(gje_group(up, st, grp[v], flag, v));
+  for (int v = 0; v < 5; ++v) RSRS_TRY(gje_group(up, st, grp[v], flag, v));
   return RSRS_OK;
 }
 

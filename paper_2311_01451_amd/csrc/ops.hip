@@ -81,7 +81,13 @@ __global__ void kernel_matrix_kernel(T* A, int64_t n, int kind, int dim, const d
     const int64_t i = idx / n, j = idx % n;
     double v;
     if (i == j) {
-      v = (kind == 2) ? 1.0 : 1.0 + 0.5 * p1 * p1;
+      if (kind == 4) {   // the kernel's mean over the point's cell of side p1
+        const double ln2 = 0.69314718055994530941723212145818;
+        const double mean_log_unit_square = 0.5 * (ln2 - 3.0 + 0.25 * two_pi) - ln2;
+        v = p1 * p1 * (-log(p1) - mean_log_unit_square) / two_pi;
+      } else {
+        v = (kind == 2) ? 1.0 : 1.0 + 0.5 * p1 * p1;
+      }
     } else {
       double r2 = 0.0, dx0 = 0.0;
       for (int a = 0; a < dim; ++a) {

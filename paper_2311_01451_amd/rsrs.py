@@ -24,6 +24,7 @@ _lib = None
 RSRS_OP_LOG2D = 1
 RSRS_OP_INVR3D = 2
 RSRS_OP_LOG2D_SKEW = 3
+RSRS_OP_LOG2D_FIRST = 4
 RSRS_PREC_F64 = 0
 RSRS_ID_SUM, RSRS_ID_CONCAT = 0, 1
 RSRS_PREC_F32_MIXED = 1
@@ -98,7 +99,7 @@ EXPORTS = [
     "rsrs_sample", "rsrs_sample_symmetric", "rsrs_samples_wrap_symmetric", "rsrs_samples_destroy", "rsrs_gaussian", "rsrs_factor", "rsrs_factor_batched",
     "rsrs_factor_destroy", "rsrs_release_cached",
     "rsrs_factor_get_info", "rsrs_factor_box_sizes", "rsrs_factor_box_copy",
-    "rsrs_factor_root_copy", "rsrs_solve", "rsrs_solve_noalloc", "rsrs_apply", "rsrs_solve_refine",
+    "rsrs_factor_root_copy", "rsrs_solve", "rsrs_solve_noalloc", "rsrs_apply", "rsrs_solve_refine", "rsrs_solve_gmres",
     "rsrs_profile_enable", "rsrs_profile_filter", "rsrs_profile_reset", "rsrs_profile_read", "rsrs_solve_graphs",
     "rsrs_server_create", "rsrs_server_destroy", "rsrs_server_add_factor",
     "rsrs_server_release_factor", "rsrs_server_set_refine", "rsrs_server_submit_solve", "rsrs_server_submit_factor",
@@ -152,6 +153,7 @@ def lib():
         "rsrs_solve_noalloc": (i32, [vp, i32, i64, vp, i64, vp, i64, vp]),
         "rsrs_solve_refine": (i32, [vp, vp, vp, i64, vp, i64, vp, i64, dbl, i32, P(dbl),
                                     P(i32), vp]),
+        "rsrs_solve_gmres": (i32, [vp, vp, vp, i64, vp, i64, vp, i64, dbl, i32, i32, P(dbl), P(i32), vp]),
         "rsrs_server_create": (i32, [P(ServerOpts), P(vp)]),
         "rsrs_server_destroy": (None, [vp]),
         "rsrs_server_add_factor": (i32, [vp, vp, P(i64)]),
@@ -549,6 +551,22 @@ def rsrs_solve_refine(f: Factor, op: Operator, F, tol: float = 1e-10, maxit: int
     it = C.c_int()
     _check(lib().rsrs_solve_refine(f.handle, Operator.fn_ptr(), op.handle, F.shape[1], pf, ldf, pu, ldu,
                                    tol, maxit, C.byref(rel), C.byref(it), _stream(stream)))
+    return out, rel.value, it.value
+
+
+def rsrs_solve_gmres(f: Factor, op: Operator, F, tol: float = 1e-10, restart: int = 30, maxit: int = 200,
+                     out=None, stream=None):
+    """GMRES preconditioned by the factorization; returns (u, relres, iterations)."""
+    import torch
+    pf, ldf = _dev(F, "F")
+    if out is None:
+        out = torch.empty_like(F)
+    pu, ldu = _dev(out, "out")
+    rel = C.c_double()
+    it = C.c_int()
+    _check(lib().rsrs_solve_gmres(f.handle, Operator.fn_ptr(), op.handle, F.shape[1], pf, ldf, pu, ldu,
+                                  float(tol), int(restart), int(maxit), C.byref(rel), C.byref(it),
+                                  _stream(stream)))
     return out, rel.value, it.value
 
 

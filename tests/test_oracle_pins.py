@@ -631,3 +631,73 @@ def test_concatenated_id_option():
     Om2, Psi2 = inputs.test_matrices(256, s)
     Fh = orr.factor(th, H @ Om2, H.T @ Psi2, Om2, Psi2, 6, id_mode="concat")
     assert orr.relerr(Fh, H) < 1e-11
+
+
+# ---------------------------------------------------------------- preconditioned GMRES (Sec. 5)
+
+def test_first_kind_log_operator_diagonal():
+    """log2d_first: the diagonal is the kernel's average over the point's
+    cell (closed form of the mean of log|u| over the unit square, checked by
+    quadrature); off-diagonal entries equal log2d's without the identity."""
+    import scipy.integrate as si
+    f = lambda y, x: np.log(np.hypot(x, y)) if (x > 0 or y > 0) else 0.0
+    quad, _ = si.dblquad(f, 0, 0.5, 0, 0.5, epsabs=1e-13, epsrel=1e-13)
+    assert abs(4 * quad - oop.LOG_MEAN_UNIT_SQUARE) < 1e-11
+    pts = inputs.grid2d(8)
+    h = 1.0 / 8
+    A1, A0 = oop.log2d_first(pts, h), oop.log2d(pts, h)
+    off = ~np.eye(64, dtype=bool)
+    assert np.abs(A1[off] - A0[off]).max() == 0.0
+    assert np.allclose(np.diag(A1), h * h * (-np.log(h) - oop.LOG_MEAN_UNIT_SQUARE) / (2 * np.pi), rtol=0, atol=1e-18)
+
+
+def test_gmres_exact_preconditioner_and_rank_one_perturbation():
+    """GMRES with right preconditioning by the factorization: an exact
+    factor (exactly H2 operator) converges in one step; for A + u v^T the
+    preconditioned operator is I + (rank one), two distinct eigenvalues, so
+    GMRES terminates in at most two steps; the solution matches a dense
+    solve and the Arnoldi residual estimates never increase."""
+    pts = inputs.grid2d(16)
+    t = ot.build_tree(pts, leaf_size=16)
+    H = exact_h2(t, r=3)
+    s = ot.samples_required(t, 6, 6)
+    Om, Psi = inputs.test_matrices(256, s)
+    F = orr.factor(t, H @ Om, H.T @ Psi, Om, Psi, 6)
+    f = inputs.rhs(256, 2)
+    x, its, hists = orr.gmres(F, lambda v: H @ v, f, tol=1e-10)
+    assert its == [1, 1]
+    rng = np.random.default_rng(14)
+    u, v = rng.standard_normal(256), rng.standard_normal(256)
+    A = H + 0.3 * np.outer(u, v)
+    x, its, hists = orr.gmres(F, lambda y: A @ y, f, tol=1e-10)
+    assert max(its) <= 2
+    xs = np.linalg.solve(A, f)
+    assert np.abs(x - xs).max() < 1e-8 * np.abs(xs).max()
+    for h in hists:
+        est = h[1:-1]
+        assert all(est[i + 1] <= est[i] * (1 + 1e-12) for i in range(len(est) - 1))
+
+
+def test_gmres_converges_where_refinement_diverges():
+    """Sec. 5 uses the factorization to precondition GMRES.  On the first-kind
+    log kernel with a rank far too low (k = 4; ||I - A_approx^{-1} A|| in the
+    hundreds) the refinement iteration diverges while GMRES still reaches
+    1e-10 (trend of the paper's n_iter tables: more iterations for a coarser
+    factorization, but convergence)."""
+    n, k = 32, 4
+    pts = inputs.grid2d(n)
+    A = oop.log2d_first(pts, 1.0 / n)
+    t = ot.build_tree(pts, 32)
+    s = ot.samples_required(t, k, k)
+    Om, Psi = inputs.test_matrices(n * n, s)
+    F = orr.factor(t, A @ Om, A.T @ Psi, Om, Psi, k)
+    f = inputs.rhs(n * n, 1)[:, 0]
+    _, hist = orr.refine(F, lambda v: A @ v, f, tol=1e-10, maxit=12)
+    assert hist[-1] > 1.0
+    x, its, hists = orr.gmres(F, lambda v: A @ v, f, tol=1e-10, restart=30, maxit=200)
+    assert hists[0][-1] <= 1e-10 and its[0] < 120
+    s2 = ot.samples_required(t, 12, 12)
+    Om2, Psi2 = inputs.test_matrices(n * n, s2)
+    F2 = orr.factor(t, A @ Om2, A.T @ Psi2, Om2, Psi2, 12)
+    _, its2, _ = orr.gmres(F2, lambda v: A @ v, f, tol=1e-10)
+    assert its2[0] < its[0] / 4
