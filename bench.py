@@ -619,6 +619,146 @@ def config2_leg() -> dict:
     return out
 
 
+def config3_leg() -> dict:
+    """The many-problem workload: 48 jittered 2D log-kernel problems (N
+    log-uniform from about 2,000 to 33,000, k in {32, 48, 64}, leaf 64,
+    s = s_required, FP32 samples and products with FP64 pivots), factored
+    by one batched call; 16 right-hand sides per problem refined to 1e-6
+    through each problem's FP64 operator.  Beside it, the same problems
+    factored one at a time."""
+    import torch
+    from paper_2311_01451_amd import inputs, rsrs
+
+    specs = inputs.uneven_batch()
+    trees, ks, ss, model = [], [], [], 0.0
+    for P in specs:
+        P["pts"] = inputs.jittered_grid2d(P["n"], seed_offset=P["geom_seed"])
+        tc = rsrs.rsrs_build_tree(P["pts"], LEAF)
+        s = tc.samples_required(P["k"], P["k"])
+        trees.append(tc)
+        ks.append(P["k"])
+        ss.append(s)
+        model += rsrs.rsrs_work_model(tc, P["k"], s, False, 4)["flops"]
+
+    def samples():
+        out = []
+        for P, tc, s in zip(specs, trees, ss):
+            op = rsrs.rsrs_op_create_kernel(rsrs.RSRS_OP_LOG2D, P["pts"], 1.0 / P["n"])
+            out.append(rsrs.rsrs_sample(tc, op, s, inputs.BASE_SEED + P["seed"], dtype=rsrs.RSRS_F32))
+            torch.cuda.synchronize()
+            del op
+        return out
+
+    smps = samples()
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    Fs = rsrs.rsrs_factor_batched(trees, smps, ks, precision=rsrs.RSRS_PREC_F32_MIXED)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - a
+    del smps
+    t_ref, worst, iters = 0.0, 0.0, []
+    for P, F in zip(specs, Fs):
+        op = rsrs.rsrs_op_create_kernel(rsrs.RSRS_OP_LOG2D, P["pts"], 1.0 / P["n"])
+        f = torch.tensor(inputs.rhs(P["n"] ** 2, NRHS, P["seed"]), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        u, rel, it = rsrs.rsrs_solve_refine(F, op, f, tol=TOL, maxit=30)
+        torch.cuda.synchronize()
+        t_ref += time.perf_counter() - a
+        worst = max(worst, rel)
+        iters.append(it)
+        del op
+    del Fs
+    smps = samples()
+    t_single = 0.0
+    for tc, smp, k in zip(trees, smps, ks):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        F = rsrs.rsrs_factor(tc, smp, k, precision=rsrs.RSRS_PREC_F32_MIXED)
+        torch.cuda.synchronize()
+        t_single += time.perf_counter() - a
+        del F
+    del smps
+    Ns = [P["n"] ** 2 for P in specs]
+    return {"workload": f"{len(specs)} jittered 2D log-kernel problems, N log-uniform in [{min(Ns)}, {max(Ns)}] "
+                        f"(total {sum(Ns)}), k in {{32, 48, 64}}, leaf 64, s = s_required, mixed precision, "
+                        "16 RHS each refined to 1e-6",
+            "batch_factor_s": round(t_batch, 4), "one_at_a_time_factor_s": round(t_single, 4),
+            "batch_speedup": round(t_single / t_batch, 3),
+            "refine_s_all": round(t_ref, 4), "cols_per_s": round(NRHS * len(specs) / (t_batch + t_ref), 2),
+            "worst_relres": worst, "refine_iters_max": int(max(iters)),
+            "factor_tflops_work_model": round(model / t_batch / 1e12, 3)}
+
+
+def col_subset_leg(ctx: dict) -> dict:
+    """Per-box column subsets (a box reads its first s_B = min(s, l + k + p)
+    sample columns in its nullification, ID and extraction) beside the
+    default (all s columns), one step each after one warm-up:
+      * the 64 x 64 grid in FP64 (general variant, k = p = 32): factor time
+        and the factorization's relerr ||A - A_approx|| / ||A|| from the
+        dense apply;
+      * the headline workload (256 x 256, mixed, symmetric): factor time,
+        one-shot residual, refinement steps to 1e-6 and columns per second."""
+    import torch
+    from paper_2311_01451_amd import inputs, rsrs
+
+    out = {"what": "s_B = min(s, l + k + p) columns per box vs all s; work model flops of each"}
+    n, k = 64, 32
+    pts = inputs.grid2d(n)
+    op0 = rsrs.rsrs_op_create_kernel(rsrs.RSRS_OP_LOG2D, pts, 1.0 / n)
+    eye = torch.eye(n * n, dtype=torch.float64, device="cuda")
+    A = op0.matvec(eye)
+    nA = float(torch.linalg.matrix_norm(A, 2))
+    c0 = {}
+    for label, cs in (("all_columns", False), ("col_subset", True)):
+        for rep in range(2):
+            tc = rsrs.rsrs_build_tree(pts, LEAF)
+            s = max(320, tc.samples_required(k, k))
+            smp = rsrs.rsrs_sample(tc, op0, s, inputs.BASE_SEED, dtype=rsrs.RSRS_F64)
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            F = rsrs.rsrs_factor(tc, smp, k, col_subset=cs)
+            torch.cuda.synchronize()
+            b = time.perf_counter()
+        Aap = F.apply(eye)
+        c0[label] = {"factor_ms": round((b - a) * 1e3, 3),
+                     "relerr": float(torch.linalg.matrix_norm(A - Aap, 2)) / nA,
+                     "work_model_gflop": round(rsrs.rsrs_work_model(tc, k, s, False, 8, col_subset=cs)["flops"]
+                                               / 1e9, 2)}
+        del F, Aap
+    del A, eye
+    out["config0_fp64_k32"] = c0
+    op, f = ctx["op"], ctx["f"]
+    pts1 = inputs.grid2d(GRID_N)
+    c1 = {}
+    for label, cs in (("all_columns", False), ("col_subset", True)):
+        for rep in range(2):
+            tc = rsrs.rsrs_build_tree(pts1, LEAF)
+            s = max(S_CFG, tc.samples_required(K, K))
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            smp = rsrs.rsrs_sample(tc, op, s, inputs.BASE_SEED, dtype=rsrs.RSRS_BF16, symmetric=True)
+            F = rsrs.rsrs_factor(tc, smp, K, precision=rsrs.RSRS_PREC_F32_MIXED, symmetric=True,
+                                 col_subset=cs)
+            torch.cuda.synchronize()
+            b = time.perf_counter()
+            u0 = F.solve(f)
+            r0 = float(torch.linalg.norm(f - op.matvec(u0)) / torch.linalg.norm(f))
+            torch.cuda.synchronize()
+            c = time.perf_counter()
+            u, rel, its = rsrs.rsrs_solve_refine(F, op, f, tol=TOL, maxit=30)
+            torch.cuda.synchronize()
+            d = time.perf_counter()
+            del smp
+        c1[label] = {"sample_factor_ms": round((b - a) * 1e3, 3), "relres_oneshot": r0, "relres": rel,
+                     "refine_iters": its, "cols_per_s": round(NRHS / ((b - a) + (d - c)), 2),
+                     "work_model_gflop": round(rsrs.rsrs_work_model(tc, K, s, True, 4, col_subset=cs)["flops"]
+                                               / 1e9, 2)}
+        del F
+    out["headline_mixed_symmetric"] = c1
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -638,6 +778,8 @@ def main():
                     help="run only the serving workload for this many seconds and print its line")
     ap.add_argument("--serving-seconds", type=float, default=8.0,
                     help="length of the Poisson stream of the serving leg in the default run")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the built-in GEMM tile rule instead of measuring the tile table first")
     ap.add_argument("--no-configs", action="store_true",
                     help="leave out the legs of the other workloads (configs 0, 2 and 4)")
     a = ap.parse_args()
@@ -651,6 +793,12 @@ def main():
         out.update(serving_bench(a.serving))
         print(json.dumps(out))
         return
+    tune = None
+    if not a.no_autotune:
+        from paper_2311_01451_amd import rsrs as _r
+        t0 = time.perf_counter()
+        tune = _r.rsrs_gemm_autotune(None)
+        tune["seconds"] = round(time.perf_counter() - t0, 3)
     ctx = {}
     runs = {}
     plan = (("mixed", "bf16", True), ("mixed_general", "bf16", False),
@@ -713,6 +861,7 @@ def main():
         "config": workload_config(s_req, s_eff, a.reproject),
     }
     out.update({k: v for k, v in sm.items() if k not in ("value", "ms_per_step")})
+    out["gemm_autotune"] = tune
     for name in ("mixed_general", "fp64", "fp64_general"):
         if name in sums:
             keep = name == "fp64"
@@ -725,10 +874,12 @@ def main():
     if not a.no_configs:
         import torch
         out["configs"] = {}
-        for name, fn in (("config0_fp64", config0_leg), ("config2_poisson_mixed", config2_leg)):
+        for name, fn in (("config0_fp64", config0_leg), ("config2_poisson_mixed", config2_leg),
+                         ("config3_batch_mixed", config3_leg)):
             out["configs"][name] = fn()
             torch.cuda.synchronize()
         out["configs"]["config4_serving"] = serving_bench(a.serving_seconds)
+        out["column_subsets"] = col_subset_leg(ctx)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(s_eff)
     print(json.dumps(out))

@@ -127,21 +127,33 @@ rsrs_status rsrs_tree_schedule(const rsrs_tree_t* t, int k, int32_t* colour, int
  * Returns -1 on invalid arguments. */
 int64_t rsrs_samples_required(const rsrs_tree_t* t, int k, int p);
 
-/* Algorithmic work of a fixed-rank factorization with s samples, as the
- * cost analysis of Sec. 4.5 prices the steps of Algorithm 1 (the method's own
- * operations, not the kernels that carry them out): per processed box with
- * b active points, n active neighbour points, l = b + n, k_B = min(k, b),
- * r = b - k_B,
- *   2(4 s l^2 - 4/3 l^3) + 8 b s l + 4 s b k_B + 8 r k_B s + 4 r s l
- *   + 2/3 r^3 + 4 r^2 (k_B + n) + 8 r (k_B + n) s  flops,
- * esize (s (2l + 2b + 2n) + s (4b + 2n) + stored) bytes with
- * r k_B + r^2 + 2 r (k_B + n) stored entries; symmetric != 0 halves the
- * two-sided terms (all but the pivoted QR and the LU) and stores one
- * multiplier.  The root adds (4 s t^2 - 4/3 t^3) + 2 s t^2 + t^3 + 2/3 t^3
- * flops and t^2 stored entries, t = |B_t|.  A solve costs 2 flops per stored
- * entry and right-hand side.  Outputs may be NULL.  esize is 4 or 8. */
-rsrs_status rsrs_work_model(const rsrs_tree_t* t, int k, int64_t s, int symmetric, int esize,
-                            double* flops, double* bytes, int64_t* stored_entries);
+/* Tile autotuning of the batched MFMA GEMM behind every factorization and
+ * solve product (not a step of the paper: a property of this implementation).
+ * The candidates are 64 x 64 tiles on 4 waves, 128 x 64 on 4 waves and
+ * 128 x 128 on 8 waves; the triangular (SYRK) form takes only the square
+ * ones.  Launch classes: element type (FP32, FP64), product form, the
+ * launch's count of 64 x 64 output tiles (4^1 .. 4^7, nearest in log scale)
+ * and its contraction length (128 or 1024, nearest in log scale): 196
+ * classes.  Each class is timed on synthetic operands (one warm-up and the
+ * best of three launches per candidate), and a challenger replaces the
+ * built-in rule only when it is 3% faster.  The fastest shape then serves
+ * every later automatic launch of its class in this process.  Without a
+ * table the built-in rule applies: 128 x 128 when the launch has >= 256 such
+ * tiles, else 64 x 64.
+ * cache_path (may be NULL): a table that an earlier call wrote there is
+ * loaded and nothing is timed; otherwise the table is measured on the current
+ * device (about 3 GB of scratch, freed again) and written there.
+ * *entries receives the number of classes and *changed how many of them
+ * differ from the built-in rule (either may be NULL).  The shape never
+ * changes a result: every candidate accumulates each output entry over the
+ * same K slices in the same order.  Call it while no factorization or solve
+ * is running.  Errors: RSRS_E_HIP, RSRS_E_NOMEM. */
+rsrs_status rsrs_gemm_autotune(const char* cache_path, int64_t* entries, int64_t* changed);
+/* Forces one tile shape for every automatic launch: 0 = 64 x 64,
+ * 1 = 128 x 64 (64 x 64 for the triangular form), 2 = 128 x 128.  -1 goes
+ * back to the table (or the built-in rule).  -2 also forgets the table.  For
+ * tests and measurements.  Other values -> RSRS_E_INVALID. */
+rsrs_status rsrs_gemm_tile_override(int shape);
 
 /* ------------------------------------------------------------------------
  * Black-box operator access (Sec. 4, eq. rand_sample_setting).
@@ -278,7 +290,31 @@ typedef struct {
                        column-pivoted QR whose |R_jj| exceeds rank_tol ||[Y_B Z_B]||_F
                        (at most min(k, b)); boxes and their order stay those of the
                        fixed-rank schedule, whose active counts bound the actual ones */
+  int col_subset;   /* 0: every box reads all s sample columns.  1: a box with l active
+                       columns reads only the first s_B = min(s, l + k + p) in its
+                       nullification, ID and extraction (the leading columns of a sample
+                       pair are a sample pair, Sec. 1.1; s_B - l = k + p is the null-space
+                       dimension the count of Sec. 4.5 gives every box); its
+                       sparsification and elimination still update all s columns.  Less
+                       oversampling for boxes with small l: a variant, not the default */
 } rsrs_factor_opts;
+
+/* Algorithmic work of a fixed-rank factorization with s samples and the
+ * options opts (k, p, symmetric, col_subset are read), as the cost analysis
+ * of Sec. 4.5 prices the steps of Algorithm 1 (the method's own operations,
+ * not the kernels that carry them out): per processed box with b active
+ * points, n active neighbour points, l = b + n, k_B = min(k, b), r = b - k_B,
+ * and c = s (c = s_B = min(s, l + k + p) with col_subset) columns read,
+ *   2(4 c l^2 - 4/3 l^3) + 8 b c l + 4 c b k_B + 8 r k_B s + 4 r c l
+ *   + 2/3 r^3 + 4 r^2 (k_B + n) + 8 r (k_B + n) s  flops,
+ * esize (c (2l + 2b) + 2 s n + s (4b + 2n) + stored) bytes with
+ * r k_B + r^2 + 2 r (k_B + n) stored entries; symmetric != 0 halves the
+ * two-sided terms (all but the pivoted QR and the LU) and stores one
+ * multiplier.  The root adds (4 s t^2 - 4/3 t^3) + 2 s t^2 + t^3 + 2/3 t^3
+ * flops and t^2 stored entries, t = |B_t|.  A solve costs 2 flops per stored
+ * entry and right-hand side.  Outputs may be NULL.  esize is 4 or 8. */
+rsrs_status rsrs_work_model(const rsrs_tree_t* t, const rsrs_factor_opts* opts, int64_t s, int esize,
+                            double* flops, double* bytes, int64_t* stored_entries);
 
 rsrs_status rsrs_factor(const rsrs_tree_t* t, rsrs_samples_t* smp, const rsrs_factor_opts* opts,
                         void* stream, rsrs_factor_t** out);

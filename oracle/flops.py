@@ -18,7 +18,9 @@ samples, the general (two-sided) step costs
   8 r (k + n) s           elimination of Y, Z, Omega, Psi
 
 and moves (element size e bytes) e s (2l + 2b + 2n) read, e s (4b + 2n)
-written and e (r k + r^2 + 2 r (k + n)) stored.  The symmetric variant keeps
+written and e (r k + r^2 + 2 r (k + n)) stored.  With per-box column
+subsets the QR, projection, ID and extraction terms and the 2l + 2b read
+panels count s_B = min(s, l + k + p) columns instead of s.  The symmetric variant keeps
 one sketch side: every two-sided term is halved except the ID and the LU.
 The root costs a thin QR with Q of the s x |B_t| panel, the product with Y,
 a triangular solve and an LU.  Solves cost 2 flops per stored entry and
@@ -42,23 +44,26 @@ class BoxWork:
     stored: int
 
 
-def box_work(b: int, n: int, k: int, s: int, symmetric: bool = False, esize: int = 8) -> BoxWork:
+def box_work(b: int, n: int, k: int, s: int, symmetric: bool = False, esize: int = 8,
+             sB: int | None = None) -> BoxWork:
     """Work of one processed box (cost terms of Sec. 4.5 for the steps of
-    Algorithm 1); see the module docstring for the terms."""
+    Algorithm 1); see the module docstring for the terms.  ``sB``: the
+    columns the box's nullification, ID and extraction use (default s)."""
     kb = min(k, b)
     r = b - kb
     l = b + n
     h = 0.5 if symmetric else 1.0
-    f = (h * 2.0 * (4.0 * s * l * l - (4.0 / 3.0) * l ** 3)
-         + h * 8.0 * b * s * l
-         + 4.0 * s * b * kb
+    c = s if sB is None else sB
+    f = (h * 2.0 * (4.0 * c * l * l - (4.0 / 3.0) * l ** 3)
+         + h * 8.0 * b * c * l
+         + 4.0 * c * b * kb
          + h * 8.0 * r * kb * s
-         + h * 4.0 * r * s * l
+         + h * 4.0 * r * c * l
          + (2.0 / 3.0) * r ** 3
          + h * 4.0 * r * r * (kb + n)
          + h * 8.0 * r * (kb + n) * s)
     stored = r * kb + r * r + (1 if symmetric else 2) * r * (kb + n)
-    moved = (h * esize * s * (2 * l + 2 * b + 2 * n)
+    moved = (h * esize * (c * (2 * l + 2 * b) + s * 2 * n)
              + h * esize * s * (4 * b + 2 * n)
              + esize * stored)
     return BoxWork(b=b, n=n, k=kb, r=r, flops=f, bytes_moved=moved, stored=stored)
@@ -81,10 +86,14 @@ class FactorWork:
 
 
 def factor_work(tree: otree.Tree, k: int, s: int, symmetric: bool = False,
-                esize: int = 8) -> FactorWork:
+                esize: int = 8, col_subset: bool = False, p: int | None = None) -> FactorWork:
     """Work of a fixed-rank factorization of ``tree`` with s samples: every
     processed box of the schedule (active counts from the count model of
-    Sec. 4.5 under the box order of ``oracle.tree.schedule``) plus the root."""
+    Sec. 4.5 under the box order of ``oracle.tree.schedule``) plus the root
+    (which uses all s columns).  ``col_subset``: boxes use s_B = min(s, l +
+    k + p) columns (p defaults to k), as ``oracle.rsrs.factor`` does."""
+    if p is None:
+        p = k
     sch = otree.schedule(tree, k)
     out = []
     for classes in sch.order:
@@ -92,7 +101,8 @@ def factor_work(tree: otree.Tree, k: int, s: int, symmetric: bool = False,
             for bx in cls:
                 b = int(sch.b_count[bx])
                 n = int(sch.l_count[bx]) - b
-                out.append(box_work(b, n, k, s, symmetric, esize))
+                sB = min(s, int(sch.l_count[bx]) + k + p) if col_subset else s
+                out.append(box_work(b, n, k, s, symmetric, esize, sB))
     nt = int(sch.root_count)
     flops = sum(w.flops for w in out) + root_work(nt, s)
     stored = sum(w.stored for w in out) + nt * nt

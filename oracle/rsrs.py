@@ -145,7 +145,8 @@ def row_id(M: np.ndarray, k: int, want_r11_min: bool = False, rank_tol: float = 
 
 def factor(tree: otree.Tree, Y, Z, Om, Psi, k: int, p: int | None = None,
            keep_M: bool = False, check_samples: bool = True, on_box=None,
-           symmetric: bool = False, id_mode: str = "sum", rank_tol: float = 0.0) -> Factorization:
+           symmetric: bool = False, id_mode: str = "sum", rank_tol: float = 0.0,
+           col_subset: bool = False) -> Factorization:
     """Algorithm 1 on sketches given in user point order (N x s each).
 
     The caller's arrays are not modified; the oracle works on tree-ordered
@@ -161,7 +162,15 @@ def factor(tree: otree.Tree, Y, Z, Om, Psi, k: int, p: int | None = None,
     ID of M_Y.  ``rank_tol`` > 0 replaces the fixed rank by the numerical
     rank of the ID's sketch relative to ||[Y_B Z_B]||_F (capped at k); the
     boxes and their order stay those of the fixed-rank schedule, and a box
-    may then hold fewer than k (even no) active points when its level runs."""
+    may then hold fewer than k (even no) active points when its level runs.
+
+    ``col_subset``: a box with l = |B_a| + |N_a| active columns uses only the
+    first s_B = min(s, l + k + p) sample columns for its nullification, ID
+    and extraction, while its sparsification and elimination still update
+    all s columns.  The first s_B columns of a sample pair are a sample pair
+    of the same operator (Sec. 1.1), and s_B - l = k + p is the null-space
+    dimension the required sample count of Sec. 4.5 gives every box; the
+    variant trades the oversampling of boxes with small l for work."""
     if id_mode not in ("sum", "concat"):
         raise ValueError("id_mode must be 'sum' or 'concat'")
     if p is None:
@@ -203,8 +212,9 @@ def factor(tree: otree.Tree, Y, Z, Om, Psi, k: int, p: int | None = None,
                 Ba = cur[b]
                 Na = np.sort(np.concatenate([cur[x] for x in nb[b].tolist()])) \
                     if len(nb[b]) else np.zeros(0, dtype=np.int64)
+                sB = min(s, len(Ba) + len(Na) + k + p) if col_subset else s
                 bf = _process_box(b, int(lev), int(sch.colour[b]), Ba, Na, Y, Z, Om, Psi,
-                                  k, keep_M, symmetric, id_mode, rank_tol)
+                                  k, keep_M, symmetric, id_mode, rank_tol, sB)
                 boxes_out.append(bf)
                 cur[b] = bf.S
                 if on_box is not None:
@@ -233,7 +243,10 @@ def _empty_box(box, lev, colour, Ba, Na, S) -> BoxFactor:
 
 
 def _process_box(box, lev, colour, Ba, Na, Y, Z, Om, Psi, k, keep_M, symmetric=False,
-                 id_mode="sum", rank_tol=0.0) -> BoxFactor:
+                 id_mode="sum", rank_tol=0.0, sB=None) -> BoxFactor:
+    """One box of Algorithm 1.  The sketches' first sB columns (all by
+    default) serve the nullification, the ID and the extraction; the
+    sparsification and elimination update every column."""
     b = Ba.shape[0]
     C = np.concatenate([Ba, Na])
     l = C.shape[0]
@@ -242,12 +255,14 @@ def _process_box(box, lev, colour, Ba, Na, Y, Z, Om, Psi, k, keep_M, symmetric=F
         raise InsufficientSamples(f"box {box}: s - l = {s - l} < k = {k}")
     if b == 0:
         return _empty_box(box, lev, colour, Ba, Na, Ba)
+    cs = slice(0, s if sB is None else sB)
     if symmetric:
-        return _process_box_symmetric(box, lev, colour, Ba, Na, C, Y, Om, k, keep_M, rank_tol)
+        return _process_box_symmetric(box, lev, colour, Ba, Na, C, Y, Om, k, keep_M, rank_tol, cs)
     # block nullification, eq. nullYZ (projector form, see module docstring)
-    MY, MZ = nullify(Y[Ba], Om[C]), nullify(Z[Ba], Psi[C])
+    YB, ZB = Y[Ba, cs], Z[Ba, cs]
+    MY, MZ = nullify(YB, Om[C, cs]), nullify(ZB, Psi[C, cs])
     M = MY + MZ if id_mode == "sum" else np.concatenate([MY, MZ], axis=1)
-    norm_yz = float(np.sqrt(np.sum(Y[Ba] ** 2) + np.sum(Z[Ba] ** 2)))
+    norm_yz = float(np.sqrt(np.sum(YB ** 2) + np.sum(ZB ** 2)))
     # row ID of the far-field sketch (Algorithm 1, "Compute the row-ID")
     S_pos, R_pos, T, r11_min, rdiag = row_id(M, k, want_r11_min=True, rank_tol=rank_tol, ref_norm=norm_yz)
     Sg = Ba[S_pos]
@@ -264,8 +279,8 @@ def _process_box(box, lev, colour, Ba, Na, Y, Z, Om, Psi, k, keep_M, symmetric=F
     # block extraction on the updated sketches, columns [R; S; N_a] (eq. pinvYZ)
     Ch = np.concatenate([Rg, Sg, Na])
     r = Rg.shape[0]
-    Xy = _right_pinv_apply(Y[Rg], Om[Ch])          # X_{R,C}
-    Xz = _right_pinv_apply(Z[Rg], Psi[Ch])         # (X_{C,R})^T
+    Xy = _right_pinv_apply(Y[Rg, cs], Om[Ch, cs])          # X_{R,C}
+    Xz = _right_pinv_apply(Z[Rg, cs], Psi[Ch, cs])         # (X_{C,R})^T
     XRR = Xy[:, :r]
     lu = sla.lu_factor(XRR)
     KU = sla.lu_solve(lu, Xy[:, r:])                       # X_RR^{-1} X_{R,SN}
@@ -281,13 +296,15 @@ def _process_box(box, lev, colour, Ba, Na, Y, Z, Om, Psi, k, keep_M, symmetric=F
                      norm_yz=norm_yz, norm_m=float(np.linalg.norm(M)), r11_min=r11_min, rdiag=rdiag)
 
 
-def _process_box_symmetric(box, lev, colour, Ba, Na, C, Y, Om, k, keep_M, rank_tol=0.0) -> BoxFactor:
+def _process_box_symmetric(box, lev, colour, Ba, Na, C, Y, Om, k, keep_M, rank_tol=0.0,
+                           cs=slice(None)) -> BoxFactor:
     """One box of the symmetric variant (module docstring): the Y / Omega side
     of the general step, X_RR symmetrized, K_L = K_U^T.  The ID of M_Y equals
     that of M_Y + M_Z = 2 M_Y, whose R is twice M_Y's: the rank threshold
     rank_tol * ||[Y_B Z_B]|| is halved accordingly."""
-    M = nullify(Y[Ba], Om[C])
-    norm_yz = float(np.sqrt(2.0 * np.sum(Y[Ba] ** 2)))
+    YB = Y[Ba, cs]
+    M = nullify(YB, Om[C, cs])
+    norm_yz = float(np.sqrt(2.0 * np.sum(YB ** 2)))
     S_pos, R_pos, T, r11_min, rdiag = row_id(M, k, want_r11_min=True, rank_tol=rank_tol, ref_norm=0.5 * norm_yz)
     rdiag = 2.0 * rdiag
     Sg = Ba[S_pos]
@@ -301,7 +318,7 @@ def _process_box_symmetric(box, lev, colour, Ba, Na, C, Y, Om, k, keep_M, rank_t
     Om[Sg] += T.T @ Om[Rg]
     Ch = np.concatenate([Rg, Sg, Na])
     r = Rg.shape[0]
-    Xy = _right_pinv_apply(Y[Rg], Om[Ch])
+    Xy = _right_pinv_apply(Y[Rg, cs], Om[Ch, cs])
     XRR = 0.5 * (Xy[:, :r] + Xy[:, :r].T)
     lu = sla.lu_factor(XRR)
     KU = sla.lu_solve(lu, Xy[:, r:])

@@ -124,14 +124,21 @@ int64_t rsrs_samples_required(const rsrs_tree_t* th, int k, int p) {
   return samples_required(th->t, s, k, p);
 }
 
-rsrs_status rsrs_work_model(const rsrs_tree_t* th, int k, int64_t s, int symmetric, int esize,
+rsrs_status rsrs_work_model(const rsrs_tree_t* th, const rsrs_factor_opts* o, int64_t s, int esize,
                             double* flops, double* bytes, int64_t* stored_entries) {
-  if (!th || k < 1 || s < 1 || (esize != 4 && esize != 8)) return invalid("bad tree, k, s or element size");
+  if (!th || !o || o->k < 1 || s < 1 || (esize != 4 && esize != 8)) return invalid("bad tree, options, s or element size");
   Schedule sc;
-  make_schedule(th->t, k, sc);
-  work_model(th->t, sc, k, s, symmetric != 0, esize, flops, bytes, stored_entries);
+  make_schedule(th->t, o->k, sc);
+  const int p = o->p < 0 ? o->k : o->p;
+  work_model(th->t, sc, o->k, s, o->symmetric != 0, esize, o->col_subset ? p : -1, flops, bytes, stored_entries);
   return RSRS_OK;
 }
+
+rsrs_status rsrs_gemm_autotune(const char* cache_path, int64_t* entries, int64_t* changed) {
+  return gemm_autotune(cache_path, entries, changed);
+}
+
+rsrs_status rsrs_gemm_tile_override(int shape) { return gemm_tile_override(shape); }
 
 // ------------------------------------------------------------------ operators
 rsrs_status rsrs_op_create_kernel(int kind, const double* pts, int64_t n, int dim, double param,

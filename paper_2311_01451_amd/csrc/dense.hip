@@ -5,6 +5,7 @@
 #include <utility>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -173,11 +174,86 @@ static rsrs_status plan_forms(const std::vector<GemmDescT<TI, TO>>& descs, size_
   return RSRS_E_UNSUPPORTED;
 }
 
-// Tile choice, measured on MI355X: 128 x 128 tiles on 8 waves (each wave
-// 64 x 32, 4 waves per SIMD) reach 50+ TFLOP/s on the large FP64 products;
-// they are used whenever the batch still yields >= 256 such tiles, otherwise
-// 64 x 64 tiles on 4 waves keep the chip busy; narrow right-hand sides use
-// 64 x 16.
+// ---------------------------------------------------------------- tile autotuner
+// Candidate tile shapes of the automatic choice: 0 = 64 x 64 on 4 waves,
+// 1 = 128 x 64 on 4 waves, 2 = 128 x 128 on 8 waves (each wave of the last
+// two holds a 64 x 32 block).  The triangular SYRK form needs square tiles
+// (0 or 2).  Every shape runs the same K slices (BK depends only on the
+// element type for tiles at least 64 wide) in the same order, and masked
+// slices add exact zeros, so the shape never changes a result bit.
+//
+// Launch classes: element type, form (TA, TB, mode), the launch's number of
+// 64 x 64 output tiles (nearest of 4^1 .. 4^7 in log scale) and its
+// contraction length (nearest of 128 and 1024 in log scale).  The table
+// holds the measured fastest shape of each class; without a table the
+// built-in rule applies (128 x 128 when the launch has >= 256 such tiles).
+namespace {
+constexpr int kTuneForms = 7;
+constexpr int kTuneT = 7;   // 4^1 .. 4^7 tiles of 64 x 64
+constexpr int kTuneK = 2;   // K = 128, 1024
+constexpr int kTuneForm[kTuneForms][3] = {{0, 0, GM_FULL}, {0, 1, GM_FULL},     {1, 0, GM_FULL},
+                                          {0, 1, GM_SYRK_L}, {0, 1, GM_B_NT_LOW}, {0, 0, GM_B_NN_LOW},
+                                          {0, 0, GM_A_LOW}};
+constexpr int kTuneKv[kTuneK] = {128, 1024};
+std::atomic<int> g_tile_override{-1};
+std::atomic<bool> g_tune_ready{false};
+int8_t g_tune[2][kTuneForms][kTuneT][kTuneK];
+
+int tune_form(int ta, int tb, int mode) {
+  for (int f = 0; f < kTuneForms; ++f)
+    if (kTuneForm[f][0] == ta && kTuneForm[f][1] == tb && kTuneForm[f][2] == mode) return f;
+  return -1;
+}
+int tune_tbin(double t64) {
+  const int b = (int)std::lround(std::log(std::max(t64, 1.0)) / std::log(4.0)) - 1;
+  return std::min(kTuneT - 1, std::max(0, b));
+}
+int tune_kbin(int K) { return K >= 362 ? 1 : 0; }
+}  // namespace
+
+template <typename TI, typename TO>
+static int builtin_shape(const std::vector<GemmDescT<TI, TO>>& descs, int mode) {
+  int64_t t128 = 0;
+  for (const auto& d : descs) {
+    if (d.M <= 0 || d.N <= 0) continue;
+    const int64_t tm = (d.M + 127) / 128, tn = (d.N + 127) / 128;
+    t128 += mode == GM_SYRK_L ? tm * (tm + 1) / 2 : tm * tn;
+  }
+  return t128 >= 256 ? 2 : 0;
+}
+
+template <typename TI, typename TO>
+static int chosen_shape(const std::vector<GemmDescT<TI, TO>>& descs, int ta, int tb, int mode) {
+  const int ov = g_tile_override.load(std::memory_order_relaxed);
+  if (ov >= 0) return (mode == GM_SYRK_L && ov == 1) ? 0 : ov;
+  const int f = tune_form(ta, tb, mode);
+  if (f >= 0 && g_tune_ready.load(std::memory_order_acquire)) {
+    double t64 = 0.0;
+    int kmax = 0;
+    for (const auto& d : descs) {
+      if (d.M <= 0 || d.N <= 0) continue;
+      const double tm = (d.M + 63) / 64, tn = (d.N + 63) / 64;
+      t64 += mode == GM_SYRK_L ? tm * (tm + 1) / 2 : tm * tn;
+      kmax = std::max(kmax, d.K);
+    }
+    return g_tune[sizeof(TI) == 4 ? 1 : 0][f][tune_tbin(t64)][tune_kbin(kmax)];
+  }
+  return builtin_shape(descs, mode);
+}
+
+template <typename TI, typename TO>
+static rsrs_status plan_with_shape(int shp, const std::vector<GemmDescT<TI, TO>>& descs, size_t base, int ta,
+                                   int tb, int mode, std::vector<GemmLaunch>& out) {
+  if (shp == 2) return plan_forms<TI, TO, 128, 128, 2, 4>(descs, base, ta, tb, mode, out);
+  if (shp == 1 && mode != GM_SYRK_L) return plan_forms<TI, TO, 128, 64, 2, 2>(descs, base, ta, tb, mode, out);
+  return plan_forms<TI, TO, 64, 64, 2, 2>(descs, base, ta, tb, mode, out);
+}
+
+// Tile choice: the autotuner's table when one was measured or loaded
+// (rsrs_gemm_autotune), else the built-in rule measured on MI355X -- 128 x 128
+// tiles on 8 waves reach 50+ TFLOP/s on the large FP64 products and are
+// used whenever the batch still yields >= 256 such tiles, otherwise 64 x 64
+// tiles on 4 waves keep the chip busy.  Narrow right-hand sides use 64 x 16.
 template <typename TI, typename TO>
 rsrs_status gemm_plan(const std::vector<GemmDescT<TI, TO>>& descs, size_t base, int ta, int tb, int mode,
                       GemmShape shape, const char* site, std::vector<GemmLaunch>& out) {
@@ -190,14 +266,186 @@ rsrs_status gemm_plan(const std::vector<GemmDescT<TI, TO>>& descs, size_t base, 
     if (shape == GS_64x16 && mode == GM_FULL) return plan_forms<TI, TO, 64, 16, 4, 1>(descs, base, ta, tb, mode, out);
   }
   if (shape == GS_64x64_ONLY) return plan_forms<TI, TO, 64, 64, 2, 2>(descs, base, ta, tb, mode, out);
-  int64_t t128 = 0;
-  for (const auto& d : descs) {
-    if (d.M <= 0 || d.N <= 0) continue;
-    const int64_t tm = (d.M + 127) / 128, tn = (d.N + 127) / 128;
-    t128 += mode == GM_SYRK_L ? tm * (tm + 1) / 2 : tm * tn;
+  return plan_with_shape<TI, TO>(chosen_shape(descs, ta, tb, mode), descs, base, ta, tb, mode, out);
+}
+
+// Times shape `shp` on the synthetic launch `descs` (device copy at dd):
+// the best of three launches after one warm-up, in milliseconds.
+template <typename T>
+static rsrs_status time_shape(int shp, const std::vector<GemmDescT<T, T>>& descs, const GemmDescT<T, T>* dd,
+                              int ta, int tb, int mode, hipStream_t st, hipEvent_t e0, hipEvent_t e1,
+                              float* best) {
+  std::vector<GemmLaunch> L;
+  RSRS_TRY(plan_with_shape<T, T>(shp, descs, 0, ta, tb, mode, L));
+  *best = 1e30f;
+  for (int rep = 0; rep < 4; ++rep) {
+    RSRS_HIP(hipEventRecord(e0, st));
+    for (const auto& x : L) {
+      const void* p = dd + x.first;
+      void* args[] = {&p};
+      RSRS_HIP(hipLaunchKernel(x.fn, x.grid, x.block, args, 0, st));
+    }
+    RSRS_HIP(hipEventRecord(e1, st));
+    RSRS_HIP(hipEventSynchronize(e1));
+    float ms = 0.0f;
+    RSRS_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (rep > 0) *best = std::min(*best, ms);
   }
-  if (t128 >= 256) return plan_forms<TI, TO, 128, 128, 2, 4>(descs, base, ta, tb, mode, out);
-  return plan_forms<TI, TO, 64, 64, 2, 2>(descs, base, ta, tb, mode, out);
+  return RSRS_OK;
+}
+
+// One class: nb products of D x D with contraction K, each with its own
+// operands and output (tile count t64 = nb (D / 64)^2, or the lower
+// triangle's for SYRK), every candidate shape timed.
+template <typename T>
+static rsrs_status tune_type(int* changed, hipStream_t st, hipEvent_t e0, hipEvent_t e1, DevBuf& bufA,
+                             DevBuf& bufB, DevBuf& bufC, DevBuf& bufD) {
+  constexpr int ti = sizeof(T) == 4 ? 1 : 0;
+  for (int f = 0; f < kTuneForms; ++f) {
+    const int ta = kTuneForm[f][0], tb = kTuneForm[f][1], mode = kTuneForm[f][2];
+    for (int tt = 0; tt < kTuneT; ++tt) {
+      const int64_t t64 = (int64_t)1 << (2 * (tt + 1));
+      const int64_t per = std::min<int64_t>(t64, 64);
+      const int D = (int)std::lround(64.0 * std::sqrt((double)per));
+      const int64_t nb = t64 / per;
+      for (int kk = 0; kk < kTuneK; ++kk) {
+        const int K = kTuneKv[kk];
+        std::vector<GemmDescT<T, T>> descs;
+        for (int64_t q = 0; q < nb; ++q) {
+          T* A = bufA.as<T>() + q * (int64_t)D * K;
+          T* B = bufB.as<T>() + q * (int64_t)D * K;
+          T* C = bufC.as<T>() + q * (int64_t)D * D;
+          // A: M x K (TA = 0) or K x M (TA = 1); B: N x K (TB = 1) or K x N (TB = 0)
+          descs.push_back(gdescT<T, T>(A, nullptr, ta ? D : K, B, nullptr, tb ? K : D, C, nullptr, D, D, D, K));
+        }
+        GemmDescT<T, T>* dd = reinterpret_cast<GemmDescT<T, T>*>(bufD.p);
+        RSRS_HIP(hipMemcpyAsync(dd, descs.data(), descs.size() * sizeof(descs[0]), hipMemcpyHostToDevice, st));
+        const int def = builtin_shape(descs, mode);
+        int win = -1;
+        float wbest = 1e30f;
+        for (int shp = 0; shp < 3; ++shp) {
+          if (mode == GM_SYRK_L && shp == 1) continue;
+          float ms = 0.0f;
+          RSRS_TRY(time_shape<T>(shp, descs, dd, ta, tb, mode, st, e0, e1, &ms));
+          // a challenger must beat the built-in choice by 3% to replace it
+          const float bar = (win == def || shp == def) ? 0.97f : 1.0f;
+          if (win < 0 || (shp == def ? ms < wbest / bar : ms < wbest * bar)) {
+            win = shp;
+            wbest = ms;
+          }
+        }
+        g_tune[ti][f][tt][kk] = (int8_t)win;
+        if (win != def) ++*changed;
+      }
+    }
+  }
+  return RSRS_OK;
+}
+
+static bool tune_load(const char* path) {
+  FILE* fp = path ? std::fopen(path, "r") : nullptr;
+  if (!fp) return false;
+  int8_t tab[2][kTuneForms][kTuneT][kTuneK];
+  int seen = 0;
+  char line[128];
+  while (std::fgets(line, sizeof(line), fp)) {
+    int a, b, c, d, e;
+    if (line[0] == '#') continue;
+    if (std::sscanf(line, "%d %d %d %d %d", &a, &b, &c, &d, &e) != 5 || a < 0 || a > 1 || b < 0 ||
+        b >= kTuneForms || c < 0 || c >= kTuneT || d < 0 || d >= kTuneK || e < 0 || e > 2 ||
+        (kTuneForm[b][2] == GM_SYRK_L && e == 1)) {
+      std::fclose(fp);
+      return false;
+    }
+    tab[a][b][c][d] = (int8_t)e;
+    ++seen;
+  }
+  std::fclose(fp);
+  if (seen != 2 * kTuneForms * kTuneT * kTuneK) return false;
+  std::memcpy(g_tune, tab, sizeof(tab));
+  return true;
+}
+
+static void tune_save(const char* path) {
+  FILE* fp = std::fopen(path, "w");
+  if (!fp) return;
+  std::fprintf(fp, "# GEMM tile table: fp32 form tiles(4^(i+1)) K(128|1024) shape(0 64x64, 1 128x64, 2 128x128)\n");
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < kTuneForms; ++b)
+      for (int c = 0; c < kTuneT; ++c)
+        for (int d = 0; d < kTuneK; ++d) std::fprintf(fp, "%d %d %d %d %d\n", a, b, c, d, (int)g_tune[a][b][c][d]);
+  std::fclose(fp);
+}
+
+rsrs_status gemm_autotune(const char* cache_path, int64_t* entries, int64_t* changed) {
+  constexpr int64_t total = 2 * kTuneForms * kTuneT * kTuneK;
+  if (entries) *entries = total;
+  if (changed) *changed = 0;
+  auto count_changed = [&]() {
+    // against the built-in rule on the same synthetic classes
+    int64_t c = 0;
+    for (int a = 0; a < 2; ++a)
+      for (int f = 0; f < kTuneForms; ++f)
+        for (int tt = 0; tt < kTuneT; ++tt)
+          for (int kk = 0; kk < kTuneK; ++kk) {
+            const int64_t t64 = (int64_t)1 << (2 * (tt + 1));
+            const int64_t per = std::min<int64_t>(t64, 64);
+            const int64_t D = std::lround(64.0 * std::sqrt((double)per)), nb = t64 / per;
+            const int64_t tm = (D + 127) / 128;
+            const int64_t t128 = nb * (kTuneForm[f][2] == GM_SYRK_L ? tm * (tm + 1) / 2 : tm * tm);
+            c += g_tune[a][f][tt][kk] != (t128 >= 256 ? 2 : 0);
+          }
+    return c;
+  };
+  if (tune_load(cache_path)) {
+    g_tune_ready.store(true, std::memory_order_release);
+    if (changed) *changed = count_changed();
+    return RSRS_OK;
+  }
+  g_tune_ready.store(false, std::memory_order_release);
+  // largest class: 256 products of 512 x 512 with K = 1024
+  const size_t opnd = (size_t)256 * 512 * 1024 * 8, outb = (size_t)256 * 512 * 512 * 8;
+  DevBuf A, B, Cb, Dd;
+  RSRS_TRY(A.alloc(opnd));
+  RSRS_TRY(B.alloc(opnd));
+  RSRS_TRY(Cb.alloc(outb));
+  RSRS_TRY(Dd.alloc((size_t)256 * sizeof(GemmDescT<double, double>)));
+  hipStream_t st = nullptr;
+  RSRS_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  rsrs_status rs = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess ? RSRS_OK : RSRS_E_HIP;
+  // operands: small values, so that no product overflows or goes subnormal
+  if (rs == RSRS_OK && (hipMemsetAsync(A.p, 0x3c, opnd, st) != hipSuccess ||
+                        hipMemsetAsync(B.p, 0x3c, opnd, st) != hipSuccess))
+    rs = RSRS_E_HIP;
+  int ch = 0;
+  if (rs == RSRS_OK) rs = tune_type<float>(&ch, st, e0, e1, A, B, Cb, Dd);
+  if (rs == RSRS_OK) rs = tune_type<double>(&ch, st, e0, e1, A, B, Cb, Dd);
+  if (rs == RSRS_OK && hipStreamSynchronize(st) != hipSuccess) rs = RSRS_E_HIP;
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipStreamDestroy(st);
+  if (rs != RSRS_OK) {
+    if (rs == RSRS_E_HIP) set_error("GEMM autotuning: HIP call failed");
+    return rs;
+  }
+  g_tune_ready.store(true, std::memory_order_release);
+  if (changed) *changed = ch;
+  if (cache_path) tune_save(cache_path);
+  return RSRS_OK;
+}
+
+rsrs_status gemm_tile_override(int shape) {
+  if (shape < -2 || shape > 2) {
+    set_error("tile shape must be -2 (built-in rule), -1 (table or rule), 0, 1 or 2");
+    return RSRS_E_INVALID;
+  }
+  if (shape == -2) {
+    g_tune_ready.store(false, std::memory_order_release);
+    shape = -1;
+  }
+  g_tile_override.store(shape, std::memory_order_relaxed);
+  return RSRS_OK;
 }
 
 rsrs_status gemm_exec(const GemmLaunch& L, const void* descs, size_t desc_bytes, hipStream_t st) {

@@ -64,6 +64,7 @@
 #include <unordered_map>
 
 #include "impl.hpp"
+#include "profile.hpp"
 #include <memory>
 #include <string>
 
@@ -81,6 +82,56 @@ struct Bump {
     return p;
   }
 };
+
+// ---- index lists assembled on the device (fixed rank).  With a fixed rank
+// every count is known from the schedule, so the host tracks where each
+// active list lives (pieces: a range of the index store, or a range of
+// tree positions) and never needs the skeleton values themselves: a class's
+// B_a and N_a slots are filled by one launch of list segments, and its S and
+// R slots by one launch that maps the ID's positions through B_a.  No host
+// synchronisation is needed between classes.
+struct ListSeg {
+  int64_t* dst;
+  const int64_t* src;   // nullptr: write iota, iota + 1, ...
+  int64_t iota, len;
+};
+
+__global__ __launch_bounds__(256) void list_assemble_kernel(const ListSeg* __restrict__ segs) {
+  const ListSeg g = segs[blockIdx.x];
+  for (int64_t j = threadIdx.x; j < g.len; j += 256) g.dst[j] = g.src ? g.src[j] : g.iota + j;
+}
+
+struct SkelSeg {
+  const int64_t* Ba;    // the box's B_a slot
+  const int64_t* pos;   // ID positions: k skeletons ascending, then the b - k others
+  int64_t* S;
+  int64_t* R;
+  int b, k;
+};
+
+__global__ __launch_bounds__(256) void skel_scatter_kernel(const SkelSeg* __restrict__ segs) {
+  const SkelSeg g = segs[blockIdx.x];
+  for (int j = threadIdx.x; j < g.b; j += 256) {
+    // positions come from the ID's own row indices; the clamp only keeps a
+    // corrupted one inside the slot
+    const int64_t p = min(max(g.pos[j], (int64_t)0), (int64_t)(g.b - 1));
+    const int64_t v = g.Ba[p];
+    if (j < g.k) g.S[j] = v;
+    else g.R[j - g.k] = v;
+  }
+}
+
+template <class S>
+rsrs_status launch_segments(Uploader& up, hipStream_t st, const std::vector<S>& segs, void (*kern)(const S*),
+                            const char* tag) {
+  if (segs.empty()) return RSRS_OK;
+  S* d = nullptr;
+  RSRS_TRY(up.put_vec(segs, &d));
+  ProfScope ps(st, tag);
+  hipLaunchKernelGGL(kern, dim3((unsigned)segs.size()), dim3(256), 0, st, d);
+  RSRS_HIP(hipGetLastError());
+  return RSRS_OK;
+}
 
 // A second stream and the two events that order it against the main one;
 // the destructor drains it, so no kernel outlives the workspace it reads.
@@ -257,6 +308,12 @@ struct Job {
   bool sym = false;             // symmetric variant: the Y / Omega side only
   bool concat = false;          // ID of [M_Y, M_Z] instead of M_Y + M_Z (general variant)
   double rank_tol = 0.0;        // > 0: k_B from the pivots' size (storage planned for k_B = 0)
+  bool col_subset = false;      // a box reads its first s_B = min(s, l + k + p) sample columns
+  bool deferred = false;        // fixed rank in every problem: lists assembled on the device
+  // active list as pieces: src != nullptr is a range of the index store,
+  // else the tree positions iota .. iota + len - 1
+  struct Piece { const int64_t* src; int64_t iota, len; };
+  std::vector<std::vector<Piece>> pcur, prem;
   Schedule sch;
   std::unique_ptr<rsrs_factor_t> F;
   T *Y = nullptr, *Z = nullptr, *Om = nullptr, *Psi = nullptr;
@@ -274,6 +331,9 @@ struct Job {
   double flops_b = 0.0;   // phase B's share (accumulated by the enqueue thread)
 
   const Tree& tree() const { return th->t; }
+  // Sample columns a box with l active columns reads in its nullification,
+  // ID and extraction; its updates cover all s.
+  int sB(int64_t l) const { return (int)(col_subset ? std::min<int64_t>(s, l + k + p) : s); }
   std::vector<int64_t> leaf_range(int64_t b) const {
     std::vector<int64_t> v((size_t)tree().npts(b));
     std::iota(v.begin(), v.end(), tree().pt_begin[b]);
@@ -287,7 +347,19 @@ struct Job {
     for (size_t i = 0; i < lb.size(); ++i) {
       const int64_t b = lb[i];
       pos[b] = i;
-      if (t.is_leaf[b]) {
+      if (deferred) {
+        std::vector<Piece> v;
+        if (t.is_leaf[b]) {
+          if (t.npts(b) > 0) v.push_back(Piece{nullptr, t.pt_begin[b], t.npts(b)});
+        } else {
+          // children own disjoint, ascending point ranges: in range order
+          // their sorted lists concatenate to a sorted list
+          std::vector<int64_t> ch(t.child_ids.begin() + t.child_off[b], t.child_ids.begin() + t.child_off[b + 1]);
+          std::sort(ch.begin(), ch.end(), [&](int64_t x, int64_t y) { return t.pt_begin[x] < t.pt_begin[y]; });
+          for (int64_t c : ch) v.insert(v.end(), prem[c].begin(), prem[c].end());
+        }
+        pcur[b] = std::move(v);
+      } else if (t.is_leaf[b]) {
         cur[b] = leaf_range(b);
       } else {
         std::vector<int64_t> v;
@@ -301,7 +373,10 @@ struct Job {
     }
   }
   void leave_level() {
-    for (int64_t b : tree().level_boxes[sch.levels[li]]) remaining[b] = cur[b];
+    for (int64_t b : tree().level_boxes[sch.levels[li]]) {
+      if (deferred) prem[b] = pcur[b];
+      else remaining[b] = cur[b];
+    }
     ++li;
     ci = 0;
   }
@@ -312,6 +387,24 @@ struct Job {
       leave_level();
     }
     if (li < sch.levels.size() && ci == 0) enter_level();
+  }
+  // pieces of a neighbour's active list (a coarser neighbour is a leaf that
+  // keeps all its points)
+  const std::vector<Piece>& pieces_of(int64_t x) {
+    if (tree().level[x] < sch.levels[li] && pcur[x].empty() && tree().npts(x) > 0)
+      pcur[x] = {Piece{nullptr, tree().pt_begin[x], tree().npts(x)}};
+    return pcur[x];
+  }
+  // segments writing the pieces to dst (at most cap entries); returns the count
+  int64_t emit(std::vector<ListSeg>& segs, int64_t* dst, const std::vector<Piece>& pc, int64_t cap) const {
+    int64_t n = 0;
+    for (const Piece& q : pc) {
+      if (q.len <= 0) continue;
+      if (n + q.len > cap) return cap + 1;
+      segs.push_back(ListSeg{dst + n, q.src, q.iota, q.len});
+      n += q.len;
+    }
+    return n;
   }
   const std::vector<int64_t>& active_of(int64_t x) {
     if (tree().level[x] < sch.levels[li] && cur[x].empty()) cur[x] = leaf_range(x);
@@ -332,6 +425,7 @@ rsrs_status job_init(Job<T>& J, const rsrs_tree_t* th, rsrs_samples_t* smp,
   J.sym = o->symmetric != 0;
   J.concat = !J.sym && o->id_mode == RSRS_ID_CONCAT;
   J.rank_tol = o->rank_tol;
+  J.col_subset = o->col_subset != 0;
   const bool adaptive = J.rank_tol > 0.0;
   const Tree& t = th->t;
   const int k = J.k;
@@ -421,7 +515,8 @@ rsrs_status job_init(Job<T>& J, const rsrs_tree_t* th, rsrs_samples_t* smp,
   J.iS = F->istore.template as<int64_t>();
   J.cur.assign((size_t)t.nbox(), {});
   J.remaining.assign((size_t)t.nbox(), {});
-  J.settle();
+  J.pcur.assign((size_t)t.nbox(), {});
+  J.prem.assign((size_t)t.nbox(), {});
   return RSRS_OK;
 }
 
@@ -520,15 +615,39 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
   HostBuf hpos;   // skeleton positions of a class, read back, then the flag word
   RSRS_TRY(pool_alloc(hpos, (pos_max + 1) * 8));
   int* hflag_slot = reinterpret_cast<int*>(hpos.as<int64_t>() + pos_max);
+  const bool deferred = !jobs.empty() && jobs[0].deferred;
   for (size_t t = 0; t < nsteps; ++t) {
     // ---- host index lists and factor-store uploads (Ba, Na, Na copy)
     std::vector<Item<T>> items;
     std::vector<int64_t> nbs;
+    std::vector<ListSeg> lsegs;
     for (auto& J : jobs) {
       if (t >= J.F->groups.size()) continue;
       const Tree& tr = J.tree();
       const Group& g = J.F->groups[t];
       const int lev = J.sch.levels[J.li];
+      if (deferred) {
+        // the class's B_a, N_a and second N_a slots as segments of the
+        // neighbours' and its own pieces (counts are the schedule's)
+        for (int64_t q = 0; q < g.count; ++q) {
+          BoxRec& R = J.F->boxes[g.first + q];
+          const size_t ip = J.pos.at(R.box);
+          nbs.assign(tr.nb_ids[lev].begin() + tr.nb_off[lev][ip], tr.nb_ids[lev].begin() + tr.nb_off[lev][ip + 1]);
+          std::sort(nbs.begin(), nbs.end(), [&](int64_t x, int64_t y) { return tr.pt_begin[x] < tr.pt_begin[y]; });
+          std::vector<typename Job<T>::Piece> na;
+          for (int64_t x : nbs) {
+            const auto& pc = J.pieces_of(x);
+            na.insert(na.end(), pc.begin(), pc.end());
+          }
+          if (J.emit(lsegs, J.iS + R.oBa, J.pcur[R.box], R.b) != R.b ||
+              J.emit(lsegs, J.iS + R.oNa, na, R.n) != R.n || J.emit(lsegs, J.iS + R.oBa + R.b, na, R.n) != R.n) {
+            set_error("internal: active sets disagree with the count model");
+            return RSRS_E_INVALID;
+          }
+          items.push_back(Item<T>{&J, &R, {}});
+        }
+        continue;
+      }
       for (int64_t q = 0; q < g.count; ++q) {
         BoxRec& R = J.F->boxes[g.first + q];
         const size_t ip = J.pos.at(R.box);
@@ -577,6 +696,7 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
       // are filled and uploaded again once the skeletons are known)
       RSRS_TRY(upload_class_lists(J, g, st));
     }
+    RSRS_TRY(launch_segments<ListSeg>(up, st, lsegs, list_assemble_kernel, "list_assemble"));
     // ---- workspace: the part read by the extraction alternates between two
     // buffers, the one it reads may still be in use by the previous class
     Bump bump{ws.as<char>(), 0, ws.bytes};
@@ -646,13 +766,14 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
         const int l = (int)(R.b + R.n);
         const int64_t* idxC = J.iS + R.oBa;
         // the Gram matrix is factored in place: L^{-1} lands where it is used
-        gd.push_back(gdescT<T, T>(J.Om, idxC, J.sld, J.Om, idxC, J.sld, w.LO, nullptr, w.lp, l, l, (int)J.s));
+        const int sb = J.sB(l);
+        gd.push_back(gdescT<T, T>(J.Om, idxC, J.sld, J.Om, idxC, J.sld, w.LO, nullptr, w.lp, l, l, sb));
         cm.push_back(CholMatT<T>{w.LO, w.GO, w.lp, l});
         if (!J.sym) {
-          gd.push_back(gdescT<T, T>(J.Psi, idxC, J.sld, J.Psi, idxC, J.sld, w.LP, nullptr, w.lp, l, l, (int)J.s));
+          gd.push_back(gdescT<T, T>(J.Psi, idxC, J.sld, J.Psi, idxC, J.sld, w.LP, nullptr, w.lp, l, l, sb));
           cm.push_back(CholMatT<T>{w.LP, w.GP, w.lp, l});
         }
-        const double dl = l, db = (double)R.b, ds = (double)J.s, sides = J.sym ? 1.0 : 2.0;
+        const double dl = l, db = (double)R.b, ds = (double)sb, sides = J.sym ? 1.0 : 2.0;
         it.J->flops += sides * (dl * dl * ds                              // Gram matrices
                                 + (2.0 / 3.0) * dl * dl * dl              // Cholesky + inverse factor
                                 + (1.0 + J.reproject) * (4.0 * db * dl * ds + 2.0 * db * dl * dl));  // projections
@@ -666,8 +787,8 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
       RSRS_TRY(worker.join());   // phase B of the previous class is enqueued
       RSRS_HIP(hipStreamWaitEvent(st, side.eB, 0));
     }
-    for (auto& it : items)   // [M_Y, M_Z] rows: the columns s..sld of each half stay zero
-      if (it.J->concat && it.J->sld > it.J->s)
+    for (auto& it : items)   // [M_Y, M_Z] rows: the columns s_B..sld of each half stay zero
+      if (it.J->concat && it.J->sld > it.J->sB(it.R->b + it.R->n))
         RSRS_HIP(hipMemsetAsync(it.w.MY, 0, (size_t)(2 * it.R->b * it.J->sld) * sizeof(T), st));
     for (int pass = 0; pass <= 1; ++pass) {
       std::vector<GemmDescT<T, T>> gp, gw, gx, gm;
@@ -677,7 +798,7 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
         if (pass > J.reproject) continue;
         const BoxRec& R = *it.R;
         const BoxWs<T>& w = it.w;
-        const int l = (int)(R.b + R.n), b = (int)R.b;
+        const int l = (int)(R.b + R.n), b = (int)R.b, sb = J.sB(l);
         const int64_t* idxB = J.iS + R.oBa;
         const int64_t* idxC = J.iS + R.oBa;
         const int64_t sld = J.sld;
@@ -691,16 +812,16 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
           T* Lb = side ? w.LP : w.LO;
           T* Xout = pass == 0 ? Xb : Pb;   // second pass: correction into P
           if (pass == 0)
-            gp.push_back(gdescT<T, T>(Ysd, idxB, sld, Tst, idxC, sld, Pb, nullptr, w.lp, b, l, (int)J.s));
+            gp.push_back(gdescT<T, T>(Ysd, idxB, sld, Tst, idxC, sld, Pb, nullptr, w.lp, b, l, sb));
           else
-            gp.push_back(gdescT<T, T>(Mb, nullptr, w.mld, Tst, idxC, sld, Pb, nullptr, w.lp, b, l, (int)J.s));
+            gp.push_back(gdescT<T, T>(Mb, nullptr, w.mld, Tst, idxC, sld, Pb, nullptr, w.lp, b, l, sb));
           gw.push_back(gdescT<T, T>(Pb, nullptr, w.lp, Lb, nullptr, w.lp, Wb, nullptr, w.lp, b, l, l));
           gx.push_back(gdescT<T, T>(Wb, nullptr, w.lp, Lb, nullptr, w.lp, Xout, nullptr, w.lp, b, l, l));
           if (pass == 0)
-            gm.push_back(gdescT<T, T>(Xout, nullptr, w.lp, Tst, idxC, sld, Mb, nullptr, w.mld, b, (int)J.s, l,
+            gm.push_back(gdescT<T, T>(Xout, nullptr, w.lp, Tst, idxC, sld, Mb, nullptr, w.mld, b, sb, l,
                                       -1.0, 1.0, Ysd, idxB, sld));
           else
-            gm.push_back(gdescT<T, T>(Xout, nullptr, w.lp, Tst, idxC, sld, Mb, nullptr, w.mld, b, (int)J.s, l,
+            gm.push_back(gdescT<T, T>(Xout, nullptr, w.lp, Tst, idxC, sld, Mb, nullptr, w.mld, b, sb, l,
                                       -1.0, 1.0));
           if (pass == 1) acc.push_back(Copy2DT<T, T>{Pb, Xb, w.lp, w.lp, b, l, 1.0, 1, 0});
         }
@@ -734,59 +855,81 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
         }
         e.norms = w.norms; e.sel = w.sel; e.Rc = w.Rc; e.piv = w.piv;
         e.Spos = w.Spos; e.kB = w.kB;
-        e.b = (int)R.b; e.s = (int)(J.concat ? J.sld + J.s : J.s); e.k = (int)R.k;
+        const int sb = J.sB(R.b + R.n);
+        e.b = (int)R.b; e.s = (int)(J.concat ? J.sld + sb : sb); e.k = (int)R.k;
         // rank tolerance: |R_jj|^2 against rank_tol^2 ||[Y_B Z_B]||_F^2, whose
         // row sums the first launch gathers from the sketches (Y_B only in
         // the symmetric variant, whose R is half that of M_Y + M_Z = 2 M_Y)
         e.tol2 = J.rank_tol > 0.0 ? J.rank_tol * J.rank_tol * (J.sym ? 0.25 * 2.0 : 1.0) : 0.0;
         e.rowyz = w.norms + 2 * R.b;
-        e.Yg = J.Y; e.Zg = J.sym ? nullptr : J.Z; e.idx = J.iS + R.oBa; e.ldy = J.sld; e.sy = (int)J.s;
+        e.Yg = J.Y; e.Zg = J.sym ? nullptr : J.Z; e.idx = J.iS + R.oBa; e.ldy = J.sld; e.sy = sb;
         idd.push_back(e);
         it.J->flops += 4.0 * R.b * e.s * R.k;
       }
       RSRS_TRY(id_run(up, st, idd, mixed));
     }
-    // ---- skeleton sets back to the host (one copy, positions back to back)
-    // and the flag word behind them, so that one synchronisation brings both
-    *hflag_slot = 0;
-    RSRS_HIP(hipMemcpyAsync(hpos.as<int64_t>(), posall, (size_t)npos * 8, hipMemcpyDeviceToHost, st));
-    RSRS_HIP(hipMemcpyAsync(hflag_slot, flag, sizeof(int), hipMemcpyDeviceToHost, st));
-    RSRS_TRY(up.reset());
-    {
-      const int hflag = *hflag_slot;
-      if (hflag & 1) {
-        set_error("Gram matrix of a test-matrix panel is not positive definite (rank-deficient panel)");
-        return RSRS_E_SINGULAR;
-      }
-    }
-    // ---- phase B: global R / S / SN lists (k_B of each box from the ID)
-    {
-      int64_t o2 = 0;
+    if (deferred) {
+      // ---- S and R slots from the ID's positions, on the device; the
+      // skeleton counts are the schedule's (k_B = min(k, b))
+      std::vector<SkelSeg> ss;
       for (auto& it : items) {
         Job<T>& J = *it.J;
-        BoxRec& R = *it.R;
-        const int64_t* sp = hpos.as<int64_t>() + o2;
-        const int64_t kb = sp[R.b];
-        if (kb < 0 || kb > R.k) {
-          set_error("internal: skeleton count out of range");
-          return RSRS_E_INVALID;
-        }
-        R.k = kb;
-        R.r = R.b - kb;
-        R.oS = R.oNa - kb;          // S ends where N_a begins: S || N_a = SN
-        it.w.Rpos = it.w.Spos + kb;
-        const int64_t* rp = sp + kb;
-        std::vector<int64_t> Sg((size_t)kb), Rg((size_t)R.r);
-        const int64_t* ba = J.hI + R.oBa;   // B_a as staged for the upload
-        for (int64_t j = 0; j < kb; ++j) Sg[j] = ba[sp[j]];
-        for (int64_t j = 0; j < R.r; ++j) Rg[j] = ba[rp[j]];
-        std::memcpy(J.hI + R.oR, Rg.data(), R.r * 8);
-        std::memcpy(J.hI + R.oS, Sg.data(), (size_t)kb * 8);
-        J.cur[R.box] = std::move(Sg);
-        o2 += R.b + 1;
+        const BoxRec& R = *it.R;
+        ss.push_back(SkelSeg{J.iS + R.oBa, it.w.Spos, J.iS + R.oS, J.iS + R.oR, (int)R.b, (int)R.k});
       }
-      for (auto& J : jobs)
-        if (t < J.F->groups.size()) RSRS_TRY(upload_class_lists(J, J.F->groups[t], st));
+      RSRS_TRY(launch_segments<SkelSeg>(up, st, ss, skel_scatter_kernel, "skel_scatter"));
+      for (auto& it : items) {
+        Job<T>& J = *it.J;
+        const BoxRec& R = *it.R;
+        J.pcur[R.box].clear();
+        if (R.k > 0) J.pcur[R.box].push_back(typename Job<T>::Piece{J.iS + R.oS, 0, R.k});
+      }
+    }
+    if (!deferred) {
+      // ---- skeleton sets back to the host (one copy, positions back to back)
+      // and the flag word behind them, so that one synchronisation brings both
+      *hflag_slot = 0;
+      RSRS_HIP(hipMemcpyAsync(hpos.as<int64_t>(), posall, (size_t)npos * 8, hipMemcpyDeviceToHost, st));
+      RSRS_HIP(hipMemcpyAsync(hflag_slot, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+      RSRS_TRY(up.reset());
+      {
+        const int hflag = *hflag_slot;
+        if (hflag & 1) {
+          set_error("Gram matrix of a test-matrix panel is not positive definite (rank-deficient panel)");
+          return RSRS_E_SINGULAR;
+        }
+      }
+      // ---- phase B: global R / S / SN lists (k_B of each box from the ID)
+      {
+        int64_t o2 = 0;
+        for (auto& it : items) {
+          Job<T>& J = *it.J;
+          BoxRec& R = *it.R;
+          const int64_t* sp = hpos.as<int64_t>() + o2;
+          const int64_t kb = sp[R.b];
+          if (kb < 0 || kb > R.k) {
+            set_error("internal: skeleton count out of range");
+            return RSRS_E_INVALID;
+          }
+          R.k = kb;
+          R.r = R.b - kb;
+          R.oS = R.oNa - kb;          // S ends where N_a begins: S || N_a = SN
+          it.w.Rpos = it.w.Spos + kb;
+          const int64_t* rp = sp + kb;
+          std::vector<int64_t> Sg((size_t)kb), Rg((size_t)R.r);
+          const int64_t* ba = J.hI + R.oBa;   // B_a as staged for the upload
+          for (int64_t j = 0; j < kb; ++j) Sg[j] = ba[sp[j]];
+          for (int64_t j = 0; j < R.r; ++j) Rg[j] = ba[rp[j]];
+          std::memcpy(J.hI + R.oR, Rg.data(), R.r * 8);
+          std::memcpy(J.hI + R.oS, Sg.data(), (size_t)kb * 8);
+          J.cur[R.box] = std::move(Sg);
+          o2 += R.b + 1;
+        }
+        for (auto& J : jobs)
+          if (t < J.F->groups.size()) RSRS_TRY(upload_class_lists(J, J.F->groups[t], st));
+      }
+    }
+    {
       if constexpr (mixed) {   // T rounded into the factor store
         std::vector<Copy2DT<double, T>> tc;
         for (auto& it : items) {
@@ -954,11 +1097,28 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
       Job<T>* job;
     };
     std::vector<Root> roots;
+    std::vector<ListSeg> rsegs;
     for (auto& J : jobs) {
       rsrs_factor_t* F = J.F.get();
       const Tree& tr = J.tree();
       std::vector<int64_t> Bt;
-      if (tr.nlevels == 0) {
+      if (deferred) {
+        // B_t: the level-1 boxes' remaining pieces in point-range order
+        std::vector<typename Job<T>::Piece> pc;
+        if (tr.nlevels == 0) {
+          pc.push_back(typename Job<T>::Piece{nullptr, 0, J.n});
+        } else {
+          std::vector<int64_t> top(tr.level_boxes[1].begin(), tr.level_boxes[1].end());
+          std::sort(top.begin(), top.end(), [&](int64_t x, int64_t y) { return tr.pt_begin[x] < tr.pt_begin[y]; });
+          for (int64_t b : top) pc.insert(pc.end(), J.prem[b].begin(), J.prem[b].end());
+        }
+        if (J.emit(rsegs, J.iS + F->oBt, pc, F->nt) != F->nt) {
+          set_error("internal: root size mismatch");
+          return RSRS_E_INVALID;
+        }
+        RSRS_TRY(launch_segments<ListSeg>(up, st, rsegs, list_assemble_kernel, "list_assemble"));
+        rsegs.clear();
+      } else if (tr.nlevels == 0) {
         Bt.resize((size_t)J.n);
         std::iota(Bt.begin(), Bt.end(), 0);
       } else {
@@ -966,11 +1126,11 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
         std::sort(Bt.begin(), Bt.end());
       }
       // with a rank tolerance the schedule's root count bounds the actual one
-      if (J.rank_tol > 0.0 ? (int64_t)Bt.size() > F->nt : (int64_t)Bt.size() != F->nt) {
+      if (!deferred && (J.rank_tol > 0.0 ? (int64_t)Bt.size() > F->nt : (int64_t)Bt.size() != F->nt)) {
         set_error("internal: root size mismatch");
         return RSRS_E_INVALID;
       }
-      F->nt = (int64_t)Bt.size();
+      if (!deferred) F->nt = (int64_t)Bt.size();
       if (F->nt == 0) continue;   // every point eliminated: no root block
       Root R{};
       R.job = &J;
@@ -978,8 +1138,10 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
       R.s = (int)J.s;
       R.reproject = J.reproject;
       const int nt = R.nt;
-      std::memcpy(J.hI + F->oBt, Bt.data(), (size_t)nt * 8);
-      RSRS_HIP(hipMemcpyAsync(J.iS + F->oBt, J.hI + F->oBt, (size_t)nt * 8, hipMemcpyHostToDevice, st));
+      if (!deferred) {
+        std::memcpy(J.hI + F->oBt, Bt.data(), (size_t)nt * 8);
+        RSRS_HIP(hipMemcpyAsync(J.iS + F->oBt, J.hI + F->oBt, (size_t)nt * 8, hipMemcpyHostToDevice, st));
+      }
       const int64_t* iBt = J.iS + F->oBt;
       R.ntp = round_up(nt, 16);
       R.rp = round_up(J.s, 16);
@@ -1069,7 +1231,11 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
   {
     int hflag = 0;
     RSRS_HIP(hipMemcpy(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost));
-    if (hflag & 1) { set_error("Gram matrix of the root panel is not positive definite"); return RSRS_E_SINGULAR; }
+    if (hflag & 1) {
+      set_error(deferred ? "Gram matrix of a test-matrix panel or of the root panel is not positive definite"
+                         : "Gram matrix of the root panel is not positive definite");
+      return RSRS_E_SINGULAR;
+    }
     if (hflag & 2) { set_error("singular pivot block X_RR or root block"); return RSRS_E_SINGULAR; }
   }
   const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -1104,6 +1270,14 @@ rsrs_status factor_batch_t(int64_t nprob, const rsrs_tree_t* const* trees, rsrs_
       return r;
     }
   }
+  // index lists on the device unless some problem's counts depend on its
+  // data (rank tolerance): then every class reads its skeletons back
+  bool deferred = true;
+  for (const auto& J : jobs) deferred = deferred && !(J.rank_tol > 0.0);
+  for (auto& J : jobs) {
+    J.deferred = deferred;
+    J.settle();
+  }
   RSRS_TRY(factor_many<T>(jobs, st));
   for (int64_t i = 0; i < nprob; ++i) out[i] = jobs[i].F.release();
   return RSRS_OK;
@@ -1128,6 +1302,10 @@ rsrs_status factor_batch_impl(int64_t nprob, const rsrs_tree_t* const* trees, rs
     if (o->reproject < 0 || o->reproject > 1) { set_error(who + "reproject must be 0 or 1"); return RSRS_E_INVALID; }
     if (o->id_mode != RSRS_ID_SUM && o->id_mode != RSRS_ID_CONCAT) {
       set_error(who + "id_mode must be RSRS_ID_SUM or RSRS_ID_CONCAT");
+      return RSRS_E_INVALID;
+    }
+    if (o->col_subset != 0 && o->col_subset != 1) {
+      set_error(who + "col_subset must be 0 or 1");
       return RSRS_E_INVALID;
     }
     if (!(o->rank_tol >= 0.0) || !std::isfinite(o->rank_tol)) {

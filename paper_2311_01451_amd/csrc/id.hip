@@ -365,65 +365,90 @@ __global__ __launch_bounds__(256) void id_finalize_kernel(const IdDesc* __restri
   }
 }
 
+// Per step, the descriptors [0, npair) take the paired FP32 layout and the
+// rest the one-column layout.  The one-column forms (16 or 40 registers, or
+// the streaming kernel) sum every dot product and norm in the same order,
+// so which of them runs does not change a bit; the paired layout sums in
+// another order, so a box takes it according to its own row length and
+// alignment only (never according to the other boxes of the launch).
 template <typename S>
-static void id_launch(hipStream_t st, const IdDesc* de, unsigned nb, int bmax, int kmax, int smax, bool pairs,
-                      double fstep, double bstep) {
+static void id_launch(hipStream_t st, const IdDesc* de, unsigned npair, unsigned nsingle, int bpair, int bsingle,
+                      int kmax, int ssingle, double fstep, double bstep) {
+  const unsigned nb = npair + nsingle;
   {
     ProfScope ps(st, "id_init", 0.0, bstep);
-    hipLaunchKernelGGL(id_init_kernel<S>, dim3((unsigned)bmax, nb), dim3(64), 0, st, de);
+    hipLaunchKernelGGL(id_init_kernel<S>, dim3((unsigned)std::max(bpair, bsingle), nb), dim3(64), 0, st, de);
   }
-  // register variant when every row fits (the summation order of the dot
-  // product and norm is then fixed by the lane layout, the same for all s);
-  // FP32 rows of even length and leading dimension move two columns per load
   // The steps are many short launches: when measured, each carries its own
   // start / stop events instead of two separate event records.
-  const int nchunk = (smax + 63) / 64;
+  const int nchunk = (ssingle + 63) / 64;
   for (int j = 0; j < kmax; ++j) {
     hipEvent_t ea, eb;
     const int slot = prof_begin_ext("id_step", &ea, &eb);
-    const unsigned g4 = (unsigned)((bmax + 3) / 4);
-    if (pairs && nchunk <= 40)
-      hipExtLaunchKernelGGL((id_step_reg_kernel<S, 20, (sizeof(S) == 4 ? 2 : 1)>), dim3(g4, nb), dim3(256), 0, st,
-                            ea, eb, 0, de, j);
-    else if (nchunk <= 16)
-      hipExtLaunchKernelGGL((id_step_reg_kernel<S, 16, 1>), dim3(g4, nb), dim3(256), 0, st, ea, eb, 0, de, j);
-    else if (nchunk <= 40)
-      hipExtLaunchKernelGGL((id_step_reg_kernel<S, 40, 1>), dim3(g4, nb), dim3(256), 0, st, ea, eb, 0, de, j);
-    else
-      hipExtLaunchKernelGGL(id_step_kernel<S>, dim3((unsigned)bmax, nb), dim3(64), 0, st, ea, eb, 0, de, j);
+    if (npair > 0) {
+      const unsigned g4 = (unsigned)((bpair + 3) / 4);
+      hipExtLaunchKernelGGL((id_step_reg_kernel<S, 20, (sizeof(S) == 4 ? 2 : 1)>), dim3(g4, npair), dim3(256), 0, st,
+                            ea, nsingle > 0 ? nullptr : eb, 0, de, j);
+    }
+    if (nsingle > 0) {
+      const IdDesc* d1 = de + npair;
+      hipEvent_t e0 = npair > 0 ? nullptr : ea;
+      const unsigned g4 = (unsigned)((bsingle + 3) / 4);
+      if (nchunk <= 16)
+        hipExtLaunchKernelGGL((id_step_reg_kernel<S, 16, 1>), dim3(g4, nsingle), dim3(256), 0, st, e0, eb, 0, d1, j);
+      else if (nchunk <= 40)
+        hipExtLaunchKernelGGL((id_step_reg_kernel<S, 40, 1>), dim3(g4, nsingle), dim3(256), 0, st, e0, eb, 0, d1, j);
+      else
+        hipExtLaunchKernelGGL(id_step_kernel<S>, dim3((unsigned)bsingle, nsingle), dim3(64), 0, st, e0, eb, 0, d1, j);
+    }
     if (slot >= 0) prof_end_ext(slot, "id_step", fstep, bstep);
   }
 }
 
 rsrs_status id_run(Uploader& up, hipStream_t st, const std::vector<IdDesc>& e, bool fp32) {
   if (e.empty()) return RSRS_OK;
-  int bmax = 0, kmax = 0, smax = 0;
+  int kmax = 0;
   for (const auto& x : e) {
-    smax = std::max(smax, x.s);
     if (x.k > 256 || x.b > 4352 || x.k > x.b || x.k < 1) {
       set_error("ID sizes out of range (need 1 <= k <= b <= 4352, k <= 256)");
       return RSRS_E_UNSUPPORTED;
     }
-    bmax = std::max(bmax, x.b);
     kmax = std::max(kmax, x.k);
   }
+  // paired FP32 rows: even length and leading dimension, 8-byte aligned,
+  // and short enough for 20 pairs per lane
+  auto paired = [&](const IdDesc& x) {
+    return fp32 && x.s % 2 == 0 && x.ldm % 2 == 0 && ((uintptr_t)x.M & 7) == 0 && (x.s + 63) / 64 <= 40;
+  };
+  std::vector<IdDesc> ord;
+  ord.reserve(e.size());
+  int bpair = 0, bsingle = 0, ssingle = 0;
+  for (const auto& x : e)
+    if (paired(x)) {
+      ord.push_back(x);
+      bpair = std::max(bpair, x.b);
+    }
+  const unsigned npair = (unsigned)ord.size();
+  for (const auto& x : e)
+    if (!paired(x)) {
+      ord.push_back(x);
+      bsingle = std::max(bsingle, x.b);
+      ssingle = std::max(ssingle, x.s);
+    }
+  const unsigned nsingle = (unsigned)(ord.size() - npair);
   IdDesc* de = nullptr;
-  RSRS_TRY(up.put_vec(e, &de));
-  const unsigned nb = (unsigned)e.size();
+  RSRS_TRY(up.put_vec(ord, &de));
   const double esz = fp32 ? 4.0 : 8.0;
   double fstep = 0.0, bstep = 0.0;
   for (const auto& x : e) {
     fstep += 4.0 * x.b * x.s;
     bstep += 2.0 * esz * x.b * x.s;   // read and write every row
   }
-  bool pairs = fp32;
-  for (const auto& x : e)
-    pairs = pairs && x.s % 2 == 0 && x.ldm % 2 == 0 && ((uintptr_t)x.M & 7) == 0;
-  if (fp32) id_launch<float>(st, de, nb, bmax, kmax, smax, pairs, fstep, bstep);
-  else id_launch<double>(st, de, nb, bmax, kmax, smax, false, fstep, bstep);
+  if (fp32) id_launch<float>(st, de, npair, nsingle, bpair, bsingle, kmax, ssingle, fstep, bstep);
+  else id_launch<double>(st, de, npair, nsingle, bpair, bsingle, kmax, ssingle, fstep, bstep);
   {
     ProfScope ps(st, "id_finalize");
-    hipLaunchKernelGGL(id_finalize_kernel, dim3(nb), dim3(256), 0, st, de);
+    hipLaunchKernelGGL(id_finalize_kernel, dim3((unsigned)ord.size()), dim3(256), 0, st, de);
   }
   RSRS_HIP(hipGetLastError());
   return RSRS_OK;

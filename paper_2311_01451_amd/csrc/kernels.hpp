@@ -51,6 +51,10 @@ struct GemmLaunch {
 template <typename TI, typename TO>
 rsrs_status gemm_plan(const std::vector<GemmDescT<TI, TO>>& descs, size_t base, int ta, int tb, int mode,
                       GemmShape shape, const char* site, std::vector<GemmLaunch>& out);
+// Tile autotuning of the automatic choice (see dense.hip) and a forced shape
+// for every automatic launch (-1: table or rule, -2: forget the table).
+rsrs_status gemm_autotune(const char* cache_path, int64_t* entries, int64_t* changed);
+rsrs_status gemm_tile_override(int shape);
 // Launches one record; descs is the device copy of the caller's array.
 rsrs_status gemm_exec(const GemmLaunch& L, const void* descs, size_t desc_bytes, hipStream_t st);
 // Instantiated for <double, double> and <float, float> (all forms).

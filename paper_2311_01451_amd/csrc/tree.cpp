@@ -399,7 +399,7 @@ namespace rsrs {
 // multiplier.  The root adds a thin QR with Q of the s x |B_t| panel, the
 // product with Y, a triangular solve and an LU; it stores |B_t|^2 entries.
 void work_model(const Tree& t, const Schedule& sc, int k, int64_t s, bool sym, int esize,
-                double* flops, double* bytes, int64_t* stored) {
+                int subset_p, double* flops, double* bytes, int64_t* stored) {
   const double h = sym ? 0.5 : 1.0, ds = (double)s, e = (double)esize;
   double f = 0.0, by = 0.0;
   int64_t st = 0;
@@ -408,13 +408,16 @@ void work_model(const Tree& t, const Schedule& sc, int k, int64_t s, bool sym, i
       for (int64_t bx : cl) {
         const int64_t b = sc.b_count[bx], n = sc.l_count[bx] - b;
         const int64_t kb = std::min<int64_t>(k, b), r = b - kb, l = b + n;
+        // columns of the nullification, ID and extraction
+        const double dc = subset_p >= 0 ? (double)std::min<int64_t>(s, l + k + subset_p) : ds;
         const double db = (double)b, dn = (double)n, dk = (double)kb, dr = (double)r, dl = (double)l;
-        f += h * 2.0 * (4.0 * ds * dl * dl - (4.0 / 3.0) * dl * dl * dl) + h * 8.0 * db * ds * dl +
-             4.0 * ds * db * dk + h * 8.0 * dr * dk * ds + h * 4.0 * dr * ds * dl +
+        f += h * 2.0 * (4.0 * dc * dl * dl - (4.0 / 3.0) * dl * dl * dl) + h * 8.0 * db * dc * dl +
+             4.0 * dc * db * dk + h * 8.0 * dr * dk * ds + h * 4.0 * dr * dc * dl +
              (2.0 / 3.0) * dr * dr * dr + h * 4.0 * dr * dr * (dk + dn) + h * 8.0 * dr * (dk + dn) * ds;
         const int64_t sb = r * kb + r * r + (sym ? 1 : 2) * r * (kb + n);
         st += sb;
-        by += h * e * ds * (double)(2 * l + 2 * b + 2 * n) + h * e * ds * (double)(4 * b + 2 * n) + e * (double)sb;
+        by += h * e * (dc * (double)(2 * l + 2 * b) + ds * (double)(2 * n)) + h * e * ds * (double)(4 * b + 2 * n) +
+              e * (double)sb;
       }
   const double nt = (double)sc.root_count;
   f += (4.0 * ds * nt * nt - (4.0 / 3.0) * nt * nt * nt) + 2.0 * ds * nt * nt + nt * nt * nt +

@@ -40,8 +40,9 @@ std::string build_tree(const double* pts, int64_t n, int dim, int leaf_size, int
                        const double* lo, double side, Tree& t);
 void make_schedule(const Tree& t, int k, Schedule& s);
 int64_t samples_required(const Tree& t, const Schedule& s, int k, int p);
-// Algorithmic flops, bytes and stored entries of a fixed-rank factorization.
+// Algorithmic flops, bytes and stored entries of a fixed-rank factorization;
+// subset_p >= 0: boxes read s_B = min(s, l + k + subset_p) sample columns.
 void work_model(const Tree& t, const Schedule& s, int k, int64_t nsamples, bool sym, int esize,
-                double* flops, double* bytes, int64_t* stored);
+                int subset_p, double* flops, double* bytes, int64_t* stored);
 
 }  // namespace rsrs

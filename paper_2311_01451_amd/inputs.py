@@ -77,3 +77,19 @@ def smooth_log_coefficient(n_nodes: int, seed_offset: int = 4) -> np.ndarray:
         g = (gp[tuple(a)] + gp[tuple(b)] + gp[tuple(c)]) / 3.0
         del sl
     return np.exp(g)
+
+
+def uneven_batch(count: int = 48, n_lo: int = 45, n_hi: int = 181, ranks=(32, 48, 64),
+                 seed_offset: int = 7) -> list:
+    """The many-problem workload: ``count`` jittered 2D grids with n_i x n_i
+    points, n_i^2 log-uniform between n_lo^2 and n_hi^2 (about 2,000 to
+    33,000 points), and ranks drawn uniformly from ``ranks``.  Problem i's
+    geometry, samples and right-hand sides use seed offsets +100 i (jitter
+    at 3 + 100 i).  Returns a list of dicts {i, n, k, geom_seed, seed}."""
+    r = rng(seed_offset)
+    out = []
+    for i in range(count):
+        n = int(round(np.exp(r.uniform(np.log(n_lo), np.log(n_hi)))))
+        k = int(r.choice(np.asarray(ranks)))
+        out.append({"i": i, "n": n, "k": k, "geom_seed": 3 + 100 * i, "seed": 100 * i})
+    return out

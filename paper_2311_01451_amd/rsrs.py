@@ -60,7 +60,8 @@ class TreeInfo(C.Structure):
 
 class FactorOpts(C.Structure):
     _fields_ = [("k", C.c_int), ("p", C.c_int), ("precision", C.c_int), ("reproject", C.c_int),
-                ("symmetric", C.c_int), ("id_mode", C.c_int), ("rank_tol", C.c_double)]
+                ("symmetric", C.c_int), ("id_mode", C.c_int), ("rank_tol", C.c_double),
+                ("col_subset", C.c_int)]
 
 
 class FactorInfo(C.Structure):
@@ -94,7 +95,7 @@ MATVEC_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int, C.c_int, C.c_int64, C.c_vo
 EXPORTS = [
     "rsrs_status_string", "rsrs_last_error", "rsrs_last_required_s", "rsrs_build_tree",
     "rsrs_tree_destroy", "rsrs_tree_get_info", "rsrs_tree_neighbours", "rsrs_tree_schedule",
-    "rsrs_samples_required", "rsrs_work_model", "rsrs_op_create_kernel", "rsrs_op_create_dense",
+    "rsrs_samples_required", "rsrs_work_model", "rsrs_gemm_autotune", "rsrs_gemm_tile_override", "rsrs_op_create_kernel", "rsrs_op_create_dense",
     "rsrs_op_create_poisson7", "rsrs_op_matvec", "rsrs_op_destroy", "rsrs_samples_wrap",
     "rsrs_sample", "rsrs_sample_symmetric", "rsrs_samples_wrap_symmetric", "rsrs_samples_destroy", "rsrs_gaussian", "rsrs_factor", "rsrs_factor_batched",
     "rsrs_factor_destroy", "rsrs_release_cached",
@@ -128,7 +129,9 @@ def lib():
         "rsrs_tree_neighbours": (i32, [vp, i32, P(i64), P(P(i64)), P(P(i64)), P(P(i64))]),
         "rsrs_tree_schedule": (i32, [vp, i32, P(C.c_int32), P(i64), P(i64), P(i64)]),
         "rsrs_samples_required": (i64, [vp, i32, i32]),
-        "rsrs_work_model": (i32, [vp, i32, i64, i32, i32, P(dbl), P(dbl), P(i64)]),
+        "rsrs_work_model": (i32, [vp, P(FactorOpts), i64, i32, P(dbl), P(dbl), P(i64)]),
+        "rsrs_gemm_autotune": (i32, [C.c_char_p, P(i64), P(i64)]),
+        "rsrs_gemm_tile_override": (i32, [i32]),
         "rsrs_op_create_kernel": (i32, [i32, P(C.c_double), i64, i32, dbl, dbl, P(vp)]),
         "rsrs_op_create_dense": (i32, [vp, i64, i64, P(vp)]),
         "rsrs_op_create_poisson7": (i32, [i32, P(C.c_double), P(vp)]),
@@ -287,12 +290,27 @@ def rsrs_samples_required(tree: Tree, k: int, p: int) -> int:
     return int(v)
 
 
-def rsrs_work_model(tree: Tree, k: int, s: int, symmetric: bool = False, esize: int = 8) -> dict:
+def rsrs_work_model(tree: Tree, k: int, s: int, symmetric: bool = False, esize: int = 8,
+                    col_subset: bool = False, p: int = -1) -> dict:
     """Algorithmic flops, bytes and stored entries of a fixed-rank factorization."""
     f, b, st = C.c_double(), C.c_double(), C.c_int64()
-    _check(lib().rsrs_work_model(tree.handle, k, s, int(symmetric), esize, C.byref(f), C.byref(b),
+    o = FactorOpts(int(k), int(p), 0, 1, int(symmetric), 0, 0.0, int(col_subset))
+    _check(lib().rsrs_work_model(tree.handle, C.byref(o), int(s), esize, C.byref(f), C.byref(b),
                                  C.byref(st)))
     return {"flops": f.value, "bytes": b.value, "stored_entries": st.value}
+
+
+def rsrs_gemm_autotune(cache_path: str | None = None) -> dict:
+    """Measures (or loads from cache_path) the GEMM tile table; returns the
+    number of launch classes and how many differ from the built-in rule."""
+    e, c = C.c_int64(), C.c_int64()
+    _check(lib().rsrs_gemm_autotune(cache_path.encode() if cache_path else None, C.byref(e), C.byref(c)))
+    return {"classes": e.value, "changed": c.value}
+
+
+def rsrs_gemm_tile_override(shape: int) -> None:
+    """Forces a tile shape (0, 1, 2); -1 back to the table, -2 forgets it."""
+    _check(lib().rsrs_gemm_tile_override(int(shape)))
 
 
 # --------------------------------------------------------------------------- operators
@@ -484,8 +502,8 @@ class Factor:
 
 def rsrs_factor(tree: Tree, samples: Samples, k: int, p: int = -1, reproject: int = 1,
                 precision: int = RSRS_PREC_F64, stream=None, symmetric: bool = False,
-                id_mode: int = 0, rank_tol: float = 0.0) -> Factor:
-    o = FactorOpts(k, p, precision, reproject, int(symmetric), int(id_mode), float(rank_tol))
+                id_mode: int = 0, rank_tol: float = 0.0, col_subset: bool = False) -> Factor:
+    o = FactorOpts(k, p, precision, reproject, int(symmetric), int(id_mode), float(rank_tol), int(col_subset))
     h = C.c_void_p()
     _check(lib().rsrs_factor(tree.handle, samples.handle, C.byref(o), _stream(stream), C.byref(h)))
     return Factor(h, keep=tree)
@@ -493,7 +511,7 @@ def rsrs_factor(tree: Tree, samples: Samples, k: int, p: int = -1, reproject: in
 
 def rsrs_factor_batched(trees, samples, ks, p: int = -1, reproject: int = 1,
                         precision: int = RSRS_PREC_F64, stream=None, symmetric: bool = False,
-                        id_mode: int = 0, rank_tol: float = 0.0) -> list:
+                        id_mode: int = 0, rank_tol: float = 0.0, col_subset: bool = False) -> list:
     """Factor independent problems together; ks gives each problem's rank."""
     n = len(trees)
     if len(samples) != n or len(ks) != n:
@@ -501,7 +519,7 @@ def rsrs_factor_batched(trees, samples, ks, p: int = -1, reproject: int = 1,
     th = (C.c_void_p * n)(*[t.handle for t in trees])
     sh = (C.c_void_p * n)(*[x.handle for x in samples])
     opts = (FactorOpts * n)(*[FactorOpts(int(k), p, precision, reproject, int(symmetric), int(id_mode),
-                                         float(rank_tol)) for k in ks])
+                                         float(rank_tol), int(col_subset)) for k in ks])
     outs = (C.c_void_p * n)()
     _check(lib().rsrs_factor_batched(n, th, sh, opts, _stream(stream), outs))
     return [Factor(C.c_void_p(outs[i]), keep=trees[i]) for i in range(n)]
@@ -629,10 +647,11 @@ class Server:
     def submit_factor(self, tree: Tree, op: Operator, s: int, seed: int, k: int,
                       precision: int = RSRS_PREC_F64, p: int = -1, reproject: int = 1,
                       dtype: int | None = None, symmetric: bool = False, id_mode: int = 0,
-                      rank_tol: float = 0.0) -> int:
+                      rank_tol: float = 0.0, col_subset: bool = False) -> int:
         if dtype is None:
             dtype = RSRS_F64 if precision == RSRS_PREC_F64 else RSRS_F32
-        o = FactorOpts(int(k), p, precision, reproject, int(symmetric), int(id_mode), float(rank_tol))
+        o = FactorOpts(int(k), p, precision, reproject, int(symmetric), int(id_mode), float(rank_tol),
+                       int(col_subset))
         t = C.c_int64()
         _check(lib().rsrs_server_submit_factor(self._h, tree.handle, Operator.fn_ptr(), op.handle,
                                                int(s), int(seed), dtype, C.byref(o), C.byref(t)))

@@ -94,9 +94,13 @@ def test_work_model_native_equals_oracle(symmetric):
         to = ot.build_tree(pts, m, lo=lo)
         tc = rsrs.rsrs_build_tree(pts, m, root_lo=lo)
         s = tc.samples_required(k, k)
-        for esize in (8, 4):
-            w = rsrs.rsrs_work_model(tc, k, s, bool(symmetric), esize)
-            o = ofl.factor_work(to, k, s, symmetric=bool(symmetric), esize=esize)
+        for esize, cs in ((8, False), (4, False), (8, True)):
+            w = rsrs.rsrs_work_model(tc, k, s, bool(symmetric), esize, col_subset=cs)
+            o = ofl.factor_work(to, k, s, symmetric=bool(symmetric), esize=esize, col_subset=cs)
             assert abs(w["flops"] - o.flops) <= 1e-12 * o.flops
             assert abs(w["bytes"] - o.bytes_moved) <= 1e-12 * o.bytes_moved
             assert w["stored_entries"] == o.stored_entries
+        # column subsets price fewer flops whenever some box has l + k + p < s
+        full = ofl.factor_work(to, k, s, symmetric=bool(symmetric))
+        sub = ofl.factor_work(to, k, s, symmetric=bool(symmetric), col_subset=True)
+        assert sub.flops < full.flops and sub.stored_entries == full.stored_entries

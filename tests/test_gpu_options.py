@@ -1,7 +1,8 @@
 """GPU parity of the factor options against the oracle: the rank tolerance
 (k_B = the numerical rank of the ID's sketch relative to ||[Y_B Z_B]||,
-capped at k) and the concatenated-sketch ID ([M_Y, M_Z] instead of
-M_Y + M_Z).
+capped at k), the concatenated-sketch ID ([M_Y, M_Z] instead of
+M_Y + M_Z) and per-box column subsets (a box reads its first
+s_B = min(s, l + k + p) sample columns).
 
 With a rank tolerance the skeleton counts are data-dependent; on the
 64 x 64 workload at k = 32 they range from 0 to 20, boxes whose children
@@ -90,13 +91,56 @@ def test_concatenated_id_parity():
         _solution_checks(P)
 
 
+@pytest.mark.parametrize("n,m,k,skew,id_mode", [(64, 64, 16, 0.0, 0), (32, 32, 16, 4e-3, 0),
+                                                (32, 32, 16, 4e-3, 1)])
+def test_column_subsets_parity(n, m, k, skew, id_mode):
+    """Per-box column subsets against the oracle's variant: the 64 x 64
+    workload's geometry at k = 16 (every box compared, root included) and a
+    nonsymmetric operator with either ID sketch."""
+    need_gpu()
+    P = _log_problem(n, m, k, skew=skew, id_mode=id_mode, col_subset=True)
+    sB = [min(P.s, len(bo.Ba) + len(bo.Na) + 2 * k) for bo in P.Fo.boxes]
+    assert min(sB) < P.s
+    worst, ncmp = compare_boxes(P)
+    print(f"[col_subset n={n} skew={skew} id={id_mode}] s_B {min(sB)}..{max(sB)} of {P.s}; "
+          f"{ncmp}/{len(P.Fo.boxes)} boxes compared, worst / predicted {worst:.2f}", flush=True)
+    assert ncmp == len(P.Fo.boxes)
+    Bt, At = P.F.root()
+    assert np.array_equal(Bt, P.Fo.Bt)
+    assert relmax(At, P.Fo.At) < 100.0 * P.max_pred
+    _solution_checks(P)
+    eo = orr.relerr(P.Fo, P.A)
+    Fo_full = orr.factor(P.to, P.A @ P.Om, P.A.T @ P.Psi, P.Om, P.Psi, k)
+    print(f"[col_subset n={n}] oracle relerr {eo:.2e} (all columns {orr.relerr(Fo_full, P.A):.2e})", flush=True)
+
+
+def test_column_subsets_mixed_refines():
+    """The mixed path (BF16 sample products, FP32 factor) with column
+    subsets, symmetric and general, refines to 1e-10 on the 64 x 64 workload."""
+    need_gpu()
+    pts = inputs.grid2d(64)
+    op = rsrs.rsrs_op_create_kernel(rsrs.RSRS_OP_LOG2D, pts, 1.0 / 64)
+    tc = rsrs.rsrs_build_tree(pts, 64)
+    s = tc.samples_required(32, 32)
+    for sym in (False, True):
+        smp = rsrs.rsrs_sample(tc, op, s, inputs.BASE_SEED, dtype=rsrs.RSRS_BF16, symmetric=sym)
+        F = rsrs.rsrs_factor(tc, smp, 32, precision=rsrs.RSRS_PREC_F32_MIXED, symmetric=sym, col_subset=True)
+        f = torch.tensor(inputs.rhs(4096, 3), dtype=torch.float64, device="cuda")
+        u0 = rsrs.rsrs_solve(F, f)
+        r0 = float(torch.linalg.norm(f - op.matvec(u0)) / torch.linalg.norm(f))
+        u, rel, it = rsrs.rsrs_solve_refine(F, op, f, tol=1e-10, maxit=30)
+        print(f"[col_subset mixed sym={sym}] one-shot residual {r0:.1e}; refined {rel:.1e} after {it}",
+              flush=True)
+        assert rel <= 1e-10
+
+
 def test_option_validation():
     need_gpu()
     pts = inputs.grid2d(16)
     tc = rsrs.rsrs_build_tree(pts, 16)
     op = rsrs.rsrs_op_create_kernel(rsrs.RSRS_OP_LOG2D, pts, 1.0 / 16)
     s = tc.samples_required(8, 8)
-    for kw in ({"id_mode": 7}, {"rank_tol": -1.0}, {"rank_tol": float("nan")}):
+    for kw in ({"id_mode": 7}, {"rank_tol": -1.0}, {"rank_tol": float("nan")}, {"col_subset": 2}):
         smp = rsrs.rsrs_sample(tc, op, s, 1)
         with pytest.raises(rsrs.RSRSError) as e:
             rsrs.rsrs_factor(tc, smp, 8, **kw)

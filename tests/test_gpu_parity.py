@@ -44,7 +44,7 @@ class Problem:
     """One operator + geometry, factored on both sides with identical inputs."""
 
     def __init__(self, pts, A, m, k, lo=None, side=1.0, s=None, seed_off=0, reproject=1, keep_M=False,
-                 rank_tol=0.0, id_mode=0):
+                 rank_tol=0.0, id_mode=0, col_subset=False):
         print(f"[problem] N={len(pts)} m={m} k={k}", flush=True)
         self.pts, self.A, self.k, self.rank_tol = pts, A, k, rank_tol
         N = len(pts)
@@ -59,10 +59,12 @@ class Problem:
         dY = self.op.matvec(dOm)
         dZ = self.op.matvec(dPsi, transpose=True)
         smp = rsrs.rsrs_samples_wrap(self.tc, dY, dZ, dOm, dPsi)
-        self.F = rsrs.rsrs_factor(self.tc, smp, k, reproject=reproject, rank_tol=rank_tol, id_mode=id_mode)
+        self.F = rsrs.rsrs_factor(self.tc, smp, k, reproject=reproject, rank_tol=rank_tol, id_mode=id_mode,
+                                  col_subset=col_subset)
         torch.cuda.synchronize()
         self.Fo = orr.factor(self.to, A @ Om, A.T @ Psi, Om, Psi, k, keep_M=keep_M, rank_tol=rank_tol,
-                             id_mode="concat" if id_mode == rsrs.RSRS_ID_CONCAT else "sum")
+                             id_mode="concat" if id_mode == rsrs.RSRS_ID_CONCAT else "sum",
+                             col_subset=col_subset)
         self.all_matched = False
 
 

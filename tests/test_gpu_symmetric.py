@@ -105,3 +105,46 @@ def test_symmetric_samples_need_the_symmetric_variant():
     with pytest.raises(rsrs.RSRSError) as e:
         rsrs.rsrs_factor(tc, smp, 8)
     assert e.value.status == 1
+
+
+def test_symmetric_equals_general_with_equal_samples():
+    """Sec. 2.2 on the GPU: the general factorization fed Psi = Omega and
+    Z = Y must reproduce the symmetric variant.  First-class boxes see
+    M_Y + M_Z = 2 M_Y and must pick the same skeletons with the same T to
+    rounding; afterwards the paths differ only through the asymmetry of the
+    general X_RR (of the order of the approximation error), so the two
+    solutions must agree to within that error."""
+    need_gpu()
+    n, m, k = 32, 32, 12
+    N = n * n
+    pts = inputs.grid2d(n)
+    A = oop.log2d(pts, 1.0 / n)
+    tc = rsrs.rsrs_build_tree(pts, m)
+    s = tc.samples_required(k, k)
+    Om, _ = inputs.test_matrices(N, s)
+    Y = A @ Om
+    Fs = rsrs.rsrs_factor(tc, rsrs.rsrs_samples_wrap(tc, dev(Y), None, dev(Om), None), k, symmetric=True)
+    Fg = rsrs.rsrs_factor(tc, rsrs.rsrs_samples_wrap(tc, dev(Y), dev(Y), dev(Om), dev(Om)), k)
+    nb = Fs.info()["nboxes"]
+    same = 0
+    first = None
+    for i in range(nb):
+        a, g = Fs.box(i), Fg.box(i)
+        key = (a["level"], a["colour"])
+        first = key if first is None else first
+        match = np.array_equal(a["S"], g["S"]) and np.array_equal(a["R"], g["R"])
+        if key == first:
+            assert match, i
+            if a["T"].size:
+                d = np.abs(a["T"] - g["T"]).max() / np.abs(a["T"]).max()
+                assert d < 1e-12, (i, d)
+        same += match
+    print(f"[symmetric vs general] {same}/{nb} boxes with equal skeletons", flush=True)
+    Aap = Fs.apply(dev(np.eye(N))).cpu().numpy()
+    e = float(np.linalg.norm(A - Aap, 2) / np.linalg.norm(A, 2))
+    f = inputs.rhs(N, 3)
+    us = Fs.solve(dev(f)).cpu().numpy()
+    ug = Fg.solve(dev(f)).cpu().numpy()
+    d = float(np.abs(us - ug).max() / np.abs(us).max())
+    print(f"[symmetric vs general] solutions differ by {d:.2e}, relerr {e:.2e}", flush=True)
+    assert d < e

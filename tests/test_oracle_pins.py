@@ -199,12 +199,14 @@ def _dense_ops(bf, N):
     return E, F, L, U
 
 
-@pytest.mark.parametrize("skew", [0.0, 2e-3])
-def test_sample_pair_invariant_every_box(skew):
+@pytest.mark.parametrize("skew,col_subset", [(0.0, False), (2e-3, False), (2e-3, True)])
+def test_sample_pair_invariant_every_box(skew, col_subset):
     """Sec. 1.1 and eq. updateVW_sketch/test/adj: after every box the updated
     sketches are an exact sample pair of V^{-1} A W^{-1}, whatever the
     approximation quality; the R rows/columns are decoupled to the level of the
-    far-field remainder."""
+    far-field remainder.  With per-box column subsets the updates must still
+    cover every column: an update cut to the s_B columns a box reads breaks
+    the pair in the remaining ones."""
     A, t, Om, Psi = _small_log_problem(skew=skew)
     Y, Z = A @ Om, A.T @ Psi
     N = A.shape[0]
@@ -222,9 +224,55 @@ def test_sample_pair_invariant_every_box(skew):
         worst[1] = max(worst[1], np.abs(At[np.ix_(bf.R, rest)]).max(),
                        np.abs(At[np.ix_(rest, bf.R)]).max())
 
-    orr.factor(t, Y, Z, Om, Psi, 8, on_box=check)
+    orr.factor(t, Y, Z, Om, Psi, 8, on_box=check, col_subset=col_subset)
     assert worst[0] < 1e-12
-    assert worst[1] < 2e-4 * np.abs(A).max()
+    # column subsets oversample boxes with small l less (s_B - l = k + p
+    # instead of up to s - l): a somewhat larger far-field remainder
+    assert worst[1] < (4e-4 if col_subset else 2e-4) * np.abs(A).max()
+
+
+def test_column_subsets():
+    """Per-box column subsets (a box reads the first s_B = min(s, l + k + p)
+    sample columns; the first columns of a sample pair are a sample pair of
+    the same operator, Sec. 1.1):
+    (a) some boxes of this geometry really use fewer than s columns;
+    (b) a first-class box is the plain step on sketches cut to its s_B columns;
+    (c) with p so large that every s_B = s the factorization is the plain one,
+        bit for bit;
+    (d) an exactly H2 operator is still recovered to rounding (s_B - l = k + p
+        null-space directions cover its far-field rank);
+    (e) less oversampling costs accuracy only mildly: relerr within 10x."""
+    A, t, Om, Psi = _small_log_problem(skew=2e-3)
+    Y, Z = A @ Om, A.T @ Psi
+    s = Om.shape[1]
+    k = p = 8
+    F = orr.factor(t, Y, Z, Om, Psi, k, col_subset=True)
+    F0 = orr.factor(t, Y, Z, Om, Psi, k)
+    sBs = [min(s, len(bf.Ba) + len(bf.Na) + k + p) for bf in F.boxes]
+    assert min(sBs) < s and max(sBs) == s
+    P = t.perm
+    b0 = F.boxes[0]
+    for i, bf in enumerate(F.boxes):
+        if (bf.level, bf.colour) != (b0.level, b0.colour):
+            break
+        sB = sBs[i]
+        cut = [np.ascontiguousarray(X[P][:, :sB]) for X in (Y, Z, Om, Psi)]
+        ref = orr._process_box(bf.box, bf.level, bf.colour, bf.Ba, bf.Na, *cut, k, False)
+        assert np.array_equal(ref.S, bf.S) and np.array_equal(ref.R, bf.R)
+        for a, b in ((ref.T, bf.T), (ref.XRR, bf.XRR), (ref.KU, bf.KU), (ref.KL, bf.KL)):
+            assert np.allclose(a, b, rtol=0, atol=1e-12 * max(1.0, np.abs(a).max()))
+    Fbig = orr.factor(t, Y, Z, Om, Psi, k, p=10 * s, check_samples=False, col_subset=True)
+    for a, b in zip(Fbig.boxes, F0.boxes):
+        assert np.array_equal(a.S, b.S) and np.array_equal(a.T, b.T) and np.array_equal(a.KU, b.KU)
+    e, e0 = orr.relerr(F, A), orr.relerr(F0, A)
+    assert e < 10 * e0, (e, e0)
+    pts = inputs.grid2d(16)
+    th = ot.build_tree(pts, leaf_size=16)
+    H = _exact_h2_symmetric(th, r=3)
+    sh = ot.samples_required(th, 6, 6)
+    Om2, Psi2 = inputs.test_matrices(256, sh)
+    Fh = orr.factor(th, H @ Om2, H.T @ Psi2, Om2, Psi2, 6, col_subset=True)
+    assert orr.relerr(Fh, H) < 1e-11
 
 
 def test_solve_apply_inverse_and_adjoint():
@@ -366,6 +414,50 @@ def test_symmetric_variant():
     Om2, _ = inputs.test_matrices(256, s)
     Fh = orr.factor(th, H @ Om2, None, Om2, None, k, symmetric=True)
     assert orr.relerr(Fh, H) < 1e-11
+
+
+def test_symmetric_variant_is_the_general_step_with_equal_samples():
+    """Sec. 2.2: on A = A^T, the general step run with Psi = Omega (so Z = Y)
+    computes the symmetric variant.  (a) Boxes of the first class see
+    M_Y + M_Z = 2 M_Y: scaling by two is exact, so skeletons and T are bit for
+    bit those of the symmetric variant.  (b) Later, the two paths differ only
+    through the asymmetry of the general X_RR (the symmetric variant takes its
+    symmetric part), which is of the order of the approximation error: every
+    skeleton agrees and the solutions differ by less than that error.
+    (c) On an exactly H2 symmetric operator X_RR is symmetric to rounding,
+    and the two solves agree to rounding."""
+    A, t, Om, Psi = _small_log_problem(n=32, m=32, k=12)
+    Y = A @ Om
+    Fs = orr.factor(t, Y, None, Om, None, 12, symmetric=True)
+    Fg = orr.factor(t, Y, Y.copy(), Om, Om.copy(), 12)
+    b0 = Fs.boxes[0]
+    first = [i for i, bf in enumerate(Fs.boxes) if (bf.level, bf.colour) == (b0.level, b0.colour)]
+    assert len(first) == 9
+    for i in first:
+        assert np.array_equal(Fs.boxes[i].T, Fg.boxes[i].T)
+    e = orr.relerr(Fs, A)
+    for a, g in zip(Fs.boxes, Fg.boxes):
+        assert np.array_equal(a.S, g.S) and np.array_equal(a.R, g.R)
+        if g.R.size:
+            asym = np.abs(g.XRR - g.XRR.T).max() / np.abs(g.XRR).max()
+            assert asym < e, (a.box, asym, e)
+    f = inputs.rhs(A.shape[0], 3)
+    us, ug = orr.solve(Fs, f), orr.solve(Fg, f)
+    assert np.abs(us - ug).max() < e * np.abs(us).max()
+    pts = inputs.grid2d(16)
+    th = ot.build_tree(pts, leaf_size=16)
+    H = _exact_h2_symmetric(th, r=3)
+    s = ot.samples_required(th, 6, 6)
+    Om2, _ = inputs.test_matrices(256, s)
+    Yh = H @ Om2
+    # rank_tol keeps both paths off the rounding-noise pivots beyond rank 3
+    Fhs = orr.factor(th, Yh, None, Om2, None, 6, symmetric=True, rank_tol=1e-10)
+    Fhg = orr.factor(th, Yh, Yh.copy(), Om2, Om2.copy(), 6, rank_tol=1e-10)
+    for a, g in zip(Fhs.boxes, Fhg.boxes):
+        assert np.array_equal(a.S, g.S)
+    f = inputs.rhs(256, 2)
+    us = orr.solve(Fhs, f)
+    assert np.abs(us - orr.solve(Fhg, f)).max() < 1e-12 * np.abs(us).max()
 
 
 def test_insufficient_samples_raises():
