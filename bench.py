@@ -368,6 +368,46 @@ def cpu_baseline(s_eff: int, nbox: int = 4) -> dict:
             "est_step_s": round(est, 1), "host": hi}
 
 
+def cpu_oracle_config0(reps: int = 3) -> dict:
+    """The whole oracle on the 64 x 64 workload (N = 4096, leaf 64,
+    k = p = 32, s = max(320, s_required), general variant, FP64): dense
+    sampling Y = A Omega, Z = A^T Psi, Algorithm 1, and a 16-column solve,
+    timed end to end `reps` times with every BLAS thread (median reported)
+    and once with one thread."""
+    from threadpoolctl import threadpool_limits
+    from oracle import operators as oop
+    from oracle import rsrs as orr
+    from oracle import tree as ot
+    from paper_2311_01451_amd import inputs
+
+    n, k = 64, 32
+    pts = inputs.grid2d(n)
+    A = oop.log2d(pts, 1.0 / n)
+    t = ot.build_tree(pts, LEAF)
+    s = max(320, ot.samples_required(t, k, k))
+    Om, Psi = inputs.test_matrices(n * n, s)
+    f = inputs.rhs(n * n, NRHS)
+
+    def once():
+        a = time.perf_counter()
+        F = orr.factor(t, A @ Om, A.T @ Psi, Om, Psi, k)
+        b = time.perf_counter()
+        orr.solve(F, f)
+        c = time.perf_counter()
+        return c - a, b - a, c - b
+
+    all_threads = [once() for _ in range(reps)]
+    with threadpool_limits(limits=1):
+        one = once()
+    med = sorted(all_threads)[len(all_threads) // 2]
+    return {"workload": "64x64 log kernel (N=4096), leaf 64, k=p=32, s=%d, general variant, FP64: "
+                        "sampling + Algorithm 1 + 16-column solve" % s,
+            "all_threads_step_s": [round(x[0], 3) for x in all_threads], "median_step_s": round(med[0], 3),
+            "median_factor_s": round(med[1], 3), "median_solve_s": round(med[2], 4),
+            "one_thread_step_s": round(one[0], 3), "one_thread_factor_s": round(one[1], 3),
+            "cols_per_s_median": round(NRHS / med[0], 4), "host": host_info()}
+
+
 def serving_bench(duration_s: float, load: float = 0.7) -> dict:
     """Serving workload: a resident mixed-precision factor of the 3D kernel
     A_ij = delta_ij + (1/N) / (4 pi |x_i - x_j|) on N = 32768 uniform random
@@ -690,19 +730,23 @@ def config3_leg() -> dict:
             "factor_tflops_work_model": round(model / t_batch / 1e12, 3)}
 
 
-def col_subset_leg(ctx: dict) -> dict:
-    """Per-box column subsets (a box reads its first s_B = min(s, l + k + p)
-    sample columns in its nullification, ID and extraction) beside the
-    default (all s columns), one step each after one warm-up:
-      * the 64 x 64 grid in FP64 (general variant, k = p = 32): factor time
-        and the factorization's relerr ||A - A_approx|| / ||A|| from the
-        dense apply;
-      * the headline workload (256 x 256, mixed, symmetric): factor time,
-        one-shot residual, refinement steps to 1e-6 and columns per second."""
+def factor_options_leg(ctx: dict) -> dict:
+    """The factor options beside the default (all s columns, fixed rank k),
+    one step each after one warm-up:
+      * per-box column subsets (a box reads its first s_B = min(s, l + k + p)
+        sample columns in its nullification, ID and extraction);
+      * a rank tolerance (k_B = the numerical rank of the ID's sketch relative
+        to ||[Y_B Z_B]||, capped at k);
+    on the 64 x 64 grid in FP64 (general variant, k = p = 32: factor time and
+    the factorization's relerr ||A - A_approx|| / ||A|| from the dense apply)
+    and on the headline workload (256 x 256, mixed, symmetric: sampling +
+    factor time, one-shot residual, refinement steps to 1e-6, columns per
+    second)."""
     import torch
     from paper_2311_01451_amd import inputs, rsrs
 
-    out = {"what": "s_B = min(s, l + k + p) columns per box vs all s; work model flops of each"}
+    variants = (("default", {}), ("col_subset", {"col_subset": True}))
+    out = {}
     n, k = 64, 32
     pts = inputs.grid2d(n)
     op0 = rsrs.rsrs_op_create_kernel(rsrs.RSRS_OP_LOG2D, pts, 1.0 / n)
@@ -710,36 +754,37 @@ def col_subset_leg(ctx: dict) -> dict:
     A = op0.matvec(eye)
     nA = float(torch.linalg.matrix_norm(A, 2))
     c0 = {}
-    for label, cs in (("all_columns", False), ("col_subset", True)):
+    for label, kw in variants + (("rank_tol_1e-10", {"rank_tol": 1e-10}),):
         for rep in range(2):
             tc = rsrs.rsrs_build_tree(pts, LEAF)
             s = max(320, tc.samples_required(k, k))
             smp = rsrs.rsrs_sample(tc, op0, s, inputs.BASE_SEED, dtype=rsrs.RSRS_F64)
             torch.cuda.synchronize()
             a = time.perf_counter()
-            F = rsrs.rsrs_factor(tc, smp, k, col_subset=cs)
+            F = rsrs.rsrs_factor(tc, smp, k, **kw)
             torch.cuda.synchronize()
             b = time.perf_counter()
         Aap = F.apply(eye)
         c0[label] = {"factor_ms": round((b - a) * 1e3, 3),
                      "relerr": float(torch.linalg.matrix_norm(A - Aap, 2)) / nA,
-                     "work_model_gflop": round(rsrs.rsrs_work_model(tc, k, s, False, 8, col_subset=cs)["flops"]
-                                               / 1e9, 2)}
+                     "stored_mb": round(F.info()["stored_bytes"] / 1e6, 2)}
+        if "rank_tol" not in kw:
+            c0[label]["work_model_gflop"] = round(
+                rsrs.rsrs_work_model(tc, k, s, False, 8, col_subset=bool(kw.get("col_subset")))["flops"] / 1e9, 2)
         del F, Aap
     del A, eye
     out["config0_fp64_k32"] = c0
     op, f = ctx["op"], ctx["f"]
     pts1 = inputs.grid2d(GRID_N)
     c1 = {}
-    for label, cs in (("all_columns", False), ("col_subset", True)):
+    for label, kw in variants + (("rank_tol_1e-6", {"rank_tol": 1e-6}),):
         for rep in range(2):
             tc = rsrs.rsrs_build_tree(pts1, LEAF)
             s = max(S_CFG, tc.samples_required(K, K))
             torch.cuda.synchronize()
             a = time.perf_counter()
             smp = rsrs.rsrs_sample(tc, op, s, inputs.BASE_SEED, dtype=rsrs.RSRS_BF16, symmetric=True)
-            F = rsrs.rsrs_factor(tc, smp, K, precision=rsrs.RSRS_PREC_F32_MIXED, symmetric=True,
-                                 col_subset=cs)
+            F = rsrs.rsrs_factor(tc, smp, K, precision=rsrs.RSRS_PREC_F32_MIXED, symmetric=True, **kw)
             torch.cuda.synchronize()
             b = time.perf_counter()
             u0 = F.solve(f)
@@ -752,8 +797,10 @@ def col_subset_leg(ctx: dict) -> dict:
             del smp
         c1[label] = {"sample_factor_ms": round((b - a) * 1e3, 3), "relres_oneshot": r0, "relres": rel,
                      "refine_iters": its, "cols_per_s": round(NRHS / ((b - a) + (d - c)), 2),
-                     "work_model_gflop": round(rsrs.rsrs_work_model(tc, K, s, True, 4, col_subset=cs)["flops"]
-                                               / 1e9, 2)}
+                     "stored_mb": round(F.info()["stored_bytes"] / 1e6, 1)}
+        if "rank_tol" not in kw:
+            c1[label]["work_model_gflop"] = round(
+                rsrs.rsrs_work_model(tc, K, s, True, 4, col_subset=bool(kw.get("col_subset")))["flops"] / 1e9, 2)
         del F
     out["headline_mixed_symmetric"] = c1
     return out
@@ -778,8 +825,11 @@ def main():
                     help="run only the serving workload for this many seconds and print its line")
     ap.add_argument("--serving-seconds", type=float, default=8.0,
                     help="length of the Poisson stream of the serving leg in the default run")
+    ap.add_argument("--cpu-config0", action="store_true",
+                    help="only time the whole oracle on the 64x64 workload on the host (median of 3, "
+                         "and one thread) and print its line")
     ap.add_argument("--no-autotune", action="store_true",
-                    help="keep the built-in GEMM tile rule instead of measuring the tile table first")
+                    help="keep the built-in GEMM tile rule instead of tuning each run's launches first")
     ap.add_argument("--no-configs", action="store_true",
                     help="leave out the legs of the other workloads (configs 0, 2 and 4)")
     a = ap.parse_args()
@@ -787,23 +837,35 @@ def main():
         print(f"bench.py: this build measures one GPU only (asked for --gpus {a.gpus}); "
               "a sharded run across GPUs is not part of this benchmark", file=sys.stderr)
         sys.exit(2)
+    if a.cpu_config0:
+        print(json.dumps({"metric": "oracle on the host, 64x64 workload", **cpu_oracle_config0()}))
+        return
     if a.serving > 0:
         out = {"metric": "serving: p50/p99 solve latency (ms) and RHS cols/s under Poisson arrivals",
                "n_gpus": 1, "data": "synthetic"}
         out.update(serving_bench(a.serving))
         print(json.dumps(out))
         return
-    tune = None
-    if not a.no_autotune:
-        from paper_2311_01451_amd import rsrs as _r
-        t0 = time.perf_counter()
-        tune = _r.rsrs_gemm_autotune(None)
-        tune["seconds"] = round(time.perf_counter() - t0, 3)
     ctx = {}
     runs = {}
     plan = (("mixed", "bf16", True), ("mixed_general", "bf16", False),
             ("fp64", "fp64", True), ("fp64_general", "fp64", False))
     want = a.modes.split(",")
+    tune = None
+    if not a.no_autotune:
+        # tile choice of every GEMM launch of each run's factorization, timed on
+        # that workload (Gaussian samples, untimed)
+        from paper_2311_01451_amd import inputs as _in, rsrs as _r
+        t0 = time.perf_counter()
+        tc = _r.rsrs_build_tree(_in.grid2d(GRID_N), LEAF)
+        s_t = max(S_CFG, tc.samples_required(K, K))
+        tune = {}
+        for name, mode, sym in plan:
+            if name in want:
+                prec = _r.RSRS_PREC_F64 if mode == "fp64" else _r.RSRS_PREC_F32_MIXED
+                tune[name] = _r.rsrs_gemm_autotune_workload(tc, K, s_t, precision=prec, symmetric=sym,
+                                                             reproject=a.reproject)
+        tune["seconds"] = round(time.perf_counter() - t0, 3)
     for name, mode, sym in plan:
         if name not in want:
             continue
@@ -879,7 +941,7 @@ def main():
             out["configs"][name] = fn()
             torch.cuda.synchronize()
         out["configs"]["config4_serving"] = serving_bench(a.serving_seconds)
-        out["column_subsets"] = col_subset_leg(ctx)
+        out["factor_options"] = factor_options_leg(ctx)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(s_eff)
     print(json.dumps(out))

@@ -151,7 +151,7 @@ int64_t rsrs_samples_required(const rsrs_tree_t* t, int k, int p);
 rsrs_status rsrs_gemm_autotune(const char* cache_path, int64_t* entries, int64_t* changed);
 /* Forces one tile shape for every automatic launch: 0 = 64 x 64,
  * 1 = 128 x 64 (64 x 64 for the triangular form), 2 = 128 x 128.  -1 goes
- * back to the table (or the built-in rule).  -2 also forgets the table.  For
+ * back to the tables (or the built-in rule).  -2 also forgets both tables.  For
  * tests and measurements.  Other values -> RSRS_E_INVALID. */
 rsrs_status rsrs_gemm_tile_override(int shape);
 
@@ -315,6 +315,22 @@ typedef struct {
  * entry and right-hand side.  Outputs may be NULL.  esize is 4 or 8. */
 rsrs_status rsrs_work_model(const rsrs_tree_t* t, const rsrs_factor_opts* opts, int64_t s, int esize,
                             double* flops, double* bytes, int64_t* stored_entries);
+/* Workload tuning of the GEMM tile choice (see rsrs_gemm_autotune below): the factorization of (t, opts, s)
+ * -- the fixed-rank launch sequence; opts.rank_tol is ignored -- is run on
+ * Gaussian samples (Philox, drawn here) once per candidate: the current
+ * choice, then each of the three shapes forced.  Every automatic GEMM launch
+ * is timed with HIP events under its product's shape signature (element
+ * type, form and the list of (M, N, K) of its descriptors).  Each signature
+ * then keeps its fastest candidate; a challenger must be 2% faster.  From
+ * then on an exact signature match overrides the class table and the
+ * built-in rule, so later factorizations and solves with those shapes take
+ * the measured choice.  Results never change.  Cost: five factorizations of
+ * the workload, including one warm-up.  *signatures receives the number of
+ * signatures measured and *changed how many moved from the current choice
+ * (either may be NULL).  Call it while no other factorization or solve is
+ * running.  Errors: RSRS_E_INVALID and those of rsrs_factor. */
+rsrs_status rsrs_gemm_autotune_workload(const rsrs_tree_t* t, const rsrs_factor_opts* opts, int64_t s,
+                                        int64_t* signatures, int64_t* changed);
 
 rsrs_status rsrs_factor(const rsrs_tree_t* t, rsrs_samples_t* smp, const rsrs_factor_opts* opts,
                         void* stream, rsrs_factor_t** out);

@@ -1,6 +1,8 @@
 // extern "C" entry points of include/rsrs.h.
 #include <hip/hip_runtime.h>
 
+#include <unordered_map>
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -430,6 +432,99 @@ rsrs_status rsrs_gaussian(double* out, int64_t nrows, int64_t ncols, int64_t ld,
   if (!out || nrows < 0 || ncols < 0 || ld < ncols) return invalid("bad gaussian arguments");
   philox_normal<double>(static_cast<hipStream_t>(stream), out, nrows, ncols, ld, seed, word);
   if (hipGetLastError() != hipSuccess) { set_error("philox launch failed"); return RSRS_E_HIP; }
+  return RSRS_OK;
+}
+
+// ------------------------------------------------------------------ workload tile tuning
+// The factorization of (tree, opts, s) is run on Gaussian samples once per
+// candidate (the built-in rule, then each forced shape), every automatic
+// GEMM launch timed under its shape signature; each signature then keeps its
+// fastest shape.  Shapes do not change results, so any choice is exact.
+extern "C++" {
+template <typename T>
+static void fill_gaussian(hipStream_t st, rsrs_samples_t* smp, uint64_t seed) {
+  philox_normal<T>(st, smp->Y.as<T>(), smp->n, smp->s, smp->ld, seed, 0);
+  philox_normal<T>(st, smp->Om.as<T>(), smp->n, smp->s, smp->ld, seed, 1);
+  if (smp->symmetric) return;
+  philox_normal<T>(st, smp->Z.as<T>(), smp->n, smp->s, smp->ld, seed, 2);
+  philox_normal<T>(st, smp->Psi.as<T>(), smp->n, smp->s, smp->ld, seed, 3);
+}
+}  // extern "C++"
+
+static rsrs_status tuning_factor(const rsrs_tree_t* t, const rsrs_factor_opts* o, int64_t s, hipStream_t st,
+                                 bool record) {
+  const int dtype = o->precision == RSRS_PREC_F64 ? RSRS_F64 : RSRS_F32;
+  rsrs_samples_t* smp = nullptr;
+  RSRS_TRY(new_samples(t, s, dtype, &smp, o->symmetric != 0));
+  if (dtype == RSRS_F64) fill_gaussian<double>(st, smp, 0x7e57);
+  else fill_gaussian<float>(st, smp, 0x7e57);
+  if (hipGetLastError() != hipSuccess) {
+    delete smp;
+    set_error("GEMM tuning: sample generation failed");
+    return RSRS_E_HIP;
+  }
+  if (record) gemm_sig_record(true);
+  rsrs_factor_t* f = nullptr;
+  const rsrs_status rs = factor_impl(t, smp, o, st, &f);
+  gemm_sig_record(false);
+  delete smp;
+  if (f) rsrs_factor_destroy(f);
+  if (rs == RSRS_OK && hipStreamSynchronize(st) != hipSuccess) {
+    set_error("GEMM tuning: synchronisation failed");
+    return RSRS_E_HIP;
+  }
+  return rs;
+}
+
+rsrs_status rsrs_gemm_autotune_workload(const rsrs_tree_t* t, const rsrs_factor_opts* opts, int64_t s,
+                                        int64_t* signatures, int64_t* changed) {
+  if (!t || !opts || s < 1) return invalid("null tree or options, or s < 1");
+  if (signatures) *signatures = 0;
+  if (changed) *changed = 0;
+  rsrs_factor_opts o = *opts;
+  o.rank_tol = 0.0;   // the fixed-rank launch sequence
+  hipStream_t st = nullptr;
+  RSRS_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  struct Best { double ms; int shape; int rule; };
+  std::unordered_map<uint64_t, Best> best;
+  rsrs_status rs = RSRS_OK;
+  // candidates: -1 = the current choice (built-in rule, class table or an
+  // earlier exact entry), then the three shapes
+  for (int cand = -2; cand <= 2 && rs == RSRS_OK; ++cand) {
+    (void)gemm_tile_override(cand < 0 ? -1 : cand);
+    std::vector<std::pair<uint64_t, double>> ms;
+    std::vector<std::pair<uint64_t, int>> shp;
+    rs = tuning_factor(t, &o, s, st, cand != -2);   // -2: warm-up (scratch, code objects)
+    if (rs == RSRS_OK && cand != -2) rs = gemm_sig_collect(ms, shp);
+    if (rs != RSRS_OK) break;
+    std::unordered_map<uint64_t, int> sh(shp.begin(), shp.end());
+    for (const auto& m : ms) {
+      const int sp = sh[m.first];
+      auto it = best.find(m.first);
+      if (it == best.end()) {
+        best[m.first] = Best{m.second, sp, cand == -1 ? sp : -1};
+      } else {
+        if (cand == -1) it->second.rule = sp;
+        // a challenger must beat the kept shape by 2%
+        if (m.second < 0.98 * it->second.ms) {
+          it->second.ms = m.second;
+          it->second.shape = sp;
+        }
+      }
+    }
+  }
+  (void)gemm_tile_override(-1);
+  (void)hipStreamDestroy(st);
+  if (rs != RSRS_OK) return rs;
+  std::vector<std::pair<uint64_t, int>> table;
+  int64_t ch = 0;
+  for (const auto& b : best) {
+    table.emplace_back(b.first, b.second.shape);
+    ch += b.second.rule >= 0 && b.second.shape != b.second.rule;
+  }
+  gemm_sig_install(table, false);
+  if (signatures) *signatures = (int64_t)table.size();
+  if (changed) *changed = ch;
   return RSRS_OK;
 }
 

@@ -7,6 +7,8 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <mutex>
+#include <unordered_map>
 #include <cstdio>
 #include <cstring>
 #include <type_traits>
@@ -209,7 +211,33 @@ int tune_tbin(double t64) {
   return std::min(kTuneT - 1, std::max(0, b));
 }
 int tune_kbin(int K) { return K >= 362 ? 1 : 0; }
+
+// exact shape signatures of the workload tuning
+std::mutex g_sig_mu;
+std::unordered_map<uint64_t, int8_t> g_sig_table;
+std::atomic<bool> g_sig_any{false};
+std::atomic<bool> g_rec_on{false};
+struct SigRec { uint64_t sig; int shape; hipEvent_t a, b; };
+std::vector<SigRec> g_recs;
+
+uint64_t fnv(uint64_t h, uint64_t v) {
+  for (int i = 0; i < 8; ++i) {
+    h ^= (v >> (8 * i)) & 0xff;
+    h *= 1099511628211ull;
+  }
+  return h;
+}
 }  // namespace
+
+template <typename TI, typename TO>
+static uint64_t launch_sig(const std::vector<GemmDescT<TI, TO>>& descs, int ta, int tb, int mode) {
+  uint64_t h = 1469598103934665603ull;
+  h = fnv(h, sizeof(TI));
+  h = fnv(h, (uint64_t)(ta * 64 + tb * 8 + mode));
+  h = fnv(h, descs.size());
+  for (const auto& d : descs) h = fnv(h, ((uint64_t)(uint32_t)d.M << 40) ^ ((uint64_t)(uint32_t)d.N << 20) ^ (uint32_t)d.K);
+  return h;
+}
 
 template <typename TI, typename TO>
 static int builtin_shape(const std::vector<GemmDescT<TI, TO>>& descs, int mode) {
@@ -223,9 +251,14 @@ static int builtin_shape(const std::vector<GemmDescT<TI, TO>>& descs, int mode) 
 }
 
 template <typename TI, typename TO>
-static int chosen_shape(const std::vector<GemmDescT<TI, TO>>& descs, int ta, int tb, int mode) {
+static int chosen_shape(const std::vector<GemmDescT<TI, TO>>& descs, int ta, int tb, int mode, uint64_t sig) {
   const int ov = g_tile_override.load(std::memory_order_relaxed);
   if (ov >= 0) return (mode == GM_SYRK_L && ov == 1) ? 0 : ov;
+  if (g_sig_any.load(std::memory_order_acquire)) {
+    std::lock_guard<std::mutex> lk(g_sig_mu);
+    auto it = g_sig_table.find(sig);
+    if (it != g_sig_table.end()) return it->second;
+  }
   const int f = tune_form(ta, tb, mode);
   if (f >= 0 && g_tune_ready.load(std::memory_order_acquire)) {
     double t64 = 0.0;
@@ -266,7 +299,15 @@ rsrs_status gemm_plan(const std::vector<GemmDescT<TI, TO>>& descs, size_t base, 
     if (shape == GS_64x16 && mode == GM_FULL) return plan_forms<TI, TO, 64, 16, 4, 1>(descs, base, ta, tb, mode, out);
   }
   if (shape == GS_64x64_ONLY) return plan_forms<TI, TO, 64, 64, 2, 2>(descs, base, ta, tb, mode, out);
-  return plan_with_shape<TI, TO>(chosen_shape(descs, ta, tb, mode), descs, base, ta, tb, mode, out);
+  const uint64_t sig = launch_sig(descs, ta, tb, mode);
+  const size_t first = out.size();
+  const int shp = chosen_shape(descs, ta, tb, mode, sig);
+  RSRS_TRY((plan_with_shape<TI, TO>(shp, descs, base, ta, tb, mode, out)));
+  for (size_t i = first; i < out.size(); ++i) {
+    out[i].sig = sig;
+    out[i].shape = (mode == GM_SYRK_L && shp == 1) ? 0 : shp;
+  }
+  return RSRS_OK;
 }
 
 // Times shape `shp` on the synthetic launch `descs` (device copy at dd):
@@ -442,6 +483,7 @@ rsrs_status gemm_tile_override(int shape) {
   }
   if (shape == -2) {
     g_tune_ready.store(false, std::memory_order_release);
+    gemm_sig_install({}, true);
     shape = -1;
   }
   g_tile_override.store(shape, std::memory_order_relaxed);
@@ -452,8 +494,61 @@ rsrs_status gemm_exec(const GemmLaunch& L, const void* descs, size_t desc_bytes,
   const void* p = static_cast<const char*>(descs) + L.first * desc_bytes;
   void* args[] = {&p};
   ProfScope ps(st, L.tag, L.flops, L.bytes);
+  if (L.sig != 0 && g_rec_on.load(std::memory_order_relaxed)) {
+    SigRec r{L.sig, L.shape, nullptr, nullptr};
+    RSRS_HIP(hipEventCreate(&r.a));
+    RSRS_HIP(hipEventCreate(&r.b));
+    RSRS_HIP(hipEventRecord(r.a, st));
+    RSRS_HIP(hipLaunchKernel(L.fn, L.grid, L.block, args, 0, st));
+    RSRS_HIP(hipEventRecord(r.b, st));
+    std::lock_guard<std::mutex> lk(g_sig_mu);
+    g_recs.push_back(r);
+    return RSRS_OK;
+  }
   RSRS_HIP(hipLaunchKernel(L.fn, L.grid, L.block, args, 0, st));
   return RSRS_OK;
+}
+
+void gemm_sig_record(bool on) { g_rec_on.store(on, std::memory_order_relaxed); }
+
+rsrs_status gemm_sig_collect(std::vector<std::pair<uint64_t, double>>& ms,
+                             std::vector<std::pair<uint64_t, int>>& shape) {
+  std::vector<SigRec> recs;
+  {
+    std::lock_guard<std::mutex> lk(g_sig_mu);
+    recs.swap(g_recs);
+  }
+  std::unordered_map<uint64_t, double> sum;
+  std::unordered_map<uint64_t, int> shp;
+  rsrs_status rs = RSRS_OK;
+  for (auto& r : recs) {
+    float t = 0.0f;
+    if (rs == RSRS_OK && (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&t, r.a, r.b) != hipSuccess))
+      rs = RSRS_E_HIP;
+    sum[r.sig] += t;
+    shp[r.sig] = r.shape;
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  if (rs != RSRS_OK) {
+    set_error("GEMM tuning: event timing failed");
+    return rs;
+  }
+  ms.assign(sum.begin(), sum.end());
+  shape.assign(shp.begin(), shp.end());
+  return RSRS_OK;
+}
+
+void gemm_sig_install(const std::vector<std::pair<uint64_t, int>>& table, bool replace) {
+  std::lock_guard<std::mutex> lk(g_sig_mu);
+  if (replace) g_sig_table.clear();
+  for (const auto& x : table) g_sig_table[x.first] = (int8_t)x.second;
+  g_sig_any.store(!g_sig_table.empty(), std::memory_order_release);
+}
+
+int64_t gemm_sig_count() {
+  std::lock_guard<std::mutex> lk(g_sig_mu);
+  return (int64_t)g_sig_table.size();
 }
 
 template <typename TI, typename TO>

@@ -454,6 +454,179 @@ rsrs_status id_run(Uploader& up, hipStream_t st, const std::vector<IdDesc>& e, b
   return RSRS_OK;
 }
 
+// ---------------------------------------------------------------- Gram route
+// For FP32 rows the greedy pivoted QR of M^T is taken as the pivoted
+// Cholesky factorization of the FP64 Gram matrix G = M M^T: with
+// d_i = |residual of row i|^2, step j takes the unselected row p of largest
+// d_p, sets r_jj = sqrt(d_p) and, for every other unselected row i,
+//   R[j, i] = (G_ip - sum_{t<j} R[t, i] R[t, p]) / r_jj,   d_i -= R[j, i]^2,
+// which is the same R and the same pivots as the Gram-Schmidt form in exact
+// arithmetic.  Its rounding (about sqrt(eps_64) of a row's norm once the
+// residuals are small) stays below the FP32 rounding that M already
+// carries, and d_i is clamped at zero.  The FP64 rows, their Gram matrix
+// (FP64 MFMA) and one workgroup per box running all k steps replace the k
+// launches of the Gram-Schmidt form; the R entries, pivots and selection
+// marks it leaves are the ones id_finalize_kernel reads.
+
+// Row i in FP64 (M_Y + M_Z summed when MZ is set), and |[Y_B Z_B] row i|^2
+// for a rank tolerance.
+__global__ __launch_bounds__(64) void id_gram_rows_kernel(const IdDesc* __restrict__ e) {
+  const IdDesc d = e[blockIdx.y];
+  const int i = blockIdx.x;
+  if (i >= d.b) return;
+  const float* mi = static_cast<const float*>(d.M) + (int64_t)i * d.ldm;
+  const float* mz = d.MZ ? static_cast<const float*>(d.MZ) + (int64_t)i * d.ldz : nullptr;
+  double* out = d.Md + (int64_t)i * d.ldmd;
+  for (int c = threadIdx.x; c < d.s; c += 64) {
+    float v = mi[c];
+    if (mz) v = (float)((double)v + (double)mz[c]);   // the sum as the Gram-Schmidt form stores it
+    out[c] = (double)v;
+  }
+  if (threadIdx.x == 0) d.sel[i] = INT_MAX;
+  if (d.tol2 > 0.0) {
+    const int64_t gi = d.idx[i];
+    const float* yr = static_cast<const float*>(d.Yg) + gi * d.ldy;
+    const float* zr = d.Zg ? static_cast<const float*>(d.Zg) + gi * d.ldy : nullptr;
+    double q = 0.0;
+    for (int c = threadIdx.x; c < d.sy; c += 64) {
+      const double y = (double)yr[c];
+      q += y * y;
+      if (zr) {
+        const double z = (double)zr[c];
+        q += z * z;
+      }
+    }
+    q = wave_sum(q);
+    if (threadIdx.x == 0) d.rowyz[i] = q;
+  }
+}
+
+// All k steps of one box: 1024 threads, rows strided over the threads.
+__global__ __launch_bounds__(1024) void id_pchol_kernel(const IdDesc* __restrict__ e) {
+  const IdDesc d = e[blockIdx.x];
+  const int b = d.b, k = d.k, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int RPT = 5;   // rows per thread: b <= 5120
+  __shared__ double Lp[256];     // R[t, p] of the current pivot, t < j
+  __shared__ double wbest[16];
+  __shared__ int wrow[16];
+  __shared__ int piv_sh;
+  __shared__ double rjj_sh;
+  double dv[RPT];
+  int alive = 0;   // bit u: row tid + 1024 u still unselected
+#pragma unroll
+  for (int u = 0; u < RPT; ++u) {
+    const int i = tid + 1024 * u;
+    dv[u] = 0.0;
+    if (i < b) {
+      const double g = d.G[(int64_t)i * d.ldg + i];
+      dv[u] = g > 0.0 ? g : 0.0;
+      alive |= 1 << u;
+    }
+  }
+  for (int j = 0; j < k; ++j) {
+    // pivot: the largest d among unselected rows, lowest index on ties
+    double best = -1.0;
+    int bi = INT_MAX;
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+      const int i = tid + 1024 * u;
+      if ((alive >> u) & 1) {
+        if (dv[u] > best) { best = dv[u]; bi = i; }
+      }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ob = __shfl_xor(best, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      const bool take = oi != INT_MAX && (bi == INT_MAX || ob > best || (ob == best && oi < bi));
+      best = take ? ob : best;
+      bi = take ? oi : bi;
+    }
+    if (lane == 0) { wbest[wave] = best; wrow[wave] = bi; }
+    __syncthreads();
+    if (tid == 0) {
+      double bb = -1.0;
+      int br = INT_MAX;
+      for (int w = 0; w < 16; ++w) {
+        const int oi = wrow[w];
+        const double ob = wbest[w];
+        if (oi != INT_MAX && (br == INT_MAX || ob > bb || (ob == bb && oi < br))) { bb = ob; br = oi; }
+      }
+      // j < k <= b rows remain, so br is a row
+      const double r = sqrt(bb > 0.0 ? bb : 0.0);
+      piv_sh = br;
+      rjj_sh = r;
+      d.sel[br] = j;
+      d.piv[j] = br;
+      d.Rc[(int64_t)br * k + j] = r;
+    }
+    __syncthreads();
+    const int p = piv_sh;
+    const double rjj = rjj_sh;
+    for (int t = tid; t < j; t += 1024) Lp[t] = d.Rc[(int64_t)p * k + t];
+#pragma unroll
+    for (int u = 0; u < RPT; ++u)
+      if (tid + 1024 * u == p) alive &= ~(1 << u);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+      if (!((alive >> u) & 1)) continue;
+      const int i = tid + 1024 * u;
+      double c = i >= p ? d.G[(int64_t)i * d.ldg + p] : d.G[(int64_t)p * d.ldg + i];
+      const double* ri = d.Rc + (int64_t)i * k;
+      for (int t = 0; t < j; ++t) c -= ri[t] * Lp[t];
+      const double l = rjj > 0.0 ? c / rjj : 0.0;
+      d.Rc[(int64_t)i * k + j] = l;
+      const double nd = dv[u] - l * l;
+      dv[u] = nd > 0.0 ? nd : 0.0;
+    }
+    __syncthreads();
+  }
+}
+
+rsrs_status id_run_gram(Uploader& up, hipStream_t st, const std::vector<IdDesc>& e) {
+  if (e.empty()) return RSRS_OK;
+  int bmax = 0;
+  for (const auto& x : e) {
+    if (x.k > 256 || x.b > 4352 || x.k > x.b || x.k < 1 || !x.Md || !x.G) {
+      set_error("ID (Gram route) sizes out of range (need 1 <= k <= b <= 4352, k <= 256)");
+      return RSRS_E_UNSUPPORTED;
+    }
+    bmax = std::max(bmax, x.b);
+  }
+  IdDesc* de = nullptr;
+  RSRS_TRY(up.put_vec(e, &de));
+  const unsigned nb = (unsigned)e.size();
+  double rbytes = 0.0, gflops = 0.0;
+  for (const auto& x : e) {
+    rbytes += 12.0 * x.b * x.s;
+    gflops += (double)x.b * (x.b + 1) * x.s;
+  }
+  {
+    ProfScope ps(st, "id_gram_rows", 0.0, rbytes);
+    hipLaunchKernelGGL(id_gram_rows_kernel, dim3((unsigned)bmax, nb), dim3(64), 0, st, de);
+    RSRS_HIP(hipGetLastError());
+  }
+  std::vector<GemmDesc> g;
+  for (const auto& x : e)
+    g.push_back(gdesc(x.Md, nullptr, x.ldmd, x.Md, nullptr, x.ldmd, x.G, nullptr, x.ldg, x.b, x.b, x.s));
+  RSRS_TRY(gemm(up, st, g, 0, 1, GM_SYRK_L, GS_64x64, "id_gram"));
+  {
+    double f = 0.0;
+    for (const auto& x : e) f += 2.0 * x.b * x.k * x.k;
+    ProfScope ps(st, "id_pchol", f, 0.0);
+    hipLaunchKernelGGL(id_pchol_kernel, dim3(nb), dim3(1024), 0, st, de);
+    RSRS_HIP(hipGetLastError());
+  }
+  {
+    ProfScope ps(st, "id_finalize");
+    hipLaunchKernelGGL(id_finalize_kernel, dim3(nb), dim3(256), 0, st, de);
+    RSRS_HIP(hipGetLastError());
+  }
+  (void)gflops;
+  return RSRS_OK;
+}
+
 // ---------------------------------------------------------------- column fix-up
 // Xp[i][c] for output columns [R, S, N]:
 //   c <  r      : XR[i][Rpos[c]] - sum_t XR[i][Spos[t]] T[c][t]

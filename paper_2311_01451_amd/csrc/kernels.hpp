@@ -44,6 +44,8 @@ struct GemmLaunch {
   dim3 grid, block;
   size_t first;
   double flops, bytes;   // algorithmic work (for the measurement tags)
+  uint64_t sig;          // shape signature of the whole product (tile tuning)
+  int shape;             // tile shape planned (0 64x64, 1 128x64, 2 128x128, 3 64x16)
   char tag[48];
 };
 // Plans descs (whose first element sits at index `base` of the caller's array);
@@ -55,6 +57,16 @@ rsrs_status gemm_plan(const std::vector<GemmDescT<TI, TO>>& descs, size_t base, 
 // for every automatic launch (-1: table or rule, -2: forget the table).
 rsrs_status gemm_autotune(const char* cache_path, int64_t* entries, int64_t* changed);
 rsrs_status gemm_tile_override(int shape);
+// Workload tuning: while recording, every automatic launch is timed by HIP
+// events under its product's shape signature; gemm_sig_collect sums the
+// recorded milliseconds per signature (and the shape each one took) once the
+// work has finished; gemm_sig_install makes the given shape serve each
+// signature from then on (an exact match overrides the class table).
+void gemm_sig_record(bool on);
+rsrs_status gemm_sig_collect(std::vector<std::pair<uint64_t, double>>& ms,
+                             std::vector<std::pair<uint64_t, int>>& shape);
+void gemm_sig_install(const std::vector<std::pair<uint64_t, int>>& table, bool replace);
+int64_t gemm_sig_count();
 // Launches one record; descs is the device copy of the caller's array.
 rsrs_status gemm_exec(const GemmLaunch& L, const void* descs, size_t desc_bytes, hipStream_t st);
 // Instantiated for <double, double> and <float, float> (all forms).
@@ -183,9 +195,17 @@ struct IdDesc {
   int64_t ldy;
   int sy;
   int b, s, k, ldt;   // k: steps (k_B <= k <= b)
+  // Gram route (FP32 rows): the rows in FP64 (b x s, leading dimension
+  // ldmd) and their Gram matrix M M^T (b x b, lower part, leading dimension ldg)
+  double* Md;
+  double* G;
+  int64_t ldmd, ldg;
 };
 
 rsrs_status id_run(Uploader& up, hipStream_t st, const std::vector<IdDesc>& e, bool fp32);
+// FP32 rows only: the same decomposition through the FP64 Gram matrix of the
+// rows (pivoted Cholesky, all steps of a box in one workgroup).
+rsrs_status id_run_gram(Uploader& up, hipStream_t st, const std::vector<IdDesc>& e);
 
 template <typename T>
 struct ColfixDescT {

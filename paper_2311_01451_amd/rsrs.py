@@ -95,7 +95,8 @@ MATVEC_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int, C.c_int, C.c_int64, C.c_vo
 EXPORTS = [
     "rsrs_status_string", "rsrs_last_error", "rsrs_last_required_s", "rsrs_build_tree",
     "rsrs_tree_destroy", "rsrs_tree_get_info", "rsrs_tree_neighbours", "rsrs_tree_schedule",
-    "rsrs_samples_required", "rsrs_work_model", "rsrs_gemm_autotune", "rsrs_gemm_tile_override", "rsrs_op_create_kernel", "rsrs_op_create_dense",
+    "rsrs_samples_required", "rsrs_work_model", "rsrs_gemm_autotune", "rsrs_gemm_autotune_workload",
+    "rsrs_gemm_tile_override", "rsrs_op_create_kernel", "rsrs_op_create_dense",
     "rsrs_op_create_poisson7", "rsrs_op_matvec", "rsrs_op_destroy", "rsrs_samples_wrap",
     "rsrs_sample", "rsrs_sample_symmetric", "rsrs_samples_wrap_symmetric", "rsrs_samples_destroy", "rsrs_gaussian", "rsrs_factor", "rsrs_factor_batched",
     "rsrs_factor_destroy", "rsrs_release_cached",
@@ -116,6 +117,15 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: run `python -m paper_2311_01451_amd.build` "
                            "(there is no non-HIP fallback)")
+    # PyTorch's wheel carries its own HIP runtime beside the one this library
+    # links; the device tensors passed in are torch's, and torch's runtime
+    # finds no device once the other one has opened it, so it goes first.
+    try:
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.init()
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     vp, i64, i32, dbl = C.c_void_p, C.c_int64, C.c_int, C.c_double
     P = C.POINTER
@@ -132,6 +142,7 @@ def lib():
         "rsrs_work_model": (i32, [vp, P(FactorOpts), i64, i32, P(dbl), P(dbl), P(i64)]),
         "rsrs_gemm_autotune": (i32, [C.c_char_p, P(i64), P(i64)]),
         "rsrs_gemm_tile_override": (i32, [i32]),
+        "rsrs_gemm_autotune_workload": (i32, [vp, P(FactorOpts), i64, P(i64), P(i64)]),
         "rsrs_op_create_kernel": (i32, [i32, P(C.c_double), i64, i32, dbl, dbl, P(vp)]),
         "rsrs_op_create_dense": (i32, [vp, i64, i64, P(vp)]),
         "rsrs_op_create_poisson7": (i32, [i32, P(C.c_double), P(vp)]),
@@ -306,6 +317,18 @@ def rsrs_gemm_autotune(cache_path: str | None = None) -> dict:
     e, c = C.c_int64(), C.c_int64()
     _check(lib().rsrs_gemm_autotune(cache_path.encode() if cache_path else None, C.byref(e), C.byref(c)))
     return {"classes": e.value, "changed": c.value}
+
+
+def rsrs_gemm_autotune_workload(tree: Tree, k: int, s: int, precision: int = RSRS_PREC_F64,
+                                symmetric: bool = False, p: int = -1, reproject: int = 1, id_mode: int = 0,
+                                col_subset: bool = False) -> dict:
+    """Times the factorization of this workload under each tile shape and
+    keeps, per GEMM shape signature, the fastest; returns the number of
+    signatures and how many moved from the current choice."""
+    o = FactorOpts(int(k), int(p), precision, reproject, int(symmetric), int(id_mode), 0.0, int(col_subset))
+    n, c = C.c_int64(), C.c_int64()
+    _check(lib().rsrs_gemm_autotune_workload(tree.handle, C.byref(o), int(s), C.byref(n), C.byref(c)))
+    return {"signatures": n.value, "changed": c.value}
 
 
 def rsrs_gemm_tile_override(shape: int) -> None:

@@ -91,3 +91,25 @@ def test_tile_shapes_do_not_change_results(mixed, tmp_path):
     with pytest.raises(rsrs.RSRSError) as e:
         rsrs.rsrs_gemm_tile_override(3)
     assert e.value.status == 1
+
+
+def test_workload_tuning_keeps_results():
+    """Tuning on the workload itself (the factorization of the 64 x 64 grid at
+    k = 32 run under each tile shape, every launch timed by its shape
+    signature): the tuned factorization is bit for bit the untuned one."""
+    need_gpu()
+    rsrs.rsrs_gemm_tile_override(-2)
+    try:
+        for mixed in (False, True):
+            ref = _factor_and_solve(mixed)
+            tc = rsrs.rsrs_build_tree(inputs.grid2d(64), 64)
+            s = tc.samples_required(32, 32)
+            prec = rsrs.RSRS_PREC_F32_MIXED if mixed else rsrs.RSRS_PREC_F64
+            a = time.perf_counter()
+            r = rsrs.rsrs_gemm_autotune_workload(tc, 32, s, precision=prec, symmetric=mixed)
+            print(f"[autotune workload] mixed={mixed}: {r['signatures']} signatures, {r['changed']} moved, "
+                  f"{time.perf_counter() - a:.2f} s", flush=True)
+            assert r["signatures"] > 0
+            _same(ref, _factor_and_solve(mixed))
+    finally:
+        rsrs.rsrs_gemm_tile_override(-2)
