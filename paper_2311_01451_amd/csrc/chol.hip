@@ -512,7 +512,7 @@ rsrs_status chol_inverse(Uploader& up, hipStream_t st, const std::vector<CholMat
     for (const auto& L : cl[j]) RSRS_TRY(gemm_exec(L, dc, sizeof(GD), st));
     const unsigned nt = (unsigned)(toff[j + 1] - toff[j]);
     {
-      ProfScope ps(st, "chol_panel", pflops[j], 0.0);
+      ProfScope ps(st, sizeof(T) == 4 ? "chol32_panel" : "chol_panel", pflops[j], 0.0);
       hipLaunchKernelGGL((chol_panel_kernel<T, fused>), dim3(nt), dim3(256), 0, st, dt + toff[j], flag);
       RSRS_HIP(hipGetLastError());
     }

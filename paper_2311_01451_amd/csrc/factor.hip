@@ -273,7 +273,7 @@ void box_ws_bytes(int64_t b, int64_t l, int64_t k, int64_t r, int64_t sp, size_t
                  + 4 * r * lp;     // XR, Xp for both sides
   if (mixed) {
     dblA += r * round_up(k, 4);    // T as computed by the ID
-    dblA += b * 2 * sp + b * round_up(b, 16);   // the ID's FP64 rows (up to 2 sp long) and their Gram matrix
+    dblA += b * 2 * sp + kIdGramSplit * b * round_up(b, 16) + b * k;   // the ID's FP64 rows (up to 2 sp long), partial Gram matrices, R
     dblB += 2 * r * r;             // X_RR and its inverse in FP64
   }
   const int64_t ints = b + k;      // sel, piv (int32)
@@ -293,7 +293,7 @@ struct BoxWs {
   int32_t *sel, *piv;
   int64_t *Spos, *Rpos, *kB;
   int64_t mld;                  // leading dimension of M_Y, M_Z
-  double *Md, *Gm;              // mixed precision: the ID's FP64 rows and their Gram matrix
+  double *Md, *Gm, *Rt;         // mixed precision: the ID's FP64 rows, their Gram matrix, R column-major
   int64_t ldmd, ldg;
 };
 
@@ -752,10 +752,11 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
         w.ldmd = round_up(srow, 16);
         w.ldg = round_up(b, 16);
         w.Md = bump.take<double>(b * w.ldmd);
-        w.Gm = bump.take<double>(b * w.ldg);
+        w.Gm = bump.take<double>(kIdGramSplit * b * w.ldg);   // the partial Gram matrices of the ID
+        w.Rt = bump.take<double>(b * k);                         // its R entries, column-major
       } else {
         w.Td = w.XRRd = w.Xinvd = nullptr;
-        w.Md = w.Gm = nullptr;
+        w.Md = w.Gm = w.Rt = nullptr;
         w.ldmd = w.ldg = 0;
       }
     }
@@ -873,7 +874,7 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
         e.tol2 = J.rank_tol > 0.0 ? J.rank_tol * J.rank_tol * (J.sym ? 0.25 * 2.0 : 1.0) : 0.0;
         e.rowyz = w.norms + 2 * R.b;
         e.Yg = J.Y; e.Zg = J.sym ? nullptr : J.Z; e.idx = J.iS + R.oBa; e.ldy = J.sld; e.sy = sb;
-        e.Md = w.Md; e.G = w.Gm; e.ldmd = w.ldmd; e.ldg = w.ldg;
+        e.Md = w.Md; e.G = w.Gm; e.Rt = w.Rt; e.ldmd = w.ldmd; e.ldg = w.ldg;
         idd.push_back(e);
         it.J->flops += 4.0 * R.b * e.s * R.k;
       }

@@ -468,6 +468,9 @@ rsrs_status id_run(Uploader& up, hipStream_t st, const std::vector<IdDesc>& e, b
 // launches of the Gram-Schmidt form; the R entries, pivots and selection
 // marks it leaves are the ones id_finalize_kernel reads.
 
+constexpr int kGramSplit = kIdGramSplit;   // partial Gram matrices per box (column ranges of the rows)
+constexpr int kGramRows = 2048;            // largest b of the Gram route (the rows stay in registers)
+
 // Row i in FP64 (M_Y + M_Z summed when MZ is set), and |[Y_B Z_B] row i|^2
 // for a rank tolerance.
 __global__ __launch_bounds__(64) void id_gram_rows_kernel(const IdDesc* __restrict__ e) {
@@ -501,16 +504,24 @@ __global__ __launch_bounds__(64) void id_gram_rows_kernel(const IdDesc* __restri
   }
 }
 
-// All k steps of one box: 1024 threads, rows strided over the threads.
-__global__ __launch_bounds__(1024) void id_pchol_kernel(const IdDesc* __restrict__ e) {
+// All k steps of one box: 1024 threads, rows strided over the threads.  The
+// Gram matrix arrives as NG full partial sums over column ranges of the
+// rows (G = sum_q G_q, each b x ldg, NG apart by gstride), added here in a
+// fixed order; its symmetry lets row p stand for column p, so each step
+// reads the pivot's row, contiguous across the threads.  The R entries are
+// kept twice: row-major in Rc (what the finalisation reads) and
+// column-major in Rt (b apart), where the dot product of step j reads
+// entry t of every row at consecutive addresses.  One barrier per step:
+// after it every thread reduces the 16 wave maxima itself, so all agree on
+// the pivot without a second exchange.
+template <int NG>
+__global__ __launch_bounds__(1024) void id_pchol_kernel(const IdDesc* __restrict__ e, int64_t gstride) {
   const IdDesc d = e[blockIdx.x];
   const int b = d.b, k = d.k, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  constexpr int RPT = 5;   // rows per thread: b <= 5120
-  __shared__ double Lp[256];     // R[t, p] of the current pivot, t < j
-  __shared__ double wbest[16];
-  __shared__ int wrow[16];
-  __shared__ int piv_sh;
-  __shared__ double rjj_sh;
+  constexpr int RPT = kGramRows / 1024;   // rows per thread
+  __shared__ double wbest[2][16];
+  __shared__ int wrow[2][16];
+  double* Rt = d.Rt;
   double dv[RPT];
   int alive = 0;   // bit u: row tid + 1024 u still unselected
 #pragma unroll
@@ -518,22 +529,23 @@ __global__ __launch_bounds__(1024) void id_pchol_kernel(const IdDesc* __restrict
     const int i = tid + 1024 * u;
     dv[u] = 0.0;
     if (i < b) {
-      const double g = d.G[(int64_t)i * d.ldg + i];
+      double g = 0.0;
+#pragma unroll
+      for (int q = 0; q < NG; ++q) g += d.G[(int64_t)i * d.ldg + i + q * gstride];
       dv[u] = g > 0.0 ? g : 0.0;
       alive |= 1 << u;
     }
   }
   for (int j = 0; j < k; ++j) {
-    // pivot: the largest d among unselected rows, lowest index on ties
+    // this thread's candidates, then the wave's (lowest index on ties)
     double best = -1.0;
     int bi = INT_MAX;
 #pragma unroll
-    for (int u = 0; u < RPT; ++u) {
-      const int i = tid + 1024 * u;
-      if ((alive >> u) & 1) {
-        if (dv[u] > best) { best = dv[u]; bi = i; }
+    for (int u = 0; u < RPT; ++u)
+      if (((alive >> u) & 1) && dv[u] > best) {
+        best = dv[u];
+        bi = tid + 1024 * u;
       }
-    }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
       const double ob = __shfl_xor(best, off, 64);
@@ -542,54 +554,73 @@ __global__ __launch_bounds__(1024) void id_pchol_kernel(const IdDesc* __restrict
       best = take ? ob : best;
       bi = take ? oi : bi;
     }
-    if (lane == 0) { wbest[wave] = best; wrow[wave] = bi; }
-    __syncthreads();
-    if (tid == 0) {
-      double bb = -1.0;
-      int br = INT_MAX;
-      for (int w = 0; w < 16; ++w) {
-        const int oi = wrow[w];
-        const double ob = wbest[w];
-        if (oi != INT_MAX && (br == INT_MAX || ob > bb || (ob == bb && oi < br))) { bb = ob; br = oi; }
-      }
-      // j < k <= b rows remain, so br is a row
-      const double r = sqrt(bb > 0.0 ? bb : 0.0);
-      piv_sh = br;
-      rjj_sh = r;
-      d.sel[br] = j;
-      d.piv[j] = br;
-      d.Rc[(int64_t)br * k + j] = r;
+    // double-buffered by step parity: a fast wave of the next step cannot
+    // overwrite what a slow one still reads
+    if (lane == 0) {
+      wbest[j & 1][wave] = best;
+      wrow[j & 1][wave] = bi;
     }
     __syncthreads();
-    const int p = piv_sh;
-    const double rjj = rjj_sh;
-    for (int t = tid; t < j; t += 1024) Lp[t] = d.Rc[(int64_t)p * k + t];
+    double bb = -1.0;
+    int p = INT_MAX;
 #pragma unroll
-    for (int u = 0; u < RPT; ++u)
-      if (tid + 1024 * u == p) alive &= ~(1 << u);
-    __syncthreads();
+    for (int w = 0; w < 16; ++w) {
+      const int oi = wrow[j & 1][w];
+      const double ob = wbest[j & 1][w];
+      if (oi != INT_MAX && (p == INT_MAX || ob > bb || (ob == bb && oi < p))) {
+        bb = ob;
+        p = oi;
+      }
+    }
+    // j < k <= b rows remain, so p is a row
+    const double rjj = sqrt(bb > 0.0 ? bb : 0.0);
+    const double* gp = d.G + (int64_t)p * d.ldg;
 #pragma unroll
     for (int u = 0; u < RPT; ++u) {
       if (!((alive >> u) & 1)) continue;
       const int i = tid + 1024 * u;
-      double c = i >= p ? d.G[(int64_t)i * d.ldg + p] : d.G[(int64_t)p * d.ldg + i];
-      const double* ri = d.Rc + (int64_t)i * k;
-      for (int t = 0; t < j; ++t) c -= ri[t] * Lp[t];
+      if (i == p) {
+        alive &= ~(1 << u);
+        d.sel[p] = j;
+        d.piv[j] = p;
+        d.Rc[(int64_t)p * k + j] = rjj;
+        Rt[(int64_t)j * b + p] = rjj;
+        continue;
+      }
+      // the pivot row's entries t < j were written in earlier steps, before
+      // this step's barrier
+      double c = 0.0;
+#pragma unroll
+      for (int q = 0; q < NG; ++q) c += gp[i + q * gstride];
+      double c1 = 0.0, c2 = 0.0;
+      int t = 0;
+      for (; t + 1 < j; t += 2) {
+        c1 += Rt[(int64_t)t * b + i] * Rt[(int64_t)t * b + p];
+        c2 += Rt[(int64_t)(t + 1) * b + i] * Rt[(int64_t)(t + 1) * b + p];
+      }
+      if (t < j) c1 += Rt[(int64_t)t * b + i] * Rt[(int64_t)t * b + p];
+      c -= c1 + c2;
       const double l = rjj > 0.0 ? c / rjj : 0.0;
       d.Rc[(int64_t)i * k + j] = l;
+      Rt[(int64_t)j * b + i] = l;
       const double nd = dv[u] - l * l;
       dv[u] = nd > 0.0 ? nd : 0.0;
     }
-    __syncthreads();
   }
 }
 
-rsrs_status id_run_gram(Uploader& up, hipStream_t st, const std::vector<IdDesc>& e) {
+rsrs_status id_run_gram(Uploader& up, hipStream_t st, const std::vector<IdDesc>& all) {
+  if (all.empty()) return RSRS_OK;
+  // boxes with more rows than the Gram route holds take the Gram-Schmidt
+  // form (a box's route depends on its own size only)
+  std::vector<IdDesc> e, big;
+  for (const auto& x : all) (x.b <= kGramRows ? e : big).push_back(x);
+  if (!big.empty()) RSRS_TRY(id_run(up, st, big, true));
   if (e.empty()) return RSRS_OK;
   int bmax = 0;
   for (const auto& x : e) {
-    if (x.k > 256 || x.b > 4352 || x.k > x.b || x.k < 1 || !x.Md || !x.G) {
-      set_error("ID (Gram route) sizes out of range (need 1 <= k <= b <= 4352, k <= 256)");
+    if (x.k > 256 || x.k > x.b || x.k < 1 || !x.Md || !x.G || !x.Rt) {
+      set_error("ID (Gram route) sizes out of range (need 1 <= k <= b, k <= 256)");
       return RSRS_E_UNSUPPORTED;
     }
     bmax = std::max(bmax, x.b);
@@ -597,33 +628,53 @@ rsrs_status id_run_gram(Uploader& up, hipStream_t st, const std::vector<IdDesc>&
   IdDesc* de = nullptr;
   RSRS_TRY(up.put_vec(e, &de));
   const unsigned nb = (unsigned)e.size();
-  double rbytes = 0.0, gflops = 0.0;
-  for (const auto& x : e) {
-    rbytes += 12.0 * x.b * x.s;
-    gflops += (double)x.b * (x.b + 1) * x.s;
-  }
+  double rbytes = 0.0;
+  for (const auto& x : e) rbytes += 12.0 * x.b * x.s;
   {
     ProfScope ps(st, "id_gram_rows", 0.0, rbytes);
     hipLaunchKernelGGL(id_gram_rows_kernel, dim3((unsigned)bmax, nb), dim3(64), 0, st, de);
     RSRS_HIP(hipGetLastError());
   }
+  // the Gram matrices as kGramSplit partial sums over column ranges (a long
+  // K and few output tiles per box: the split keeps the chip busy); every
+  // box's split depends on its own sizes only
   std::vector<GemmDesc> g;
-  for (const auto& x : e)
-    g.push_back(gdesc(x.Md, nullptr, x.ldmd, x.Md, nullptr, x.ldmd, x.G, nullptr, x.ldg, x.b, x.b, x.s));
-  RSRS_TRY(gemm(up, st, g, 0, 1, GM_SYRK_L, GS_64x64, "id_gram"));
+  for (const auto& x : e) {
+    const int step = (int)round_up((x.s + kGramSplit - 1) / kGramSplit, 16);
+    for (int q = 0; q < kGramSplit; ++q) {
+      const int c0 = std::min(x.s, q * step), c1 = std::min(x.s, (q + 1) * step);
+      g.push_back(gdesc(x.Md + c0, nullptr, x.ldmd, x.Md + c0, nullptr, x.ldmd, x.G + q * x.b * x.ldg, nullptr,
+                        x.ldg, x.b, x.b, c1 - c0));
+    }
+  }
+  // both triangles: the pivot's column is then read as its row
+  RSRS_TRY(gemm(up, st, g, 0, 1, GM_FULL, GS_64x64, "id_gram"));
   {
     double f = 0.0;
     for (const auto& x : e) f += 2.0 * x.b * x.k * x.k;
     ProfScope ps(st, "id_pchol", f, 0.0);
-    hipLaunchKernelGGL(id_pchol_kernel, dim3(nb), dim3(1024), 0, st, de);
-    RSRS_HIP(hipGetLastError());
+    // partial sums of box x lie b * ldg apart: one stride per launch needs
+    // equal (b, ldg), so boxes are launched in groups of equal stride
+    std::vector<std::pair<int64_t, std::vector<IdDesc>>> groups;
+    for (const auto& x : e) {
+      const int64_t gs = (int64_t)x.b * x.ldg;
+      auto it = std::find_if(groups.begin(), groups.end(), [&](const auto& gr) { return gr.first == gs; });
+      if (it == groups.end()) groups.push_back({gs, {x}});
+      else it->second.push_back(x);
+    }
+    for (const auto& gr : groups) {
+      IdDesc* dg = nullptr;
+      RSRS_TRY(up.put_vec(gr.second, &dg));
+      hipLaunchKernelGGL((id_pchol_kernel<kGramSplit>), dim3((unsigned)gr.second.size()), dim3(1024), 0, st, dg,
+                         gr.first);
+      RSRS_HIP(hipGetLastError());
+    }
   }
   {
     ProfScope ps(st, "id_finalize");
     hipLaunchKernelGGL(id_finalize_kernel, dim3(nb), dim3(256), 0, st, de);
     RSRS_HIP(hipGetLastError());
   }
-  (void)gflops;
   return RSRS_OK;
 }
 

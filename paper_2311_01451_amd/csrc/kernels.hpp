@@ -199,12 +199,15 @@ struct IdDesc {
   // ldmd) and their Gram matrix M M^T (b x b, lower part, leading dimension ldg)
   double* Md;
   double* G;
+  double* Rt;   // the R entries column-major (k x b), scratch of the Gram route
   int64_t ldmd, ldg;
 };
 
 rsrs_status id_run(Uploader& up, hipStream_t st, const std::vector<IdDesc>& e, bool fp32);
 // FP32 rows only: the same decomposition through the FP64 Gram matrix of the
-// rows (pivoted Cholesky, all steps of a box in one workgroup).
+// rows (pivoted Cholesky, all steps of a box in one workgroup).  G holds
+// kIdGramSplit partial Gram matrices (b x ldg each, back to back).
+constexpr int kIdGramSplit = 4;
 rsrs_status id_run_gram(Uploader& up, hipStream_t st, const std::vector<IdDesc>& e);
 
 template <typename T>
