@@ -194,10 +194,14 @@ def by_kernel(prof: dict) -> dict:
 # dominant one: tag -> committed summary (kernel name, bytes per launch and
 # the hash of the source the kernel was built from when measured)
 TRAFFIC_FILES = {
-    "id_step": os.path.join(ROOT, "profiles", "id_step_65k_log2d_mixed_traffic.json"),
-    "gemm32_nn_full_128x128": os.path.join(ROOT, "profiles", "gemm32_nn_128x128_65k_log2d_mixed_traffic.json"),
+    "chol32_panel": os.path.join(ROOT, "profiles", "chol32_panel_65k_log2d_mixed_traffic.json"),
+    "gemm32_nt_syrk_128x128": os.path.join(ROOT, "profiles", "gemm32_syrk_128x128_65k_log2d_mixed_traffic.json"),
+    "gemm32_nt_syrk_64x64": os.path.join(ROOT, "profiles", "gemm32_syrk_64x64_65k_log2d_mixed_traffic.json"),
+    "gemm32_nn_full_64x64": os.path.join(ROOT, "profiles", "gemm32_nn_64x64_65k_log2d_mixed_traffic.json"),
+    "gemm_bf16_nt_256x256": os.path.join(ROOT, "profiles", "gemm_bf16_nt256_65k_log2d_mixed_traffic.json"),
+    "gauss_jordan_blk": os.path.join(ROOT, "profiles", "gje_blk_65k_log2d_mixed_traffic.json"),
+    "id_pchol": os.path.join(ROOT, "profiles", "id_pchol_65k_log2d_mixed_traffic.json"),
     "gemm_nn_full_128x128": os.path.join(ROOT, "profiles", "gemm_f64_nn_128x128_65k_log2d_fp64_traffic.json"),
-    "gauss_jordan_reg": os.path.join(ROOT, "profiles", "gje_reg_65k_log2d_mixed_traffic.json"),
 }
 # machine balance of MI355X in FP64 (flops per HBM byte): below it a kernel
 # is priced against HBM bandwidth
