@@ -334,6 +334,25 @@ rsrs_status rsrs_gemm_autotune_workload(const rsrs_tree_t* t, const rsrs_factor_
 
 rsrs_status rsrs_factor(const rsrs_tree_t* t, rsrs_samples_t* smp, const rsrs_factor_opts* opts,
                         void* stream, rsrs_factor_t** out);
+/* Sampling and factorization with the samples redrawn at the start of every
+ * processed level after the first (Sec. 4.4: the approximation errors of a
+ * fixed set of sketches accumulate from level to level).  The first samples
+ * are those of rsrs_sample / rsrs_sample_symmetric (mv, user, s, seed,
+ * dtype; opts.symmetric selects which).  The boxes processed so far have
+ * turned A into V^{-1} A W^{-1} (eq. tildeA_diag), and the updated sketches
+ * are a sample pair of it (Sec. 1.1).  A redraw replaces them by a fresh
+ * pair of the same operator: Omega' Gaussian (Philox as in rsrs_sample, rows
+ * in tree order, word 2r for the r-th redraw) and Y' = V^{-1} A W^{-1} Omega'.
+ * For the general variant also Psi' (word 2r + 1) and
+ * Z' = W^{-T} A^T V^{-T} Psi'. W^{-1} and V^{-1} are the downward and upward
+ * sweeps of eq. Ainvfact over the processed boxes, and mv gets and returns
+ * blocks in user point order (FP64 for the FP64 factorization, FP32 for the
+ * mixed one, whatever the first samples' dtype).  Each redraw costs one
+ * product with A (and one with A^T) of s columns.  Fixed rank or rank_tol
+ * as in opts.  Errors: those of rsrs_sample and rsrs_factor; RSRS_E_CALLBACK
+ * when mv fails during a redraw. */
+rsrs_status rsrs_factor_redraw(const rsrs_tree_t* t, rsrs_matvec_fn mv, void* user, int64_t s, uint64_t seed,
+                               int dtype, const rsrs_factor_opts* opts, void* stream, rsrs_factor_t** out);
 /* Many independent problems factored together (Algorithm 1 on each): trees,
  * samples and opts are arrays of nprob entries (each problem its own N, tree,
  * s and k; all of one precision); out receives nprob factors.  The problems

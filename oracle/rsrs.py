@@ -146,7 +146,7 @@ def row_id(M: np.ndarray, k: int, want_r11_min: bool = False, rank_tol: float = 
 def factor(tree: otree.Tree, Y, Z, Om, Psi, k: int, p: int | None = None,
            keep_M: bool = False, check_samples: bool = True, on_box=None,
            symmetric: bool = False, id_mode: str = "sum", rank_tol: float = 0.0,
-           col_subset: bool = False) -> Factorization:
+           col_subset: bool = False, redraw: dict | None = None) -> Factorization:
     """Algorithm 1 on sketches given in user point order (N x s each).
 
     The caller's arrays are not modified; the oracle works on tree-ordered
@@ -170,7 +170,19 @@ def factor(tree: otree.Tree, Y, Z, Om, Psi, k: int, p: int | None = None,
     all s columns.  The first s_B columns of a sample pair are a sample pair
     of the same operator (Sec. 1.1), and s_B - l = k + p is the null-space
     dimension the required sample count of Sec. 4.5 gives every box; the
-    variant trades the oversampling of boxes with small l for work."""
+    variant trades the oversampling of boxes with small l for work.
+
+    ``redraw`` = {"matvec": f, "rmatvec": g, "seed": q}: fresh samples at the
+    start of every processed level after the first, against the error the
+    fixed sketches carry from level to level (Sec. 4.4).  The boxes processed
+    so far have turned A into V^{-1} A W^{-1} (eq. tildeA_diag), and the
+    updated sketches are a sample pair of it (Sec. 1.1); a fresh pair of the
+    same operator is Omega' (drawn), Y' = V^{-1} A W^{-1} Omega' and, for
+    the general variant, Psi', Z' = W^{-T} A^T V^{-T} Psi', with W^{-1}, V^{-1}
+    the downward and upward passes of eq. Ainvfact over the processed boxes
+    and A applied by f (g for A^T) to blocks in user point order.  The r-th
+    redraw takes Omega' and Psi' from ``philox.gaussian`` with words 2 r and
+    2 r + 1 (rows in tree order)."""
     if id_mode not in ("sum", "concat"):
         raise ValueError("id_mode must be 'sum' or 'concat'")
     if p is None:
@@ -193,9 +205,13 @@ def factor(tree: otree.Tree, Y, Z, Om, Psi, k: int, p: int | None = None,
     nbox = tree.nbox
     remaining = [None] * nbox
     boxes_out = []
+    redraws = 0
     for li, lev in enumerate(sch.levels):
         classes = sch.order[li]
         nb = sch.nbrs[lev]
+        if redraw is not None and classes and boxes_out:
+            redraws += 1
+            _redraw(boxes_out, perm, Y, Z, Om, Psi, symmetric, redraw, redraws)
         cur = {}
         for b in tree.level_boxes[lev]:
             b = int(b)
@@ -232,6 +248,43 @@ def factor(tree: otree.Tree, Y, Z, Om, Psi, k: int, p: int | None = None,
         At = 0.5 * (At + At.T)
     return Factorization(tree=tree, k=k, p=p, s=s, boxes=boxes_out, Bt=Bt, At=At,
                          At_lu=sla.lu_factor(At) if len(Bt) else None, perm=perm)
+
+
+def _redraw(boxes, perm, Y, Z, Om, Psi, symmetric, rd, r):
+    """Fresh sample pair(s) of V^{-1} A W^{-1} over the processed boxes, in
+    place in the tree-ordered sketches (see ``factor``)."""
+    from . import philox
+    N, s = Y.shape
+
+    def user(x):
+        out = np.empty_like(x)
+        out[perm] = x
+        return out
+
+    Om_new = philox.gaussian(N, s, rd["seed"], 2 * r)
+    x = Om_new.copy()
+    for bf in reversed(boxes):          # W^{-1}: U then F, boxes in reverse order
+        x[bf.R] -= bf.KU @ x[bf.SN]
+        x[bf.S] -= bf.T.T @ x[bf.R]
+    y = np.asarray(rd["matvec"](user(x)), dtype=np.float64)[perm]
+    for bf in boxes:                    # V^{-1}: E then L
+        y[bf.R] -= bf.T @ y[bf.S]
+        y[bf.SN] -= bf.KL @ y[bf.R]
+    Om[:] = Om_new
+    Y[:] = y
+    if symmetric:
+        return
+    Psi_new = philox.gaussian(N, s, rd["seed"], 2 * r + 1)
+    x = Psi_new.copy()
+    for bf in reversed(boxes):          # V^{-T}: L^T then E^T, reverse order
+        x[bf.R] -= bf.KL.T @ x[bf.SN]
+        x[bf.S] -= bf.T.T @ x[bf.R]
+    z = np.asarray(rd["rmatvec"](user(x)), dtype=np.float64)[perm]
+    for bf in boxes:                    # W^{-T}: F^T then U^T
+        z[bf.R] -= bf.T @ z[bf.S]
+        z[bf.SN] -= bf.KU.T @ z[bf.R]
+    Psi[:] = Psi_new
+    Z[:] = z
 
 
 def _empty_box(box, lev, colour, Ba, Na, S) -> BoxFactor:

@@ -17,10 +17,6 @@ static thread_local int64_t g_req_s = -1;
 void set_error(const std::string& msg) { g_err = msg; }
 void set_required_s(int64_t s) { g_req_s = s; }
 
-rsrs_status factor_impl(const rsrs_tree_t* th, rsrs_samples_t* smp, const rsrs_factor_opts* o,
-                        hipStream_t st, rsrs_factor_t** out);
-rsrs_status factor_batch_impl(int64_t nprob, const rsrs_tree_t* const* trees, rsrs_samples_t* const* smps,
-                              const rsrs_factor_opts* opts, hipStream_t st, rsrs_factor_t** out);
 rsrs_status apply_factor_noalloc(const rsrs_factor_t* F, int op, int transpose, int64_t w, const double* Fin,
                                  int64_t ldf, double* Uout, int64_t ldu, hipStream_t st);
 rsrs_status apply_factor(const rsrs_factor_t* F, int op, int transpose, int64_t w, const double* Fin,
@@ -529,6 +525,20 @@ rsrs_status rsrs_gemm_autotune_workload(const rsrs_tree_t* t, const rsrs_factor_
 }
 
 // ------------------------------------------------------------------ factor
+rsrs_status rsrs_factor_redraw(const rsrs_tree_t* t, rsrs_matvec_fn mv, void* user, int64_t s, uint64_t seed,
+                               int dtype, const rsrs_factor_opts* opts, void* stream, rsrs_factor_t** out) {
+  if (!t || !mv || !opts || !out || s < 1) return invalid("null argument or s < 1");
+  *out = nullptr;
+  if ((opts->precision == RSRS_PREC_F64) != (dtype == RSRS_F64))
+    return invalid("FP64 factorization needs FP64 samples, the mixed one FP32 or BF16 samples");
+  rsrs_samples_t* smp = nullptr;
+  RSRS_TRY(sample_impl(t, mv, user, s, seed, dtype, stream, &smp, opts->symmetric != 0));
+  RedrawSpec rd{mv, user, seed};
+  const rsrs_status r = factor_impl(t, smp, opts, static_cast<hipStream_t>(stream), out, &rd);
+  delete smp;
+  return r;
+}
+
 rsrs_status rsrs_factor(const rsrs_tree_t* t, rsrs_samples_t* smp, const rsrs_factor_opts* opts,
                         void* stream, rsrs_factor_t** out) {
   if (!t || !smp || !opts || !out) return invalid("null argument");

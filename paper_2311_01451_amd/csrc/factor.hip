@@ -313,6 +313,12 @@ struct Job {
   double rank_tol = 0.0;        // > 0: k_B from the pivots' size (storage planned for k_B = 0)
   bool col_subset = false;      // a box reads its first s_B = min(s, l + k + p) sample columns
   bool deferred = false;        // fixed rank in every problem: lists assembled on the device
+  // per-level redraw: the operator, seed, redraws done, and their buffers
+  // (N x sld in tree order, the same in user order twice; the inverse permutation)
+  const RedrawSpec* rd = nullptr;
+  int redraws = 0;
+  DevBuf rd_x, rd_u, rd_y, rd_iperm;
+  HostBuf rd_hiperm;
   // active list as pieces: src != nullptr is a range of the index store,
   // else the tree positions iota .. iota + len - 1
   struct Piece { const int64_t* src; int64_t iota, len; };
@@ -543,6 +549,104 @@ rsrs_status upload_class_lists(Job<T>& J, const Group& g, hipStream_t st) {
   return RSRS_OK;
 }
 
+// x (N x s rows in tree order, leading dimension sld) through the processed
+// boxes' factors of groups [0, ng): the upward sweep of eq. Ainvfact (V^{-1}:
+// E then L per box, groups in order; W^{-T}: F^T then U^T) or the downward
+// one (W^{-1}: U then F per box, groups in reverse order; V^{-T}: L^T then
+// E^T), in place, as the solve applies them to its right-hand sides.
+template <typename T>
+rsrs_status redraw_sweep(Job<T>& J, size_t ng, T* x, bool down, bool transpose, Uploader& up, hipStream_t st) {
+  const int64_t ld = J.sld;
+  const int W = (int)J.s;
+  const T* dS = J.dS;
+  const int64_t* iS = J.iS;
+  auto one = [&](const Group& g) -> rsrs_status {
+    std::vector<GemmDescT<T, T>> a0, a1, b0, b1;
+    for (int64_t q = g.first; q < g.first + g.count; ++q) {
+      const BoxRec& R = J.F->boxes[q];
+      const int r = (int)R.r, k = (int)R.k, kn = (int)(R.k + R.n);
+      if (r == 0) continue;
+      const int64_t* gR = iS + R.oR;
+      const int64_t* gS = iS + R.oS;
+      const int64_t* gSN = iS + R.oS;
+      const T* Tm = dS + R.oT;
+      const T* KU = dS + R.oKU;
+      const T* KL = dS + R.oKL;
+      const int64_t lT = R.ldT, lR = R.ldR, lU = R.ldKU;
+      if (!down && !transpose) {          // E then L
+        if (k > 0) a0.push_back(gdescT<T, T>(Tm, nullptr, lT, x, gS, ld, x, gR, ld, r, W, k, -1.0, 1.0));
+        if (kn > 0) b0.push_back(gdescT<T, T>(KL, nullptr, lR, x, gR, ld, x, gSN, ld, kn, W, r, -1.0, 1.0));
+      } else if (!down) {                 // F^T then U^T
+        if (k > 0) a0.push_back(gdescT<T, T>(Tm, nullptr, lT, x, gS, ld, x, gR, ld, r, W, k, -1.0, 1.0));
+        if (kn > 0) b1.push_back(gdescT<T, T>(KU, nullptr, lU, x, gR, ld, x, gSN, ld, kn, W, r, -1.0, 1.0));
+      } else if (!transpose) {            // U then F
+        if (kn > 0) a0.push_back(gdescT<T, T>(KU, nullptr, lU, x, gSN, ld, x, gR, ld, r, W, kn, -1.0, 1.0));
+        if (k > 0) b1.push_back(gdescT<T, T>(Tm, nullptr, lT, x, gR, ld, x, gS, ld, k, W, r, -1.0, 1.0));
+      } else {                            // L^T then E^T
+        if (kn > 0) a1.push_back(gdescT<T, T>(KL, nullptr, lR, x, gSN, ld, x, gR, ld, r, W, kn, -1.0, 1.0));
+        if (k > 0) b1.push_back(gdescT<T, T>(Tm, nullptr, lT, x, gR, ld, x, gS, ld, k, W, r, -1.0, 1.0));
+      }
+    }
+    RSRS_TRY(gemm<T, T>(up, st, a0, 0, 0, GM_FULL, GS_64x64, "redraw"));
+    RSRS_TRY(gemm<T, T>(up, st, a1, 1, 0, GM_FULL, GS_64x64, "redraw"));
+    RSRS_TRY(gemm<T, T>(up, st, b0, 0, 0, GM_FULL, GS_64x64, "redraw"));
+    RSRS_TRY(gemm<T, T>(up, st, b1, 1, 0, GM_FULL, GS_64x64, "redraw"));
+    return RSRS_OK;
+  };
+  if (down)
+    for (size_t g = ng; g-- > 0;) RSRS_TRY(one(J.F->groups[g]));
+  else
+    for (size_t g = 0; g < ng; ++g) RSRS_TRY(one(J.F->groups[g]));
+  return RSRS_OK;
+}
+
+// Fresh samples of the partially factored operator V^{-1} A W^{-1} (groups
+// [0, ng) processed; the sketches are a sample pair of it, Sec. 1.1), in
+// place of the sketches: Omega' from the generator in tree order (word 2 r
+// for the r-th redraw), Y' = V^{-1} A W^{-1} Omega', and for the general
+// variant Psi' (word 2 r + 1), Z' = W^{-T} A^T V^{-T} Psi'.  The operator
+// gets and returns blocks in user point order.
+template <typename T>
+rsrs_status redraw_job(Job<T>& J, size_t ng, Uploader& up, hipStream_t st) {
+  constexpr int dt = sizeof(T) == 8 ? RSRS_F64 : RSRS_F32;
+  const int64_t n = J.n, s = J.s, ld = J.sld;
+  const size_t bytes = (size_t)n * ld * sizeof(T);
+  if (!J.rd_x.p) {
+    RSRS_TRY(J.rd_x.alloc(bytes));
+    RSRS_TRY(J.rd_u.alloc(bytes));
+    RSRS_TRY(J.rd_y.alloc(bytes));
+    RSRS_TRY(J.rd_iperm.alloc((size_t)n * 8));
+    RSRS_TRY(pool_alloc(J.rd_hiperm, (size_t)n * 8));
+    int64_t* ip = J.rd_hiperm.template as<int64_t>();
+    const auto& perm = J.tree().perm;
+    for (int64_t i = 0; i < n; ++i) ip[perm[i]] = i;
+    RSRS_HIP(hipMemcpyAsync(J.rd_iperm.p, ip, (size_t)n * 8, hipMemcpyHostToDevice, st));
+  }
+  ++J.redraws;
+  T* x = J.rd_x.template as<T>();
+  T* u = J.rd_u.template as<T>();
+  T* y = J.rd_y.template as<T>();
+  const int64_t* iperm = J.rd_iperm.template as<int64_t>();
+  const int64_t* perm = J.F->perm.template as<int64_t>();
+  for (int side = 0; side < (J.sym ? 1 : 2); ++side) {
+    T* Tst = side ? J.Psi : J.Om;
+    T* Ysd = side ? J.Z : J.Y;
+    philox_normal<T>(st, Tst, n, s, ld, J.rd->seed, (uint32_t)(2 * J.redraws + side));
+    RSRS_HIP(hipMemcpyAsync(x, Tst, bytes, hipMemcpyDeviceToDevice, st));
+    // W^{-1} (V^{-T} for the transposed side), then A (A^T) in user order
+    RSRS_TRY(redraw_sweep<T>(J, ng, x, true, side == 1, up, st));
+    gather_rows<T, T>(st, u, ld, x, ld, iperm, n, s);
+    if (J.rd->mv(J.rd->user, side, dt, s, u, ld, y, ld, st) != 0) {
+      set_error("matvec callback returned nonzero (per-level redraw)");
+      return RSRS_E_CALLBACK;
+    }
+    gather_rows<T, T>(st, Ysd, ld, y, ld, perm, n, s);
+    // V^{-1} (W^{-T})
+    RSRS_TRY(redraw_sweep<T>(J, ng, Ysd, false, side == 1, up, st));
+  }
+  return RSRS_OK;
+}
+
 template <typename T>
 rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
   constexpr bool mixed = Job<T>::mixed;
@@ -620,6 +724,19 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
   int* hflag_slot = reinterpret_cast<int*>(hpos.as<int64_t>() + pos_max);
   const bool deferred = !jobs.empty() && jobs[0].deferred;
   for (size_t t = 0; t < nsteps; ++t) {
+    // ---- per-level redraw: a job entering a processed level after its first
+    // starts it from fresh samples, once every earlier class has finished
+    // (phase B of the previous class included)
+    {
+      bool any = false;
+      for (auto& J : jobs) any = any || (J.rd && t > 0 && t < J.F->groups.size() && J.ci == 0);
+      if (any) {
+        RSRS_TRY(worker.join());
+        RSRS_HIP(hipStreamWaitEvent(st, side.eB, 0));
+        for (auto& J : jobs)
+          if (J.rd && t > 0 && t < J.F->groups.size() && J.ci == 0) RSRS_TRY(redraw_job<T>(J, t, up, st));
+      }
+    }
     // ---- host index lists and factor-store uploads (Ba, Na, Na copy)
     std::vector<Item<T>> items;
     std::vector<int64_t> nbs;
@@ -1275,9 +1392,11 @@ rsrs_status factor_many(std::vector<Job<T>>& jobs, hipStream_t st) {
 
 template <typename T>
 rsrs_status factor_batch_t(int64_t nprob, const rsrs_tree_t* const* trees, rsrs_samples_t* const* smps,
-                           const rsrs_factor_opts* opts, hipStream_t st, rsrs_factor_t** out) {
+                           const rsrs_factor_opts* opts, hipStream_t st, rsrs_factor_t** out,
+                           const RedrawSpec* rd) {
   std::vector<Job<T>> jobs((size_t)nprob);
   for (int64_t i = 0; i < nprob; ++i) {
+    jobs[i].rd = rd;
     const rsrs_status r = job_init<T>(jobs[i], trees[i], smps[i], &opts[i]);
     if (r != RSRS_OK) {
       if (nprob > 1) set_error("problem " + std::to_string(i) + ": " + rsrs_last_error());
@@ -1300,8 +1419,10 @@ rsrs_status factor_batch_t(int64_t nprob, const rsrs_tree_t* const* trees, rsrs_
 }  // namespace
 
 rsrs_status factor_batch_impl(int64_t nprob, const rsrs_tree_t* const* trees, rsrs_samples_t* const* smps,
-                              const rsrs_factor_opts* opts, hipStream_t st, rsrs_factor_t** out) {
+                              const rsrs_factor_opts* opts, hipStream_t st, rsrs_factor_t** out,
+                              const RedrawSpec* rd) {
   if (nprob < 1) { set_error("need at least one problem"); return RSRS_E_INVALID; }
+  if (rd && nprob != 1) { set_error("the per-level redraw factors one problem"); return RSRS_E_INVALID; }
   for (int64_t i = 0; i < nprob; ++i) out[i] = nullptr;
   const int prec = opts[0].precision;
   for (int64_t i = 0; i < nprob; ++i) {
@@ -1342,15 +1463,15 @@ rsrs_status factor_batch_impl(int64_t nprob, const rsrs_tree_t* const* trees, rs
       return RSRS_E_INVALID;
     }
   }
-  if (prec == RSRS_PREC_F64) return factor_batch_t<double>(nprob, trees, smps, opts, st, out);
-  if (prec == RSRS_PREC_F32_MIXED) return factor_batch_t<float>(nprob, trees, smps, opts, st, out);
+  if (prec == RSRS_PREC_F64) return factor_batch_t<double>(nprob, trees, smps, opts, st, out, rd);
+  if (prec == RSRS_PREC_F32_MIXED) return factor_batch_t<float>(nprob, trees, smps, opts, st, out, rd);
   set_error("unknown precision");
   return RSRS_E_UNSUPPORTED;
 }
 
 rsrs_status factor_impl(const rsrs_tree_t* th, rsrs_samples_t* smp, const rsrs_factor_opts* o,
-                        hipStream_t st, rsrs_factor_t** out) {
-  return factor_batch_impl(1, &th, &smp, o, st, out);
+                        hipStream_t st, rsrs_factor_t** out, const RedrawSpec* rd) {
+  return factor_batch_impl(1, &th, &smp, o, st, out, rd);
 }
 
 // Device bytes of a factorization of tree t with s samples: the stored factor

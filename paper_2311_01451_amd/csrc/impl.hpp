@@ -52,6 +52,21 @@ struct BoxRec {
   int64_t oR = 0, oS = 0, oSN = 0, oBa = 0, oNa = 0;       // int64 tree positions
 };
 
+// Per-level redrawing of the samples: the operator and the generator seed.
+struct RedrawSpec {
+  rsrs_matvec_fn mv;
+  void* user;
+  uint64_t seed;
+};
+
+// Factorization of one problem or a batch (factor.hip); rd: per-level redraw
+// (one problem only), null for none.
+rsrs_status factor_impl(const rsrs_tree_t* th, rsrs_samples_t* smp, const rsrs_factor_opts* o,
+                        hipStream_t st, rsrs_factor_t** out, const RedrawSpec* rd = nullptr);
+rsrs_status factor_batch_impl(int64_t nprob, const rsrs_tree_t* const* trees, rsrs_samples_t* const* smps,
+                              const rsrs_factor_opts* opts, hipStream_t st, rsrs_factor_t** out,
+                              const RedrawSpec* rd = nullptr);
+
 struct Group {  // one colour class: boxes [first, first+count) in processing order
   int64_t first = 0, count = 0;
 };

@@ -37,14 +37,10 @@
 #include "impl.hpp"
 
 namespace rsrs {
-rsrs_status factor_impl(const rsrs_tree_t* th, rsrs_samples_t* smp, const rsrs_factor_opts* o,
-                        hipStream_t st, rsrs_factor_t** out);
 rsrs_status apply_factor(const rsrs_factor_t* F, int op, int transpose, int64_t w, const double* Fin,
                          int64_t ldf, double* Uout, int64_t ldu, hipStream_t st);
 size_t factor_bytes_estimate(const rsrs_tree_t* th, int k, int p, int64_t s, int precision,
                              size_t* stored, bool adaptive);
-rsrs_status factor_batch_impl(int64_t nprob, const rsrs_tree_t* const* trees, rsrs_samples_t* const* smps,
-                              const rsrs_factor_opts* opts, hipStream_t st, rsrs_factor_t** out);
 }  // namespace rsrs
 
 using namespace rsrs;

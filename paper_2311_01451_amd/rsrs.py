@@ -98,7 +98,7 @@ EXPORTS = [
     "rsrs_samples_required", "rsrs_work_model", "rsrs_gemm_autotune", "rsrs_gemm_autotune_workload",
     "rsrs_gemm_tile_override", "rsrs_op_create_kernel", "rsrs_op_create_dense",
     "rsrs_op_create_poisson7", "rsrs_op_matvec", "rsrs_op_destroy", "rsrs_samples_wrap",
-    "rsrs_sample", "rsrs_sample_symmetric", "rsrs_samples_wrap_symmetric", "rsrs_samples_destroy", "rsrs_gaussian", "rsrs_factor", "rsrs_factor_batched",
+    "rsrs_sample", "rsrs_sample_symmetric", "rsrs_samples_wrap_symmetric", "rsrs_samples_destroy", "rsrs_gaussian", "rsrs_factor", "rsrs_factor_redraw", "rsrs_factor_batched",
     "rsrs_factor_destroy", "rsrs_release_cached",
     "rsrs_factor_get_info", "rsrs_factor_box_sizes", "rsrs_factor_box_copy",
     "rsrs_factor_root_copy", "rsrs_solve", "rsrs_solve_noalloc", "rsrs_apply", "rsrs_solve_refine", "rsrs_solve_gmres",
@@ -155,6 +155,7 @@ def lib():
         "rsrs_samples_destroy": (None, [vp]),
         "rsrs_gaussian": (i32, [vp, i64, i64, i64, C.c_uint64, C.c_uint32, vp]),
         "rsrs_factor": (i32, [vp, vp, P(FactorOpts), vp, P(vp)]),
+        "rsrs_factor_redraw": (i32, [vp, vp, vp, i64, C.c_uint64, i32, P(FactorOpts), vp, P(vp)]),
         "rsrs_factor_batched": (i32, [i64, P(vp), P(vp), P(FactorOpts), vp, P(vp)]),
         "rsrs_factor_destroy": (None, [vp]),
         "rsrs_factor_get_info": (i32, [vp, P(FactorInfo)]),
@@ -529,6 +530,21 @@ def rsrs_factor(tree: Tree, samples: Samples, k: int, p: int = -1, reproject: in
     o = FactorOpts(k, p, precision, reproject, int(symmetric), int(id_mode), float(rank_tol), int(col_subset))
     h = C.c_void_p()
     _check(lib().rsrs_factor(tree.handle, samples.handle, C.byref(o), _stream(stream), C.byref(h)))
+    return Factor(h, keep=tree)
+
+
+def rsrs_factor_redraw(tree: Tree, op: "Operator", s: int, seed: int, k: int, p: int = -1, reproject: int = 1,
+                       precision: int = RSRS_PREC_F64, dtype: int | None = None, stream=None,
+                       symmetric: bool = False, id_mode: int = 0, rank_tol: float = 0.0,
+                       col_subset: bool = False) -> Factor:
+    """Sample and factor with fresh samples at every processed level after the
+    first (rsrs_factor_redraw)."""
+    if dtype is None:
+        dtype = RSRS_F64 if precision == RSRS_PREC_F64 else RSRS_F32
+    o = FactorOpts(k, p, precision, reproject, int(symmetric), int(id_mode), float(rank_tol), int(col_subset))
+    h = C.c_void_p()
+    _check(lib().rsrs_factor_redraw(tree.handle, Operator.fn_ptr(), op.handle, int(s), int(seed), int(dtype),
+                                    C.byref(o), _stream(stream), C.byref(h)))
     return Factor(h, keep=tree)
 
 

@@ -199,14 +199,18 @@ def _dense_ops(bf, N):
     return E, F, L, U
 
 
-@pytest.mark.parametrize("skew,col_subset", [(0.0, False), (2e-3, False), (2e-3, True)])
-def test_sample_pair_invariant_every_box(skew, col_subset):
+@pytest.mark.parametrize("skew,col_subset,redraw", [(0.0, False, False), (2e-3, False, False),
+                                                   (2e-3, True, False), (2e-3, False, True)])
+def test_sample_pair_invariant_every_box(skew, col_subset, redraw):
     """Sec. 1.1 and eq. updateVW_sketch/test/adj: after every box the updated
     sketches are an exact sample pair of V^{-1} A W^{-1}, whatever the
     approximation quality; the R rows/columns are decoupled to the level of the
     far-field remainder.  With per-box column subsets the updates must still
     cover every column: an update cut to the s_B columns a box reads breaks
-    the pair in the remaining ones."""
+    the pair in the remaining ones.  With per-level redrawing the fresh
+    sketches must be a sample pair of the same partially factored operator:
+    a pass in the wrong order, or a factor applied from the wrong side,
+    breaks it from the first box of the next level on."""
     A, t, Om, Psi = _small_log_problem(skew=skew)
     Y, Z = A @ Om, A.T @ Psi
     N = A.shape[0]
@@ -224,7 +228,8 @@ def test_sample_pair_invariant_every_box(skew, col_subset):
         worst[1] = max(worst[1], np.abs(At[np.ix_(bf.R, rest)]).max(),
                        np.abs(At[np.ix_(rest, bf.R)]).max())
 
-    orr.factor(t, Y, Z, Om, Psi, 8, on_box=check, col_subset=col_subset)
+    rd = {"matvec": lambda X: A @ X, "rmatvec": lambda X: A.T @ X, "seed": 11} if redraw else None
+    orr.factor(t, Y, Z, Om, Psi, 8, on_box=check, col_subset=col_subset, redraw=rd)
     assert worst[0] < 1e-12
     # column subsets oversample boxes with small l less (s_B - l = k + p
     # instead of up to s - l): a somewhat larger far-field remainder
@@ -272,6 +277,52 @@ def test_column_subsets():
     sh = ot.samples_required(th, 6, 6)
     Om2, Psi2 = inputs.test_matrices(256, sh)
     Fh = orr.factor(th, H @ Om2, H.T @ Psi2, Om2, Psi2, 6, col_subset=True)
+    assert orr.relerr(Fh, H) < 1e-11
+
+
+def test_philox_published_vectors_and_redraw():
+    """The redraw's generator: Philox-4x32-10 on the three published
+    known-answer vectors (zero counter and key, all-ones, the digits of pi),
+    Gaussian moments of a large block; then the redraw itself: drawn with
+    word 2 r for the r-th redraw (the level's Omega equals the generator's
+    block), exact on an exactly H2 symmetric operator, and with an accuracy
+    of the order of the fixed sketches' (trend, within 10x)."""
+    from oracle import philox
+    kat = [((0, 0, 0, 0), (0, 0), (0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8)),
+           ((0xFFFFFFFF,) * 4, (0xFFFFFFFF,) * 2, (0x408F276D, 0x41C83B0E, 0xA20BC7C6, 0x6D5451FD)),
+           ((0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344), (0xA4093822, 0x299F31D0),
+            (0xD16CFE09, 0x94FDCCEB, 0x5001E420, 0x24126EA1))]
+    for ctr, key, want in kat:
+        out = philox.philox4x32_10(*[np.array([c], dtype=np.uint64) for c in ctr], *key)
+        assert tuple(int(o[0]) for o in out) == want
+    g = philox.gaussian(1000, 400, 5, 0)
+    assert abs(g.mean()) < 4 / np.sqrt(g.size) and abs(g.var() - 1.0) < 4 * np.sqrt(2.0 / g.size)
+    A, t, Om, Psi = _small_log_problem(n=32, m=32, k=12)
+    rd = {"matvec": lambda X: A @ X, "rmatvec": lambda X: A.T @ X, "seed": 99}
+    seen = {}
+
+    def grab(bf, Yt, Zt, Omt, Psit):
+        if bf.level not in seen:
+            seen[bf.level] = Omt.copy()
+
+    F = orr.factor(t, A @ Om, None, Om, None, 12, symmetric=True, redraw=rd, on_box=grab)
+    levels = sorted(seen, reverse=True)
+    assert len(levels) >= 2
+    # the first box of the second processed level saw the first redraw; its
+    # own rows were then updated, the others are the generator's block
+    b0 = next(bf for bf in F.boxes if bf.level == levels[1])
+    untouched = np.setdiff1d(np.arange(t.n), np.concatenate([b0.Ba]))
+    fresh = philox.gaussian(t.n, Om.shape[1], 99, 2)
+    assert np.array_equal(seen[levels[1]][untouched], fresh[untouched])
+    F0 = orr.factor(t, A @ Om, None, Om, None, 12, symmetric=True)
+    assert orr.relerr(F, A) < 10 * orr.relerr(F0, A)
+    pts = inputs.grid2d(16)
+    th = ot.build_tree(pts, leaf_size=16)
+    H = _exact_h2_symmetric(th, r=3)
+    sh = ot.samples_required(th, 6, 6)
+    Om2, _ = inputs.test_matrices(256, sh)
+    rdh = {"matvec": lambda X: H @ X, "rmatvec": lambda X: H.T @ X, "seed": 3}
+    Fh = orr.factor(th, H @ Om2, None, Om2, None, 6, symmetric=True, redraw=rdh)
     assert orr.relerr(Fh, H) < 1e-11
 
 
