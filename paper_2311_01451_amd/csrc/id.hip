@@ -514,14 +514,18 @@ __global__ __launch_bounds__(64) void id_gram_rows_kernel(const IdDesc* __restri
 // entry t of every row at consecutive addresses.  One barrier per step:
 // after it every thread reduces the 16 wave maxima itself, so all agree on
 // the pivot without a second exchange.
-template <int NG>
+// With LDSR the column-major R entries live in LDS (b k <= kRtLds), else in
+// the global scratch: the same arithmetic in the same order either way.
+constexpr int kRtLds = 16384;
+template <int NG, bool LDSR>
 __global__ __launch_bounds__(1024) void id_pchol_kernel(const IdDesc* __restrict__ e, int64_t gstride) {
   const IdDesc d = e[blockIdx.x];
   const int b = d.b, k = d.k, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   constexpr int RPT = kGramRows / 1024;   // rows per thread
   __shared__ double wbest[2][16];
   __shared__ int wrow[2][16];
-  double* Rt = d.Rt;
+  __shared__ double RtL[LDSR ? kRtLds : 1];
+  double* Rt = LDSR ? RtL : d.Rt;
   double dv[RPT];
   int alive = 0;   // bit u: row tid + 1024 u still unselected
 #pragma unroll
@@ -654,19 +658,24 @@ rsrs_status id_run_gram(Uploader& up, hipStream_t st, const std::vector<IdDesc>&
     for (const auto& x : e) f += 2.0 * x.b * x.k * x.k;
     ProfScope ps(st, "id_pchol", f, 0.0);
     // partial sums of box x lie b * ldg apart: one stride per launch needs
-    // equal (b, ldg), so boxes are launched in groups of equal stride
-    std::vector<std::pair<int64_t, std::vector<IdDesc>>> groups;
+    // equal (b, ldg), so boxes are launched in groups of equal stride (and of
+    // R entries in LDS or not)
+    std::vector<std::pair<std::pair<int64_t, bool>, std::vector<IdDesc>>> groups;
     for (const auto& x : e) {
-      const int64_t gs = (int64_t)x.b * x.ldg;
-      auto it = std::find_if(groups.begin(), groups.end(), [&](const auto& gr) { return gr.first == gs; });
-      if (it == groups.end()) groups.push_back({gs, {x}});
+      const std::pair<int64_t, bool> key{(int64_t)x.b * x.ldg, (int64_t)x.b * x.k <= kRtLds};
+      auto it = std::find_if(groups.begin(), groups.end(), [&](const auto& gr) { return gr.first == key; });
+      if (it == groups.end()) groups.push_back({key, {x}});
       else it->second.push_back(x);
     }
     for (const auto& gr : groups) {
       IdDesc* dg = nullptr;
       RSRS_TRY(up.put_vec(gr.second, &dg));
-      hipLaunchKernelGGL((id_pchol_kernel<kGramSplit>), dim3((unsigned)gr.second.size()), dim3(1024), 0, st, dg,
-                         gr.first);
+      if (gr.first.second)
+        hipLaunchKernelGGL((id_pchol_kernel<kGramSplit, true>), dim3((unsigned)gr.second.size()), dim3(1024), 0, st,
+                           dg, gr.first.first);
+      else
+        hipLaunchKernelGGL((id_pchol_kernel<kGramSplit, false>), dim3((unsigned)gr.second.size()), dim3(1024), 0,
+                           st, dg, gr.first.first);
       RSRS_HIP(hipGetLastError());
     }
   }
