@@ -28,7 +28,11 @@
 // inverse of the 64 x 64 factor follows from the 8 x 8 ones by doubling,
 //   [A 0; C D]^{-1} = [A^{-1} 0; -D^{-1} C A^{-1}  D^{-1}],
 // and the off-diagonal blocks are G_ij X_jj^T on MFMA, the next block's
-// loads in flight during each product.
+// loads in flight during each product.  No global read of a panel launch
+// depends on its own arithmetic, so the diagonal block, the first row block
+// and the first pending panel are requested together at the start (raw buffer
+// loads, whose range check zero-fills the rows past a partial block), and
+// each further pending panel is fetched while the previous one is multiplied.
 //
 // Element type T = double (FP64 MFMA) or float (FP32 MFMA, FP32
 // accumulation; the Gram matrices of the FP32 path are formed in FP32, so
@@ -50,6 +54,19 @@
 namespace rsrs {
 
 namespace {
+
+// Raw buffer view of `bytes` bytes from a wave-uniform base: loads at byte
+// offsets beyond the range return zero (the hardware's range check), so a
+// partial block is read without branches or clamped addresses.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_view(const void* base, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, bytes, 0x00020000);
+}
+__device__ __forceinline__ float buf_ld(__amdgpu_buffer_rsrc_t r, float, int off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ double buf_ld(__amdgpu_buffer_rsrc_t r, double, int off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
 
 constexpr int PB = 64;        // panel width
 constexpr int PP = PB + 1;    // LDS row pitch (elements)
@@ -80,23 +97,6 @@ __device__ __forceinline__ void mma_abt(const T* A, const T* B, typename Mfma<T>
     for (int a = 0; a < 2; ++a)
 #pragma unroll
       for (int bb = 0; bb < 2; ++bb) acc[a][bb] = Mfma<T>::mma(av[a], bv[bb], acc[a][bb]);
-  }
-}
-
-// rows [0, rows) of the 64 x 64 block at src (leading dimension ld) into
-// LDS, zero below
-template <typename T>
-__device__ __forceinline__ void load_block(T* dst, const T* src, int64_t ld, int rows, int tid) {
-  T v[16];
-#pragma unroll
-  for (int u = 0; u < 16; ++u) {
-    const int x = tid + 256 * u, r = x >> 6, c = x & 63;
-    v[u] = r < rows ? src[(int64_t)r * ld + c] : T(0);
-  }
-#pragma unroll
-  for (int u = 0; u < 16; ++u) {
-    const int x = tid + 256 * u;
-    dst[(x >> 6) * PP + (x & 63)] = v[u];
   }
 }
 
@@ -175,9 +175,12 @@ __global__ __launch_bounds__(256, 2) void chol_panel_kernel(const CholPanel<T>* 
   __shared__ T Xa[PB * PP];   // X_jj = L_jj^{-1}
   __shared__ T Vs[32 * 33];   // products of the doubling steps
   __shared__ T Lj[FUSED ? PB * PP : 1];   // L_jt of the pending panels
+  __shared__ T Pa[FUSED ? PB * PP : 1];   // the first row block of the products
   const CholPanel<T> d = e[blockIdx.x];
+  const gptr<T> G = to_global(d.G);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t ld = d.ld;
+  const int ldi = (int)d.ld;   // offsets inside one 64-row block fit in 32 bits
   const int j0 = PB * d.j;
   const int nj = min(PB, d.n - j0);
   const int wm = wave >> 1, wn = wave & 1, q = lane >> 4, c16 = lane & 15;
@@ -191,43 +194,100 @@ __global__ __launch_bounds__(256, 2) void chol_panel_kernel(const CholPanel<T>* 
 #pragma unroll
       for (int b = 0; b < RB; ++b) ao[b][a][bb] = acc_t{0, 0, 0, 0};
     }
-  if constexpr (FUSED) {
-    for (int t = d.t0; t < d.j; ++t) {
-      load_block(Lj, d.G + (int64_t)j0 * ld + PB * t, ld, nj, tid);
-      __syncthreads();
-      mma_abt(Lj, Lj, ad, wm, wn, q, c16);
+  // Every global read of the launch is independent of its arithmetic (the
+  // pending updates are applied from registers after the loads), so the
+  // diagonal block, the first row block of the products and the first pending
+  // panel's three blocks are all requested up front, and each later pending
+  // panel is fetched while the previous one is multiplied.
+  const T* gd = d.G + (int64_t)j0 * ld + j0;
+  T vd[16], pf[16];
+  const int nrb = max(0, min(RB, d.ie - ifirst));
+  // thread tid reads row tid / 64 + 4 u, column tid % 64 of a block
+  const int voff = ((tid >> 6) * ldi + (tid & 63)) * (int)sizeof(T), vstep = 4 * ldi * (int)sizeof(T);
+  auto ldregs = [&](T (&v)[16], const T* src, int rows) {
+    const auto rs = buf_view(src, ((rows - 1) * ldi + PB) * (int)sizeof(T));
 #pragma unroll
-      for (int b = 0; b < RB; ++b) {
-        const int i = ifirst + b;
-        if (i >= d.ie) break;   // the same in every thread
-        load_block(La, d.G + (int64_t)PB * i * ld + PB * t, ld, min(PB, d.n - PB * i), tid);
-        __syncthreads();
-        mma_abt(La, Lj, ao[b], wm, wn, q, c16);
-        __syncthreads();
-      }
-      __syncthreads();
-    }
-  }
-  {
-    // lower part of the diagonal block, identity beyond n, zero above
-    const T* g = d.G + (int64_t)j0 * ld + j0;
-    T v[16];
-#pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int x = tid + 256 * u, r = x >> 6, c = x & 63;
-      v[u] = (r < nj && c <= r) ? g[(int64_t)r * ld + c] : T((r == c) ? 1 : 0);
-    }
+    for (int u = 0; u < 16; ++u) v[u] = buf_ld(rs, T(0), voff + u * vstep);
+  };
+  auto stregs = [&](T* dst, const T (&v)[16]) {
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
       const int x = tid + 256 * u;
-      La[(x >> 6) * PP + (x & 63)] = v[u];
-      if ((x & 63) > (x >> 6)) Xa[(x >> 6) * PP + (x & 63)] = T(0);   // Xa stays zero above the diagonal
+      dst[(x >> 6) * PP + (x & 63)] = v[u];
+    }
+  };
+  auto fetch = [&](int ib) {
+    const int ni = min(PB, d.n - PB * ib);
+    ldregs(pf, d.G + (int64_t)PB * ib * ld + j0, ni);
+  };
+  if constexpr (FUSED) {
+    T nx[1 + RB][16];
+    const int t0 = d.t0;
+    if (t0 < d.j) {
+      ldregs(nx[0], d.G + (int64_t)j0 * ld + PB * t0, nj);
+#pragma unroll
+      for (int b = 0; b < RB; ++b)
+        if (b < nrb) ldregs(nx[1 + b], d.G + (int64_t)PB * (ifirst + b) * ld + PB * t0, min(PB, d.n - PB * (ifirst + b)));
+    }
+    {
+      const auto rs = buf_view(gd, ((nj - 1) * ldi + nj) * (int)sizeof(T));
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int x = tid + 256 * u, r = x >> 6, c = x & 63;
+        const T g = buf_ld(rs, T(0), voff + u * vstep);
+        vd[u] = (r < nj && c <= r) ? g : T((r == c) ? 1 : 0);
+      }
+    }
+    if (nrb > 0) fetch(ifirst);
+    for (int t = t0; t < d.j; ++t) {
+      stregs(Lj, nx[0]);
+      if (nrb > 0) stregs(La, nx[1]);
+      if (nrb > 1) stregs(Xa, nx[2]);
+      __syncthreads();
+      if (t + 1 < d.j) {
+        ldregs(nx[0], d.G + (int64_t)j0 * ld + PB * (t + 1), nj);
+#pragma unroll
+        for (int b = 0; b < RB; ++b)
+          if (b < nrb)
+            ldregs(nx[1 + b], d.G + (int64_t)PB * (ifirst + b) * ld + PB * (t + 1), min(PB, d.n - PB * (ifirst + b)));
+      }
+      mma_abt(Lj, Lj, ad, wm, wn, q, c16);
+      if (nrb > 0) mma_abt(La, Lj, ao[0], wm, wn, q, c16);
+      if (nrb > 1) mma_abt(Xa, Lj, ao[1], wm, wn, q, c16);
+      __syncthreads();
+    }
+  } else {
+    {
+      const auto rs = buf_view(gd, ((nj - 1) * ldi + nj) * (int)sizeof(T));
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int x = tid + 256 * u, r = x >> 6, c = x & 63;
+        const T g = buf_ld(rs, T(0), voff + u * vstep);
+        vd[u] = (r < nj && c <= r) ? g : T((r == c) ? 1 : 0);
+      }
+    }
+  }
+  // lower part of the diagonal block, identity beyond n, zero above
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int x = tid + 256 * u;
+    La[(x >> 6) * PP + (x & 63)] = vd[u];
+    if ((x & 63) > (x >> 6)) Xa[(x >> 6) * PP + (x & 63)] = T(0);   // Xa stays zero above the diagonal
+  }
+  if constexpr (FUSED) {
+    if (nrb > 0) {
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int x = tid + 256 * u;
+        Pa[(x >> 6) * PP + (x & 63)] = pf[u];
+      }
     }
   }
   __syncthreads();
   if constexpr (FUSED) {
     if (d.t0 < d.j) {
       sub_acc(La, ad, nj, true, wm, wn, q, c16);
+      if (nrb > 0) sub_acc(Pa, ao[0], min(PB, d.n - PB * ifirst), false, wm, wn, q, c16);
       __syncthreads();
     }
   }
@@ -339,7 +399,7 @@ __global__ __launch_bounds__(256, 2) void chol_panel_kernel(const CholPanel<T>* 
     __syncthreads();
   }
   if (d.ib == d.j) {
-    T* xo = d.X + (int64_t)j0 * ld + j0;
+    gptr<T> xo = to_global(d.X) + (int64_t)j0 * ld + j0;
     for (int x = tid; x < PB * PB; x += 256) {
       const int r = x >> 6, c = x & 63;
       if (r < nj && c < nj) xo[(int64_t)r * ld + c] = Xa[r * PP + c];
@@ -348,34 +408,30 @@ __global__ __launch_bounds__(256, 2) void chol_panel_kernel(const CholPanel<T>* 
   }
   // ---- off-diagonal blocks L_ij = G_ij X_jj^T (panel j is full here) on
   // MFMA: wave w computes rows 32 (w / 2).., columns 32 (w % 2)..
-  T pf[16];
-  auto fetch = [&](int ib) {
-    const int ni = min(PB, d.n - PB * ib);
-    const T* src = d.G + (int64_t)PB * ib * ld + j0;
-#pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int x = tid + 256 * u, r = x >> 6, c = x & 63;
-      pf[u] = (r < ni) ? src[(int64_t)r * ld + c] : T(0);
-    }
-  };
-  if (ifirst < d.ie) fetch(ifirst);
+  if constexpr (!FUSED) {
+    if (ifirst < d.ie) fetch(ifirst);
+  }
 #pragma unroll
   for (int b = 0; b < RB; ++b) {
     const int i = ifirst + b;
     if (i >= d.ie) break;   // the same in every thread
     const int i0 = PB * i;
     const int ni = min(PB, d.n - i0);
-    T* gi = d.G + (int64_t)i0 * ld + j0;
+    gptr<T> gi = G + (int64_t)i0 * ld + j0;
+    // FP32: the first row block already sits in Pa with its pending update
+    const bool inpa = FUSED && b == 0;
+    if (!inpa) {
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int x = tid + 256 * u;
-      La[(x >> 6) * PP + (x & 63)] = pf[u];
-    }
-    __syncthreads();
-    if constexpr (FUSED) {
-      if (d.t0 < d.j) {
-        sub_acc(La, ao[b], ni, false, wm, wn, q, c16);
-        __syncthreads();
+      for (int u = 0; u < 16; ++u) {
+        const int x = tid + 256 * u;
+        La[(x >> 6) * PP + (x & 63)] = pf[u];
+      }
+      __syncthreads();
+      if constexpr (FUSED) {
+        if (d.t0 < d.j) {
+          sub_acc(La, ao[b], ni, false, wm, wn, q, c16);
+          __syncthreads();
+        }
       }
     }
     if (i + 1 < d.ie) fetch(i + 1);   // in flight during the product
@@ -384,7 +440,7 @@ __global__ __launch_bounds__(256, 2) void chol_panel_kernel(const CholPanel<T>* 
     for (int a = 0; a < 2; ++a)
 #pragma unroll
       for (int bb = 0; bb < 2; ++bb) acc[a][bb] = acc_t{0, 0, 0, 0};
-    mma_abt(La, Xa, acc, wm, wn, q, c16);
+    mma_abt(inpa ? Pa : La, Xa, acc, wm, wn, q, c16);
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll

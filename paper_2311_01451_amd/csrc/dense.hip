@@ -784,6 +784,7 @@ __global__ __launch_bounds__(512) void gje_blk_kernel(const GjeDesc* __restrict_
   constexpr int PRS = NP + 2;              // row stride of the pivot-row buffer
   static_assert(NT % 4 == 0, "NT is a multiple of 4");
   const GjeDesc d = e[blockIdx.x];
+  const gptr<const double> gA = to_global(d.A);
   const int n = d.n;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -805,7 +806,10 @@ __global__ __launch_bounds__(512) void gje_blk_kernel(const GjeDesc* __restrict_
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = 16 * (tr0 + a) + 4 * v + q, col = 16 * (tc0 + b) + c16;
-        acc[a][b][v] = (row < n && col < n) ? d.A[(int64_t)row * d.lda + col] : (row == col ? 1.0 : 0.0);
+        // every load in bounds and unconditional (all in flight together),
+        // the padding then selected in registers
+        const double x = gA[(int64_t)min(row, n - 1) * d.lda + min(col, n - 1)];
+        acc[a][b][v] = (row < n && col < n) ? x : (row == col ? 1.0 : 0.0);
       }
   for (int i = tid; i < NP; i += 512) {
     usedf[i] = 0;
@@ -905,7 +909,7 @@ __global__ __launch_bounds__(512) void gje_blk_kernel(const GjeDesc* __restrict_
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = 16 * (tr0 + a) + 4 * v + q, col = 16 * (tc0 + b) + c16;
-        if (row < n && col < n) d.Ainv[(int64_t)qinv[row] * d.ldi + piv[col]] = acc[a][b][v];
+        if (row < n && col < n) to_global(d.Ainv)[(int64_t)qinv[row] * d.ldi + piv[col]] = acc[a][b][v];
       }
 }
 

@@ -80,15 +80,23 @@ template <> struct Mfma<float> {
   static __device__ __forceinline__ int row(int v, int q) { return 4 * q + v; }
 };
 
+// Pointers read from descriptors in memory are generic to the compiler, and
+// generic (flat) loads count against the LDS wait counter as well: a wait for
+// an LDS read would then also wait for every global prefetch in flight.  The
+// kernels therefore cast them to the global address space first.
+template <typename T> using gptr = __attribute__((address_space(1))) T*;
+template <typename T> __device__ __forceinline__ gptr<T> to_global(T* p) { return (gptr<T>)p; }
+
 // 16-byte load of VEC consecutive elements (VEC * sizeof(T) == 16).
 template <typename T, int VEC>
-__device__ __forceinline__ void load16(const T* p, T (&out)[VEC]) {
+__device__ __forceinline__ void load16(gptr<const T> p, T (&out)[VEC]) {
   if constexpr (sizeof(T) == 8) {
-    const double2 v = *reinterpret_cast<const double2*>(p);
+    typedef double v2d __attribute__((ext_vector_type(2)));
+    const v2d v = *(gptr<const v2d>)p;
     out[0] = v.x;
     out[VEC - 1] = v.y;
   } else {
-    const float4 v = *reinterpret_cast<const float4*>(p);
+    const v4f v = *(gptr<const v4f>)p;
     out[0] = v.x;
     out[1 % VEC] = v.y;
     out[2 % VEC] = v.z;
@@ -119,6 +127,11 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmDescT<TI, 
   __shared__ TI Bs[2][BK * PB];
 
   const GemmDescT<TI, TO> d = descs[blockIdx.y];
+  const gptr<const TI> gA = to_global(d.A), gB = to_global(d.B);
+  const gptr<const TO> gCin = to_global(d.Cin);
+  const gptr<TO> gC = to_global(d.C);
+  const gptr<const int64_t> ia = to_global(d.ia), ib = to_global(d.ib), icin = to_global(d.icin),
+                            ic = to_global(d.ic);
   const int tm = (d.M + BM - 1) / BM;
   const int tn = (d.N + BN - 1) / BN;
   // SYRK_L (M == N, BM == BN) enumerates only the lower-triangle tiles
@@ -154,15 +167,15 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmDescT<TI, 
   // Fetch coordinates (fixed across slices).  Each thread reads VEC
   // consecutive elements along the contiguous dimension of its operand.
   int am[NA], ak[NA], bn_[NB], bk[NB];
-  const TI* arowp[NA];
-  const TI* browp[NB];
+  gptr<const TI> arowp[NA];
+  gptr<const TI> browp[NB];
 #pragma unroll
   for (int q = 0; q < NA; ++q) {
     const int e = (tid + q * NT) * VEC;
     if (TA == 0) { am[q] = e / BK; ak[q] = e % BK; }
     else         { ak[q] = e / BM; am[q] = e % BM; }
     const int gm = min(m0 + am[q], d.M - 1);
-    arowp[q] = (TA == 0) ? d.A + (d.ia ? d.ia[gm] : (int64_t)gm) * d.lda : d.A;
+    arowp[q] = (TA == 0) ? gA + (ia ? ia[gm] : (int64_t)gm) * d.lda : gA;
   }
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
@@ -170,7 +183,7 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmDescT<TI, 
     if (TB == 1) { bn_[q] = e / BK; bk[q] = e % BK; }
     else         { bk[q] = e / BN; bn_[q] = e % BN; }
     const int gn = min(n0 + bn_[q], d.N - 1);
-    browp[q] = (TB == 1) ? d.B + (d.ib ? d.ib[gn] : (int64_t)gn) * d.ldb : d.B;
+    browp[q] = (TB == 1) ? gB + (ib ? ib[gn] : (int64_t)gn) * d.ldb : gB;
   }
 
   // Row indices of the K-dimension gathers (TA = 1, TB = 0) are loaded one
@@ -179,12 +192,12 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmDescT<TI, 
 #pragma unroll
   for (int q = 0; q < NA; ++q) {
     const int gk = kbeg + ak[q];
-    anext[q] = (TA == 1 && gk < kend) ? (d.ia ? d.ia[gk] : (int64_t)gk) : 0;
+    anext[q] = (TA == 1 && gk < kend) ? (ia ? ia[gk] : (int64_t)gk) : 0;
   }
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
     const int gk = kbeg + bk[q];
-    bnext[q] = (TB == 0 && gk < kend) ? (d.ib ? d.ib[gk] : (int64_t)gk) : 0;
+    bnext[q] = (TB == 0 && gk < kend) ? (ib ? ib[gk] : (int64_t)gk) : 0;
   }
 
   TI ra[NA][VEC], rb[NB][VEC];
@@ -209,9 +222,9 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmDescT<TI, 
       } else {
         // VEC consecutive m of row gk (A stored K x M)
         const bool rowok = gk < kend;
-        const TI* rp = d.A + anext[q] * d.lda;
+        const gptr<const TI> rp = gA + anext[q] * d.lda;
         const int gk2 = gk + BK;
-        anext[q] = gk2 < kend ? (d.ia ? d.ia[gk2] : (int64_t)gk2) : 0;
+        anext[q] = gk2 < kend ? (ia ? ia[gk2] : (int64_t)gk2) : 0;
         if (VEC > 1 && rowok && gm + VEC - 1 < d.M) {
           load16<TI, VEC>(rp + gm, ra[q]);
         } else {
@@ -240,9 +253,9 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmDescT<TI, 
       } else {
         // VEC consecutive n of row gk
         const bool rowok = gk < kend;
-        const TI* rp = d.B + bnext[q] * d.ldb;
+        const gptr<const TI> rp = gB + bnext[q] * d.ldb;
         const int gk2 = gk + BK;
-        bnext[q] = gk2 < kend ? (d.ib ? d.ib[gk2] : (int64_t)gk2) : 0;
+        bnext[q] = gk2 < kend ? (ib ? ib[gk2] : (int64_t)gk2) : 0;
         bool full = rowok && gn + VEC - 1 < d.N;
         if (MODE == GM_B_NN_LOW) full = full && gk >= gn + VEC - 1;
         if (VEC > 1 && full) {
@@ -318,15 +331,15 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmDescT<TI, 
     for (int v = 0; v < 4; ++v) {
       const int gm = m0 + wm * (BM / WM) + i * 16 + Mfma<TI>::row(v, rowq);
       if (gm >= d.M) continue;
-      const int64_t ro = d.ic ? d.ic[gm] : gm;
-      const int64_t rc = d.icin ? d.icin[gm] : gm;
+      const int64_t ro = ic ? ic[gm] : gm;
+      const int64_t rc = icin ? icin[gm] : gm;
 #pragma unroll
       for (int j = 0; j < FN; ++j) {
         const int gn = n0 + wn * (BN / WN) + j * 16 + coll;
         if (gn < d.N) {
           double out = d.alpha * (double)acc[i][j][v];
-          if (d.beta != 0.0) out += d.beta * (double)d.Cin[rc * d.ldcin + gn];
-          d.C[ro * d.ldc + gn] = (TO)out;
+          if (d.beta != 0.0) out += d.beta * (double)gCin[rc * d.ldcin + gn];
+          gC[ro * d.ldc + gn] = (TO)out;
         }
       }
     }

@@ -520,6 +520,9 @@ constexpr int kRtLds = 16384;
 template <int NG, bool LDSR>
 __global__ __launch_bounds__(1024) void id_pchol_kernel(const IdDesc* __restrict__ e, int64_t gstride) {
   const IdDesc d = e[blockIdx.x];
+  const gptr<const double> G = to_global(d.G);
+  const gptr<double> Rc = to_global(d.Rc);
+  const gptr<int> sel = to_global(d.sel), piv = to_global(d.piv);
   const int b = d.b, k = d.k, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   constexpr int RPT = kGramRows / 1024;   // rows per thread
   __shared__ double wbest[2][16];
@@ -535,7 +538,7 @@ __global__ __launch_bounds__(1024) void id_pchol_kernel(const IdDesc* __restrict
     if (i < b) {
       double g = 0.0;
 #pragma unroll
-      for (int q = 0; q < NG; ++q) g += d.G[(int64_t)i * d.ldg + i + q * gstride];
+      for (int q = 0; q < NG; ++q) g += G[(int64_t)i * d.ldg + i + q * gstride];
       dv[u] = g > 0.0 ? g : 0.0;
       alive |= 1 << u;
     }
@@ -578,16 +581,16 @@ __global__ __launch_bounds__(1024) void id_pchol_kernel(const IdDesc* __restrict
     }
     // j < k <= b rows remain, so p is a row
     const double rjj = sqrt(bb > 0.0 ? bb : 0.0);
-    const double* gp = d.G + (int64_t)p * d.ldg;
+    const gptr<const double> gp = G + (int64_t)p * d.ldg;
 #pragma unroll
     for (int u = 0; u < RPT; ++u) {
       if (!((alive >> u) & 1)) continue;
       const int i = tid + 1024 * u;
       if (i == p) {
         alive &= ~(1 << u);
-        d.sel[p] = j;
-        d.piv[j] = p;
-        d.Rc[(int64_t)p * k + j] = rjj;
+        sel[p] = j;
+        piv[j] = p;
+        Rc[(int64_t)p * k + j] = rjj;
         Rt[(int64_t)j * b + p] = rjj;
         continue;
       }
@@ -605,7 +608,7 @@ __global__ __launch_bounds__(1024) void id_pchol_kernel(const IdDesc* __restrict
       if (t < j) c1 += Rt[(int64_t)t * b + i] * Rt[(int64_t)t * b + p];
       c -= c1 + c2;
       const double l = rjj > 0.0 ? c / rjj : 0.0;
-      d.Rc[(int64_t)i * k + j] = l;
+      Rc[(int64_t)i * k + j] = l;
       Rt[(int64_t)j * b + i] = l;
       const double nd = dv[u] - l * l;
       dv[u] = nd > 0.0 ? nd : 0.0;
