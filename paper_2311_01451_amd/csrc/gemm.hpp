@@ -123,8 +123,18 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmDescT<TI, 
   static_assert(NA >= 1 && NB >= 1 && NA * NT * VEC == BM * BK && NB * NT * VEC == BN * BK,
                 "tile split");
   static_assert(VEC == 1 || VEC == VW, "VEC is 1 or one 16-byte load");
-  __shared__ TI As[2][BK * PA];
-  __shared__ TI Bs[2][BK * PB];
+  // KC layout (FP32, both operands K-contiguous in memory, 16-byte loads):
+  // the slices sit row-major in LDS as well (row pitch PK = BK + 4 floats),
+  // so a thread stores its four consecutive k with one 16-byte write and a
+  // lane reads four consecutive k of its fragment row with one 16-byte read.
+  // Within each 16-k group, MFMA step s takes k = 4 q + s from lane group q
+  // (the same k on the A and the B side: any assignment sums the same terms);
+  // both accesses are free of bank conflicts.  Other forms keep the K-major
+  // slices (pitch BM + 2, BN + 2).
+  constexpr bool KC = sizeof(TI) == 4 && TA == 0 && TB == 1 && VEC == 4 && BK % 16 == 0;
+  constexpr int PK = BK + 4;
+  __shared__ __align__(16) TI As[2][KC ? BM * PK : BK * PA];
+  __shared__ __align__(16) TI Bs[2][KC ? BN * PK : BK * PB];
 
   const GemmDescT<TI, TO> d = descs[blockIdx.y];
   const gptr<const TI> gA = to_global(d.A), gB = to_global(d.B);
@@ -272,6 +282,15 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmDescT<TI, 
     }
   };
   auto stash = [&](int b) {
+    if constexpr (KC) {
+#pragma unroll
+      for (int q = 0; q < NA; ++q)
+        *reinterpret_cast<v4f*>(&As[b][am[q] * PK + ak[q]]) = v4f{ra[q][0], ra[q][1], ra[q][2], ra[q][3]};
+#pragma unroll
+      for (int q = 0; q < NB; ++q)
+        *reinterpret_cast<v4f*>(&Bs[b][bn_[q] * PK + bk[q]]) = v4f{rb[q][0], rb[q][1], rb[q][2], rb[q][3]};
+      return;
+    }
 #pragma unroll
     for (int q = 0; q < NA; ++q)
 #pragma unroll
@@ -305,6 +324,25 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmDescT<TI, 
     if (more) fetch(k0 + BK);
     const TI* as = As[buf];
     const TI* bs = Bs[buf];
+    if constexpr (KC) {
+#pragma unroll
+      for (int kc = 0; kc < BK; kc += 16) {
+        v4f a[FM], b[FN];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+          a[i] = *reinterpret_cast<const v4f*>(&as[(wm * (BM / WM) + i * 16 + coll) * PK + kc + 4 * rowq]);
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          b[j] = *reinterpret_cast<const v4f*>(&bs[(wn * (BN / WN) + j * 16 + coll) * PK + kc + 4 * rowq]);
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+              acc[i][j] = Mfma<TI>::mma(a[i][t], b[j][t], acc[i][j]);
+      }
+    } else
 #pragma unroll
     for (int kq = 0; kq < BK; kq += 4) {
       TI a[FM], b[FN];
