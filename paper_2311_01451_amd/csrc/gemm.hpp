@@ -123,18 +123,25 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmDescT<TI, 
   static_assert(NA >= 1 && NB >= 1 && NA * NT * VEC == BM * BK && NB * NT * VEC == BN * BK,
                 "tile split");
   static_assert(VEC == 1 || VEC == VW, "VEC is 1 or one 16-byte load");
-  // KC layout (FP32, both operands K-contiguous in memory, 16-byte loads):
-  // the slices sit row-major in LDS as well (row pitch PK = BK + 4 floats),
-  // so a thread stores its four consecutive k with one 16-byte write and a
-  // lane reads four consecutive k of its fragment row with one 16-byte read.
-  // Within each 16-k group, MFMA step s takes k = 4 q + s from lane group q
-  // (the same k on the A and the B side: any assignment sums the same terms);
-  // both accesses are free of bank conflicts.  Other forms keep the K-major
-  // slices (pitch BM + 2, BN + 2).
-  constexpr bool KC = sizeof(TI) == 4 && TA == 0 && TB == 1 && VEC == 4 && BK % 16 == 0;
+  // FP32 (KC): each operand's slice sits in LDS in the operand's own memory
+  // order, so every store is one contiguous VEC-wide write: a K-contiguous
+  // operand (A as M x K, B as N x K) row-major with pitch BK + 4, the other
+  // K-major with pitch BM + 4 (BN + 4).  Within each 16-k group, MFMA step t
+  // takes k = 4 q + t from lane group q on both operands (any assignment sums
+  // the same terms; this one lets a lane read its four k of a K-contiguous
+  // fragment row with one 16-byte read).  The order depends on the element
+  // type only, so every tile shape and load width gives the same bits.  With
+  // these pitches the 16-byte accesses and the K-major fragment reads are
+  // free of bank conflicts.  FP64 keeps K-major slices (pitch BM + 2, BN + 2).
+  constexpr bool KC = sizeof(TI) == 4;
+  constexpr bool AR = KC && TA == 0;   // A slice row-major (m, k)
+  constexpr bool BR = KC && TB == 1;   // B slice row-major (n, k)
   constexpr int PK = BK + 4;
-  __shared__ __align__(16) TI As[2][KC ? BM * PK : BK * PA];
-  __shared__ __align__(16) TI Bs[2][KC ? BN * PK : BK * PB];
+  constexpr int PMA = KC ? BM + 4 : PA;   // K-major pitches
+  constexpr int PNB = KC ? BN + 4 : PB;
+  static_assert(!KC || BK % 16 == 0, "FP32 K slices hold whole 16-k groups");
+  __shared__ __align__(16) TI As[2][AR ? BM * PK : BK * PMA];
+  __shared__ __align__(16) TI Bs[2][BR ? BN * PK : BK * PNB];
 
   const GemmDescT<TI, TO> d = descs[blockIdx.y];
   const gptr<const TI> gA = to_global(d.A), gB = to_global(d.B);
@@ -283,12 +290,27 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmDescT<TI, 
   };
   auto stash = [&](int b) {
     if constexpr (KC) {
+      // every thread's VEC elements are contiguous in the LDS layout
 #pragma unroll
-      for (int q = 0; q < NA; ++q)
-        *reinterpret_cast<v4f*>(&As[b][am[q] * PK + ak[q]]) = v4f{ra[q][0], ra[q][1], ra[q][2], ra[q][3]};
+      for (int q = 0; q < NA; ++q) {
+        TI* dst = AR ? &As[b][am[q] * PK + ak[q]] : &As[b][ak[q] * PMA + am[q]];
+        if constexpr (VEC == 4) {
+          *reinterpret_cast<v4f*>(dst) = v4f{ra[q][0], ra[q][1 % VEC], ra[q][2 % VEC], ra[q][3 % VEC]};
+        } else {
 #pragma unroll
-      for (int q = 0; q < NB; ++q)
-        *reinterpret_cast<v4f*>(&Bs[b][bn_[q] * PK + bk[q]]) = v4f{rb[q][0], rb[q][1], rb[q][2], rb[q][3]};
+          for (int u = 0; u < VEC; ++u) dst[u] = ra[q][u];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        TI* dst = BR ? &Bs[b][bn_[q] * PK + bk[q]] : &Bs[b][bk[q] * PNB + bn_[q]];
+        if constexpr (VEC == 4) {
+          *reinterpret_cast<v4f*>(dst) = v4f{rb[q][0], rb[q][1 % VEC], rb[q][2 % VEC], rb[q][3 % VEC]};
+        } else {
+#pragma unroll
+          for (int u = 0; u < VEC; ++u) dst[u] = rb[q][u];
+        }
+      }
       return;
     }
 #pragma unroll
@@ -329,11 +351,25 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmDescT<TI, 
       for (int kc = 0; kc < BK; kc += 16) {
         v4f a[FM], b[FN];
 #pragma unroll
-        for (int i = 0; i < FM; ++i)
-          a[i] = *reinterpret_cast<const v4f*>(&as[(wm * (BM / WM) + i * 16 + coll) * PK + kc + 4 * rowq]);
+        for (int i = 0; i < FM; ++i) {
+          const int r = wm * (BM / WM) + i * 16 + coll;
+          if constexpr (AR) {
+            a[i] = *reinterpret_cast<const v4f*>(&as[r * PK + kc + 4 * rowq]);
+          } else {
 #pragma unroll
-        for (int j = 0; j < FN; ++j)
-          b[j] = *reinterpret_cast<const v4f*>(&bs[(wn * (BN / WN) + j * 16 + coll) * PK + kc + 4 * rowq]);
+            for (int t = 0; t < 4; ++t) a[i][t] = as[(kc + 4 * rowq + t) * PMA + r];
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          const int c = wn * (BN / WN) + j * 16 + coll;
+          if constexpr (BR) {
+            b[j] = *reinterpret_cast<const v4f*>(&bs[c * PK + kc + 4 * rowq]);
+          } else {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) b[j][t] = bs[(kc + 4 * rowq + t) * PNB + c];
+          }
+        }
 #pragma unroll
         for (int t = 0; t < 4; ++t)
 #pragma unroll
