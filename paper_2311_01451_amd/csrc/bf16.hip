@@ -16,10 +16,21 @@
 // A block X (K x N float, row-major: the layout of the samples) is brought
 // into the Bt form by a tiled transpose that rounds each value to BF16
 // (round to nearest even).
+//
+// The operator product itself is a plain dense GEMM (the explicit operator
+// matrix times the block), so it goes to hipBLASLt (BF16 operands, FP32
+// accumulation and output) when the library offers an algorithm for the
+// shape that needs no workspace (so that products on several streams share
+// nothing); the kernels above are the fallback.  The handle and the chosen
+// algorithm per shape are kept per device for the life of the process.
 #include <hip/hip_runtime.h>
+#include <hipblaslt/hipblaslt.h>
 
 #include <algorithm>
 #include <cstdint>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "kernels.hpp"
 #include "profile.hpp"
@@ -302,6 +313,85 @@ void round_to_bf16_values(hipStream_t st, float* x, int64_t rows, int64_t cols, 
   hipLaunchKernelGGL(round_f32_to_bf16_values_kernel, dim3(g), dim3(256), 0, st, x, rows, cols, ld);
 }
 
+namespace {
+
+// hipBLASLt state of one device.  In column-major terms the product is
+// Y^T (N x M, ld ldy) = Xt^T (Xt stored K x N, ld ldt, op T) * A^T (A stored
+// K x M, ld lda, op N).
+struct LtDev {
+  std::mutex mu;
+  bool tried = false, ok = false;
+  hipblasLtHandle_t h = nullptr;
+  std::map<std::tuple<int64_t, int64_t, int64_t, int64_t, int64_t, int64_t>, hipblasLtMatmulAlgo_t> algo;
+  std::map<std::tuple<int64_t, int64_t, int64_t, int64_t, int64_t, int64_t>, bool> none;
+};
+LtDev& lt_dev(int dev) {
+  static LtDev d[64];
+  return d[dev & 63];
+}
+
+// The product's descriptors and algorithm; false when hipBLASLt has none for
+// this shape (then nothing is enqueued).
+struct LtCall {
+  hipblasLtMatmulDesc_t desc = nullptr;
+  hipblasLtMatrixLayout_t la = nullptr, lb = nullptr, lc = nullptr;
+  const hipblasLtMatmulAlgo_t* algo = nullptr;
+  LtDev* dev = nullptr;
+  ~LtCall() {
+    if (lc) (void)hipblasLtMatrixLayoutDestroy(lc);
+    if (lb) (void)hipblasLtMatrixLayoutDestroy(lb);
+    if (la) (void)hipblasLtMatrixLayoutDestroy(la);
+    if (desc) (void)hipblasLtMatmulDescDestroy(desc);
+  }
+};
+bool lt_prepare(LtCall& c, int64_t lda, int64_t M, int64_t K, int64_t ldt, int64_t N, int64_t ldy) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  LtDev& L = lt_dev(dev);
+  std::lock_guard<std::mutex> lk(L.mu);
+  if (!L.tried) {
+    L.tried = true;
+    if (hipblasLtCreate(&L.h) != HIPBLAS_STATUS_SUCCESS) return false;
+    L.ok = true;
+  }
+  if (!L.ok) return false;
+  const auto key = std::make_tuple(M, N, K, lda, ldt, ldy);
+  if (L.none.count(key)) return false;
+  const hipblasOperation_t opT = HIPBLAS_OP_T, opN = HIPBLAS_OP_N;
+  if (hipblasLtMatmulDescCreate(&c.desc, HIPBLAS_COMPUTE_32F, HIP_R_32F) != HIPBLAS_STATUS_SUCCESS ||
+      hipblasLtMatmulDescSetAttribute(c.desc, HIPBLASLT_MATMUL_DESC_TRANSA, &opT, sizeof(opT)) !=
+          HIPBLAS_STATUS_SUCCESS ||
+      hipblasLtMatmulDescSetAttribute(c.desc, HIPBLASLT_MATMUL_DESC_TRANSB, &opN, sizeof(opN)) !=
+          HIPBLAS_STATUS_SUCCESS ||
+      hipblasLtMatrixLayoutCreate(&c.la, HIP_R_16BF, (uint64_t)K, (uint64_t)N, ldt) != HIPBLAS_STATUS_SUCCESS ||
+      hipblasLtMatrixLayoutCreate(&c.lb, HIP_R_16BF, (uint64_t)K, (uint64_t)M, lda) != HIPBLAS_STATUS_SUCCESS ||
+      hipblasLtMatrixLayoutCreate(&c.lc, HIP_R_32F, (uint64_t)N, (uint64_t)M, ldy) != HIPBLAS_STATUS_SUCCESS)
+    return false;
+  auto it = L.algo.find(key);
+  if (it == L.algo.end()) {
+    hipblasLtMatmulPreference_t pref = nullptr;
+    hipblasLtMatmulHeuristicResult_t res[1];
+    int nres = 0;
+    uint64_t wsb = 0;
+    if (hipblasLtMatmulPreferenceCreate(&pref) == HIPBLAS_STATUS_SUCCESS &&
+        hipblasLtMatmulPreferenceSetAttribute(pref, HIPBLASLT_MATMUL_PREF_MAX_WORKSPACE_BYTES, &wsb, sizeof(wsb)) ==
+            HIPBLAS_STATUS_SUCCESS &&
+        hipblasLtMatmulAlgoGetHeuristic(L.h, c.desc, c.la, c.lb, c.lc, c.lc, pref, 1, res, &nres) ==
+            HIPBLAS_STATUS_SUCCESS &&
+        nres > 0 && res[0].state == HIPBLAS_STATUS_SUCCESS && res[0].workspaceSize == 0)
+      it = L.algo.emplace(key, res[0].algo).first;
+    else
+      L.none[key] = true;
+    if (pref) (void)hipblasLtMatmulPreferenceDestroy(pref);
+    if (it == L.algo.end()) return false;
+  }
+  c.algo = &it->second;
+  c.dev = &L;
+  return true;
+}
+
+}  // namespace
+
 // Y (M x N float) = A (M x K bf16, row-major) * X (K x N float with values
 // representable in bf16), through the transposed bf16 copy Xt (N x K) held in
 // the caller's workspace.
@@ -320,6 +410,18 @@ rsrs_status gemm_bf16_op(hipStream_t st, const uint16_t* A, int64_t lda, int64_t
   }
   Bf16Desc d{A, Xt, Y, lda, ldt, ldy, (int)M, (int)N, (int)K};
   const double fl = 2.0 * M * N * K, by = 2.0 * (M * K + N * K) + 4.0 * M * N;
+  {
+    LtCall c;
+    if (lt_prepare(c, lda, M, K, ldt, N, ldy)) {
+      const float alpha = 1.0f, beta = 0.0f;
+      ProfScope ps(st, "gemm_bf16_hipblaslt:operator", fl, by);
+      if (hipblasLtMatmul(c.dev->h, c.desc, &alpha, Xt, c.la, A, c.lb, &beta, Y, c.lc, Y, c.lc, c.algo, nullptr, 0,
+                          st) == HIPBLAS_STATUS_SUCCESS)
+        return RSRS_OK;
+      set_error("hipBLASLt operator product failed");
+      return RSRS_E_INVALID;
+    }
+  }
   if (M >= WBM && N >= WBN) {
     const int64_t tiles = ((M + WBM - 1) / WBM) * ((N + WBN - 1) / WBN);
     ProfScope ps(st, "gemm_bf16_nt_256x256:operator", fl, by);
