@@ -198,7 +198,8 @@ TRAFFIC_FILES = {
     "gemm32_nt_syrk_128x128": os.path.join(ROOT, "profiles", "gemm32_syrk_128x128_65k_log2d_mixed_traffic.json"),
     "gemm32_nt_syrk_64x64": os.path.join(ROOT, "profiles", "gemm32_syrk_64x64_65k_log2d_mixed_traffic.json"),
     "gemm32_nn_full_64x64": os.path.join(ROOT, "profiles", "gemm32_nn_64x64_65k_log2d_mixed_traffic.json"),
-    "gemm_bf16_nt_256x256": os.path.join(ROOT, "profiles", "gemm_bf16_nt256_65k_log2d_mixed_traffic.json"),
+    "gemm_bf16_hipblaslt": os.path.join(ROOT, "profiles", "gemm_bf16_hipblaslt_65k_log2d_mixed_traffic.json"),
+    "gemm32_nt_full_64x64": os.path.join(ROOT, "profiles", "gemm32_nt_64x64_65k_log2d_mixed_traffic.json"),
     "gauss_jordan_blk": os.path.join(ROOT, "profiles", "gje_blk_65k_log2d_mixed_traffic.json"),
     "id_pchol": os.path.join(ROOT, "profiles", "id_pchol_65k_log2d_mixed_traffic.json"),
     "gemm_nn_full_128x128": os.path.join(ROOT, "profiles", "gemm_f64_nn_128x128_65k_log2d_fp64_traffic.json"),

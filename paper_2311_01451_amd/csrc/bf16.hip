@@ -418,8 +418,10 @@ rsrs_status gemm_bf16_op(hipStream_t st, const uint16_t* A, int64_t lda, int64_t
       if (hipblasLtMatmul(c.dev->h, c.desc, &alpha, Xt, c.la, A, c.lb, &beta, Y, c.lc, Y, c.lc, c.algo, nullptr, 0,
                           st) == HIPBLAS_STATUS_SUCCESS)
         return RSRS_OK;
-      set_error("hipBLASLt operator product failed");
-      return RSRS_E_INVALID;
+      // refused (hipBLASLt validates before it launches): this shape takes
+      // the kernels below from now on
+      std::lock_guard<std::mutex> lk(c.dev->mu);
+      c.dev->none[std::make_tuple(M, N, K, lda, ldt, ldy)] = true;
     }
   }
   if (M >= WBM && N >= WBN) {
