@@ -232,13 +232,13 @@ def roofline_entry(tag: str, e: dict, total_ms: float, all_ms: float, steps: int
     byte fall below the machine balance are priced by their bytes against
     HBM; the rest are FP64 vector work."""
     streaming = e["bytes"] > 0 and e["flops"] < MACHINE_BALANCE * e["bytes"]
-    if tag.startswith("gemm") or (e["flops"] > 0 and not streaming):
+    if tag.startswith(("gemm", "rocblas")) or (e["flops"] > 0 and not streaming):
         ach = e["flops"] / (e["ms"] * 1e-3) / 1e12
         if tag.startswith("gemm_bf16"):
             bound, peak = "mfma", PEAK_BF16_TFLOPS
-        elif tag.startswith("gemm32") or tag.startswith("chol32"):
+        elif tag.startswith(("gemm32", "chol32", "rocblas_sgemm")):
             bound, peak = "mfma", PEAK_FP32_TFLOPS
-        elif tag.startswith("gemm") or tag.startswith("gauss_jordan") or tag.startswith("chol"):
+        elif tag.startswith(("gemm", "gauss_jordan", "chol", "rocblas_dgemm")):
             bound, peak = "mfma", PEAK_FP64_TFLOPS
         else:
             bound, peak = "alu", PEAK_FP64_TFLOPS

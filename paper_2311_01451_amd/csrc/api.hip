@@ -1,14 +1,17 @@
 // extern "C" entry points of include/rsrs.h.
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
 
 #include <unordered_map>
 
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "impl.hpp"
+#include "profile.hpp"
 
 namespace rsrs {
 
@@ -31,6 +34,40 @@ static rsrs_status invalid(const char* msg) {
   return RSRS_E_INVALID;
 }
 
+// Wide products of a dense operator matrix are plain library GEMMs: rocBLAS
+// when it takes them (one handle per device, kept for the process), the own
+// GEMM otherwise.  In column-major terms Y^T (w x n) = X^T (w x n) * A^T,
+// A (n x n, row-major) being A^T column-major: op N for A, op T for A^T.
+struct RbDev {
+  std::mutex mu;
+  bool tried = false, ok = false;
+  rocblas_handle h = nullptr;
+};
+template <typename T>
+bool rb_operator_product(hipStream_t st, const T* A, int64_t lda, int64_t n, int ta, const T* X, int64_t ldx,
+                         int64_t w, T* Y, int64_t ldy) {
+  if (n > INT32_MAX || w > INT32_MAX || lda > INT32_MAX || ldx > INT32_MAX || ldy > INT32_MAX) return false;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  static RbDev devs[64];
+  RbDev& R = devs[dev & 63];
+  std::lock_guard<std::mutex> lk(R.mu);   // the handle's stream is set per call
+  if (!R.tried) {
+    R.tried = true;
+    R.ok = rocblas_create_handle(&R.h) == rocblas_status_success;
+  }
+  if (!R.ok || rocblas_set_stream(R.h, st) != rocblas_status_success) return false;
+  const T one = 1, zero = 0;
+  const rocblas_operation ob = ta ? rocblas_operation_transpose : rocblas_operation_none;
+  rocblas_status r;
+  if constexpr (sizeof(T) == 8)
+    r = rocblas_dgemm(R.h, rocblas_operation_none, ob, (rocblas_int)w, (rocblas_int)n, (rocblas_int)n, &one, X,
+                      (rocblas_int)ldx, A, (rocblas_int)lda, &zero, Y, (rocblas_int)ldy);
+  else
+    r = rocblas_sgemm(R.h, rocblas_operation_none, ob, (rocblas_int)w, (rocblas_int)n, (rocblas_int)n, &one, X,
+                      (rocblas_int)ldx, A, (rocblas_int)lda, &zero, Y, (rocblas_int)ldy);
+  return r == rocblas_status_success;
+}
 }  // namespace rsrs
 
 using namespace rsrs;
@@ -253,6 +290,12 @@ int rsrs_op_matvec(void* opv, int transpose, int dtype, int64_t ncols, const voi
                       ldy, op->skinny.as<double>()) == RSRS_OK ? 0 : 1;
   }
   if (dtype == RSRS_F64) {
+    if (ncols > 16) {
+      ProfScope ps(st, "rocblas_dgemm:operator", 2.0 * n * n * ncols, 8.0 * ((double)n * n + 2.0 * n * ncols));
+      if (rb_operator_product<double>(st, op->A, op->lda, n, ta, static_cast<const double*>(X), ldx, ncols,
+                                      static_cast<double*>(Y), ldy))
+        return 0;
+    }
     std::vector<GemmDesc> d{gdesc(op->A, nullptr, op->lda, static_cast<const double*>(X), nullptr, ldx,
                                   static_cast<double*>(Y), nullptr, ldy, n, (int)ncols, n)};
     return gemm(op->up, st, d, ta, 0, GM_FULL, shp, "operator") == RSRS_OK ? 0 : 1;
@@ -276,6 +319,12 @@ int rsrs_op_matvec(void* opv, int transpose, int dtype, int64_t ncols, const voi
   if (!op->owned32.p) {   // FP32 kernel matrix, entries rounded from the FP64 formula
     if (op->owned32.alloc((size_t)op->n * op->n * 4) != RSRS_OK) return 1;
     if (kernel_materialise<float>(st, op->kop, op->owned32.as<float>()) != RSRS_OK) return 1;
+  }
+  if (ncols > 16) {
+    ProfScope ps(st, "rocblas_sgemm:operator", 2.0 * n * n * ncols, 4.0 * ((double)n * n + 2.0 * n * ncols));
+    if (rb_operator_product<float>(st, op->owned32.as<float>(), op->n, n, ta, static_cast<const float*>(X), ldx,
+                                   ncols, static_cast<float*>(Y), ldy))
+      return 0;
   }
   std::vector<GemmDescT<float, float>> d{gdescT<float, float>(
       op->owned32.as<float>(), nullptr, op->n, static_cast<const float*>(X), nullptr, ldx,

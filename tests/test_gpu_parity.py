@@ -146,7 +146,8 @@ def solve_tolerance(P):
 
 
 def test_dense_operator_gemm_paths():
-    """The batched MFMA GEMM (NN and transposed-A forms, both tile shapes)."""
+    """Dense operator products in both forms (A X and A^T X): rocBLAS for the
+    wide blocks (w > 16), the own MFMA GEMM for the narrow ones."""
     need_gpu()
     rng = np.random.default_rng(0)
     for n, w in ((300, 37), (129, 5), (64, 16), (200, 130)):
