@@ -208,6 +208,14 @@ rsrs_status rsrs_op_create_poisson7(int n, const double* coef, rsrs_operator_t**
 int rsrs_op_matvec(void* op, int transpose, int dtype, int64_t ncols, const void* X, int64_t ldx,
                    void* Y, int64_t ldy, void* stream);
 void rsrs_op_destroy(rsrs_operator_t* op);
+/* Products of the built-in dense operators (kernel matrices and explicit
+ * matrices, the stand-ins for a user's black box) with blocks wider than 16
+ * columns are plain GEMMs: they go to rocBLAS (FP64, FP32) and hipBLASLt
+ * (BF16) when those take the shape.  enable = 0 sends them to the library's
+ * own MFMA GEMM kernels instead, process-wide; 1 restores the default.  The
+ * results agree to rounding either way.  For tests and comparisons; call it
+ * while no product is running.  Returns RSRS_OK. */
+rsrs_status rsrs_op_library_gemm(int enable);
 
 /* ------------------------------------------------------------------------
  * Samples {Y, Z, Omega, Psi} (Algorithm 1, Require).  Stored by the library

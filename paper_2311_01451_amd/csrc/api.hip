@@ -290,7 +290,7 @@ int rsrs_op_matvec(void* opv, int transpose, int dtype, int64_t ncols, const voi
                       ldy, op->skinny.as<double>()) == RSRS_OK ? 0 : 1;
   }
   if (dtype == RSRS_F64) {
-    if (ncols > 16) {
+    if (ncols > 16 && operator_library_gemm()) {
       ProfScope ps(st, "rocblas_dgemm:operator", 2.0 * n * n * ncols, 8.0 * ((double)n * n + 2.0 * n * ncols));
       if (rb_operator_product<double>(st, op->A, op->lda, n, ta, static_cast<const double*>(X), ldx, ncols,
                                       static_cast<double*>(Y), ldy))
@@ -320,7 +320,7 @@ int rsrs_op_matvec(void* opv, int transpose, int dtype, int64_t ncols, const voi
     if (op->owned32.alloc((size_t)op->n * op->n * 4) != RSRS_OK) return 1;
     if (kernel_materialise<float>(st, op->kop, op->owned32.as<float>()) != RSRS_OK) return 1;
   }
-  if (ncols > 16) {
+  if (ncols > 16 && operator_library_gemm()) {
     ProfScope ps(st, "rocblas_sgemm:operator", 2.0 * n * n * ncols, 4.0 * ((double)n * n + 2.0 * n * ncols));
     if (rb_operator_product<float>(st, op->owned32.as<float>(), op->n, n, ta, static_cast<const float*>(X), ldx,
                                    ncols, static_cast<float*>(Y), ldy))
@@ -333,6 +333,11 @@ int rsrs_op_matvec(void* opv, int transpose, int dtype, int64_t ncols, const voi
 }
 
 void rsrs_op_destroy(rsrs_operator_t* op) { delete op; }
+
+rsrs_status rsrs_op_library_gemm(int enable) {
+  set_operator_library_gemm(enable != 0);
+  return RSRS_OK;
+}
 
 // ------------------------------------------------------------------ samples
 static rsrs_status new_samples(const rsrs_tree_t* th, int64_t s, int dtype, rsrs_samples_t** out,

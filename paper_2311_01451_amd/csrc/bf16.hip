@@ -27,6 +27,7 @@
 #include <hipblaslt/hipblaslt.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdint>
 #include <map>
 #include <mutex>
@@ -390,7 +391,12 @@ bool lt_prepare(LtCall& c, int64_t lda, int64_t M, int64_t K, int64_t ldt, int64
   return true;
 }
 
+std::atomic<bool> g_lib_gemm{true};
+
 }  // namespace
+
+bool operator_library_gemm() { return g_lib_gemm.load(std::memory_order_relaxed); }
+void set_operator_library_gemm(bool on) { g_lib_gemm.store(on, std::memory_order_relaxed); }
 
 // Y (M x N float) = A (M x K bf16, row-major) * X (K x N float with values
 // representable in bf16), through the transposed bf16 copy Xt (N x K) held in
@@ -412,7 +418,7 @@ rsrs_status gemm_bf16_op(hipStream_t st, const uint16_t* A, int64_t lda, int64_t
   const double fl = 2.0 * M * N * K, by = 2.0 * (M * K + N * K) + 4.0 * M * N;
   {
     LtCall c;
-    if (lt_prepare(c, lda, M, K, ldt, N, ldy)) {
+    if (operator_library_gemm() && lt_prepare(c, lda, M, K, ldt, N, ldy)) {
       const float alpha = 1.0f, beta = 0.0f;
       ProfScope ps(st, "gemm_bf16_hipblaslt:operator", fl, by);
       if (hipblasLtMatmul(c.dev->h, c.desc, &alpha, Xt, c.la, A, c.lb, &beta, Y, c.lc, Y, c.lc, c.algo, nullptr, 0,

@@ -234,6 +234,10 @@ void philox_normal(hipStream_t st, T* out, int64_t nrows, int64_t ncols, int64_t
                    uint64_t seed, uint32_t word);
 // BF16 products (bf16.hip): Y (M x N float) = A (M x K bf16) X (K x N float
 // holding BF16 values), FP32 accumulation, with Xt (N x ldt bf16) as workspace.
+// Whether wide products of the built-in dense operators may go to rocBLAS /
+// hipBLASLt (default true; rsrs_op_library_gemm).
+bool operator_library_gemm();
+void set_operator_library_gemm(bool on);
 rsrs_status gemm_bf16_op(hipStream_t st, const uint16_t* A, int64_t lda, int64_t M, int64_t K,
                          const float* X, int64_t ldx, int64_t N, float* Y, int64_t ldy, uint16_t* Xt,
                          int64_t ldt);

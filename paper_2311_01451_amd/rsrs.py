@@ -96,7 +96,7 @@ EXPORTS = [
     "rsrs_status_string", "rsrs_last_error", "rsrs_last_required_s", "rsrs_build_tree",
     "rsrs_tree_destroy", "rsrs_tree_get_info", "rsrs_tree_neighbours", "rsrs_tree_schedule",
     "rsrs_samples_required", "rsrs_work_model", "rsrs_gemm_autotune", "rsrs_gemm_autotune_workload",
-    "rsrs_gemm_tile_override", "rsrs_op_create_kernel", "rsrs_op_create_dense",
+    "rsrs_gemm_tile_override", "rsrs_op_library_gemm", "rsrs_op_create_kernel", "rsrs_op_create_dense",
     "rsrs_op_create_poisson7", "rsrs_op_matvec", "rsrs_op_destroy", "rsrs_samples_wrap",
     "rsrs_sample", "rsrs_sample_symmetric", "rsrs_samples_wrap_symmetric", "rsrs_samples_destroy", "rsrs_gaussian", "rsrs_factor", "rsrs_factor_redraw", "rsrs_factor_batched",
     "rsrs_factor_destroy", "rsrs_release_cached",
@@ -142,6 +142,7 @@ def lib():
         "rsrs_work_model": (i32, [vp, P(FactorOpts), i64, i32, P(dbl), P(dbl), P(i64)]),
         "rsrs_gemm_autotune": (i32, [C.c_char_p, P(i64), P(i64)]),
         "rsrs_gemm_tile_override": (i32, [i32]),
+        "rsrs_op_library_gemm": (i32, [i32]),
         "rsrs_gemm_autotune_workload": (i32, [vp, P(FactorOpts), i64, P(i64), P(i64)]),
         "rsrs_op_create_kernel": (i32, [i32, P(C.c_double), i64, i32, dbl, dbl, P(vp)]),
         "rsrs_op_create_dense": (i32, [vp, i64, i64, P(vp)]),
@@ -335,6 +336,12 @@ def rsrs_gemm_autotune_workload(tree: Tree, k: int, s: int, precision: int = RSR
 def rsrs_gemm_tile_override(shape: int) -> None:
     """Forces a tile shape (0, 1, 2); -1 back to the table, -2 forgets it."""
     _check(lib().rsrs_gemm_tile_override(int(shape)))
+
+
+def rsrs_op_library_gemm(enable: bool) -> None:
+    """Wide products of the built-in dense operators through rocBLAS /
+    hipBLASLt (True, the default) or the library's own MFMA GEMMs (False)."""
+    _check(lib().rsrs_op_library_gemm(int(bool(enable))))
 
 
 # --------------------------------------------------------------------------- operators

@@ -46,24 +46,31 @@ def test_fp32_operator_products_within_rounding_bound():
     N = n * n
     A32 = oop.log2d(pts, 1.0 / n).astype(np.float32).astype(np.float64)
     op = rsrs.rsrs_op_create_kernel(rsrs.RSRS_OP_LOG2D, pts, 1.0 / n)
-    for w in (1, 16, 77, 300):
-        print(f"[fp32 operator] N={N} w={w}", flush=True)
-        X = np.random.default_rng(w).standard_normal((N, w)).astype(np.float32)
-        Y = op.matvec(dev(X, torch.float32)).cpu().numpy().astype(np.float64)
-        Xd = X.astype(np.float64)
-        exact = A32 @ Xd
-        bound = 1.0001 * N * U32 * (np.abs(A32) @ np.abs(Xd)) + 1e-30
-        assert np.all(np.abs(Y - exact) <= bound), float(np.max(np.abs(Y - exact) / bound))
-    # skewed (non-symmetric) kernel: the transposed product reads A column-wise
     Ask = oop.log2d_skew(pts, 1.0 / n, 0.3).astype(np.float32).astype(np.float64)
     opk = rsrs.rsrs_op_create_kernel(rsrs.RSRS_OP_LOG2D_SKEW, pts, 1.0 / n, 0.3)
-    X = np.random.default_rng(5).standard_normal((N, 64)).astype(np.float32)
-    Xd = X.astype(np.float64)
-    for tr in (False, True):
-        M = Ask.T if tr else Ask
-        Y = opk.matvec(dev(X, torch.float32), transpose=tr).cpu().numpy().astype(np.float64)
-        bound = 1.0001 * N * U32 * (np.abs(M) @ np.abs(Xd)) + 1e-30
-        assert np.all(np.abs(Y - M @ Xd) <= bound)
+    try:
+        # rocBLAS for the wide blocks, then the own FP32 GEMM for all
+        for lib_gemm in (True, False):
+            rsrs.rsrs_op_library_gemm(lib_gemm)
+            for w in (1, 16, 77, 300):
+                print(f"[fp32 operator] N={N} w={w} library GEMM {lib_gemm}", flush=True)
+                X = np.random.default_rng(w).standard_normal((N, w)).astype(np.float32)
+                Y = op.matvec(dev(X, torch.float32)).cpu().numpy().astype(np.float64)
+                Xd = X.astype(np.float64)
+                exact = A32 @ Xd
+                bound = 1.0001 * N * U32 * (np.abs(A32) @ np.abs(Xd)) + 1e-30
+                assert np.all(np.abs(Y - exact) <= bound), (lib_gemm, float(np.max(np.abs(Y - exact) / bound)))
+            # skewed (non-symmetric) kernel: the transposed product reads A
+            # column-wise
+            X = np.random.default_rng(5).standard_normal((N, 64)).astype(np.float32)
+            Xd = X.astype(np.float64)
+            for tr in (False, True):
+                M = Ask.T if tr else Ask
+                Y = opk.matvec(dev(X, torch.float32), transpose=tr).cpu().numpy().astype(np.float64)
+                bound = 1.0001 * N * U32 * (np.abs(M) @ np.abs(Xd)) + 1e-30
+                assert np.all(np.abs(Y - M @ Xd) <= bound), (lib_gemm, tr)
+    finally:
+        rsrs.rsrs_op_library_gemm(True)
 
 
 def _bf16(x):
@@ -84,13 +91,19 @@ def test_bf16_operator_products_within_rounding_bound():
     N = n * n
     A16 = _bf16(oop.log2d(pts, 1.0 / n))
     op = rsrs.rsrs_op_create_kernel(rsrs.RSRS_OP_LOG2D, pts, 1.0 / n)
-    for w in (1, 33, 130, 300):
-        print(f"[bf16 operator] N={N} w={w}", flush=True)
-        X = _bf16(np.random.default_rng(w).standard_normal((N, w)))
-        Y = op.matvec(dev(X, torch.float32), bf16=True).cpu().numpy().astype(np.float64)
-        exact = A16 @ X
-        bound = 1.0001 * N * U32 * (np.abs(A16) @ np.abs(X)) + 1e-30
-        assert np.all(np.abs(Y - exact) <= bound), float(np.max(np.abs(Y - exact) / bound))
+    try:
+        # hipBLASLt where it takes the shape, then the own BF16 MFMA kernels
+        for lib_gemm in (True, False):
+            rsrs.rsrs_op_library_gemm(lib_gemm)
+            for w in (1, 33, 130, 300):
+                print(f"[bf16 operator] N={N} w={w} library GEMM {lib_gemm}", flush=True)
+                X = _bf16(np.random.default_rng(w).standard_normal((N, w)))
+                Y = op.matvec(dev(X, torch.float32), bf16=True).cpu().numpy().astype(np.float64)
+                exact = A16 @ X
+                bound = 1.0001 * N * U32 * (np.abs(A16) @ np.abs(X)) + 1e-30
+                assert np.all(np.abs(Y - exact) <= bound), (lib_gemm, float(np.max(np.abs(Y - exact) / bound)))
+    finally:
+        rsrs.rsrs_op_library_gemm(True)
 
 
 def test_bf16_sampling_mixed_factor_refines():

@@ -147,17 +147,23 @@ def solve_tolerance(P):
 
 def test_dense_operator_gemm_paths():
     """Dense operator products in both forms (A X and A^T X): rocBLAS for the
-    wide blocks (w > 16), the own MFMA GEMM for the narrow ones."""
+    wide blocks (w > 16), the own MFMA GEMM for the narrow ones, and the own
+    GEMM for every width once the library GEMMs are switched off."""
     need_gpu()
     rng = np.random.default_rng(0)
-    for n, w in ((300, 37), (129, 5), (64, 16), (200, 130)):
-        A = rng.standard_normal((n, n))
-        X = rng.standard_normal((n, w))
-        op = rsrs.rsrs_op_create_dense(dev(A))
-        y = op.matvec(dev(X)).cpu().numpy()
-        yt = op.matvec(dev(X), transpose=True).cpu().numpy()
-        assert relmax(y, A @ X) < 1e-13
-        assert relmax(yt, A.T @ X) < 1e-13
+    try:
+        for lib_gemm in (True, False):
+            rsrs.rsrs_op_library_gemm(lib_gemm)
+            for n, w in ((300, 37), (129, 5), (64, 16), (200, 130)):
+                A = rng.standard_normal((n, n))
+                X = rng.standard_normal((n, w))
+                op = rsrs.rsrs_op_create_dense(dev(A))
+                y = op.matvec(dev(X)).cpu().numpy()
+                yt = op.matvec(dev(X), transpose=True).cpu().numpy()
+                assert relmax(y, A @ X) < 1e-13, (lib_gemm, n, w)
+                assert relmax(yt, A.T @ X) < 1e-13, (lib_gemm, n, w)
+    finally:
+        rsrs.rsrs_op_library_gemm(True)
 
 
 def philox4x32_10(ctr, key):
