@@ -110,8 +110,10 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmDescT<TI, 
   constexpr int VW = 16 / (int)sizeof(TI);   // elements per 16-byte load
   constexpr int NT = 64 * WM * WN;    // threads per workgroup
   // K slice: 32 for FP32 operands on wide tiles (the MFMA work of one slice
-  // then covers a global-load round trip), 16 otherwise
-  constexpr int BK = (sizeof(TI) == 4 && BN >= 64) ? 32 : 16;
+  // then covers a global-load round trip), 64 on the narrow FP32 tiles of the
+  // solves (their K loops were round-trip bound: four times fewer), 16 for
+  // FP64.  FP32 sums each 16-k group in the same order whatever the slice.
+  constexpr int BK = (sizeof(TI) == 4) ? (BN >= 64 ? 32 : 64) : 16;
   constexpr int PA = BM + 2;
   constexpr int PB = BN + 2;
   constexpr int FM = BM / WM / 16;
